@@ -1,0 +1,182 @@
+/*
+ * ibm_lb.h — C-ABI of the MI355X (gfx950) IB-LB droplet library.
+ *
+ * One call of ibm_lb_step advances the coupled immersed-boundary /
+ * lattice-Boltzmann droplet of Taglienti, Guglietta & Sbragaglia,
+ * "Droplet dynamics in homogeneous isotropic turbulence with the immersed
+ * boundary-lattice Boltzmann method" (arXiv 2403.01161), by whole timesteps.
+ * Each timestep runs, on the GPU, in this order:
+ *   1. surface-tension nodal forces of the mesh (Sec. 3.1, Eq. pi_drop),
+ *      taken as phi_k = -sigma dA_surface/dr_k;
+ *   2. spreading of the forces onto the lattice with the Peskin 4-point
+ *      stencil (Sec. 3.1, Eq. ibm_force_d first line, stencil phi(x));
+ *   3. a fused D3Q19 BGK collide with Guo forcing and push-streaming
+ *      (Sec. 3.1, Eqs. LBMEQ, collision, equilibriumLB, Guo source,
+ *      density_velocity_LB), with moving-wall velocity bounce-back
+ *      (Eq. standard BB) imposing u = A (x - x_c) on the box faces
+ *      (Sec. 2 Eq. linearized velocity; Sec. 3.1 Eq. velo_facce_cubo_da_gradiente);
+ *   4. interpolation of the half-force-corrected velocity onto the mesh and
+ *      the forward-Euler move (Eq. ibm_force_d second line, Eq. fwd_euler);
+ *   5. extended Laplacian (HC) smoothing of the mesh (Sec. 3.3, Eqs.
+ *      extended laplacian smoothing, HC_algo_full, distanceregularization).
+ * Observables (Sec. 2: morphological tensor S, lambda_max, v_max, Eq. beta)
+ * are FP64 reductions over the mesh computed on request.
+ *
+ * Conventions
+ *  - Lattice nodes sit at integer coordinates 0..L[a]-1; the walls are half a
+ *    spacing outside the outermost nodes; the box centre is x_c = (L-1)/2.
+ *  - Gradients are row-major 3x3 doubles, A[3a+b] = d u_a / d x_b, so the
+ *    imposed wall velocity is u_w = A (x_w - x_c).
+ *  - Vertex coordinates crossing the ABI are absolute lattice coordinates,
+ *    double [nv][3]. Triangles are int32 [nt][3], counter-clockwise seen
+ *    from outside (outward normals).
+ *  - Fields crossing the ABI are double, x fastest: rho [Lz][Ly][Lx],
+ *    u [3][Lz][Ly][Lx].
+ *  - Every function returns IBM_LB_OK (0) or a negative error code and never
+ *    aborts. Work is enqueued on cfg->stream (a hipStream_t, NULL for the
+ *    null stream) and is asynchronous unless stated; errors raised on the
+ *    GPU (stencil outside the box, non-finite state) are sticky on the handle
+ *    and returned by the next synchronising call. ibm_lb_last_error() gives a
+ *    thread-local message for the last failure.
+ *  - A handle is used by one host thread at a time.
+ */
+#ifndef IBM_LB_H
+#define IBM_LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define IBM_LB_OK 0
+#define IBM_LB_EINVAL (-1)     /* invalid argument or configuration */
+#define IBM_LB_ENOMEM (-2)     /* device or host allocation failed, or workspace too small */
+#define IBM_LB_EDEVICE (-3)    /* a HIP runtime call failed */
+#define IBM_LB_EDOMAIN (-4)    /* a vertex stencil left the box across a wall */
+#define IBM_LB_ENONFINITE (-5) /* non-finite or non-positive density, velocity or position */
+
+/* ---- population storage formats (populations are stored as deviations
+ * f_i - w_i rho0 from the rest equilibrium; the collision runs in FP64 for
+ * IBM_LB_F64 and in FP32 for the other formats) ---- */
+#define IBM_LB_F64 0
+#define IBM_LB_F32 1
+#define IBM_LB_F16DEV 2  /* FP16 of deviation * f16_scale (a power of two) */
+#define IBM_LB_BF16DEV 3 /* BF16 of deviation */
+
+/* ---- initial state ---- */
+#define IBM_LB_INIT_LINEAR 0 /* f_eq(rho0, A0 (x - x_c)) - 3 tau w_i rho0 (c_i c_i - I/3):A0 */
+#define IBM_LB_INIT_REST 1   /* f_i = w_i rho0 */
+
+/* ---- observable flags ---- */
+#define IBM_LB_OBS_DEGENERATE 1 /* lambda_1 - lambda_2 < 1e-12 radius^2: v_max, beta, theta are NaN */
+#define IBM_LB_OBS_E_ZERO 2     /* ||E||_F == 0: beta is NaN */
+#define IBM_LB_OBS_REG_CAP 4    /* smoothing hit reg_max_iter in a step since the last observables call */
+
+/* ---- field selectors for ibm_lb_read_field ---- */
+#define IBM_LB_FIELD_RHO 0
+#define IBM_LB_FIELD_U 1
+
+typedef struct ibm_lb ibm_lb;
+typedef struct ibm_lb_batch ibm_lb_batch;
+
+typedef struct ibm_lb_config {
+    int32_t L[3];          /* nodes per axis, each >= 8 */
+    int32_t periodic[3];   /* per axis: 0 = moving walls, 1 = periodic */
+    double tau;            /* BGK relaxation time (Eq. collision), > 0.5; nu = (tau - 1/2)/3 */
+    double sigma;          /* surface tension (Eq. pi_drop), >= 0 */
+    double radius;         /* rest radius R (> 0): scale of the degeneracy threshold */
+    double rho0;           /* reference density (> 0, normally 1) */
+    int32_t n_vertices;    /* 0 runs the lattice without a droplet */
+    int32_t n_triangles;
+    const double* vertices;    /* host [n_vertices][3], absolute coordinates; copied */
+    const int32_t* triangles;  /* host [n_triangles][3]; copied */
+    double reg_alpha;      /* smoothing alpha (Sec. 3.3; 0.1) */
+    double reg_gamma;      /* smoothing gamma (0.51) */
+    double reg_tol;        /* exit when max_i |x_p - x_q| < reg_tol (0.01) */
+    int32_t reg_max_iter;  /* iteration cap per step (50); 0 disables smoothing */
+    int32_t reg_sign;      /* +1: correction adds the neighbour mean of b (default); -1: subtracts it */
+    int32_t storage;       /* IBM_LB_F64 / F32 / F16DEV / BF16DEV */
+    int32_t init;          /* IBM_LB_INIT_LINEAR or IBM_LB_INIT_REST */
+    double A0[9];          /* gradient of the initial linear field */
+    double f16_scale;      /* IBM_LB_F16DEV only: power of two >= 1; 0 selects 4096 */
+    void* stream;          /* hipStream_t the library enqueues on; NULL = null stream */
+    void* workspace;       /* device memory of >= ibm_lb_workspace_size bytes, caller-owned
+                              and kept alive until ibm_lb_destroy; NULL: the library
+                              allocates (and frees) its own */
+    size_t workspace_bytes;
+} ibm_lb_config;
+
+typedef struct ibm_lb_obs {
+    int64_t step;          /* completed timesteps */
+    double volume;         /* enclosed volume of the mesh */
+    double centroid[3];    /* absolute coordinates */
+    double S[9];           /* morphological tensor (5/V) int (x-xb)(x-xb)^T dV, row-major */
+    double eigval[3];      /* eigenvalues of S, descending (lambda_max first) */
+    double eigvec[9];      /* row k = unit eigenvector of eigval[k] */
+    double D;              /* (sqrt(l1) - sqrt(l3)) / (sqrt(l1) + sqrt(l3)) */
+    double beta;           /* Eq. beta with E = (A + A^T)/2 of the last step */
+    double theta_deg;      /* atan2(v1_y, v1_x) folded into (-90, 90] degrees */
+    double mass;           /* sum over nodes of sum_i f_i */
+    double momentum[3];    /* sum over nodes of sum_i c_i f_i */
+    int32_t reg_iters;     /* smoothing iterations of the last step */
+    int32_t flags;         /* IBM_LB_OBS_* */
+} ibm_lb_obs;
+
+/* Device bytes the configuration needs when cfg->workspace is supplied.
+ * Errors: EINVAL (bad configuration). */
+int ibm_lb_workspace_size(const ibm_lb_config* cfg, size_t* bytes);
+
+/* Validate cfg, copy the mesh and build its adjacency, lay out device memory
+ * and enqueue the initial state on cfg->stream. *out is owned by the library
+ * until ibm_lb_destroy. Errors: EINVAL (L < 8, tau <= 0.5, sigma < 0,
+ * radius <= 0, rho0 <= 0, bad storage/init, index out of range, open or
+ * inward mesh, a vertex stencil outside a wall axis), ENOMEM, EDEVICE. */
+int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out);
+
+/* Advance nsteps timesteps holding the gradient A fixed (the paper's
+ * protocol holds each gradient sample for N steps, Sec. 3.2). A is a host
+ * pointer, copied before return. Asynchronous. Errors: EINVAL, sticky. */
+int ibm_lb_step(ibm_lb* h, const double A[9], int32_t nsteps);
+
+/* Advance nsteps timesteps, step n using A + 9 n. on_device = 0: A is host
+ * memory, copied before return. on_device = 1: A is device memory the
+ * caller keeps unchanged until the next synchronising call. Asynchronous. */
+int ibm_lb_step_table(ibm_lb* h, const double* A, int32_t nsteps, int32_t on_device);
+
+/* Synchronise the stream and fill *out (FP64 reductions on the GPU).
+ * Returns the sticky GPU error if one was raised. */
+int ibm_lb_observables(ibm_lb* h, ibm_lb_obs* out);
+
+/* Synchronising reads for tests and analysis. vertices: host double [nv][3]
+ * absolute. read_field: which = IBM_LB_FIELD_RHO (rho^n, host double [N]) or
+ * IBM_LB_FIELD_U (u^n including F^n/2 from the current mesh, host double
+ * [3][N]). read_field allocates a temporary device buffer. */
+int ibm_lb_read_vertices(ibm_lb* h, double* out);
+int ibm_lb_read_field(ibm_lb* h, int32_t which, double* out);
+
+/* Checkpoints: ibm_lb_state_bytes is the size of the state (populations,
+ * vertices, step counter). save/load copy it to/from dst/src, which may be
+ * host or device memory of at least that many bytes (caller-owned); both
+ * synchronise the stream. Errors: EINVAL (size too small), EDEVICE. */
+size_t ibm_lb_state_bytes(const ibm_lb* h);
+int ibm_lb_save(ibm_lb* h, void* dst, size_t n);
+int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
+
+/* Kernel timing of the fused lattice kernel: when enabled, every step records
+ * HIP events around the lattice kernel on the handle's stream.
+ * ibm_lb_timing_read synchronises and returns the summed elapsed time (ms)
+ * and launch count since the last read. */
+int ibm_lb_timing_enable(ibm_lb* h, int32_t enable);
+int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
+
+void ibm_lb_destroy(ibm_lb* h);
+const char* ibm_lb_strerror(int code);
+const char* ibm_lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBM_LB_H */

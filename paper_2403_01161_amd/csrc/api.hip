@@ -1,0 +1,672 @@
+// C-ABI of the IB-LB droplet library: validation, device memory layout,
+// launch sequencing and synchronising reads. The per-timestep order is the
+// one documented in include/ibm_lb.h.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ibmlb_internal.h"
+
+using namespace ibmlb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(IBM_LB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                          \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Byte offsets of every device array inside one workspace.
+struct Layout {
+    size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, phi, tris, vt_start, vt_list, nb_start,
+        nb_list, obs_part, mass_part, obs_out, Abuf, total;
+};
+
+struct MeshCSR {
+    std::vector<int> vt_start, vt_list, nb_start, nb_list;
+};
+
+Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t nb_total) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes > 0 ? bytes : 1);
+        return o;
+    };
+    const size_t sb = storage_bytes(storage), rb = real_bytes(storage);
+    L.f[0] = take(19ull * N * sb);
+    L.f[1] = take(19ull * N * sb);
+    L.F = take(3ull * N * rb);
+    L.u = take(3ull * N * rb);
+    L.mark = take(sizeof(int) * (size_t)ntiles);
+    L.ctl = take(sizeof(Ctl));
+    const size_t v4 = 4 * rb * (size_t)nv;
+    L.r = take(v4);
+    L.o = take(v4);
+    L.qa = take(v4);
+    L.qb = take(v4);
+    L.pp = take(v4);
+    L.bb = take(v4);
+    L.phi = take(v4);
+    L.tris = take(sizeof(int4) * (size_t)nt);
+    L.vt_start = take(sizeof(int) * (size_t)(nv + 1));
+    L.vt_list = take(sizeof(int) * 3 * (size_t)nt);
+    L.nb_start = take(sizeof(int) * (size_t)(nv + 1));
+    L.nb_list = take(sizeof(int) * nb_total);
+    L.obs_part = take(sizeof(double) * 16 * OBS_BLOCKS);
+    L.mass_part = take(sizeof(double) * 4 * MASS_BLOCKS);
+    L.obs_out = take(sizeof(double) * OBS_OUT_N);
+    L.Abuf = take(sizeof(double) * 9 * (ACAP + 1));
+    L.total = off;
+    return L;
+}
+
+// Validate the configuration and build the mesh adjacency.
+int validate(const ibm_lb_config* c, MeshCSR* csr) {
+    if (!c) return fail(IBM_LB_EINVAL, "config is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (c->L[a] < 8) return fail(IBM_LB_EINVAL, "every box side needs at least 8 nodes");
+    if ((long long)c->L[0] * c->L[1] * c->L[2] > (1ll << 31) / 19)
+        return fail(IBM_LB_EINVAL, "box too large for 32-bit plane indexing");
+    if (!(c->tau > 0.5)) return fail(IBM_LB_EINVAL, "tau must exceed 1/2");
+    if (!(c->sigma >= 0.0)) return fail(IBM_LB_EINVAL, "sigma must be >= 0");
+    if (!(c->radius > 0.0)) return fail(IBM_LB_EINVAL, "radius must be > 0");
+    if (!(c->rho0 > 0.0)) return fail(IBM_LB_EINVAL, "rho0 must be > 0");
+    if (c->storage < IBM_LB_F64 || c->storage > IBM_LB_BF16DEV)
+        return fail(IBM_LB_EINVAL, "unknown storage format");
+    if (c->init != IBM_LB_INIT_LINEAR && c->init != IBM_LB_INIT_REST)
+        return fail(IBM_LB_EINVAL, "unknown init mode");
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(c->A0[k])) return fail(IBM_LB_EINVAL, "A0 is not finite");
+    if (c->storage == IBM_LB_F16DEV && c->f16_scale != 0.0) {
+        int ex;
+        double m = frexp(c->f16_scale, &ex);
+        if (!(c->f16_scale >= 1.0) || m != 0.5 || c->f16_scale > 65536.0)
+            return fail(IBM_LB_EINVAL, "f16_scale must be a power of two in [1, 65536]");
+    }
+    const int nv = c->n_vertices, nt = c->n_triangles;
+    if (nv < 0 || nt < 0) return fail(IBM_LB_EINVAL, "negative mesh size");
+    if (nv == 0 && nt == 0) return IBM_LB_OK;
+    if (nv < 4 || nt < 4 || !c->vertices || !c->triangles)
+        return fail(IBM_LB_EINVAL, "a mesh needs >= 4 vertices, >= 4 triangles and both arrays");
+    if (c->reg_max_iter < 0) return fail(IBM_LB_EINVAL, "reg_max_iter must be >= 0");
+    if (c->reg_max_iter > 0) {
+        if (!(c->reg_alpha >= 0.0 && c->reg_alpha <= 1.0) || !(c->reg_gamma >= 0.0 && c->reg_gamma <= 1.0))
+            return fail(IBM_LB_EINVAL, "reg_alpha and reg_gamma must lie in [0, 1]");
+        if (c->reg_sign != 1 && c->reg_sign != -1) return fail(IBM_LB_EINVAL, "reg_sign must be +1 or -1");
+        if (!(c->reg_tol >= 0.0) && !(c->reg_tol < 0.0)) return fail(IBM_LB_EINVAL, "reg_tol is NaN");
+    }
+    for (int k = 0; k < 3 * nv; ++k)
+        if (!isfinite(c->vertices[k])) return fail(IBM_LB_EINVAL, "vertex coordinate not finite");
+    const int32_t* T = c->triangles;
+    for (int k = 0; k < 3 * nt; ++k)
+        if (T[k] < 0 || T[k] >= nv) return fail(IBM_LB_EINVAL, "triangle index out of range");
+    // closed, consistently oriented: every directed edge once, with its reverse
+    std::map<std::pair<int, int>, int> edges;
+    for (int t = 0; t < nt; ++t)
+        for (int j = 0; j < 3; ++j) {
+            int a = T[3 * t + j], b = T[3 * t + (j + 1) % 3];
+            if (a == b) return fail(IBM_LB_EINVAL, "degenerate triangle");
+            if (++edges[{a, b}] > 1) return fail(IBM_LB_EINVAL, "mesh is not consistently oriented");
+        }
+    for (auto& e : edges)
+        if (!edges.count({e.first.second, e.first.first}))
+            return fail(IBM_LB_EINVAL, "mesh is not closed");
+    // outward orientation: positive enclosed volume
+    double vol = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        const double* a = c->vertices + 3 * T[3 * t];
+        const double* b = c->vertices + 3 * T[3 * t + 1];
+        const double* d = c->vertices + 3 * T[3 * t + 2];
+        vol += (a[0] * (b[1] * d[2] - b[2] * d[1]) + a[1] * (b[2] * d[0] - b[0] * d[2]) +
+                a[2] * (b[0] * d[1] - b[1] * d[0])) / 6.0;
+    }
+    if (!(vol > 0.0)) return fail(IBM_LB_EINVAL, "mesh encloses a non-positive volume (inward?)");
+    // stencils inside the wall axes
+    for (int k = 0; k < nv; ++k)
+        for (int a = 0; a < 3; ++a) {
+            if (c->periodic[a]) continue;
+            double fl = floor(c->vertices[3 * k + a]);
+            if (fl - 1.0 < 0.0 || fl + 2.0 > c->L[a] - 1)
+                return fail(IBM_LB_EINVAL, "a vertex stencil leaves the box across a wall");
+        }
+    // adjacency: vertex -> incident triangle corners (triangles ascending),
+    // and the one-ring (sorted)
+    csr->vt_start.assign(nv + 1, 0);
+    for (int k = 0; k < 3 * nt; ++k) csr->vt_start[T[k] + 1]++;
+    for (int v = 0; v < nv; ++v) csr->vt_start[v + 1] += csr->vt_start[v];
+    csr->vt_list.assign(3 * (size_t)nt, 0);
+    std::vector<int> fill(csr->vt_start.begin(), csr->vt_start.end() - 1);
+    for (int t = 0; t < nt; ++t)
+        for (int j = 0; j < 3; ++j) csr->vt_list[fill[T[3 * t + j]]++] = (t << 2) | j;
+    std::vector<std::vector<int>> ring(nv);
+    for (auto& e : edges) ring[e.first.first].push_back(e.first.second);
+    csr->nb_start.assign(nv + 1, 0);
+    csr->nb_list.clear();
+    for (int v = 0; v < nv; ++v) {
+        auto& r = ring[v];
+        std::sort(r.begin(), r.end());
+        r.erase(std::unique(r.begin(), r.end()), r.end());
+        if (r.empty()) return fail(IBM_LB_EINVAL, "vertex without neighbours");
+        csr->nb_list.insert(csr->nb_list.end(), r.begin(), r.end());
+        csr->nb_start[v + 1] = (int)csr->nb_list.size();
+    }
+    return IBM_LB_OK;
+}
+
+Geom make_geom(const ibm_lb_config* c) {
+    Geom g{};
+    g.Lx = c->L[0];
+    g.Ly = c->L[1];
+    g.Lz = c->L[2];
+    g.px = c->periodic[0] ? 1 : 0;
+    g.py = c->periodic[1] ? 1 : 0;
+    g.pz = c->periodic[2] ? 1 : 0;
+    g.TX = (g.Lx + 7) >> 3;
+    g.TY = (g.Ly + 7) >> 3;
+    g.TZ = (g.Lz + 7) >> 3;
+    g.N = (long long)g.Lx * g.Ly * g.Lz;
+    for (int a = 0; a < 3; ++a) {
+        double xc = (c->L[a] - 1) / 2.0;
+        g.xci[a] = (int)floor(xc);
+        g.xcf[a] = xc - g.xci[a];
+    }
+    return g;
+}
+
+}  // namespace
+
+struct ibm_lb {
+    ibm_lb_config cfg;
+    int storage = 0, nv = 0, nt = 0, device = 0;
+    Geom g{};
+    LatticeParams lp{};
+    SmoothParams sp{};
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    Layout lay{};
+    DevPtrs d{};
+    int cur = 0;
+    int64_t step = 0;
+    int sticky = IBM_LB_OK;
+    double* stage = nullptr;     // pinned host staging for gradient rows
+    hipEvent_t stage_done = nullptr;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t ev_used = 0;
+    double acc_ms = 0.0;
+    int64_t launches = 0;
+};
+
+namespace {
+
+int set_device(ibm_lb* h) {
+    HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    return IBM_LB_OK;
+}
+
+// Read the device flags after a synchronisation; record a sticky error.
+int check_flags(ibm_lb* h) {
+    Ctl c;
+    HIP_TRY(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost), "read flags");
+    if (c.flags & DFLAG_NONFINITE) {
+        h->sticky = IBM_LB_ENONFINITE;
+        return fail(IBM_LB_ENONFINITE, "non-finite or non-positive density, velocity or position");
+    }
+    if (c.flags & DFLAG_DOMAIN) {
+        h->sticky = IBM_LB_EDOMAIN;
+        return fail(IBM_LB_EDOMAIN, "a vertex stencil left the box across a wall");
+    }
+    return IBM_LB_OK;
+}
+
+int sync_and_check(ibm_lb* h) {
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return check_flags(h);
+}
+
+int accumulate_timing(ibm_lb* h) {
+    for (size_t k = 0; k < h->ev_used; ++k) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventSynchronize(h->ev[k].second), "hipEventSynchronize");
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev[k].first, h->ev[k].second), "hipEventElapsedTime");
+        h->acc_ms += ms;
+    }
+    h->launches += (int64_t)h->ev_used;
+    h->ev_used = 0;
+    return IBM_LB_OK;
+}
+
+// Enqueue nsteps timesteps; step j reads the gradient row A + 9 j*stride.
+int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
+    const bool ib = h->nv > 0;
+    for (int j = 0; j < nsteps; ++j) {
+        const double* Arow = A + 9ll * j * stride;
+        if (ib) {
+            HIP_TRY(launch_forces(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->stream), "forces launch");
+            HIP_TRY(launch_spread(h->storage, h->g, h->d, h->nv, h->stream), "spread launch");
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (h->timing) {
+            if (h->ev_used == 4096) {
+                int rc = accumulate_timing(h);
+                if (rc) return rc;
+            }
+            if (h->ev_used == h->ev.size()) {
+                hipEvent_t a, b;
+                HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+                HIP_TRY(hipEventCreate(&b), "hipEventCreate");
+                h->ev.push_back({a, b});
+            }
+            e0 = h->ev[h->ev_used].first;
+            e1 = h->ev[h->ev_used].second;
+            HIP_TRY(hipEventRecord(e0, h->stream), "hipEventRecord");
+        }
+        HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->stream), "lattice launch");
+        if (h->timing) {
+            HIP_TRY(hipEventRecord(e1, h->stream), "hipEventRecord");
+            h->ev_used++;
+        }
+        if (ib) {
+            HIP_TRY(launch_interp(h->storage, h->g, h->d, h->nv, h->stream), "interp launch");
+            HIP_TRY(launch_smooth(h->storage, h->d, h->nv, h->sp, h->stream), "smooth launch");
+        }
+        h->cur ^= 1;
+        h->step++;
+    }
+    if (nsteps > 0) {
+        const double* last = A + 9ll * (nsteps - 1) * stride;
+        double* slot = h->d.Abuf + 9ll * ACAP;
+        if (last != slot)
+            HIP_TRY(hipMemcpyAsync(slot, last, 9 * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
+                    "copy last gradient");
+    }
+    return IBM_LB_OK;
+}
+
+// Copy n host gradient rows into the device gradient buffer (through pinned
+// staging, so the caller's array may change once this returns).
+int upload_rows(ibm_lb* h, const double* A, int n) {
+    HIP_TRY(hipEventSynchronize(h->stage_done), "staging wait");
+    memcpy(h->stage, A, sizeof(double) * 9 * (size_t)n);
+    HIP_TRY(hipMemcpyAsync(h->d.Abuf, h->stage, sizeof(double) * 9 * (size_t)n, hipMemcpyHostToDevice,
+                           h->stream),
+            "upload gradient rows");
+    HIP_TRY(hipEventRecord(h->stage_done, h->stream), "hipEventRecord");
+    return IBM_LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ibm_lb_strerror(int code) {
+    switch (code) {
+        case IBM_LB_OK: return "ok";
+        case IBM_LB_EINVAL: return "invalid argument";
+        case IBM_LB_ENOMEM: return "out of memory";
+        case IBM_LB_EDEVICE: return "HIP runtime error";
+        case IBM_LB_EDOMAIN: return "vertex stencil outside the box";
+        case IBM_LB_ENONFINITE: return "non-finite state";
+        default: return "unknown error";
+    }
+}
+
+const char* ibm_lb_last_error(void) { return g_last_error.c_str(); }
+
+int ibm_lb_workspace_size(const ibm_lb_config* cfg, size_t* bytes) {
+    MeshCSR csr;
+    int rc = validate(cfg, &csr);
+    if (rc) return rc;
+    if (!bytes) return fail(IBM_LB_EINVAL, "bytes is NULL");
+    Geom g = make_geom(cfg);
+    *bytes = make_layout(cfg->storage, g.N, g.TX * g.TY * g.TZ, cfg->n_vertices, cfg->n_triangles,
+                         csr.nb_list.size())
+                 .total;
+    return IBM_LB_OK;
+}
+
+int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
+    if (!out) return fail(IBM_LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    MeshCSR csr;
+    int rc = validate(cfg, &csr);
+    if (rc) return rc;
+    ibm_lb* h = new (std::nothrow) ibm_lb();
+    if (!h) return fail(IBM_LB_ENOMEM, "host allocation");
+    h->cfg = *cfg;
+    h->cfg.vertices = nullptr;
+    h->cfg.triangles = nullptr;
+    h->storage = cfg->storage;
+    h->nv = cfg->n_vertices;
+    h->nt = cfg->n_triangles;
+    h->stream = (hipStream_t)cfg->stream;
+    h->g = make_geom(cfg);
+    h->lp.omega = 1.0 / cfg->tau;
+    h->lp.kguo = 1.0 - 1.0 / (2.0 * cfg->tau);
+    h->lp.rho0 = cfg->rho0;
+    h->lp.tau = cfg->tau;
+    double sc = (cfg->storage == IBM_LB_F16DEV) ? (cfg->f16_scale == 0.0 ? 4096.0 : cfg->f16_scale) : 1.0;
+    h->lp.scale = (float)sc;
+    h->lp.inv_scale = (float)(1.0 / sc);
+    h->sp.alpha = cfg->reg_alpha;
+    h->sp.gamma = cfg->reg_gamma;
+    h->sp.tol = cfg->reg_tol;
+    h->sp.max_iter = cfg->reg_max_iter;
+    h->sp.sign = cfg->reg_sign == -1 ? -1 : 1;
+    auto bail = [&](int code) {
+        ibm_lb_destroy(h);
+        return code;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
+    const int ntiles = h->g.TX * h->g.TY * h->g.TZ;
+    h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt, csr.nb_list.size());
+    if (cfg->workspace) {
+        if (cfg->workspace_bytes < h->lay.total)
+            return bail(fail(IBM_LB_ENOMEM, "workspace smaller than ibm_lb_workspace_size"));
+        if (((uintptr_t)cfg->workspace) % ALIGN)
+            return bail(fail(IBM_LB_EINVAL, "workspace must be 256-byte aligned"));
+        h->ws = (char*)cfg->workspace;
+        h->ws_bytes = cfg->workspace_bytes;
+    } else {
+        e = hipMalloc((void**)&h->ws, h->lay.total);
+        if (e != hipSuccess) return bail(fail(IBM_LB_ENOMEM, "hipMalloc of the workspace failed"));
+        h->own_ws = true;
+        h->ws_bytes = h->lay.total;
+    }
+    e = hipHostMalloc((void**)&h->stage, sizeof(double) * 9 * ACAP, hipHostMallocDefault);
+    if (e != hipSuccess) return bail(fail(IBM_LB_ENOMEM, "pinned staging allocation"));
+    e = hipEventCreateWithFlags(&h->stage_done, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(hip_fail(e, "hipEventCreate"));
+    e = hipEventRecord(h->stage_done, h->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "hipEventRecord"));
+
+    char* b = h->ws;
+    const Layout& L = h->lay;
+    DevPtrs& d = h->d;
+    d.f[0] = b + L.f[0];
+    d.f[1] = b + L.f[1];
+    d.F = b + L.F;
+    d.u = b + L.u;
+    d.mark = (int*)(b + L.mark);
+    d.ctl = (Ctl*)(b + L.ctl);
+    d.r = b + L.r;
+    d.o = b + L.o;
+    d.qa = b + L.qa;
+    d.qb = b + L.qb;
+    d.pp = b + L.pp;
+    d.bb = b + L.bb;
+    d.phi = b + L.phi;
+    d.tris = (int4*)(b + L.tris);
+    d.vt_start = (int*)(b + L.vt_start);
+    d.vt_list = (int*)(b + L.vt_list);
+    d.nb_start = (int*)(b + L.nb_start);
+    d.nb_list = (int*)(b + L.nb_list);
+    d.obs_part = (double*)(b + L.obs_part);
+    d.mass_part = (double*)(b + L.mass_part);
+    d.obs_out = (double*)(b + L.obs_out);
+    d.Abuf = (double*)(b + L.Abuf);
+
+    // Zero the fields that must start at zero (force, velocity, marks, control).
+    const size_t rb = real_bytes(h->storage);
+#define INIT_TRY(expr, where)                        \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return bail(hip_fail(e_, where)); \
+    } while (0)
+    INIT_TRY(hipMemsetAsync(d.F, 0, 3 * rb * (size_t)h->g.N, h->stream), "zero F");
+    INIT_TRY(hipMemsetAsync(d.u, 0, 3 * rb * (size_t)h->g.N, h->stream), "zero u");
+    INIT_TRY(hipMemsetAsync(d.mark, 0, sizeof(int) * (size_t)ntiles, h->stream), "zero marks");
+    Ctl ctl0{};
+    ctl0.epoch = 1;
+    INIT_TRY(hipMemcpyAsync(d.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice, h->stream), "ctl");
+    INIT_TRY(hipStreamSynchronize(h->stream), "sync");  // ctl0 is a stack value
+    // initial gradient in the last-gradient slot; the initial populations read it
+    double* slot = d.Abuf + 9ll * ACAP;
+    INIT_TRY(hipMemcpy(slot, cfg->A0, 9 * sizeof(double), hipMemcpyHostToDevice), "A0");
+    if (h->nv > 0) {
+        std::vector<int4> tris(h->nt);
+        for (int t = 0; t < h->nt; ++t)
+            tris[t] = int4{cfg->triangles[3 * t], cfg->triangles[3 * t + 1], cfg->triangles[3 * t + 2], 0};
+        INIT_TRY(hipMemcpy(d.tris, tris.data(), sizeof(int4) * h->nt, hipMemcpyHostToDevice), "tris");
+        INIT_TRY(hipMemcpy(d.vt_start, csr.vt_start.data(), sizeof(int) * csr.vt_start.size(),
+                           hipMemcpyHostToDevice), "vt_start");
+        INIT_TRY(hipMemcpy(d.vt_list, csr.vt_list.data(), sizeof(int) * csr.vt_list.size(),
+                           hipMemcpyHostToDevice), "vt_list");
+        INIT_TRY(hipMemcpy(d.nb_start, csr.nb_start.data(), sizeof(int) * csr.nb_start.size(),
+                           hipMemcpyHostToDevice), "nb_start");
+        INIT_TRY(hipMemcpy(d.nb_list, csr.nb_list.data(), sizeof(int) * csr.nb_list.size(),
+                           hipMemcpyHostToDevice), "nb_list");
+        double* tmp = nullptr;
+        INIT_TRY(hipMalloc((void**)&tmp, sizeof(double) * 3 * h->nv), "vertex upload buffer");
+        hipError_t e1 = hipMemcpy(tmp, cfg->vertices, sizeof(double) * 3 * h->nv, hipMemcpyHostToDevice);
+        hipError_t e2 = e1 == hipSuccess
+                            ? launch_positions_from_abs(h->storage, h->g, d, h->nv, tmp, h->stream)
+                            : e1;
+        hipError_t e3 = hipStreamSynchronize(h->stream);
+        (void)hipFree(tmp);
+        if (e2 != hipSuccess) return bail(hip_fail(e2, "vertex upload"));
+        if (e3 != hipSuccess) return bail(hip_fail(e3, "vertex upload"));
+    }
+    INIT_TRY(launch_init(h->storage, h->g, h->lp, d, slot, cfg->init == IBM_LB_INIT_REST, h->stream),
+             "init launch");
+#undef INIT_TRY
+    *out = h;
+    return IBM_LB_OK;
+}
+
+int ibm_lb_step_table(ibm_lb* h, const double* A, int32_t nsteps, int32_t on_device) {
+    if (!h || !A || nsteps < 0) return fail(IBM_LB_EINVAL, "bad step arguments");
+    if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
+    int rc = set_device(h);
+    if (rc) return rc;
+    if (on_device) return enqueue_steps(h, A, nsteps, 1);
+    for (int done = 0; done < nsteps;) {
+        int n = std::min(nsteps - done, ACAP);
+        rc = upload_rows(h, A + 9ll * done, n);
+        if (rc) return rc;
+        rc = enqueue_steps(h, h->d.Abuf, n, 1);
+        if (rc) return rc;
+        done += n;
+    }
+    return IBM_LB_OK;
+}
+
+int ibm_lb_step(ibm_lb* h, const double A[9], int32_t nsteps) {
+    if (!h || !A || nsteps < 0) return fail(IBM_LB_EINVAL, "bad step arguments");
+    if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
+    int rc = set_device(h);
+    if (rc) return rc;
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(A[k])) return fail(IBM_LB_EINVAL, "gradient not finite");
+    rc = upload_rows(h, A, 1);
+    if (rc) return rc;
+    return enqueue_steps(h, h->d.Abuf, nsteps, 0);
+}
+
+int ibm_lb_observables(ibm_lb* h, ibm_lb_obs* out) {
+    if (!h || !out) return fail(IBM_LB_EINVAL, "bad observables arguments");
+    int rc = set_device(h);
+    if (rc) return rc;
+    HIP_TRY(launch_observables(h->storage, h->g, h->lp, h->d, h->cur, h->nv, h->nt, h->cfg.radius,
+                               h->d.Abuf + 9ll * ACAP, h->stream),
+            "observables launch");
+    double o[OBS_OUT_N];
+    HIP_TRY(hipMemcpyAsync(o, h->d.obs_out, sizeof(o), hipMemcpyDeviceToHost, h->stream), "observables copy");
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    memset(out, 0, sizeof(*out));
+    out->step = h->step;
+    const double xc[3] = {h->g.xci[0] + h->g.xcf[0], h->g.xci[1] + h->g.xcf[1], h->g.xci[2] + h->g.xcf[2]};
+    out->volume = o[0];
+    for (int a = 0; a < 3; ++a) out->centroid[a] = h->nv ? o[1 + a] + xc[a] : 0.0;
+    for (int k = 0; k < 9; ++k) out->S[k] = o[4 + k];
+    for (int k = 0; k < 3; ++k) out->eigval[k] = o[13 + k];
+    for (int k = 0; k < 9; ++k) out->eigvec[k] = o[16 + k];
+    out->D = o[25];
+    out->beta = o[26];
+    out->theta_deg = o[27];
+    out->flags = (int)o[28];
+    out->mass = (double)h->g.N * h->cfg.rho0 + o[29];
+    for (int a = 0; a < 3; ++a) out->momentum[a] = o[30 + a];
+    out->reg_iters = (int)o[33];
+    if (o[34] > 0) out->flags |= IBM_LB_OBS_REG_CAP;
+    return IBM_LB_OK;
+}
+
+int ibm_lb_read_vertices(ibm_lb* h, double* out) {
+    if (!h || (!out && h->nv)) return fail(IBM_LB_EINVAL, "bad read_vertices arguments");
+    if (h->nv == 0) return IBM_LB_OK;
+    int rc = set_device(h);
+    if (rc) return rc;
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc((void**)&tmp, sizeof(double) * 3 * h->nv), "hipMalloc");
+    hipError_t e = launch_positions_to_abs(h->storage, h->g, h->d, h->nv, tmp, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, tmp, sizeof(double) * 3 * h->nv, hipMemcpyDeviceToHost, h->stream);
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "read vertices");
+    if (e2 != hipSuccess) return hip_fail(e2, "read vertices");
+    return check_flags(h);
+}
+
+int ibm_lb_read_field(ibm_lb* h, int32_t which, double* out) {
+    if (!h || !out || (which != IBM_LB_FIELD_RHO && which != IBM_LB_FIELD_U))
+        return fail(IBM_LB_EINVAL, "bad read_field arguments");
+    int rc = set_device(h);
+    if (rc) return rc;
+    const size_t N = (size_t)h->g.N;
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc((void**)&tmp, sizeof(double) * 4 * N), "hipMalloc");
+    const bool ib = which == IBM_LB_FIELD_U && h->nv > 0;
+    hipError_t e = hipSuccess;
+    if (ib) {
+        e = launch_forces(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->stream);
+        if (e == hipSuccess) e = launch_spread(h->storage, h->g, h->d, h->nv, h->stream);
+    }
+    if (e == hipSuccess) e = launch_moments(h->storage, h->g, h->lp, h->d, h->cur, ib, tmp, tmp + N, h->stream);
+    if (e == hipSuccess && ib) e = launch_bump_epoch(h->d, h->stream);
+    if (e == hipSuccess) {
+        const double* src = which == IBM_LB_FIELD_RHO ? tmp : tmp + N;
+        size_t cnt = which == IBM_LB_FIELD_RHO ? N : 3 * N;
+        e = hipMemcpyAsync(out, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, h->stream);
+    }
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "read field");
+    if (e2 != hipSuccess) return hip_fail(e2, "read field");
+    return check_flags(h);
+}
+
+namespace {
+struct StateHeader {
+    int64_t magic, storage, N, nv, step, pad[3];
+};
+constexpr int64_t STATE_MAGIC = 0x49424d4c42535431ll;
+}  // namespace
+
+size_t ibm_lb_state_bytes(const ibm_lb* h) {
+    if (!h) return 0;
+    return sizeof(StateHeader) + 19ull * h->g.N * storage_bytes(h->storage) +
+           4ull * real_bytes(h->storage) * h->nv;
+}
+
+int ibm_lb_save(ibm_lb* h, void* dst, size_t n) {
+    if (!h || !dst || n < ibm_lb_state_bytes(h)) return fail(IBM_LB_EINVAL, "bad save arguments");
+    int rc = set_device(h);
+    if (rc) return rc;
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    StateHeader hd{STATE_MAGIC, h->storage, h->g.N, h->nv, h->step, {0, 0, 0}};
+    char* p = (char*)dst;
+    HIP_TRY(hipMemcpy(p, &hd, sizeof(hd), hipMemcpyDefault), "save header");
+    const size_t fb = 19ull * h->g.N * storage_bytes(h->storage);
+    HIP_TRY(hipMemcpy(p + sizeof(hd), h->d.f[h->cur], fb, hipMemcpyDefault), "save populations");
+    HIP_TRY(hipMemcpy(p + sizeof(hd) + fb, h->d.r, 4ull * real_bytes(h->storage) * h->nv, hipMemcpyDefault),
+            "save vertices");
+    return IBM_LB_OK;
+}
+
+int ibm_lb_load(ibm_lb* h, const void* src, size_t n) {
+    if (!h || !src || n < ibm_lb_state_bytes(h)) return fail(IBM_LB_EINVAL, "bad load arguments");
+    int rc = set_device(h);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    StateHeader hd;
+    const char* p = (const char*)src;
+    HIP_TRY(hipMemcpy(&hd, p, sizeof(hd), hipMemcpyDefault), "load header");
+    if (hd.magic != STATE_MAGIC || hd.storage != h->storage || hd.N != h->g.N || hd.nv != h->nv)
+        return fail(IBM_LB_EINVAL, "checkpoint does not match this configuration");
+    const size_t fb = 19ull * h->g.N * storage_bytes(h->storage);
+    HIP_TRY(hipMemcpy(h->d.f[h->cur], p + sizeof(hd), fb, hipMemcpyDefault), "load populations");
+    HIP_TRY(hipMemcpy(h->d.r, p + sizeof(hd) + fb, 4ull * real_bytes(h->storage) * h->nv, hipMemcpyDefault),
+            "load vertices");
+    h->step = hd.step;
+    h->sticky = IBM_LB_OK;
+    Ctl c;
+    HIP_TRY(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost), "ctl");
+    c.flags = 0;
+    c.cap_hits = 0;
+    HIP_TRY(hipMemcpy(h->d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice), "ctl");
+    return IBM_LB_OK;
+}
+
+int ibm_lb_timing_enable(ibm_lb* h, int32_t enable) {
+    if (!h) return fail(IBM_LB_EINVAL, "handle is NULL");
+    h->timing = enable != 0;
+    return IBM_LB_OK;
+}
+
+int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches) {
+    if (!h || !lattice_ms || !launches) return fail(IBM_LB_EINVAL, "bad timing arguments");
+    int rc = set_device(h);
+    if (rc) return rc;
+    rc = accumulate_timing(h);
+    if (rc) return rc;
+    *lattice_ms = h->acc_ms;
+    *launches = h->launches;
+    h->acc_ms = 0.0;
+    h->launches = 0;
+    return IBM_LB_OK;
+}
+
+void ibm_lb_destroy(ibm_lb* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& p : h->ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    if (h->stage_done) (void)hipEventDestroy(h->stage_done);
+    if (h->stage) (void)hipHostFree(h->stage);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ibm_lb.h"
+
+namespace ibmlb {
+
+// Device-side sticky flags (bit set by any thread that sees the condition).
+enum : int {
+    DFLAG_DOMAIN = 1,
+    DFLAG_NONFINITE = 2,
+};
+
+// IB tiles: 8x8x8 lattice nodes. A tile is "marked" for a step when some
+// vertex stencil touches it; only marked tiles carry force and velocity.
+constexpr int TILE_SHIFT = 3;
+
+// Positions on the GPU are stored relative to the box centre x_c so that
+// FP32 keeps the resolution of the droplet scale, not of the box scale.
+template <class R>
+struct alignas(4 * sizeof(R)) V4 {
+    R x, y, z, w;
+};
+
+// Geometry of one lattice as kernels see it.
+struct Geom {
+    int Lx, Ly, Lz;
+    int px, py, pz;          // periodic flags
+    int TX, TY, TZ;          // tile grid
+    long long N;             // nodes
+    int xci[3];              // floor(x_c)
+    double xcf[3];           // x_c - floor(x_c), 0 or 0.5
+};
+
+struct LatticeParams {
+    double omega;            // 1/tau
+    double kguo;             // 1 - 1/(2 tau)
+    double rho0;
+    double tau;
+    float scale, inv_scale;  // 16-bit deviation scaling
+};
+
+struct SmoothParams {
+    double alpha, gamma, tol;
+    int max_iter, sign;
+};
+
+// Control block in device memory.
+struct Ctl {
+    int epoch;               // step epoch used by tile marks
+    int flags;               // DFLAG_*
+    int iters;               // smoothing iterations of the last step
+    int cap_hits;            // steps that hit the smoothing cap since last read
+    int pad[60];
+};
+
+// Device pointers of one droplet system (types erased; real is double for
+// IBM_LB_F64, float otherwise).
+struct DevPtrs {
+    void* f[2];              // populations [19][N] in the storage type
+    void* F;                 // force density [3][N] (real)
+    void* u;                 // velocity [3][N] (real), valid in marked tiles
+    int* mark;               // [TX*TY*TZ]
+    Ctl* ctl;
+    void* r;                 // V4<real> [nv] current positions (relative to x_c)
+    void* o;                 // V4 [nv] after the Euler move
+    void* qa;                // V4 [nv] smoothing scratch
+    void* qb;
+    void* pp;
+    void* bb;
+    void* phi;               // V4 [nv] nodal forces
+    int4* tris;              // [nt]
+    int* vt_start;           // [nv+1] vertex -> incident (triangle << 2 | corner)
+    int* vt_list;            // [3 nt]
+    int* nb_start;           // [nv+1] one-ring neighbours
+    int* nb_list;            // [sum of valences]
+    double* obs_part;        // [OBS_BLOCKS][16]
+    double* mass_part;       // [MASS_BLOCKS][4]
+    double* obs_out;         // [48] final observables
+    double* Abuf;            // [ACAP][9] gradient rows
+};
+
+constexpr int OBS_BLOCKS = 128;
+constexpr int MASS_BLOCKS = 512;
+constexpr int ACAP = 4096;
+constexpr int OBS_OUT_N = 48;
+
+// Kernel launchers (kernels.hip). All enqueue on `s` and return the
+// hipError_t of the launch.
+hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
+                       const double* A0, int rest, hipStream_t s);
+hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
+                          int cur, bool ib, const double* A_row, hipStream_t s);
+hipError_t launch_forces(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
+                         hipStream_t s);
+hipError_t launch_spread(int storage, const Geom& g, const DevPtrs& d, int nv, hipStream_t s);
+hipError_t launch_interp(int storage, const Geom& g, const DevPtrs& d, int nv, hipStream_t s);
+hipError_t launch_smooth(int storage, const DevPtrs& d, int nv, const SmoothParams& sp,
+                         hipStream_t s);
+hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
+hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
+                          int cur, bool ib, double* rho_out, double* u_out, hipStream_t s);
+hipError_t launch_observables(int storage, const Geom& g, const LatticeParams& lp,
+                              const DevPtrs& d, int cur, int nv, int nt, double radius,
+                              const double* A_row, hipStream_t s);
+hipError_t launch_positions_to_abs(int storage, const Geom& g, const DevPtrs& d, int nv,
+                                   double* out, hipStream_t s);
+hipError_t launch_positions_from_abs(int storage, const Geom& g, const DevPtrs& d, int nv,
+                                     const double* in, hipStream_t s);
+
+size_t storage_bytes(int storage);
+size_t real_bytes(int storage);
+
+}  // namespace ibmlb

@@ -1,0 +1,885 @@
+// HIP kernels of the IB-LB droplet step for gfx950 (wave64).
+//
+// Method: arXiv 2403.01161 (Taglienti, Guglietta & Sbragaglia), Sec. 3.1
+// (D3Q19 BGK + Guo forcing, Peskin 4-point immersed boundary, moving walls)
+// and Sec. 3.3 (HC mesh smoothing); observables of Sec. 2.
+//
+// Layout: populations are SoA planes f[i][z][y][x] holding deviations
+// d_i = f_i - w_i rho0 from the rest equilibrium; force and velocity fields
+// are SoA [3][z][y][x] and are only touched inside the 8^3 tiles marked for
+// the current step; vertex data are AoS V4 records relative to the box centre.
+#include <math.h>
+
+#include "ibmlb_internal.h"
+
+namespace ibmlb {
+
+// ---------------------------------------------------------------- D3Q19
+// Index 0 is the rest population; 2p-1 and 2p (p = 1..9) are opposite.
+constexpr int Q = 19;
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+template <class R>
+__host__ __device__ constexpr R wgt(int i) {
+    return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
+}
+
+// ---------------------------------------------------------------- storage
+struct SF64 { using store_t = double; using real = double; };
+struct SF32 { using store_t = float; using real = float; };
+struct SF16 { using store_t = _Float16; using real = float; };
+struct SBF16 { using store_t = uint16_t; using real = float; };
+
+__device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+__device__ inline uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                          // round to nearest even
+    return uint16_t(u >> 16);
+}
+
+template <class C> __device__ inline typename C::real dec(typename C::store_t v, float inv);
+template <> __device__ inline double dec<SF64>(double v, float) { return v; }
+template <> __device__ inline float dec<SF32>(float v, float) { return v; }
+template <> __device__ inline float dec<SF16>(_Float16 v, float inv) { return float(v) * inv; }
+template <> __device__ inline float dec<SBF16>(uint16_t v, float) { return bf16_to_f32(v); }
+
+template <class C> __device__ inline typename C::store_t enc(typename C::real v, float sc);
+template <> __device__ inline double enc<SF64>(double v, float) { return v; }
+template <> __device__ inline float enc<SF32>(float v, float) { return v; }
+template <> __device__ inline _Float16 enc<SF16>(float v, float sc) { return _Float16(v * sc); }
+template <> __device__ inline uint16_t enc<SBF16>(float v, float) { return f32_to_bf16(v); }
+
+// ---------------------------------------------------------------- helpers
+__device__ inline int wrap(int j, int L) { return j < 0 ? j + L : (j >= L ? j - L : j); }
+
+// Peskin 4-point weights of the four nodes floor(s)-1 .. floor(s)+2 for a
+// coordinate with fractional part f in [0, 1). All four stencil arguments
+// (1+f, f, 1-f, 2-f) share the radicand 1 + 4f - 4f^2 of the two branches of
+// phi(x), so one square root serves the whole axis.
+template <class R>
+__device__ inline void peskin4(R f, R w[4]) {
+    R q = sqrt(R(1) + R(4) * f - R(4) * f * f);
+    w[0] = (R(3) - R(2) * f - q) * R(0.125);
+    w[1] = (R(3) - R(2) * f + q) * R(0.125);
+    w[2] = (R(1) + R(2) * f + q) * R(0.125);
+    w[3] = (R(1) + R(2) * f - q) * R(0.125);
+}
+
+// Stencil base along one axis: absolute node of the first stencil node and
+// the fractional part. Returns false if the position is not finite or the
+// stencil leaves a wall axis.
+template <class R>
+__device__ inline bool stencil_axis(R rel, int xci, double xcf, int L, int periodic, int* first,
+                                    R* frac) {
+    R s = rel + R(xcf);
+    if (!(fabs(s) < R(1e8))) return false;
+    R fl = floor(s);
+    *frac = s - fl;
+    int b = int(fl) + xci - 1;
+    if (periodic) {
+        int m = b % L;
+        *first = m < 0 ? m + L : m;
+        return true;
+    }
+    *first = b;
+    return b >= 0 && b + 3 <= L - 1;
+}
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- initial state
+template <class C>
+__global__ __launch_bounds__(256) void k_init(Geom g, LatticeParams lp, typename C::store_t* f,
+                                              const double* A0, int rest) {
+    long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    if (rest) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i * g.N + n] = enc<C>(typename C::real(0), lp.scale);
+        return;
+    }
+    int LxLy = g.Lx * g.Ly;
+    int z = int(n / LxLy), rem = int(n - (long long)z * LxLy), y = rem / g.Lx, x = rem - y * g.Lx;
+    double dx = x - (g.xci[0] + g.xcf[0]), dy = y - (g.xci[1] + g.xcf[1]),
+           dz = z - (g.xci[2] + g.xcf[2]);
+    double ux = A0[0] * dx + A0[1] * dy + A0[2] * dz;
+    double uy = A0[3] * dx + A0[4] * dy + A0[5] * dz;
+    double uz = A0[6] * dx + A0[7] * dy + A0[8] * dz;
+    double uu = ux * ux + uy * uy + uz * uz, tr = A0[0] + A0[4] + A0[8];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        double cAc = 0.0;
+        const int c[3] = {CX[i], CY[i], CZ[i]};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) cAc += c[a] * A0[3 * a + b] * c[b];
+        double w = wgt<double>(i);
+        // f_eq(rho0, u) - w rho0 plus the Chapman-Enskog non-equilibrium part
+        double dv = w * lp.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu) -
+                    3.0 * lp.tau * w * lp.rho0 * (cAc - tr / 3.0);
+        f[i * g.N + n] = enc<C>(typename C::real(dv), lp.scale);
+    }
+}
+
+// ---------------------------------------------------------------- fused lattice step
+// One thread per node: load the 19 deviations (coalesced), form rho and the
+// half-force-corrected u, relax with BGK plus the Guo source, and push each
+// post-collision population to its neighbour. A population whose target lies
+// beyond a wall is reflected into the opposite slot of the same node with
+// the moving-wall term -2 w_i rho0 c_i.u_w / cs^2, u_w = A (x + c_i/2 - x_c).
+template <class C, bool IB>
+__global__ __launch_bounds__(256) void k_lattice(Geom g, LatticeParams lp,
+                                                 const typename C::store_t* __restrict__ fin,
+                                                 typename C::store_t* __restrict__ fout,
+                                                 typename C::real* __restrict__ F,
+                                                 typename C::real* __restrict__ U,
+                                                 const int* __restrict__ mark, Ctl* ctl,
+                                                 const double* __restrict__ Arow) {
+    using R = typename C::real;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const long long N = g.N;
+    const int LxLy = g.Lx * g.Ly;
+    const int z = int(n / LxLy);
+    const int rem = int(n - (long long)z * LxLy);
+    const int y = rem / g.Lx;
+    const int x = rem - y * g.Lx;
+
+    R d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = dec<C>(fin[i * N + n], lp.inv_scale);
+
+    R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += d[i];
+        if (CX[i] == 1) jx += d[i];
+        if (CX[i] == -1) jx -= d[i];
+        if (CY[i] == 1) jy += d[i];
+        if (CY[i] == -1) jy -= d[i];
+        if (CZ[i] == 1) jz += d[i];
+        if (CZ[i] == -1) jz -= d[i];
+    }
+
+    R Fx = R(0), Fy = R(0), Fz = R(0);
+    bool marked = false;
+    if (IB) {
+        const int tile = (x >> TILE_SHIFT) + g.TX * ((y >> TILE_SHIFT) + g.TY * (z >> TILE_SHIFT));
+        marked = mark[tile] == ctl->epoch;
+        if (marked) {
+            Fx = F[n];
+            Fy = F[N + n];
+            Fz = F[2 * N + n];
+            // leave the force field zero for the next step's spreading
+            F[n] = R(0);
+            F[N + n] = R(0);
+            F[2 * N + n] = R(0);
+        }
+    }
+    const R rho = R(lp.rho0) + drho;
+    const R inv = R(1) / rho;
+    const R ux = (jx + R(0.5) * Fx) * inv;
+    const R uy = (jy + R(0.5) * Fy) * inv;
+    const R uz = (jz + R(0.5) * Fz) * inv;
+    if (IB && marked) {
+        U[n] = ux;
+        U[N + n] = uy;
+        U[2 * N + n] = uz;
+    }
+    if (!(rho > R(0)) || !isfinite(ux + uy + uz)) atomicOr(&ctl->flags, DFLAG_NONFINITE);
+
+    const R omega = R(lp.omega), kg = R(lp.kguo), rho0 = R(lp.rho0);
+    const R usq = ux * ux + uy * uy + uz * uz;
+    const R uF = ux * Fx + uy * Fy + uz * Fz;
+    R A[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) A[k] = R(Arow[k]);
+    const R xr = R(x - g.xci[0]) - R(g.xcf[0]);
+    const R yr = R(y - g.xci[1]) - R(g.xcf[1]);
+    const R zr = R(z - g.xci[2]) - R(g.xcf[2]);
+
+    auto push = [&](int i, R val) {
+        int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
+        bool wall = false;
+        if (CX[i] != 0 && (tx < 0 || tx >= g.Lx)) {
+            if (g.px) tx = wrap(tx, g.Lx); else wall = true;
+        }
+        if (CY[i] != 0 && (ty < 0 || ty >= g.Ly)) {
+            if (g.py) ty = wrap(ty, g.Ly); else wall = true;
+        }
+        if (CZ[i] != 0 && (tz < 0 || tz >= g.Lz)) {
+            if (g.pz) tz = wrap(tz, g.Lz); else wall = true;
+        }
+        if (!wall) {
+            fout[i * N + tx + (long long)g.Lx * (ty + (long long)g.Ly * tz)] = enc<C>(val, lp.scale);
+        } else {
+            const R wx = xr + R(0.5) * R(CX[i]), wy = yr + R(0.5) * R(CY[i]), wz = zr + R(0.5) * R(CZ[i]);
+            const R uwx = A[0] * wx + A[1] * wy + A[2] * wz;
+            const R uwy = A[3] * wx + A[4] * wy + A[5] * wz;
+            const R uwz = A[6] * wx + A[7] * wy + A[8] * wz;
+            const R cuw = R(CX[i]) * uwx + R(CY[i]) * uwy + R(CZ[i]) * uwz;
+            fout[opp(i) * N + n] = enc<C>(val - R(6) * wgt<R>(i) * rho0 * cuw, lp.scale);
+        }
+    };
+
+    {   // rest population
+        const R w = wgt<R>(0);
+        const R deq = w * (drho + rho * (R(-1.5) * usq));
+        const R S = kg * w * (R(-3) * uF);
+        fout[n] = enc<C>(d[0] - omega * (d[0] - deq) + S, lp.scale);
+    }
+#pragma unroll
+    for (int p = 1; p <= 9; ++p) {
+        const int i = 2 * p - 1, j = 2 * p;
+        const R w = wgt<R>(i);
+        const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+        const R cF = R(CX[i]) * Fx + R(CY[i]) * Fy + R(CZ[i]) * Fz;
+        const R sym = w * (drho + rho * (R(4.5) * cu * cu - R(1.5) * usq));
+        const R anti = w * rho * R(3) * cu;
+        const R Ssym = kg * w * (R(9) * cu * cF - R(3) * uF);
+        const R Santi = kg * w * R(3) * cF;
+        push(i, d[i] - omega * (d[i] - (sym + anti)) + Ssym + Santi);
+        push(j, d[j] - omega * (d[j] - (sym - anti)) + Ssym - Santi);
+    }
+}
+
+// Diagnostic moments: rho and u (with F/2) of the current populations.
+template <class C>
+__global__ __launch_bounds__(256) void k_moments(Geom g, LatticeParams lp,
+                                                 const typename C::store_t* __restrict__ fin,
+                                                 typename C::real* __restrict__ F,
+                                                 const int* __restrict__ mark, const Ctl* ctl,
+                                                 int ib, double* rho_out, double* u_out) {
+    using R = typename C::real;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const long long N = g.N;
+    const int LxLy = g.Lx * g.Ly;
+    const int z = int(n / LxLy), rem = int(n - (long long)z * LxLy), y = rem / g.Lx, x = rem - y * g.Lx;
+    R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        R v = dec<C>(fin[i * N + n], lp.inv_scale);
+        drho += v;
+        jx += R(CX[i]) * v;
+        jy += R(CY[i]) * v;
+        jz += R(CZ[i]) * v;
+    }
+    R Fx = R(0), Fy = R(0), Fz = R(0);
+    if (ib) {
+        const int tile = (x >> TILE_SHIFT) + g.TX * ((y >> TILE_SHIFT) + g.TY * (z >> TILE_SHIFT));
+        if (mark[tile] == ctl->epoch) {
+            Fx = F[n]; Fy = F[N + n]; Fz = F[2 * N + n];
+            F[n] = R(0); F[N + n] = R(0); F[2 * N + n] = R(0);
+        }
+    }
+    const R rho = R(lp.rho0) + drho;
+    rho_out[n] = double(rho);
+    u_out[n] = double((jx + R(0.5) * Fx) / rho);
+    u_out[N + n] = double((jy + R(0.5) * Fy) / rho);
+    u_out[2 * N + n] = double((jz + R(0.5) * Fz) / rho);
+}
+
+// FP64 mass and momentum partial sums (sum of deviations; the host adds N rho0).
+template <class C>
+__global__ __launch_bounds__(256) void k_mass(Geom g, LatticeParams lp,
+                                              const typename C::store_t* __restrict__ fin,
+                                              double* part) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+         n += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            double v = double(dec<C>(fin[i * g.N + n], lp.inv_scale));
+            s[0] += v;
+            s[1] += CX[i] * v;
+            s[2] += CY[i] * v;
+            s[3] += CZ[i] * v;
+        }
+    }
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v = wave_sum(s[k]);
+        if (lane == 0) red[k][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        int k = threadIdx.x;
+        part[blockIdx.x * 4 + k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    }
+}
+
+// ---------------------------------------------------------------- IB: forces + tile marks
+// phi_k = -sigma sum_{t ∋ k} dA_t/dr_k, dA_t/dr_k = n_t x (r_prev - r_next)/2
+// (Eq. pi_drop read as a uniform isotropic tension). The same thread marks the
+// 8^3 tiles its 4x4x4 stencil touches with the current epoch.
+template <class R>
+__global__ __launch_bounds__(256) void k_forces(Geom g, int nv, R sigma, const V4<R>* __restrict__ r,
+                                                const int4* __restrict__ tris,
+                                                const int* __restrict__ vt_start,
+                                                const int* __restrict__ vt_list, V4<R>* phi,
+                                                int* mark, Ctl* ctl) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    R fx = R(0), fy = R(0), fz = R(0);
+    const int e1 = vt_start[k + 1];
+    for (int e = vt_start[k]; e < e1; ++e) {
+        const int pk = vt_list[e];
+        const int4 t = tris[pk >> 2];
+        const int c = pk & 3;
+        const V4<R> a = r[t.x], b = r[t.y], cc = r[t.z];
+        const R e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
+        const R e2x = cc.x - a.x, e2y = cc.y - a.y, e2z = cc.z - a.z;
+        R nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+        const R len = sqrt(nx * nx + ny * ny + nz * nz);
+        if (len == R(0)) continue;
+        nx /= len; ny /= len; nz /= len;
+        // corner c: next = (c+1)%3, prev = (c+2)%3
+        V4<R> nxt = c == 0 ? b : (c == 1 ? cc : a);
+        V4<R> prv = c == 0 ? cc : (c == 1 ? a : b);
+        const R dx = prv.x - nxt.x, dy = prv.y - nxt.y, dz = prv.z - nxt.z;
+        fx -= sigma * R(0.5) * (ny * dz - nz * dy);
+        fy -= sigma * R(0.5) * (nz * dx - nx * dz);
+        fz -= sigma * R(0.5) * (nx * dy - ny * dx);
+    }
+    phi[k] = V4<R>{fx, fy, fz, R(0)};
+
+    const V4<R> p = r[k];
+    int s0[3];
+    R fr[3];
+    const bool okx = stencil_axis(p.x, g.xci[0], g.xcf[0], g.Lx, g.px, &s0[0], &fr[0]);
+    const bool oky = stencil_axis(p.y, g.xci[1], g.xcf[1], g.Ly, g.py, &s0[1], &fr[1]);
+    const bool okz = stencil_axis(p.z, g.xci[2], g.xcf[2], g.Lz, g.pz, &s0[2], &fr[2]);
+    if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) {
+        atomicOr(&ctl->flags, DFLAG_NONFINITE);
+        return;
+    }
+    if (!(okx && oky && okz)) {
+        atomicOr(&ctl->flags, DFLAG_DOMAIN);
+        return;
+    }
+    // distinct tiles of the four stencil nodes per axis (up to three when a
+    // periodic stencil wraps around a box side that is not a tile multiple)
+    const int L[3] = {g.Lx, g.Ly, g.Lz};
+    int tl[3][3], nt[3];
+    for (int a = 0; a < 3; ++a) {
+        nt[a] = 0;
+        for (int j = 0; j < 4; ++j) {
+            const int t = wrap(s0[a] + j, L[a]) >> TILE_SHIFT;
+            bool seen = false;
+            for (int m = 0; m < nt[a]; ++m) seen |= tl[a][m] == t;
+            if (!seen) tl[a][nt[a]++] = t;
+        }
+    }
+    const int ep = ctl->epoch;
+    for (int cz = 0; cz < nt[2]; ++cz)
+        for (int cy = 0; cy < nt[1]; ++cy)
+            for (int cx = 0; cx < nt[0]; ++cx)
+                mark[tl[0][cx] + g.TX * (tl[1][cy] + g.TY * tl[2][cz])] = ep;
+}
+
+// ---------------------------------------------------------------- IB: spreading
+// 16 lanes per vertex, lane = (dz, dy) row of the 4x4x4 stencil, 4 x-nodes
+// each; F(x) += phi_k Delta(r_k - x) with device-wide float atomics.
+template <class R>
+__global__ __launch_bounds__(256) void k_spread(Geom g, int nv, const V4<R>* __restrict__ r,
+                                                const V4<R>* __restrict__ phi, R* F) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = gid >> 4, l = gid & 15;
+    if (k >= nv) return;
+    const V4<R> p = r[k];
+    int s0[3];
+    R fr[3];
+    if (!stencil_axis(p.x, g.xci[0], g.xcf[0], g.Lx, g.px, &s0[0], &fr[0]) ||
+        !stencil_axis(p.y, g.xci[1], g.xcf[1], g.Ly, g.py, &s0[1], &fr[1]) ||
+        !stencil_axis(p.z, g.xci[2], g.xcf[2], g.Lz, g.pz, &s0[2], &fr[2]))
+        return;
+    const V4<R> fk = phi[k];
+    R wx[4], wy[4], wz[4];
+    peskin4(fr[0], wx);
+    peskin4(fr[1], wy);
+    peskin4(fr[2], wz);
+    const int jy = l & 3, jz = l >> 2;
+    const int ny = wrap(s0[1] + jy, g.Ly), nz = wrap(s0[2] + jz, g.Lz);
+    const R wyz = wy[jy] * wz[jz];
+    const long long N = g.N;
+    const long long row = (long long)g.Lx * (ny + (long long)g.Ly * nz);
+#pragma unroll
+    for (int jx = 0; jx < 4; ++jx) {
+        const long long node = row + wrap(s0[0] + jx, g.Lx);
+        const R w = wx[jx] * wyz;
+        unsafeAtomicAdd(F + node, fk.x * w);
+        unsafeAtomicAdd(F + N + node, fk.y * w);
+        unsafeAtomicAdd(F + 2 * N + node, fk.z * w);
+    }
+}
+
+// ---------------------------------------------------------------- IB: interpolation + Euler
+// U_k = sum_x u(x) Delta(r_k - x) over the 4x4x4 stencil (16 lanes per vertex,
+// reduced across the lane group), then o_k = r_k + U_k.
+template <class R>
+__global__ __launch_bounds__(256) void k_interp(Geom g, int nv, const V4<R>* __restrict__ r,
+                                                const R* __restrict__ U, V4<R>* o) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = gid >> 4, l = gid & 15;
+    const bool active = k < nv;
+    R ax = R(0), ay = R(0), az = R(0);
+    V4<R> p = V4<R>{R(0), R(0), R(0), R(0)};
+    bool ok = false;
+    if (active) {
+        p = r[k];
+        int s0[3];
+        R fr[3];
+        ok = stencil_axis(p.x, g.xci[0], g.xcf[0], g.Lx, g.px, &s0[0], &fr[0]) &&
+             stencil_axis(p.y, g.xci[1], g.xcf[1], g.Ly, g.py, &s0[1], &fr[1]) &&
+             stencil_axis(p.z, g.xci[2], g.xcf[2], g.Lz, g.pz, &s0[2], &fr[2]);
+        if (ok) {
+            R wx[4], wy[4], wz[4];
+            peskin4(fr[0], wx);
+            peskin4(fr[1], wy);
+            peskin4(fr[2], wz);
+            const int jy = l & 3, jz = l >> 2;
+            const int ny = wrap(s0[1] + jy, g.Ly), nz = wrap(s0[2] + jz, g.Lz);
+            const R wyz = wy[jy] * wz[jz];
+            const long long N = g.N;
+            const long long row = (long long)g.Lx * (ny + (long long)g.Ly * nz);
+#pragma unroll
+            for (int jx = 0; jx < 4; ++jx) {
+                const long long node = row + wrap(s0[0] + jx, g.Lx);
+                const R w = wx[jx] * wyz;
+                ax += U[node] * w;
+                ay += U[N + node] * w;
+                az += U[2 * N + node] * w;
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 8; m > 0; m >>= 1) {
+        ax += __shfl_xor(ax, m, 16);
+        ay += __shfl_xor(ay, m, 16);
+        az += __shfl_xor(az, m, 16);
+    }
+    if (active && l == 0) o[k] = V4<R>{p.x + ax, p.y + ay, p.z + az, R(0)};
+}
+
+// ---------------------------------------------------------------- HC smoothing
+// One work-group runs the whole data-dependent iteration of Sec. 3.3:
+//   x_q = x_p; x_p = alpha x_o + (1-alpha) mean_nb(x_q);
+//   x_b = x_p - (alpha x_o + (1-alpha) x_q);
+//   x_p -= gamma x_b + sign (1-gamma) mean_nb(x_b);
+// until max |x_p - x_q| < tol or max_iter iterations, then r = x_p. The
+// work-group barrier orders the passes; the exit test is work-group uniform.
+template <class R>
+__global__ __launch_bounds__(1024) void k_smooth(int nv, SmoothParams sp, const V4<R>* __restrict__ o,
+                                                 V4<R>* qa, V4<R>* qb, V4<R>* P, V4<R>* B,
+                                                 const int* __restrict__ nb_start,
+                                                 const int* __restrict__ nb_list, V4<R>* r_out,
+                                                 Ctl* ctl) {
+    __shared__ R red[16];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const R alpha = R(sp.alpha), gamma = R(sp.gamma), tol = R(sp.tol), sgn = R(sp.sign);
+    int it = 0;
+    bool capped = false;
+    V4<R>* q = qa;
+    V4<R>* qn = qb;
+    if (sp.max_iter > 0) {
+        for (int k = tid; k < nv; k += nth) q[k] = o[k];
+        __syncthreads();
+        for (;;) {
+            ++it;
+            for (int k = tid; k < nv; k += nth) {
+                const int e0 = nb_start[k], e1 = nb_start[k + 1];
+                R sx = R(0), sy = R(0), sz = R(0);
+                for (int e = e0; e < e1; ++e) {
+                    const V4<R> v = q[nb_list[e]];
+                    sx += v.x; sy += v.y; sz += v.z;
+                }
+                const R c = (R(1) - alpha) / R(e1 - e0);
+                const V4<R> ok = o[k], qk = q[k];
+                const R px = alpha * ok.x + c * sx, py = alpha * ok.y + c * sy, pz = alpha * ok.z + c * sz;
+                P[k] = V4<R>{px, py, pz, R(0)};
+                B[k] = V4<R>{px - (alpha * ok.x + (R(1) - alpha) * qk.x),
+                             py - (alpha * ok.y + (R(1) - alpha) * qk.y),
+                             pz - (alpha * ok.z + (R(1) - alpha) * qk.z), R(0)};
+            }
+            __syncthreads();
+            R dmax = R(0);
+            for (int k = tid; k < nv; k += nth) {
+                const int e0 = nb_start[k], e1 = nb_start[k + 1];
+                R sx = R(0), sy = R(0), sz = R(0);
+                for (int e = e0; e < e1; ++e) {
+                    const V4<R> v = B[nb_list[e]];
+                    sx += v.x; sy += v.y; sz += v.z;
+                }
+                const R c = sgn * (R(1) - gamma) / R(e1 - e0);
+                const V4<R> bk = B[k], pk = P[k], qk = q[k];
+                const R nx = pk.x - (gamma * bk.x + c * sx);
+                const R ny = pk.y - (gamma * bk.y + c * sy);
+                const R nz = pk.z - (gamma * bk.z + c * sz);
+                qn[k] = V4<R>{nx, ny, nz, R(0)};
+                const R dx = nx - qk.x, dy = ny - qk.y, dz = nz - qk.z;
+                dmax = fmax(dmax, sqrt(dx * dx + dy * dy + dz * dz));
+            }
+            for (int m = 32; m > 0; m >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, m, 64));
+            if ((tid & 63) == 0) red[tid >> 6] = dmax;
+            __syncthreads();
+            R all = red[0];
+            for (int w = 1; w < (nth + 63) / 64; ++w) all = fmax(all, red[w]);
+            __syncthreads();
+            if (all < tol) break;
+            if (it >= sp.max_iter) {
+                capped = true;
+                break;
+            }
+            V4<R>* t = q;
+            q = qn;
+            qn = t;
+        }
+        for (int k = tid; k < nv; k += nth) r_out[k] = qn[k];
+    } else {
+        for (int k = tid; k < nv; k += nth) r_out[k] = o[k];
+    }
+    if (tid == 0) {
+        ctl->iters = it;
+        if (capped) ctl->cap_hits += 1;
+        ctl->epoch += 1;
+    }
+}
+
+__global__ void k_bump_epoch(Ctl* ctl) {
+    if (threadIdx.x == 0) ctl->epoch += 1;
+}
+
+// ---------------------------------------------------------------- observables (FP64)
+// Signed tetrahedra (x_c, a, b, c) of every triangle: V_t = a.(b x c)/6,
+// int x dV = V_t (a+b+c)/4, int x x^T dV = V_t/20 (aa^T+bb^T+cc^T+ss^T).
+template <class R>
+__global__ __launch_bounds__(256) void k_obs_partial(int nt, const int4* __restrict__ tris,
+                                                     const V4<R>* __restrict__ r, double* part) {
+    double s[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) s[k] = 0.0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x) {
+        const int4 tr = tris[t];
+        const V4<R> pa = r[tr.x], pb = r[tr.y], pc = r[tr.z];
+        const double a[3] = {double(pa.x), double(pa.y), double(pa.z)};
+        const double b[3] = {double(pb.x), double(pb.y), double(pb.z)};
+        const double c[3] = {double(pc.x), double(pc.y), double(pc.z)};
+        const double bxc0 = b[1] * c[2] - b[2] * c[1], bxc1 = b[2] * c[0] - b[0] * c[2],
+                     bxc2 = b[0] * c[1] - b[1] * c[0];
+        const double V = (a[0] * bxc0 + a[1] * bxc1 + a[2] * bxc2) / 6.0;
+        const double sx = a[0] + b[0] + c[0], sy = a[1] + b[1] + c[1], sz = a[2] + b[2] + c[2];
+        s[0] += V;
+        s[1] += V * sx * 0.25;
+        s[2] += V * sy * 0.25;
+        s[3] += V * sz * 0.25;
+        const double v20 = V / 20.0;
+        s[4] += v20 * (a[0] * a[0] + b[0] * b[0] + c[0] * c[0] + sx * sx);
+        s[5] += v20 * (a[1] * a[1] + b[1] * b[1] + c[1] * c[1] + sy * sy);
+        s[6] += v20 * (a[2] * a[2] + b[2] * b[2] + c[2] * c[2] + sz * sz);
+        s[7] += v20 * (a[0] * a[1] + b[0] * b[1] + c[0] * c[1] + sx * sy);
+        s[8] += v20 * (a[0] * a[2] + b[0] * b[2] + c[0] * c[2] + sx * sz);
+        s[9] += v20 * (a[1] * a[2] + b[1] * b[2] + c[1] * c[2] + sy * sz);
+    }
+    __shared__ double red[10][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        double v = wave_sum(s[k]);
+        if (lane == 0) red[k][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const int k = threadIdx.x;
+        part[blockIdx.x * 16 + k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    }
+}
+
+// Symmetric 3x3 eigenpairs by cyclic Jacobi rotations (FP64), descending, each
+// eigenvector with its largest-magnitude component positive.
+__device__ void jacobi3(const double S[9], double ev[3], double vec[9]) {
+    double a[3][3], v[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            a[i][j] = 0.5 * (S[3 * i + j] + S[3 * j + i]);
+            v[i][j] = i == j ? 1.0 : 0.0;
+        }
+    const double scale = fabs(a[0][0]) + fabs(a[1][1]) + fabs(a[2][2]) + fabs(a[0][1]) +
+                         fabs(a[0][2]) + fabs(a[1][2]);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        const double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+        if (off == 0.0 || off <= 1e-15 * scale) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (a[p][q] == 0.0) continue;
+                const double th = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < 3; ++k) {
+                    const double x = a[k][p], y = a[k][q];
+                    a[k][p] = c * x - s * y;
+                    a[k][q] = s * x + c * y;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double x = a[p][k], y = a[q][k];
+                    a[p][k] = c * x - s * y;
+                    a[q][k] = s * x + c * y;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double x = v[k][p], y = v[k][q];
+                    v[k][p] = c * x - s * y;
+                    v[k][q] = s * x + c * y;
+                }
+            }
+    }
+    int o[3] = {0, 1, 2};
+    for (int i = 0; i < 3; ++i)
+        for (int j = i + 1; j < 3; ++j)
+            if (a[o[j]][o[j]] > a[o[i]][o[i]]) {
+                const int t = o[i];
+                o[i] = o[j];
+                o[j] = t;
+            }
+    for (int k = 0; k < 3; ++k) {
+        const int col = o[k];
+        ev[k] = a[col][col];
+        int big = 0;
+        for (int i = 1; i < 3; ++i)
+            if (fabs(v[i][col]) > fabs(v[big][col])) big = i;
+        const double sg = v[big][col] < 0.0 ? -1.0 : 1.0;
+        for (int i = 0; i < 3; ++i) vec[3 * k + i] = sg * v[i][col];
+    }
+}
+
+// Output layout (doubles): 0 volume, 1..3 centroid (relative to x_c),
+// 4..12 S, 13..15 eigval, 16..24 eigvec, 25 D, 26 beta, 27 theta_deg,
+// 28 flags, 29 sum of deviations, 30..32 momentum, 33 iters, 34 cap hits.
+__global__ void k_obs_final(int nblocks, const double* part, int mblocks, const double* mpart,
+                            const double* Arow, double radius, int has_mesh, Ctl* ctl,
+                            double* out) {
+    if (threadIdx.x != 0) return;
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < mblocks; ++b)
+        for (int k = 0; k < 4; ++k) m[k] += mpart[4 * b + k];
+    for (int k = 0; k < OBS_OUT_N; ++k) out[k] = 0.0;
+    out[29] = m[0];
+    out[30] = m[1];
+    out[31] = m[2];
+    out[32] = m[3];
+    out[33] = ctl->iters;
+    out[34] = ctl->cap_hits;
+    ctl->cap_hits = 0;
+    if (!has_mesh) return;
+    double s[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < nblocks; ++b)
+        for (int k = 0; k < 10; ++k) s[k] += part[16 * b + k];
+    const double V = s[0];
+    const double xb[3] = {s[1] / V, s[2] / V, s[3] / V};
+    const double M[9] = {s[4], s[7], s[8], s[7], s[5], s[9], s[8], s[9], s[6]};
+    double S[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[3 * a + b] = 5.0 / V * (M[3 * a + b] - V * xb[a] * xb[b]);
+    double ev[3], vec[9];
+    jacobi3(S, ev, vec);
+    const double D = (sqrt(ev[0]) - sqrt(ev[2])) / (sqrt(ev[0]) + sqrt(ev[2]));
+    double E[9], En = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            E[3 * a + b] = 0.5 * (Arow[3 * a + b] + Arow[3 * b + a]);
+            En += E[3 * a + b] * E[3 * a + b];
+        }
+    En = sqrt(En);
+    int flags = 0;
+    if (ev[0] - ev[1] < 1e-12 * radius * radius) flags |= IBM_LB_OBS_DEGENERATE;
+    if (En == 0.0) flags |= IBM_LB_OBS_E_ZERO;
+    double beta = __builtin_nan(""), theta = __builtin_nan("");
+    if (!(flags & IBM_LB_OBS_DEGENERATE)) {
+        theta = atan2(vec[1], vec[0]) * (180.0 / 3.14159265358979323846);
+        if (theta > 90.0) theta -= 180.0;
+        if (theta <= -90.0) theta += 180.0;
+        if (!(flags & IBM_LB_OBS_E_ZERO)) {
+            double q = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) q += vec[a] * E[3 * a + b] * vec[b];
+            beta = q / En;
+        }
+    }
+    out[0] = V;
+    for (int a = 0; a < 3; ++a) out[1 + a] = xb[a];
+    for (int k = 0; k < 9; ++k) out[4 + k] = S[k];
+    for (int k = 0; k < 3; ++k) out[13 + k] = ev[k];
+    for (int k = 0; k < 9; ++k) out[16 + k] = vec[k];
+    out[25] = D;
+    out[26] = beta;
+    out[27] = theta;
+    out[28] = flags;
+}
+
+// ---------------------------------------------------------------- position transfer
+template <class R>
+__global__ void k_pos_to_abs(Geom g, int nv, const V4<R>* r, double* out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    const V4<R> p = r[k];
+    out[3 * k + 0] = double(p.x) + (g.xci[0] + g.xcf[0]);
+    out[3 * k + 1] = double(p.y) + (g.xci[1] + g.xcf[1]);
+    out[3 * k + 2] = double(p.z) + (g.xci[2] + g.xcf[2]);
+}
+
+template <class R>
+__global__ void k_pos_from_abs(Geom g, int nv, const double* in, V4<R>* r) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    r[k] = V4<R>{R(in[3 * k + 0] - (g.xci[0] + g.xcf[0])), R(in[3 * k + 1] - (g.xci[1] + g.xcf[1])),
+                 R(in[3 * k + 2] - (g.xci[2] + g.xcf[2])), R(0)};
+}
+
+// ---------------------------------------------------------------- launchers
+size_t storage_bytes(int storage) {
+    switch (storage) {
+        case IBM_LB_F64: return 8;
+        case IBM_LB_F32: return 4;
+        default: return 2;
+    }
+}
+size_t real_bytes(int storage) { return storage == IBM_LB_F64 ? 8 : 4; }
+
+static inline unsigned blocks_for(long long n, int bs) { return unsigned((n + bs - 1) / bs); }
+
+#define DISPATCH_STORAGE(storage, C, ...)                  \
+    switch (storage) {                                     \
+        case IBM_LB_F64: { using C = SF64; __VA_ARGS__; break; }  \
+        case IBM_LB_F32: { using C = SF32; __VA_ARGS__; break; }  \
+        case IBM_LB_F16DEV: { using C = SF16; __VA_ARGS__; break; } \
+        default: { using C = SBF16; __VA_ARGS__; break; }  \
+    }
+
+hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
+                       const double* A0, int rest, hipStream_t s) {
+    DISPATCH_STORAGE(storage, C, {
+        hipLaunchKernelGGL(k_init<C>, dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
+                           (typename C::store_t*)d.f[0], A0, rest);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
+                          int cur, bool ib, const double* A_row, hipStream_t s) {
+    DISPATCH_STORAGE(storage, C, {
+        using R = typename C::real;
+        using S = typename C::store_t;
+        if (ib)
+            hipLaunchKernelGGL((k_lattice<C, true>), dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
+                               (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl,
+                               A_row);
+        else
+            hipLaunchKernelGGL((k_lattice<C, false>), dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
+                               (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl,
+                               A_row);
+    });
+    return hipGetLastError();
+}
+
+#define DISPATCH_REAL(storage, R, ...)                                   \
+    if ((storage) == IBM_LB_F64) { using R = double; __VA_ARGS__; }     \
+    else { using R = float; __VA_ARGS__; }
+
+hipError_t launch_forces(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
+                         hipStream_t s) {
+    DISPATCH_REAL(storage, R, {
+        hipLaunchKernelGGL(k_forces<R>, dim3(blocks_for(nv, 256)), dim3(256), 0, s, g, nv, R(sigma),
+                           (const V4<R>*)d.r, d.tris, d.vt_start, d.vt_list, (V4<R>*)d.phi, d.mark,
+                           d.ctl);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_spread(int storage, const Geom& g, const DevPtrs& d, int nv, hipStream_t s) {
+    DISPATCH_REAL(storage, R, {
+        hipLaunchKernelGGL(k_spread<R>, dim3(blocks_for(16LL * nv, 256)), dim3(256), 0, s, g, nv,
+                           (const V4<R>*)d.r, (const V4<R>*)d.phi, (R*)d.F);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(int storage, const Geom& g, const DevPtrs& d, int nv, hipStream_t s) {
+    DISPATCH_REAL(storage, R, {
+        hipLaunchKernelGGL(k_interp<R>, dim3(blocks_for(16LL * nv, 256)), dim3(256), 0, s, g, nv,
+                           (const V4<R>*)d.r, (const R*)d.u, (V4<R>*)d.o);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth(int storage, const DevPtrs& d, int nv, const SmoothParams& sp,
+                         hipStream_t s) {
+    DISPATCH_REAL(storage, R, {
+        hipLaunchKernelGGL(k_smooth<R>, dim3(1), dim3(1024), 0, s, nv, sp, (const V4<R>*)d.o,
+                           (V4<R>*)d.qa, (V4<R>*)d.qb, (V4<R>*)d.pp, (V4<R>*)d.bb, d.nb_start,
+                           d.nb_list, (V4<R>*)d.r, d.ctl);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, s, d.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
+                          int cur, bool ib, double* rho_out, double* u_out, hipStream_t s) {
+    DISPATCH_STORAGE(storage, C, {
+        using R = typename C::real;
+        hipLaunchKernelGGL(k_moments<C>, dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
+                           (const typename C::store_t*)d.f[cur], (R*)d.F, d.mark, d.ctl, ib ? 1 : 0,
+                           rho_out, u_out);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_observables(int storage, const Geom& g, const LatticeParams& lp,
+                              const DevPtrs& d, int cur, int nv, int nt, double radius,
+                              const double* A_row, hipStream_t s) {
+    DISPATCH_STORAGE(storage, C, {
+        hipLaunchKernelGGL(k_mass<C>, dim3(MASS_BLOCKS), dim3(256), 0, s, g, lp,
+                           (const typename C::store_t*)d.f[cur], d.mass_part);
+    });
+    if (nv > 0) {
+        DISPATCH_REAL(storage, R, {
+            hipLaunchKernelGGL(k_obs_partial<R>, dim3(OBS_BLOCKS), dim3(256), 0, s, nt, d.tris,
+                               (const V4<R>*)d.r, d.obs_part);
+        });
+    }
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, s, OBS_BLOCKS, d.obs_part, MASS_BLOCKS,
+                       d.mass_part, A_row, radius, nv > 0 ? 1 : 0, d.ctl, d.obs_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_positions_to_abs(int storage, const Geom& g, const DevPtrs& d, int nv,
+                                   double* out, hipStream_t s) {
+    DISPATCH_REAL(storage, R, {
+        hipLaunchKernelGGL(k_pos_to_abs<R>, dim3(blocks_for(nv, 256)), dim3(256), 0, s, g, nv,
+                           (const V4<R>*)d.r, out);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_positions_from_abs(int storage, const Geom& g, const DevPtrs& d, int nv,
+                                     const double* in, hipStream_t s) {
+    DISPATCH_REAL(storage, R, {
+        hipLaunchKernelGGL(k_pos_from_abs<R>, dim3(blocks_for(nv, 256)), dim3(256), 0, s, g, nv, in,
+                           (V4<R>*)d.r);
+    });
+    return hipGetLastError();
+}
+
+}  // namespace ibmlb

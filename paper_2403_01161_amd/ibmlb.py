@@ -1,0 +1,236 @@
+"""Python binding of the gfx950 IB-LB droplet library (libibmlb.so).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C-ABI of include/ibm_lb.h. PyTorch supplies device memory (the
+workspace tensor) and the HIP stream. There is no CPU fallback: if the
+library has not been built, importing the handle classes raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibmlb.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EDOMAIN, ENONFINITE = 0, -1, -2, -3, -4, -5
+F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
+STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
+INIT_LINEAR, INIT_REST = 0, 1
+OBS_DEGENERATE, OBS_E_ZERO, OBS_REG_CAP = 1, 2, 4
+FIELD_RHO, FIELD_U = 0, 1
+
+_lib = None
+
+
+class IbmLbError(RuntimeError):
+    def __init__(self, code, where, detail=""):
+        super().__init__(f"{where}: {_lib.ibm_lb_strerror(code).decode() if _lib else code}"
+                         + (f" ({detail})" if detail else ""))
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("L", C.c_int32 * 3), ("periodic", C.c_int32 * 3), ("tau", C.c_double),
+                ("sigma", C.c_double), ("radius", C.c_double), ("rho0", C.c_double),
+                ("n_vertices", C.c_int32), ("n_triangles", C.c_int32),
+                ("vertices", C.POINTER(C.c_double)), ("triangles", C.POINTER(C.c_int32)),
+                ("reg_alpha", C.c_double), ("reg_gamma", C.c_double), ("reg_tol", C.c_double),
+                ("reg_max_iter", C.c_int32), ("reg_sign", C.c_int32), ("storage", C.c_int32),
+                ("init", C.c_int32), ("A0", C.c_double * 9), ("f16_scale", C.c_double),
+                ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("step", C.c_int64), ("volume", C.c_double), ("centroid", C.c_double * 3),
+                ("S", C.c_double * 9), ("eigval", C.c_double * 3), ("eigvec", C.c_double * 9),
+                ("D", C.c_double), ("beta", C.c_double), ("theta_deg", C.c_double),
+                ("mass", C.c_double), ("momentum", C.c_double * 3), ("reg_iters", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_table",
+           "ibm_lb_observables", "ibm_lb_read_vertices", "ibm_lb_read_field",
+           "ibm_lb_state_bytes", "ibm_lb_save", "ibm_lb_load", "ibm_lb_timing_enable",
+           "ibm_lb_timing_read", "ibm_lb_destroy", "ibm_lb_strerror", "ibm_lb_last_error"]
+
+
+def lib():
+    """Load libibmlb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i32 = C.c_void_p, C.POINTER(C.c_double), C.c_int32
+        L.ibm_lb_workspace_size.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
+        L.ibm_lb_init.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.ibm_lb_step.argtypes = [vp, dp, i32]
+        L.ibm_lb_step_table.argtypes = [vp, vp, i32, i32]
+        L.ibm_lb_observables.argtypes = [vp, C.POINTER(Obs)]
+        L.ibm_lb_read_vertices.argtypes = [vp, dp]
+        L.ibm_lb_read_field.argtypes = [vp, i32, dp]
+        L.ibm_lb_state_bytes.argtypes = [vp]
+        L.ibm_lb_state_bytes.restype = C.c_size_t
+        L.ibm_lb_save.argtypes = [vp, vp, C.c_size_t]
+        L.ibm_lb_load.argtypes = [vp, vp, C.c_size_t]
+        L.ibm_lb_timing_enable.argtypes = [vp, i32]
+        L.ibm_lb_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+        L.ibm_lb_destroy.argtypes = [vp]
+        L.ibm_lb_destroy.restype = None
+        L.ibm_lb_strerror.argtypes = [C.c_int]
+        L.ibm_lb_strerror.restype = C.c_char_p
+        L.ibm_lb_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise IbmLbError(rc, where, lib().ibm_lb_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_config(L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None, periodic=(0, 0, 0),
+                storage="f32", init="linear", A0=None, rho0=1.0, reg_alpha=0.1, reg_gamma=0.51,
+                reg_tol=0.01, reg_max_iter=50, reg_sign=1, f16_scale=0.0):
+    """Fill an ibm_lb_config; returns (config, keep-alive arrays)."""
+    cfg = Config()
+    for a in range(3):
+        cfg.L[a] = int(L[a])
+        cfg.periodic[a] = int(periodic[a])
+    cfg.tau, cfg.sigma, cfg.radius, cfg.rho0 = float(tau), float(sigma), float(radius), float(rho0)
+    if vertices is None:
+        V = np.zeros((0, 3))
+        T = np.zeros((0, 3), dtype=np.int32)
+    else:
+        V = np.ascontiguousarray(vertices, dtype=np.float64)
+        T = np.ascontiguousarray(triangles, dtype=np.int32)
+    cfg.n_vertices, cfg.n_triangles = len(V), len(T)
+    cfg.vertices = _dp(V) if len(V) else None
+    cfg.triangles = T.ctypes.data_as(C.POINTER(C.c_int32)) if len(T) else None
+    cfg.reg_alpha, cfg.reg_gamma, cfg.reg_tol = reg_alpha, reg_gamma, reg_tol
+    cfg.reg_max_iter, cfg.reg_sign = int(reg_max_iter), int(reg_sign)
+    cfg.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    cfg.init = {"linear": INIT_LINEAR, "rest": INIT_REST}[init] if isinstance(init, str) else int(init)
+    A0 = np.zeros(9) if A0 is None else np.asarray(A0, dtype=np.float64).reshape(9)
+    for k in range(9):
+        cfg.A0[k] = A0[k]
+    cfg.f16_scale = float(f16_scale)
+    return cfg, (V, T)
+
+
+def workspace_size(cfg):
+    n = C.c_size_t()
+    _check(lib().ibm_lb_workspace_size(C.byref(cfg), C.byref(n)), "ibm_lb_workspace_size")
+    return n.value
+
+
+def _obs_dict(o):
+    return {"step": o.step, "volume": o.volume, "centroid": np.array(o.centroid[:]),
+            "S": np.array(o.S[:]).reshape(3, 3), "eigval": np.array(o.eigval[:]),
+            "eigvec": np.array(o.eigvec[:]).reshape(3, 3), "D": o.D, "beta": o.beta,
+            "theta_deg": o.theta_deg, "mass": o.mass, "momentum": np.array(o.momentum[:]),
+            "reg_iters": o.reg_iters, "flags": o.flags}
+
+
+class Simulation:
+    """One droplet (or a bare lattice) advanced on the GPU.
+
+    Device memory comes from a torch uint8 tensor on `device`; the work is
+    enqueued on torch's current stream of that device (or `stream`).
+    """
+
+    def __init__(self, L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None,
+                 periodic=(0, 0, 0), storage="f32", init="linear", A0=None, device="cuda:0",
+                 stream=None, **kw):
+        lib()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        cfg, keep = make_config(L, tau, sigma, radius, vertices, triangles, periodic, storage, init,
+                                A0, **kw)
+        nbytes = workspace_size(cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        cfg.workspace = self.workspace.data_ptr()
+        cfg.workspace_bytes = nbytes
+        cfg.stream = self.stream.cuda_stream
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().ibm_lb_init(C.byref(cfg), C.byref(h)), "ibm_lb_init")
+        self._h = h
+        self.L = tuple(int(v) for v in L)
+        self.N = int(np.prod(self.L))
+        self.nv = cfg.n_vertices
+        self.storage = cfg.storage
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ibm_lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, A, nsteps=1):
+        A = np.ascontiguousarray(A, dtype=np.float64).reshape(9)
+        _check(lib().ibm_lb_step(self._h, _dp(A), int(nsteps)), "ibm_lb_step")
+
+    def step_table(self, A_table):
+        """A_table: host array [n, 9] or a float64 CUDA tensor [n, 9] (kept alive by the caller
+        until the next synchronising call)."""
+        if isinstance(A_table, torch.Tensor) and A_table.is_cuda:
+            assert A_table.dtype == torch.float64 and A_table.is_contiguous()
+            n = A_table.numel() // 9
+            _check(lib().ibm_lb_step_table(self._h, A_table.data_ptr(), n, 1), "ibm_lb_step_table")
+        else:
+            A = np.ascontiguousarray(A_table, dtype=np.float64).reshape(-1, 9)
+            _check(lib().ibm_lb_step_table(self._h, A.ctypes.data, len(A), 0), "ibm_lb_step_table")
+
+    def observables(self):
+        o = Obs()
+        _check(lib().ibm_lb_observables(self._h, C.byref(o)), "ibm_lb_observables")
+        return _obs_dict(o)
+
+    def vertices(self):
+        out = np.zeros((self.nv, 3))
+        _check(lib().ibm_lb_read_vertices(self._h, _dp(out)), "ibm_lb_read_vertices")
+        return out
+
+    def fields(self):
+        Lx, Ly, Lz = self.L
+        rho = np.zeros(self.N)
+        u = np.zeros(3 * self.N)
+        _check(lib().ibm_lb_read_field(self._h, FIELD_RHO, _dp(rho)), "ibm_lb_read_field")
+        _check(lib().ibm_lb_read_field(self._h, FIELD_U, _dp(u)), "ibm_lb_read_field")
+        return rho.reshape(Lz, Ly, Lx), u.reshape(3, Lz, Ly, Lx)
+
+    def state_bytes(self):
+        return lib().ibm_lb_state_bytes(self._h)
+
+    def save(self, dst=None):
+        n = self.state_bytes()
+        if dst is None:
+            dst = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().ibm_lb_save(self._h, dst.data_ptr(), n), "ibm_lb_save")
+        return dst
+
+    def load(self, src):
+        _check(lib().ibm_lb_load(self._h, src.data_ptr(), src.numel()), "ibm_lb_load")
+
+    def timing(self, enable=True):
+        _check(lib().ibm_lb_timing_enable(self._h, int(enable)), "ibm_lb_timing_enable")
+
+    def timing_read(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().ibm_lb_timing_read(self._h, C.byref(ms), C.byref(n)), "ibm_lb_timing_read")
+        return ms.value, n.value

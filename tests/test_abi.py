@@ -1,0 +1,114 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects
+bad configurations on the host (no GPU needed: validation runs before any
+HIP call)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2403_01161_amd.inputs import box_center, icosphere
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^[A-Za-z_][\w \*]*?\b(ibm_lb_\w+)\s*\(", src, re.M))
+    return names
+
+
+@pytest.fixture(scope="module")
+def ib():
+    from paper_2403_01161_amd import ibmlb
+    if not os.path.exists(ibmlb.LIB_PATH):
+        pytest.skip("libibmlb.so not built")
+    ibmlb.lib()
+    return ibmlb
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("ibm_lb_init", "ibm_lb_step", "ibm_lb_observables", "ibm_lb_destroy"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(ib):
+    lib = ib.lib()
+    missing = [n for n in sorted(_declared()) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(ib.EXPORTS) <= _declared()
+
+
+def test_strerror(ib):
+    lib = ib.lib()
+    assert lib.ibm_lb_strerror(0) == b"ok"
+    assert lib.ibm_lb_strerror(-4) == b"vertex stencil outside the box"
+
+
+def _cfg(ib, **kw):
+    L = kw.pop("L", (16, 16, 16))
+    V, T = icosphere(2, 3.0, box_center(L))
+    args = dict(L=L, tau=0.9, sigma=0.01, radius=3.0, vertices=V, triangles=T)
+    args.update(kw)
+    return ib.make_config(**args)
+
+
+def _size_rc(ib, cfg):
+    import ctypes as C
+    n = C.c_size_t()
+    rc = ib.lib().ibm_lb_workspace_size(C.byref(cfg), C.byref(n))
+    return rc, n.value
+
+
+def test_valid_config_sizes(ib):
+    cfg, keep = _cfg(ib)
+    rc, n = _size_rc(ib, cfg)
+    assert rc == 0
+    N = 16 ** 3
+    assert n >= 2 * 19 * N * 4 + 6 * N * 4
+    cfg64, keep = _cfg(ib, storage="f64")
+    assert _size_rc(ib, cfg64)[1] > n
+    cfg16, keep = _cfg(ib, storage="bf16dev")
+    assert _size_rc(ib, cfg16)[1] < n
+
+
+@pytest.mark.parametrize("bad", [
+    dict(L=(7, 16, 16)), dict(tau=0.5), dict(sigma=-1.0), dict(radius=0.0), dict(rho0=0.0),
+    dict(storage=7), dict(init=5), dict(reg_sign=2), dict(reg_max_iter=-1),
+    dict(f16_scale=3.0, storage="f16dev"), dict(A0=[np.nan] + [0] * 8),
+])
+def test_invalid_parameters(ib, bad):
+    cfg, keep = _cfg(ib, **bad)
+    assert _size_rc(ib, cfg)[0] == ib.EINVAL
+    import ctypes as C
+    h = C.c_void_p()
+    assert ib.lib().ibm_lb_init(C.byref(cfg), C.byref(h)) == ib.EINVAL
+    assert not h.value
+    assert len(ib.lib().ibm_lb_last_error()) > 0
+
+
+def test_invalid_meshes(ib):
+    L = (16, 16, 16)
+    V, T = icosphere(2, 3.0, box_center(L))
+    cases = {
+        "inward": (V, T[:, ::-1].copy()),
+        "open": (V, T[1:].copy()),
+        "index": (V, np.where(T == 5, len(V), T).astype(np.int32)),
+        "wall": (V + [5.5, 0, 0], T),
+        "nan": (np.where(np.arange(V.size).reshape(V.shape) == 4, np.nan, V), T),
+    }
+    for name, (v, t) in cases.items():
+        cfg, keep = ib.make_config(L, 0.9, 0.01, 3.0, v, t)
+        assert _size_rc(ib, cfg)[0] == ib.EINVAL, name
+    # the same stencil is fine on a periodic axis
+    cfg, keep = ib.make_config(L, 0.9, 0.01, 3.0, V + [5.5, 0, 0], T, periodic=(1, 0, 0))
+    assert _size_rc(ib, cfg)[0] == 0
+
+
+def test_lattice_only_config(ib):
+    cfg, keep = ib.make_config((8, 9, 10), 0.8)
+    assert _size_rc(ib, cfg)[0] == 0
