@@ -38,15 +38,19 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of every device array inside one workspace.
 struct Layout {
-    size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, phi, tris, vt_start, vt_list, nb_start,
-        nb_list, obs_part, mass_part, obs_out, Abuf, total;
+    size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, tris, fan, obs_part, mass_part, obs_out, Abuf,
+        red, total;
 };
 
+// Per vertex: valence m and the one-ring neighbours n_0 .. n_{m-1} in
+// counter-clockwise order, so that (k, n_j, n_{j+1 mod m}) are exactly the
+// triangles around k with their orientation. FAN ints per vertex.
+constexpr int FAN = 16;
 struct MeshCSR {
-    std::vector<int> vt_start, vt_list, nb_start, nb_list;
+    std::vector<int> fan;
 };
 
-Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t nb_total) {
+Layout make_layout(int storage, long long N, int ntiles, int nv, int nt) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -68,22 +72,19 @@ Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t 
     L.qb = take(v4);
     L.pp = take(v4);
     L.bb = take(v4);
-    L.phi = take(v4);
     L.tris = take(sizeof(int4) * (size_t)nt);
-    L.vt_start = take(sizeof(int) * (size_t)(nv + 1));
-    L.vt_list = take(sizeof(int) * 3 * (size_t)nt);
-    L.nb_start = take(sizeof(int) * (size_t)(nv + 1));
-    L.nb_list = take(sizeof(int) * nb_total);
+    L.fan = take(sizeof(int) * FAN * (size_t)nv);
     L.obs_part = take(sizeof(double) * 16 * OBS_BLOCKS);
     L.mass_part = take(sizeof(double) * 4 * MASS_BLOCKS);
     L.obs_out = take(sizeof(double) * OBS_OUT_N);
     L.Abuf = take(sizeof(double) * 9 * (ACAP + 1));
+    L.red = take(sizeof(unsigned long long) * 2);
     L.total = off;
     return L;
 }
 
 // Validate the configuration and build the mesh adjacency.
-int validate(const ibm_lb_config* c, MeshCSR* csr) {
+int validate(const ibm_lb_config* c) {
     if (!c) return fail(IBM_LB_EINVAL, "config is NULL");
     for (int a = 0; a < 3; ++a)
         if (c->L[a] < 8) return fail(IBM_LB_EINVAL, "every box side needs at least 8 nodes");
@@ -151,28 +152,107 @@ int validate(const ibm_lb_config* c, MeshCSR* csr) {
             if (fl - 1.0 < 0.0 || fl + 2.0 > c->L[a] - 1)
                 return fail(IBM_LB_EINVAL, "a vertex stencil leaves the box across a wall");
         }
-    // adjacency: vertex -> incident triangle corners (triangles ascending),
-    // and the one-ring (sorted)
-    csr->vt_start.assign(nv + 1, 0);
-    for (int k = 0; k < 3 * nt; ++k) csr->vt_start[T[k] + 1]++;
-    for (int v = 0; v < nv; ++v) csr->vt_start[v + 1] += csr->vt_start[v];
-    csr->vt_list.assign(3 * (size_t)nt, 0);
-    std::vector<int> fill(csr->vt_start.begin(), csr->vt_start.end() - 1);
+    return IBM_LB_OK;
+}
+
+// Recursive bisection of the vertex set along the longest axis of its
+// bounding box, splitting at a multiple of 256 vertices: every run of 256
+// consecutive vertices in the resulting order (one work-group's patch) is
+// spatially compact.
+void bisect(const double* V, int* idx, int n, std::vector<int>* out) {
+    if (n <= 256) {
+        out->insert(out->end(), idx, idx + n);
+        return;
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int k = 0; k < n; ++k)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], V[3 * idx[k] + a]);
+            hi[a] = std::max(hi[a], V[3 * idx[k] + a]);
+        }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+        if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+    int nl = ((n / 2 + 255) / 256) * 256;
+    if (nl >= n) nl = n - 256;
+    std::nth_element(idx, idx + nl, idx + n, [&](int p, int q) {
+        const double vp = V[3 * p + ax], vq = V[3 * q + ax];
+        return vp < vq || (vp == vq && p < q);
+    });
+    bisect(V, idx, nl, out);
+    bisect(V, idx + nl, n - nl, out);
+}
+
+// Internal vertex order (perm[new] = old) from the bisection above.
+// Triangles are renumbered and sorted by their lowest new corner index; each
+// keeps its corner order (orientation).
+void renumber(const ibm_lb_config* c, std::vector<int>* perm, std::vector<int>* tris) {
+    const int nv = c->n_vertices, nt = c->n_triangles;
+    std::vector<int> idx(nv);
+    for (int k = 0; k < nv; ++k) idx[k] = k;
+    perm->clear();
+    perm->reserve(nv);
+    bisect(c->vertices, idx.data(), nv, perm);
+    std::vector<int> inv(nv);
+    for (int k = 0; k < nv; ++k) inv[(*perm)[k]] = k;
+    std::vector<std::pair<int, int>> order(nt);
+    for (int t = 0; t < nt; ++t) {
+        int a = inv[c->triangles[3 * t]], b = inv[c->triangles[3 * t + 1]], d = inv[c->triangles[3 * t + 2]];
+        order[t] = {std::min(a, std::min(b, d)), t};
+    }
+    std::stable_sort(order.begin(), order.end());
+    tris->resize(3 * (size_t)nt);
+    for (int j = 0; j < nt; ++j) {
+        const int t = order[j].second;
+        for (int q = 0; q < 3; ++q) (*tris)[3 * j + q] = inv[c->triangles[3 * t + q]];
+    }
+}
+
+// Ordered one-rings of the internal numbering (see FAN). A vertex whose
+// incident triangles do not form a single fan (non-manifold) or whose
+// valence exceeds FAN - 1 is rejected.
+int build_adjacency(int nv, int nt, const int* T, MeshCSR* csr) {
+    std::vector<std::vector<std::pair<int, int>>> inc(nv);
     for (int t = 0; t < nt; ++t)
-        for (int j = 0; j < 3; ++j) csr->vt_list[fill[T[3 * t + j]]++] = (t << 2) | j;
-    std::vector<std::vector<int>> ring(nv);
-    for (auto& e : edges) ring[e.first.first].push_back(e.first.second);
-    csr->nb_start.assign(nv + 1, 0);
-    csr->nb_list.clear();
+        for (int j = 0; j < 3; ++j) inc[T[3 * t + j]].push_back({T[3 * t + (j + 1) % 3], T[3 * t + (j + 2) % 3]});
+    csr->fan.assign((size_t)FAN * nv, -1);
     for (int v = 0; v < nv; ++v) {
-        auto& r = ring[v];
-        std::sort(r.begin(), r.end());
-        r.erase(std::unique(r.begin(), r.end()), r.end());
-        if (r.empty()) return fail(IBM_LB_EINVAL, "vertex without neighbours");
-        csr->nb_list.insert(csr->nb_list.end(), r.begin(), r.end());
-        csr->nb_start[v + 1] = (int)csr->nb_list.size();
+        auto& e = inc[v];
+        const int m = (int)e.size();
+        if (m < 3) return fail(IBM_LB_EINVAL, "vertex with fewer than three incident triangles");
+        if (m > FAN - 1) return fail(IBM_LB_EINVAL, "vertex valence above 15 is not supported");
+        int* f = &csr->fan[(size_t)FAN * v];
+        f[0] = m;
+        int cur = 0;
+        std::vector<char> used(m, 0);
+        for (int j = 0; j < m; ++j) {
+            used[cur] = 1;
+            f[1 + j] = e[cur].first;
+            const int want = e[cur].second;
+            int nxt = -1;
+            for (int q = 0; q < m; ++q)
+                if (!used[q] && e[q].first == want) nxt = q;
+            if (j + 1 < m) {
+                if (nxt < 0) return fail(IBM_LB_EINVAL, "non-manifold vertex (incident triangles are not one fan)");
+                cur = nxt;
+            } else if (want != f[1]) {
+                return fail(IBM_LB_EINVAL, "non-manifold vertex (fan does not close)");
+            }
+        }
     }
     return IBM_LB_OK;
+}
+
+struct MeshData {
+    std::vector<int> perm, tris;
+    MeshCSR csr;
+};
+
+int prepare(const ibm_lb_config* c, MeshData* m) {
+    int rc = validate(c);
+    if (rc || c->n_vertices == 0) return rc;
+    renumber(c, &m->perm, &m->tris);
+    return build_adjacency(c->n_vertices, c->n_triangles, m->tris.data(), &m->csr);
 }
 
 Geom make_geom(const ibm_lb_config* c) {
@@ -212,6 +292,8 @@ struct ibm_lb {
     int cur = 0;
     int64_t step = 0;
     int sticky = IBM_LB_OK;
+    bool f_ready = false;        // F and tile marks hold the spread of the current mesh
+    std::vector<int> perm;       // internal vertex k is caller vertex perm[k]
     double* stage = nullptr;     // pinned host staging for gradient rows
     hipEvent_t stage_done = nullptr;
     bool timing = false;
@@ -260,19 +342,29 @@ int accumulate_timing(ibm_lb* h) {
     return IBM_LB_OK;
 }
 
+// Forces and spreading of the current mesh into F (marks at the current
+// epoch), needed before the first lattice kernel after set-up or a load.
+int ensure_force(ibm_lb* h) {
+    if (h->f_ready || h->nv == 0) return IBM_LB_OK;
+    HIP_TRY(launch_ib_pre(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream), "ib_pre launch");
+    h->f_ready = true;
+    return IBM_LB_OK;
+}
+
 // Enqueue nsteps timesteps; step j reads the gradient row A + 9 j*stride.
+// Per step: the fused lattice kernel (which consumes F^n and writes u^n in
+// the marked tiles), then the IB half: interpolation + Euler, smoothing and
+// the next step's forces + spreading.
 int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
     const bool ib = h->nv > 0;
+    int rc = ensure_force(h);
+    if (rc) return rc;
     for (int j = 0; j < nsteps; ++j) {
         const double* Arow = A + 9ll * j * stride;
-        if (ib) {
-            HIP_TRY(launch_forces(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->stream), "forces launch");
-            HIP_TRY(launch_spread(h->storage, h->g, h->d, h->nv, h->stream), "spread launch");
-        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (h->timing) {
             if (h->ev_used == 4096) {
-                int rc = accumulate_timing(h);
+                rc = accumulate_timing(h);
                 if (rc) return rc;
             }
             if (h->ev_used == h->ev.size()) {
@@ -290,10 +382,8 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
             HIP_TRY(hipEventRecord(e1, h->stream), "hipEventRecord");
             h->ev_used++;
         }
-        if (ib) {
-            HIP_TRY(launch_interp(h->storage, h->g, h->d, h->nv, h->stream), "interp launch");
-            HIP_TRY(launch_smooth(h->storage, h->d, h->nv, h->sp, h->stream), "smooth launch");
-        }
+        if (ib)
+            HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream), "ib_step launch");
         h->cur ^= 1;
         h->step++;
     }
@@ -338,23 +428,22 @@ const char* ibm_lb_strerror(int code) {
 const char* ibm_lb_last_error(void) { return g_last_error.c_str(); }
 
 int ibm_lb_workspace_size(const ibm_lb_config* cfg, size_t* bytes) {
-    MeshCSR csr;
-    int rc = validate(cfg, &csr);
+    MeshData m;
+    int rc = prepare(cfg, &m);
     if (rc) return rc;
     if (!bytes) return fail(IBM_LB_EINVAL, "bytes is NULL");
     Geom g = make_geom(cfg);
-    *bytes = make_layout(cfg->storage, g.N, g.TX * g.TY * g.TZ, cfg->n_vertices, cfg->n_triangles,
-                         csr.nb_list.size())
-                 .total;
+    *bytes = make_layout(cfg->storage, g.N, g.TX * g.TY * g.TZ, cfg->n_vertices, cfg->n_triangles).total;
     return IBM_LB_OK;
 }
 
 int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     if (!out) return fail(IBM_LB_EINVAL, "out is NULL");
     *out = nullptr;
-    MeshCSR csr;
-    int rc = validate(cfg, &csr);
+    MeshData mesh;
+    int rc = prepare(cfg, &mesh);
     if (rc) return rc;
+    const MeshCSR& csr = mesh.csr;
     ibm_lb* h = new (std::nothrow) ibm_lb();
     if (!h) return fail(IBM_LB_ENOMEM, "host allocation");
     h->cfg = *cfg;
@@ -384,7 +473,7 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
     const int ntiles = h->g.TX * h->g.TY * h->g.TZ;
-    h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt, csr.nb_list.size());
+    h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt);
     if (cfg->workspace) {
         if (cfg->workspace_bytes < h->lay.total)
             return bail(fail(IBM_LB_ENOMEM, "workspace smaller than ibm_lb_workspace_size"));
@@ -420,16 +509,18 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     d.qb = b + L.qb;
     d.pp = b + L.pp;
     d.bb = b + L.bb;
-    d.phi = b + L.phi;
     d.tris = (int4*)(b + L.tris);
-    d.vt_start = (int*)(b + L.vt_start);
-    d.vt_list = (int*)(b + L.vt_list);
-    d.nb_start = (int*)(b + L.nb_start);
-    d.nb_list = (int*)(b + L.nb_list);
+    d.fan = (int4*)(b + L.fan);
     d.obs_part = (double*)(b + L.obs_part);
     d.mass_part = (double*)(b + L.mass_part);
     d.obs_out = (double*)(b + L.obs_out);
     d.Abuf = (double*)(b + L.Abuf);
+    d.red = (unsigned long long*)(b + L.red);
+    h->perm = mesh.perm;
+    if (h->nv > 0) {
+        e = patch_setup(h->storage);
+        if (e != hipSuccess) return bail(hip_fail(e, "patch kernel set-up"));
+    }
 
     // Zero the fields that must start at zero (force, velocity, marks, control).
     const size_t rb = real_bytes(h->storage);
@@ -441,6 +532,7 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     INIT_TRY(hipMemsetAsync(d.F, 0, 3 * rb * (size_t)h->g.N, h->stream), "zero F");
     INIT_TRY(hipMemsetAsync(d.u, 0, 3 * rb * (size_t)h->g.N, h->stream), "zero u");
     INIT_TRY(hipMemsetAsync(d.mark, 0, sizeof(int) * (size_t)ntiles, h->stream), "zero marks");
+    INIT_TRY(hipMemsetAsync(d.red, 0, 2 * sizeof(unsigned long long), h->stream), "zero reduction slots");
     Ctl ctl0{};
     ctl0.epoch = 1;
     INIT_TRY(hipMemcpyAsync(d.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice, h->stream), "ctl");
@@ -451,19 +543,15 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     if (h->nv > 0) {
         std::vector<int4> tris(h->nt);
         for (int t = 0; t < h->nt; ++t)
-            tris[t] = int4{cfg->triangles[3 * t], cfg->triangles[3 * t + 1], cfg->triangles[3 * t + 2], 0};
+            tris[t] = int4{mesh.tris[3 * t], mesh.tris[3 * t + 1], mesh.tris[3 * t + 2], 0};
         INIT_TRY(hipMemcpy(d.tris, tris.data(), sizeof(int4) * h->nt, hipMemcpyHostToDevice), "tris");
-        INIT_TRY(hipMemcpy(d.vt_start, csr.vt_start.data(), sizeof(int) * csr.vt_start.size(),
-                           hipMemcpyHostToDevice), "vt_start");
-        INIT_TRY(hipMemcpy(d.vt_list, csr.vt_list.data(), sizeof(int) * csr.vt_list.size(),
-                           hipMemcpyHostToDevice), "vt_list");
-        INIT_TRY(hipMemcpy(d.nb_start, csr.nb_start.data(), sizeof(int) * csr.nb_start.size(),
-                           hipMemcpyHostToDevice), "nb_start");
-        INIT_TRY(hipMemcpy(d.nb_list, csr.nb_list.data(), sizeof(int) * csr.nb_list.size(),
-                           hipMemcpyHostToDevice), "nb_list");
+        INIT_TRY(hipMemcpy(d.fan, csr.fan.data(), sizeof(int) * csr.fan.size(), hipMemcpyHostToDevice), "fan");
+        std::vector<double> vin(3 * (size_t)h->nv);
+        for (int k = 0; k < h->nv; ++k)
+            for (int a = 0; a < 3; ++a) vin[3 * k + a] = cfg->vertices[3 * mesh.perm[k] + a];
         double* tmp = nullptr;
         INIT_TRY(hipMalloc((void**)&tmp, sizeof(double) * 3 * h->nv), "vertex upload buffer");
-        hipError_t e1 = hipMemcpy(tmp, cfg->vertices, sizeof(double) * 3 * h->nv, hipMemcpyHostToDevice);
+        hipError_t e1 = hipMemcpy(tmp, vin.data(), sizeof(double) * 3 * h->nv, hipMemcpyHostToDevice);
         hipError_t e2 = e1 == hipSuccess
                             ? launch_positions_from_abs(h->storage, h->g, d, h->nv, tmp, h->stream)
                             : e1;
@@ -545,13 +633,16 @@ int ibm_lb_read_vertices(ibm_lb* h, double* out) {
     if (rc) return rc;
     double* tmp = nullptr;
     HIP_TRY(hipMalloc((void**)&tmp, sizeof(double) * 3 * h->nv), "hipMalloc");
+    std::vector<double> in(3 * (size_t)h->nv);
     hipError_t e = launch_positions_to_abs(h->storage, h->g, h->d, h->nv, tmp, h->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(out, tmp, sizeof(double) * 3 * h->nv, hipMemcpyDeviceToHost, h->stream);
+        e = hipMemcpyAsync(in.data(), tmp, sizeof(double) * 3 * h->nv, hipMemcpyDeviceToHost, h->stream);
     hipError_t e2 = hipStreamSynchronize(h->stream);
     (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "read vertices");
     if (e2 != hipSuccess) return hip_fail(e2, "read vertices");
+    for (int k = 0; k < h->nv; ++k)
+        for (int a = 0; a < 3; ++a) out[3 * h->perm[k] + a] = in[3 * k + a];
     return check_flags(h);
 }
 
@@ -564,13 +655,14 @@ int ibm_lb_read_field(ibm_lb* h, int32_t which, double* out) {
     double* tmp = nullptr;
     HIP_TRY(hipMalloc((void**)&tmp, sizeof(double) * 4 * N), "hipMalloc");
     const bool ib = which == IBM_LB_FIELD_U && h->nv > 0;
-    hipError_t e = hipSuccess;
     if (ib) {
-        e = launch_forces(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->stream);
-        if (e == hipSuccess) e = launch_spread(h->storage, h->g, h->d, h->nv, h->stream);
+        rc = ensure_force(h);
+        if (rc) {
+            (void)hipFree(tmp);
+            return rc;
+        }
     }
-    if (e == hipSuccess) e = launch_moments(h->storage, h->g, h->lp, h->d, h->cur, ib, tmp, tmp + N, h->stream);
-    if (e == hipSuccess && ib) e = launch_bump_epoch(h->d, h->stream);
+    hipError_t e = launch_moments(h->storage, h->g, h->lp, h->d, h->cur, ib, tmp, tmp + N, h->stream);
     if (e == hipSuccess) {
         const double* src = which == IBM_LB_FIELD_RHO ? tmp : tmp + N;
         size_t cnt = which == IBM_LB_FIELD_RHO ? N : 3 * N;
@@ -628,11 +720,16 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n) {
             "load vertices");
     h->step = hd.step;
     h->sticky = IBM_LB_OK;
+    // the force field of the previous mesh is stale: clear it and retire its marks
+    HIP_TRY(launch_clear_force(h->storage, h->g, h->d, h->stream), "clear force");
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
     Ctl c;
     HIP_TRY(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost), "ctl");
     c.flags = 0;
     c.cap_hits = 0;
+    c.epoch += 1;
     HIP_TRY(hipMemcpy(h->d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice), "ctl");
+    h->f_ready = false;
     return IBM_LB_OK;
 }
 

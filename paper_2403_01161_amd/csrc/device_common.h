@@ -1,0 +1,53 @@
+// Device helpers shared by the lattice and immersed-boundary kernels.
+#pragma once
+
+#include <math.h>
+
+#include "ibmlb_internal.h"
+
+namespace ibmlb {
+
+__device__ inline int wrap(int j, int L) { return j < 0 ? j + L : (j >= L ? j - L : j); }
+
+// Peskin 4-point weights of the four nodes floor(s)-1 .. floor(s)+2 for a
+// coordinate with fractional part f in [0, 1). The four stencil arguments
+// 1+f, f, 1-f, 2-f share the radicand 1 + 4f - 4f^2 of the two branches of
+// phi(x) (Sec. 3.1), so one square root serves the whole axis.
+template <class R>
+__device__ inline void peskin4(R f, R w[4]) {
+    R q = sqrt(R(1) + R(4) * f - R(4) * f * f);
+    w[0] = (R(3) - R(2) * f - q) * R(0.125);
+    w[1] = (R(3) - R(2) * f + q) * R(0.125);
+    w[2] = (R(1) + R(2) * f + q) * R(0.125);
+    w[3] = (R(1) + R(2) * f - q) * R(0.125);
+}
+
+// Stencil of one axis for a coordinate `rel` relative to the box centre:
+// the unwrapped absolute index of the first stencil node (floor - 1) and the
+// fractional part. False if the coordinate is not finite (or absurdly large)
+// or the stencil leaves a wall axis.
+template <class R>
+__device__ inline bool stencil_base(R rel, int xci, double xcf, int L, int periodic, int* first,
+                                    R* frac) {
+    R s = rel + R(xcf);
+    if (!(fabs(s) < R(1e7))) return false;
+    R fl = floor(s);
+    *frac = s - fl;
+    int b = int(fl) + xci - 1;
+    *first = b;
+    return periodic || (b >= 0 && b + 3 <= L - 1);
+}
+
+// Wrap an unwrapped node index into 0..L-1 (any distance).
+__device__ inline int wrap_any(int j, int L) {
+    int m = j % L;
+    return m < 0 ? m + L : m;
+}
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace ibmlb

@@ -1,0 +1,604 @@
+// Immersed-boundary half of the timestep, organised by surface patches.
+//
+// At set-up the vertices are renumbered by recursive bisection of their
+// positions so that every run of 256 consecutive vertices is a compact patch
+// of the droplet surface; one work-group owns one patch and one thread one
+// vertex. The lattice window covered by a patch's 4x4x4 stencils is staged
+// in LDS:
+//   * spreading (Sec. 3.1, Eq. ibm_force_d, first line): 16 lanes per vertex
+//     add its 64 contributions into an FP64 LDS window with LDS atomics, and
+//     the window is flushed to F with one global atomic per touched node;
+//   * interpolation (Eq. ibm_force_d, second line): the window of u is loaded
+//     once and each vertex gathers its 64 nodes from LDS.
+// A window beyond the LDS capacity falls back to direct global access.
+//
+// Topology is the ordered one-ring ("fan") of each vertex: valence m and
+// neighbours n_0 .. n_{m-1} counter-clockwise, so (k, n_j, n_{j+1}) are the
+// triangles around k. Forces and smoothing need two dependent loads per
+// vertex: the fan, then the neighbour positions.
+//
+// Kernels of one step, after the fused lattice kernel:
+//   k_interp_patch  interpolation + Euler move (Eq. fwd_euler): o = r + U
+//   k_hc_pass1      first HC pass of iteration 1 (q = o)
+//   k_hc_pass2      correction pass of iteration 1, grid-wide max |p - q|
+//   k_hc_finish     one work-group: nothing if iteration 1 converged, else
+//                   the remaining iterations; advances the step epoch
+//   k_fs_patch      next step's surface-tension forces (Eq. pi_drop), tile
+//                   marks and spreading, from the final positions
+#include "device_common.h"
+
+namespace ibmlb {
+
+constexpr int PATCH = 256;
+constexpr int MAXV = 15;        // valence capacity of a fan
+
+template <class R>
+struct IbArgs {
+    Geom g;
+    int nv;
+    R sigma;
+    SmoothParams sp;
+    V4<R>* r;              // positions at the start of the step (relative to x_c)
+    V4<R>* o;              // after the Euler move
+    V4<R>* qa;             // smoothing iterates; qa holds the final positions
+    V4<R>* qb;
+    V4<R>* pp;
+    V4<R>* bb;
+    const int4* fan;       // [nv][4]
+    R* F;                  // [3][N]
+    const R* U;            // [3][N]
+    int* mark;
+    Ctl* ctl;
+    unsigned long long* red;  // grid-wide max of |p - q| (bit pattern of a non-negative real)
+    int wcap;              // LDS window capacity in nodes
+};
+
+// ---------------------------------------------------------------- topology
+// Valence and neighbours of vertex k (unused slots are -1).
+__device__ inline int load_fan(const int4* fan, int k, int nb[MAXV]) {
+    const int4 a = fan[4 * k], b = fan[4 * k + 1];
+    nb[0] = a.y; nb[1] = a.z; nb[2] = a.w;
+    nb[3] = b.x; nb[4] = b.y; nb[5] = b.z; nb[6] = b.w;
+    if (a.x > 7) {
+        const int4 c = fan[4 * k + 2], d = fan[4 * k + 3];
+        nb[7] = c.x; nb[8] = c.y; nb[9] = c.z; nb[10] = c.w;
+        nb[11] = d.x; nb[12] = d.y; nb[13] = d.z; nb[14] = d.w;
+    } else {
+#pragma unroll
+        for (int j = 7; j < MAXV; ++j) nb[j] = -1;
+    }
+    return a.x;
+}
+
+// ---------------------------------------------------------------- forces
+// Surface-tension force of vertex k at positions P: Eq. (pi_drop) read as
+// phi_k = -sigma dA/dr_k, with dA/dr_k = n_t x (r_{n_{j+1}} - r_{n_j}) / 2
+// for the triangle t = (k, n_j, n_{j+1}) of unit normal n_t.
+template <class R>
+__device__ inline void force_of(const IbArgs<R>& a, const V4<R>* P, int k, const V4<R>& pk, R& fx,
+                                R& fy, R& fz) {
+    int nb[MAXV];
+    const int m = load_fan(a.fan, k, nb);
+    V4<R> pn[MAXV];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+        if (j < m) pn[j] = P[nb[j]];
+    fx = fy = fz = R(0);
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j) {
+        if (j < m) {
+            const V4<R> pa = pn[j];
+            const V4<R> pb = (j + 1 < MAXV && j + 1 < m) ? pn[j + 1 < MAXV ? j + 1 : 0] : pn[0];
+            const R ax = pa.x - pk.x, ay = pa.y - pk.y, az = pa.z - pk.z;
+            const R bx = pb.x - pk.x, by = pb.y - pk.y, bz = pb.z - pk.z;
+            R nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+            const R len = sqrt(nx * nx + ny * ny + nz * nz);
+            if (len > R(0)) {
+                nx /= len; ny /= len; nz /= len;
+                const R dx = pb.x - pa.x, dy = pb.y - pa.y, dz = pb.z - pa.z;
+                fx -= a.sigma * R(0.5) * (ny * dz - nz * dy);
+                fy -= a.sigma * R(0.5) * (nz * dx - nx * dz);
+                fz -= a.sigma * R(0.5) * (nx * dy - ny * dx);
+            }
+        }
+    }
+}
+
+// Tiles touched by a stencil starting at unwrapped `first`, marked with `ep`.
+template <class R>
+__device__ inline void mark_tiles(const IbArgs<R>& a, const int first[3], int ep) {
+    const int L[3] = {a.g.Lx, a.g.Ly, a.g.Lz};
+    int t0[3], t1[3], t2[3];
+    for (int d = 0; d < 3; ++d) {
+        // four consecutive nodes cover at most three tiles (three only when a
+        // periodic stencil wraps around a side that is not a tile multiple)
+        t0[d] = wrap_any(first[d], L[d]) >> TILE_SHIFT;
+        t1[d] = wrap_any(first[d] + 3, L[d]) >> TILE_SHIFT;
+        t2[d] = t0[d];
+        for (int j = 1; j < 3; ++j) {
+            const int t = wrap_any(first[d] + j, L[d]) >> TILE_SHIFT;
+            if (t != t0[d] && t != t1[d]) t2[d] = t;
+        }
+    }
+    for (int cz = 0; cz < 3; ++cz) {
+        const int tz = cz == 0 ? t0[2] : (cz == 1 ? t1[2] : t2[2]);
+        if (cz > 0 && (tz == t0[2] || (cz == 2 && tz == t1[2]))) continue;
+        for (int cy = 0; cy < 3; ++cy) {
+            const int ty = cy == 0 ? t0[1] : (cy == 1 ? t1[1] : t2[1]);
+            if (cy > 0 && (ty == t0[1] || (cy == 2 && ty == t1[1]))) continue;
+            for (int cx = 0; cx < 3; ++cx) {
+                const int tx = cx == 0 ? t0[0] : (cx == 1 ? t1[0] : t2[0]);
+                if (cx > 0 && (tx == t0[0] || (cx == 2 && tx == t1[0]))) continue;
+                a.mark[tx + a.g.TX * (ty + a.g.TY * tz)] = ep;
+            }
+        }
+    }
+}
+
+// Stencil of a vertex at p: unwrapped first nodes and Peskin weights. False
+// (and the device flag raised) for a non-finite position or a stencil
+// through a wall.
+template <class R>
+__device__ inline bool stencil_of(const IbArgs<R>& a, const V4<R>& p, int f[3], R w[3][4]) {
+    R fr[3];
+    const bool fin = isfinite(p.x) && isfinite(p.y) && isfinite(p.z);
+    const bool ok = fin && stencil_base(p.x, a.g.xci[0], a.g.xcf[0], a.g.Lx, a.g.px, &f[0], &fr[0]) &&
+                    stencil_base(p.y, a.g.xci[1], a.g.xcf[1], a.g.Ly, a.g.py, &f[1], &fr[1]) &&
+                    stencil_base(p.z, a.g.xci[2], a.g.xcf[2], a.g.Lz, a.g.pz, &f[2], &fr[2]);
+    if (!fin) atomicOr(&a.ctl->flags, DFLAG_NONFINITE);
+    else if (!ok) atomicOr(&a.ctl->flags, DFLAG_DOMAIN);
+    if (ok)
+        for (int d = 0; d < 3; ++d) peskin4(fr[d], w[d]);
+    return ok;
+}
+
+// Block-wide window (origin, extent in unwrapped nodes) of the active
+// threads' stencils.
+struct Win {
+    int o[3], e[3], vol;
+    bool fits;
+};
+
+__device__ inline Win block_window(bool active, const int f[3], int wcap) {
+    __shared__ int red[6][PATCH / 64];
+    const int t = threadIdx.x;
+    int mn[3], mx[3];
+    for (int d = 0; d < 3; ++d) {
+        mn[d] = active ? f[d] : 0x3fffffff;
+        mx[d] = active ? f[d] : -0x3fffffff;
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = min(mn[d], __shfl_xor(mn[d], off, 64));
+            mx[d] = max(mx[d], __shfl_xor(mx[d], off, 64));
+        }
+    if ((t & 63) == 0)
+        for (int d = 0; d < 3; ++d) {
+            red[d][t >> 6] = mn[d];
+            red[3 + d][t >> 6] = mx[d];
+        }
+    __syncthreads();
+    Win w;
+    bool any = true;
+    long long vol = 1;
+    for (int d = 0; d < 3; ++d) {
+        int lo = red[d][0], hi = red[3 + d][0];
+        for (int k = 1; k < PATCH / 64; ++k) {
+            lo = min(lo, red[d][k]);
+            hi = max(hi, red[3 + d][k]);
+        }
+        any = any && lo <= hi;
+        w.o[d] = lo;
+        w.e[d] = any ? hi - lo + 4 : 0;
+        vol *= w.e[d];
+    }
+    __syncthreads();
+    w.fits = any && vol <= wcap;
+    w.vol = w.fits ? int(vol) : 0;
+    return w;
+}
+
+__device__ inline long long node_index(const Geom& g, int x, int y, int z) {
+    return wrap_any(x, g.Lx) + (long long)g.Lx * (wrap_any(y, g.Ly) + (long long)g.Ly * wrap_any(z, g.Lz));
+}
+
+// ---------------------------------------------------------------- forces + spreading
+// Staged stencils of a patch. The spreading window accumulates in FP64: LDS
+// atomic adds on doubles run at integer speed on this device, while FP32 LDS
+// atomic adds are about twenty times slower.
+template <class R>
+struct Stage {
+    int first[PATCH][3];
+    R w[PATCH][3][4];
+    R val[PATCH][3];
+    int ok[PATCH];
+};
+
+constexpr int SPREAD_WCAP = 4096;  // nodes of the FP64 spreading window
+
+// Accumulate the staged vertices [lo_v, hi_v) into an LDS window and flush
+// each touched node once to F; false if their window exceeds the capacity.
+template <class R>
+__device__ bool spread_window(const IbArgs<R>& a, const Stage<R>& st, double* win, int lo_v, int hi_v) {
+    const int t = threadIdx.x;
+    const bool in = t >= lo_v && t < hi_v && st.ok[t];
+    const int f[3] = {st.first[t][0], st.first[t][1], st.first[t][2]};
+    const Win w = block_window(in, f, SPREAD_WCAP);
+    if (!w.fits) return false;
+    const int lane = t & 15, jy = lane & 3, jz = lane >> 2;
+    const long long N = a.g.N;
+    for (int i = t; i < 3 * w.vol; i += PATCH) win[i] = 0.0;
+    __syncthreads();
+    for (int v = lo_v + (t >> 4); v < hi_v; v += PATCH / 16) {
+        if (!st.ok[v]) continue;
+        const double wyz = double(st.w[v][1][jy]) * double(st.w[v][2][jz]);
+        const double fx = st.val[v][0], fy = st.val[v][1], fz = st.val[v][2];
+        const int lx = st.first[v][0] - w.o[0];
+        const int ly = st.first[v][1] + jy - w.o[1];
+        const int lz = st.first[v][2] + jz - w.o[2];
+        const int base = lx + w.e[0] * (ly + w.e[1] * lz);
+#pragma unroll
+        for (int jx = 0; jx < 4; ++jx) {
+            const double wt = double(st.w[v][0][jx]) * wyz;
+            atomicAdd(&win[base + jx], fx * wt);
+            atomicAdd(&win[w.vol + base + jx], fy * wt);
+            atomicAdd(&win[2 * w.vol + base + jx], fz * wt);
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < w.vol; i += PATCH) {
+        const double vx = win[i], vy = win[w.vol + i], vz = win[2 * w.vol + i];
+        if (vx == 0.0 && vy == 0.0 && vz == 0.0) continue;
+        const int lx = i % w.e[0], rest = i / w.e[0];
+        const int ly = rest % w.e[1], lz = rest / w.e[1];
+        const long long n = node_index(a.g, w.o[0] + lx, w.o[1] + ly, w.o[2] + lz);
+        unsafeAtomicAdd(a.F + n, R(vx));
+        unsafeAtomicAdd(a.F + N + n, R(vy));
+        unsafeAtomicAdd(a.F + 2 * N + n, R(vz));
+    }
+    __syncthreads();
+    return true;
+}
+
+// Forces, tile marks and spreading of one patch from positions P. With
+// `commit`, P (the final smoothed positions) also becomes the state r.
+template <class R>
+__global__ __launch_bounds__(PATCH) void k_fs_patch(IbArgs<R> a, const V4<R>* P, int commit) {
+    extern __shared__ unsigned char dyn[];
+    double* win = reinterpret_cast<double*>(dyn);
+    __shared__ Stage<R> st;
+    const int t = threadIdx.x;
+    const int k = blockIdx.x * PATCH + t;
+    const int ep = a.ctl->epoch;
+    const long long N = a.g.N;
+    int f[3] = {0, 0, 0};
+    R w[3][4];
+    bool ok = false;
+    if (k < a.nv) {
+        const V4<R> pos = P[k];
+        if (commit) a.r[k] = pos;
+        ok = stencil_of(a, pos, f, w);
+        if (ok) {
+            R fx, fy, fz;
+            force_of(a, P, k, pos, fx, fy, fz);
+            mark_tiles(a, f, ep);
+            st.val[t][0] = fx;
+            st.val[t][1] = fy;
+            st.val[t][2] = fz;
+            for (int d = 0; d < 3; ++d)
+                for (int j = 0; j < 4; ++j) st.w[t][d][j] = w[d][j];
+        }
+    }
+    for (int d = 0; d < 3; ++d) st.first[t][d] = f[d];
+    st.ok[t] = ok ? 1 : 0;
+    __syncthreads();
+    if (spread_window(a, st, win, 0, PATCH)) return;
+    // not compact: one window per 64-vertex chunk, else direct global atomics
+    const int lane = t & 15, jy = lane & 3, jz = lane >> 2;
+    for (int c = 0; c < PATCH; c += 64) {
+        if (spread_window(a, st, win, c, c + 64)) continue;
+        for (int v = c + (t >> 4); v < c + 64; v += PATCH / 16) {
+            if (!st.ok[v]) continue;
+            const R wyz = st.w[v][1][jy] * st.w[v][2][jz];
+#pragma unroll
+            for (int jx = 0; jx < 4; ++jx) {
+                const R wt = st.w[v][0][jx] * wyz;
+                const long long n = node_index(a.g, st.first[v][0] + jx, st.first[v][1] + jy,
+                                               st.first[v][2] + jz);
+                unsafeAtomicAdd(a.F + n, st.val[v][0] * wt);
+                unsafeAtomicAdd(a.F + N + n, st.val[v][1] * wt);
+                unsafeAtomicAdd(a.F + 2 * N + n, st.val[v][2] * wt);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- interpolation
+template <class R>
+__global__ __launch_bounds__(PATCH) void k_interp_patch(IbArgs<R> a) {
+    extern __shared__ unsigned char dyn[];
+    R* win = reinterpret_cast<R*>(dyn);
+    const int t = threadIdx.x;
+    const int k = blockIdx.x * PATCH + t;
+    const long long N = a.g.N;
+    int f[3] = {0, 0, 0};
+    R w[3][4];
+    bool ok = false;
+    V4<R> p = V4<R>{R(0), R(0), R(0), R(0)};
+    if (k < a.nv) {
+        p = a.r[k];
+        ok = stencil_of(a, p, f, w);
+    }
+    const Win wn = block_window(ok, f, a.wcap);
+    if (wn.fits) {
+        for (int i = t; i < wn.vol; i += PATCH) {
+            const int lx = i % wn.e[0], rest = i / wn.e[0];
+            const int ly = rest % wn.e[1], lz = rest / wn.e[1];
+            const long long n = node_index(a.g, wn.o[0] + lx, wn.o[1] + ly, wn.o[2] + lz);
+            win[i] = a.U[n];
+            win[wn.vol + i] = a.U[N + n];
+            win[2 * wn.vol + i] = a.U[2 * N + n];
+        }
+        __syncthreads();
+    }
+    if (k >= a.nv) return;
+    R ux = R(0), uy = R(0), uz = R(0);
+    if (ok) {
+        if (wn.fits) {
+            const int lx = f[0] - wn.o[0];
+            for (int jz = 0; jz < 4; ++jz)
+                for (int jy = 0; jy < 4; ++jy) {
+                    const int base = lx + wn.e[0] * ((f[1] - wn.o[1] + jy) + wn.e[1] * (f[2] - wn.o[2] + jz));
+                    const R wyz = w[1][jy] * w[2][jz];
+#pragma unroll
+                    for (int jx = 0; jx < 4; ++jx) {
+                        const R wt = w[0][jx] * wyz;
+                        ux += win[base + jx] * wt;
+                        uy += win[wn.vol + base + jx] * wt;
+                        uz += win[2 * wn.vol + base + jx] * wt;
+                    }
+                }
+        } else {
+            for (int jz = 0; jz < 4; ++jz)
+                for (int jy = 0; jy < 4; ++jy) {
+                    const R wyz = w[1][jy] * w[2][jz];
+#pragma unroll
+                    for (int jx = 0; jx < 4; ++jx) {
+                        const R wt = w[0][jx] * wyz;
+                        const long long n = node_index(a.g, f[0] + jx, f[1] + jy, f[2] + jz);
+                        ux += a.U[n] * wt;
+                        uy += a.U[N + n] * wt;
+                        uz += a.U[2 * N + n] * wt;
+                    }
+                }
+        }
+    }
+    a.o[k] = V4<R>{p.x + ux, p.y + uy, p.z + uz, R(0)};
+}
+
+// ---------------------------------------------------------------- HC smoothing
+// Sec. 3.3 with x_o = o: x_q = x_p; x_p = alpha x_o + (1-alpha) mean_nb(x_q);
+// x_b = x_p - (alpha x_o + (1-alpha) x_q); x_p -= gamma x_b + sign (1-gamma)
+// mean_nb(x_b); stop when max |x_p - x_q| < tol.
+template <class R>
+__device__ inline V4<R> ring_sum(const IbArgs<R>& a, const V4<R>* X, int k, int* m_out) {
+    int nb[MAXV];
+    const int m = load_fan(a.fan, k, nb);
+    R sx = R(0), sy = R(0), sz = R(0);
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j) {
+        if (j < m) {
+            const V4<R> v = X[nb[j]];
+            sx += v.x; sy += v.y; sz += v.z;
+        }
+    }
+    *m_out = m;
+    return V4<R>{sx, sy, sz, R(0)};
+}
+
+template <class R>
+__device__ inline void hc_first(const IbArgs<R>& a, const V4<R>* q, int k, R alpha) {
+    int m;
+    const V4<R> s = ring_sum(a, q, k, &m);
+    const R c = (R(1) - alpha) / R(m);
+    const V4<R> ok = a.o[k], qk = q[k];
+    const R px = alpha * ok.x + c * s.x, py = alpha * ok.y + c * s.y, pz = alpha * ok.z + c * s.z;
+    a.pp[k] = V4<R>{px, py, pz, R(0)};
+    a.bb[k] = V4<R>{px - (alpha * ok.x + (R(1) - alpha) * qk.x), py - (alpha * ok.y + (R(1) - alpha) * qk.y),
+                    pz - (alpha * ok.z + (R(1) - alpha) * qk.z), R(0)};
+}
+
+template <class R>
+__device__ inline R hc_second(const IbArgs<R>& a, const V4<R>* q, V4<R>* qn, int k, R gamma, R sgn) {
+    int m;
+    const V4<R> s = ring_sum(a, a.bb, k, &m);
+    const R c = sgn * (R(1) - gamma) / R(m);
+    const V4<R> bk = a.bb[k], pk = a.pp[k], qk = q[k];
+    const R nx = pk.x - (gamma * bk.x + c * s.x);
+    const R ny = pk.y - (gamma * bk.y + c * s.y);
+    const R nz = pk.z - (gamma * bk.z + c * s.z);
+    qn[k] = V4<R>{nx, ny, nz, R(0)};
+    const R dx = nx - qk.x, dy = ny - qk.y, dz = nz - qk.z;
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+template <class R>
+__device__ inline unsigned long long max_bits(R v);
+template <>
+__device__ inline unsigned long long max_bits<float>(float v) { return (unsigned long long)__float_as_uint(v); }
+template <>
+__device__ inline unsigned long long max_bits<double>(double v) {
+    return (unsigned long long)__double_as_longlong(v);
+}
+template <class R>
+__device__ inline R from_bits(unsigned long long b);
+template <>
+__device__ inline float from_bits<float>(unsigned long long b) { return __uint_as_float((unsigned)b); }
+template <>
+__device__ inline double from_bits<double>(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+template <class R>
+__global__ __launch_bounds__(256) void k_hc_pass1(IbArgs<R> a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < a.nv) hc_first(a, a.o, k, R(a.sp.alpha));
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_hc_pass2(IbArgs<R> a) {
+    __shared__ R bred[4];
+    const int t = threadIdx.x;
+    const int k = blockIdx.x * blockDim.x + t;
+    R d = R(0);
+    if (k < a.nv) d = hc_second(a, a.o, a.qa, k, R(a.sp.gamma), R(a.sp.sign));
+    for (int m = 32; m > 0; m >>= 1) d = fmax(d, __shfl_xor(d, m, 64));
+    if ((t & 63) == 0) bred[t >> 6] = d;
+    __syncthreads();
+    if (t == 0) {
+        const R b = fmax(fmax(bred[0], bred[1]), fmax(bred[2], bred[3]));
+        atomicMax(a.red, max_bits(b));
+    }
+}
+
+// One work-group: iteration 1 is done; continue while not converged (rare),
+// leave the final positions in qa, record the iteration count, advance the
+// epoch and reset the reduction slot.
+template <class R>
+__global__ __launch_bounds__(1024) void k_hc_finish(IbArgs<R> a) {
+    __shared__ R bred[16];
+    __shared__ int more;
+    const int t = threadIdx.x, nth = blockDim.x;
+    const R alpha = R(a.sp.alpha), gamma = R(a.sp.gamma), tol = R(a.sp.tol), sgn = R(a.sp.sign);
+    const R dmax = from_bits<R>(*a.red);
+    int it = 1;
+    bool capped = false;
+    bool converged = dmax < tol;
+    if (!converged && it >= a.sp.max_iter) capped = true;
+    V4<R>* q = a.qa;
+    V4<R>* qn = a.qb;
+    while (!converged && !capped) {
+        ++it;
+        for (int k = t; k < a.nv; k += nth) hc_first(a, q, k, alpha);
+        __syncthreads();
+        R d = R(0);
+        for (int k = t; k < a.nv; k += nth) d = fmax(d, hc_second(a, q, qn, k, gamma, sgn));
+        for (int m = 32; m > 0; m >>= 1) d = fmax(d, __shfl_xor(d, m, 64));
+        if ((t & 63) == 0) bred[t >> 6] = d;
+        __syncthreads();
+        if (t == 0) {
+            R bmax = bred[0];
+            for (int w = 1; w < (nth + 63) / 64; ++w) bmax = fmax(bmax, bred[w]);
+            more = bmax < tol ? 0 : (it >= a.sp.max_iter ? 2 : 1);
+        }
+        __syncthreads();
+        converged = more == 0;
+        capped = more == 2;
+        V4<R>* tmp = q;
+        q = qn;
+        qn = tmp;
+    }
+    // the newest iterate is in q
+    if (q != a.qa)
+        for (int k = t; k < a.nv; k += nth) a.qa[k] = q[k];
+    if (t == 0) {
+        a.ctl->iters = it;
+        if (capped) a.ctl->cap_hits += 1;
+        a.ctl->epoch += 1;
+        *a.red = 0ull;
+    }
+}
+
+__global__ void k_bump_epoch_ib(Ctl* ctl) {
+    if (threadIdx.x == 0) ctl->epoch += 1;
+}
+
+// ---------------------------------------------------------------- launchers
+int patch_window_nodes(int storage) { return storage == IBM_LB_F64 ? 4096 : 8192; }
+
+static size_t dyn_lds(int storage) { return 3 * (size_t)patch_window_nodes(storage) * real_bytes(storage); }
+static size_t dyn_lds_spread() { return 3 * (size_t)SPREAD_WCAP * sizeof(double); }
+
+template <class R>
+static IbArgs<R> make_args(const Geom& g, const DevPtrs& d, int nv, double sigma, const SmoothParams& sp) {
+    IbArgs<R> a{};
+    a.g = g;
+    a.nv = nv;
+    a.sigma = R(sigma);
+    a.sp = sp;
+    a.r = (V4<R>*)d.r;
+    a.o = (V4<R>*)d.o;
+    a.qa = (V4<R>*)d.qa;
+    a.qb = (V4<R>*)d.qb;
+    a.pp = (V4<R>*)d.pp;
+    a.bb = (V4<R>*)d.bb;
+    a.fan = d.fan;
+    a.F = (R*)d.F;
+    a.U = (const R*)d.u;
+    a.mark = d.mark;
+    a.ctl = d.ctl;
+    a.red = d.red;
+    a.wcap = patch_window_nodes(sizeof(R) == 8 ? IBM_LB_F64 : IBM_LB_F32);
+    return a;
+}
+
+hipError_t patch_setup(int storage) {
+    const int lds = (int)dyn_lds(storage);
+    hipError_t e;
+    if (storage == IBM_LB_F64) {
+        e = hipFuncSetAttribute((const void*)k_fs_patch<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)dyn_lds_spread());
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_interp_patch<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    lds);
+    } else {
+        e = hipFuncSetAttribute((const void*)k_fs_patch<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)dyn_lds_spread());
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_interp_patch<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    lds);
+    }
+    return e;
+}
+
+template <class R>
+static hipError_t launch_step_t(const Geom& g, const DevPtrs& d, int nv, double sigma, const SmoothParams& sp,
+                                hipStream_t s, size_t lds) {
+    IbArgs<R> a = make_args<R>(g, d, nv, sigma, sp);
+    const unsigned npatch = (nv + PATCH - 1) / PATCH;
+    const unsigned nb = (nv + 255) / 256;
+    hipLaunchKernelGGL(k_interp_patch<R>, dim3(npatch), dim3(PATCH), lds, s, a);
+    const V4<R>* final_pos = a.o;
+    if (sp.max_iter > 0) {
+        hipLaunchKernelGGL(k_hc_pass1<R>, dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_hc_pass2<R>, dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_hc_finish<R>, dim3(1), dim3(1024), 0, s, a);
+        final_pos = a.qa;
+    } else {
+        hipLaunchKernelGGL(k_bump_epoch_ib, dim3(1), dim3(64), 0, s, d.ctl);
+    }
+    hipLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(PATCH), dyn_lds_spread(), s, a, final_pos, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
+                         const SmoothParams& sp, hipStream_t s) {
+    const unsigned npatch = (nv + PATCH - 1) / PATCH;
+    const size_t lds = dyn_lds_spread();
+    if (storage == IBM_LB_F64) {
+        IbArgs<double> a = make_args<double>(g, d, nv, sigma, sp);
+        hipLaunchKernelGGL(k_fs_patch<double>, dim3(npatch), dim3(PATCH), lds, s, a, (const V4<double>*)a.r, 0);
+    } else {
+        IbArgs<float> a = make_args<float>(g, d, nv, sigma, sp);
+        hipLaunchKernelGGL(k_fs_patch<float>, dim3(npatch), dim3(PATCH), lds, s, a, (const V4<float>*)a.r, 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ib_step(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
+                          const SmoothParams& sp, hipStream_t s) {
+    const size_t lds = dyn_lds(storage);
+    if (storage == IBM_LB_F64) return launch_step_t<double>(g, d, nv, sigma, sp, s, lds);
+    return launch_step_t<float>(g, d, nv, sigma, sp, s, lds);
+}
+
+}  // namespace ibmlb

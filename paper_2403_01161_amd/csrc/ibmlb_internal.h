@@ -72,16 +72,13 @@ struct DevPtrs {
     void* qb;
     void* pp;
     void* bb;
-    void* phi;               // V4 [nv] nodal forces
     int4* tris;              // [nt]
-    int* vt_start;           // [nv+1] vertex -> incident (triangle << 2 | corner)
-    int* vt_list;            // [3 nt]
-    int* nb_start;           // [nv+1] one-ring neighbours
-    int* nb_list;            // [sum of valences]
+    int4* fan;               // [nv][4]: valence, then the ordered one-ring (15 slots)
     double* obs_part;        // [OBS_BLOCKS][16]
     double* mass_part;       // [MASS_BLOCKS][4]
     double* obs_out;         // [48] final observables
     double* Abuf;            // [ACAP][9] gradient rows
+    unsigned long long* red; // [2] grid-wide max reduction slots
 };
 
 constexpr int OBS_BLOCKS = 128;
@@ -95,12 +92,6 @@ hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, cons
                        const double* A0, int rest, hipStream_t s);
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, hipStream_t s);
-hipError_t launch_forces(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
-                         hipStream_t s);
-hipError_t launch_spread(int storage, const Geom& g, const DevPtrs& d, int nv, hipStream_t s);
-hipError_t launch_interp(int storage, const Geom& g, const DevPtrs& d, int nv, hipStream_t s);
-hipError_t launch_smooth(int storage, const DevPtrs& d, int nv, const SmoothParams& sp,
-                         hipStream_t s);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
 hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, double* rho_out, double* u_out, hipStream_t s);
@@ -111,6 +102,18 @@ hipError_t launch_positions_to_abs(int storage, const Geom& g, const DevPtrs& d,
                                    double* out, hipStream_t s);
 hipError_t launch_positions_from_abs(int storage, const Geom& g, const DevPtrs& d, int nv,
                                      const double* in, hipStream_t s);
+
+// Patch-organised IB kernels (ib_patch.hip). patch_setup raises the dynamic
+// LDS limit of the patch kernels. launch_ib_pre spreads the forces of the
+// current mesh; launch_ib_step runs the IB half of one step (interpolation,
+// Euler move, smoothing, next forces and spreading).
+hipError_t patch_setup(int storage);
+int patch_window_nodes(int storage);
+hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
+                         const SmoothParams& sp, hipStream_t s);
+hipError_t launch_ib_step(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
+                          const SmoothParams& sp, hipStream_t s);
+hipError_t launch_clear_force(int storage, const Geom& g, const DevPtrs& d, hipStream_t s);
 
 size_t storage_bytes(int storage);
 size_t real_bytes(int storage);

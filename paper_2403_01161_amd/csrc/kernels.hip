@@ -10,7 +10,7 @@
 // the current step; vertex data are AoS V4 records relative to the box centre.
 #include <math.h>
 
-#include "ibmlb_internal.h"
+#include "device_common.h"
 
 namespace ibmlb {
 
@@ -54,47 +54,6 @@ template <> __device__ inline _Float16 enc<SF16>(float v, float sc) { return _Fl
 template <> __device__ inline uint16_t enc<SBF16>(float v, float) { return f32_to_bf16(v); }
 
 // ---------------------------------------------------------------- helpers
-__device__ inline int wrap(int j, int L) { return j < 0 ? j + L : (j >= L ? j - L : j); }
-
-// Peskin 4-point weights of the four nodes floor(s)-1 .. floor(s)+2 for a
-// coordinate with fractional part f in [0, 1). All four stencil arguments
-// (1+f, f, 1-f, 2-f) share the radicand 1 + 4f - 4f^2 of the two branches of
-// phi(x), so one square root serves the whole axis.
-template <class R>
-__device__ inline void peskin4(R f, R w[4]) {
-    R q = sqrt(R(1) + R(4) * f - R(4) * f * f);
-    w[0] = (R(3) - R(2) * f - q) * R(0.125);
-    w[1] = (R(3) - R(2) * f + q) * R(0.125);
-    w[2] = (R(1) + R(2) * f + q) * R(0.125);
-    w[3] = (R(1) + R(2) * f - q) * R(0.125);
-}
-
-// Stencil base along one axis: absolute node of the first stencil node and
-// the fractional part. Returns false if the position is not finite or the
-// stencil leaves a wall axis.
-template <class R>
-__device__ inline bool stencil_axis(R rel, int xci, double xcf, int L, int periodic, int* first,
-                                    R* frac) {
-    R s = rel + R(xcf);
-    if (!(fabs(s) < R(1e8))) return false;
-    R fl = floor(s);
-    *frac = s - fl;
-    int b = int(fl) + xci - 1;
-    if (periodic) {
-        int m = b % L;
-        *first = m < 0 ? m + L : m;
-        return true;
-    }
-    *first = b;
-    return b >= 0 && b + 3 <= L - 1;
-}
-
-template <class T>
-__device__ inline T wave_sum(T v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // ---------------------------------------------------------------- initial state
 template <class C>
 __global__ __launch_bounds__(256) void k_init(Geom g, LatticeParams lp, typename C::store_t* f,
@@ -251,11 +210,12 @@ __global__ __launch_bounds__(256) void k_lattice(Geom g, LatticeParams lp,
     }
 }
 
-// Diagnostic moments: rho and u (with F/2) of the current populations.
+// Diagnostic moments: rho and u (with F/2) of the current populations; the
+// force field is the one already spread for the coming step (read only).
 template <class C>
 __global__ __launch_bounds__(256) void k_moments(Geom g, LatticeParams lp,
                                                  const typename C::store_t* __restrict__ fin,
-                                                 typename C::real* __restrict__ F,
+                                                 const typename C::real* __restrict__ F,
                                                  const int* __restrict__ mark, const Ctl* ctl,
                                                  int ib, double* rho_out, double* u_out) {
     using R = typename C::real;
@@ -278,7 +238,6 @@ __global__ __launch_bounds__(256) void k_moments(Geom g, LatticeParams lp,
         const int tile = (x >> TILE_SHIFT) + g.TX * ((y >> TILE_SHIFT) + g.TY * (z >> TILE_SHIFT));
         if (mark[tile] == ctl->epoch) {
             Fx = F[n]; Fy = F[N + n]; Fz = F[2 * N + n];
-            F[n] = R(0); F[N + n] = R(0); F[2 * N + n] = R(0);
         }
     }
     const R rho = R(lp.rho0) + drho;
@@ -319,245 +278,15 @@ __global__ __launch_bounds__(256) void k_mass(Geom g, LatticeParams lp,
     }
 }
 
-// ---------------------------------------------------------------- IB: forces + tile marks
-// phi_k = -sigma sum_{t ∋ k} dA_t/dr_k, dA_t/dr_k = n_t x (r_prev - r_next)/2
-// (Eq. pi_drop read as a uniform isotropic tension). The same thread marks the
-// 8^3 tiles its 4x4x4 stencil touches with the current epoch.
-template <class R>
-__global__ __launch_bounds__(256) void k_forces(Geom g, int nv, R sigma, const V4<R>* __restrict__ r,
-                                                const int4* __restrict__ tris,
-                                                const int* __restrict__ vt_start,
-                                                const int* __restrict__ vt_list, V4<R>* phi,
-                                                int* mark, Ctl* ctl) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nv) return;
-    R fx = R(0), fy = R(0), fz = R(0);
-    const int e1 = vt_start[k + 1];
-    for (int e = vt_start[k]; e < e1; ++e) {
-        const int pk = vt_list[e];
-        const int4 t = tris[pk >> 2];
-        const int c = pk & 3;
-        const V4<R> a = r[t.x], b = r[t.y], cc = r[t.z];
-        const R e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
-        const R e2x = cc.x - a.x, e2y = cc.y - a.y, e2z = cc.z - a.z;
-        R nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-        const R len = sqrt(nx * nx + ny * ny + nz * nz);
-        if (len == R(0)) continue;
-        nx /= len; ny /= len; nz /= len;
-        // corner c: next = (c+1)%3, prev = (c+2)%3
-        V4<R> nxt = c == 0 ? b : (c == 1 ? cc : a);
-        V4<R> prv = c == 0 ? cc : (c == 1 ? a : b);
-        const R dx = prv.x - nxt.x, dy = prv.y - nxt.y, dz = prv.z - nxt.z;
-        fx -= sigma * R(0.5) * (ny * dz - nz * dy);
-        fy -= sigma * R(0.5) * (nz * dx - nx * dz);
-        fz -= sigma * R(0.5) * (nx * dy - ny * dx);
-    }
-    phi[k] = V4<R>{fx, fy, fz, R(0)};
-
-    const V4<R> p = r[k];
-    int s0[3];
-    R fr[3];
-    const bool okx = stencil_axis(p.x, g.xci[0], g.xcf[0], g.Lx, g.px, &s0[0], &fr[0]);
-    const bool oky = stencil_axis(p.y, g.xci[1], g.xcf[1], g.Ly, g.py, &s0[1], &fr[1]);
-    const bool okz = stencil_axis(p.z, g.xci[2], g.xcf[2], g.Lz, g.pz, &s0[2], &fr[2]);
-    if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) {
-        atomicOr(&ctl->flags, DFLAG_NONFINITE);
-        return;
-    }
-    if (!(okx && oky && okz)) {
-        atomicOr(&ctl->flags, DFLAG_DOMAIN);
-        return;
-    }
-    // distinct tiles of the four stencil nodes per axis (up to three when a
-    // periodic stencil wraps around a box side that is not a tile multiple)
-    const int L[3] = {g.Lx, g.Ly, g.Lz};
-    int tl[3][3], nt[3];
-    for (int a = 0; a < 3; ++a) {
-        nt[a] = 0;
-        for (int j = 0; j < 4; ++j) {
-            const int t = wrap(s0[a] + j, L[a]) >> TILE_SHIFT;
-            bool seen = false;
-            for (int m = 0; m < nt[a]; ++m) seen |= tl[a][m] == t;
-            if (!seen) tl[a][nt[a]++] = t;
-        }
-    }
-    const int ep = ctl->epoch;
-    for (int cz = 0; cz < nt[2]; ++cz)
-        for (int cy = 0; cy < nt[1]; ++cy)
-            for (int cx = 0; cx < nt[0]; ++cx)
-                mark[tl[0][cx] + g.TX * (tl[1][cy] + g.TY * tl[2][cz])] = ep;
-}
-
-// ---------------------------------------------------------------- IB: spreading
-// 16 lanes per vertex, lane = (dz, dy) row of the 4x4x4 stencil, 4 x-nodes
-// each; F(x) += phi_k Delta(r_k - x) with device-wide float atomics.
-template <class R>
-__global__ __launch_bounds__(256) void k_spread(Geom g, int nv, const V4<R>* __restrict__ r,
-                                                const V4<R>* __restrict__ phi, R* F) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = gid >> 4, l = gid & 15;
-    if (k >= nv) return;
-    const V4<R> p = r[k];
-    int s0[3];
-    R fr[3];
-    if (!stencil_axis(p.x, g.xci[0], g.xcf[0], g.Lx, g.px, &s0[0], &fr[0]) ||
-        !stencil_axis(p.y, g.xci[1], g.xcf[1], g.Ly, g.py, &s0[1], &fr[1]) ||
-        !stencil_axis(p.z, g.xci[2], g.xcf[2], g.Lz, g.pz, &s0[2], &fr[2]))
-        return;
-    const V4<R> fk = phi[k];
-    R wx[4], wy[4], wz[4];
-    peskin4(fr[0], wx);
-    peskin4(fr[1], wy);
-    peskin4(fr[2], wz);
-    const int jy = l & 3, jz = l >> 2;
-    const int ny = wrap(s0[1] + jy, g.Ly), nz = wrap(s0[2] + jz, g.Lz);
-    const R wyz = wy[jy] * wz[jz];
-    const long long N = g.N;
-    const long long row = (long long)g.Lx * (ny + (long long)g.Ly * nz);
-#pragma unroll
-    for (int jx = 0; jx < 4; ++jx) {
-        const long long node = row + wrap(s0[0] + jx, g.Lx);
-        const R w = wx[jx] * wyz;
-        unsafeAtomicAdd(F + node, fk.x * w);
-        unsafeAtomicAdd(F + N + node, fk.y * w);
-        unsafeAtomicAdd(F + 2 * N + node, fk.z * w);
-    }
-}
-
-// ---------------------------------------------------------------- IB: interpolation + Euler
-// U_k = sum_x u(x) Delta(r_k - x) over the 4x4x4 stencil (16 lanes per vertex,
-// reduced across the lane group), then o_k = r_k + U_k.
-template <class R>
-__global__ __launch_bounds__(256) void k_interp(Geom g, int nv, const V4<R>* __restrict__ r,
-                                                const R* __restrict__ U, V4<R>* o) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = gid >> 4, l = gid & 15;
-    const bool active = k < nv;
-    R ax = R(0), ay = R(0), az = R(0);
-    V4<R> p = V4<R>{R(0), R(0), R(0), R(0)};
-    bool ok = false;
-    if (active) {
-        p = r[k];
-        int s0[3];
-        R fr[3];
-        ok = stencil_axis(p.x, g.xci[0], g.xcf[0], g.Lx, g.px, &s0[0], &fr[0]) &&
-             stencil_axis(p.y, g.xci[1], g.xcf[1], g.Ly, g.py, &s0[1], &fr[1]) &&
-             stencil_axis(p.z, g.xci[2], g.xcf[2], g.Lz, g.pz, &s0[2], &fr[2]);
-        if (ok) {
-            R wx[4], wy[4], wz[4];
-            peskin4(fr[0], wx);
-            peskin4(fr[1], wy);
-            peskin4(fr[2], wz);
-            const int jy = l & 3, jz = l >> 2;
-            const int ny = wrap(s0[1] + jy, g.Ly), nz = wrap(s0[2] + jz, g.Lz);
-            const R wyz = wy[jy] * wz[jz];
-            const long long N = g.N;
-            const long long row = (long long)g.Lx * (ny + (long long)g.Ly * nz);
-#pragma unroll
-            for (int jx = 0; jx < 4; ++jx) {
-                const long long node = row + wrap(s0[0] + jx, g.Lx);
-                const R w = wx[jx] * wyz;
-                ax += U[node] * w;
-                ay += U[N + node] * w;
-                az += U[2 * N + node] * w;
-            }
-        }
-    }
-#pragma unroll
-    for (int m = 8; m > 0; m >>= 1) {
-        ax += __shfl_xor(ax, m, 16);
-        ay += __shfl_xor(ay, m, 16);
-        az += __shfl_xor(az, m, 16);
-    }
-    if (active && l == 0) o[k] = V4<R>{p.x + ax, p.y + ay, p.z + az, R(0)};
-}
-
-// ---------------------------------------------------------------- HC smoothing
-// One work-group runs the whole data-dependent iteration of Sec. 3.3:
-//   x_q = x_p; x_p = alpha x_o + (1-alpha) mean_nb(x_q);
-//   x_b = x_p - (alpha x_o + (1-alpha) x_q);
-//   x_p -= gamma x_b + sign (1-gamma) mean_nb(x_b);
-// until max |x_p - x_q| < tol or max_iter iterations, then r = x_p. The
-// work-group barrier orders the passes; the exit test is work-group uniform.
-template <class R>
-__global__ __launch_bounds__(1024) void k_smooth(int nv, SmoothParams sp, const V4<R>* __restrict__ o,
-                                                 V4<R>* qa, V4<R>* qb, V4<R>* P, V4<R>* B,
-                                                 const int* __restrict__ nb_start,
-                                                 const int* __restrict__ nb_list, V4<R>* r_out,
-                                                 Ctl* ctl) {
-    __shared__ R red[16];
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const R alpha = R(sp.alpha), gamma = R(sp.gamma), tol = R(sp.tol), sgn = R(sp.sign);
-    int it = 0;
-    bool capped = false;
-    V4<R>* q = qa;
-    V4<R>* qn = qb;
-    if (sp.max_iter > 0) {
-        for (int k = tid; k < nv; k += nth) q[k] = o[k];
-        __syncthreads();
-        for (;;) {
-            ++it;
-            for (int k = tid; k < nv; k += nth) {
-                const int e0 = nb_start[k], e1 = nb_start[k + 1];
-                R sx = R(0), sy = R(0), sz = R(0);
-                for (int e = e0; e < e1; ++e) {
-                    const V4<R> v = q[nb_list[e]];
-                    sx += v.x; sy += v.y; sz += v.z;
-                }
-                const R c = (R(1) - alpha) / R(e1 - e0);
-                const V4<R> ok = o[k], qk = q[k];
-                const R px = alpha * ok.x + c * sx, py = alpha * ok.y + c * sy, pz = alpha * ok.z + c * sz;
-                P[k] = V4<R>{px, py, pz, R(0)};
-                B[k] = V4<R>{px - (alpha * ok.x + (R(1) - alpha) * qk.x),
-                             py - (alpha * ok.y + (R(1) - alpha) * qk.y),
-                             pz - (alpha * ok.z + (R(1) - alpha) * qk.z), R(0)};
-            }
-            __syncthreads();
-            R dmax = R(0);
-            for (int k = tid; k < nv; k += nth) {
-                const int e0 = nb_start[k], e1 = nb_start[k + 1];
-                R sx = R(0), sy = R(0), sz = R(0);
-                for (int e = e0; e < e1; ++e) {
-                    const V4<R> v = B[nb_list[e]];
-                    sx += v.x; sy += v.y; sz += v.z;
-                }
-                const R c = sgn * (R(1) - gamma) / R(e1 - e0);
-                const V4<R> bk = B[k], pk = P[k], qk = q[k];
-                const R nx = pk.x - (gamma * bk.x + c * sx);
-                const R ny = pk.y - (gamma * bk.y + c * sy);
-                const R nz = pk.z - (gamma * bk.z + c * sz);
-                qn[k] = V4<R>{nx, ny, nz, R(0)};
-                const R dx = nx - qk.x, dy = ny - qk.y, dz = nz - qk.z;
-                dmax = fmax(dmax, sqrt(dx * dx + dy * dy + dz * dz));
-            }
-            for (int m = 32; m > 0; m >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, m, 64));
-            if ((tid & 63) == 0) red[tid >> 6] = dmax;
-            __syncthreads();
-            R all = red[0];
-            for (int w = 1; w < (nth + 63) / 64; ++w) all = fmax(all, red[w]);
-            __syncthreads();
-            if (all < tol) break;
-            if (it >= sp.max_iter) {
-                capped = true;
-                break;
-            }
-            V4<R>* t = q;
-            q = qn;
-            qn = t;
-        }
-        for (int k = tid; k < nv; k += nth) r_out[k] = qn[k];
-    } else {
-        for (int k = tid; k < nv; k += nth) r_out[k] = o[k];
-    }
-    if (tid == 0) {
-        ctl->iters = it;
-        if (capped) ctl->cap_hits += 1;
-        ctl->epoch += 1;
-    }
-}
-
 __global__ void k_bump_epoch(Ctl* ctl) {
     if (threadIdx.x == 0) ctl->epoch += 1;
+}
+
+template <class R>
+__global__ void k_clear(R* F, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        F[i] = R(0);
 }
 
 // ---------------------------------------------------------------- observables (FP64)
@@ -794,44 +523,15 @@ hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, c
     if ((storage) == IBM_LB_F64) { using R = double; __VA_ARGS__; }     \
     else { using R = float; __VA_ARGS__; }
 
-hipError_t launch_forces(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
-                         hipStream_t s) {
-    DISPATCH_REAL(storage, R, {
-        hipLaunchKernelGGL(k_forces<R>, dim3(blocks_for(nv, 256)), dim3(256), 0, s, g, nv, R(sigma),
-                           (const V4<R>*)d.r, d.tris, d.vt_start, d.vt_list, (V4<R>*)d.phi, d.mark,
-                           d.ctl);
-    });
-    return hipGetLastError();
-}
-
-hipError_t launch_spread(int storage, const Geom& g, const DevPtrs& d, int nv, hipStream_t s) {
-    DISPATCH_REAL(storage, R, {
-        hipLaunchKernelGGL(k_spread<R>, dim3(blocks_for(16LL * nv, 256)), dim3(256), 0, s, g, nv,
-                           (const V4<R>*)d.r, (const V4<R>*)d.phi, (R*)d.F);
-    });
-    return hipGetLastError();
-}
-
-hipError_t launch_interp(int storage, const Geom& g, const DevPtrs& d, int nv, hipStream_t s) {
-    DISPATCH_REAL(storage, R, {
-        hipLaunchKernelGGL(k_interp<R>, dim3(blocks_for(16LL * nv, 256)), dim3(256), 0, s, g, nv,
-                           (const V4<R>*)d.r, (const R*)d.u, (V4<R>*)d.o);
-    });
-    return hipGetLastError();
-}
-
-hipError_t launch_smooth(int storage, const DevPtrs& d, int nv, const SmoothParams& sp,
-                         hipStream_t s) {
-    DISPATCH_REAL(storage, R, {
-        hipLaunchKernelGGL(k_smooth<R>, dim3(1), dim3(1024), 0, s, nv, sp, (const V4<R>*)d.o,
-                           (V4<R>*)d.qa, (V4<R>*)d.qb, (V4<R>*)d.pp, (V4<R>*)d.bb, d.nb_start,
-                           d.nb_list, (V4<R>*)d.r, d.ctl);
-    });
-    return hipGetLastError();
-}
-
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s) {
     hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, s, d.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_force(int storage, const Geom& g, const DevPtrs& d, hipStream_t s) {
+    DISPATCH_REAL(storage, R, {
+        hipLaunchKernelGGL(k_clear<R>, dim3(1024), dim3(256), 0, s, (R*)d.F, 3 * g.N);
+    });
     return hipGetLastError();
 }
 
@@ -840,7 +540,7 @@ hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, c
     DISPATCH_STORAGE(storage, C, {
         using R = typename C::real;
         hipLaunchKernelGGL(k_moments<C>, dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
-                           (const typename C::store_t*)d.f[cur], (R*)d.F, d.mark, d.ctl, ib ? 1 : 0,
+                           (const typename C::store_t*)d.f[cur], (const R*)d.F, d.mark, d.ctl, ib ? 1 : 0,
                            rho_out, u_out);
     });
     return hipGetLastError();
