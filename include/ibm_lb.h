@@ -165,12 +165,47 @@ size_t ibm_lb_state_bytes(const ibm_lb* h);
 int ibm_lb_save(ibm_lb* h, void* dst, size_t n);
 int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
 
+/* Autotuner: times `reps` launches of each variant of the fused lattice
+ * kernel (non-temporal population loads on/off, 256/512-thread work-groups)
+ * on this handle's buffers and keeps the fastest for later steps. The state
+ * is unchanged (the timed launches write only the spare population copy).
+ * Synchronises the stream. *variant (may be NULL) receives the choice.
+ * Errors: EINVAL, EDEVICE, sticky. */
+int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);
+
 /* Kernel timing of the fused lattice kernel: when enabled, every step records
  * HIP events around the lattice kernel on the handle's stream.
  * ibm_lb_timing_read synchronises and returns the summed elapsed time (ms)
  * and launch count since the last read. */
 int ibm_lb_timing_enable(ibm_lb* h, int32_t enable);
 int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
+
+/* ---- ensembles of independent droplets (one set of launches per step) ----
+ * The paper's statistics come from many independent trajectories, one
+ * droplet each (Sec. 4); an ensemble advances n of them together. Members
+ * may differ in box size, periodicity, tau, sigma, mesh and gradient history
+ * but share one storage format. Each step is one batched launch of the fused
+ * lattice kernel over every member's nodes, then the batched IB kernels over
+ * every member's surface patches; work-groups map to members by offset
+ * tables, so heterogeneous boxes balance by tile count.
+ *
+ * ibm_lb_batch_init: cfgs[n] as for ibm_lb_init (each member's workspace
+ *   rule applies; cfgs[i].stream is ignored); all work goes to `stream`.
+ *   Errors: EINVAL (n < 1, mixed storage, any member invalid), ENOMEM, EDEVICE.
+ * ibm_lb_batch_step: A_tables is host memory [n][nsteps][9] (member-major),
+ *   copied before return; member i's step j uses A_tables + 9 (i nsteps + j).
+ * ibm_lb_batch_observables: out[n]; synchronising; returns the first member
+ *   error. ibm_lb_batch_member gives member i's handle for synchronising
+ *   reads (vertices, fields, observables, save); stepping a member on its
+ *   own while it belongs to an ensemble is not supported.
+ * ibm_lb_batch_autotune: as ibm_lb_autotune for the batched lattice launch.
+ * ibm_lb_batch_destroy frees the ensemble and its members. */
+int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb_batch** out);
+int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps);
+int ibm_lb_batch_observables(ibm_lb_batch* b, ibm_lb_obs* out);
+int ibm_lb_batch_member(ibm_lb_batch* b, int32_t i, ibm_lb** out);
+int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant);
+void ibm_lb_batch_destroy(ibm_lb_batch* b);
 
 void ibm_lb_destroy(ibm_lb* h);
 const char* ibm_lb_strerror(int code);

@@ -294,6 +294,7 @@ struct ibm_lb {
     int sticky = IBM_LB_OK;
     bool f_ready = false;        // F and tile marks hold the spread of the current mesh
     std::vector<int> perm;       // internal vertex k is caller vertex perm[k]
+    int lattice_variant = 0;     // chosen by ibm_lb_autotune
     double* stage = nullptr;     // pinned host staging for gradient rows
     hipEvent_t stage_done = nullptr;
     bool timing = false;
@@ -377,7 +378,8 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
             e1 = h->ev[h->ev_used].second;
             HIP_TRY(hipEventRecord(e0, h->stream), "hipEventRecord");
         }
-        HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->stream), "lattice launch");
+        HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->lattice_variant, h->stream),
+                "lattice launch");
         if (h->timing) {
             HIP_TRY(hipEventRecord(e1, h->stream), "hipEventRecord");
             h->ev_used++;
@@ -733,6 +735,44 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n) {
     return IBM_LB_OK;
 }
 
+int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
+    if (!h || reps < 1) return fail(IBM_LB_EINVAL, "bad autotune arguments");
+    if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
+    int rc = set_device(h);
+    if (rc) return rc;
+    // The timed launches read the current populations and write the other
+    // copy, which the next step overwrites; the force field is not touched.
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&b), "hipEventCreate");
+    const double* Arow = h->d.Abuf + 9ll * ACAP;
+    // interleaved rounds; each variant scores its fastest round
+    float best_of[LATTICE_VARIANTS];
+    for (int v = 0; v < LATTICE_VARIANTS; ++v) best_of[v] = 1e30f;
+    hipError_t e = hipSuccess;
+    for (int round = 0; round < 4 && e == hipSuccess; ++round)
+        for (int v = 0; v < LATTICE_VARIANTS && e == hipSuccess; ++v) {
+            e = launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, false, Arow, v, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(a, h->stream);
+            for (int k = 0; k < reps && e == hipSuccess; ++k)
+                e = launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, false, Arow, v, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(b, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e == hipSuccess) best_of[v] = std::min(best_of[v], ms);
+        }
+    int best_v = 0;
+    for (int v = 1; v < LATTICE_VARIANTS; ++v)
+        if (best_of[v] < best_of[best_v]) best_v = v;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    h->lattice_variant = best_v;
+    if (variant) *variant = best_v;
+    return IBM_LB_OK;
+}
+
 int ibm_lb_timing_enable(ibm_lb* h, int32_t enable) {
     if (!h) return fail(IBM_LB_EINVAL, "handle is NULL");
     h->timing = enable != 0;
@@ -750,6 +790,233 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches) {
     h->acc_ms = 0.0;
     h->launches = 0;
     return IBM_LB_OK;
+}
+
+// ---------------------------------------------------------------- ensembles
+struct ibm_lb_batch {
+    std::vector<ibm_lb*> m;
+    int storage = 0, device = 0, n = 0;
+    hipStream_t stream = nullptr;
+    LatDesc* lat_desc = nullptr;  // device [n]
+    int* lat_start = nullptr;     // device [2][n + 1]
+    int nblk256 = 0, nblk512 = 0;
+    void* ib_args = nullptr;      // device [n] records
+    int* patch_start = nullptr;   // device [n + 1]
+    int npatch_total = 0;
+    double* Atab = nullptr;       // device [2 halves][n][ACAP][9]
+    double* stage = nullptr;      // pinned [2 halves][n][ACAP][9]
+    hipEvent_t stage_done[2] = {nullptr, nullptr};
+    int half = 0;
+    int cur = 0;
+    int64_t step = 0;
+    bool f_ready = false;
+    int variant = 0;
+};
+
+namespace {
+int batch_fail_cleanup(ibm_lb_batch* b, int code) {
+    ibm_lb_batch_destroy(b);
+    return code;
+}
+}  // namespace
+
+int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb_batch** out) {
+    if (!out || !cfgs || n < 1) return fail(IBM_LB_EINVAL, "bad batch_init arguments");
+    *out = nullptr;
+    for (int i = 1; i < n; ++i)
+        if (cfgs[i].storage != cfgs[0].storage) return fail(IBM_LB_EINVAL, "ensemble members need one storage format");
+    ibm_lb_batch* b = new (std::nothrow) ibm_lb_batch();
+    if (!b) return fail(IBM_LB_ENOMEM, "host allocation");
+    b->n = n;
+    b->storage = cfgs[0].storage;
+    b->stream = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        ibm_lb_config c = cfgs[i];
+        c.stream = stream;
+        ibm_lb* h = nullptr;
+        int rc = ibm_lb_init(&c, &h);
+        if (rc) {
+            std::string msg = "member " + std::to_string(i) + ": " + g_last_error;
+            batch_fail_cleanup(b, rc);
+            return fail(rc, msg);
+        }
+        b->m.push_back(h);
+    }
+    b->device = b->m[0]->device;
+    auto bail = [&](hipError_t e, const char* where) { return batch_fail_cleanup(b, hip_fail(e, where)); };
+    hipError_t e;
+    std::vector<LatDesc> ld(n);
+    std::vector<int> st(2 * (n + 1), 0), ps(n + 1, 0);
+    const size_t rec = ib_args_bytes(b->storage);
+    std::vector<char> args(rec * n);
+    for (int i = 0; i < n; ++i) {
+        ibm_lb* h = b->m[i];
+        LatDesc& L = ld[i];
+        L.g = h->g;
+        L.lp = h->lp;
+        L.f[0] = h->d.f[0];
+        L.f[1] = h->d.f[1];
+        L.F = h->d.F;
+        L.u = h->d.u;
+        L.mark = h->d.mark;
+        L.ctl = h->d.ctl;
+        L.A = nullptr;  // set below, once the table is allocated
+        L.ib = h->nv > 0 ? 1 : 0;
+        st[i + 1] = st[i] + (int)((h->g.N + 255) / 256);
+        st[n + 1 + i + 1] = st[n + 1 + i] + (int)((h->g.N + 511) / 512);
+        ps[i + 1] = ps[i] + (h->nv + 255) / 256;
+        fill_ib_args(b->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, args.data() + rec * i);
+    }
+    b->nblk256 = st[n];
+    b->nblk512 = st[2 * n + 1];
+    b->npatch_total = ps[n];
+    const size_t tab = (size_t)n * ACAP * 9;
+    if ((e = hipMalloc((void**)&b->Atab, 2 * tab * sizeof(double))) != hipSuccess) return bail(e, "gradient tables");
+    if ((e = hipHostMalloc((void**)&b->stage, 2 * tab * sizeof(double), hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "pinned staging");
+    if ((e = hipMemset(b->Atab, 0, 2 * tab * sizeof(double))) != hipSuccess) return bail(e, "gradient tables");
+    for (int i = 0; i < n; ++i) ld[i].A = b->Atab + (size_t)i * ACAP * 9;
+    if ((e = hipMalloc((void**)&b->lat_desc, sizeof(LatDesc) * n)) != hipSuccess) return bail(e, "descriptors");
+    if ((e = hipMalloc((void**)&b->lat_start, sizeof(int) * st.size())) != hipSuccess) return bail(e, "offsets");
+    if ((e = hipMalloc(&b->ib_args, rec * n)) != hipSuccess) return bail(e, "ib records");
+    if ((e = hipMalloc((void**)&b->patch_start, sizeof(int) * ps.size())) != hipSuccess) return bail(e, "offsets");
+    if ((e = hipMemcpy(b->lat_desc, ld.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "descriptors");
+    if ((e = hipMemcpy(b->lat_start, st.data(), sizeof(int) * st.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "offsets");
+    if ((e = hipMemcpy(b->ib_args, args.data(), rec * n, hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "ib records");
+    if ((e = hipMemcpy(b->patch_start, ps.data(), sizeof(int) * ps.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "offsets");
+    for (int k = 0; k < 2; ++k) {
+        if ((e = hipEventCreateWithFlags(&b->stage_done[k], hipEventDisableTiming)) != hipSuccess)
+            return bail(e, "hipEventCreate");
+        if ((e = hipEventRecord(b->stage_done[k], b->stream)) != hipSuccess) return bail(e, "hipEventRecord");
+    }
+    if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return bail(e, "sync");
+    *out = b;
+    return IBM_LB_OK;
+}
+
+int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps) {
+    if (!b || !A_tables || nsteps < 0) return fail(IBM_LB_EINVAL, "bad batch_step arguments");
+    for (ibm_lb* h : b->m)
+        if (h->sticky) return fail(h->sticky, "earlier asynchronous error in a member");
+    HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
+    const int n = b->n;
+    const size_t tab = (size_t)n * ACAP * 9;
+    if (!b->f_ready) {
+        HIP_TRY(launch_ib_pre_batch(b->storage, b->ib_args, b->patch_start, n, b->npatch_total, b->stream),
+                "ib_pre launch");
+        b->f_ready = true;
+    }
+    for (int done = 0; done < nsteps;) {
+        const int len = std::min(nsteps - done, ACAP);
+        const int hf = b->half;
+        // wait until the staging half is free, then fill it member by member
+        HIP_TRY(hipEventSynchronize(b->stage_done[hf]), "staging wait");
+        double* sg = b->stage + hf * tab;
+        for (int i = 0; i < n; ++i)
+            memcpy(sg + (size_t)i * ACAP * 9, A_tables + ((size_t)i * nsteps + done) * 9, sizeof(double) * 9 * len);
+        double* dst = b->Atab + hf * tab;
+        HIP_TRY(hipMemcpyAsync(dst, sg, sizeof(double) * tab, hipMemcpyHostToDevice, b->stream), "upload tables");
+        HIP_TRY(hipEventRecord(b->stage_done[hf], b->stream), "hipEventRecord");
+        for (int j = 0; j < len; ++j) {
+            HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_start, n, b->nblk256, b->nblk512, b->cur,
+                                         (long long)hf * tab + 9ll * j, b->variant, b->stream),
+                    "lattice batch launch");
+            HIP_TRY(launch_ib_step_batch(b->storage, b->ib_args, b->patch_start, n, b->npatch_total, b->stream),
+                    "ib batch launch");
+            b->cur ^= 1;
+        }
+        // each member keeps its last gradient for the orientation observable
+        for (int i = 0; i < n; ++i)
+            HIP_TRY(hipMemcpyAsync(b->m[i]->d.Abuf + 9ll * ACAP, dst + (size_t)i * ACAP * 9 + 9ll * (len - 1),
+                                   9 * sizeof(double), hipMemcpyDeviceToDevice, b->stream),
+                    "copy last gradient");
+        b->half ^= 1;
+        done += len;
+    }
+    b->step += nsteps;
+    for (ibm_lb* h : b->m) {
+        h->cur = b->cur;
+        h->step = b->step;
+        h->f_ready = true;
+    }
+    return IBM_LB_OK;
+}
+
+int ibm_lb_batch_observables(ibm_lb_batch* b, ibm_lb_obs* out) {
+    if (!b || !out) return fail(IBM_LB_EINVAL, "bad batch_observables arguments");
+    int first_rc = IBM_LB_OK;
+    for (int i = 0; i < b->n; ++i) {
+        int rc = ibm_lb_observables(b->m[i], &out[i]);
+        if (rc && !first_rc) first_rc = rc;
+    }
+    return first_rc;
+}
+
+int ibm_lb_batch_member(ibm_lb_batch* b, int32_t i, ibm_lb** out) {
+    if (!b || !out || i < 0 || i >= b->n) return fail(IBM_LB_EINVAL, "bad batch_member arguments");
+    *out = b->m[i];
+    return IBM_LB_OK;
+}
+
+int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant) {
+    if (!b || reps < 1) return fail(IBM_LB_EINVAL, "bad batch_autotune arguments");
+    HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    float best_of[LATTICE_VARIANTS];
+    for (int v = 0; v < LATTICE_VARIANTS; ++v) best_of[v] = 1e30f;
+    hipError_t e = hipSuccess;
+    // the timed launches write only the spare population copies; the force
+    // field is consumed, so it is spread again before the next step
+    for (int round = 0; round < 4 && e == hipSuccess; ++round)
+        for (int v = 0; v < LATTICE_VARIANTS && e == hipSuccess; ++v) {
+            e = hipEventRecord(e0, b->stream);
+            for (int k = 0; k < reps && e == hipSuccess; ++k)
+                e = launch_lattice_batch(b->storage, b->lat_desc, b->lat_start, b->n, b->nblk256, b->nblk512, b->cur,
+                                         0, v, b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) best_of[v] = std::min(best_of[v], ms);
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "batch autotune");
+    int best_v = 0;
+    for (int v = 1; v < LATTICE_VARIANTS; ++v)
+        if (best_of[v] < best_of[best_v]) best_v = v;
+    b->variant = best_v;
+    // the autotune launches consumed and cleared the force field of the members
+    for (ibm_lb* h : b->m) {
+        HIP_TRY(launch_clear_force(h->storage, h->g, h->d, b->stream), "clear force");
+        HIP_TRY(launch_bump_epoch(h->d, b->stream), "bump epoch");
+        h->f_ready = false;
+    }
+    b->f_ready = false;
+    if (variant) *variant = best_v;
+    return IBM_LB_OK;
+}
+
+void ibm_lb_batch_destroy(ibm_lb_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream || !b->m.empty()) (void)hipStreamSynchronize(b->stream);
+    for (auto& ev : b->stage_done)
+        if (ev) (void)hipEventDestroy(ev);
+    if (b->stage) (void)hipHostFree(b->stage);
+    if (b->Atab) (void)hipFree(b->Atab);
+    if (b->lat_desc) (void)hipFree(b->lat_desc);
+    if (b->lat_start) (void)hipFree(b->lat_start);
+    if (b->ib_args) (void)hipFree(b->ib_args);
+    if (b->patch_start) (void)hipFree(b->patch_start);
+    for (ibm_lb* h : b->m) ibm_lb_destroy(h);
+    delete b;
 }
 
 void ibm_lb_destroy(ibm_lb* h) {

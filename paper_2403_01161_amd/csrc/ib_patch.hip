@@ -260,15 +260,12 @@ __device__ bool spread_window(const IbArgs<R>& a, const Stage<R>& st, double* wi
     return true;
 }
 
-// Forces, tile marks and spreading of one patch from positions P. With
+// Forces, tile marks and spreading of patch p from positions P. With
 // `commit`, P (the final smoothed positions) also becomes the state r.
 template <class R>
-__global__ __launch_bounds__(PATCH) void k_fs_patch(IbArgs<R> a, const V4<R>* P, int commit) {
-    extern __shared__ unsigned char dyn[];
-    double* win = reinterpret_cast<double*>(dyn);
-    __shared__ Stage<R> st;
+__device__ void fs_patch(const IbArgs<R>& a, int p, const V4<R>* P, int commit, Stage<R>& st, double* win) {
     const int t = threadIdx.x;
-    const int k = blockIdx.x * PATCH + t;
+    const int k = p * PATCH + t;
     const int ep = a.ctl->epoch;
     const long long N = a.g.N;
     int f[3] = {0, 0, 0};
@@ -314,13 +311,18 @@ __global__ __launch_bounds__(PATCH) void k_fs_patch(IbArgs<R> a, const V4<R>* P,
     }
 }
 
+template <class R>
+__global__ __launch_bounds__(PATCH) void k_fs_patch(IbArgs<R> a, const V4<R>* P, int commit) {
+    extern __shared__ unsigned char dyn[];
+    __shared__ Stage<R> st;
+    fs_patch(a, blockIdx.x, P, commit, st, reinterpret_cast<double*>(dyn));
+}
+
 // ---------------------------------------------------------------- interpolation
 template <class R>
-__global__ __launch_bounds__(PATCH) void k_interp_patch(IbArgs<R> a) {
-    extern __shared__ unsigned char dyn[];
-    R* win = reinterpret_cast<R*>(dyn);
+__device__ void interp_patch(const IbArgs<R>& a, int patch, R* win) {
     const int t = threadIdx.x;
-    const int k = blockIdx.x * PATCH + t;
+    const int k = patch * PATCH + t;
     const long long N = a.g.N;
     int f[3] = {0, 0, 0};
     R w[3][4];
@@ -375,6 +377,12 @@ __global__ __launch_bounds__(PATCH) void k_interp_patch(IbArgs<R> a) {
         }
     }
     a.o[k] = V4<R>{p.x + ux, p.y + uy, p.z + uz, R(0)};
+}
+
+template <class R>
+__global__ __launch_bounds__(PATCH) void k_interp_patch(IbArgs<R> a) {
+    extern __shared__ unsigned char dyn[];
+    interp_patch(a, blockIdx.x, reinterpret_cast<R*>(dyn));
 }
 
 // ---------------------------------------------------------------- HC smoothing
@@ -439,16 +447,22 @@ template <>
 __device__ inline double from_bits<double>(unsigned long long b) { return __longlong_as_double((long long)b); }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_hc_pass1(IbArgs<R> a) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < a.nv) hc_first(a, a.o, k, R(a.sp.alpha));
+__device__ void hc_pass1(const IbArgs<R>& a, int blk) {
+    const int k = blk * 256 + threadIdx.x;
+    if (a.sp.max_iter > 0 && k < a.nv) hc_first(a, a.o, k, R(a.sp.alpha));
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_hc_pass2(IbArgs<R> a) {
+__global__ __launch_bounds__(256) void k_hc_pass1(IbArgs<R> a) {
+    hc_pass1(a, blockIdx.x);
+}
+
+template <class R>
+__device__ void hc_pass2(const IbArgs<R>& a, int blk) {
     __shared__ R bred[4];
+    if (a.sp.max_iter <= 0) return;
     const int t = threadIdx.x;
-    const int k = blockIdx.x * blockDim.x + t;
+    const int k = blk * 256 + t;
     R d = R(0);
     if (k < a.nv) d = hc_second(a, a.o, a.qa, k, R(a.sp.gamma), R(a.sp.sign));
     for (int m = 32; m > 0; m >>= 1) d = fmax(d, __shfl_xor(d, m, 64));
@@ -460,14 +474,26 @@ __global__ __launch_bounds__(256) void k_hc_pass2(IbArgs<R> a) {
     }
 }
 
+template <class R>
+__global__ __launch_bounds__(256) void k_hc_pass2(IbArgs<R> a) {
+    hc_pass2(a, blockIdx.x);
+}
+
 // One work-group: iteration 1 is done; continue while not converged (rare),
 // leave the final positions in qa, record the iteration count, advance the
 // epoch and reset the reduction slot.
 template <class R>
-__global__ __launch_bounds__(1024) void k_hc_finish(IbArgs<R> a) {
+__device__ void hc_finish(const IbArgs<R>& a) {
     __shared__ R bred[16];
     __shared__ int more;
     const int t = threadIdx.x, nth = blockDim.x;
+    if (a.sp.max_iter <= 0) {
+        if (t == 0) {
+            a.ctl->iters = 0;
+            a.ctl->epoch += 1;
+        }
+        return;
+    }
     const R alpha = R(a.sp.alpha), gamma = R(a.sp.gamma), tol = R(a.sp.tol), sgn = R(a.sp.sign);
     const R dmax = from_bits<R>(*a.red);
     int it = 1;
@@ -508,8 +534,59 @@ __global__ __launch_bounds__(1024) void k_hc_finish(IbArgs<R> a) {
     }
 }
 
-__global__ void k_bump_epoch_ib(Ctl* ctl) {
-    if (threadIdx.x == 0) ctl->epoch += 1;
+template <class R>
+__global__ __launch_bounds__(1024) void k_hc_finish(IbArgs<R> a) {
+    hc_finish(a);
+}
+
+// ---------------------------------------------------------------- ensemble forms
+// Work-group b of a batched launch belongs to the member d with
+// start[d] <= b < start[d+1] (start: patch offsets, one patch = 256 vertices).
+__device__ inline int member_of(const int* __restrict__ start, int ndrop, int b) {
+    int lo = 0, hi = ndrop;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <class R>
+__global__ __launch_bounds__(PATCH) void k_interp_batch(const IbArgs<R>* __restrict__ args,
+                                                       const int* __restrict__ start, int ndrop) {
+    extern __shared__ unsigned char dyn[];
+    const int d = member_of(start, ndrop, blockIdx.x);
+    interp_patch(args[d], blockIdx.x - start[d], reinterpret_cast<R*>(dyn));
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_hc_pass1_batch(const IbArgs<R>* __restrict__ args,
+                                                        const int* __restrict__ start, int ndrop) {
+    const int d = member_of(start, ndrop, blockIdx.x);
+    hc_pass1(args[d], blockIdx.x - start[d]);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_hc_pass2_batch(const IbArgs<R>* __restrict__ args,
+                                                        const int* __restrict__ start, int ndrop) {
+    const int d = member_of(start, ndrop, blockIdx.x);
+    hc_pass2(args[d], blockIdx.x - start[d]);
+}
+
+template <class R>
+__global__ __launch_bounds__(1024) void k_hc_finish_batch(const IbArgs<R>* __restrict__ args) {
+    hc_finish(args[blockIdx.x]);
+}
+
+template <class R>
+__global__ __launch_bounds__(PATCH) void k_fs_batch(const IbArgs<R>* __restrict__ args, const int* __restrict__ start,
+                                                   int ndrop, int commit) {
+    extern __shared__ unsigned char dyn[];
+    __shared__ Stage<R> st;
+    const int d = member_of(start, ndrop, blockIdx.x);
+    const IbArgs<R>& a = args[d];
+    const V4<R>* P = commit ? (a.sp.max_iter > 0 ? a.qa : a.o) : a.r;
+    fs_patch(a, blockIdx.x - start[d], P, commit, st, reinterpret_cast<double*>(dyn));
 }
 
 // ---------------------------------------------------------------- launchers
@@ -544,17 +621,26 @@ static IbArgs<R> make_args(const Geom& g, const DevPtrs& d, int nv, double sigma
 hipError_t patch_setup(int storage) {
     const int lds = (int)dyn_lds(storage);
     hipError_t e;
+    const int lds_s = (int)dyn_lds_spread();
     if (storage == IBM_LB_F64) {
-        e = hipFuncSetAttribute((const void*)k_fs_patch<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)dyn_lds_spread());
+        e = hipFuncSetAttribute((const void*)k_fs_patch<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_s);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_fs_batch<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_s);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_interp_patch<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_interp_batch<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    lds);
     } else {
-        e = hipFuncSetAttribute((const void*)k_fs_patch<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)dyn_lds_spread());
+        e = hipFuncSetAttribute((const void*)k_fs_patch<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_s);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_fs_batch<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_s);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_interp_patch<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_interp_batch<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     lds);
     }
     return e;
@@ -567,16 +653,50 @@ static hipError_t launch_step_t(const Geom& g, const DevPtrs& d, int nv, double 
     const unsigned npatch = (nv + PATCH - 1) / PATCH;
     const unsigned nb = (nv + 255) / 256;
     hipLaunchKernelGGL(k_interp_patch<R>, dim3(npatch), dim3(PATCH), lds, s, a);
-    const V4<R>* final_pos = a.o;
+    const V4<R>* final_pos = sp.max_iter > 0 ? a.qa : a.o;
     if (sp.max_iter > 0) {
         hipLaunchKernelGGL(k_hc_pass1<R>, dim3(nb), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_hc_pass2<R>, dim3(nb), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(k_hc_finish<R>, dim3(1), dim3(1024), 0, s, a);
-        final_pos = a.qa;
-    } else {
-        hipLaunchKernelGGL(k_bump_epoch_ib, dim3(1), dim3(64), 0, s, d.ctl);
     }
+    hipLaunchKernelGGL(k_hc_finish<R>, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(PATCH), dyn_lds_spread(), s, a, final_pos, 1);
+    return hipGetLastError();
+}
+
+size_t ib_args_bytes(int storage) { return storage == IBM_LB_F64 ? sizeof(IbArgs<double>) : sizeof(IbArgs<float>); }
+
+void fill_ib_args(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma, const SmoothParams& sp,
+                  void* out) {
+    if (storage == IBM_LB_F64) *(IbArgs<double>*)out = make_args<double>(g, d, nv, sigma, sp);
+    else *(IbArgs<float>*)out = make_args<float>(g, d, nv, sigma, sp);
+}
+
+template <class R>
+static hipError_t batch_step_t(const void* args, const int* start, int ndrop, int npatch_total, hipStream_t s) {
+    const IbArgs<R>* a = (const IbArgs<R>*)args;
+    hipLaunchKernelGGL(k_interp_batch<R>, dim3(npatch_total), dim3(PATCH), dyn_lds(sizeof(R) == 8 ? IBM_LB_F64 : IBM_LB_F32),
+                       s, a, start, ndrop);
+    hipLaunchKernelGGL(k_hc_pass1_batch<R>, dim3(npatch_total), dim3(256), 0, s, a, start, ndrop);
+    hipLaunchKernelGGL(k_hc_pass2_batch<R>, dim3(npatch_total), dim3(256), 0, s, a, start, ndrop);
+    hipLaunchKernelGGL(k_hc_finish_batch<R>, dim3(ndrop), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_fs_batch<R>, dim3(npatch_total), dim3(PATCH), dyn_lds_spread(), s, a, start, ndrop, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_ib_step_batch(int storage, const void* args, const int* start, int ndrop, int npatch_total,
+                                hipStream_t s) {
+    if (storage == IBM_LB_F64) return batch_step_t<double>(args, start, ndrop, npatch_total, s);
+    return batch_step_t<float>(args, start, ndrop, npatch_total, s);
+}
+
+hipError_t launch_ib_pre_batch(int storage, const void* args, const int* start, int ndrop, int npatch_total,
+                               hipStream_t s) {
+    if (storage == IBM_LB_F64)
+        hipLaunchKernelGGL(k_fs_batch<double>, dim3(npatch_total), dim3(PATCH), dyn_lds_spread(), s,
+                           (const IbArgs<double>*)args, start, ndrop, 0);
+    else
+        hipLaunchKernelGGL(k_fs_batch<float>, dim3(npatch_total), dim3(PATCH), dyn_lds_spread(), s,
+                           (const IbArgs<float>*)args, start, ndrop, 0);
     return hipGetLastError();
 }
 

@@ -81,6 +81,21 @@ struct DevPtrs {
     unsigned long long* red; // [2] grid-wide max reduction slots
 };
 
+// One ensemble member as the batched lattice kernel sees it. A points at the
+// member's gradient rows; a launch reads the row at A + `step` (an offset in
+// doubles that selects the staging half and the step).
+struct LatDesc {
+    Geom g;
+    LatticeParams lp;
+    void* f[2];
+    void* F;
+    void* u;
+    int* mark;
+    Ctl* ctl;
+    const double* A;
+    int ib;
+};
+
 constexpr int OBS_BLOCKS = 128;
 constexpr int MASS_BLOCKS = 512;
 constexpr int ACAP = 4096;
@@ -90,9 +105,15 @@ constexpr int OBS_OUT_N = 48;
 // hipError_t of the launch.
 hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                        const double* A0, int rest, hipStream_t s);
+// variant: bit 0 = non-temporal population loads, bit 1 = 512-thread blocks.
+constexpr int LATTICE_VARIANTS = 4;
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
-                          int cur, bool ib, const double* A_row, hipStream_t s);
+                          int cur, bool ib, const double* A_row, int variant, hipStream_t s);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
+// start: member block offsets for 256-thread blocks [ndrop + 1], followed by
+// those for 512-thread blocks [ndrop + 1].
+hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int* start, int ndrop, int nblocks256,
+                                int nblocks512, int cur, long long step, int variant, hipStream_t s);
 hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, double* rho_out, double* u_out, hipStream_t s);
 hipError_t launch_observables(int storage, const Geom& g, const LatticeParams& lp,
@@ -113,6 +134,16 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
                          const SmoothParams& sp, hipStream_t s);
 hipError_t launch_ib_step(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
                           const SmoothParams& sp, hipStream_t s);
+// Ensemble forms: args is a device array of per-member IB argument records
+// (ib_args_bytes each, filled by fill_ib_args), start the members' patch
+// offsets [ndrop + 1].
+size_t ib_args_bytes(int storage);
+void fill_ib_args(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma, const SmoothParams& sp,
+                  void* out);
+hipError_t launch_ib_pre_batch(int storage, const void* args, const int* start, int ndrop, int npatch_total,
+                               hipStream_t s);
+hipError_t launch_ib_step_batch(int storage, const void* args, const int* start, int ndrop, int npatch_total,
+                                hipStream_t s);
 hipError_t launch_clear_force(int storage, const Geom& g, const DevPtrs& d, hipStream_t s);
 
 size_t storage_bytes(int storage);

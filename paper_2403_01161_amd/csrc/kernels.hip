@@ -94,17 +94,18 @@ __global__ __launch_bounds__(256) void k_init(Geom g, LatticeParams lp, typename
 // post-collision population to its neighbour. A population whose target lies
 // beyond a wall is reflected into the opposite slot of the same node with
 // the moving-wall term -2 w_i rho0 c_i.u_w / cs^2, u_w = A (x + c_i/2 - x_c).
-template <class C, bool IB>
-__global__ __launch_bounds__(256) void k_lattice(Geom g, LatticeParams lp,
-                                                 const typename C::store_t* __restrict__ fin,
-                                                 typename C::store_t* __restrict__ fout,
-                                                 typename C::real* __restrict__ F,
-                                                 typename C::real* __restrict__ U,
-                                                 const int* __restrict__ mark, Ctl* ctl,
-                                                 const double* __restrict__ Arow) {
+// Variants (chosen per configuration by the autotuner): non-temporal
+// population loads (pays when the two population copies fit the
+// last-level cache) and the work-group size.
+template <class C, bool IB, bool NTL>
+__device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp,
+                                             const typename C::store_t* __restrict__ fin,
+                                             typename C::store_t* __restrict__ fout,
+                                             typename C::real* __restrict__ F,
+                                             typename C::real* __restrict__ U,
+                                             const int* __restrict__ mark, Ctl* ctl,
+                                             const double* __restrict__ Arow, const long long n) {
     using R = typename C::real;
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.N) return;
     const long long N = g.N;
     const int LxLy = g.Lx * g.Ly;
     const int z = int(n / LxLy);
@@ -114,7 +115,10 @@ __global__ __launch_bounds__(256) void k_lattice(Geom g, LatticeParams lp,
 
     R d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = dec<C>(fin[i * N + n], lp.inv_scale);
+    for (int i = 0; i < Q; ++i) {
+        if (NTL) d[i] = dec<C>(__builtin_nontemporal_load(&fin[i * N + n]), lp.inv_scale);
+        else d[i] = dec<C>(fin[i * N + n], lp.inv_scale);
+    }
 
     R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
@@ -208,6 +212,44 @@ __global__ __launch_bounds__(256) void k_lattice(Geom g, LatticeParams lp,
         push(i, d[i] - omega * (d[i] - (sym + anti)) + Ssym + Santi);
         push(j, d[j] - omega * (d[j] - (sym - anti)) + Ssym - Santi);
     }
+}
+
+template <class C, bool IB, bool NTL, int BS>
+__global__ __launch_bounds__(BS) void k_lattice(Geom g, LatticeParams lp,
+                                                 const typename C::store_t* __restrict__ fin,
+                                                 typename C::store_t* __restrict__ fout,
+                                                 typename C::real* __restrict__ F,
+                                                 typename C::real* __restrict__ U,
+                                                 const int* __restrict__ mark, Ctl* ctl,
+                                                 const double* __restrict__ Arow) {
+    const long long n = (long long)blockIdx.x * BS + threadIdx.x;
+    if (n < g.N) lattice_node<C, IB, NTL>(g, lp, fin, fout, F, U, mark, ctl, Arow, n);
+}
+
+// Ensemble form: one launch covers every member's lattice; work-group b
+// belongs to the member whose block range [start[d], start[d+1]) holds b.
+template <class C, bool NTL, int BS>
+__global__ __launch_bounds__(BS) void k_lattice_batch(const LatDesc* __restrict__ desc,
+                                                       const int* __restrict__ start, int ndrop, int cur,
+                                                       long long arow) {
+    using R = typename C::real;
+    using S = typename C::store_t;
+    const int b = blockIdx.x;
+    int lo = 0, hi = ndrop;  // largest d with start[d] <= b
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid; else hi = mid;
+    }
+    const LatDesc& D = desc[lo];
+    const long long n = (long long)(b - start[lo]) * BS + threadIdx.x;
+    if (n >= D.g.N) return;
+    const double* Arow = D.A + arow;
+    if (D.ib)
+        lattice_node<C, true, NTL>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F, (R*)D.u, D.mark,
+                                   D.ctl, Arow, n);
+    else
+        lattice_node<C, false, NTL>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F, (R*)D.u, D.mark,
+                                    D.ctl, Arow, n);
 }
 
 // Diagnostic moments: rho and u (with F/2) of the current populations; the
@@ -502,19 +544,63 @@ hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, cons
     return hipGetLastError();
 }
 
+template <class C, bool IB>
+static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
+                             const double* A_row, hipStream_t s) {
+    using R = typename C::real;
+    using S = typename C::store_t;
+    const S* fi = (const S*)d.f[cur];
+    S* fo = (S*)d.f[cur ^ 1];
+    switch (variant & 3) {
+        case 0:
+            hipLaunchKernelGGL((k_lattice<C, IB, false, 256>), dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
+                               fi, fo, (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_lattice<C, IB, true, 256>), dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
+                               fi, fo, (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_lattice<C, IB, false, 512>), dim3(blocks_for(g.N, 512)), dim3(512), 0, s, g, lp,
+                               fi, fo, (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
+            break;
+        default:
+            hipLaunchKernelGGL((k_lattice<C, IB, true, 512>), dim3(blocks_for(g.N, 512)), dim3(512), 0, s, g, lp,
+                               fi, fo, (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
+            break;
+    }
+}
+
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
-                          int cur, bool ib, const double* A_row, hipStream_t s) {
+                          int cur, bool ib, const double* A_row, int variant, hipStream_t s) {
     DISPATCH_STORAGE(storage, C, {
-        using R = typename C::real;
-        using S = typename C::store_t;
-        if (ib)
-            hipLaunchKernelGGL((k_lattice<C, true>), dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
-                               (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl,
-                               A_row);
-        else
-            hipLaunchKernelGGL((k_lattice<C, false>), dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
-                               (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl,
-                               A_row);
+        if (ib) launch_lattice_v<C, true>(variant, g, lp, d, cur, A_row, s);
+        else launch_lattice_v<C, false>(variant, g, lp, d, cur, A_row, s);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int* start, int ndrop, int nblocks256,
+                                int nblocks512, int cur, long long step, int variant, hipStream_t s) {
+    DISPATCH_STORAGE(storage, C, {
+        switch (variant & 3) {
+            case 0:
+                hipLaunchKernelGGL((k_lattice_batch<C, false, 256>), dim3(nblocks256), dim3(256), 0, s, desc, start,
+                                   ndrop, cur, step);
+                break;
+            case 1:
+                hipLaunchKernelGGL((k_lattice_batch<C, true, 256>), dim3(nblocks256), dim3(256), 0, s, desc, start,
+                                   ndrop, cur, step);
+                break;
+            case 2:
+                hipLaunchKernelGGL((k_lattice_batch<C, false, 512>), dim3(nblocks512), dim3(512), 0, s, desc,
+                                   start + ndrop + 1, ndrop, cur, step);
+                break;
+            default:
+                hipLaunchKernelGGL((k_lattice_batch<C, true, 512>), dim3(nblocks512), dim3(512), 0, s, desc,
+                                   start + ndrop + 1, ndrop, cur, step);
+                break;
+        }
     });
     return hipGetLastError();
 }

@@ -54,8 +54,10 @@ class Obs(C.Structure):
 
 EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_table",
            "ibm_lb_observables", "ibm_lb_read_vertices", "ibm_lb_read_field",
-           "ibm_lb_state_bytes", "ibm_lb_save", "ibm_lb_load", "ibm_lb_timing_enable",
-           "ibm_lb_timing_read", "ibm_lb_destroy", "ibm_lb_strerror", "ibm_lb_last_error"]
+           "ibm_lb_state_bytes", "ibm_lb_save", "ibm_lb_load", "ibm_lb_autotune", "ibm_lb_timing_enable",
+           "ibm_lb_timing_read", "ibm_lb_destroy", "ibm_lb_strerror", "ibm_lb_last_error",
+           "ibm_lb_batch_init", "ibm_lb_batch_step", "ibm_lb_batch_observables", "ibm_lb_batch_member",
+           "ibm_lb_batch_autotune", "ibm_lb_batch_destroy"]
 
 
 def lib():
@@ -77,10 +79,18 @@ def lib():
         L.ibm_lb_state_bytes.restype = C.c_size_t
         L.ibm_lb_save.argtypes = [vp, vp, C.c_size_t]
         L.ibm_lb_load.argtypes = [vp, vp, C.c_size_t]
+        L.ibm_lb_autotune.argtypes = [vp, i32, C.POINTER(C.c_int32)]
         L.ibm_lb_timing_enable.argtypes = [vp, i32]
         L.ibm_lb_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
         L.ibm_lb_destroy.argtypes = [vp]
         L.ibm_lb_destroy.restype = None
+        L.ibm_lb_batch_init.argtypes = [C.POINTER(Config), i32, vp, C.POINTER(vp)]
+        L.ibm_lb_batch_step.argtypes = [vp, dp, i32]
+        L.ibm_lb_batch_observables.argtypes = [vp, C.POINTER(Obs)]
+        L.ibm_lb_batch_member.argtypes = [vp, i32, C.POINTER(vp)]
+        L.ibm_lb_batch_autotune.argtypes = [vp, i32, C.POINTER(C.c_int32)]
+        L.ibm_lb_batch_destroy.argtypes = [vp]
+        L.ibm_lb_batch_destroy.restype = None
         L.ibm_lb_strerror.argtypes = [C.c_int]
         L.ibm_lb_strerror.restype = C.c_char_p
         L.ibm_lb_last_error.restype = C.c_char_p
@@ -226,6 +236,12 @@ class Simulation:
     def load(self, src):
         _check(lib().ibm_lb_load(self._h, src.data_ptr(), src.numel()), "ibm_lb_load")
 
+    def autotune(self, reps=20):
+        """Pick the fastest lattice-kernel variant for this configuration."""
+        v = C.c_int32()
+        _check(lib().ibm_lb_autotune(self._h, int(reps), C.byref(v)), "ibm_lb_autotune")
+        return v.value
+
     def timing(self, enable=True):
         _check(lib().ibm_lb_timing_enable(self._h, int(enable)), "ibm_lb_timing_enable")
 
@@ -234,3 +250,80 @@ class Simulation:
         n = C.c_int64()
         _check(lib().ibm_lb_timing_read(self._h, C.byref(ms), C.byref(n)), "ibm_lb_timing_read")
         return ms.value, n.value
+
+
+class _Member:
+    """Read access to one ensemble member (the ensemble owns the handle)."""
+
+    def __init__(self, ens, h, L, nv):
+        self._ens, self._h, self.L, self.nv = ens, h, L, nv
+        self.N = int(np.prod(L))
+
+    observables = Simulation.observables
+    vertices = Simulation.vertices
+    fields = Simulation.fields
+
+
+class Ensemble:
+    """Independent droplets advanced together: one batched lattice launch and
+    one set of batched IB launches per step. `members` is a list of keyword
+    dicts for make_config (L, tau, sigma, radius, vertices, triangles, ...);
+    all members share `storage`."""
+
+    def __init__(self, members, storage="f32", device="cuda:0", stream=None):
+        lib()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        n = len(members)
+        cfgs = (Config * n)()
+        self._keep, self.workspaces, self._shapes = [], [], []
+        for i, kw in enumerate(members):
+            kw = dict(kw)
+            L, tau = kw.pop("L"), kw.pop("tau")
+            cfg, keep = make_config(L, tau, storage=storage, **kw)
+            nbytes = workspace_size(cfg)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            cfg.workspace, cfg.workspace_bytes = ws.data_ptr(), nbytes
+            cfgs[i] = cfg
+            self._keep.append(keep)
+            self.workspaces.append(ws)
+            self._shapes.append((tuple(int(v) for v in L), cfg.n_vertices))
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().ibm_lb_batch_init(cfgs, n, self.stream.cuda_stream, C.byref(h)), "ibm_lb_batch_init")
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ibm_lb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def autotune(self, reps=10):
+        v = C.c_int32()
+        _check(lib().ibm_lb_batch_autotune(self._h, int(reps), C.byref(v)), "ibm_lb_batch_autotune")
+        return v.value
+
+    def step(self, A_tables):
+        """A_tables: host array [n, nsteps, 9]."""
+        A = np.ascontiguousarray(A_tables, dtype=np.float64)
+        assert A.ndim == 3 and A.shape[0] == self.n and A.shape[2] == 9
+        _check(lib().ibm_lb_batch_step(self._h, _dp(A), A.shape[1]), "ibm_lb_batch_step")
+
+    def observables(self):
+        out = (Obs * self.n)()
+        _check(lib().ibm_lb_batch_observables(self._h, out), "ibm_lb_batch_observables")
+        return [_obs_dict(o) for o in out]
+
+    def member(self, i):
+        h = C.c_void_p()
+        _check(lib().ibm_lb_batch_member(self._h, int(i), C.byref(h)), "ibm_lb_batch_member")
+        L, nv = self._shapes[i]
+        return _Member(self, h, L, nv)
+
