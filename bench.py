@@ -43,6 +43,78 @@ def workload(storage="f32"):
                 corr=2000.0, seed=2)
 
 
+def ensemble_workload(n=64, seed=3, level=4):
+    """64 independent droplets: box sides drawn from {48, 64, 96}, R = L/8,
+    level-4 icospheres (2562 vertices), tau = 1, rms Ca uniform in
+    [0.05, 0.2] at R/eta = 0.472, own OU gradient table (seed 1000 + d)."""
+    import numpy as np
+    from paper_2403_01161_amd.inputs import box_center, icosphere
+    rng = np.random.default_rng(seed)
+    sides = rng.choice([48, 64, 96], size=n)
+    cas = rng.uniform(0.05, 0.2, size=n)
+    members, rms = [], []
+    for d in range(n):
+        L = int(sides[d])
+        R, tau = L / 8.0, 1.0
+        nu = (tau - 0.5) / 3.0
+        G = (0.472 ** 2) * nu / R ** 2
+        V, T = icosphere(level, R, box_center((L, L, L)))
+        members.append(dict(L=(L, L, L), tau=tau, sigma=nu * R * G / cas[d], radius=R, vertices=V,
+                            triangles=T))
+        rms.append(G)
+    return members, rms
+
+
+def ensemble_bench(steps, warmup=20):
+    import numpy as np
+    import torch
+    from paper_2403_01161_amd import ibmlb
+    from paper_2403_01161_amd.inputs import ou_gradient_table
+    members, rms = ensemble_workload()
+    n = len(members)
+    tabs = np.stack([ou_gradient_table(warmup + steps, 2000.0, rms[d], seed=1000 + d) for d in range(n)])
+    for d in range(n):
+        members[d]["A0"] = tabs[d, 0]
+    nodes = sum(int(np.prod(m["L"])) for m in members)
+    ens = ibmlb.Ensemble(members, storage="f32")
+    variant = ens.autotune(5)
+    ens.step(tabs[:, :warmup])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(tabs[:, warmup:])
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    obs = ens.observables()
+    ens.close()
+    del ens
+    solos = []
+    for d in range(n):
+        kw = dict(members[d])
+        L, tau = kw.pop("L"), kw.pop("tau")
+        s = ibmlb.Simulation(L, tau, storage="f32", **kw)
+        s.autotune(5)
+        s.step_table(tabs[d, :warmup])
+        solos.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in range(n):
+        solos[d].step_table(tabs[d, warmup:])
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    for s in solos:
+        s.close()
+    return {"workload": "64 droplets, boxes drawn from {48,64,96}^3, R = L/8, 2562-vertex icospheres, "
+                        "tau 1, OU A(t) per droplet, rms Ca U(0.05, 0.2), f32",
+            "droplets": n, "nodes": nodes, "vertices": sum(len(m["vertices"]) for m in members),
+            "steps": steps, "batched_mlups": round(nodes * steps / t_batch / 1e6, 1),
+            "solo_mlups": round(nodes * steps / t_solo / 1e6, 1),
+            "batched_over_solo": round(t_solo / t_batch, 3),
+            "batched_ms_per_step": round(t_batch / steps * 1e3, 4),
+            "batched_hbm_frac": round(152 * nodes * steps / t_batch / 1e9 / HBM_PEAK_GBS, 4),
+            "lattice_variant": variant,
+            "max_D": round(max(o["D"] for o in obs), 5)}
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2403_01161_amd", "csrc", "kernels.hip"), "rb") as f:
@@ -90,6 +162,7 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16dev", "bf16dev"])
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the ensemble and a "
@@ -170,11 +243,15 @@ def main():
                         "beta": obs2["beta"], "reg_iters": obs2["reg_iters"],
                         "mass_drift_rel": (obs2["mass"] - obs["mass"]) / obs["mass"]},
     }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if args.ensemble_steps > 0:
+        line["ensemble"] = ensemble_bench(args.ensemble_steps)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, table, args.cpu_steps)
     else:
         line["cpu_baseline"] = None
-    sim.close()
     print(json.dumps(line), flush=True)
 
 
