@@ -154,6 +154,33 @@ def cpu_baseline(w, table, steps):
                       f"({dt:.1f} s), OpenMP over z-planes for the lattice, serial IB"}
 
 
+def counters_sequence(dev, storage):
+    """Kernels whose HBM counters are read: a plain 256 MiB copy whose source
+    was first pushed out of the 256 MB last-level cache by a 1 GiB fill (three
+    times; the known 256 MiB read + 256 MiB write calibrate the counters), and
+    20 steps of the single-droplet workload after 5 warm-up steps."""
+    import torch
+    from paper_2403_01161_amd import ibmlb
+    from paper_2403_01161_amd.inputs import ou_gradient_table
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    flush = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        flush.fill_(1.0)
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del flush
+    w = workload(storage)
+    table = ou_gradient_table(26, w["corr"], w["G"], seed=w["seed"])
+    sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage=w["storage"],
+                           A0=table[0], device=dev)
+    sim.autotune(5)
+    sim.step_table(table[:5])
+    sim.step_table(table[5:25])
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_sequence": "done", "storage": storage}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +190,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=300)
+    ap.add_argument("--counters", action="store_true",
+                    help="short fixed sequence for hardware-counter runs: 3 device copies of "
+                         "256 MiB (calibration) and 20 steps of the single-droplet workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the ensemble and a "
@@ -175,6 +205,9 @@ def main():
     from paper_2403_01161_amd.inputs import ou_gradient_table
 
     dev = torch.device("cuda:0")
+    if args.counters:
+        counters_sequence(dev, args.storage)
+        return
     w = workload(args.storage)
     K, W = args.steps, args.warmup
     table = ou_gradient_table(W + 2 * K + 1, w["corr"], w["G"], seed=w["seed"])
