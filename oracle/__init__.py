@@ -77,6 +77,9 @@ def lib():
         L.ibo_fields.argtypes = [C.c_void_p, dp, dp]
         L.ibo_get_populations.argtypes = [C.c_void_p, dp]
         L.ibo_set_populations.argtypes = [C.c_void_p, dp]
+        L.ibo_freeze_iters.argtypes = [C.c_void_p, ip, i]
+        L.ibo_last_iters.argtypes = [C.c_void_p]
+        L.ibo_last_iters.restype = C.c_int
         L.ibo_nodes.argtypes = [C.c_void_p]
         L.ibo_nodes.restype = C.c_long
         _lib = L
@@ -249,6 +252,14 @@ class Oracle:
         _check(lib().ibo_fields(self._h, _dp(rho), _dp(u)), "fields")
         Lx, Ly, Lz = self.L
         return rho.reshape(Lz, Ly, Lx), u.T.reshape(3, Lz, Ly, Lx).copy()
+
+    def freeze_iters(self, counts):
+        """The next len(counts) steps run exactly counts[j] smoothing iterations."""
+        c = np.ascontiguousarray(counts, dtype=np.int32)
+        _check(lib().ibo_freeze_iters(self._h, _ip(c), len(c)), "freeze_iters")
+
+    def last_iters(self):
+        return int(lib().ibo_last_iters(self._h))
 
     def populations(self):
         f = np.zeros((self.N, 19))

@@ -497,6 +497,8 @@ struct ibo_sim {
     int last_iters;
     int cap_hits;
     double A_last[9];
+    int* sched;             /* frozen smoothing iteration counts, see ibo_freeze_iters */
+    int sched_n, sched_pos;
 };
 
 long ibo_nodes(const ibo_sim* s) { return s->N; }
@@ -506,6 +508,7 @@ void ibo_destroy(ibo_sim* s)
     if (!s) return;
     free(s->f); free(s->fpost); free(s->F); free(s->rho); free(s->u);
     free(s->r); free(s->phi); free(s->U); free(s->tris);
+    free(s->sched);
     free_ring(&s->ring);
     free(s);
 }
@@ -674,9 +677,17 @@ static int one_step(ibo_sim* s, const double A[9])
     stream(s, A);
     for (int k = 0; k < 3 * s->nv; ++k) s->r[k] += s->U[k];   /* Eq. (fwd_euler) */
     int capped = 0;
-    s->last_iters = hc_run(s->nv, &s->ring, s->reg_alpha, s->reg_gamma, s->reg_tol,
-                           s->reg_max_iter, s->reg_sign, s->r, &capped);
-    if (capped) s->cap_hits++;
+    if (s->sched_pos < s->sched_n) {
+        /* frozen count: exactly m iterations, no convergence test (a negative
+         * tolerance is never met, so the loop ends at its cap m) */
+        int m = s->sched[s->sched_pos++];
+        s->last_iters = hc_run(s->nv, &s->ring, s->reg_alpha, s->reg_gamma, -1.0, m, s->reg_sign,
+                               s->r, &capped);
+    } else {
+        s->last_iters = hc_run(s->nv, &s->ring, s->reg_alpha, s->reg_gamma, s->reg_tol,
+                               s->reg_max_iter, s->reg_sign, s->r, &capped);
+        if (capped) s->cap_hits++;
+    }
     for (int k = 0; k < 9; ++k) s->A_last[k] = A[k];
     s->step++;
     for (int k = 0; k < 3 * s->nv; ++k)
@@ -715,6 +726,24 @@ int ibo_observables(ibo_sim* s, double out[IBO_OBS_N])
     s->cap_hits = 0;
     return rc;
 }
+
+int ibo_freeze_iters(ibo_sim* s, const int* counts, int n)
+{
+    if (!s || n < 0 || (n > 0 && !counts)) return IBO_EINVAL;
+    for (int j = 0; j < n; ++j)
+        if (counts[j] < 0) return IBO_EINVAL;
+    free(s->sched);
+    s->sched = NULL;
+    s->sched_n = s->sched_pos = 0;
+    if (n == 0) return IBO_OK;
+    s->sched = malloc(sizeof(int) * (size_t)n);
+    if (!s->sched) return IBO_ENOMEM;
+    memcpy(s->sched, counts, sizeof(int) * (size_t)n);
+    s->sched_n = n;
+    return IBO_OK;
+}
+
+int ibo_last_iters(const ibo_sim* s) { return s->last_iters; }
 
 int ibo_get_vertices(const ibo_sim* s, double* r)
 {

@@ -95,6 +95,13 @@ int ibo_get_vertices(const ibo_sim* s, double* r);
 int ibo_set_vertices(ibo_sim* s, const double* r);
 /* rho [N], u [N][3] of the current state (u includes F/2 from the current mesh). */
 int ibo_fields(ibo_sim* s, double* rho, double* u);
+/* Freeze the smoothing: the next n steps run exactly counts[j] HC iterations
+ * each (no convergence test), so that a perturbed run takes the same discrete
+ * path as the nominal one (finite-difference checks of derivatives). n = 0
+ * restores the tolerance test. */
+int ibo_freeze_iters(ibo_sim* s, const int* counts, int n);
+/* Smoothing iterations of the last step. */
+int ibo_last_iters(const ibo_sim* s);
 int ibo_get_populations(const ibo_sim* s, double* f); /* [N][19] */
 int ibo_set_populations(ibo_sim* s, const double* f); /* [N][19] */
 long ibo_nodes(const ibo_sim* s);
