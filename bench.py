@@ -117,8 +117,9 @@ def ensemble_bench(steps, warmup=20):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2403_01161_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("kernels.hip", "lattice_common.h", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_2403_01161_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -207,6 +207,45 @@ int ibm_lb_batch_member(ibm_lb_batch* b, int32_t i, ibm_lb** out);
 int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant);
 void ibm_lb_batch_destroy(ibm_lb_batch* b);
 
+/* ---- adjoint: reverse-mode derivatives of the droplet deformation ----
+ * Objective J = D(r^T) = (sqrt(l1) - sqrt(l3)) / (sqrt(l1) + sqrt(l3)) of the
+ * morphological tensor S of the final mesh (Sec. 2). The adjoint is the
+ * exact transpose of the linearised timestep (forces, spreading, moments,
+ * interpolation, BGK + Guo collision, streaming with moving-wall bounce-back,
+ * Euler move, HC smoothing), with the smoothing iteration count of every step
+ * held at the value the forward run took: the tolerance test is a discrete
+ * decision and has no derivative. The adjoint computes in FP64 for every
+ * storage format.
+ *
+ * ibm_lb_objective_grad: synchronises; *value = D of the current mesh and
+ *   rbar (device double [nv][3], caller vertex order) = dD/dr. Errors:
+ *   EINVAL (no mesh; l1 - l2 or l2 - l3 below 1e-12 radius^2, where D has no
+ *   derivative), sticky.
+ *
+ * ibm_lb_adjoint_segment: reverse one segment of nsteps >= 1 steps.
+ *   ckpt (host or device, ckpt_bytes) is the checkpoint ibm_lb_save wrote at
+ *   the segment's first step and A its gradient rows [nsteps][9] (host memory
+ *   if A_on_device = 0, else device). The library reloads ckpt and recomputes
+ *   the segment, recording rho, u and F on every node and the positions and
+ *   smoothing iteration counts of every step (FP64, 56 N + 32 nv bytes per
+ *   step, in device memory the library allocates and keeps until
+ *   ibm_lb_destroy), then sweeps the steps backwards.
+ *   fbar_end: device double [19][N] (x fastest), the adjoint of the
+ *   population deviations after the segment, NULL for zero (the final time of
+ *   J = D(r^T)). rbar_end: device double [nv][3], caller vertex order, the
+ *   adjoint of the positions after the segment.
+ *   Outputs, device memory: fbar_begin and rbar_begin, the same at the
+ *   segment start (they may alias the _end arrays; fbar_begin may be NULL);
+ *   dA [nsteps][9], dJ/dA of each step (overwritten); dsigma [1], dJ/dsigma
+ *   of the segment added to *dsigma.
+ *   On return the handle holds the segment's end state. Work is enqueued on
+ *   the handle's stream; the call synchronises once, after the recompute.
+ *   Errors: EINVAL (bad arguments or checkpoint), ENOMEM, EDEVICE, sticky. */
+int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar);
+int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const double* A, int32_t nsteps,
+                           int32_t A_on_device, const double* fbar_end, const double* rbar_end, double* fbar_begin,
+                           double* rbar_begin, double* dA, double* dsigma);
+
 void ibm_lb_destroy(ibm_lb* h);
 const char* ibm_lb_strerror(int code);
 const char* ibm_lb_last_error(void);

@@ -1,0 +1,626 @@
+// Discrete adjoint (reverse-mode derivative) of the IB-LB droplet timestep.
+//
+// The forward step n -> n+1 (Sec. 3.1 and Sec. 3.3) is, with the HC iteration
+// count of the step frozen, a smooth map of (f^n, r^n, sigma, A^n):
+//   phi   = -sigma dA_surf/dr                      Eq. (pi_drop)
+//   F     = sum_k phi_k Delta(r_k - x)             Eq. (ibm_force_d), line 1
+//   rho, u from f and F/2                          Eq. (density_velocity_LB)
+//   U_k   = sum_x u(x) Delta(r_k - x)              Eq. (ibm_force_d), line 2
+//   f*    = f - (f - f^eq)/tau + S                 Eqs. (LBMEQ), (collision)
+//   f^{n+1} = stream f* with moving-wall bounce-back, Eq. (standard BB)
+//   o     = r + U                                  Eq. (fwd_euler)
+//   r^{n+1} = m_n HC iterations on o               Eq. (HC_algo_full)
+// The kernels below apply the transpose of each of these linearised maps, in
+// reverse order, to the adjoint state (fbar, rbar) and accumulate the
+// derivatives of the objective with respect to sigma and to the gradient
+// rows A^n. All adjoint arithmetic is FP64 whatever the population storage;
+// the forward quantities it needs (rho, u, F on every node, positions and
+// iteration counts of every step) are recorded during a recompute of the
+// segment from its checkpoint.
+#include <math.h>
+
+#include "lattice_common.h"
+
+namespace ibmlb {
+
+__device__ inline double4 d4(double x, double y, double z) { return make_double4(x, y, z, 0.0); }
+__device__ inline double4 operator+(double4 a, double4 b) { return d4(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ inline double4 operator-(double4 a, double4 b) { return d4(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ inline double4 operator*(double s, double4 a) { return d4(s * a.x, s * a.y, s * a.z); }
+__device__ inline double dot3(double4 a, double4 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline double4 cross3(double4 a, double4 b) {
+    return d4(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// ---------------------------------------------------------------- recording
+// rho, u (with F/2) and F of the current populations on every node: the
+// state the lattice kernel of this step will see.
+template <class C>
+__global__ __launch_bounds__(256) void k_rec_fields(Geom g, LatticeParams lp, const typename C::store_t* __restrict__ fin,
+                                                    const typename C::real* __restrict__ F,
+                                                    const int* __restrict__ mark, const Ctl* __restrict__ ctl, int ib,
+                                                    double* __restrict__ rho, double* __restrict__ u,
+                                                    double* __restrict__ Fo) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const long long N = g.N;
+    double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double v = double(dec<C>(fin[i * N + n], lp.inv_scale));
+        dr += v;
+        jx += CX[i] * v;
+        jy += CY[i] * v;
+        jz += CZ[i] * v;
+    }
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    if (ib) {
+        const int LxLy = g.Lx * g.Ly;
+        const int z = int(n / LxLy), rem = int(n - (long long)z * LxLy), y = rem / g.Lx, x = rem - y * g.Lx;
+        const int tile = (x >> TILE_SHIFT) + g.TX * ((y >> TILE_SHIFT) + g.TY * (z >> TILE_SHIFT));
+        if (mark[tile] == ctl->epoch) {
+            Fx = double(F[n]);
+            Fy = double(F[N + n]);
+            Fz = double(F[2 * N + n]);
+        }
+    }
+    const double r = lp.rho0 + dr;
+    rho[n] = r;
+    u[n] = (jx + 0.5 * Fx) / r;
+    u[N + n] = (jy + 0.5 * Fy) / r;
+    u[2 * N + n] = (jz + 0.5 * Fz) / r;
+    Fo[n] = Fx;
+    Fo[N + n] = Fy;
+    Fo[2 * N + n] = Fz;
+}
+
+template <class R>
+__global__ void k_rec_pos(int nv, const V4<R>* __restrict__ r, double4* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    const V4<R> p = r[k];
+    out[k] = d4(double(p.x), double(p.y), double(p.z));
+}
+
+__global__ void k_rec_iters(const Ctl* ctl, int* slot) {
+    if (threadIdx.x == 0) *slot = ctl->iters;
+}
+
+// ---------------------------------------------------------------- HC transpose
+// Forward iteration (o fixed, M the one-ring mean, s the sign):
+//   p' = a o + (1-a) M q,  b = p' - a o - (1-a) q,  p = p' - g b - s (1-g) M b.
+// Transpose for an incoming pbar:
+//   bbar = -g pbar - s (1-g) M^T pbar,   p'bar = pbar + bbar,
+//   obar += a pbar,   qbar = -(1-a) bbar + (1-a) M^T p'bar,
+// with (M^T y)_j = sum_{k in ring(j)} y_k / m_k. After the m iterations
+// (q_0 = o), obar += qbar. PS and PpS hold P / m and P' / m.
+__global__ void k_adj_hc_init(int nv, const int4* __restrict__ fan, const double4* __restrict__ rb,
+                              double4* __restrict__ P, double4* __restrict__ PS, double4* __restrict__ Ob) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    const double4 v = rb[k];
+    P[k] = v;
+    PS[k] = (1.0 / double(fan[4 * k].x)) * v;
+    Ob[k] = d4(0.0, 0.0, 0.0);
+}
+
+__device__ inline double4 ring_total(const int4* fan, const double4* X, int k, int* m_out) {
+    int nb[MAXV];
+    const int m = load_fan(fan, k, nb);
+    double4 s = d4(0.0, 0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+        if (j < m) s = s + X[nb[j]];
+    *m_out = m;
+    return s;
+}
+
+__global__ void k_adj_hc_a(int nv, const int4* __restrict__ fan, double alpha, double gamma, double sgn,
+                           const double4* __restrict__ P, const double4* __restrict__ PS, double4* __restrict__ Pp,
+                           double4* __restrict__ PpS, double4* __restrict__ Ob, double4* __restrict__ Qp) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    int m;
+    const double4 s = ring_total(fan, PS, k, &m);
+    const double4 p = P[k];
+    const double4 bb = (-gamma) * p - (sgn * (1.0 - gamma)) * s;
+    const double4 pp = p + bb;
+    Pp[k] = pp;
+    PpS[k] = (1.0 / double(m)) * pp;
+    Ob[k] = Ob[k] + alpha * p;  // a bbar + a p'bar - a bbar
+    Qp[k] = (-(1.0 - alpha)) * bb;
+}
+
+__global__ void k_adj_hc_b(int nv, const int4* __restrict__ fan, double alpha, const double4* __restrict__ PpS,
+                           const double4* __restrict__ Qp, double4* __restrict__ P, double4* __restrict__ PS) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    int m;
+    const double4 s = ring_total(fan, PpS, k, &m);
+    const double4 q = Qp[k] + (1.0 - alpha) * s;
+    P[k] = q;
+    PS[k] = (1.0 / double(m)) * q;
+}
+
+__global__ void k_adj_hc_end(int nv, const double4* __restrict__ P, double4* __restrict__ Ob) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    Ob[k] = Ob[k] + P[k];
+}
+
+// ---------------------------------------------------------------- stencils (FP64)
+// Peskin 4-point weights and their derivatives with respect to the vertex
+// coordinate, for fractional part f: with q = sqrt(1 + 4f - 4f^2),
+// dq/df = (2 - 4f)/q.
+__device__ inline void peskin4_d(double f, double w[4], double dw[4]) {
+    const double q = sqrt(1.0 + 4.0 * f - 4.0 * f * f);
+    const double dq = (2.0 - 4.0 * f) / q;
+    w[0] = (3.0 - 2.0 * f - q) * 0.125;
+    w[1] = (3.0 - 2.0 * f + q) * 0.125;
+    w[2] = (1.0 + 2.0 * f + q) * 0.125;
+    w[3] = (1.0 + 2.0 * f - q) * 0.125;
+    dw[0] = (-2.0 - dq) * 0.125;
+    dw[1] = (-2.0 + dq) * 0.125;
+    dw[2] = (2.0 + dq) * 0.125;
+    dw[3] = (2.0 - dq) * 0.125;
+}
+
+__device__ inline bool stencil_d(const Geom& g, double4 p, int f[3], double w[3][4], double dw[3][4]) {
+    double fr[3];
+    const bool ok = stencil_base(p.x, g.xci[0], g.xcf[0], g.Lx, g.px, &f[0], &fr[0]) &&
+                    stencil_base(p.y, g.xci[1], g.xcf[1], g.Ly, g.py, &f[1], &fr[1]) &&
+                    stencil_base(p.z, g.xci[2], g.xcf[2], g.Lz, g.pz, &f[2], &fr[2]);
+    if (ok)
+        for (int d = 0; d < 3; ++d) peskin4_d(fr[d], w[d], dw[d]);
+    return ok;
+}
+
+// Transpose of the interpolation U_k = sum_x u(x) Delta: ubar(x) += Ubar_k
+// Delta(r_k - x). One wave per vertex, one lane per stencil node.
+__global__ __launch_bounds__(256) void k_adj_spread(Geom g, int nv, const double4* __restrict__ pos,
+                                                    const double4* __restrict__ Ub, double* __restrict__ ubar) {
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= nv) return;
+    int f[3];
+    double w[3][4], dw[3][4];
+    if (!stencil_d(g, pos[k], f, w, dw)) return;
+    const int jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
+    const double wt = w[0][jx] * w[1][jy] * w[2][jz];
+    const long long n = node_index(g, f[0] + jx, f[1] + jy, f[2] + jz);
+    const double4 v = Ub[k];
+    const long long N = g.N;
+    unsafeAtomicAdd(ubar + n, v.x * wt);
+    unsafeAtomicAdd(ubar + N + n, v.y * wt);
+    unsafeAtomicAdd(ubar + 2 * N + n, v.z * wt);
+}
+
+// ---------------------------------------------------------------- lattice adjoint
+// One thread per node x. Streaming transpose (pull): gbar_i(x) = fbar_i(x +
+// c_i), or fbar_{-i}(x) when x + c_i lies beyond a wall; in the latter case
+// the wall term -6 w_i rho0 c_i.A(x + c_i/2 - x_c) contributes
+// gbar_i (-6 w_i rho0) c_i (x + c_i/2 - x_c)^T to dJ/dA. Collision and
+// moments transpose with the recorded rho, u, F:
+//   rhobar = omega sum_i gbar_i f^eq_i / rho
+//   ubar   = ubar_ext + sum_i gbar_i [omega df^eq_i/du + dS_i/du]
+//   Fbar   = sum_i gbar_i dS_i/dF + ubar / (2 rho)
+//   fbar_j = (1 - omega) gbar_j + rhobar + ubar.(c_j - u) / rho.
+// ubar_ext (the transposed interpolation) is cleared once read. Each block
+// writes its 9 partial sums of dJ/dA to part[block][9].
+__global__ __launch_bounds__(256) void k_adj_lattice(Geom g, LatticeParams lp, const double* __restrict__ fbin,
+                                                     double* __restrict__ fbout, const double* __restrict__ rho_,
+                                                     const double* __restrict__ u_, const double* __restrict__ F_,
+                                                     double* __restrict__ ubar, double* __restrict__ Fbar,
+                                                     double* __restrict__ part) {
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long N = g.N;
+    double dA[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dA[c] = 0.0;
+    if (n < N) {
+        const int LxLy = g.Lx * g.Ly;
+        const int z = int(n / LxLy), rem = int(n - (long long)z * LxLy), y = rem / g.Lx, x = rem - y * g.Lx;
+        const double xr = double(x - g.xci[0]) - g.xcf[0];
+        const double yr = double(y - g.xci[1]) - g.xcf[1];
+        const double zr = double(z - g.xci[2]) - g.xcf[2];
+        const double rho0 = lp.rho0;
+        double gb[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
+            bool wall = false;
+            if (CX[i] != 0 && (tx < 0 || tx >= g.Lx)) {
+                if (g.px) tx = wrap(tx, g.Lx); else wall = true;
+            }
+            if (CY[i] != 0 && (ty < 0 || ty >= g.Ly)) {
+                if (g.py) ty = wrap(ty, g.Ly); else wall = true;
+            }
+            if (CZ[i] != 0 && (tz < 0 || tz >= g.Lz)) {
+                if (g.pz) tz = wrap(tz, g.Lz); else wall = true;
+            }
+            if (!wall) {
+                gb[i] = fbin[i * N + tx + (long long)g.Lx * (ty + (long long)g.Ly * tz)];
+            } else {
+                const double v = fbin[opp(i) * N + n];
+                gb[i] = v;
+                const double s = -6.0 * wgt<double>(i) * rho0 * v;
+                const double wv[3] = {xr + 0.5 * CX[i], yr + 0.5 * CY[i], zr + 0.5 * CZ[i]};
+                const int ci[3] = {CX[i], CY[i], CZ[i]};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) dA[3 * a + b] += s * ci[a] * wv[b];
+            }
+        }
+        const double rho = rho_[n];
+        const double ux = u_[n], uy = u_[N + n], uz = u_[2 * N + n];
+        const double Fx = F_[n], Fy = F_[N + n], Fz = F_[2 * N + n];
+        double ex = ubar[n], ey = ubar[N + n], ez = ubar[2 * N + n];
+        if (ex != 0.0 || ey != 0.0 || ez != 0.0) {
+            ubar[n] = 0.0;
+            ubar[N + n] = 0.0;
+            ubar[2 * N + n] = 0.0;
+        }
+        const double om = lp.omega, kg = lp.kguo;
+        const double uu = ux * ux + uy * uy + uz * uz;
+        double rb = 0.0, ubx = ex, uby = ey, ubz = ez, fbx = 0.0, fby = 0.0, fbz = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double w = wgt<double>(i);
+            const double cx = CX[i], cy = CY[i], cz = CZ[i];
+            const double cu = cx * ux + cy * uy + cz * uz;
+            const double cF = cx * Fx + cy * Fy + cz * Fz;
+            const double gi = gb[i];
+            rb += gi * w * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+            // omega df^eq_i/du_a = omega w rho (3 c_a + 9 cu c_a - 3 u_a); dS_i/du_a = kg w (9 c_a cF - 3 F_a)
+            const double e1 = om * w * rho * (3.0 + 9.0 * cu) + kg * w * 9.0 * cF;
+            const double e2 = -om * w * rho * 3.0;
+            const double e3 = -kg * w * 3.0;
+            ubx += gi * (e1 * cx + e2 * ux + e3 * Fx);
+            uby += gi * (e1 * cy + e2 * uy + e3 * Fy);
+            ubz += gi * (e1 * cz + e2 * uz + e3 * Fz);
+            // dS_i/dF_a = kg w (3 c_a - 3 u_a + 9 cu c_a)
+            const double h1 = kg * w * (3.0 + 9.0 * cu), h2 = -kg * w * 3.0;
+            fbx += gi * (h1 * cx + h2 * ux);
+            fby += gi * (h1 * cy + h2 * uy);
+            fbz += gi * (h1 * cz + h2 * uz);
+        }
+        rb *= om;
+        const double inv = 1.0 / rho;
+        const double ubu = ubx * ux + uby * uy + ubz * uz;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            const double ubc = ubx * CX[j] + uby * CY[j] + ubz * CZ[j];
+            fbout[j * N + n] = (1.0 - om) * gb[j] + rb + (ubc - ubu) * inv;
+        }
+        Fbar[n] = fbx + 0.5 * ubx * inv;
+        Fbar[N + n] = fby + 0.5 * uby * inv;
+        Fbar[2 * N + n] = fbz + 0.5 * ubz * inv;
+    }
+    __shared__ double red[9][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        const double v = wave_sum(dA[c]);
+        if (lane == 0) red[c][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const int c = threadIdx.x;
+        part[(long long)blockIdx.x * 9 + c] = ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3];
+    }
+}
+
+// ---------------------------------------------------------------- vertex adjoints
+// Nodal surface-tension forces (FP64) of the recorded positions, same rule
+// as the forward: phi_k = -sigma sum_t n_t x (r_{n_{j+1}} - r_{n_j}) / 2.
+__global__ void k_adj_forces(int nv, const int4* __restrict__ fan, double sigma, const double4* __restrict__ pos,
+                             double4* __restrict__ phi) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    int nb[MAXV];
+    const int m = load_fan(fan, k, nb);
+    const double4 pk = pos[k];
+    double4 f = d4(0.0, 0.0, 0.0);
+    for (int j = 0; j < m; ++j) {
+        const double4 pa = pos[nb[j]], pb = pos[nb[j + 1 < m ? j + 1 : 0]];
+        const double4 nn = cross3(pa - pk, pb - pk);
+        const double len = sqrt(dot3(nn, nn));
+        if (len > 0.0) f = f - (0.5 * sigma / len) * cross3(nn, pb - pa);
+    }
+    phi[k] = f;
+}
+
+// Transposes of spreading and interpolation with respect to the forces and
+// the positions. One wave per vertex, one lane per stencil node:
+//   phibar_k = sum_x Fbar(x) Delta(r_k - x)
+//   rt_k     = Ob_k + sum_x [Fbar(x).phi_k + u(x).Ubar_k] grad Delta(r_k - x)
+// (Ob = Ubar is also the direct term of the Euler move o = r + U.)
+__global__ __launch_bounds__(256) void k_adj_interp(Geom g, int nv, const double4* __restrict__ pos,
+                                                    const double4* __restrict__ phi, const double4* __restrict__ Ob,
+                                                    const double* __restrict__ Fbar, const double* __restrict__ u_,
+                                                    double4* __restrict__ phib, double4* __restrict__ rt) {
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= nv) return;
+    int f[3];
+    double w[3][4], dw[3][4];
+    const double4 ub = Ob[k];
+    if (!stencil_d(g, pos[k], f, w, dw)) {
+        if (lane == 0) {
+            phib[k] = d4(0.0, 0.0, 0.0);
+            rt[k] = ub;
+        }
+        return;
+    }
+    const int jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
+    const long long n = node_index(g, f[0] + jx, f[1] + jy, f[2] + jz);
+    const long long N = g.N;
+    const double W = w[0][jx] * w[1][jy] * w[2][jz];
+    const double Gx = dw[0][jx] * w[1][jy] * w[2][jz];
+    const double Gy = w[0][jx] * dw[1][jy] * w[2][jz];
+    const double Gz = w[0][jx] * w[1][jy] * dw[2][jz];
+    const double4 fb = d4(Fbar[n], Fbar[N + n], Fbar[2 * N + n]);
+    const double4 uu = d4(u_[n], u_[N + n], u_[2 * N + n]);
+    const double s = dot3(fb, phi[k]) + dot3(uu, ub);
+    const double px = wave_sum(fb.x * W), py = wave_sum(fb.y * W), pz = wave_sum(fb.z * W);
+    const double rx = wave_sum(s * Gx), ry = wave_sum(s * Gy), rz = wave_sum(s * Gz);
+    if (lane == 0) {
+        phib[k] = d4(px, py, pz);
+        rt[k] = ub + d4(rx, ry, rz);
+    }
+}
+
+// Transpose of the forces with respect to the positions and to sigma. For
+// the triangle t = (k, a, b) with e1 = r_a - r_k, e2 = r_b - r_k, n = e1 x e2,
+// the force adjoint is the directional derivative of its area along phibar,
+//   g_t = n^.(de1 x e2 + e1 x de2) / 2,  de1 = phibar_a - phibar_k, ...
+// whose position gradient at r_k is -(dg/de1 + dg/de2) with
+//   dg/de1 = (e2 x w + de2 x n^)/2,  dg/de2 = (w x e1 + n^ x de1)/2,
+//   w = (dn - (n^.dn) n^)/|n|,  dn = de1 x e2 + e1 x de2.
+// rbar_k = rt_k - sigma sum_t dg_t/dr_k; dJ/dsigma gets -sum_t g_t, each
+// triangle counted at its lowest vertex index (block partials in part).
+__global__ __launch_bounds__(256) void k_adj_hess(int nv, const int4* __restrict__ fan, double sigma,
+                                                  const double4* __restrict__ pos, const double4* __restrict__ phib,
+                                                  const double4* __restrict__ rt, double4* __restrict__ rb,
+                                                  double* __restrict__ part) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    double gs = 0.0;
+    if (k < nv) {
+        int nb[MAXV];
+        const int m = load_fan(fan, k, nb);
+        const double4 pk = pos[k], qk = phib[k];
+        double4 acc = d4(0.0, 0.0, 0.0);
+        for (int j = 0; j < m; ++j) {
+            const int a = nb[j], b = nb[j + 1 < m ? j + 1 : 0];
+            const double4 e1 = pos[a] - pk, e2 = pos[b] - pk;
+            const double4 nn = cross3(e1, e2);
+            const double len = sqrt(dot3(nn, nn));
+            if (!(len > 0.0)) continue;
+            const double4 nh = (1.0 / len) * nn;
+            const double4 de1 = phib[a] - qk, de2 = phib[b] - qk;
+            const double4 dn = cross3(de1, e2) + cross3(e1, de2);
+            const double nd = dot3(nh, dn);
+            const double4 wv = (1.0 / len) * (dn - nd * nh);
+            const double4 g1 = 0.5 * (cross3(e2, wv) + cross3(de2, nh));
+            const double4 g2 = 0.5 * (cross3(wv, e1) + cross3(nh, de1));
+            acc = acc - (g1 + g2);
+            if (k < a && k < b) gs += 0.5 * nd;
+        }
+        rb[k] = rt[k] - sigma * acc;
+    }
+    __shared__ double red[4];
+    const double v = wave_sum(-gs);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Per-step block partials -> dJ/dA rows (overwritten) and dJ/dsigma
+// (accumulated), summed in a fixed order.
+__global__ void k_adj_reduce(int nsteps, int nbl, const double* __restrict__ Apart, int nbv,
+                             const double* __restrict__ spart, double* __restrict__ dA, double* __restrict__ dsigma) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 9 * nsteps) {
+        const int j = t / 9, c = t - 9 * (t / 9);
+        double s = 0.0;
+        for (int b = 0; b < nbl; ++b) s += Apart[((long long)j * nbl + b) * 9 + c];
+        dA[t] = s;
+    }
+    if (t == 0 && nbv > 0) {
+        double s = 0.0;
+        for (int j = 0; j < nsteps; ++j)
+            for (int b = 0; b < nbv; ++b) s += spart[(long long)j * nbv + b];
+        *dsigma += s;
+    }
+}
+
+// ---------------------------------------------------------------- objective
+// J = D = (sqrt(l1) - sqrt(l3)) / (sqrt(l1) + sqrt(l3)) of S = (5/V)(M - V xb xb^T)
+// (Sec. 2). dD/dl1 = c/(a (a+c)^2), dD/dl3 = -a/(c (a+c)^2) with a = sqrt(l1),
+// c = sqrt(l3), and dl_i/dS = v_i v_i^T, so Sbar = dD/dl1 v1 v1^T + dD/dl3 v3 v3^T.
+// Through S = 5M/V - 5 P P^T / V^2 (P = V xb):
+//   Mbar = 5 Sbar / V,  Pbar = -10 Sbar xb / V,  Vbar = (-Sbar:S + 5 xb.Sbar xb) / V.
+// obs: the observables record (0 V, 1..3 xb relative to x_c, 4..12 S,
+// 13..15 eigenvalues, 16..24 eigenvectors by rows). coef: Vbar, Pbar[3], Mbar[9].
+__global__ void k_adj_seed_coef(const double* __restrict__ obs, double* __restrict__ coef) {
+    if (threadIdx.x != 0) return;
+    const double V = obs[0];
+    const double xb[3] = {obs[1], obs[2], obs[3]};
+    const double* S = obs + 4;
+    const double a = sqrt(obs[13]), c = sqrt(obs[15]);
+    const double d1 = c / (a * (a + c) * (a + c)), d3 = -a / (c * (a + c) * (a + c));
+    const double* v1 = obs + 16;
+    const double* v3 = obs + 22;
+    double Sb[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Sb[3 * i + j] = d1 * v1[i] * v1[j] + d3 * v3[i] * v3[j];
+    double SbS = 0.0, xSx = 0.0, Sx[3];
+    for (int i = 0; i < 3; ++i) {
+        Sx[i] = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            SbS += Sb[3 * i + j] * S[3 * i + j];
+            Sx[i] += Sb[3 * i + j] * xb[j];
+        }
+        xSx += xb[i] * Sx[i];
+    }
+    coef[0] = (-SbS + 5.0 * xSx) / V;
+    for (int i = 0; i < 3; ++i) coef[1 + i] = -10.0 * Sx[i] / V;
+    for (int k = 0; k < 9; ++k) coef[4 + k] = 5.0 * Sb[k] / V;
+}
+
+// dJ/dr_k from the tetrahedra (x_c, r_k, b, c) of the fan triangles (k, b, c):
+//   V_t = r_k.(b x c)/6, s = r_k + b + c, Q = r_k r_k^T + b b^T + c c^T + s s^T,
+//   dJ/dr_k = sum_t [Vbar + Pbar.s/4 + Mbar:Q/20] (b x c)/6 + V_t [Pbar/4 + Mbar (r_k + s)/10].
+__device__ inline double qform(const double* M, double4 v) {
+    return v.x * (M[0] * v.x + M[1] * v.y + M[2] * v.z) + v.y * (M[3] * v.x + M[4] * v.y + M[5] * v.z) +
+           v.z * (M[6] * v.x + M[7] * v.y + M[8] * v.z);
+}
+
+template <class R>
+__global__ void k_adj_seed(int nv, const int4* __restrict__ fan, const V4<R>* __restrict__ r,
+                           const double* __restrict__ coef, double4* __restrict__ rb) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    const double Vb = coef[0];
+    const double4 Pb = d4(coef[1], coef[2], coef[3]);
+    const double* Mb = coef + 4;
+    int nb[MAXV];
+    const int m = load_fan(fan, k, nb);
+    const V4<R> pk = r[k];
+    const double4 a = d4(double(pk.x), double(pk.y), double(pk.z));
+    double4 g = d4(0.0, 0.0, 0.0);
+    for (int j = 0; j < m; ++j) {
+        const V4<R> qb = r[nb[j]], qc = r[nb[j + 1 < m ? j + 1 : 0]];
+        const double4 b = d4(double(qb.x), double(qb.y), double(qb.z));
+        const double4 c = d4(double(qc.x), double(qc.y), double(qc.z));
+        const double4 bxc = cross3(b, c);
+        const double Vt = dot3(a, bxc) / 6.0;
+        const double4 s = a + b + c;
+        const double MQ = qform(Mb, a) + qform(Mb, b) + qform(Mb, c) + qform(Mb, s);
+        const double4 as = a + s;
+        const double4 Mas = d4(Mb[0] * as.x + Mb[1] * as.y + Mb[2] * as.z, Mb[3] * as.x + Mb[4] * as.y + Mb[5] * as.z,
+                               Mb[6] * as.x + Mb[7] * as.y + Mb[8] * as.z);
+        g = g + ((Vb + 0.25 * dot3(Pb, s) + MQ / 20.0) / 6.0) * bxc + Vt * (0.25 * Pb + 0.1 * Mas);
+    }
+    rb[k] = g;
+}
+
+// ---------------------------------------------------------------- vertex order
+// perm[k] = caller index of internal vertex k.
+__global__ void k_adj_perm_in(int nv, const int* __restrict__ perm, const double* __restrict__ user,
+                              double4* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    const int p = perm[k];
+    out[k] = d4(user[3 * p], user[3 * p + 1], user[3 * p + 2]);
+}
+
+__global__ void k_adj_perm_out(int nv, const int* __restrict__ perm, const double4* __restrict__ in,
+                               double* __restrict__ user) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    const int p = perm[k];
+    const double4 v = in[k];
+    user[3 * p] = v.x;
+    user[3 * p + 1] = v.y;
+    user[3 * p + 2] = v.z;
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned nblk(long long n, int bs) { return unsigned((n + bs - 1) / bs); }
+
+#define ADJ_DISPATCH_STORAGE(storage, C, ...)                                \
+    switch (storage) {                                                      \
+        case IBM_LB_F64: { using C = SF64; __VA_ARGS__; break; }            \
+        case IBM_LB_F32: { using C = SF32; __VA_ARGS__; break; }            \
+        case IBM_LB_F16DEV: { using C = SF16; __VA_ARGS__; break; }         \
+        default: { using C = SBF16; __VA_ARGS__; break; }                   \
+    }
+
+hipError_t launch_adj_record(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
+                             int nv, const AdjStep& st, hipStream_t s) {
+    ADJ_DISPATCH_STORAGE(storage, C, {
+        using R = typename C::real;
+        hipLaunchKernelGGL(k_rec_fields<C>, dim3(nblk(g.N, 256)), dim3(256), 0, s, g, lp,
+                           (const typename C::store_t*)d.f[cur], (const R*)d.F, d.mark, d.ctl, nv > 0 ? 1 : 0,
+                           st.rho, st.u, st.F);
+        if (nv > 0)
+            hipLaunchKernelGGL(k_rec_pos<R>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, (const V4<R>*)d.r, st.pos);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_record_iters(const DevPtrs& d, int* slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_rec_iters, dim3(1), dim3(64), 0, s, d.ctl, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_hc(int nv, const int4* fan, const SmoothParams& sp, int iters, const AdjVerts& v,
+                         hipStream_t s) {
+    const unsigned nb = nblk(nv, 256);
+    hipLaunchKernelGGL(k_adj_hc_init, dim3(nb), dim3(256), 0, s, nv, fan, v.rb, v.P, v.PS, v.Ob);
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(k_adj_hc_a, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, sp.gamma, double(sp.sign), v.P,
+                           v.PS, v.Pp, v.PpS, v.Ob, v.Qp);
+        hipLaunchKernelGGL(k_adj_hc_b, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, v.PpS, v.Qp, v.P, v.PS);
+    }
+    hipLaunchKernelGGL(k_adj_hc_end, dim3(nb), dim3(256), 0, s, nv, v.P, v.Ob);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_ib_spread(const Geom& g, int nv, const double4* pos, const AdjVerts& v, double* ubar,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_spread, dim3(nblk(nv, 4)), dim3(256), 0, s, g, nv, pos, v.Ob, ubar);
+    return hipGetLastError();
+}
+
+int adj_lattice_blocks(long long N) { return (int)nblk(N, 256); }
+int adj_vertex_blocks(int nv) { return (int)nblk(nv, 256); }
+
+hipError_t launch_adj_lattice(const Geom& g, const LatticeParams& lp, const double* fbin, double* fbout,
+                              const AdjStep& st, double* ubar, double* Fbar, double* Apart, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_lattice, dim3(nblk(g.N, 256)), dim3(256), 0, s, g, lp, fbin, fbout, st.rho, st.u, st.F,
+                       ubar, Fbar, Apart);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_ib_back(const Geom& g, int nv, const int4* fan, double sigma, const AdjStep& st,
+                              const double* Fbar, const AdjVerts& v, double* spart, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_forces, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, fan, sigma, st.pos, v.phi);
+    hipLaunchKernelGGL(k_adj_interp, dim3(nblk(nv, 4)), dim3(256), 0, s, g, nv, st.pos, v.phi, v.Ob, Fbar, st.u,
+                       v.phib, v.rt);
+    hipLaunchKernelGGL(k_adj_hess, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, fan, sigma, st.pos, v.phib, v.rt, v.rb,
+                       spart);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(int nsteps, int nbl, const double* Apart, int nbv, const double* spart, double* dA,
+                             double* dsigma, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_reduce, dim3(nblk(9ll * nsteps, 256)), dim3(256), 0, s, nsteps, nbl, Apart, nbv, spart,
+                       dA, dsigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_seed(int storage, int nv, const DevPtrs& d, double* coef, double4* rb, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_seed_coef, dim3(1), dim3(64), 0, s, d.obs_out, coef);
+    if (storage == IBM_LB_F64)
+        hipLaunchKernelGGL(k_adj_seed<double>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, d.fan,
+                           (const V4<double>*)d.r, coef, rb);
+    else
+        hipLaunchKernelGGL(k_adj_seed<float>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, d.fan, (const V4<float>*)d.r,
+                           coef, rb);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_perm_in(int nv, const int* perm, const double* user, double4* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_perm_in, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, perm, user, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_perm_out(int nv, const int* perm, const double4* in, double* user, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_perm_out, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, perm, in, user);
+    return hipGetLastError();
+}
+
+}  // namespace ibmlb

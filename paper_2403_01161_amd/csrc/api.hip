@@ -302,6 +302,16 @@ struct ibm_lb {
     size_t ev_used = 0;
     double acc_ms = 0.0;
     int64_t launches = 0;
+    // adjoint buffers (allocated on first use, grown with the segment length)
+    char* adj = nullptr;
+    int adj_cap = 0;             // steps the records hold
+    double* adj_fb[2] = {nullptr, nullptr};
+    double *adj_ubar = nullptr, *adj_Fbar = nullptr, *adj_Apart = nullptr, *adj_spart = nullptr,
+           *adj_coef = nullptr, *adj_rec = nullptr;
+    double4* adj_pos = nullptr;
+    int* adj_iters = nullptr;
+    int* adj_perm = nullptr;
+    AdjVerts adj_v{};
 };
 
 namespace {
@@ -792,6 +802,179 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches) {
     return IBM_LB_OK;
 }
 
+// ---------------------------------------------------------------- adjoint
+namespace {
+
+// Device memory of the adjoint for segments of up to `steps` steps: per-step
+// records (rho, u, F: 7 N doubles; positions: nv double4; iteration count),
+// two adjoint population copies, the adjoint velocity and force fields,
+// per-vertex work arrays and the per-step block partials of dJ/dA, dJ/dsigma.
+int adj_reserve(ibm_lb* h, int steps) {
+    if (h->adj && h->adj_cap >= steps) return IBM_LB_OK;
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    if (h->adj) (void)hipFree(h->adj);
+    h->adj = nullptr;
+    h->adj_cap = 0;
+    const size_t N = (size_t)h->g.N, nv = (size_t)h->nv;
+    const size_t nbl = (size_t)adj_lattice_blocks(h->g.N), nbv = (size_t)adj_vertex_blocks(h->nv);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes > 0 ? bytes : 1);
+        return o;
+    };
+    const size_t o_rec = take(sizeof(double) * 7 * N * steps);
+    const size_t o_pos = take(sizeof(double4) * nv * steps);
+    const size_t o_it = take(sizeof(int) * (size_t)steps);
+    const size_t o_fb0 = take(sizeof(double) * 19 * N);
+    const size_t o_fb1 = take(sizeof(double) * 19 * N);
+    const size_t o_ub = take(sizeof(double) * 3 * N);
+    const size_t o_Fb = take(sizeof(double) * 3 * N);
+    const size_t o_Ap = take(sizeof(double) * 9 * nbl * steps);
+    const size_t o_sp = take(sizeof(double) * (nbv > 0 ? nbv : 1) * steps);
+    const size_t o_coef = take(sizeof(double) * 16);
+    const size_t o_perm = take(sizeof(int) * nv);
+    size_t o_v[10];
+    for (int k = 0; k < 10; ++k) o_v[k] = take(sizeof(double4) * nv);
+    char* b = nullptr;
+    if (hipMalloc((void**)&b, off) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(IBM_LB_ENOMEM, "hipMalloc of the adjoint records failed");
+    }
+    h->adj = b;
+    h->adj_cap = steps;
+    h->adj_rec = (double*)(b + o_rec);
+    h->adj_pos = (double4*)(b + o_pos);
+    h->adj_iters = (int*)(b + o_it);
+    h->adj_fb[0] = (double*)(b + o_fb0);
+    h->adj_fb[1] = (double*)(b + o_fb1);
+    h->adj_ubar = (double*)(b + o_ub);
+    h->adj_Fbar = (double*)(b + o_Fb);
+    h->adj_Apart = (double*)(b + o_Ap);
+    h->adj_spart = (double*)(b + o_sp);
+    h->adj_coef = (double*)(b + o_coef);
+    h->adj_perm = (int*)(b + o_perm);
+    double4** vv[10] = {&h->adj_v.rb, &h->adj_v.P,   &h->adj_v.PS,  &h->adj_v.Pp,   &h->adj_v.PpS,
+                        &h->adj_v.Ob, &h->adj_v.Qp,  &h->adj_v.phi, &h->adj_v.phib, &h->adj_v.rt};
+    for (int k = 0; k < 10; ++k) *vv[k] = (double4*)(b + o_v[k]);
+    if (nv > 0)
+        HIP_TRY(hipMemcpy(h->adj_perm, h->perm.data(), sizeof(int) * nv, hipMemcpyHostToDevice), "perm upload");
+    return IBM_LB_OK;
+}
+
+AdjStep adj_step(ibm_lb* h, int j) {
+    const size_t N = (size_t)h->g.N;
+    double* base = h->adj_rec + 7 * N * (size_t)j;
+    return AdjStep{base, base + N, base + 4 * N, h->adj_pos + (size_t)h->nv * j};
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar) {
+    if (!h || !value || !rbar) return fail(IBM_LB_EINVAL, "bad objective_grad arguments");
+    if (h->nv == 0) return fail(IBM_LB_EINVAL, "the objective needs a mesh");
+    if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
+    int rc = set_device(h);
+    if (rc) return rc;
+    rc = adj_reserve(h, std::max(h->adj_cap, 1));
+    if (rc) return rc;
+    HIP_TRY(launch_observables(h->storage, h->g, h->lp, h->d, h->cur, h->nv, h->nt, h->cfg.radius,
+                               h->d.Abuf + 9ll * ACAP, h->stream),
+            "observables launch");
+    double o[OBS_OUT_N];
+    HIP_TRY(hipMemcpyAsync(o, h->d.obs_out, sizeof(o), hipMemcpyDeviceToHost, h->stream), "observables copy");
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    const double tie = 1e-12 * h->cfg.radius * h->cfg.radius;
+    if (!(o[13] - o[14] >= tie) || !(o[14] - o[15] >= tie))
+        return fail(IBM_LB_EINVAL, "repeated eigenvalue of S: the deformation D has no derivative here");
+    *value = o[25];
+    HIP_TRY(launch_adj_seed(h->storage, h->nv, h->d, h->adj_coef, h->adj_v.rb, h->stream), "seed launch");
+    HIP_TRY(launch_adj_perm_out(h->nv, h->adj_perm, h->adj_v.rb, rbar, h->stream), "seed permute");
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    return IBM_LB_OK;
+}
+
+int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const double* A, int32_t nsteps,
+                           int32_t A_on_device, const double* fbar_end, const double* rbar_end, double* fbar_begin,
+                           double* rbar_begin, double* dA, double* dsigma) {
+    if (!h || !ckpt || !A || nsteps < 1 || !dA || !dsigma)
+        return fail(IBM_LB_EINVAL, "bad adjoint_segment arguments");
+    if (h->nv > 0 && (!rbar_end || !rbar_begin))
+        return fail(IBM_LB_EINVAL, "rbar_end and rbar_begin are required with a mesh");
+    int rc = set_device(h);
+    if (rc) return rc;
+    rc = ibm_lb_load(h, ckpt, ckpt_bytes);
+    if (rc) return rc;
+    rc = adj_reserve(h, nsteps);
+    if (rc) return rc;
+    const long long N = h->g.N;
+    const int nv = h->nv;
+    hipStream_t s = h->stream;
+    // 1. recompute the segment, recording what the transposed step needs
+    for (int done = 0; done < nsteps;) {
+        const int n = A_on_device ? nsteps : std::min(nsteps - done, ACAP);
+        const double* rows = A + 9ll * done;
+        if (!A_on_device) {
+            rc = upload_rows(h, rows, n);
+            if (rc) return rc;
+            rows = h->d.Abuf;
+        }
+        for (int j = 0; j < n; ++j) {
+            rc = ensure_force(h);
+            if (rc) return rc;
+            HIP_TRY(launch_adj_record(h->storage, h->g, h->lp, h->d, h->cur, nv, adj_step(h, done + j), s),
+                    "record launch");
+            rc = enqueue_steps(h, rows + 9ll * j, 1, 1);
+            if (rc) return rc;
+            HIP_TRY(launch_adj_record_iters(h->d, h->adj_iters + done + j, s), "record iterations");
+        }
+        done += n;
+    }
+    std::vector<int> iters(nsteps);
+    HIP_TRY(hipMemcpyAsync(iters.data(), h->adj_iters, sizeof(int) * nsteps, hipMemcpyDeviceToHost, s),
+            "read iteration counts");
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    // 2. adjoint state at the segment end
+    int c = 0;
+    if (fbar_end)
+        HIP_TRY(hipMemcpyAsync(h->adj_fb[0], fbar_end, sizeof(double) * 19 * N, hipMemcpyDeviceToDevice, s),
+                "fbar_end copy");
+    else
+        HIP_TRY(hipMemsetAsync(h->adj_fb[0], 0, sizeof(double) * 19 * N, s), "fbar zero");
+    HIP_TRY(hipMemsetAsync(h->adj_ubar, 0, sizeof(double) * 3 * N, s), "ubar zero");
+    if (nv > 0) HIP_TRY(launch_adj_perm_in(nv, h->adj_perm, rbar_end, h->adj_v.rb, s), "rbar_end permute");
+    // 3. backward sweep
+    const int nbl = adj_lattice_blocks(N), nbv = nv > 0 ? adj_vertex_blocks(nv) : 0;
+    for (int j = nsteps - 1; j >= 0; --j) {
+        const AdjStep st = adj_step(h, j);
+        if (nv > 0) {
+            HIP_TRY(launch_adj_hc(nv, h->d.fan, h->sp, h->sp.max_iter > 0 ? iters[j] : 0, h->adj_v, s),
+                    "HC transpose");
+            HIP_TRY(launch_adj_ib_spread(h->g, nv, st.pos, h->adj_v, h->adj_ubar, s), "interp transpose");
+        }
+        HIP_TRY(launch_adj_lattice(h->g, h->lp, h->adj_fb[c], h->adj_fb[c ^ 1], st, h->adj_ubar, h->adj_Fbar,
+                                   h->adj_Apart + 9ll * nbl * j, s),
+                "lattice adjoint");
+        if (nv > 0)
+            HIP_TRY(launch_adj_ib_back(h->g, nv, h->d.fan, h->cfg.sigma, st, h->adj_Fbar, h->adj_v,
+                                       h->adj_spart + (long long)nbv * j, s),
+                    "vertex adjoint");
+        c ^= 1;
+    }
+    HIP_TRY(launch_adj_reduce(nsteps, nbl, h->adj_Apart, nbv, h->adj_spart, dA, dsigma, s), "adjoint reduce");
+    if (fbar_begin)
+        HIP_TRY(hipMemcpyAsync(fbar_begin, h->adj_fb[c], sizeof(double) * 19 * N, hipMemcpyDeviceToDevice, s),
+                "fbar_begin copy");
+    if (nv > 0) HIP_TRY(launch_adj_perm_out(nv, h->adj_perm, h->adj_v.rb, rbar_begin, s), "rbar_begin permute");
+    return IBM_LB_OK;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------- ensembles
 struct ibm_lb_batch {
     std::vector<ibm_lb*> m;
@@ -1030,6 +1213,7 @@ void ibm_lb_destroy(ibm_lb* h) {
     if (h->stage_done) (void)hipEventDestroy(h->stage_done);
     if (h->stage) (void)hipHostFree(h->stage);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    if (h->adj) (void)hipFree(h->adj);
     delete h;
 }
 

@@ -44,6 +44,30 @@ __device__ inline int wrap_any(int j, int L) {
     return m < 0 ? m + L : m;
 }
 
+// Node index of unwrapped lattice coordinates (periodic images folded in).
+__device__ inline long long node_index(const Geom& g, int x, int y, int z) {
+    return wrap_any(x, g.Lx) + (long long)g.Lx * (wrap_any(y, g.Ly) + (long long)g.Ly * wrap_any(z, g.Lz));
+}
+
+constexpr int MAXV = 15;  // valence capacity of a fan
+
+// ---------------------------------------------------------------- topology
+// Valence and neighbours of vertex k (unused slots are -1).
+__device__ inline int load_fan(const int4* fan, int k, int nb[MAXV]) {
+    const int4 a = fan[4 * k], b = fan[4 * k + 1];
+    nb[0] = a.y; nb[1] = a.z; nb[2] = a.w;
+    nb[3] = b.x; nb[4] = b.y; nb[5] = b.z; nb[6] = b.w;
+    if (a.x > 7) {
+        const int4 c = fan[4 * k + 2], d = fan[4 * k + 3];
+        nb[7] = c.x; nb[8] = c.y; nb[9] = c.z; nb[10] = c.w;
+        nb[11] = d.x; nb[12] = d.y; nb[13] = d.z; nb[14] = d.w;
+    } else {
+#pragma unroll
+        for (int j = 7; j < MAXV; ++j) nb[j] = -1;
+    }
+    return a.x;
+}
+
 template <class T>
 __device__ inline T wave_sum(T v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -30,7 +30,6 @@
 namespace ibmlb {
 
 constexpr int PATCH = 256;
-constexpr int MAXV = 15;        // valence capacity of a fan
 
 template <class R>
 struct IbArgs {
@@ -52,23 +51,6 @@ struct IbArgs {
     unsigned long long* red;  // grid-wide max of |p - q| (bit pattern of a non-negative real)
     int wcap;              // LDS window capacity in nodes
 };
-
-// ---------------------------------------------------------------- topology
-// Valence and neighbours of vertex k (unused slots are -1).
-__device__ inline int load_fan(const int4* fan, int k, int nb[MAXV]) {
-    const int4 a = fan[4 * k], b = fan[4 * k + 1];
-    nb[0] = a.y; nb[1] = a.z; nb[2] = a.w;
-    nb[3] = b.x; nb[4] = b.y; nb[5] = b.z; nb[6] = b.w;
-    if (a.x > 7) {
-        const int4 c = fan[4 * k + 2], d = fan[4 * k + 3];
-        nb[7] = c.x; nb[8] = c.y; nb[9] = c.z; nb[10] = c.w;
-        nb[11] = d.x; nb[12] = d.y; nb[13] = d.z; nb[14] = d.w;
-    } else {
-#pragma unroll
-        for (int j = 7; j < MAXV; ++j) nb[j] = -1;
-    }
-    return a.x;
-}
 
 // ---------------------------------------------------------------- forces
 // Surface-tension force of vertex k at positions P: Eq. (pi_drop) read as
@@ -196,10 +178,6 @@ __device__ inline Win block_window(bool active, const int f[3], int wcap) {
     w.fits = any && vol <= wcap;
     w.vol = w.fits ? int(vol) : 0;
     return w;
-}
-
-__device__ inline long long node_index(const Geom& g, int x, int y, int z) {
-    return wrap_any(x, g.Lx) + (long long)g.Lx * (wrap_any(y, g.Ly) + (long long)g.Ly * wrap_any(z, g.Lz));
 }
 
 // ---------------------------------------------------------------- forces + spreading

@@ -149,4 +149,46 @@ hipError_t launch_clear_force(int storage, const Geom& g, const DevPtrs& d, hipS
 size_t storage_bytes(int storage);
 size_t real_bytes(int storage);
 
+// ---------------------------------------------------------------- adjoint (adjoint.hip)
+// Forward quantities of one step recorded for the adjoint (FP64).
+struct AdjStep {
+    double* rho;             // [N]
+    double* u;               // [3][N], with F/2
+    double* F;               // [3][N]
+    double4* pos;            // [nv] positions at the start of the step (relative to x_c)
+};
+
+// Per-vertex adjoint work arrays (FP64, [nv] each).
+struct AdjVerts {
+    double4* rb;             // adjoint of the positions (current step boundary)
+    double4* P;              // HC transpose: incoming adjoint of the iterate
+    double4* PS;             // P / valence
+    double4* Pp;             // adjoint of p'
+    double4* PpS;            // Pp / valence
+    double4* Ob;             // adjoint of o (= of U)
+    double4* Qp;             // partial adjoint of q
+    double4* phi;            // recomputed nodal forces
+    double4* phib;           // adjoint of the nodal forces
+    double4* rt;             // adjoint of the positions before the force term
+};
+
+hipError_t launch_adj_record(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
+                             int nv, const AdjStep& st, hipStream_t s);
+hipError_t launch_adj_record_iters(const DevPtrs& d, int* slot, hipStream_t s);
+hipError_t launch_adj_hc(int nv, const int4* fan, const SmoothParams& sp, int iters, const AdjVerts& v,
+                         hipStream_t s);
+hipError_t launch_adj_ib_spread(const Geom& g, int nv, const double4* pos, const AdjVerts& v, double* ubar,
+                                hipStream_t s);
+int adj_lattice_blocks(long long N);
+int adj_vertex_blocks(int nv);
+hipError_t launch_adj_lattice(const Geom& g, const LatticeParams& lp, const double* fbin, double* fbout,
+                              const AdjStep& st, double* ubar, double* Fbar, double* Apart, hipStream_t s);
+hipError_t launch_adj_ib_back(const Geom& g, int nv, const int4* fan, double sigma, const AdjStep& st,
+                              const double* Fbar, const AdjVerts& v, double* spart, hipStream_t s);
+hipError_t launch_adj_reduce(int nsteps, int nbl, const double* Apart, int nbv, const double* spart, double* dA,
+                             double* dsigma, hipStream_t s);
+hipError_t launch_adj_seed(int storage, int nv, const DevPtrs& d, double* coef, double4* rb, hipStream_t s);
+hipError_t launch_adj_perm_in(int nv, const int* perm, const double* user, double4* out, hipStream_t s);
+hipError_t launch_adj_perm_out(int nv, const int* perm, const double4* in, double* user, hipStream_t s);
+
 }  // namespace ibmlb

@@ -10,50 +10,10 @@
 // the current step; vertex data are AoS V4 records relative to the box centre.
 #include <math.h>
 
-#include "device_common.h"
+#include "lattice_common.h"
 
 namespace ibmlb {
 
-// ---------------------------------------------------------------- D3Q19
-// Index 0 is the rest population; 2p-1 and 2p (p = 1..9) are opposite.
-constexpr int Q = 19;
-constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-
-__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-template <class R>
-__host__ __device__ constexpr R wgt(int i) {
-    return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
-}
-
-// ---------------------------------------------------------------- storage
-struct SF64 { using store_t = double; using real = double; };
-struct SF32 { using store_t = float; using real = float; };
-struct SF16 { using store_t = _Float16; using real = float; };
-struct SBF16 { using store_t = uint16_t; using real = float; };
-
-__device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
-__device__ inline uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                                          // round to nearest even
-    return uint16_t(u >> 16);
-}
-
-template <class C> __device__ inline typename C::real dec(typename C::store_t v, float inv);
-template <> __device__ inline double dec<SF64>(double v, float) { return v; }
-template <> __device__ inline float dec<SF32>(float v, float) { return v; }
-template <> __device__ inline float dec<SF16>(_Float16 v, float inv) { return float(v) * inv; }
-template <> __device__ inline float dec<SBF16>(uint16_t v, float) { return bf16_to_f32(v); }
-
-template <class C> __device__ inline typename C::store_t enc(typename C::real v, float sc);
-template <> __device__ inline double enc<SF64>(double v, float) { return v; }
-template <> __device__ inline float enc<SF32>(float v, float) { return v; }
-template <> __device__ inline _Float16 enc<SF16>(float v, float sc) { return _Float16(v * sc); }
-template <> __device__ inline uint16_t enc<SBF16>(float v, float) { return f32_to_bf16(v); }
-
-// ---------------------------------------------------------------- helpers
 // ---------------------------------------------------------------- initial state
 template <class C>
 __global__ __launch_bounds__(256) void k_init(Geom g, LatticeParams lp, typename C::store_t* f,

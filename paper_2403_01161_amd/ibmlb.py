@@ -57,7 +57,8 @@ EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_t
            "ibm_lb_state_bytes", "ibm_lb_save", "ibm_lb_load", "ibm_lb_autotune", "ibm_lb_timing_enable",
            "ibm_lb_timing_read", "ibm_lb_destroy", "ibm_lb_strerror", "ibm_lb_last_error",
            "ibm_lb_batch_init", "ibm_lb_batch_step", "ibm_lb_batch_observables", "ibm_lb_batch_member",
-           "ibm_lb_batch_autotune", "ibm_lb_batch_destroy"]
+           "ibm_lb_batch_autotune", "ibm_lb_batch_destroy", "ibm_lb_objective_grad",
+           "ibm_lb_adjoint_segment"]
 
 
 def lib():
@@ -91,6 +92,8 @@ def lib():
         L.ibm_lb_batch_autotune.argtypes = [vp, i32, C.POINTER(C.c_int32)]
         L.ibm_lb_batch_destroy.argtypes = [vp]
         L.ibm_lb_batch_destroy.restype = None
+        L.ibm_lb_objective_grad.argtypes = [vp, dp, vp]
+        L.ibm_lb_adjoint_segment.argtypes = [vp, vp, C.c_size_t, vp, i32, i32, vp, vp, vp, vp, vp, vp]
         L.ibm_lb_strerror.argtypes = [C.c_int]
         L.ibm_lb_strerror.restype = C.c_char_p
         L.ibm_lb_last_error.restype = C.c_char_p
@@ -251,6 +254,46 @@ class Simulation:
         _check(lib().ibm_lb_timing_read(self._h, C.byref(ms), C.byref(n)), "ibm_lb_timing_read")
         return ms.value, n.value
 
+    # ---- adjoint
+    def objective_grad(self):
+        """D of the current mesh and dD/dr as a float64 CUDA tensor [nv, 3] (caller vertex order)."""
+        rbar = torch.empty((self.nv, 3), dtype=torch.float64, device=self.device)
+        v = C.c_double()
+        _check(lib().ibm_lb_objective_grad(self._h, C.byref(v), rbar.data_ptr()), "ibm_lb_objective_grad")
+        return v.value, rbar
+
+    def adjoint_segment(self, ckpt, A, fbar_end, rbar_end, fbar_begin=None, rbar_begin=None, dA=None,
+                        dsigma=None):
+        """Reverse one segment that starts at checkpoint `ckpt` (a tensor written by save) and runs
+        the gradient rows A (float64 CUDA tensor [n, 9] or host array). fbar_end: float64 CUDA
+        tensor [19 N] or None (zero); rbar_end: float64 CUDA tensor [nv, 3]. Returns
+        (fbar_begin, rbar_begin, dA [n, 9], dsigma [1]); dsigma is accumulated into."""
+        dev = self.device
+        if isinstance(A, torch.Tensor) and A.is_cuda:
+            A = A.contiguous()
+            assert A.dtype == torch.float64
+            n, a_ptr, on_dev = A.numel() // 9, A.data_ptr(), 1
+        else:
+            A = np.ascontiguousarray(A, dtype=np.float64).reshape(-1, 9)
+            n, a_ptr, on_dev = len(A), A.ctypes.data, 0
+        if fbar_begin is None:
+            fbar_begin = torch.empty(19 * self.N, dtype=torch.float64, device=dev)
+        if rbar_begin is None:
+            rbar_begin = torch.empty((self.nv, 3), dtype=torch.float64, device=dev)
+        if dA is None:
+            dA = torch.empty((n, 9), dtype=torch.float64, device=dev)
+        if dsigma is None:
+            dsigma = torch.zeros(1, dtype=torch.float64, device=dev)
+        for t in (fbar_begin, rbar_begin, dA, dsigma) + ((fbar_end,) if fbar_end is not None else ()) + (rbar_end,):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        assert dA.numel() == 9 * n and fbar_begin.numel() == 19 * self.N and rbar_end.numel() == 3 * self.nv
+        _check(lib().ibm_lb_adjoint_segment(self._h, ckpt.data_ptr(), ckpt.numel(), a_ptr, n, on_dev,
+                                            None if fbar_end is None else fbar_end.data_ptr(),
+                                            rbar_end.data_ptr(), fbar_begin.data_ptr(), rbar_begin.data_ptr(),
+                                            dA.data_ptr(), dsigma.data_ptr()),
+               "ibm_lb_adjoint_segment")
+        return fbar_begin, rbar_begin, dA, dsigma
+
 
 class _Member:
     """Read access to one ensemble member (the ensemble owns the handle)."""
@@ -327,3 +370,58 @@ class Ensemble:
         L, nv = self._shapes[i]
         return _Member(self, h, L, nv)
 
+
+
+class DeformationFunction(torch.autograd.Function):
+    """J = D(r^T): the deformation of a droplet started from a fresh initial
+    state and driven by the gradient rows A[n, 9], differentiable with
+    respect to sigma, A and the initial vertex positions.
+
+    Forward: run the HIP timestep, saving a checkpoint every K steps.
+    Backward: for each segment, last first, reload its checkpoint, recompute
+    it and sweep the discrete adjoint (ibm_lb_adjoint_segment), chaining the
+    adjoint state (fbar, rbar) from segment to segment. The smoothing
+    iteration counts are those the forward took."""
+
+    @staticmethod
+    def forward(ctx, sigma, A, vertices, spec, K):
+        spec = dict(spec)
+        sim = Simulation(sigma=float(sigma), vertices=vertices.detach().cpu().numpy(), **spec)
+        ctx.adev = A.device
+        A = A.detach().to(device=sim.device, dtype=torch.float64).contiguous()
+        n = A.shape[0]
+        ckpts = []
+        for s0 in range(0, n, K):
+            ckpts.append(sim.save())
+            sim.step_table(A[s0:s0 + K])
+        D, rbar = sim.objective_grad()
+        ctx.sim, ctx.ckpts, ctx.K, ctx.rbar, ctx.A = sim, ckpts, K, rbar, A
+        ctx.sigma_shape, ctx.sdev, ctx.vdev = sigma.shape, sigma.device, vertices.device
+        return torch.tensor(D, dtype=torch.float64, device=sim.device)
+
+    @staticmethod
+    def backward(ctx, gD):
+        sim, A, K = ctx.sim, ctx.A, ctx.K
+        n = A.shape[0]
+        rbar = (ctx.rbar * gD).contiguous()
+        rnext = torch.empty_like(rbar)
+        fbar = None
+        fbuf = torch.empty(19 * sim.N, dtype=torch.float64, device=sim.device)
+        dA = torch.empty_like(A)
+        dsig = torch.zeros(1, dtype=torch.float64, device=sim.device)
+        for idx in reversed(range(len(ctx.ckpts))):
+            s0, s1 = idx * K, min(n, idx * K + K)
+            sim.adjoint_segment(ctx.ckpts[idx], A[s0:s1], fbar, rbar, fbuf, rnext, dA[s0:s1], dsig)
+            fbar = fbuf
+            rbar, rnext = rnext, rbar
+        return (dsig.reshape(ctx.sigma_shape).to(ctx.sdev), dA.to(ctx.adev), rbar.to(ctx.vdev), None, None)
+
+
+def deformation(sigma, A, vertices, K=50, **spec):
+    """Differentiable droplet deformation D(r^T); spec holds the Simulation
+    keywords other than sigma and vertices (L, tau, radius, triangles, ...)."""
+    if not isinstance(sigma, torch.Tensor):
+        sigma = torch.tensor(float(sigma), dtype=torch.float64)
+    if not isinstance(vertices, torch.Tensor):
+        vertices = torch.as_tensor(np.asarray(vertices, dtype=np.float64))
+    return DeformationFunction.apply(sigma, A, vertices, spec, int(K))
