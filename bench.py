@@ -155,6 +155,140 @@ def cpu_baseline(w, table, steps):
                       f"({dt:.1f} s), OpenMP over z-planes for the lattice, serial IB"}
 
 
+def adjoint_workload():
+    """64^3 box, tau 1, R 8 on a level-4 icosphere (2562 vertices); simple shear
+    at Ca 0.1 (gamma 5.8e-4, sigma = mu R gamma / Ca) plus a seeded OU
+    perturbation of rms 0.1 gamma and correlation time 100 steps (seed 5);
+    500 steps, checkpoints every 50."""
+    from paper_2403_01161_amd.inputs import box_center, icosphere, ou_gradient_table
+    L = (64, 64, 64)
+    R, tau, gamma, Ca = 8.0, 1.0, 5.80e-4, 0.1
+    nu = (tau - 0.5) / 3.0
+    V, T = icosphere(4, R, box_center(L))
+    A = ou_gradient_table(500, 100.0, 0.1 * gamma, seed=5)
+    A[:, 1] += gamma
+    return dict(L=L, R=R, tau=tau, sigma=nu * R * gamma / Ca, V=V, T=T, A=A, K=50)
+
+
+def adjoint_bench(dev):
+    """Forward (with a checkpoint every K steps) and backward (recompute + adjoint
+    sweep of every segment) of J = D(r^T), timed separately after one untimed
+    pass; FP32 populations. The FP64-forward gradient is reported beside it."""
+    import numpy as np
+    import torch
+    from paper_2403_01161_amd import ibmlb
+    w = adjoint_workload()
+    A = torch.from_numpy(w["A"]).to(dev)
+    n, K = A.shape[0], w["K"]
+
+    def run(storage, timed):
+        sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage=storage,
+                               A0=w["A"][0], device=dev)
+        sim.autotune(5)
+        ck = [torch.empty(sim.state_bytes(), dtype=torch.uint8, device=dev) for _ in range(0, n, K)]
+        fbuf = torch.empty(19 * sim.N, dtype=torch.float64, device=dev)
+        rnext = torch.empty((sim.nv, 3), dtype=torch.float64, device=dev)
+        dA = torch.empty((n, 9), dtype=torch.float64, device=dev)
+        dsig = torch.zeros(1, dtype=torch.float64, device=dev)
+        times = []
+        for rep in range(2 if timed else 1):
+            st0 = sim.save()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i, s0 in enumerate(range(0, n, K)):
+                sim.save(ck[i])
+                sim.step_table(A[s0:s0 + K])
+            D, rbar = sim.objective_grad()
+            t1 = time.perf_counter()
+            dsig.zero_()
+            fbar = None
+            for i in reversed(range(len(ck))):
+                s0 = i * K
+                sim.adjoint_segment(ck[i], A[s0:s0 + K], fbar, rbar, fbuf, rnext, dA[s0:s0 + K], dsig)
+                fbar = fbuf
+                rbar, rnext = rnext, rbar
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            times.append((t1 - t0, t2 - t1))
+            sim.load(st0)
+        out = (D, float(dsig[0]), dA.cpu().numpy(), times[-1])
+        sim.close()
+        return out
+
+    D32, s32, a32, (tf, tb) = run("f32", True)
+    D64, s64, a64, _ = run("f64", False)
+    return {"workload": "64^3 box, tau 1, R 8, 2562-vertex icosphere, shear Ca 0.1 + OU perturbation, "
+                        "500 steps, checkpoints every 50, f32 populations, FP64 adjoint",
+            "objective": "D(r^T)", "D": round(D32, 8), "forward_ms": round(tf * 1e3, 2),
+            "backward_ms": round(tb * 1e3, 2), "backward_over_forward": round(tb / tf, 3),
+            "dD_dsigma": s32, "f32_vs_f64_forward": {
+                "dD_dsigma_rel": abs(s32 - s64) / abs(s64),
+                "dD_dA_rel": float(np.linalg.norm(a32 - a64) / np.linalg.norm(a64))}}
+
+
+def precision_workload():
+    """256^3 box, tau 0.8, R 32 on a level-6 icosphere (40962 vertices), OU
+    traceless A(t) with rms Ca 0.15 at R/eta = 0.472, correlation 2000 steps,
+    seed 4."""
+    from paper_2403_01161_amd.inputs import box_center, icosphere
+    L = (256, 256, 256)
+    R, tau, Ca = 32.0, 0.8, 0.15
+    nu = (tau - 0.5) / 3.0
+    G = (0.472 ** 2) * nu / R ** 2
+    V, T = icosphere(6, R, box_center(L))
+    return dict(L=L, R=R, tau=tau, G=G, sigma=nu * R * G / Ca, V=V, T=T, corr=2000.0, seed=4)
+
+
+def precision_bench(dev, steps, every=500):
+    """Every population storage format on the same 256^3 run: throughput, the
+    lattice kernel's roofline fraction, D and theta along the run and the
+    final velocity field, each against the FP64-storage run."""
+    import numpy as np
+    import torch
+    from paper_2403_01161_amd import ibmlb
+    from paper_2403_01161_amd.inputs import ou_gradient_table
+    w = precision_workload()
+    table = ou_gradient_table(steps, w["corr"], w["G"], seed=w["seed"])
+    dtab = torch.from_numpy(table).to(dev)
+    nodes = int(np.prod(w["L"]))
+    res, ref = {}, None
+    for storage, sb in (("f64", 8), ("f32", 4), ("f16dev", 2), ("bf16dev", 2)):
+        sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage=storage,
+                               A0=table[0], device=dev)
+        variant = sim.autotune(10)
+        sim.timing(True)
+        Ds, th = [], []
+        torch.cuda.synchronize()
+        t_run = 0.0
+        for s0 in range(0, steps, every):
+            t0 = time.perf_counter()
+            sim.step_table(dtab[s0:s0 + every])
+            torch.cuda.synchronize()
+            t_run += time.perf_counter() - t0
+            o = sim.observables()
+            Ds.append(o["D"])
+            th.append(o["theta_deg"])
+        lat_ms, launches = sim.timing_read()
+        _, u = sim.fields()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        r = {"mlups": round(nodes * steps / t_run / 1e6, 1),
+             "lattice_frac": round(2 * 19 * sb * nodes / (lat_ms / 1e3 / launches) / 1e9 / HBM_PEAK_GBS, 4),
+             "lattice_variant": variant, "D_final": Ds[-1], "theta_final_deg": th[-1]}
+        if ref is None:
+            ref = (np.array(Ds), np.array(th), u)
+        else:
+            Dr, thr, ur = ref
+            r["D_rel_err_max"] = float(np.max(np.abs(np.array(Ds) - Dr) / np.abs(Dr)))
+            r["theta_err_max_deg"] = float(np.max(np.abs(np.array(th) - thr)))
+            r["u_err_rel"] = float(np.abs(u - ur).max() / np.abs(ur).max())
+        res[storage] = r
+        print(json.dumps({"precision_format_done": storage, **r}), flush=True)
+    return {"workload": "256^3 moving-wall box, tau 0.8, R 32, 40962-vertex icosphere, OU A(t) rms Ca 0.15",
+            "steps": steps, "sample_every": every, "formats": res}
+
+
 def counters_sequence(dev, storage):
     """Kernels whose HBM counters are read: a plain 256 MiB copy whose source
     was first pushed out of the 256 MB last-level cache by a 1 GiB fill (three
@@ -191,6 +325,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=300)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--precision", type=int, default=0, metavar="STEPS",
+                    help="run only the storage-precision study (256^3, every format) for STEPS steps")
     ap.add_argument("--counters", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 3 device copies of "
                          "256 MiB (calibration) and 20 steps of the single-droplet workload")
@@ -208,6 +345,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.counters:
         counters_sequence(dev, args.storage)
+        return
+    if args.precision:
+        print(json.dumps({"precision": precision_bench(dev, args.precision)}), flush=True)
         return
     w = workload(args.storage)
     K, W = args.steps, args.warmup
@@ -282,6 +422,8 @@ def main():
     torch.cuda.empty_cache()
     if args.ensemble_steps > 0:
         line["ensemble"] = ensemble_bench(args.ensemble_steps)
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_bench(dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, table, args.cpu_steps)
     else:
