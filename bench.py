@@ -258,6 +258,7 @@ def precision_bench(dev, steps, every=500):
         variant = sim.autotune(10)
         sim.timing(True)
         Ds, th = [], []
+        mass0 = sim.observables()["mass"]
         torch.cuda.synchronize()
         t_run = 0.0
         for s0 in range(0, steps, every):
@@ -268,6 +269,7 @@ def precision_bench(dev, steps, every=500):
             o = sim.observables()
             Ds.append(o["D"])
             th.append(o["theta_deg"])
+        mass_drift = (o["mass"] - mass0) / mass0
         lat_ms, launches = sim.timing_read()
         _, u = sim.fields()
         sim.close()
@@ -275,7 +277,8 @@ def precision_bench(dev, steps, every=500):
         torch.cuda.empty_cache()
         r = {"mlups": round(nodes * steps / t_run / 1e6, 1),
              "lattice_frac": round(2 * 19 * sb * nodes / (lat_ms / 1e3 / launches) / 1e9 / HBM_PEAK_GBS, 4),
-             "lattice_variant": variant, "D_final": Ds[-1], "theta_final_deg": th[-1]}
+             "lattice_variant": variant, "D_final": Ds[-1], "theta_final_deg": th[-1],
+             "mass_rel_drift": mass_drift}
         if ref is None:
             ref = (np.array(Ds), np.array(th), u)
         else:
