@@ -412,7 +412,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
                      "variant": {"nontemporal_loads": bool(variant & 1),
-                                 "block": 512 if variant & 2 else 256}},
+                                 "block": (128, 256, 512, 64)[(variant >> 1) & 3]}},
         "vertex_updates_per_s": round(nv * K / dt, 1),
         "hbm_frac_whole_step": round(alg_bytes * K / dt / 1e9 / HBM_PEAK_GBS, 4),
         "ms_per_step_with_kernel_events": round(dt_ev / K * 1e3, 5),

@@ -165,12 +165,15 @@ size_t ibm_lb_state_bytes(const ibm_lb* h);
 int ibm_lb_save(ibm_lb* h, void* dst, size_t n);
 int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
 
-/* Autotuner: times `reps` launches of each variant of the fused lattice
- * kernel (non-temporal population loads on/off, 256/512-thread work-groups)
- * on this handle's buffers and keeps the fastest for later steps. The state
- * is unchanged (the timed launches write only the spare population copy).
- * Synchronises the stream. *variant (may be NULL) receives the choice.
- * Errors: EINVAL, EDEVICE, sticky. */
+/* Autotuner: picks the variant of the fused lattice kernel (non-temporal
+ * population loads on/off; 64, 128, 256 or 512-thread work-groups) for this
+ * configuration by timing `reps` whole steps with each, in four interleaved
+ * rounds, from a snapshot of the state that is restored afterwards (the
+ * state after the call equals the state before; the force field is spread
+ * again at the next step). Synchronises the stream. *variant (may be NULL)
+ * receives the choice: bit 0 non-temporal loads, bits 1-2 index the
+ * work-group sizes {128, 256, 512, 64}. Errors: EINVAL, ENOMEM, EDEVICE,
+ * sticky. */
 int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);
 
 /* Kernel timing of the fused lattice kernel: when enabled, every step records
@@ -198,7 +201,8 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
  *   error. ibm_lb_batch_member gives member i's handle for synchronising
  *   reads (vertices, fields, observables, save); stepping a member on its
  *   own while it belongs to an ensemble is not supported.
- * ibm_lb_batch_autotune: as ibm_lb_autotune for the batched lattice launch.
+ * ibm_lb_batch_autotune: as ibm_lb_autotune for the batched steps (gradient
+ *   rows of the last upload); every member is restored afterwards.
  * ibm_lb_batch_destroy frees the ensemble and its members. */
 int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb_batch** out);
 int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps);

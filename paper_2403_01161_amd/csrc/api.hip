@@ -38,8 +38,8 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of every device array inside one workspace.
 struct Layout {
-    size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, tris, fan, obs_part, mass_part, obs_out, Abuf,
-        red, total;
+    size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, tris, fan, lfan, hstart, hids, obs_part, mass_part,
+        obs_out, Abuf, red, total;
 };
 
 // Per vertex: valence m and the one-ring neighbours n_0 .. n_{m-1} in
@@ -50,7 +50,7 @@ struct MeshCSR {
     std::vector<int> fan;
 };
 
-Layout make_layout(int storage, long long N, int ntiles, int nv, int nt) {
+Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t nhalo) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -74,6 +74,9 @@ Layout make_layout(int storage, long long N, int ntiles, int nv, int nt) {
     L.bb = take(v4);
     L.tris = take(sizeof(int4) * (size_t)nt);
     L.fan = take(sizeof(int) * FAN * (size_t)nv);
+    L.lfan = take(sizeof(int) * FAN * (size_t)nv);
+    L.hstart = take(sizeof(int) * ((size_t)(nv + IB_PATCH - 1) / IB_PATCH + 1));
+    L.hids = take(sizeof(int) * nhalo);
     L.obs_part = take(sizeof(double) * 16 * OBS_BLOCKS);
     L.mass_part = take(sizeof(double) * 4 * MASS_BLOCKS);
     L.obs_out = take(sizeof(double) * OBS_OUT_N);
@@ -156,11 +159,11 @@ int validate(const ibm_lb_config* c) {
 }
 
 // Recursive bisection of the vertex set along the longest axis of its
-// bounding box, splitting at a multiple of 256 vertices: every run of 256
-// consecutive vertices in the resulting order (one work-group's patch) is
-// spatially compact.
+// bounding box, splitting at a multiple of IB_PATCH vertices: every run of
+// IB_PATCH consecutive vertices in the resulting order (one work-group's
+// patch) is spatially compact.
 void bisect(const double* V, int* idx, int n, std::vector<int>* out) {
-    if (n <= 256) {
+    if (n <= IB_PATCH) {
         out->insert(out->end(), idx, idx + n);
         return;
     }
@@ -173,8 +176,8 @@ void bisect(const double* V, int* idx, int n, std::vector<int>* out) {
     int ax = 0;
     for (int a = 1; a < 3; ++a)
         if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
-    int nl = ((n / 2 + 255) / 256) * 256;
-    if (nl >= n) nl = n - 256;
+    int nl = ((n / 2 + IB_PATCH - 1) / IB_PATCH) * IB_PATCH;
+    if (nl >= n) nl = n - IB_PATCH;
     std::nth_element(idx, idx + nl, idx + n, [&](int p, int q) {
         const double vp = V[3 * p + ax], vq = V[3 * q + ax];
         return vp < vq || (vp == vq && p < q);
@@ -243,16 +246,59 @@ int build_adjacency(int nv, int nt, const int* T, MeshCSR* csr) {
     return IBM_LB_OK;
 }
 
+// Halos of the surface patches: for patch p (internal vertices
+// [IB_PATCH p, IB_PATCH (p+1))), the ring neighbours of its vertices that lie
+// outside it, ascending, in hids[hstart[p] .. hstart[p+1]); and every vertex's
+// fan in patch-local slots: slot j < IB_PATCH is vertex IB_PATCH p + j, slot
+// IB_PATCH + h the h-th halo vertex of the patch.
+struct Halos {
+    std::vector<int> hstart, hids, lfan;
+};
+
+void build_halos(int nv, const MeshCSR& csr, Halos* hl) {
+    const int np = (nv + IB_PATCH - 1) / IB_PATCH;
+    hl->hstart.assign(np + 1, 0);
+    hl->hids.clear();
+    hl->lfan.assign((size_t)FAN * nv, -1);
+    for (int p = 0; p < np; ++p) {
+        const int lo = p * IB_PATCH, hi = std::min(nv, lo + IB_PATCH);
+        std::vector<int> h;
+        for (int k = lo; k < hi; ++k) {
+            const int* f = &csr.fan[(size_t)FAN * k];
+            for (int j = 0; j < f[0]; ++j)
+                if (f[1 + j] < lo || f[1 + j] >= hi) h.push_back(f[1 + j]);
+        }
+        std::sort(h.begin(), h.end());
+        h.erase(std::unique(h.begin(), h.end()), h.end());
+        for (int k = lo; k < hi; ++k) {
+            const int* f = &csr.fan[(size_t)FAN * k];
+            int* g = &hl->lfan[(size_t)FAN * k];
+            g[0] = f[0];
+            for (int j = 0; j < f[0]; ++j) {
+                const int v = f[1 + j];
+                g[1 + j] = (v >= lo && v < hi) ? v - lo
+                                                : IB_PATCH + int(std::lower_bound(h.begin(), h.end(), v) - h.begin());
+            }
+        }
+        hl->hids.insert(hl->hids.end(), h.begin(), h.end());
+        hl->hstart[p + 1] = (int)hl->hids.size();
+    }
+}
+
 struct MeshData {
     std::vector<int> perm, tris;
     MeshCSR csr;
+    Halos halos;
 };
 
 int prepare(const ibm_lb_config* c, MeshData* m) {
     int rc = validate(c);
     if (rc || c->n_vertices == 0) return rc;
     renumber(c, &m->perm, &m->tris);
-    return build_adjacency(c->n_vertices, c->n_triangles, m->tris.data(), &m->csr);
+    rc = build_adjacency(c->n_vertices, c->n_triangles, m->tris.data(), &m->csr);
+    if (rc) return rc;
+    build_halos(c->n_vertices, m->csr, &m->halos);
+    return IBM_LB_OK;
 }
 
 Geom make_geom(const ibm_lb_config* c) {
@@ -294,7 +340,7 @@ struct ibm_lb {
     int sticky = IBM_LB_OK;
     bool f_ready = false;        // F and tile marks hold the spread of the current mesh
     std::vector<int> perm;       // internal vertex k is caller vertex perm[k]
-    int lattice_variant = 0;     // chosen by ibm_lb_autotune
+    int lattice_variant = 1;     // non-temporal loads, 128-thread work-groups until ibm_lb_autotune
     double* stage = nullptr;     // pinned host staging for gradient rows
     hipEvent_t stage_done = nullptr;
     bool timing = false;
@@ -445,7 +491,8 @@ int ibm_lb_workspace_size(const ibm_lb_config* cfg, size_t* bytes) {
     if (rc) return rc;
     if (!bytes) return fail(IBM_LB_EINVAL, "bytes is NULL");
     Geom g = make_geom(cfg);
-    *bytes = make_layout(cfg->storage, g.N, g.TX * g.TY * g.TZ, cfg->n_vertices, cfg->n_triangles).total;
+    *bytes = make_layout(cfg->storage, g.N, g.TX * g.TY * g.TZ, cfg->n_vertices, cfg->n_triangles,
+                         m.halos.hids.size()).total;
     return IBM_LB_OK;
 }
 
@@ -485,7 +532,7 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
     const int ntiles = h->g.TX * h->g.TY * h->g.TZ;
-    h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt);
+    h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt, mesh.halos.hids.size());
     if (cfg->workspace) {
         if (cfg->workspace_bytes < h->lay.total)
             return bail(fail(IBM_LB_ENOMEM, "workspace smaller than ibm_lb_workspace_size"));
@@ -523,6 +570,9 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     d.bb = b + L.bb;
     d.tris = (int4*)(b + L.tris);
     d.fan = (int4*)(b + L.fan);
+    d.lfan = (int4*)(b + L.lfan);
+    d.hstart = (int*)(b + L.hstart);
+    d.hids = (int*)(b + L.hids);
     d.obs_part = (double*)(b + L.obs_part);
     d.mass_part = (double*)(b + L.mass_part);
     d.obs_out = (double*)(b + L.obs_out);
@@ -558,6 +608,12 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
             tris[t] = int4{mesh.tris[3 * t], mesh.tris[3 * t + 1], mesh.tris[3 * t + 2], 0};
         INIT_TRY(hipMemcpy(d.tris, tris.data(), sizeof(int4) * h->nt, hipMemcpyHostToDevice), "tris");
         INIT_TRY(hipMemcpy(d.fan, csr.fan.data(), sizeof(int) * csr.fan.size(), hipMemcpyHostToDevice), "fan");
+        const Halos& hl = mesh.halos;
+        INIT_TRY(hipMemcpy(d.lfan, hl.lfan.data(), sizeof(int) * hl.lfan.size(), hipMemcpyHostToDevice), "lfan");
+        INIT_TRY(hipMemcpy(d.hstart, hl.hstart.data(), sizeof(int) * hl.hstart.size(), hipMemcpyHostToDevice),
+                 "hstart");
+        if (!hl.hids.empty())
+            INIT_TRY(hipMemcpy(d.hids, hl.hids.data(), sizeof(int) * hl.hids.size(), hipMemcpyHostToDevice), "hids");
         std::vector<double> vin(3 * (size_t)h->nv);
         for (int k = 0; k < h->nv; ++k)
             for (int a = 0; a < 3; ++a) vin[3 * k + a] = cfg->vertices[3 * mesh.perm[k] + a];
@@ -750,35 +806,60 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
     int rc = set_device(h);
     if (rc) return rc;
-    // The timed launches read the current populations and write the other
-    // copy, which the next step overwrites; the force field is not touched.
-    hipEvent_t a, b;
-    HIP_TRY(hipEventCreate(&a), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&b), "hipEventCreate");
+    // Each variant advances `reps` whole steps (lattice kernel and IB half,
+    // populations alternating between the two copies as in a run) with the
+    // last gradient row; the state is saved first and restored after, so the
+    // call leaves it as it found it.
+    const size_t nb = ibm_lb_state_bytes(h);
+    void* snap = nullptr;
+    if (hipMalloc(&snap, nb) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(IBM_LB_ENOMEM, "autotune snapshot allocation");
+    }
+    rc = ibm_lb_save(h, snap, nb);
+    if (rc) {
+        (void)hipFree(snap);
+        return rc;
+    }
+    const bool timing = h->timing;
+    const int before = h->lattice_variant;
+    h->timing = false;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
     const double* Arow = h->d.Abuf + 9ll * ACAP;
     // interleaved rounds; each variant scores its fastest round
     float best_of[LATTICE_VARIANTS];
     for (int v = 0; v < LATTICE_VARIANTS; ++v) best_of[v] = 1e30f;
-    hipError_t e = hipSuccess;
-    for (int round = 0; round < 4 && e == hipSuccess; ++round)
-        for (int v = 0; v < LATTICE_VARIANTS && e == hipSuccess; ++v) {
-            e = launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, false, Arow, v, h->stream);
-            if (e == hipSuccess) e = hipEventRecord(a, h->stream);
-            for (int k = 0; k < reps && e == hipSuccess; ++k)
-                e = launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, false, Arow, v, h->stream);
+    for (int round = 0; round < 4 && e == hipSuccess && rc == IBM_LB_OK; ++round)
+        for (int v = 0; v < LATTICE_VARIANTS && e == hipSuccess && rc == IBM_LB_OK; ++v) {
+            h->lattice_variant = v;
+            rc = enqueue_steps(h, Arow, 1, 0);  // untimed: first launch of this variant in the round
+            if (rc) break;
+            e = hipEventRecord(a, h->stream);
+            if (e == hipSuccess) rc = enqueue_steps(h, Arow, reps, 0);
+            if (rc) break;
             if (e == hipSuccess) e = hipEventRecord(b, h->stream);
             if (e == hipSuccess) e = hipEventSynchronize(b);
             float ms = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
             if (e == hipSuccess) best_of[v] = std::min(best_of[v], ms);
         }
-    int best_v = 0;
-    for (int v = 1; v < LATTICE_VARIANTS; ++v)
-        if (best_of[v] < best_of[best_v]) best_v = v;
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    if (e != hipSuccess) return hip_fail(e, "autotune");
+    int best_v = before;
+    if (e == hipSuccess && rc == IBM_LB_OK) {
+        best_v = 0;
+        for (int v = 1; v < LATTICE_VARIANTS; ++v)
+            if (best_of[v] < best_of[best_v]) best_v = v;
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    h->timing = timing;
     h->lattice_variant = best_v;
+    const int rc_load = ibm_lb_load(h, snap, nb);
+    (void)hipFree(snap);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    if (rc) return rc;
+    if (rc_load) return rc_load;
     if (variant) *variant = best_v;
     return IBM_LB_OK;
 }
@@ -981,8 +1062,8 @@ struct ibm_lb_batch {
     int storage = 0, device = 0, n = 0;
     hipStream_t stream = nullptr;
     LatDesc* lat_desc = nullptr;  // device [n]
-    int* lat_start = nullptr;     // device [2][n + 1]
-    int nblk256 = 0, nblk512 = 0;
+    int* lat_start = nullptr;     // device [4][n + 1]: member block offsets per work-group size
+    int nblk[4] = {0, 0, 0, 0};
     void* ib_args = nullptr;      // device [n] records
     int* patch_start = nullptr;   // device [n + 1]
     int npatch_total = 0;
@@ -993,7 +1074,7 @@ struct ibm_lb_batch {
     int cur = 0;
     int64_t step = 0;
     bool f_ready = false;
-    int variant = 0;
+    int variant = 1;
 };
 
 namespace {
@@ -1029,7 +1110,7 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     auto bail = [&](hipError_t e, const char* where) { return batch_fail_cleanup(b, hip_fail(e, where)); };
     hipError_t e;
     std::vector<LatDesc> ld(n);
-    std::vector<int> st(2 * (n + 1), 0), ps(n + 1, 0);
+    std::vector<int> st(4 * (n + 1), 0), ps(n + 1, 0);
     const size_t rec = ib_args_bytes(b->storage);
     std::vector<char> args(rec * n);
     for (int i = 0; i < n; ++i) {
@@ -1045,13 +1126,12 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
         L.ctl = h->d.ctl;
         L.A = nullptr;  // set below, once the table is allocated
         L.ib = h->nv > 0 ? 1 : 0;
-        st[i + 1] = st[i] + (int)((h->g.N + 255) / 256);
-        st[n + 1 + i + 1] = st[n + 1 + i] + (int)((h->g.N + 511) / 512);
-        ps[i + 1] = ps[i] + (h->nv + 255) / 256;
+        for (int q = 0; q < 4; ++q)
+            st[q * (n + 1) + i + 1] = st[q * (n + 1) + i] + (int)((h->g.N + LAT_BS[q] - 1) / LAT_BS[q]);
+        ps[i + 1] = ps[i] + (h->nv + IB_PATCH - 1) / IB_PATCH;
         fill_ib_args(b->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, args.data() + rec * i);
     }
-    b->nblk256 = st[n];
-    b->nblk512 = st[2 * n + 1];
+    for (int q = 0; q < 4; ++q) b->nblk[q] = st[q * (n + 1) + n];
     b->npatch_total = ps[n];
     const size_t tab = (size_t)n * ACAP * 9;
     if ((e = hipMalloc((void**)&b->Atab, 2 * tab * sizeof(double))) != hipSuccess) return bail(e, "gradient tables");
@@ -1105,7 +1185,7 @@ int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps) {
         HIP_TRY(hipMemcpyAsync(dst, sg, sizeof(double) * tab, hipMemcpyHostToDevice, b->stream), "upload tables");
         HIP_TRY(hipEventRecord(b->stage_done[hf], b->stream), "hipEventRecord");
         for (int j = 0; j < len; ++j) {
-            HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_start, n, b->nblk256, b->nblk512, b->cur,
+            HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_start, n, b->nblk, b->cur,
                                          (long long)hf * tab + 9ll * j, b->variant, b->stream),
                     "lattice batch launch");
             HIP_TRY(launch_ib_step_batch(b->storage, b->ib_args, b->patch_start, n, b->npatch_total, b->stream),
@@ -1147,41 +1227,80 @@ int ibm_lb_batch_member(ibm_lb_batch* b, int32_t i, ibm_lb** out) {
 
 int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant) {
     if (!b || reps < 1) return fail(IBM_LB_EINVAL, "bad batch_autotune arguments");
+    for (ibm_lb* h : b->m)
+        if (h->sticky) return fail(h->sticky, "earlier asynchronous error in a member");
     HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    // Whole batched steps per variant (with the gradient rows already in the
+    // first table half), members saved before and restored after.
+    const int n = b->n;
+    std::vector<size_t> nbytes(n);
+    std::vector<void*> snap(n, nullptr);
+    int rc = IBM_LB_OK;
+    for (int i = 0; i < n && rc == IBM_LB_OK; ++i) {
+        nbytes[i] = ibm_lb_state_bytes(b->m[i]);
+        if (hipMalloc(&snap[i], nbytes[i]) != hipSuccess) {
+            (void)hipGetLastError();
+            snap[i] = nullptr;
+            rc = fail(IBM_LB_ENOMEM, "batch autotune snapshot allocation");
+        } else {
+            rc = ibm_lb_save(b->m[i], snap[i], nbytes[i]);
+        }
+    }
+    const int64_t step0 = b->step;
+    const int before = b->variant;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipSuccess;
+    if (rc == IBM_LB_OK) e = hipEventCreate(&e0);
+    if (rc == IBM_LB_OK && e == hipSuccess) e = hipEventCreate(&e1);
+    if (rc == IBM_LB_OK && e == hipSuccess && !b->f_ready) {
+        e = launch_ib_pre_batch(b->storage, b->ib_args, b->patch_start, n, b->npatch_total, b->stream);
+        b->f_ready = true;
+    }
     float best_of[LATTICE_VARIANTS];
     for (int v = 0; v < LATTICE_VARIANTS; ++v) best_of[v] = 1e30f;
-    hipError_t e = hipSuccess;
-    // the timed launches write only the spare population copies; the force
-    // field is consumed, so it is spread again before the next step
-    for (int round = 0; round < 4 && e == hipSuccess; ++round)
+    auto batch_steps = [&](int v, int k) {
+        hipError_t r = hipSuccess;
+        for (int j = 0; j < k && r == hipSuccess; ++j) {
+            r = launch_lattice_batch(b->storage, b->lat_desc, b->lat_start, n, b->nblk, b->cur, 0, v, b->stream);
+            if (r == hipSuccess)
+                r = launch_ib_step_batch(b->storage, b->ib_args, b->patch_start, n, b->npatch_total, b->stream);
+            b->cur ^= 1;
+        }
+        return r;
+    };
+    for (int round = 0; round < 4 && e == hipSuccess && rc == IBM_LB_OK; ++round)
         for (int v = 0; v < LATTICE_VARIANTS && e == hipSuccess; ++v) {
-            e = hipEventRecord(e0, b->stream);
-            for (int k = 0; k < reps && e == hipSuccess; ++k)
-                e = launch_lattice_batch(b->storage, b->lat_desc, b->lat_start, b->n, b->nblk256, b->nblk512, b->cur,
-                                         0, v, b->stream);
+            e = batch_steps(v, 1);
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            if (e == hipSuccess) e = batch_steps(v, reps);
             if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e == hipSuccess) best_of[v] = std::min(best_of[v], ms);
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return hip_fail(e, "batch autotune");
-    int best_v = 0;
-    for (int v = 1; v < LATTICE_VARIANTS; ++v)
-        if (best_of[v] < best_of[best_v]) best_v = v;
-    b->variant = best_v;
-    // the autotune launches consumed and cleared the force field of the members
-    for (ibm_lb* h : b->m) {
-        HIP_TRY(launch_clear_force(h->storage, h->g, h->d, b->stream), "clear force");
-        HIP_TRY(launch_bump_epoch(h->d, b->stream), "bump epoch");
-        h->f_ready = false;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    int best_v = before;
+    if (e == hipSuccess && rc == IBM_LB_OK) {
+        best_v = 0;
+        for (int v = 1; v < LATTICE_VARIANTS; ++v)
+            if (best_of[v] < best_of[best_v]) best_v = v;
     }
+    b->variant = best_v;
+    // restore every member (each load clears its force field and retires its marks)
+    for (int i = 0; i < n; ++i) {
+        b->m[i]->cur = b->cur;
+        if (snap[i]) {
+            const int r = ibm_lb_load(b->m[i], snap[i], nbytes[i]);
+            if (r && rc == IBM_LB_OK) rc = r;
+            (void)hipFree(snap[i]);
+        }
+    }
+    b->step = step0;
     b->f_ready = false;
+    if (e != hipSuccess) return hip_fail(e, "batch autotune");
+    if (rc) return rc;
     if (variant) *variant = best_v;
     return IBM_LB_OK;
 }

@@ -1,13 +1,16 @@
 // Immersed-boundary half of the timestep, organised by surface patches.
 //
 // At set-up the vertices are renumbered by recursive bisection of their
-// positions so that every run of 256 consecutive vertices is a compact patch
-// of the droplet surface; one work-group owns one patch and one thread one
-// vertex. The lattice window covered by a patch's 4x4x4 stencils is staged
-// in LDS:
-//   * spreading (Sec. 3.1, Eq. ibm_force_d, first line): 16 lanes per vertex
-//     add its 64 contributions into an FP64 LDS window with LDS atomics, and
-//     the window is flushed to F with one global atomic per touched node;
+// positions so that every run of PATCH (64) consecutive vertices is a compact
+// patch of the droplet surface; one work-group (one wave) owns one patch and
+// one lane one vertex. Small patches put the LDS work of the IB kernels on
+// many compute units (a 10k-vertex droplet gives 161 work-groups). The
+// lattice window covered by a patch's 4x4x4 stencils is staged in LDS:
+//   * spreading (Sec. 3.1, Eq. ibm_force_d, first line): each of the four
+//     waves takes every fourth vertex, one lane per stencil node, and adds its
+//     64 contributions into an FP64 LDS window with LDS atomics (distinct
+//     addresses within each instruction); the window is flushed to F with one
+//     global atomic per touched node;
 //   * interpolation (Eq. ibm_force_d, second line): the window of u is loaded
 //     once and each vertex gathers its 64 nodes from LDS.
 // A window beyond the LDS capacity falls back to direct global access.
@@ -19,17 +22,18 @@
 //
 // Kernels of one step, after the fused lattice kernel:
 //   k_interp_patch  interpolation + Euler move (Eq. fwd_euler): o = r + U
-//   k_hc_pass1      first HC pass of iteration 1 (q = o)
-//   k_hc_pass2      correction pass of iteration 1, grid-wide max |p - q|
-//   k_hc_finish     one work-group: nothing if iteration 1 converged, else
-//                   the remaining iterations; advances the step epoch
+//   k_hc_fused      HC iteration 1 per patch (its halo's p' and b staged in
+//                   LDS), grid-wide max |p - q|; the last work-group to finish
+//                   runs the rare further iterations, records the count and
+//                   advances the step epoch
 //   k_fs_patch      next step's surface-tension forces (Eq. pi_drop), tile
 //                   marks and spreading, from the final positions
 #include "device_common.h"
 
 namespace ibmlb {
 
-constexpr int PATCH = 256;
+constexpr int PATCH = IB_PATCH;
+constexpr int IBT = 256;  // threads of a patch work-group: lanes of the first wave own the vertices
 
 template <class R>
 struct IbArgs {
@@ -44,6 +48,9 @@ struct IbArgs {
     V4<R>* pp;
     V4<R>* bb;
     const int4* fan;       // [nv][4]
+    const int4* lfan;      // [nv][4] fan in patch-local slots
+    const int* hstart;     // [npatch + 1]
+    const int* hids;       // halo vertices of each patch
     R* F;                  // [3][N]
     const R* U;            // [3][N]
     int* mark;
@@ -142,7 +149,7 @@ struct Win {
 };
 
 __device__ inline Win block_window(bool active, const int f[3], int wcap) {
-    __shared__ int red[6][PATCH / 64];
+    __shared__ int red[6][IBT / 64];
     const int t = threadIdx.x;
     int mn[3], mx[3];
     for (int d = 0; d < 3; ++d) {
@@ -165,7 +172,7 @@ __device__ inline Win block_window(bool active, const int f[3], int wcap) {
     long long vol = 1;
     for (int d = 0; d < 3; ++d) {
         int lo = red[d][0], hi = red[3 + d][0];
-        for (int k = 1; k < PATCH / 64; ++k) {
+        for (int k = 1; k < IBT / 64; ++k) {
             lo = min(lo, red[d][k]);
             hi = max(hi, red[3 + d][k]);
         }
@@ -192,7 +199,7 @@ struct Stage {
     int ok[PATCH];
 };
 
-constexpr int SPREAD_WCAP = 4096;  // nodes of the FP64 spreading window
+constexpr int SPREAD_WCAP = 2048;  // nodes of the FP64 spreading window
 
 // Accumulate the staged vertices [lo_v, hi_v) into an LDS window and flush
 // each touched node once to F; false if their window exceeds the capacity.
@@ -200,31 +207,42 @@ template <class R>
 __device__ bool spread_window(const IbArgs<R>& a, const Stage<R>& st, double* win, int lo_v, int hi_v) {
     const int t = threadIdx.x;
     const bool in = t >= lo_v && t < hi_v && st.ok[t];
-    const int f[3] = {st.first[t][0], st.first[t][1], st.first[t][2]};
+    const int tv = t < PATCH ? t : 0;
+    const int f[3] = {st.first[tv][0], st.first[tv][1], st.first[tv][2]};
     const Win w = block_window(in, f, SPREAD_WCAP);
     if (!w.fits) return false;
-    const int lane = t & 15, jy = lane & 3, jz = lane >> 2;
+    const int lane = t & 63, jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
     const long long N = a.g.N;
-    for (int i = t; i < 3 * w.vol; i += PATCH) win[i] = 0.0;
+    for (int i = t; i < 3 * w.vol; i += IBT) win[i] = 0.0;
     __syncthreads();
-    for (int v = lo_v + (t >> 4); v < hi_v; v += PATCH / 16) {
-        if (!st.ok[v]) continue;
-        const double wyz = double(st.w[v][1][jy]) * double(st.w[v][2][jz]);
-        const double fx = st.val[v][0], fy = st.val[v][1], fz = st.val[v][2];
-        const int lx = st.first[v][0] - w.o[0];
+    // wave t/64 takes vertices t/64, t/64 + 4, ...: first all their staged data
+    // into registers, then the atomics back to back (LDS operations complete
+    // in order, so interleaving the reads would wait on every atomic)
+    constexpr int VW = PATCH / (IBT / 64);
+    double cx[VW], cy[VW], cz[VW];
+    int cell[VW];
+#pragma unroll
+    for (int j = 0; j < VW; ++j) {
+        const int v = (t >> 6) + j * (IBT / 64);
+        const bool use = v >= lo_v && v < hi_v && st.ok[v];
+        const double wt = use ? double(st.w[v][0][jx]) * double(st.w[v][1][jy]) * double(st.w[v][2][jz]) : 0.0;
+        const int lx = st.first[v][0] + jx - w.o[0];
         const int ly = st.first[v][1] + jy - w.o[1];
         const int lz = st.first[v][2] + jz - w.o[2];
-        const int base = lx + w.e[0] * (ly + w.e[1] * lz);
+        cell[j] = use ? lx + w.e[0] * (ly + w.e[1] * lz) : -1;
+        cx[j] = double(st.val[v][0]) * wt;
+        cy[j] = double(st.val[v][1]) * wt;
+        cz[j] = double(st.val[v][2]) * wt;
+    }
 #pragma unroll
-        for (int jx = 0; jx < 4; ++jx) {
-            const double wt = double(st.w[v][0][jx]) * wyz;
-            atomicAdd(&win[base + jx], fx * wt);
-            atomicAdd(&win[w.vol + base + jx], fy * wt);
-            atomicAdd(&win[2 * w.vol + base + jx], fz * wt);
-        }
+    for (int j = 0; j < VW; ++j) {
+        if (cell[j] < 0) continue;
+        atomicAdd(&win[cell[j]], cx[j]);
+        atomicAdd(&win[w.vol + cell[j]], cy[j]);
+        atomicAdd(&win[2 * w.vol + cell[j]], cz[j]);
     }
     __syncthreads();
-    for (int i = t; i < w.vol; i += PATCH) {
+    for (int i = t; i < w.vol; i += IBT) {
         const double vx = win[i], vy = win[w.vol + i], vz = win[2 * w.vol + i];
         if (vx == 0.0 && vy == 0.0 && vz == 0.0) continue;
         const int lx = i % w.e[0], rest = i / w.e[0];
@@ -249,7 +267,7 @@ __device__ void fs_patch(const IbArgs<R>& a, int p, const V4<R>* P, int commit, 
     int f[3] = {0, 0, 0};
     R w[3][4];
     bool ok = false;
-    if (k < a.nv) {
+    if (t < PATCH && k < a.nv) {
         const V4<R> pos = P[k];
         if (commit) a.r[k] = pos;
         ok = stencil_of(a, pos, f, w);
@@ -264,33 +282,26 @@ __device__ void fs_patch(const IbArgs<R>& a, int p, const V4<R>* P, int commit, 
                 for (int j = 0; j < 4; ++j) st.w[t][d][j] = w[d][j];
         }
     }
-    for (int d = 0; d < 3; ++d) st.first[t][d] = f[d];
-    st.ok[t] = ok ? 1 : 0;
+    if (t < PATCH) {
+        for (int d = 0; d < 3; ++d) st.first[t][d] = f[d];
+        st.ok[t] = ok ? 1 : 0;
+    }
     __syncthreads();
     if (spread_window(a, st, win, 0, PATCH)) return;
-    // not compact: one window per 64-vertex chunk, else direct global atomics
-    const int lane = t & 15, jy = lane & 3, jz = lane >> 2;
-    for (int c = 0; c < PATCH; c += 64) {
-        if (spread_window(a, st, win, c, c + 64)) continue;
-        for (int v = c + (t >> 4); v < c + 64; v += PATCH / 16) {
-            if (!st.ok[v]) continue;
-            const R wyz = st.w[v][1][jy] * st.w[v][2][jz];
-#pragma unroll
-            for (int jx = 0; jx < 4; ++jx) {
-                const R wt = st.w[v][0][jx] * wyz;
-                const long long n = node_index(a.g, st.first[v][0] + jx, st.first[v][1] + jy,
-                                               st.first[v][2] + jz);
-                unsafeAtomicAdd(a.F + n, st.val[v][0] * wt);
-                unsafeAtomicAdd(a.F + N + n, st.val[v][1] * wt);
-                unsafeAtomicAdd(a.F + 2 * N + n, st.val[v][2] * wt);
-            }
-        }
-        __syncthreads();
+    // a patch too spread out for the window: direct global atomics
+    const int lane = t & 63, jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
+    for (int v = t >> 6; v < PATCH; v += IBT / 64) {
+        if (!st.ok[v]) continue;
+        const R wt = st.w[v][0][jx] * st.w[v][1][jy] * st.w[v][2][jz];
+        const long long n = node_index(a.g, st.first[v][0] + jx, st.first[v][1] + jy, st.first[v][2] + jz);
+        unsafeAtomicAdd(a.F + n, st.val[v][0] * wt);
+        unsafeAtomicAdd(a.F + N + n, st.val[v][1] * wt);
+        unsafeAtomicAdd(a.F + 2 * N + n, st.val[v][2] * wt);
     }
 }
 
 template <class R>
-__global__ __launch_bounds__(PATCH) void k_fs_patch(IbArgs<R> a, const V4<R>* P, int commit) {
+__global__ __launch_bounds__(IBT) void k_fs_patch(IbArgs<R> a, const V4<R>* P, int commit) {
     extern __shared__ unsigned char dyn[];
     __shared__ Stage<R> st;
     fs_patch(a, blockIdx.x, P, commit, st, reinterpret_cast<double*>(dyn));
@@ -306,13 +317,13 @@ __device__ void interp_patch(const IbArgs<R>& a, int patch, R* win) {
     R w[3][4];
     bool ok = false;
     V4<R> p = V4<R>{R(0), R(0), R(0), R(0)};
-    if (k < a.nv) {
+    if (t < PATCH && k < a.nv) {
         p = a.r[k];
         ok = stencil_of(a, p, f, w);
     }
     const Win wn = block_window(ok, f, a.wcap);
     if (wn.fits) {
-        for (int i = t; i < wn.vol; i += PATCH) {
+        for (int i = t; i < wn.vol; i += IBT) {
             const int lx = i % wn.e[0], rest = i / wn.e[0];
             const int ly = rest % wn.e[1], lz = rest / wn.e[1];
             const long long n = node_index(a.g, wn.o[0] + lx, wn.o[1] + ly, wn.o[2] + lz);
@@ -322,7 +333,7 @@ __device__ void interp_patch(const IbArgs<R>& a, int patch, R* win) {
         }
         __syncthreads();
     }
-    if (k >= a.nv) return;
+    if (t >= PATCH || k >= a.nv) return;
     R ux = R(0), uy = R(0), uz = R(0);
     if (ok) {
         if (wn.fits) {
@@ -358,7 +369,7 @@ __device__ void interp_patch(const IbArgs<R>& a, int patch, R* win) {
 }
 
 template <class R>
-__global__ __launch_bounds__(PATCH) void k_interp_patch(IbArgs<R> a) {
+__global__ __launch_bounds__(IBT) void k_interp_patch(IbArgs<R> a) {
     extern __shared__ unsigned char dyn[];
     interp_patch(a, blockIdx.x, reinterpret_cast<R*>(dyn));
 }
@@ -425,41 +436,97 @@ template <>
 __device__ inline double from_bits<double>(unsigned long long b) { return __longlong_as_double((long long)b); }
 
 template <class R>
-__device__ void hc_pass1(const IbArgs<R>& a, int blk) {
-    const int k = blk * 256 + threadIdx.x;
-    if (a.sp.max_iter > 0 && k < a.nv) hc_first(a, a.o, k, R(a.sp.alpha));
-}
+__device__ void hc_finish(const IbArgs<R>& a);
+
+// Smoothing of one step in one launch, one work-group per surface patch.
+// Phase 1: p' and b of iteration 1 (q = o) for the patch's vertices and its
+// halo (ring neighbours outside the patch) from the rings of o, into LDS.
+// Phase 2: p of the patch's vertices from the b of their rings (LDS), into
+// qa, and max |p - o| folded into the reduction slot. The last work-group to
+// arrive (counted in the second slot) sees every patch's result and finishes
+// the step: the convergence test, further iterations in the rare case they
+// are needed, the iteration count and the epoch. The arithmetic is that of a
+// pass computing every p' and b followed by a pass computing every p.
+constexpr int HALO_CAP = MAXV * PATCH;  // no patch can have more halo vertices
 
 template <class R>
-__global__ __launch_bounds__(256) void k_hc_pass1(IbArgs<R> a) {
-    hc_pass1(a, blockIdx.x);
-}
-
-template <class R>
-__device__ void hc_pass2(const IbArgs<R>& a, int blk) {
-    __shared__ R bred[4];
-    if (a.sp.max_iter <= 0) return;
+__device__ void hc_fused(const IbArgs<R>& a, int p, int npatch) {
+    __shared__ V4<R> sb[PATCH + HALO_CAP];
+    __shared__ V4<R> spp[PATCH], so[PATCH];
+    __shared__ R bred[IBT / 64];
+    __shared__ int last;
     const int t = threadIdx.x;
-    const int k = blk * 256 + t;
+    const bool on = a.sp.max_iter > 0;
+    const int base = p * PATCH;
+    const int nown = min(PATCH, a.nv - base);
+    const R alpha = R(a.sp.alpha), gamma = R(a.sp.gamma), sgn = R(a.sp.sign);
     R d = R(0);
-    if (k < a.nv) d = hc_second(a, a.o, a.qa, k, R(a.sp.gamma), R(a.sp.sign));
+    if (on) {
+        const int h0 = a.hstart[p], nh = a.hstart[p + 1] - h0;
+        for (int i = t; i < PATCH + nh; i += IBT) {
+            if (i >= nown && i < PATCH) continue;
+            const int v = i < PATCH ? base + i : a.hids[h0 + i - PATCH];
+            int m;
+            const V4<R> sum = ring_sum(a, a.o, v, &m);
+            const V4<R> ov = a.o[v];
+            const R c = (R(1) - alpha) / R(m);
+            const R px = alpha * ov.x + c * sum.x, py = alpha * ov.y + c * sum.y, pz = alpha * ov.z + c * sum.z;
+            sb[i] = V4<R>{px - (alpha * ov.x + (R(1) - alpha) * ov.x), py - (alpha * ov.y + (R(1) - alpha) * ov.y),
+                          pz - (alpha * ov.z + (R(1) - alpha) * ov.z), R(0)};
+            if (i < PATCH) {
+                spp[i] = V4<R>{px, py, pz, R(0)};
+                so[i] = ov;
+            }
+        }
+        __syncthreads();
+        if (t < nown) {
+            int nb[MAXV];
+            const int m = load_fan(a.lfan, base + t, nb);
+            R sx = R(0), sy = R(0), sz = R(0);
+#pragma unroll
+            for (int j = 0; j < MAXV; ++j) {
+                if (j < m) {
+                    const V4<R> v = sb[nb[j]];
+                    sx += v.x;
+                    sy += v.y;
+                    sz += v.z;
+                }
+            }
+            const R c = sgn * (R(1) - gamma) / R(m);
+            const V4<R> bk = sb[t], pk = spp[t], ok = so[t];
+            const R nx = pk.x - (gamma * bk.x + c * sx);
+            const R ny = pk.y - (gamma * bk.y + c * sy);
+            const R nz = pk.z - (gamma * bk.z + c * sz);
+            a.qa[base + t] = V4<R>{nx, ny, nz, R(0)};
+            const R dx = nx - ok.x, dy = ny - ok.y, dz = nz - ok.z;
+            d = sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    }
     for (int m = 32; m > 0; m >>= 1) d = fmax(d, __shfl_xor(d, m, 64));
     if ((t & 63) == 0) bred[t >> 6] = d;
     __syncthreads();
     if (t == 0) {
-        const R b = fmax(fmax(bred[0], bred[1]), fmax(bred[2], bred[3]));
-        atomicMax(a.red, max_bits(b));
+        R b = bred[0];
+        for (int w = 1; w < IBT / 64; ++w) b = fmax(b, bred[w]);
+        if (on) atomicMax(a.red, max_bits(b));
+        __threadfence();
+        last = atomicAdd(a.red + 1, 1ull) == (unsigned long long)(npatch - 1);
     }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    hc_finish(a);
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_hc_pass2(IbArgs<R> a) {
-    hc_pass2(a, blockIdx.x);
+__global__ __launch_bounds__(IBT) void k_hc_fused(IbArgs<R> a, int npatch) {
+    hc_fused(a, blockIdx.x, npatch);
 }
 
-// One work-group: iteration 1 is done; continue while not converged (rare),
-// leave the final positions in qa, record the iteration count, advance the
-// epoch and reset the reduction slot.
+// One work-group, after iteration 1 is in qa and its maximum in the
+// reduction slot: continue while not converged (rare), leave the final
+// positions in qa, record the iteration count, advance the epoch and reset
+// both reduction slots.
 template <class R>
 __device__ void hc_finish(const IbArgs<R>& a) {
     __shared__ R bred[16];
@@ -469,6 +536,7 @@ __device__ void hc_finish(const IbArgs<R>& a) {
         if (t == 0) {
             a.ctl->iters = 0;
             a.ctl->epoch += 1;
+            a.red[1] = 0ull;
         }
         return;
     }
@@ -508,18 +576,14 @@ __device__ void hc_finish(const IbArgs<R>& a) {
         a.ctl->iters = it;
         if (capped) a.ctl->cap_hits += 1;
         a.ctl->epoch += 1;
-        *a.red = 0ull;
+        a.red[0] = 0ull;
+        a.red[1] = 0ull;
     }
-}
-
-template <class R>
-__global__ __launch_bounds__(1024) void k_hc_finish(IbArgs<R> a) {
-    hc_finish(a);
 }
 
 // ---------------------------------------------------------------- ensemble forms
 // Work-group b of a batched launch belongs to the member d with
-// start[d] <= b < start[d+1] (start: patch offsets, one patch = 256 vertices).
+// start[d] <= b < start[d+1] (start: patch offsets, one patch = PATCH vertices).
 __device__ inline int member_of(const int* __restrict__ start, int ndrop, int b) {
     int lo = 0, hi = ndrop;
     while (hi - lo > 1) {
@@ -530,7 +594,7 @@ __device__ inline int member_of(const int* __restrict__ start, int ndrop, int b)
 }
 
 template <class R>
-__global__ __launch_bounds__(PATCH) void k_interp_batch(const IbArgs<R>* __restrict__ args,
+__global__ __launch_bounds__(IBT) void k_interp_batch(const IbArgs<R>* __restrict__ args,
                                                        const int* __restrict__ start, int ndrop) {
     extern __shared__ unsigned char dyn[];
     const int d = member_of(start, ndrop, blockIdx.x);
@@ -538,26 +602,14 @@ __global__ __launch_bounds__(PATCH) void k_interp_batch(const IbArgs<R>* __restr
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_hc_pass1_batch(const IbArgs<R>* __restrict__ args,
+__global__ __launch_bounds__(IBT) void k_hc_fused_batch(const IbArgs<R>* __restrict__ args,
                                                         const int* __restrict__ start, int ndrop) {
     const int d = member_of(start, ndrop, blockIdx.x);
-    hc_pass1(args[d], blockIdx.x - start[d]);
+    hc_fused(args[d], blockIdx.x - start[d], start[d + 1] - start[d]);
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_hc_pass2_batch(const IbArgs<R>* __restrict__ args,
-                                                        const int* __restrict__ start, int ndrop) {
-    const int d = member_of(start, ndrop, blockIdx.x);
-    hc_pass2(args[d], blockIdx.x - start[d]);
-}
-
-template <class R>
-__global__ __launch_bounds__(1024) void k_hc_finish_batch(const IbArgs<R>* __restrict__ args) {
-    hc_finish(args[blockIdx.x]);
-}
-
-template <class R>
-__global__ __launch_bounds__(PATCH) void k_fs_batch(const IbArgs<R>* __restrict__ args, const int* __restrict__ start,
+__global__ __launch_bounds__(IBT) void k_fs_batch(const IbArgs<R>* __restrict__ args, const int* __restrict__ start,
                                                    int ndrop, int commit) {
     extern __shared__ unsigned char dyn[];
     __shared__ Stage<R> st;
@@ -568,7 +620,7 @@ __global__ __launch_bounds__(PATCH) void k_fs_batch(const IbArgs<R>* __restrict_
 }
 
 // ---------------------------------------------------------------- launchers
-int patch_window_nodes(int storage) { return storage == IBM_LB_F64 ? 4096 : 8192; }
+int patch_window_nodes(int) { return 2048; }
 
 static size_t dyn_lds(int storage) { return 3 * (size_t)patch_window_nodes(storage) * real_bytes(storage); }
 static size_t dyn_lds_spread() { return 3 * (size_t)SPREAD_WCAP * sizeof(double); }
@@ -587,6 +639,9 @@ static IbArgs<R> make_args(const Geom& g, const DevPtrs& d, int nv, double sigma
     a.pp = (V4<R>*)d.pp;
     a.bb = (V4<R>*)d.bb;
     a.fan = d.fan;
+    a.lfan = d.lfan;
+    a.hstart = d.hstart;
+    a.hids = d.hids;
     a.F = (R*)d.F;
     a.U = (const R*)d.u;
     a.mark = d.mark;
@@ -629,15 +684,10 @@ static hipError_t launch_step_t(const Geom& g, const DevPtrs& d, int nv, double 
                                 hipStream_t s, size_t lds) {
     IbArgs<R> a = make_args<R>(g, d, nv, sigma, sp);
     const unsigned npatch = (nv + PATCH - 1) / PATCH;
-    const unsigned nb = (nv + 255) / 256;
-    hipLaunchKernelGGL(k_interp_patch<R>, dim3(npatch), dim3(PATCH), lds, s, a);
+    hipLaunchKernelGGL(k_interp_patch<R>, dim3(npatch), dim3(IBT), lds, s, a);
     const V4<R>* final_pos = sp.max_iter > 0 ? a.qa : a.o;
-    if (sp.max_iter > 0) {
-        hipLaunchKernelGGL(k_hc_pass1<R>, dim3(nb), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(k_hc_pass2<R>, dim3(nb), dim3(256), 0, s, a);
-    }
-    hipLaunchKernelGGL(k_hc_finish<R>, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(PATCH), dyn_lds_spread(), s, a, final_pos, 1);
+    hipLaunchKernelGGL(k_hc_fused<R>, dim3(npatch), dim3(IBT), 0, s, a, (int)npatch);
+    hipLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), dyn_lds_spread(), s, a, final_pos, 1);
     return hipGetLastError();
 }
 
@@ -652,12 +702,10 @@ void fill_ib_args(int storage, const Geom& g, const DevPtrs& d, int nv, double s
 template <class R>
 static hipError_t batch_step_t(const void* args, const int* start, int ndrop, int npatch_total, hipStream_t s) {
     const IbArgs<R>* a = (const IbArgs<R>*)args;
-    hipLaunchKernelGGL(k_interp_batch<R>, dim3(npatch_total), dim3(PATCH), dyn_lds(sizeof(R) == 8 ? IBM_LB_F64 : IBM_LB_F32),
+    hipLaunchKernelGGL(k_interp_batch<R>, dim3(npatch_total), dim3(IBT), dyn_lds(sizeof(R) == 8 ? IBM_LB_F64 : IBM_LB_F32),
                        s, a, start, ndrop);
-    hipLaunchKernelGGL(k_hc_pass1_batch<R>, dim3(npatch_total), dim3(256), 0, s, a, start, ndrop);
-    hipLaunchKernelGGL(k_hc_pass2_batch<R>, dim3(npatch_total), dim3(256), 0, s, a, start, ndrop);
-    hipLaunchKernelGGL(k_hc_finish_batch<R>, dim3(ndrop), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_fs_batch<R>, dim3(npatch_total), dim3(PATCH), dyn_lds_spread(), s, a, start, ndrop, 1);
+    hipLaunchKernelGGL(k_hc_fused_batch<R>, dim3(npatch_total), dim3(IBT), 0, s, a, start, ndrop);
+    hipLaunchKernelGGL(k_fs_batch<R>, dim3(npatch_total), dim3(IBT), dyn_lds_spread(), s, a, start, ndrop, 1);
     return hipGetLastError();
 }
 
@@ -670,10 +718,10 @@ hipError_t launch_ib_step_batch(int storage, const void* args, const int* start,
 hipError_t launch_ib_pre_batch(int storage, const void* args, const int* start, int ndrop, int npatch_total,
                                hipStream_t s) {
     if (storage == IBM_LB_F64)
-        hipLaunchKernelGGL(k_fs_batch<double>, dim3(npatch_total), dim3(PATCH), dyn_lds_spread(), s,
+        hipLaunchKernelGGL(k_fs_batch<double>, dim3(npatch_total), dim3(IBT), dyn_lds_spread(), s,
                            (const IbArgs<double>*)args, start, ndrop, 0);
     else
-        hipLaunchKernelGGL(k_fs_batch<float>, dim3(npatch_total), dim3(PATCH), dyn_lds_spread(), s,
+        hipLaunchKernelGGL(k_fs_batch<float>, dim3(npatch_total), dim3(IBT), dyn_lds_spread(), s,
                            (const IbArgs<float>*)args, start, ndrop, 0);
     return hipGetLastError();
 }
@@ -684,10 +732,10 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
     const size_t lds = dyn_lds_spread();
     if (storage == IBM_LB_F64) {
         IbArgs<double> a = make_args<double>(g, d, nv, sigma, sp);
-        hipLaunchKernelGGL(k_fs_patch<double>, dim3(npatch), dim3(PATCH), lds, s, a, (const V4<double>*)a.r, 0);
+        hipLaunchKernelGGL(k_fs_patch<double>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<double>*)a.r, 0);
     } else {
         IbArgs<float> a = make_args<float>(g, d, nv, sigma, sp);
-        hipLaunchKernelGGL(k_fs_patch<float>, dim3(npatch), dim3(PATCH), lds, s, a, (const V4<float>*)a.r, 0);
+        hipLaunchKernelGGL(k_fs_patch<float>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<float>*)a.r, 0);
     }
     return hipGetLastError();
 }

@@ -74,6 +74,9 @@ struct DevPtrs {
     void* bb;
     int4* tris;              // [nt]
     int4* fan;               // [nv][4]: valence, then the ordered one-ring (15 slots)
+    int4* lfan;              // [nv][4]: the same fan in patch-local slots (own vertices, then the halo)
+    int* hstart;             // [npatch + 1] halo offsets of each IB_PATCH-vertex patch
+    int* hids;               // halo vertices (outside the patch, in some ring of it), per patch ascending
     double* obs_part;        // [OBS_BLOCKS][16]
     double* mass_part;       // [MASS_BLOCKS][4]
     double* obs_out;         // [48] final observables
@@ -96,6 +99,11 @@ struct LatDesc {
     int ib;
 };
 
+// Vertices per surface patch: the set-up renumbering makes every run of
+// IB_PATCH consecutive vertices spatially compact; the patch-organised IB
+// kernels give one work-group to one patch.
+constexpr int IB_PATCH = 64;
+
 constexpr int OBS_BLOCKS = 128;
 constexpr int MASS_BLOCKS = 512;
 constexpr int ACAP = 4096;
@@ -105,15 +113,17 @@ constexpr int OBS_OUT_N = 48;
 // hipError_t of the launch.
 hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                        const double* A0, int rest, hipStream_t s);
-// variant: bit 0 = non-temporal population loads, bit 1 = 512-thread blocks.
-constexpr int LATTICE_VARIANTS = 4;
+// variant: bit 0 = non-temporal population loads, bits 1-2 = work-group size
+// LAT_BS[variant >> 1].
+constexpr int LATTICE_VARIANTS = 8;
+constexpr int LAT_BS[4] = {128, 256, 512, 64};
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, hipStream_t s);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
-// start: member block offsets for 256-thread blocks [ndrop + 1], followed by
-// those for 512-thread blocks [ndrop + 1].
-hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int* start, int ndrop, int nblocks256,
-                                int nblocks512, int cur, long long step, int variant, hipStream_t s);
+// start: member block offsets [4][ndrop + 1], one table per work-group size
+// LAT_BS[i]; nblocks[i] the total block count of table i.
+hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int* start, int ndrop, const int nblocks[4],
+                                int cur, long long step, int variant, hipStream_t s);
 hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, double* rho_out, double* u_out, hipStream_t s);
 hipError_t launch_observables(int storage, const Geom& g, const LatticeParams& lp,

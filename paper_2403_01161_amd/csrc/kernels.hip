@@ -504,63 +504,70 @@ hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, cons
     return hipGetLastError();
 }
 
-template <class C, bool IB>
-static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                             const double* A_row, hipStream_t s) {
+template <class C, bool IB, bool NTL, int BS>
+static void lattice_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
+                           hipStream_t s) {
     using R = typename C::real;
     using S = typename C::store_t;
-    const S* fi = (const S*)d.f[cur];
-    S* fo = (S*)d.f[cur ^ 1];
-    switch (variant & 3) {
-        case 0:
-            hipLaunchKernelGGL((k_lattice<C, IB, false, 256>), dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
-                               fi, fo, (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
-            break;
-        case 1:
-            hipLaunchKernelGGL((k_lattice<C, IB, true, 256>), dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, lp,
-                               fi, fo, (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_lattice<C, IB, false, 512>), dim3(blocks_for(g.N, 512)), dim3(512), 0, s, g, lp,
-                               fi, fo, (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
-            break;
-        default:
-            hipLaunchKernelGGL((k_lattice<C, IB, true, 512>), dim3(blocks_for(g.N, 512)), dim3(512), 0, s, g, lp,
-                               fi, fo, (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
-            break;
+    hipLaunchKernelGGL((k_lattice<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, g, lp,
+                       (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
+}
+
+template <class C, bool IB, bool NTL>
+static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
+                             const double* A_row, hipStream_t s) {
+    switch ((variant >> 1) & 3) {
+        case 0: lattice_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, s); break;
+        case 1: lattice_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, s); break;
+        case 2: lattice_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, s); break;
+        default: lattice_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, s); break;
     }
 }
 
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, hipStream_t s) {
     DISPATCH_STORAGE(storage, C, {
-        if (ib) launch_lattice_v<C, true>(variant, g, lp, d, cur, A_row, s);
-        else launch_lattice_v<C, false>(variant, g, lp, d, cur, A_row, s);
+        if (ib) {
+            if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, s);
+            else launch_lattice_v<C, true, false>(variant, g, lp, d, cur, A_row, s);
+        } else {
+            if (variant & 1) launch_lattice_v<C, false, true>(variant, g, lp, d, cur, A_row, s);
+            else launch_lattice_v<C, false, false>(variant, g, lp, d, cur, A_row, s);
+        }
     });
     return hipGetLastError();
 }
 
-hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int* start, int ndrop, int nblocks256,
-                                int nblocks512, int cur, long long step, int variant, hipStream_t s) {
+template <class C, bool NTL>
+static void launch_batch_v(int bsi, const LatDesc* desc, const int* start, int ndrop, const int nblocks[4], int cur,
+                           long long step, hipStream_t s) {
+    const int* st = start + bsi * (ndrop + 1);
+    switch (bsi) {
+        case 0:
+            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[0]>), dim3(nblocks[0]), dim3(LAT_BS[0]), 0, s, desc, st,
+                               ndrop, cur, step);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[1]>), dim3(nblocks[1]), dim3(LAT_BS[1]), 0, s, desc, st,
+                               ndrop, cur, step);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[2]>), dim3(nblocks[2]), dim3(LAT_BS[2]), 0, s, desc, st,
+                               ndrop, cur, step);
+            break;
+        default:
+            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[3]>), dim3(nblocks[3]), dim3(LAT_BS[3]), 0, s, desc, st,
+                               ndrop, cur, step);
+            break;
+    }
+}
+
+hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int* start, int ndrop, const int nblocks[4],
+                                int cur, long long step, int variant, hipStream_t s) {
+    const int bsi = (variant >> 1) & 3;
     DISPATCH_STORAGE(storage, C, {
-        switch (variant & 3) {
-            case 0:
-                hipLaunchKernelGGL((k_lattice_batch<C, false, 256>), dim3(nblocks256), dim3(256), 0, s, desc, start,
-                                   ndrop, cur, step);
-                break;
-            case 1:
-                hipLaunchKernelGGL((k_lattice_batch<C, true, 256>), dim3(nblocks256), dim3(256), 0, s, desc, start,
-                                   ndrop, cur, step);
-                break;
-            case 2:
-                hipLaunchKernelGGL((k_lattice_batch<C, false, 512>), dim3(nblocks512), dim3(512), 0, s, desc,
-                                   start + ndrop + 1, ndrop, cur, step);
-                break;
-            default:
-                hipLaunchKernelGGL((k_lattice_batch<C, true, 512>), dim3(nblocks512), dim3(512), 0, s, desc,
-                                   start + ndrop + 1, ndrop, cur, step);
-                break;
-        }
+        if (variant & 1) launch_batch_v<C, true>(bsi, desc, start, ndrop, nblocks, cur, step, s);
+        else launch_batch_v<C, false>(bsi, desc, start, ndrop, nblocks, cur, step, s);
     });
     return hipGetLastError();
 }
