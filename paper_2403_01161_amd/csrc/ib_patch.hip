@@ -302,7 +302,7 @@ __device__ void fs_patch(const IbArgs<R>& a, int p, const V4<R>* P, int commit, 
 
 template <class R>
 __global__ __launch_bounds__(IBT) void k_fs_patch(IbArgs<R> a, const V4<R>* P, int commit) {
-    extern __shared__ unsigned char dyn[];
+    extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ Stage<R> st;
     fs_patch(a, blockIdx.x, P, commit, st, reinterpret_cast<double*>(dyn));
 }
@@ -370,7 +370,7 @@ __device__ void interp_patch(const IbArgs<R>& a, int patch, R* win) {
 
 template <class R>
 __global__ __launch_bounds__(IBT) void k_interp_patch(IbArgs<R> a) {
-    extern __shared__ unsigned char dyn[];
+    extern __shared__ __align__(16) unsigned char dyn[];
     interp_patch(a, blockIdx.x, reinterpret_cast<R*>(dyn));
 }
 
@@ -462,6 +462,10 @@ __device__ void hc_fused(const IbArgs<R>& a, int p, int npatch) {
     const R alpha = R(a.sp.alpha), gamma = R(a.sp.gamma), sgn = R(a.sp.sign);
     R d = R(0);
     if (on) {
+        // the patch-local fan of this thread's own vertex, loaded before the
+        // first phase so that its latency overlaps that phase's loads
+        int lnb[MAXV];
+        const int lm = t < nown ? load_fan(a.lfan, base + t, lnb) : 0;
         const int h0 = a.hstart[p], nh = a.hstart[p + 1] - h0;
         for (int i = t; i < PATCH + nh; i += IBT) {
             if (i >= nown && i < PATCH) continue;
@@ -480,13 +484,12 @@ __device__ void hc_fused(const IbArgs<R>& a, int p, int npatch) {
         }
         __syncthreads();
         if (t < nown) {
-            int nb[MAXV];
-            const int m = load_fan(a.lfan, base + t, nb);
+            const int m = lm;
             R sx = R(0), sy = R(0), sz = R(0);
 #pragma unroll
             for (int j = 0; j < MAXV; ++j) {
                 if (j < m) {
-                    const V4<R> v = sb[nb[j]];
+                    const V4<R> v = sb[lnb[j]];
                     sx += v.x;
                     sy += v.y;
                     sz += v.z;
@@ -596,7 +599,7 @@ __device__ inline int member_of(const int* __restrict__ start, int ndrop, int b)
 template <class R>
 __global__ __launch_bounds__(IBT) void k_interp_batch(const IbArgs<R>* __restrict__ args,
                                                        const int* __restrict__ start, int ndrop) {
-    extern __shared__ unsigned char dyn[];
+    extern __shared__ __align__(16) unsigned char dyn[];
     const int d = member_of(start, ndrop, blockIdx.x);
     interp_patch(args[d], blockIdx.x - start[d], reinterpret_cast<R*>(dyn));
 }
@@ -611,7 +614,7 @@ __global__ __launch_bounds__(IBT) void k_hc_fused_batch(const IbArgs<R>* __restr
 template <class R>
 __global__ __launch_bounds__(IBT) void k_fs_batch(const IbArgs<R>* __restrict__ args, const int* __restrict__ start,
                                                    int ndrop, int commit) {
-    extern __shared__ unsigned char dyn[];
+    extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ Stage<R> st;
     const int d = member_of(start, ndrop, blockIdx.x);
     const IbArgs<R>& a = args[d];
