@@ -417,22 +417,44 @@ __global__ __launch_bounds__(256) void k_adj_hess(int nv, const int4* __restrict
 }
 
 // Per-step block partials -> dJ/dA rows (overwritten) and dJ/dsigma
-// (accumulated), summed in a fixed order.
-__global__ void k_adj_reduce(int nsteps, int nbl, const double* __restrict__ Apart, int nbv,
-                             const double* __restrict__ spart, double* __restrict__ dA, double* __restrict__ dsigma) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < 9 * nsteps) {
-        const int j = t / 9, c = t - 9 * (t / 9);
-        double s = 0.0;
-        for (int b = 0; b < nbl; ++b) s += Apart[((long long)j * nbl + b) * 9 + c];
-        dA[t] = s;
+// (accumulated). One work-group per step: each thread sums a fixed strided
+// subset of the partials, then a fixed-order tree in LDS; the result does not
+// depend on scheduling.
+__global__ __launch_bounds__(256) void k_adj_reduce_A(int nbl, const double* __restrict__ Apart,
+                                                      double* __restrict__ dA) {
+    __shared__ double red[9][256];
+    const int j = blockIdx.x, t = threadIdx.x;
+    double s[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) s[c] = 0.0;
+    for (int b = t; b < nbl; b += 256)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) s[c] += Apart[((long long)j * nbl + b) * 9 + c];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) red[c][t] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int c = 0; c < 9; ++c) red[c][t] += red[c][t + w];
+        __syncthreads();
     }
-    if (t == 0 && nbv > 0) {
-        double s = 0.0;
-        for (int j = 0; j < nsteps; ++j)
-            for (int b = 0; b < nbv; ++b) s += spart[(long long)j * nbv + b];
-        *dsigma += s;
+    if (t < 9) dA[9 * j + t] = red[t][0];
+}
+
+__global__ __launch_bounds__(256) void k_adj_reduce_sigma(long long n, const double* __restrict__ spart,
+                                                          double* __restrict__ dsigma) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (long long i = t; i < n; i += 256) s += spart[i];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
     }
+    if (t == 0) *dsigma += red[0];
 }
 
 // ---------------------------------------------------------------- objective
@@ -597,8 +619,9 @@ hipError_t launch_adj_ib_back(const Geom& g, int nv, const int4* fan, double sig
 
 hipError_t launch_adj_reduce(int nsteps, int nbl, const double* Apart, int nbv, const double* spart, double* dA,
                              double* dsigma, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_reduce, dim3(nblk(9ll * nsteps, 256)), dim3(256), 0, s, nsteps, nbl, Apart, nbv, spart,
-                       dA, dsigma);
+    hipLaunchKernelGGL(k_adj_reduce_A, dim3(nsteps), dim3(256), 0, s, nbl, Apart, dA);
+    if (nbv > 0)
+        hipLaunchKernelGGL(k_adj_reduce_sigma, dim3(1), dim3(256), 0, s, (long long)nsteps * nbv, spart, dsigma);
     return hipGetLastError();
 }
 
