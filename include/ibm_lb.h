@@ -165,16 +165,34 @@ size_t ibm_lb_state_bytes(const ibm_lb* h);
 int ibm_lb_save(ibm_lb* h, void* dst, size_t n);
 int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
 
-/* Autotuner: picks the variant of the fused lattice kernel (non-temporal
- * population loads on/off; 64, 128, 256 or 512-thread work-groups) for this
- * configuration by timing `reps` whole steps with each, in four interleaved
- * rounds, from a snapshot of the state that is restored afterwards (the
- * state after the call equals the state before; the force field is spread
- * again at the next step). Synchronises the stream. *variant (may be NULL)
- * receives the choice: bit 0 non-temporal loads, bits 1-2 index the
- * work-group sizes {128, 256, 512, 64}. Errors: EINVAL, ENOMEM, EDEVICE,
- * sticky. */
+/* Lattice-kernel variants (all compute the same per-node arithmetic; they
+ * differ only in how nodes map to work-groups and how populations reach
+ * memory), 0 <= variant < 32:
+ *   bit 0     non-temporal population loads;
+ *   bits 1-2  work-group size {128, 256, 512, 64}[(variant >> 1) & 3]; in the
+ *             row layout, the least number of whole x-rows (at least one)
+ *             that fits in it;
+ *   bit 4     row layout: a work-group owns whole x-rows and hands the
+ *             populations moving along x to their target thread through
+ *             LDS, so every population store is row-aligned (needs
+ *             Lx <= 512); otherwise the linear layout (consecutive nodes per
+ *             work-group, each population stored straight at its target);
+ *   bit 3     linear layout: work-groups ordered so that each XCD takes a
+ *             contiguous eighth of the lattice; row layout: non-temporal
+ *             population stores.
+ *
+ * Autotuner: picks the variant for this configuration by timing `reps` whole
+ * steps with each variant that can run, in four interleaved rounds, from a
+ * snapshot of the state that is restored afterwards (the state after the
+ * call equals the state before; the force field is spread again at the next
+ * step). Synchronises the stream. *variant (may be NULL) receives the choice.
+ * Errors: EINVAL, ENOMEM, EDEVICE, sticky.
+ *
+ * ibm_lb_set_variant selects a variant directly (EINVAL if out of range or
+ * the row layout cannot take this box). The default is 1 (linear layout,
+ * 128-thread work-groups, non-temporal loads). */
 int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);
+int ibm_lb_set_variant(ibm_lb* h, int32_t variant);
 
 /* Kernel timing of the fused lattice kernel: when enabled, every step records
  * HIP events around the lattice kernel on the handle's stream.
@@ -202,13 +220,19 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
  *   reads (vertices, fields, observables, save); stepping a member on its
  *   own while it belongs to an ensemble is not supported.
  * ibm_lb_batch_autotune: as ibm_lb_autotune for the batched steps (gradient
- *   rows of the last upload); every member is restored afterwards.
+ *   rows of the last upload); every member is restored afterwards. In the
+ *   batched row layout a work-group of the selected size takes
+ *   floor(size / Lx) whole rows of one member, so a row variant runs only
+ *   when every member's Lx fits in the work-group.
+ * ibm_lb_batch_set_variant: as ibm_lb_set_variant (EINVAL if the variant
+ *   cannot run on every member).
  * ibm_lb_batch_destroy frees the ensemble and its members. */
 int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb_batch** out);
 int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps);
 int ibm_lb_batch_observables(ibm_lb_batch* b, ibm_lb_obs* out);
 int ibm_lb_batch_member(ibm_lb_batch* b, int32_t i, ibm_lb** out);
 int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant);
+int ibm_lb_batch_set_variant(ibm_lb_batch* b, int32_t variant);
 void ibm_lb_batch_destroy(ibm_lb_batch* b);
 
 /* ---- adjoint: reverse-mode derivatives of the droplet deformation ----

@@ -833,6 +833,7 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     for (int v = 0; v < LATTICE_VARIANTS; ++v) best_of[v] = 1e30f;
     for (int round = 0; round < 4 && e == hipSuccess && rc == IBM_LB_OK; ++round)
         for (int v = 0; v < LATTICE_VARIANTS && e == hipSuccess && rc == IBM_LB_OK; ++v) {
+            if (!lattice_variant_ok(v, h->g)) continue;
             h->lattice_variant = v;
             rc = enqueue_steps(h, Arow, 1, 0);  // untimed: first launch of this variant in the round
             if (rc) break;
@@ -861,6 +862,13 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     if (rc) return rc;
     if (rc_load) return rc_load;
     if (variant) *variant = best_v;
+    return IBM_LB_OK;
+}
+
+int ibm_lb_set_variant(ibm_lb* h, int32_t variant) {
+    if (!h) return fail(IBM_LB_EINVAL, "handle is NULL");
+    if (!lattice_variant_ok(variant, h->g)) return fail(IBM_LB_EINVAL, "lattice variant cannot run on this box");
+    h->lattice_variant = variant;
     return IBM_LB_OK;
 }
 
@@ -1062,10 +1070,11 @@ struct ibm_lb_batch {
     int storage = 0, device = 0, n = 0;
     hipStream_t stream = nullptr;
     LatDesc* lat_desc = nullptr;  // device [n]
-    int* lat_start = nullptr;     // device [4][n + 1]: member block offsets per work-group size
-    int nblk[4] = {0, 0, 0, 0};
+    int2* lat_map = nullptr;      // device block maps of the eight layouts, concatenated
+    int lat_moff[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int nblk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     void* ib_args = nullptr;      // device [n] records
-    int* patch_start = nullptr;   // device [n + 1]
+    int2* patch_map = nullptr;    // device [npatch_total] {member, patch}
     int npatch_total = 0;
     double* Atab = nullptr;       // device [2 halves][n][ACAP][9]
     double* stage = nullptr;      // pinned [2 halves][n][ACAP][9]
@@ -1078,6 +1087,11 @@ struct ibm_lb_batch {
 };
 
 namespace {
+bool batch_variant_ok(const ibm_lb_batch* b, int v) {
+    if (v < 0 || v >= LATTICE_VARIANTS) return false;
+    return !(v & VAR_ROWS) || b->nblk[4 + ((v >> 1) & 3)] >= 0;
+}
+
 int batch_fail_cleanup(ibm_lb_batch* b, int code) {
     ibm_lb_batch_destroy(b);
     return code;
@@ -1110,7 +1124,8 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     auto bail = [&](hipError_t e, const char* where) { return batch_fail_cleanup(b, hip_fail(e, where)); };
     hipError_t e;
     std::vector<LatDesc> ld(n);
-    std::vector<int> st(4 * (n + 1), 0), ps(n + 1, 0);
+    std::vector<int2> lm[8], pm;
+    bool rows_ok[4] = {true, true, true, true};
     const size_t rec = ib_args_bytes(b->storage);
     std::vector<char> args(rec * n);
     for (int i = 0; i < n; ++i) {
@@ -1126,13 +1141,28 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
         L.ctl = h->d.ctl;
         L.A = nullptr;  // set below, once the table is allocated
         L.ib = h->nv > 0 ? 1 : 0;
-        for (int q = 0; q < 4; ++q)
-            st[q * (n + 1) + i + 1] = st[q * (n + 1) + i] + (int)((h->g.N + LAT_BS[q] - 1) / LAT_BS[q]);
-        ps[i + 1] = ps[i] + (h->nv + IB_PATCH - 1) / IB_PATCH;
+        for (int q = 0; q < 4; ++q) {
+            for (int k = 0; k < (int)((h->g.N + LAT_BS[q] - 1) / LAT_BS[q]); ++k) lm[q].push_back(int2{i, k});
+            const int rows = LAT_BS[q] / h->g.Lx;
+            if (rows < 1) {
+                rows_ok[q] = false;
+                continue;
+            }
+            const long long nrows = (long long)h->g.Ly * h->g.Lz;
+            for (int k = 0; k < (int)((nrows + rows - 1) / rows); ++k) lm[4 + q].push_back(int2{i, k});
+        }
+        for (int k = 0; k < (h->nv + IB_PATCH - 1) / IB_PATCH; ++k) pm.push_back(int2{i, k});
         fill_ib_args(b->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, args.data() + rec * i);
     }
-    for (int q = 0; q < 4; ++q) b->nblk[q] = st[q * (n + 1) + n];
-    b->npatch_total = ps[n];
+    std::vector<int2> lall;
+    for (int q = 0; q < 8; ++q) {
+        if (q >= 4 && !rows_ok[q - 4]) lm[q].clear();
+        b->nblk[q] = q >= 4 && !rows_ok[q - 4] ? -1 : (int)lm[q].size();
+        b->lat_moff[q] = (int)lall.size();
+        lall.insert(lall.end(), lm[q].begin(), lm[q].end());
+    }
+    b->npatch_total = (int)pm.size();
+    if (pm.empty()) pm.push_back(int2{0, 0});
     const size_t tab = (size_t)n * ACAP * 9;
     if ((e = hipMalloc((void**)&b->Atab, 2 * tab * sizeof(double))) != hipSuccess) return bail(e, "gradient tables");
     if ((e = hipHostMalloc((void**)&b->stage, 2 * tab * sizeof(double), hipHostMallocDefault)) != hipSuccess)
@@ -1140,17 +1170,17 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     if ((e = hipMemset(b->Atab, 0, 2 * tab * sizeof(double))) != hipSuccess) return bail(e, "gradient tables");
     for (int i = 0; i < n; ++i) ld[i].A = b->Atab + (size_t)i * ACAP * 9;
     if ((e = hipMalloc((void**)&b->lat_desc, sizeof(LatDesc) * n)) != hipSuccess) return bail(e, "descriptors");
-    if ((e = hipMalloc((void**)&b->lat_start, sizeof(int) * st.size())) != hipSuccess) return bail(e, "offsets");
+    if ((e = hipMalloc((void**)&b->lat_map, sizeof(int2) * lall.size())) != hipSuccess) return bail(e, "maps");
     if ((e = hipMalloc(&b->ib_args, rec * n)) != hipSuccess) return bail(e, "ib records");
-    if ((e = hipMalloc((void**)&b->patch_start, sizeof(int) * ps.size())) != hipSuccess) return bail(e, "offsets");
+    if ((e = hipMalloc((void**)&b->patch_map, sizeof(int2) * pm.size())) != hipSuccess) return bail(e, "maps");
     if ((e = hipMemcpy(b->lat_desc, ld.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "descriptors");
-    if ((e = hipMemcpy(b->lat_start, st.data(), sizeof(int) * st.size(), hipMemcpyHostToDevice)) != hipSuccess)
-        return bail(e, "offsets");
+    if ((e = hipMemcpy(b->lat_map, lall.data(), sizeof(int2) * lall.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "maps");
     if ((e = hipMemcpy(b->ib_args, args.data(), rec * n, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "ib records");
-    if ((e = hipMemcpy(b->patch_start, ps.data(), sizeof(int) * ps.size(), hipMemcpyHostToDevice)) != hipSuccess)
-        return bail(e, "offsets");
+    if ((e = hipMemcpy(b->patch_map, pm.data(), sizeof(int2) * pm.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "maps");
     for (int k = 0; k < 2; ++k) {
         if ((e = hipEventCreateWithFlags(&b->stage_done[k], hipEventDisableTiming)) != hipSuccess)
             return bail(e, "hipEventCreate");
@@ -1169,7 +1199,7 @@ int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps) {
     const int n = b->n;
     const size_t tab = (size_t)n * ACAP * 9;
     if (!b->f_ready) {
-        HIP_TRY(launch_ib_pre_batch(b->storage, b->ib_args, b->patch_start, n, b->npatch_total, b->stream),
+        HIP_TRY(launch_ib_pre_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, b->stream),
                 "ib_pre launch");
         b->f_ready = true;
     }
@@ -1185,10 +1215,10 @@ int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps) {
         HIP_TRY(hipMemcpyAsync(dst, sg, sizeof(double) * tab, hipMemcpyHostToDevice, b->stream), "upload tables");
         HIP_TRY(hipEventRecord(b->stage_done[hf], b->stream), "hipEventRecord");
         for (int j = 0; j < len; ++j) {
-            HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_start, n, b->nblk, b->cur,
+            HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->cur,
                                          (long long)hf * tab + 9ll * j, b->variant, b->stream),
                     "lattice batch launch");
-            HIP_TRY(launch_ib_step_batch(b->storage, b->ib_args, b->patch_start, n, b->npatch_total, b->stream),
+            HIP_TRY(launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, n, b->stream),
                     "ib batch launch");
             b->cur ^= 1;
         }
@@ -1253,7 +1283,7 @@ int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant) {
     if (rc == IBM_LB_OK) e = hipEventCreate(&e0);
     if (rc == IBM_LB_OK && e == hipSuccess) e = hipEventCreate(&e1);
     if (rc == IBM_LB_OK && e == hipSuccess && !b->f_ready) {
-        e = launch_ib_pre_batch(b->storage, b->ib_args, b->patch_start, n, b->npatch_total, b->stream);
+        e = launch_ib_pre_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, b->stream);
         b->f_ready = true;
     }
     float best_of[LATTICE_VARIANTS];
@@ -1261,15 +1291,17 @@ int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant) {
     auto batch_steps = [&](int v, int k) {
         hipError_t r = hipSuccess;
         for (int j = 0; j < k && r == hipSuccess; ++j) {
-            r = launch_lattice_batch(b->storage, b->lat_desc, b->lat_start, n, b->nblk, b->cur, 0, v, b->stream);
+            r = launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->cur, 0, v,
+                                     b->stream);
             if (r == hipSuccess)
-                r = launch_ib_step_batch(b->storage, b->ib_args, b->patch_start, n, b->npatch_total, b->stream);
+                r = launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, n, b->stream);
             b->cur ^= 1;
         }
         return r;
     };
     for (int round = 0; round < 4 && e == hipSuccess && rc == IBM_LB_OK; ++round)
         for (int v = 0; v < LATTICE_VARIANTS && e == hipSuccess; ++v) {
+            if (!batch_variant_ok(b, v)) continue;
             e = batch_steps(v, 1);
             if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
             if (e == hipSuccess) e = batch_steps(v, reps);
@@ -1305,6 +1337,13 @@ int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant) {
     return IBM_LB_OK;
 }
 
+int ibm_lb_batch_set_variant(ibm_lb_batch* b, int32_t variant) {
+    if (!b) return fail(IBM_LB_EINVAL, "batch handle is NULL");
+    if (!batch_variant_ok(b, variant)) return fail(IBM_LB_EINVAL, "lattice variant cannot run on every member");
+    b->variant = variant;
+    return IBM_LB_OK;
+}
+
 void ibm_lb_batch_destroy(ibm_lb_batch* b) {
     if (!b) return;
     (void)hipSetDevice(b->device);
@@ -1314,9 +1353,9 @@ void ibm_lb_batch_destroy(ibm_lb_batch* b) {
     if (b->stage) (void)hipHostFree(b->stage);
     if (b->Atab) (void)hipFree(b->Atab);
     if (b->lat_desc) (void)hipFree(b->lat_desc);
-    if (b->lat_start) (void)hipFree(b->lat_start);
+    if (b->lat_map) (void)hipFree(b->lat_map);
     if (b->ib_args) (void)hipFree(b->ib_args);
-    if (b->patch_start) (void)hipFree(b->patch_start);
+    if (b->patch_map) (void)hipFree(b->patch_map);
     for (ibm_lb* h : b->m) ibm_lb_destroy(h);
     delete b;
 }

@@ -449,8 +449,11 @@ __device__ void hc_finish(const IbArgs<R>& a);
 // pass computing every p' and b followed by a pass computing every p.
 constexpr int HALO_CAP = MAXV * PATCH;  // no patch can have more halo vertices
 
+// defer: when iteration 1 did not converge, leave the further iterations to
+// k_hc_finish_batch (the reduction slots keep the maximum and the arrival
+// count, which tells that kernel to run) instead of running them here.
 template <class R>
-__device__ void hc_fused(const IbArgs<R>& a, int p, int npatch) {
+__device__ void hc_fused(const IbArgs<R>& a, int p, int npatch, bool defer) {
     __shared__ V4<R> sb[PATCH + HALO_CAP];
     __shared__ V4<R> spp[PATCH], so[PATCH];
     __shared__ R bred[IBT / 64];
@@ -518,12 +521,13 @@ __device__ void hc_fused(const IbArgs<R>& a, int p, int npatch) {
     __syncthreads();
     if (!last) return;
     __threadfence();
+    if (defer && on && a.sp.max_iter > 1 && !(from_bits<R>(a.red[0]) < R(a.sp.tol))) return;
     hc_finish(a);
 }
 
 template <class R>
 __global__ __launch_bounds__(IBT) void k_hc_fused(IbArgs<R> a, int npatch) {
-    hc_fused(a, blockIdx.x, npatch);
+    hc_fused(a, blockIdx.x, npatch, false);
 }
 
 // One work-group, after iteration 1 is in qa and its maximum in the
@@ -585,41 +589,42 @@ __device__ void hc_finish(const IbArgs<R>& a) {
 }
 
 // ---------------------------------------------------------------- ensemble forms
-// Work-group b of a batched launch belongs to the member d with
-// start[d] <= b < start[d+1] (start: patch offsets, one patch = PATCH vertices).
-__device__ inline int member_of(const int* __restrict__ start, int ndrop, int b) {
-    int lo = 0, hi = ndrop;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (start[mid] <= b) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
+// Work-group b of a batched launch takes patch map[b].y of member map[b].x.
 template <class R>
 __global__ __launch_bounds__(IBT) void k_interp_batch(const IbArgs<R>* __restrict__ args,
-                                                       const int* __restrict__ start, int ndrop) {
+                                                       const int2* __restrict__ map) {
     extern __shared__ __align__(16) unsigned char dyn[];
-    const int d = member_of(start, ndrop, blockIdx.x);
-    interp_patch(args[d], blockIdx.x - start[d], reinterpret_cast<R*>(dyn));
+    const int2 e = map[blockIdx.x];
+    interp_patch(args[e.x], e.y, reinterpret_cast<R*>(dyn));
 }
 
 template <class R>
 __global__ __launch_bounds__(IBT) void k_hc_fused_batch(const IbArgs<R>* __restrict__ args,
-                                                        const int* __restrict__ start, int ndrop) {
-    const int d = member_of(start, ndrop, blockIdx.x);
-    hc_fused(args[d], blockIdx.x - start[d], start[d + 1] - start[d]);
+                                                        const int2* __restrict__ map) {
+    const int2 e = map[blockIdx.x];
+    const IbArgs<R>& a = args[e.x];
+    hc_fused(a, e.y, (a.nv + PATCH - 1) / PATCH, true);
+}
+
+// One work-group per member: the members whose iteration 1 did not converge
+// (their arrival count was left in the second reduction slot) run the further
+// iterations here with 1024 threads; the others have finished already.
+template <class R>
+__global__ __launch_bounds__(1024) void k_hc_finish_batch(const IbArgs<R>* __restrict__ args) {
+    const IbArgs<R>& a = args[blockIdx.x];
+    if (a.nv == 0 || a.red[1] == 0ull) return;
+    hc_finish(a);
 }
 
 template <class R>
-__global__ __launch_bounds__(IBT) void k_fs_batch(const IbArgs<R>* __restrict__ args, const int* __restrict__ start,
-                                                   int ndrop, int commit) {
+__global__ __launch_bounds__(IBT) void k_fs_batch(const IbArgs<R>* __restrict__ args, const int2* __restrict__ map,
+                                                   int commit) {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ Stage<R> st;
-    const int d = member_of(start, ndrop, blockIdx.x);
-    const IbArgs<R>& a = args[d];
+    const int2 e = map[blockIdx.x];
+    const IbArgs<R>& a = args[e.x];
     const V4<R>* P = commit ? (a.sp.max_iter > 0 ? a.qa : a.o) : a.r;
-    fs_patch(a, blockIdx.x - start[d], P, commit, st, reinterpret_cast<double*>(dyn));
+    fs_patch(a, e.y, P, commit, st, reinterpret_cast<double*>(dyn));
 }
 
 // ---------------------------------------------------------------- launchers
@@ -703,29 +708,31 @@ void fill_ib_args(int storage, const Geom& g, const DevPtrs& d, int nv, double s
 }
 
 template <class R>
-static hipError_t batch_step_t(const void* args, const int* start, int ndrop, int npatch_total, hipStream_t s) {
+static hipError_t batch_step_t(const void* args, const int2* map, int npatch_total, int ndrop, hipStream_t s) {
+    if (npatch_total == 0) return hipSuccess;  // no member carries a droplet
     const IbArgs<R>* a = (const IbArgs<R>*)args;
     hipLaunchKernelGGL(k_interp_batch<R>, dim3(npatch_total), dim3(IBT), dyn_lds(sizeof(R) == 8 ? IBM_LB_F64 : IBM_LB_F32),
-                       s, a, start, ndrop);
-    hipLaunchKernelGGL(k_hc_fused_batch<R>, dim3(npatch_total), dim3(IBT), 0, s, a, start, ndrop);
-    hipLaunchKernelGGL(k_fs_batch<R>, dim3(npatch_total), dim3(IBT), dyn_lds_spread(), s, a, start, ndrop, 1);
+                       s, a, map);
+    hipLaunchKernelGGL(k_hc_fused_batch<R>, dim3(npatch_total), dim3(IBT), 0, s, a, map);
+    hipLaunchKernelGGL(k_hc_finish_batch<R>, dim3(ndrop), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_fs_batch<R>, dim3(npatch_total), dim3(IBT), dyn_lds_spread(), s, a, map, 1);
     return hipGetLastError();
 }
 
-hipError_t launch_ib_step_batch(int storage, const void* args, const int* start, int ndrop, int npatch_total,
+hipError_t launch_ib_step_batch(int storage, const void* args, const int2* map, int npatch_total, int ndrop,
                                 hipStream_t s) {
-    if (storage == IBM_LB_F64) return batch_step_t<double>(args, start, ndrop, npatch_total, s);
-    return batch_step_t<float>(args, start, ndrop, npatch_total, s);
+    if (storage == IBM_LB_F64) return batch_step_t<double>(args, map, npatch_total, ndrop, s);
+    return batch_step_t<float>(args, map, npatch_total, ndrop, s);
 }
 
-hipError_t launch_ib_pre_batch(int storage, const void* args, const int* start, int ndrop, int npatch_total,
-                               hipStream_t s) {
+hipError_t launch_ib_pre_batch(int storage, const void* args, const int2* map, int npatch_total, hipStream_t s) {
+    if (npatch_total == 0) return hipSuccess;
     if (storage == IBM_LB_F64)
         hipLaunchKernelGGL(k_fs_batch<double>, dim3(npatch_total), dim3(IBT), dyn_lds_spread(), s,
-                           (const IbArgs<double>*)args, start, ndrop, 0);
+                           (const IbArgs<double>*)args, map, 0);
     else
         hipLaunchKernelGGL(k_fs_batch<float>, dim3(npatch_total), dim3(IBT), dyn_lds_spread(), s,
-                           (const IbArgs<float>*)args, start, ndrop, 0);
+                           (const IbArgs<float>*)args, map, 0);
     return hipGetLastError();
 }
 

@@ -113,17 +113,31 @@ constexpr int OBS_OUT_N = 48;
 // hipError_t of the launch.
 hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                        const double* A0, int rest, hipStream_t s);
-// variant: bit 0 = non-temporal population loads, bits 1-2 = work-group size
-// LAT_BS[variant >> 1].
-constexpr int LATTICE_VARIANTS = 8;
+// Lattice-kernel variant: bit 0 = non-temporal population loads; bits 1-2 =
+// work-group size LAT_BS[(variant >> 1) & 3] (rows layout: the least number
+// of whole x-rows, at least one, that fits in it); bit 4 (VAR_ROWS) = row
+// layout; bit 3 (VAR_X) = XCD-grouped block order in the linear layout,
+// non-temporal population stores in the row layout.
+constexpr int LATTICE_VARIANTS = 32;
 constexpr int LAT_BS[4] = {128, 256, 512, 64};
+constexpr int VAR_X = 8;
+constexpr int VAR_ROWS = 16;
+// Rows per work-group of a row-layout variant for rows of Lx nodes; 0 when
+// the variant is not a row layout or Lx exceeds the largest work-group.
+int lattice_rows_per_block(int variant, int Lx);
+// Whether the variant can run on this lattice.
+int lattice_variant_ok(int variant, const Geom& g);
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, hipStream_t s);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
-// start: member block offsets [4][ndrop + 1], one table per work-group size
-// LAT_BS[i]; nblocks[i] the total block count of table i.
-hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int* start, int ndrop, const int nblocks[4],
-                                int cur, long long step, int variant, hipStream_t s);
+// maps: eight block maps, concatenated (table q from entry moff[q],
+// nblocks[q] entries; entry b = {member, block index within the member}).
+// Tables 0-3: linear layout with LAT_BS[q]-node blocks; tables 4-7: row
+// layout with work-groups of LAT_BS[q - 4] threads, each member taking
+// floor(LAT_BS[q - 4] / Lx) whole rows per block (nblocks[q] = -1 when a
+// member's rows exceed that size).
+hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* maps, const int moff[8],
+                                const int nblocks[8], int cur, long long step, int variant, hipStream_t s);
 hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, double* rho_out, double* u_out, hipStream_t s);
 hipError_t launch_observables(int storage, const Geom& g, const LatticeParams& lp,
@@ -145,14 +159,13 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
 hipError_t launch_ib_step(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
                           const SmoothParams& sp, hipStream_t s);
 // Ensemble forms: args is a device array of per-member IB argument records
-// (ib_args_bytes each, filled by fill_ib_args), start the members' patch
-// offsets [ndrop + 1].
+// (ib_args_bytes each, filled by fill_ib_args), map the patch map
+// [npatch_total] (entry b = {member, patch index within the member}).
 size_t ib_args_bytes(int storage);
 void fill_ib_args(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma, const SmoothParams& sp,
                   void* out);
-hipError_t launch_ib_pre_batch(int storage, const void* args, const int* start, int ndrop, int npatch_total,
-                               hipStream_t s);
-hipError_t launch_ib_step_batch(int storage, const void* args, const int* start, int ndrop, int npatch_total,
+hipError_t launch_ib_pre_batch(int storage, const void* args, const int2* map, int npatch_total, hipStream_t s);
+hipError_t launch_ib_step_batch(int storage, const void* args, const int2* map, int npatch_total, int ndrop,
                                 hipStream_t s);
 hipError_t launch_clear_force(int storage, const Geom& g, const DevPtrs& d, hipStream_t s);
 

@@ -54,18 +54,58 @@ __global__ __launch_bounds__(256) void k_init(Geom g, LatticeParams lp, typename
 // post-collision population to its neighbour. A population whose target lies
 // beyond a wall is reflected into the opposite slot of the same node with
 // the moving-wall term -2 w_i rho0 c_i.u_w / cs^2, u_w = A (x + c_i/2 - x_c).
-// Variants (chosen per configuration by the autotuner): non-temporal
-// population loads (pays when the two population copies fit the
-// last-level cache) and the work-group size.
-template <class C, bool IB, bool NTL>
+//
+// Two store layouts, chosen per configuration by the autotuner:
+//   * linear (k_lattice): work-group b owns nodes [b BS, (b+1) BS) and writes
+//     every population straight to its target; the ten populations that move
+//     along x land one element off the thread's own node, so their stores
+//     straddle cache lines shared with the neighbouring work-group. Optional
+//     XCD grouping gives each XCD a contiguous range of the lattice, so that
+//     such shared lines meet in one L2 (pays when the two population copies
+//     nearly fit the last-level cache);
+//   * rows (k_lattice_rows): a work-group owns whole x-rows; the populations
+//     that move along x are handed to their target thread through LDS, so
+//     every global store is at the storing thread's own x (row-aligned).
+//     Pays for footprints well beyond the last-level cache.
+// Further options: non-temporal population loads, non-temporal population
+// stores (rows) and the work-group size.
+
+// Rank of population i among the ten that move along x (their LDS slot).
+__host__ __device__ constexpr int xslot(int i) {
+    int k = 0;
+    for (int j = 0; j < i; ++j) k += CX[j] != 0 ? 1 : 0;
+    return k;
+}
+constexpr int NXMOVE = xslot(Q);
+
+// Block order grouped by XCD: consecutive work-groups are dispatched to the
+// eight XCDs in turn; this sends the first eighth of the lattice to XCD 0,
+// the next eighth to XCD 1, and so on (a tail of nb mod 8 blocks keeps its
+// place).
+__device__ inline unsigned xcd_order(unsigned b, unsigned nb) {
+    const unsigned per = nb >> 3;
+    return b < (per << 3) ? (b & 7u) * per + (b >> 3) : b;
+}
+
+template <class S, bool NTS>
+__device__ __forceinline__ void put(S* p, S v) {
+    if (NTS) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// ROWS: x-moving populations that stay in the box go to stage[xslot(i) T + t]
+// instead of global memory (t: the thread's slot, T: slots per plane).
+template <class C, bool IB, bool NTL, bool ROWS, bool NTS>
 __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp,
                                              const typename C::store_t* __restrict__ fin,
                                              typename C::store_t* __restrict__ fout,
                                              typename C::real* __restrict__ F,
                                              typename C::real* __restrict__ U,
                                              const int* __restrict__ mark, Ctl* ctl,
-                                             const double* __restrict__ Arow, const long long n) {
+                                             const double* __restrict__ Arow, const long long n,
+                                             typename C::store_t* stage, int t, int T) {
     using R = typename C::real;
+    using S = typename C::store_t;
     const long long N = g.N;
     const int LxLy = g.Lx * g.Ly;
     const int z = int(n / LxLy);
@@ -142,22 +182,23 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
             if (g.pz) tz = wrap(tz, g.Lz); else wall = true;
         }
         if (!wall) {
-            fout[i * N + tx + (long long)g.Lx * (ty + (long long)g.Ly * tz)] = enc<C>(val, lp.scale);
+            if (ROWS && CX[i] != 0) stage[xslot(i) * T + t] = enc<C>(val, lp.scale);
+            else put<S, NTS>(&fout[i * N + tx + (long long)g.Lx * (ty + (long long)g.Ly * tz)], enc<C>(val, lp.scale));
         } else {
             const R wx = xr + R(0.5) * R(CX[i]), wy = yr + R(0.5) * R(CY[i]), wz = zr + R(0.5) * R(CZ[i]);
             const R uwx = A[0] * wx + A[1] * wy + A[2] * wz;
             const R uwy = A[3] * wx + A[4] * wy + A[5] * wz;
             const R uwz = A[6] * wx + A[7] * wy + A[8] * wz;
             const R cuw = R(CX[i]) * uwx + R(CY[i]) * uwy + R(CZ[i]) * uwz;
-            fout[opp(i) * N + n] = enc<C>(val - R(6) * wgt<R>(i) * rho0 * cuw, lp.scale);
+            put<S, NTS>(&fout[opp(i) * N + n], enc<C>(val - R(6) * wgt<R>(i) * rho0 * cuw, lp.scale));
         }
     };
 
     {   // rest population
         const R w = wgt<R>(0);
         const R deq = w * (drho + rho * (R(-1.5) * usq));
-        const R S = kg * w * (R(-3) * uF);
-        fout[n] = enc<C>(d[0] - omega * (d[0] - deq) + S, lp.scale);
+        const R S0 = kg * w * (R(-3) * uF);
+        put<S, NTS>(&fout[n], enc<C>(d[0] - omega * (d[0] - deq) + S0, lp.scale));
     }
 #pragma unroll
     for (int p = 1; p <= 9; ++p) {
@@ -174,6 +215,43 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
     }
 }
 
+// Second half of the row layout: thread t (node n, coordinates x, y, z)
+// stores, at its own x, every x-moving population arriving from x - c_x in
+// its row (x - c_x wrapped on a periodic axis; nothing arrives through a
+// wall, and nothing whose row shift crosses a wall, both having been
+// reflected at the source).
+template <class C, bool NTS>
+__device__ __forceinline__ void rows_receive(const Geom& g, typename C::store_t* __restrict__ fout,
+                                             const typename C::store_t* stage, long long n, int t, int T) {
+    const long long N = g.N;
+    const int LxLy = g.Lx * g.Ly;
+    const int z = int(n / LxLy);
+    const int rem = int(n - (long long)z * LxLy);
+    const int y = rem / g.Lx;
+    const int x = rem - y * g.Lx;
+    const int row0 = t - x;  // slot of x = 0 in this row
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (CX[i] == 0) continue;
+        int xs = x - CX[i];
+        if (xs < 0 || xs >= g.Lx) {
+            if (!g.px) continue;
+            xs = wrap(xs, g.Lx);
+        }
+        int ty = y + CY[i], tz = z + CZ[i];
+        if (CY[i] != 0 && (ty < 0 || ty >= g.Ly)) {
+            if (!g.py) continue;
+            ty = wrap(ty, g.Ly);
+        }
+        if (CZ[i] != 0 && (tz < 0 || tz >= g.Lz)) {
+            if (!g.pz) continue;
+            tz = wrap(tz, g.Lz);
+        }
+        put<typename C::store_t, NTS>(&fout[i * N + x + (long long)g.Lx * (ty + (long long)g.Ly * tz)],
+                                      stage[xslot(i) * T + row0 + xs]);
+    }
+}
+
 template <class C, bool IB, bool NTL, int BS>
 __global__ __launch_bounds__(BS) void k_lattice(Geom g, LatticeParams lp,
                                                  const typename C::store_t* __restrict__ fin,
@@ -181,35 +259,84 @@ __global__ __launch_bounds__(BS) void k_lattice(Geom g, LatticeParams lp,
                                                  typename C::real* __restrict__ F,
                                                  typename C::real* __restrict__ U,
                                                  const int* __restrict__ mark, Ctl* ctl,
-                                                 const double* __restrict__ Arow) {
-    const long long n = (long long)blockIdx.x * BS + threadIdx.x;
-    if (n < g.N) lattice_node<C, IB, NTL>(g, lp, fin, fout, F, U, mark, ctl, Arow, n);
+                                                 const double* __restrict__ Arow, int xcd) {
+    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    const long long n = (long long)b * BS + threadIdx.x;
+    if (n < g.N)
+        lattice_node<C, IB, NTL, false, false>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, nullptr, 0, 0);
 }
 
-// Ensemble form: one launch covers every member's lattice; work-group b
-// belongs to the member whose block range [start[d], start[d+1]) holds b.
+// Row layout: `rows` whole x-rows per work-group (blockDim = rows * Lx <= 512).
+constexpr int ROWS_MAX_T = 512;
+
+template <class C, bool IB, bool NTL, bool NTS>
+__global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticeParams lp,
+                                                             const typename C::store_t* __restrict__ fin,
+                                                             typename C::store_t* __restrict__ fout,
+                                                             typename C::real* __restrict__ F,
+                                                             typename C::real* __restrict__ U,
+                                                             const int* __restrict__ mark, Ctl* ctl,
+                                                             const double* __restrict__ Arow, int rows) {
+    using S = typename C::store_t;
+    extern __shared__ __align__(16) unsigned char dyn[];
+    S* stage = reinterpret_cast<S*>(dyn);
+    const int T = rows * g.Lx;
+    const int t = threadIdx.x;
+    const long long n = (long long)blockIdx.x * T + t;
+    const bool act = n < g.N;
+    if (act) lattice_node<C, IB, NTL, true, NTS>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, stage, t, T);
+    __syncthreads();
+    if (act) rows_receive<C, NTS>(g, fout, stage, n, t, T);
+}
+
+// Ensemble forms: one launch covers every member's lattice; work-group b
+// updates block map[b].y of member map[b].x (linear: BS nodes per block;
+// rows: floor(blockDim / Lx) whole rows of that member per block).
 template <class C, bool NTL, int BS>
-__global__ __launch_bounds__(BS) void k_lattice_batch(const LatDesc* __restrict__ desc,
-                                                       const int* __restrict__ start, int ndrop, int cur,
-                                                       long long arow) {
+__global__ __launch_bounds__(BS) void k_lattice_batch(const LatDesc* __restrict__ desc, const int2* __restrict__ map,
+                                                       int cur, long long arow, int xcd) {
     using R = typename C::real;
     using S = typename C::store_t;
-    const int b = blockIdx.x;
-    int lo = 0, hi = ndrop;  // largest d with start[d] <= b
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (start[mid] <= b) lo = mid; else hi = mid;
-    }
-    const LatDesc& D = desc[lo];
-    const long long n = (long long)(b - start[lo]) * BS + threadIdx.x;
+    const int2 e = map[xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x];
+    const LatDesc& D = desc[e.x];
+    const long long n = (long long)e.y * BS + threadIdx.x;
     if (n >= D.g.N) return;
     const double* Arow = D.A + arow;
     if (D.ib)
-        lattice_node<C, true, NTL>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F, (R*)D.u, D.mark,
-                                   D.ctl, Arow, n);
+        lattice_node<C, true, NTL, false, false>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F,
+                                                 (R*)D.u, D.mark, D.ctl, Arow, n, nullptr, 0, 0);
     else
-        lattice_node<C, false, NTL>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F, (R*)D.u, D.mark,
-                                    D.ctl, Arow, n);
+        lattice_node<C, false, NTL, false, false>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F,
+                                                  (R*)D.u, D.mark, D.ctl, Arow, n, nullptr, 0, 0);
+}
+
+template <class C, bool NTL, bool NTS>
+__global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows_batch(const LatDesc* __restrict__ desc,
+                                                                   const int2* __restrict__ map, int cur,
+                                                                   long long arow) {
+    using R = typename C::real;
+    using S = typename C::store_t;
+    extern __shared__ __align__(16) unsigned char dyn[];
+    S* stage = reinterpret_cast<S*>(dyn);
+    const int2 e = map[blockIdx.x];
+    const LatDesc& D = desc[e.x];
+    const int T = (int(blockDim.x) / D.g.Lx) * D.g.Lx;
+    const int t = threadIdx.x;
+    const long long n = (long long)e.y * T + t;
+    const bool act = t < T && n < D.g.N;
+    const double* Arow = D.A + arow;
+    const S* fin = (const S*)D.f[cur];
+    S* fout = (S*)D.f[cur ^ 1];
+    if (act) {
+        if (D.ib)
+            lattice_node<C, true, NTL, true, NTS>(D.g, D.lp, fin, fout, (R*)D.F, (R*)D.u, D.mark, D.ctl, Arow, n,
+                                                  stage, t, T);
+        else
+            lattice_node<C, false, NTL, true, NTS>(D.g, D.lp, fin, fout, (R*)D.F, (R*)D.u, D.mark, D.ctl, Arow,
+                                                   n, stage, t, T);
+    }
+    __syncthreads();
+    if (act) rows_receive<C, NTS>(D.g, fout, stage, n, t, T);
 }
 
 // Diagnostic moments: rho and u (with F/2) of the current populations; the
@@ -506,26 +633,59 @@ hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, cons
 
 template <class C, bool IB, bool NTL, int BS>
 static void lattice_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                           hipStream_t s) {
+                           int xcd, hipStream_t s) {
     using R = typename C::real;
     using S = typename C::store_t;
     hipLaunchKernelGGL((k_lattice<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, g, lp,
-                       (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row);
+                       (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row, xcd);
+}
+
+template <class C, bool IB, bool NTL, bool NTS>
+static void rows_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
+                        int rows, hipStream_t s) {
+    using R = typename C::real;
+    using S = typename C::store_t;
+    const int T = rows * g.Lx;
+    const long long nrows = (long long)g.Ly * g.Lz;
+    const unsigned nb = unsigned((nrows + rows - 1) / rows);
+    hipLaunchKernelGGL((k_lattice_rows<C, IB, NTL, NTS>), dim3(nb), dim3(T), size_t(NXMOVE) * T * sizeof(S), s, g,
+                       lp, (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row, rows);
+}
+
+int lattice_rows_per_block(int variant, int Lx) {
+    if (!(variant & VAR_ROWS) || Lx < 1 || Lx > ROWS_MAX_T) return 0;
+    const int want = LAT_BS[(variant >> 1) & 3];
+    const int r = want / Lx;
+    return r < 1 ? 1 : r;
+}
+
+int lattice_variant_ok(int variant, const Geom& g) {
+    if (variant < 0 || variant >= LATTICE_VARIANTS) return 0;
+    if (variant & VAR_ROWS) return lattice_rows_per_block(variant, g.Lx) > 0;
+    return 1;
 }
 
 template <class C, bool IB, bool NTL>
 static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
                              const double* A_row, hipStream_t s) {
+    if (variant & VAR_ROWS) {
+        const int rows = lattice_rows_per_block(variant, g.Lx);
+        if (variant & VAR_X) rows_launch<C, IB, NTL, true>(g, lp, d, cur, A_row, rows, s);
+        else rows_launch<C, IB, NTL, false>(g, lp, d, cur, A_row, rows, s);
+        return;
+    }
+    const int xcd = (variant & VAR_X) ? 1 : 0;
     switch ((variant >> 1) & 3) {
-        case 0: lattice_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, s); break;
-        case 1: lattice_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, s); break;
-        case 2: lattice_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, s); break;
-        default: lattice_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, s); break;
+        case 0: lattice_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, s); break;
+        case 1: lattice_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, s); break;
+        case 2: lattice_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, s); break;
+        default: lattice_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, s); break;
     }
 }
 
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, hipStream_t s) {
+    if (!lattice_variant_ok(variant, g)) return hipErrorInvalidValue;
     DISPATCH_STORAGE(storage, C, {
         if (ib) {
             if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, s);
@@ -539,35 +699,58 @@ hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, c
 }
 
 template <class C, bool NTL>
-static void launch_batch_v(int bsi, const LatDesc* desc, const int* start, int ndrop, const int nblocks[4], int cur,
-                           long long step, hipStream_t s) {
-    const int* st = start + bsi * (ndrop + 1);
+static void launch_batch_v(int bsi, const LatDesc* desc, const int2* map, int nblocks, int cur, long long step,
+                           int xcd, hipStream_t s) {
     switch (bsi) {
         case 0:
-            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[0]>), dim3(nblocks[0]), dim3(LAT_BS[0]), 0, s, desc, st,
-                               ndrop, cur, step);
+            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[0]>), dim3(nblocks), dim3(LAT_BS[0]), 0, s, desc, map,
+                               cur, step, xcd);
             break;
         case 1:
-            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[1]>), dim3(nblocks[1]), dim3(LAT_BS[1]), 0, s, desc, st,
-                               ndrop, cur, step);
+            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[1]>), dim3(nblocks), dim3(LAT_BS[1]), 0, s, desc, map,
+                               cur, step, xcd);
             break;
         case 2:
-            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[2]>), dim3(nblocks[2]), dim3(LAT_BS[2]), 0, s, desc, st,
-                               ndrop, cur, step);
+            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[2]>), dim3(nblocks), dim3(LAT_BS[2]), 0, s, desc, map,
+                               cur, step, xcd);
             break;
         default:
-            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[3]>), dim3(nblocks[3]), dim3(LAT_BS[3]), 0, s, desc, st,
-                               ndrop, cur, step);
+            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[3]>), dim3(nblocks), dim3(LAT_BS[3]), 0, s, desc, map,
+                               cur, step, xcd);
             break;
     }
 }
 
-hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int* start, int ndrop, const int nblocks[4],
-                                int cur, long long step, int variant, hipStream_t s) {
+template <class C, bool NTL, bool NTS>
+static void launch_rows_batch(int T, const LatDesc* desc, const int2* map, int nblocks, int cur, long long step,
+                              hipStream_t s) {
+    using S = typename C::store_t;
+    hipLaunchKernelGGL((k_lattice_rows_batch<C, NTL, NTS>), dim3(nblocks), dim3(T), size_t(NXMOVE) * T * sizeof(S),
+                       s, desc, map, cur, step);
+}
+
+hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* maps, const int moff[8],
+                                const int nblocks[8], int cur, long long step, int variant, hipStream_t s) {
+    if (variant < 0 || variant >= LATTICE_VARIANTS) return hipErrorInvalidValue;
     const int bsi = (variant >> 1) & 3;
+    const int xb = variant & VAR_X ? 1 : 0;
+    if (variant & VAR_ROWS) {
+        const int q = 4 + bsi;
+        if (nblocks[q] <= 0) return hipErrorInvalidValue;
+        DISPATCH_STORAGE(storage, C, {
+            if (variant & 1) {
+                if (xb) launch_rows_batch<C, true, true>(LAT_BS[bsi], desc, maps + moff[q], nblocks[q], cur, step, s);
+                else launch_rows_batch<C, true, false>(LAT_BS[bsi], desc, maps + moff[q], nblocks[q], cur, step, s);
+            } else {
+                if (xb) launch_rows_batch<C, false, true>(LAT_BS[bsi], desc, maps + moff[q], nblocks[q], cur, step, s);
+                else launch_rows_batch<C, false, false>(LAT_BS[bsi], desc, maps + moff[q], nblocks[q], cur, step, s);
+            }
+        });
+        return hipGetLastError();
+    }
     DISPATCH_STORAGE(storage, C, {
-        if (variant & 1) launch_batch_v<C, true>(bsi, desc, start, ndrop, nblocks, cur, step, s);
-        else launch_batch_v<C, false>(bsi, desc, start, ndrop, nblocks, cur, step, s);
+        if (variant & 1) launch_batch_v<C, true>(bsi, desc, maps + moff[bsi], nblocks[bsi], cur, step, xb, s);
+        else launch_batch_v<C, false>(bsi, desc, maps + moff[bsi], nblocks[bsi], cur, step, xb, s);
     });
     return hipGetLastError();
 }

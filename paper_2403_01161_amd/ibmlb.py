@@ -54,10 +54,11 @@ class Obs(C.Structure):
 
 EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_table",
            "ibm_lb_observables", "ibm_lb_read_vertices", "ibm_lb_read_field",
-           "ibm_lb_state_bytes", "ibm_lb_save", "ibm_lb_load", "ibm_lb_autotune", "ibm_lb_timing_enable",
+           "ibm_lb_state_bytes", "ibm_lb_save", "ibm_lb_load", "ibm_lb_autotune", "ibm_lb_set_variant",
+           "ibm_lb_timing_enable",
            "ibm_lb_timing_read", "ibm_lb_destroy", "ibm_lb_strerror", "ibm_lb_last_error",
            "ibm_lb_batch_init", "ibm_lb_batch_step", "ibm_lb_batch_observables", "ibm_lb_batch_member",
-           "ibm_lb_batch_autotune", "ibm_lb_batch_destroy", "ibm_lb_objective_grad",
+           "ibm_lb_batch_autotune", "ibm_lb_batch_set_variant", "ibm_lb_batch_destroy", "ibm_lb_objective_grad",
            "ibm_lb_adjoint_segment"]
 
 
@@ -81,6 +82,7 @@ def lib():
         L.ibm_lb_save.argtypes = [vp, vp, C.c_size_t]
         L.ibm_lb_load.argtypes = [vp, vp, C.c_size_t]
         L.ibm_lb_autotune.argtypes = [vp, i32, C.POINTER(C.c_int32)]
+        L.ibm_lb_set_variant.argtypes = [vp, i32]
         L.ibm_lb_timing_enable.argtypes = [vp, i32]
         L.ibm_lb_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
         L.ibm_lb_destroy.argtypes = [vp]
@@ -90,6 +92,7 @@ def lib():
         L.ibm_lb_batch_observables.argtypes = [vp, C.POINTER(Obs)]
         L.ibm_lb_batch_member.argtypes = [vp, i32, C.POINTER(vp)]
         L.ibm_lb_batch_autotune.argtypes = [vp, i32, C.POINTER(C.c_int32)]
+        L.ibm_lb_batch_set_variant.argtypes = [vp, i32]
         L.ibm_lb_batch_destroy.argtypes = [vp]
         L.ibm_lb_batch_destroy.restype = None
         L.ibm_lb_objective_grad.argtypes = [vp, dp, vp]
@@ -245,6 +248,10 @@ class Simulation:
         _check(lib().ibm_lb_autotune(self._h, int(reps), C.byref(v)), "ibm_lb_autotune")
         return v.value
 
+    def set_variant(self, variant):
+        """Select a lattice-kernel variant directly (0 <= variant < 32)."""
+        _check(lib().ibm_lb_set_variant(self._h, int(variant)), "ibm_lb_set_variant")
+
     def timing(self, enable=True):
         _check(lib().ibm_lb_timing_enable(self._h, int(enable)), "ibm_lb_timing_enable")
 
@@ -301,10 +308,13 @@ class _Member:
     def __init__(self, ens, h, L, nv):
         self._ens, self._h, self.L, self.nv = ens, h, L, nv
         self.N = int(np.prod(L))
+        self.device = ens.device
 
     observables = Simulation.observables
     vertices = Simulation.vertices
     fields = Simulation.fields
+    state_bytes = Simulation.state_bytes
+    save = Simulation.save
 
 
 class Ensemble:
@@ -352,6 +362,9 @@ class Ensemble:
         v = C.c_int32()
         _check(lib().ibm_lb_batch_autotune(self._h, int(reps), C.byref(v)), "ibm_lb_batch_autotune")
         return v.value
+
+    def set_variant(self, variant):
+        _check(lib().ibm_lb_batch_set_variant(self._h, int(variant)), "ibm_lb_batch_set_variant")
 
     def step(self, A_tables):
         """A_tables: host array [n, nsteps, 9]."""

@@ -1,0 +1,137 @@
+"""GPU: every lattice-kernel variant computes the same step.
+
+The variants differ only in how nodes map to work-groups (linear blocks, an
+XCD-grouped block order, whole x-rows per work-group with the x-moving
+populations exchanged through LDS) and in cache hints, never in the per-node
+arithmetic. Without a droplet the step has no atomics, so every variant must
+reproduce the default variant's state bit for bit, on boxes with walls,
+periodic axes, rows longer than a work-group and ragged last work-groups.
+With a droplet, a few variants are checked against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_01161_amd.inputs import box_center, icosphere
+
+pytestmark = pytest.mark.gpu
+
+NVAR = 32
+ROWS = 16
+BS = (128, 256, 512, 64)
+
+
+@pytest.fixture(scope="module")
+def ib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_01161_amd import ibmlb
+    ibmlb.lib()
+    return ibmlb
+
+
+def _traceless(scale, seed):
+    A = np.random.default_rng(seed).standard_normal((3, 3))
+    A -= np.trace(A) / 3 * np.eye(3)
+    return (scale * A / np.linalg.norm(A)).ravel()
+
+
+def _row_ok(v, Lx):
+    return not (v & ROWS) or Lx <= 512
+
+
+def _state_after(ib, L, periodic, storage, variant, A, nsteps):
+    sim = ib.Simulation(L, tau=0.8, periodic=periodic, storage=storage, A0=A, init="linear")
+    sim.set_variant(variant)
+    sim.step(A, nsteps)
+    out = sim.save().cpu().numpy().copy()
+    sim.close()
+    return out
+
+
+BOXES = [((13, 9, 11), (0, 0, 0)),     # odd sizes, walls on every side
+         ((16, 12, 10), (1, 0, 0)),    # periodic along x (rows wrap through LDS)
+         ((40, 8, 9), (1, 0, 1)),      # several rows per work-group, ragged tail
+         ((130, 8, 8), (0, 1, 0)),     # a row longer than 128 threads
+         ((8, 8, 8), (1, 1, 1))]       # fully periodic
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16dev"])
+@pytest.mark.parametrize("L,periodic", BOXES)
+def test_lattice_variants_bit_identical(ib, storage, L, periodic):
+    A = _traceless(2e-3, 7) if not all(periodic) else np.zeros(9)
+    print(f"case L={L} periodic={periodic} storage={storage}", flush=True)
+    ref = _state_after(ib, L, periodic, storage, 1, A, 7)
+    for v in range(NVAR):
+        if not _row_ok(v, L[0]):
+            continue
+        got = _state_after(ib, L, periodic, storage, v, A, 7)
+        assert np.array_equal(got, ref), f"variant {v} differs from variant 1"
+
+
+def test_row_layout_rejects_long_rows(ib):
+    sim = ib.Simulation((520, 8, 8), tau=0.8, storage="f32", init="rest")
+    with pytest.raises(ib.IbmLbError):
+        sim.set_variant(ROWS | 1)
+    sim.set_variant(8 | 1)  # linear layouts take any row length
+    sim.step(np.zeros(9), 2)
+    sim.close()
+    with pytest.raises(ib.IbmLbError):
+        ib.Simulation((8, 8, 8), tau=0.8, storage="f32").set_variant(NVAR)
+
+
+@pytest.mark.parametrize("variant", [1, 9, ROWS | 1, ROWS | 8, ROWS | 4 | 8 | 1, ROWS | 6])
+def test_droplet_variants_match_oracle(ib, variant):
+    L = (19, 17, 21)
+    A = _traceless(3e-3, 2)
+    V, T = icosphere(2, 3.2, box_center(L))
+    kw = dict(tau=0.9, sigma=0.02, radius=3.2, vertices=V, triangles=T, A0=A)
+    print(f"case droplet L={L} variant={variant}", flush=True)
+    sim = ib.Simulation(L, storage="f64", **kw)
+    sim.set_variant(variant)
+    ref = oracle.Oracle(L, **kw)
+    sim.step(A, 30)
+    ref.step(A, 30)
+    dr = np.abs(sim.vertices() - ref.vertices()).max()
+    rho_g, u_g = sim.fields()
+    rho_r, u_r = ref.fields()
+    du = np.abs(u_g - u_r).max() / np.abs(u_r).max()
+    assert dr <= 1e-11, f"max |dr| = {dr:.3e}"
+    assert du <= 1e-11, f"max|du|/max|u| = {du:.3e}"
+    assert np.abs(rho_g - rho_r).max() <= 1e-13
+    sim.close()
+
+
+def _ensemble_states(ib, members, tabs, variant):
+    ens = ib.Ensemble(members, storage="f32")
+    ens.set_variant(variant)
+    ens.step(tabs)
+    out = [ens.member(i).save().cpu().numpy().copy() for i in range(len(members))]
+    ens.close()
+    return out
+
+
+def test_ensemble_variants_bit_identical(ib):
+    # lattice-only members of mixed sizes and periodicity: rows of 48, 20,
+    # 96 and 9 nodes, so the row layout packs different row counts per
+    # work-group for each member
+    specs = [((48, 8, 9), (0, 0, 0)), ((20, 14, 9), (1, 0, 0)), ((96, 8, 8), (0, 1, 1)), ((9, 9, 8), (0, 0, 0))]
+    members = []
+    tabs = np.zeros((len(specs), 6, 9))
+    for i, (L, per) in enumerate(specs):
+        A = _traceless(2e-3, 20 + i)
+        tabs[i, :] = A
+        members.append(dict(L=L, periodic=per, tau=0.85, A0=A))
+    print("case ensemble variants", flush=True)
+    ref = _ensemble_states(ib, members, tabs, 1)
+    for v in range(NVAR):
+        if v & ROWS and BS[(v >> 1) & 3] < 96:
+            ens = ib.Ensemble(members, storage="f32")
+            with pytest.raises(ib.IbmLbError):
+                ens.set_variant(v)
+            ens.close()
+            continue
+        got = _ensemble_states(ib, members, tabs, v)
+        for i in range(len(specs)):
+            assert np.array_equal(got[i], ref[i]), f"variant {v}, member {i}"
