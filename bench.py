@@ -115,6 +115,62 @@ def ensemble_bench(steps, warmup=20):
             "max_D": round(max(o["D"] for o in obs), 5)}
 
 
+def describe_variant(v):
+    """Lattice-kernel variant bits as named fields (see ibm_lb_set_variant)."""
+    rows = bool(v & 16)
+    d = {"layout": "rows" if rows else "linear", "nontemporal_loads": bool(v & 1),
+         "block": (128, 256, 512, 64)[(v >> 1) & 3]}
+    if rows:
+        d["nontemporal_stores"] = bool(v & 8)
+    else:
+        d["xcd_grouped_order"] = bool(v & 8)
+    return d
+
+
+def lattice_kernel_name(v):
+    return "k_lattice_rows" if v & 16 else "k_lattice"
+
+
+def large_footprint_bench(dev, steps=300, warmup=30):
+    """The 256^3 droplet (1.27 GB per population copy, far beyond the 256 MB
+    last-level cache) in FP32: whole-step throughput and the lattice kernel's
+    roofline fraction with the autotuner's variant."""
+    import numpy as np
+    import torch
+    from paper_2403_01161_amd import ibmlb
+    from paper_2403_01161_amd.inputs import ou_gradient_table
+    w = precision_workload()
+    table = ou_gradient_table(warmup + 2 * steps, w["corr"], w["G"], seed=w["seed"])
+    dtab = torch.from_numpy(table).to(dev)
+    nodes = int(np.prod(w["L"]))
+    sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage="f32",
+                           A0=table[0], device=dev)
+    variant = sim.autotune(5)
+    sim.step_table(dtab[:warmup])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step_table(dtab[warmup:warmup + steps])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sim.timing(True)
+    sim.step_table(dtab[warmup + steps:warmup + 2 * steps])
+    lat_ms, launches = sim.timing_read()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    alg = 2 * 19 * 4 * nodes
+    avg_s = lat_ms / 1e3 / max(launches, 1)
+    ach = alg / avg_s / 1e9
+    return {"workload": "single droplet, 256^3 moving-wall box, tau 0.8, R 32, 40962-vertex icosphere, "
+                        "OU traceless A(t) rms Ca 0.15, f32 populations",
+            "steps": steps, "mlups": round(nodes * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 4),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counter_traffic("f32", "256cubed"),
+                         "kernel": lattice_kernel_name(variant), "alg_bytes_per_launch": alg,
+                         "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+                         "variant": describe_variant(variant)}}
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for name in ("kernels.hip", "lattice_common.h", "device_common.h"):
@@ -123,10 +179,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(storage, launches_per_run=None):
+def counter_traffic(storage, box="128cubed"):
     """HBM bytes per lattice launch from the committed rocprofv3 counter summary,
     valid only while the kernel source is the one profiled."""
-    path = os.path.join(ROOT, "profiles", f"lattice_{storage}_128cubed_counters.md")
+    path = os.path.join(ROOT, "profiles", f"lattice_{storage}_{box}_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -292,11 +348,12 @@ def precision_bench(dev, steps, every=500):
             "steps": steps, "sample_every": every, "formats": res}
 
 
-def counters_sequence(dev, storage):
+def counters_sequence(dev, storage, box="128"):
     """Kernels whose HBM counters are read: a plain 256 MiB copy whose source
     was first pushed out of the 256 MB last-level cache by a 1 GiB fill (three
     times; the known 256 MiB read + 256 MiB write calibrate the counters), and
-    20 steps of the single-droplet workload after 5 warm-up steps."""
+    20 steps of the single-droplet workload (128^3, or the 256^3 droplet) after
+    5 warm-up steps."""
     import torch
     from paper_2403_01161_amd import ibmlb
     from paper_2403_01161_amd.inputs import ou_gradient_table
@@ -308,15 +365,16 @@ def counters_sequence(dev, storage):
         dst.copy_(src)
     torch.cuda.synchronize()
     del flush
-    w = workload(storage)
+    w = workload(storage) if box == "128" else dict(precision_workload(), storage=storage)
     table = ou_gradient_table(26, w["corr"], w["G"], seed=w["seed"])
     sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage=w["storage"],
                            A0=table[0], device=dev)
-    sim.autotune(5)
+    variant = sim.autotune(5)
     sim.step_table(table[:5])
     sim.step_table(table[5:25])
     torch.cuda.synchronize()
-    print(json.dumps({"counters_sequence": "done", "storage": storage}), flush=True)
+    print(json.dumps({"counters_sequence": "done", "storage": storage, "box": box, "variant": variant,
+                      "kernel": lattice_kernel_name(variant)}), flush=True)
 
 
 def main():
@@ -329,9 +387,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=300)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--large-steps", type=int, default=300,
+                    help="steps of the 256^3 large-footprint leg (0 skips it)")
     ap.add_argument("--precision", type=int, default=0, metavar="STEPS",
                     help="run only the storage-precision study (256^3, every format) for STEPS steps")
-    ap.add_argument("--counters", action="store_true",
+    ap.add_argument("--counters", nargs="?", const="128", choices=["128", "256"], default=None,
                     help="short fixed sequence for hardware-counter runs: 3 device copies of "
                          "256 MiB (calibration) and 20 steps of the single-droplet workload")
     args = ap.parse_args()
@@ -347,7 +407,7 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.counters:
-        counters_sequence(dev, args.storage)
+        counters_sequence(dev, args.storage, args.counters)
         return
     if args.precision:
         print(json.dumps({"precision": precision_bench(dev, args.precision)}), flush=True)
@@ -371,7 +431,7 @@ def main():
     dt = time.perf_counter() - t0
     obs = sim.observables()
 
-    # second pass of K steps with HIP events around every lattice launch on
+    # second pass of K steps with HIP start/stop events stamped by every lattice dispatch on
     # the library's stream: the dominant kernel's average duration
     sim.timing(True)
     t1 = time.perf_counter()
@@ -408,11 +468,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_lattice (fused collide + push-stream + moving walls)",
+                     "kernel": lattice_kernel_name(variant),
                      "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
-                     "variant": {"nontemporal_loads": bool(variant & 1),
-                                 "block": (128, 256, 512, 64)[(variant >> 1) & 3]}},
+                     "variant": describe_variant(variant)},
         "vertex_updates_per_s": round(nv * K / dt, 1),
         "hbm_frac_whole_step": round(alg_bytes * K / dt / 1e9 / HBM_PEAK_GBS, 4),
         "ms_per_step_with_kernel_events": round(dt_ev / K * 1e3, 5),
@@ -423,6 +482,8 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if args.large_steps > 0:
+        line["large_footprint"] = large_footprint_bench(dev, args.large_steps)
     if args.ensemble_steps > 0:
         line["ensemble"] = ensemble_bench(args.ensemble_steps)
     if not args.no_adjoint:

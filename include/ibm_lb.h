@@ -185,8 +185,10 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  * steps with each variant that can run, in four interleaved rounds, from a
  * snapshot of the state that is restored afterwards (the state after the
  * call equals the state before; the force field is spread again at the next
- * step). Synchronises the stream. *variant (may be NULL) receives the choice.
- * Errors: EINVAL, ENOMEM, EDEVICE, sticky.
+ * step). Times within 1 % of the fastest count as ties, which go to the
+ * default variant, else to the lowest index. Synchronises the stream.
+ * *variant (may be NULL) receives the choice. Errors: EINVAL, ENOMEM,
+ * EDEVICE, sticky.
  *
  * ibm_lb_set_variant selects a variant directly (EINVAL if out of range or
  * the row layout cannot take this box). The default is 1 (linear layout,
@@ -194,8 +196,13 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
 int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);
 int ibm_lb_set_variant(ibm_lb* h, int32_t variant);
 
-/* Kernel timing of the fused lattice kernel: when enabled, every step records
- * HIP events around the lattice kernel on the handle's stream.
+/* Kernel timing of the fused lattice kernel: when enabled, each lattice
+ * launch is timed on the handle's stream from the completion of the dispatch
+ * before it to its own completion, both stamped by the dispatches themselves
+ * (hipExtLaunchKernel stop events; the first launch of each call starts
+ * from an event recorded just before it). Consecutive dispatches of one
+ * stream start as the previous one completes, so this is the kernel's
+ * duration without the cost of separate event packets around it.
  * ibm_lb_timing_read synchronises and returns the summed elapsed time (ms)
  * and launch count since the last read. */
 int ibm_lb_timing_enable(ibm_lb* h, int32_t enable);

@@ -28,6 +28,8 @@
 //                   advances the step epoch
 //   k_fs_patch      next step's surface-tension forces (Eq. pi_drop), tile
 //                   marks and spreading, from the final positions
+#include <hip/hip_ext.h>
+
 #include "device_common.h"
 
 namespace ibmlb {
@@ -689,13 +691,14 @@ hipError_t patch_setup(int storage) {
 
 template <class R>
 static hipError_t launch_step_t(const Geom& g, const DevPtrs& d, int nv, double sigma, const SmoothParams& sp,
-                                hipStream_t s, size_t lds) {
+                                hipStream_t s, size_t lds, hipEvent_t done) {
     IbArgs<R> a = make_args<R>(g, d, nv, sigma, sp);
     const unsigned npatch = (nv + PATCH - 1) / PATCH;
     hipLaunchKernelGGL(k_interp_patch<R>, dim3(npatch), dim3(IBT), lds, s, a);
     const V4<R>* final_pos = sp.max_iter > 0 ? a.qa : a.o;
     hipLaunchKernelGGL(k_hc_fused<R>, dim3(npatch), dim3(IBT), 0, s, a, (int)npatch);
-    hipLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), dyn_lds_spread(), s, a, final_pos, 1);
+    hipExtLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr, done, 0, a,
+                          final_pos, 1);
     return hipGetLastError();
 }
 
@@ -751,10 +754,10 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
 }
 
 hipError_t launch_ib_step(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
-                          const SmoothParams& sp, hipStream_t s) {
+                          const SmoothParams& sp, hipStream_t s, hipEvent_t done) {
     const size_t lds = dyn_lds(storage);
-    if (storage == IBM_LB_F64) return launch_step_t<double>(g, d, nv, sigma, sp, s, lds);
-    return launch_step_t<float>(g, d, nv, sigma, sp, s, lds);
+    if (storage == IBM_LB_F64) return launch_step_t<double>(g, d, nv, sigma, sp, s, lds, done);
+    return launch_step_t<float>(g, d, nv, sigma, sp, s, lds, done);
 }
 
 }  // namespace ibmlb

@@ -127,8 +127,11 @@ constexpr int VAR_ROWS = 16;
 int lattice_rows_per_block(int variant, int Lx);
 // Whether the variant can run on this lattice.
 int lattice_variant_ok(int variant, const Geom& g);
+// e0/e1 (may be null): events stamped at the start and at the completion of
+// the dispatch.
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
-                          int cur, bool ib, const double* A_row, int variant, hipStream_t s);
+                          int cur, bool ib, const double* A_row, int variant, hipStream_t s,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
 // maps: eight block maps, concatenated (table q from entry moff[q],
 // nblocks[q] entries; entry b = {member, block index within the member}).
@@ -151,13 +154,14 @@ hipError_t launch_positions_from_abs(int storage, const Geom& g, const DevPtrs& 
 // Patch-organised IB kernels (ib_patch.hip). patch_setup raises the dynamic
 // LDS limit of the patch kernels. launch_ib_pre spreads the forces of the
 // current mesh; launch_ib_step runs the IB half of one step (interpolation,
-// Euler move, smoothing, next forces and spreading).
+// Euler move, smoothing, next forces and spreading); `done` (may be null) is
+// stamped when its last kernel completes.
 hipError_t patch_setup(int storage);
 int patch_window_nodes(int storage);
 hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
                          const SmoothParams& sp, hipStream_t s);
 hipError_t launch_ib_step(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
-                          const SmoothParams& sp, hipStream_t s);
+                          const SmoothParams& sp, hipStream_t s, hipEvent_t done = nullptr);
 // Ensemble forms: args is a device array of per-member IB argument records
 // (ib_args_bytes each, filled by fill_ib_args), map the patch map
 // [npatch_total] (entry b = {member, patch index within the member}).

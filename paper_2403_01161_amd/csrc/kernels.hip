@@ -8,6 +8,7 @@
 // d_i = f_i - w_i rho0 from the rest equilibrium; force and velocity fields
 // are SoA [3][z][y][x] and are only touched inside the 8^3 tiles marked for
 // the current step; vertex data are AoS V4 records relative to the box centre.
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "lattice_common.h"
@@ -631,25 +632,29 @@ hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, cons
     return hipGetLastError();
 }
 
+// Launched with hipExtLaunchKernelGGL so that optional timing events are
+// stamped by the dispatch itself (no separate event packets around it).
 template <class C, bool IB, bool NTL, int BS>
 static void lattice_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                           int xcd, hipStream_t s) {
+                           int xcd, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     using R = typename C::real;
     using S = typename C::store_t;
-    hipLaunchKernelGGL((k_lattice<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, g, lp,
-                       (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row, xcd);
+    hipExtLaunchKernelGGL((k_lattice<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1, 0, g, lp,
+                          (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row,
+                          xcd);
 }
 
 template <class C, bool IB, bool NTL, bool NTS>
 static void rows_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                        int rows, hipStream_t s) {
+                        int rows, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     using R = typename C::real;
     using S = typename C::store_t;
     const int T = rows * g.Lx;
     const long long nrows = (long long)g.Ly * g.Lz;
     const unsigned nb = unsigned((nrows + rows - 1) / rows);
-    hipLaunchKernelGGL((k_lattice_rows<C, IB, NTL, NTS>), dim3(nb), dim3(T), size_t(NXMOVE) * T * sizeof(S), s, g,
-                       lp, (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, d.mark, d.ctl, A_row, rows);
+    hipExtLaunchKernelGGL((k_lattice_rows<C, IB, NTL, NTS>), dim3(nb), dim3(T), uint32_t(NXMOVE * T * sizeof(S)), s,
+                          e0, e1, 0, g, lp, (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u,
+                          (const int*)d.mark, d.ctl, A_row, rows);
 }
 
 int lattice_rows_per_block(int variant, int Lx) {
@@ -667,32 +672,33 @@ int lattice_variant_ok(int variant, const Geom& g) {
 
 template <class C, bool IB, bool NTL>
 static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                             const double* A_row, hipStream_t s) {
+                             const double* A_row, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (variant & VAR_ROWS) {
         const int rows = lattice_rows_per_block(variant, g.Lx);
-        if (variant & VAR_X) rows_launch<C, IB, NTL, true>(g, lp, d, cur, A_row, rows, s);
-        else rows_launch<C, IB, NTL, false>(g, lp, d, cur, A_row, rows, s);
+        if (variant & VAR_X) rows_launch<C, IB, NTL, true>(g, lp, d, cur, A_row, rows, s, e0, e1);
+        else rows_launch<C, IB, NTL, false>(g, lp, d, cur, A_row, rows, s, e0, e1);
         return;
     }
     const int xcd = (variant & VAR_X) ? 1 : 0;
     switch ((variant >> 1) & 3) {
-        case 0: lattice_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, s); break;
-        case 1: lattice_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, s); break;
-        case 2: lattice_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, s); break;
-        default: lattice_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, s); break;
+        case 0: lattice_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
+        case 1: lattice_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
+        case 2: lattice_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
+        default: lattice_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
     }
 }
 
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
-                          int cur, bool ib, const double* A_row, int variant, hipStream_t s) {
+                          int cur, bool ib, const double* A_row, int variant, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1) {
     if (!lattice_variant_ok(variant, g)) return hipErrorInvalidValue;
     DISPATCH_STORAGE(storage, C, {
         if (ib) {
-            if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, s);
-            else launch_lattice_v<C, true, false>(variant, g, lp, d, cur, A_row, s);
+            if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, s, e0, e1);
+            else launch_lattice_v<C, true, false>(variant, g, lp, d, cur, A_row, s, e0, e1);
         } else {
-            if (variant & 1) launch_lattice_v<C, false, true>(variant, g, lp, d, cur, A_row, s);
-            else launch_lattice_v<C, false, false>(variant, g, lp, d, cur, A_row, s);
+            if (variant & 1) launch_lattice_v<C, false, true>(variant, g, lp, d, cur, A_row, s, e0, e1);
+            else launch_lattice_v<C, false, false>(variant, g, lp, d, cur, A_row, s, e0, e1);
         }
     });
     return hipGetLastError();
