@@ -116,7 +116,7 @@ def ensemble_bench(steps, warmup=20):
 
 
 def describe_variant(v):
-    """Lattice-kernel variant bits as named fields (see ibm_lb_set_variant)."""
+    """Step-variant bits as named fields (see ibm_lb_set_variant)."""
     rows = bool(v & 16)
     d = {"layout": "rows" if rows else "linear", "nontemporal_loads": bool(v & 1),
          "block": (128, 256, 512, 64)[(v >> 1) & 3]}
@@ -124,6 +124,7 @@ def describe_variant(v):
         d["nontemporal_stores"] = bool(v & 8)
     else:
         d["xcd_grouped_order"] = bool(v & 8)
+    d["smoothing_finish_launch"] = bool(v & 32)
     return d
 
 

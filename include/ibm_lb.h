@@ -165,9 +165,9 @@ size_t ibm_lb_state_bytes(const ibm_lb* h);
 int ibm_lb_save(ibm_lb* h, void* dst, size_t n);
 int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
 
-/* Lattice-kernel variants (all compute the same per-node arithmetic; they
- * differ only in how nodes map to work-groups and how populations reach
- * memory), 0 <= variant < 32:
+/* Step variants, 0 <= variant < 64. Bits 0-4 select the lattice kernel's
+ * variant (all compute the same per-node arithmetic; they differ only in how
+ * nodes map to work-groups and how populations reach memory):
  *   bit 0     non-temporal population loads;
  *   bits 1-2  work-group size {128, 256, 512, 64}[(variant >> 1) & 3]; in the
  *             row layout, the least number of whole x-rows (at least one)
@@ -180,13 +180,20 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  *   bit 3     linear layout: work-groups ordered so that each XCD takes a
  *             contiguous eighth of the lattice; row layout: non-temporal
  *             population stores.
+ * Bit 5 runs the end of the smoothing (convergence test, further
+ * iterations, iteration count) as a one-work-group launch of its own
+ * instead of in the last of the smoothing's work-groups to finish (which
+ * needs a device-scope release in every work-group); ensembles always run it
+ * as its own launch and ignore the bit.
  *
  * Autotuner: picks the variant for this configuration by timing `reps` whole
- * steps with each variant that can run, in four interleaved rounds, from a
+ * steps with each lattice variant that can run, in four interleaved rounds,
+ * then (with a droplet) the chosen one with and without bit 5, all from a
  * snapshot of the state that is restored afterwards (the state after the
  * call equals the state before; the force field is spread again at the next
- * step). Times within 1 % of the fastest count as ties, which go to the
- * default variant, else to the lowest index. Synchronises the stream.
+ * step). Lattice times within 1 % of the fastest count as ties, which go to
+ * the default variant, else to the lowest index; bit 5 is set only when it
+ * is more than 1 % faster. Synchronises the stream.
  * *variant (may be NULL) receives the choice. Errors: EINVAL, ENOMEM,
  * EDEVICE, sticky.
  *

@@ -462,7 +462,8 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
                                e1),
                 "lattice launch");
         if (ib)
-            HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream, done),
+            HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream, done,
+                                   (h->lattice_variant & VAR_HC_SPLIT) != 0),
                     "ib_step launch");
         if (h->timing) {
             h->iv.push_back({k0, k1});
@@ -868,26 +869,39 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     const double* Arow = h->d.Abuf + 9ll * ACAP;
-    // interleaved rounds; each variant scores its fastest round
+    // interleaved rounds over the candidates; each scores its fastest round
+    auto tune = [&](const int* cand, int nc, float* best_of) {
+        for (int k = 0; k < nc; ++k) best_of[k] = 1e30f;
+        for (int round = 0; round < 4 && e == hipSuccess && rc == IBM_LB_OK; ++round)
+            for (int k = 0; k < nc && e == hipSuccess && rc == IBM_LB_OK; ++k) {
+                if (!lattice_variant_ok(cand[k], h->g)) continue;
+                h->lattice_variant = cand[k];
+                rc = enqueue_steps(h, Arow, 1, 0);  // untimed: first launch of this variant in the round
+                if (rc) break;
+                e = hipEventRecord(a, h->stream);
+                if (e == hipSuccess) rc = enqueue_steps(h, Arow, reps, 0);
+                if (rc) break;
+                if (e == hipSuccess) e = hipEventRecord(b, h->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(b);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                if (e == hipSuccess) best_of[k] = std::min(best_of[k], ms);
+            }
+    };
+    // first the lattice variants (finish of the smoothing in its last
+    // work-group), then, with a droplet, that finish as its own launch
+    int cand[LATTICE_VARIANTS];
     float best_of[LATTICE_VARIANTS];
-    for (int v = 0; v < LATTICE_VARIANTS; ++v) best_of[v] = 1e30f;
-    for (int round = 0; round < 4 && e == hipSuccess && rc == IBM_LB_OK; ++round)
-        for (int v = 0; v < LATTICE_VARIANTS && e == hipSuccess && rc == IBM_LB_OK; ++v) {
-            if (!lattice_variant_ok(v, h->g)) continue;
-            h->lattice_variant = v;
-            rc = enqueue_steps(h, Arow, 1, 0);  // untimed: first launch of this variant in the round
-            if (rc) break;
-            e = hipEventRecord(a, h->stream);
-            if (e == hipSuccess) rc = enqueue_steps(h, Arow, reps, 0);
-            if (rc) break;
-            if (e == hipSuccess) e = hipEventRecord(b, h->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-            if (e == hipSuccess) best_of[v] = std::min(best_of[v], ms);
-        }
+    for (int v = 0; v < LATTICE_VARIANTS; ++v) cand[v] = v;
+    tune(cand, LATTICE_VARIANTS, best_of);
     int best_v = before;
     if (e == hipSuccess && rc == IBM_LB_OK) best_v = pick_variant(best_of);
+    if (h->nv > 0 && e == hipSuccess && rc == IBM_LB_OK) {
+        const int pair[2] = {best_v, best_v | VAR_HC_SPLIT};
+        float t2[2];
+        tune(pair, 2, t2);
+        if (e == hipSuccess && rc == IBM_LB_OK && t2[1] < 0.99f * t2[0]) best_v = pair[1];
+    }
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     h->timing = timing;
@@ -1124,7 +1138,7 @@ struct ibm_lb_batch {
 
 namespace {
 bool batch_variant_ok(const ibm_lb_batch* b, int v) {
-    if (v < 0 || v >= LATTICE_VARIANTS) return false;
+    if (v < 0 || v >= STEP_VARIANTS) return false;
     return !(v & VAR_ROWS) || b->nblk[4 + ((v >> 1) & 3)] >= 0;
 }
 

@@ -451,11 +451,13 @@ __device__ void hc_finish(const IbArgs<R>& a);
 // pass computing every p' and b followed by a pass computing every p.
 constexpr int HALO_CAP = MAXV * PATCH;  // no patch can have more halo vertices
 
-// defer: when iteration 1 did not converge, leave the further iterations to
-// k_hc_finish_batch (the reduction slots keep the maximum and the arrival
-// count, which tells that kernel to run) instead of running them here.
+// split: no arrival count; a later launch (k_hc_finish_batch) finishes the
+// step from the reduction slot. This spares every work-group the
+// device-scope release that must precede its arrival (on this device a
+// write-back of its XCD's L2), which costs more than a launch once there are
+// thousands of work-groups.
 template <class R>
-__device__ void hc_fused(const IbArgs<R>& a, int p, int npatch, bool defer) {
+__device__ void hc_fused(const IbArgs<R>& a, int p, int npatch, bool split) {
     __shared__ V4<R> sb[PATCH + HALO_CAP];
     __shared__ V4<R> spp[PATCH], so[PATCH];
     __shared__ R bred[IBT / 64];
@@ -513,6 +515,14 @@ __device__ void hc_fused(const IbArgs<R>& a, int p, int npatch, bool defer) {
     for (int m = 32; m > 0; m >>= 1) d = fmax(d, __shfl_xor(d, m, 64));
     if ((t & 63) == 0) bred[t >> 6] = d;
     __syncthreads();
+    if (split) {
+        if (t == 0 && on) {
+            R b = bred[0];
+            for (int w = 1; w < IBT / 64; ++w) b = fmax(b, bred[w]);
+            atomicMax(a.red, max_bits(b));
+        }
+        return;
+    }
     if (t == 0) {
         R b = bred[0];
         for (int w = 1; w < IBT / 64; ++w) b = fmax(b, bred[w]);
@@ -523,13 +533,18 @@ __device__ void hc_fused(const IbArgs<R>& a, int p, int npatch, bool defer) {
     __syncthreads();
     if (!last) return;
     __threadfence();
-    if (defer && on && a.sp.max_iter > 1 && !(from_bits<R>(a.red[0]) < R(a.sp.tol))) return;
     hc_finish(a);
 }
 
 template <class R>
-__global__ __launch_bounds__(IBT) void k_hc_fused(IbArgs<R> a, int npatch) {
-    hc_fused(a, blockIdx.x, npatch, false);
+__global__ __launch_bounds__(IBT) void k_hc_fused(IbArgs<R> a, int npatch, int split) {
+    hc_fused(a, blockIdx.x, npatch, split != 0);
+}
+
+// Split smoothing of one droplet: the finish as a launch of its own.
+template <class R>
+__global__ __launch_bounds__(1024) void k_hc_finish(IbArgs<R> a) {
+    hc_finish(a);
 }
 
 // One work-group, after iteration 1 is in qa and its maximum in the
@@ -608,13 +623,13 @@ __global__ __launch_bounds__(IBT) void k_hc_fused_batch(const IbArgs<R>* __restr
     hc_fused(a, e.y, (a.nv + PATCH - 1) / PATCH, true);
 }
 
-// One work-group per member: the members whose iteration 1 did not converge
-// (their arrival count was left in the second reduction slot) run the further
-// iterations here with 1024 threads; the others have finished already.
+// One work-group per member, after k_hc_fused_batch: the convergence test,
+// the further iterations when iteration 1 did not converge (1024 threads),
+// the iteration count and the epoch.
 template <class R>
 __global__ __launch_bounds__(1024) void k_hc_finish_batch(const IbArgs<R>* __restrict__ args) {
     const IbArgs<R>& a = args[blockIdx.x];
-    if (a.nv == 0 || a.red[1] == 0ull) return;
+    if (a.nv == 0) return;
     hc_finish(a);
 }
 
@@ -691,12 +706,13 @@ hipError_t patch_setup(int storage) {
 
 template <class R>
 static hipError_t launch_step_t(const Geom& g, const DevPtrs& d, int nv, double sigma, const SmoothParams& sp,
-                                hipStream_t s, size_t lds, hipEvent_t done) {
+                                hipStream_t s, size_t lds, hipEvent_t done, bool hc_split) {
     IbArgs<R> a = make_args<R>(g, d, nv, sigma, sp);
     const unsigned npatch = (nv + PATCH - 1) / PATCH;
     hipLaunchKernelGGL(k_interp_patch<R>, dim3(npatch), dim3(IBT), lds, s, a);
     const V4<R>* final_pos = sp.max_iter > 0 ? a.qa : a.o;
-    hipLaunchKernelGGL(k_hc_fused<R>, dim3(npatch), dim3(IBT), 0, s, a, (int)npatch);
+    hipLaunchKernelGGL(k_hc_fused<R>, dim3(npatch), dim3(IBT), 0, s, a, (int)npatch, hc_split ? 1 : 0);
+    if (hc_split) hipLaunchKernelGGL(k_hc_finish<R>, dim3(1), dim3(1024), 0, s, a);
     hipExtLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr, done, 0, a,
                           final_pos, 1);
     return hipGetLastError();
@@ -754,10 +770,10 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
 }
 
 hipError_t launch_ib_step(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
-                          const SmoothParams& sp, hipStream_t s, hipEvent_t done) {
+                          const SmoothParams& sp, hipStream_t s, hipEvent_t done, bool hc_split) {
     const size_t lds = dyn_lds(storage);
-    if (storage == IBM_LB_F64) return launch_step_t<double>(g, d, nv, sigma, sp, s, lds, done);
-    return launch_step_t<float>(g, d, nv, sigma, sp, s, lds, done);
+    if (storage == IBM_LB_F64) return launch_step_t<double>(g, d, nv, sigma, sp, s, lds, done, hc_split);
+    return launch_step_t<float>(g, d, nv, sigma, sp, s, lds, done, hc_split);
 }
 
 }  // namespace ibmlb

@@ -122,6 +122,11 @@ constexpr int LATTICE_VARIANTS = 32;
 constexpr int LAT_BS[4] = {128, 256, 512, 64};
 constexpr int VAR_X = 8;
 constexpr int VAR_ROWS = 16;
+// Step variant = lattice variant (bits 0-4) + bit 5 (VAR_HC_SPLIT): the
+// smoothing's finish as a launch of its own (single droplets; ensembles
+// always split it).
+constexpr int VAR_HC_SPLIT = 32;
+constexpr int STEP_VARIANTS = 64;
 // Rows per work-group of a row-layout variant for rows of Lx nodes; 0 when
 // the variant is not a row layout or Lx exceeds the largest work-group.
 int lattice_rows_per_block(int variant, int Lx);
@@ -155,13 +160,15 @@ hipError_t launch_positions_from_abs(int storage, const Geom& g, const DevPtrs& 
 // LDS limit of the patch kernels. launch_ib_pre spreads the forces of the
 // current mesh; launch_ib_step runs the IB half of one step (interpolation,
 // Euler move, smoothing, next forces and spreading); `done` (may be null) is
-// stamped when its last kernel completes.
+// stamped when its last kernel completes. hc_split: the smoothing's finish
+// runs as a launch of its own instead of in the last work-group to arrive.
 hipError_t patch_setup(int storage);
 int patch_window_nodes(int storage);
 hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
                          const SmoothParams& sp, hipStream_t s);
 hipError_t launch_ib_step(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
-                          const SmoothParams& sp, hipStream_t s, hipEvent_t done = nullptr);
+                          const SmoothParams& sp, hipStream_t s, hipEvent_t done = nullptr,
+                          bool hc_split = false);
 // Ensemble forms: args is a device array of per-member IB argument records
 // (ib_args_bytes each, filled by fill_ib_args), map the patch map
 // [npatch_total] (entry b = {member, patch index within the member}).

@@ -665,7 +665,7 @@ int lattice_rows_per_block(int variant, int Lx) {
 }
 
 int lattice_variant_ok(int variant, const Geom& g) {
-    if (variant < 0 || variant >= LATTICE_VARIANTS) return 0;
+    if (variant < 0 || variant >= STEP_VARIANTS) return 0;
     if (variant & VAR_ROWS) return lattice_rows_per_block(variant, g.Lx) > 0;
     return 1;
 }
@@ -737,7 +737,7 @@ static void launch_rows_batch(int T, const LatDesc* desc, const int2* map, int n
 
 hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* maps, const int moff[8],
                                 const int nblocks[8], int cur, long long step, int variant, hipStream_t s) {
-    if (variant < 0 || variant >= LATTICE_VARIANTS) return hipErrorInvalidValue;
+    if (variant < 0 || variant >= STEP_VARIANTS) return hipErrorInvalidValue;
     const int bsi = (variant >> 1) & 3;
     const int xb = variant & VAR_X ? 1 : 0;
     if (variant & VAR_ROWS) {

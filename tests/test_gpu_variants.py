@@ -78,10 +78,14 @@ def test_row_layout_rejects_long_rows(ib):
     sim.step(np.zeros(9), 2)
     sim.close()
     with pytest.raises(ib.IbmLbError):
-        ib.Simulation((8, 8, 8), tau=0.8, storage="f32").set_variant(NVAR)
+        ib.Simulation((8, 8, 8), tau=0.8, storage="f32").set_variant(2 * NVAR)
 
 
-@pytest.mark.parametrize("variant", [1, 9, ROWS | 1, ROWS | 8, ROWS | 4 | 8 | 1, ROWS | 6])
+SPLIT = 32  # smoothing finish as a launch of its own
+
+
+@pytest.mark.parametrize("variant", [1, 9, ROWS | 1, ROWS | 8, ROWS | 4 | 8 | 1, ROWS | 6, SPLIT | 1,
+                                     SPLIT | ROWS | 8 | 1])
 def test_droplet_variants_match_oracle(ib, variant):
     L = (19, 17, 21)
     A = _traceless(3e-3, 2)
