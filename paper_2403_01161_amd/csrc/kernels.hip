@@ -94,6 +94,40 @@ __device__ __forceinline__ void put(S* p, S v) {
     else *p = v;
 }
 
+// Node coordinates from the linear index (32-bit division below 2^31 nodes).
+__device__ __forceinline__ void node_xyz(const Geom& g, long long n, int& x, int& y, int& z) {
+    const int LxLy = g.Lx * g.Ly;
+    int r;
+    if (g.N <= 0x7fffffffll) {
+        const int m = int(n);
+        z = m / LxLy;
+        r = m - z * LxLy;
+    } else {
+        z = int(n / LxLy);
+        r = int(n - (long long)z * LxLy);
+    }
+    y = r / g.Lx;
+    x = r - y * g.Lx;
+}
+
+// Target of population i pushed from node n = (x, y, z): n + c_i . (1, Lx,
+// Lx Ly), moved back across a periodic side; *wall when it leaves through a
+// wall instead.
+template <int I>
+__device__ __forceinline__ long long push_target(const Geom& g, long long n, int x, int y, int z, bool* wall) {
+    const long long LxLy = (long long)g.Lx * g.Ly;
+    long long t = n + CX[I] + (long long)CY[I] * g.Lx + (long long)CZ[I] * LxLy;
+    bool w = false;
+    if (CX[I] == 1 && x == g.Lx - 1) { if (g.px) t -= g.Lx; else w = true; }
+    if (CX[I] == -1 && x == 0) { if (g.px) t += g.Lx; else w = true; }
+    if (CY[I] == 1 && y == g.Ly - 1) { if (g.py) t -= LxLy; else w = true; }
+    if (CY[I] == -1 && y == 0) { if (g.py) t += LxLy; else w = true; }
+    if (CZ[I] == 1 && z == g.Lz - 1) { if (g.pz) t -= g.N; else w = true; }
+    if (CZ[I] == -1 && z == 0) { if (g.pz) t += g.N; else w = true; }
+    *wall = w;
+    return t;
+}
+
 // ROWS: x-moving populations that stay in the box go to stage[xslot(i) T + t]
 // instead of global memory (t: the thread's slot, T: slots per plane).
 template <class C, bool IB, bool NTL, bool ROWS, bool NTS>
@@ -103,16 +137,11 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
                                              typename C::real* __restrict__ F,
                                              typename C::real* __restrict__ U,
                                              const int* __restrict__ mark, Ctl* ctl,
-                                             const double* __restrict__ Arow, const long long n,
-                                             typename C::store_t* stage, int t, int T) {
+                                             const double* __restrict__ Arow, const long long n, const int x,
+                                             const int y, const int z, typename C::store_t* stage, int t, int T) {
     using R = typename C::real;
     using S = typename C::store_t;
     const long long N = g.N;
-    const int LxLy = g.Lx * g.Ly;
-    const int z = int(n / LxLy);
-    const int rem = int(n - (long long)z * LxLy);
-    const int y = rem / g.Lx;
-    const int x = rem - y * g.Lx;
 
     R d[Q];
 #pragma unroll
@@ -163,35 +192,33 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
     const R omega = R(lp.omega), kg = R(lp.kguo), rho0 = R(lp.rho0);
     const R usq = ux * ux + uy * uy + uz * uz;
     const R uF = ux * Fx + uy * Fy + uz * Fz;
-    R A[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) A[k] = R(Arow[k]);
-    const R xr = R(x - g.xci[0]) - R(g.xcf[0]);
-    const R yr = R(y - g.xci[1]) - R(g.xcf[1]);
-    const R zr = R(z - g.xci[2]) - R(g.xcf[2]);
 
-    auto push = [&](int i, R val) {
-        int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
-        bool wall = false;
-        if (CX[i] != 0 && (tx < 0 || tx >= g.Lx)) {
-            if (g.px) tx = wrap(tx, g.Lx); else wall = true;
-        }
-        if (CY[i] != 0 && (ty < 0 || ty >= g.Ly)) {
-            if (g.py) ty = wrap(ty, g.Ly); else wall = true;
-        }
-        if (CZ[i] != 0 && (tz < 0 || tz >= g.Lz)) {
-            if (g.pz) tz = wrap(tz, g.Lz); else wall = true;
-        }
+    // Moving-wall term of a reflected population: c_i . u_w with the wall
+    // velocity u_w = A (x - x_c + c_i / 2) at the link midpoint, written as
+    // c_i . (A (x - x_c)) + c_i . (A c_i) / 2.
+    auto wall_term = [&](int i) {
+        R A[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) A[k] = R(Arow[k]);
+        const R xr = R(x - g.xci[0]) - R(g.xcf[0]);
+        const R yr = R(y - g.xci[1]) - R(g.xcf[1]);
+        const R zr = R(z - g.xci[2]) - R(g.xcf[2]);
+        const R cx = R(CX[i]), cy = R(CY[i]), cz = R(CZ[i]);
+        const R ax = A[0] * (xr + R(0.5) * cx) + A[1] * (yr + R(0.5) * cy) + A[2] * (zr + R(0.5) * cz);
+        const R ay = A[3] * (xr + R(0.5) * cx) + A[4] * (yr + R(0.5) * cy) + A[5] * (zr + R(0.5) * cz);
+        const R az = A[6] * (xr + R(0.5) * cx) + A[7] * (yr + R(0.5) * cy) + A[8] * (zr + R(0.5) * cz);
+        return R(6) * wgt<R>(i) * rho0 * (cx * ax + cy * ay + cz * az);
+    };
+
+    auto push = [&](auto ic, R val) {
+        constexpr int i = decltype(ic)::value;
+        bool wall;
+        const long long tg = push_target<i>(g, n, x, y, z, &wall);
         if (!wall) {
             if (ROWS && CX[i] != 0) stage[xslot(i) * T + t] = enc<C>(val, lp.scale);
-            else put<S, NTS>(&fout[i * N + tx + (long long)g.Lx * (ty + (long long)g.Ly * tz)], enc<C>(val, lp.scale));
+            else put<S, NTS>(&fout[i * N + tg], enc<C>(val, lp.scale));
         } else {
-            const R wx = xr + R(0.5) * R(CX[i]), wy = yr + R(0.5) * R(CY[i]), wz = zr + R(0.5) * R(CZ[i]);
-            const R uwx = A[0] * wx + A[1] * wy + A[2] * wz;
-            const R uwy = A[3] * wx + A[4] * wy + A[5] * wz;
-            const R uwz = A[6] * wx + A[7] * wy + A[8] * wz;
-            const R cuw = R(CX[i]) * uwx + R(CY[i]) * uwy + R(CZ[i]) * uwz;
-            put<S, NTS>(&fout[opp(i) * N + n], enc<C>(val - R(6) * wgt<R>(i) * rho0 * cuw, lp.scale));
+            put<S, NTS>(&fout[opp(i) * N + n], enc<C>(val - wall_term(i), lp.scale));
         }
     };
 
@@ -201,9 +228,9 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
         const R S0 = kg * w * (R(-3) * uF);
         put<S, NTS>(&fout[n], enc<C>(d[0] - omega * (d[0] - deq) + S0, lp.scale));
     }
-#pragma unroll
-    for (int p = 1; p <= 9; ++p) {
-        const int i = 2 * p - 1, j = 2 * p;
+    static_for<1, 10>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = 2 * p - 1, j = 2 * p;
         const R w = wgt<R>(i);
         const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
         const R cF = R(CX[i]) * Fx + R(CY[i]) * Fy + R(CZ[i]) * Fz;
@@ -211,9 +238,9 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
         const R anti = w * rho * R(3) * cu;
         const R Ssym = kg * w * (R(9) * cu * cF - R(3) * uF);
         const R Santi = kg * w * R(3) * cF;
-        push(i, d[i] - omega * (d[i] - (sym + anti)) + Ssym + Santi);
-        push(j, d[j] - omega * (d[j] - (sym - anti)) + Ssym - Santi);
-    }
+        push(std::integral_constant<int, i>{}, d[i] - omega * (d[i] - (sym + anti)) + Ssym + Santi);
+        push(std::integral_constant<int, j>{}, d[j] - omega * (d[j] - (sym - anti)) + Ssym - Santi);
+    });
 }
 
 // Second half of the row layout: thread t (node n, coordinates x, y, z)
@@ -223,34 +250,26 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
 // reflected at the source).
 template <class C, bool NTS>
 __device__ __forceinline__ void rows_receive(const Geom& g, typename C::store_t* __restrict__ fout,
-                                             const typename C::store_t* stage, long long n, int t, int T) {
+                                             const typename C::store_t* stage, long long n, int x, int y, int z,
+                                             int t, int T) {
     const long long N = g.N;
-    const int LxLy = g.Lx * g.Ly;
-    const int z = int(n / LxLy);
-    const int rem = int(n - (long long)z * LxLy);
-    const int y = rem / g.Lx;
-    const int x = rem - y * g.Lx;
+    const long long LxLy = (long long)g.Lx * g.Ly;
     const int row0 = t - x;  // slot of x = 0 in this row
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        if (CX[i] == 0) continue;
+    static_for<1, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if (CX[i] == 0) return;
         int xs = x - CX[i];
         if (xs < 0 || xs >= g.Lx) {
-            if (!g.px) continue;
+            if (!g.px) return;
             xs = wrap(xs, g.Lx);
         }
-        int ty = y + CY[i], tz = z + CZ[i];
-        if (CY[i] != 0 && (ty < 0 || ty >= g.Ly)) {
-            if (!g.py) continue;
-            ty = wrap(ty, g.Ly);
-        }
-        if (CZ[i] != 0 && (tz < 0 || tz >= g.Lz)) {
-            if (!g.pz) continue;
-            tz = wrap(tz, g.Lz);
-        }
-        put<typename C::store_t, NTS>(&fout[i * N + x + (long long)g.Lx * (ty + (long long)g.Ly * tz)],
-                                      stage[xslot(i) * T + row0 + xs]);
-    }
+        long long tg = n + (long long)CY[i] * g.Lx + (long long)CZ[i] * LxLy;
+        if (CY[i] == 1 && y == g.Ly - 1) { if (!g.py) return; tg -= LxLy; }
+        if (CY[i] == -1 && y == 0) { if (!g.py) return; tg += LxLy; }
+        if (CZ[i] == 1 && z == g.Lz - 1) { if (!g.pz) return; tg -= N; }
+        if (CZ[i] == -1 && z == 0) { if (!g.pz) return; tg += N; }
+        put<typename C::store_t, NTS>(&fout[i * N + tg], stage[xslot(i) * T + row0 + xs]);
+    });
 }
 
 template <class C, bool IB, bool NTL, int BS>
@@ -263,8 +282,10 @@ __global__ __launch_bounds__(BS) void k_lattice(Geom g, LatticeParams lp,
                                                  const double* __restrict__ Arow, int xcd) {
     const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
     const long long n = (long long)b * BS + threadIdx.x;
-    if (n < g.N)
-        lattice_node<C, IB, NTL, false, false>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, nullptr, 0, 0);
+    if (n >= g.N) return;
+    int x, y, z;
+    node_xyz(g, n, x, y, z);
+    lattice_node<C, IB, NTL, false, false>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0, 0);
 }
 
 // Row layout: `rows` whole x-rows per work-group (blockDim = rows * Lx <= 512).
@@ -283,11 +304,17 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticePara
     S* stage = reinterpret_cast<S*>(dyn);
     const int T = rows * g.Lx;
     const int t = threadIdx.x;
-    const long long n = (long long)blockIdx.x * T + t;
+    // rows of Lx nodes: row index from the work-group, x from the thread
+    const int rl = t / g.Lx;
+    const int x = t - rl * g.Lx;
+    const int row = int(blockIdx.x) * rows + rl;
+    const int z = row / g.Ly, y = row - z * g.Ly;
+    const long long n = (long long)row * g.Lx + x;
     const bool act = n < g.N;
-    if (act) lattice_node<C, IB, NTL, true, NTS>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, stage, t, T);
+    if (act)
+        lattice_node<C, IB, NTL, true, NTS>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, stage, t, T);
     __syncthreads();
-    if (act) rows_receive<C, NTS>(g, fout, stage, n, t, T);
+    if (act) rows_receive<C, NTS>(g, fout, stage, n, x, y, z, t, T);
 }
 
 // Ensemble forms: one launch covers every member's lattice; work-group b
@@ -302,13 +329,15 @@ __global__ __launch_bounds__(BS) void k_lattice_batch(const LatDesc* __restrict_
     const LatDesc& D = desc[e.x];
     const long long n = (long long)e.y * BS + threadIdx.x;
     if (n >= D.g.N) return;
+    int x, y, z;
+    node_xyz(D.g, n, x, y, z);
     const double* Arow = D.A + arow;
     if (D.ib)
         lattice_node<C, true, NTL, false, false>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F,
-                                                 (R*)D.u, D.mark, D.ctl, Arow, n, nullptr, 0, 0);
+                                                 (R*)D.u, D.mark, D.ctl, Arow, n, x, y, z, nullptr, 0, 0);
     else
         lattice_node<C, false, NTL, false, false>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F,
-                                                  (R*)D.u, D.mark, D.ctl, Arow, n, nullptr, 0, 0);
+                                                  (R*)D.u, D.mark, D.ctl, Arow, n, x, y, z, nullptr, 0, 0);
 }
 
 template <class C, bool NTL, bool NTS>
@@ -321,9 +350,14 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows_batch(const LatDesc
     S* stage = reinterpret_cast<S*>(dyn);
     const int2 e = map[blockIdx.x];
     const LatDesc& D = desc[e.x];
-    const int T = (int(blockDim.x) / D.g.Lx) * D.g.Lx;
+    const int rows = int(blockDim.x) / D.g.Lx;
+    const int T = rows * D.g.Lx;
     const int t = threadIdx.x;
-    const long long n = (long long)e.y * T + t;
+    const int rl = t / D.g.Lx;
+    const int x = t - rl * D.g.Lx;
+    const int row = e.y * rows + rl;
+    const int z = row / D.g.Ly, y = row - z * D.g.Ly;
+    const long long n = (long long)row * D.g.Lx + x;
     const bool act = t < T && n < D.g.N;
     const double* Arow = D.A + arow;
     const S* fin = (const S*)D.f[cur];
@@ -331,13 +365,13 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows_batch(const LatDesc
     if (act) {
         if (D.ib)
             lattice_node<C, true, NTL, true, NTS>(D.g, D.lp, fin, fout, (R*)D.F, (R*)D.u, D.mark, D.ctl, Arow, n,
-                                                  stage, t, T);
+                                                  x, y, z, stage, t, T);
         else
             lattice_node<C, false, NTL, true, NTS>(D.g, D.lp, fin, fout, (R*)D.F, (R*)D.u, D.mark, D.ctl, Arow,
-                                                   n, stage, t, T);
+                                                   n, x, y, z, stage, t, T);
     }
     __syncthreads();
-    if (act) rows_receive<C, NTS>(D.g, fout, stage, n, t, T);
+    if (act) rows_receive<C, NTS>(D.g, fout, stage, n, x, y, z, t, T);
 }
 
 // Diagnostic moments: rho and u (with F/2) of the current populations; the

@@ -4,9 +4,20 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace ibmlb {
+
+// f(integral_constant<int, k>) for k = B .. E-1, unrolled at compile time.
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 // ---------------------------------------------------------------- D3Q19
 // Index 0 is the rest population; 2p-1 and 2p (p = 1..9) are opposite.
@@ -28,12 +39,9 @@ struct SF16 { using store_t = _Float16; using real = float; };
 struct SBF16 { using store_t = uint16_t; using real = float; };
 
 __device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
-__device__ inline uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                                          // round to nearest even
-    return uint16_t(u >> 16);
-}
+// Round to nearest even with the conversion instruction of gfx950
+// (v_cvt_pk_bf16_f32); NaN stays NaN.
+__device__ inline uint16_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 template <class C> __device__ inline typename C::real dec(typename C::store_t v, float inv);
 template <> __device__ inline double dec<SF64>(double v, float) { return v; }
