@@ -1123,6 +1123,7 @@ struct ibm_lb_batch {
     int2* lat_map = nullptr;      // device block maps of the eight layouts, concatenated
     int lat_moff[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int nblk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int nblk_ib[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // leading entries of each map: members with a droplet
     void* ib_args = nullptr;      // device [n] records
     int2* patch_map = nullptr;    // device [npatch_total] {member, patch}
     int npatch_total = 0;
@@ -1174,7 +1175,7 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     auto bail = [&](hipError_t e, const char* where) { return batch_fail_cleanup(b, hip_fail(e, where)); };
     hipError_t e;
     std::vector<LatDesc> ld(n);
-    std::vector<int2> lm[8], pm;
+    std::vector<int2> lm[8], lm_plain[8], pm;
     bool rows_ok[4] = {true, true, true, true};
     const size_t rec = ib_args_bytes(b->storage);
     std::vector<char> args(rec * n);
@@ -1191,25 +1192,33 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
         L.ctl = h->d.ctl;
         L.A = nullptr;  // set below, once the table is allocated
         L.ib = h->nv > 0 ? 1 : 0;
+        // members with a droplet first in every map, then the others (two
+        // launches, each compiled for one kind)
+        std::vector<int2>* dst = h->nv > 0 ? lm : lm_plain;
         for (int q = 0; q < 4; ++q) {
-            for (int k = 0; k < (int)((h->g.N + LAT_BS[q] - 1) / LAT_BS[q]); ++k) lm[q].push_back(int2{i, k});
+            for (int k = 0; k < (int)((h->g.N + LAT_BS[q] - 1) / LAT_BS[q]); ++k) dst[q].push_back(int2{i, k});
             const int rows = LAT_BS[q] / h->g.Lx;
             if (rows < 1) {
                 rows_ok[q] = false;
                 continue;
             }
             const long long nrows = (long long)h->g.Ly * h->g.Lz;
-            for (int k = 0; k < (int)((nrows + rows - 1) / rows); ++k) lm[4 + q].push_back(int2{i, k});
+            for (int k = 0; k < (int)((nrows + rows - 1) / rows); ++k) dst[4 + q].push_back(int2{i, k});
         }
         for (int k = 0; k < (h->nv + IB_PATCH - 1) / IB_PATCH; ++k) pm.push_back(int2{i, k});
         fill_ib_args(b->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, args.data() + rec * i);
     }
     std::vector<int2> lall;
     for (int q = 0; q < 8; ++q) {
-        if (q >= 4 && !rows_ok[q - 4]) lm[q].clear();
-        b->nblk[q] = q >= 4 && !rows_ok[q - 4] ? -1 : (int)lm[q].size();
+        if (q >= 4 && !rows_ok[q - 4]) {
+            lm[q].clear();
+            lm_plain[q].clear();
+        }
+        b->nblk_ib[q] = (int)lm[q].size();
+        b->nblk[q] = q >= 4 && !rows_ok[q - 4] ? -1 : (int)(lm[q].size() + lm_plain[q].size());
         b->lat_moff[q] = (int)lall.size();
         lall.insert(lall.end(), lm[q].begin(), lm[q].end());
+        lall.insert(lall.end(), lm_plain[q].begin(), lm_plain[q].end());
     }
     b->npatch_total = (int)pm.size();
     if (pm.empty()) pm.push_back(int2{0, 0});
@@ -1265,7 +1274,7 @@ int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps) {
         HIP_TRY(hipMemcpyAsync(dst, sg, sizeof(double) * tab, hipMemcpyHostToDevice, b->stream), "upload tables");
         HIP_TRY(hipEventRecord(b->stage_done[hf], b->stream), "hipEventRecord");
         for (int j = 0; j < len; ++j) {
-            HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->cur,
+            HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib, b->cur,
                                          (long long)hf * tab + 9ll * j, b->variant, b->stream),
                     "lattice batch launch");
             HIP_TRY(launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, n, b->stream),
@@ -1341,7 +1350,7 @@ int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant) {
     auto batch_steps = [&](int v, int k) {
         hipError_t r = hipSuccess;
         for (int j = 0; j < k && r == hipSuccess; ++j) {
-            r = launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->cur, 0, v,
+            r = launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib, b->cur, 0, v,
                                      b->stream);
             if (r == hipSuccess)
                 r = launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, n, b->stream);

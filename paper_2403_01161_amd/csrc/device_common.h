@@ -53,12 +53,28 @@ constexpr int MAXV = 15;  // valence capacity of a fan
 
 // ---------------------------------------------------------------- topology
 // Valence and neighbours of vertex k (unused slots are -1).
-__device__ inline int load_fan(const int4* fan, int k, int nb[MAXV]) {
-    const int4 a = fan[4 * k], b = fan[4 * k + 1];
+// Whole four-component record load and store through a generic or a
+// global-address-space pointer (records in the global space cannot use the
+// class's generic copy operations).
+template <class T, class P>
+__device__ __forceinline__ T ld4(P p) {
+    return T{p->x, p->y, p->z, p->w};
+}
+template <class P, class T>
+__device__ __forceinline__ void st4(P p, const T& v) {
+    p->x = v.x;
+    p->y = v.y;
+    p->z = v.z;
+    p->w = v.w;
+}
+
+template <class P>
+__device__ inline int load_fan(P fan, int k, int nb[MAXV]) {
+    const int4 a = ld4<int4>(fan + 4 * k), b = ld4<int4>(fan + 4 * k + 1);
     nb[0] = a.y; nb[1] = a.z; nb[2] = a.w;
     nb[3] = b.x; nb[4] = b.y; nb[5] = b.z; nb[6] = b.w;
     if (a.x > 7) {
-        const int4 c = fan[4 * k + 2], d = fan[4 * k + 3];
+        const int4 c = ld4<int4>(fan + 4 * k + 2), d = ld4<int4>(fan + 4 * k + 3);
         nb[7] = c.x; nb[8] = c.y; nb[9] = c.z; nb[10] = c.w;
         nb[11] = d.x; nb[12] = d.y; nb[13] = d.z; nb[14] = d.w;
     } else {

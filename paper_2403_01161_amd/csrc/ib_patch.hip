@@ -37,43 +37,104 @@ namespace ibmlb {
 constexpr int PATCH = IB_PATCH;
 constexpr int IBT = 256;  // threads of a patch work-group: lanes of the first wave own the vertices
 
-template <class R>
+// Pointer of address space AS: 0 = generic (kernel arguments, which the
+// compiler proves global), 1 = global (records read from memory, whose
+// pointers the compiler would otherwise access with flat instructions).
+template <class T, int AS>
+struct PtrT {
+    using type = T*;
+};
+template <class T>
+struct PtrT<T, 1> {
+    using type = __attribute__((address_space(1))) T*;
+};
+template <class T, int AS>
+using Ptr = typename PtrT<T, AS>::type;
+
+template <class R, int AS = 0>
 struct IbArgs {
     Geom g;
     int nv;
     R sigma;
     SmoothParams sp;
-    V4<R>* r;              // positions at the start of the step (relative to x_c)
-    V4<R>* o;              // after the Euler move
-    V4<R>* qa;             // smoothing iterates; qa holds the final positions
-    V4<R>* qb;
-    V4<R>* pp;
-    V4<R>* bb;
-    const int4* fan;       // [nv][4]
-    const int4* lfan;      // [nv][4] fan in patch-local slots
-    const int* hstart;     // [npatch + 1]
-    const int* hids;       // halo vertices of each patch
-    R* F;                  // [3][N]
-    const R* U;            // [3][N]
-    int* mark;
-    Ctl* ctl;
-    unsigned long long* red;  // grid-wide max of |p - q| (bit pattern of a non-negative real)
-    int wcap;              // LDS window capacity in nodes
+    Ptr<V4<R>, AS> r;      // positions at the start of the step (relative to x_c)
+    Ptr<V4<R>, AS> o;      // after the Euler move
+    Ptr<V4<R>, AS> qa;     // smoothing iterates; qa holds the final positions
+    Ptr<V4<R>, AS> qb;
+    Ptr<V4<R>, AS> pp;
+    Ptr<V4<R>, AS> bb;
+    Ptr<const int4, AS> fan;     // [nv][4]
+    Ptr<const int4, AS> lfan;    // [nv][4] fan in patch-local slots
+    Ptr<const int, AS> hstart;   // [npatch + 1]
+    Ptr<const int, AS> hids;     // halo vertices of each patch
+    Ptr<R, AS> F;                // [3][N]
+    Ptr<const R, AS> U;          // [3][N]
+    Ptr<int, AS> mark;
+    Ptr<Ctl, AS> ctl;
+    Ptr<unsigned long long, AS> red;  // grid-wide max of |p - q| (bit pattern of a non-negative real)
+    int wcap;                    // LDS window capacity in nodes
 };
+
+// A record read from memory, with its pointers in the global space.
+template <class R>
+__device__ inline IbArgs<R, 1> to_global(const IbArgs<R, 0>& a) {
+    IbArgs<R, 1> b;
+    b.g = a.g;
+    b.nv = a.nv;
+    b.sigma = a.sigma;
+    b.sp = a.sp;
+    b.r = (Ptr<V4<R>, 1>)a.r;
+    b.o = (Ptr<V4<R>, 1>)a.o;
+    b.qa = (Ptr<V4<R>, 1>)a.qa;
+    b.qb = (Ptr<V4<R>, 1>)a.qb;
+    b.pp = (Ptr<V4<R>, 1>)a.pp;
+    b.bb = (Ptr<V4<R>, 1>)a.bb;
+    b.fan = (Ptr<const int4, 1>)a.fan;
+    b.lfan = (Ptr<const int4, 1>)a.lfan;
+    b.hstart = (Ptr<const int, 1>)a.hstart;
+    b.hids = (Ptr<const int, 1>)a.hids;
+    b.F = (Ptr<R, 1>)a.F;
+    b.U = (Ptr<const R, 1>)a.U;
+    b.mark = (Ptr<int, 1>)a.mark;
+    b.ctl = (Ptr<Ctl, 1>)a.ctl;
+    b.red = (Ptr<unsigned long long, 1>)a.red;
+    b.wcap = a.wcap;
+    return b;
+}
+
+// Relaxed device-scope atomics on generic or global pointers (no return).
+template <class T>
+__device__ inline void atom_add(T* p, T v) { unsafeAtomicAdd(p, v); }
+template <class T>
+__device__ inline void atom_add(__attribute__((address_space(1))) T* p, T v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void atom_or(int* p, int v) { atomicOr(p, v); }
+__device__ inline void atom_or(__attribute__((address_space(1))) int* p, int v) {
+    __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long atom_inc(unsigned long long* p) { return atomicAdd(p, 1ull); }
+__device__ inline unsigned long long atom_inc(__attribute__((address_space(1))) unsigned long long* p) {
+    return __hip_atomic_fetch_add(p, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void atom_max(unsigned long long* p, unsigned long long v) { atomicMax(p, v); }
+__device__ inline void atom_max(__attribute__((address_space(1))) unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------- forces
 // Surface-tension force of vertex k at positions P: Eq. (pi_drop) read as
 // phi_k = -sigma dA/dr_k, with dA/dr_k = n_t x (r_{n_{j+1}} - r_{n_j}) / 2
 // for the triangle t = (k, n_j, n_{j+1}) of unit normal n_t.
-template <class R>
-__device__ inline void force_of(const IbArgs<R>& a, const V4<R>* P, int k, const V4<R>& pk, R& fx,
+template <class R, int AS>
+__device__ inline void force_of(const IbArgs<R, AS>& a, Ptr<const V4<R>, AS> P, int k, const V4<R>& pk, R& fx,
                                 R& fy, R& fz) {
     int nb[MAXV];
     const int m = load_fan(a.fan, k, nb);
     V4<R> pn[MAXV];
 #pragma unroll
     for (int j = 0; j < MAXV; ++j)
-        if (j < m) pn[j] = P[nb[j]];
+        if (j < m) pn[j] = ld4<V4<R>>(P + nb[j]);
     fx = fy = fz = R(0);
 #pragma unroll
     for (int j = 0; j < MAXV; ++j) {
@@ -96,8 +157,8 @@ __device__ inline void force_of(const IbArgs<R>& a, const V4<R>* P, int k, const
 }
 
 // Tiles touched by a stencil starting at unwrapped `first`, marked with `ep`.
-template <class R>
-__device__ inline void mark_tiles(const IbArgs<R>& a, const int first[3], int ep) {
+template <class R, int AS>
+__device__ inline void mark_tiles(const IbArgs<R, AS>& a, const int first[3], int ep) {
     const int L[3] = {a.g.Lx, a.g.Ly, a.g.Lz};
     int t0[3], t1[3], t2[3];
     for (int d = 0; d < 3; ++d) {
@@ -129,15 +190,15 @@ __device__ inline void mark_tiles(const IbArgs<R>& a, const int first[3], int ep
 // Stencil of a vertex at p: unwrapped first nodes and Peskin weights. False
 // (and the device flag raised) for a non-finite position or a stencil
 // through a wall.
-template <class R>
-__device__ inline bool stencil_of(const IbArgs<R>& a, const V4<R>& p, int f[3], R w[3][4]) {
+template <class R, int AS>
+__device__ inline bool stencil_of(const IbArgs<R, AS>& a, const V4<R>& p, int f[3], R w[3][4]) {
     R fr[3];
     const bool fin = isfinite(p.x) && isfinite(p.y) && isfinite(p.z);
     const bool ok = fin && stencil_base(p.x, a.g.xci[0], a.g.xcf[0], a.g.Lx, a.g.px, &f[0], &fr[0]) &&
                     stencil_base(p.y, a.g.xci[1], a.g.xcf[1], a.g.Ly, a.g.py, &f[1], &fr[1]) &&
                     stencil_base(p.z, a.g.xci[2], a.g.xcf[2], a.g.Lz, a.g.pz, &f[2], &fr[2]);
-    if (!fin) atomicOr(&a.ctl->flags, DFLAG_NONFINITE);
-    else if (!ok) atomicOr(&a.ctl->flags, DFLAG_DOMAIN);
+    if (!fin) atom_or(&a.ctl->flags, DFLAG_NONFINITE);
+    else if (!ok) atom_or(&a.ctl->flags, DFLAG_DOMAIN);
     if (ok)
         for (int d = 0; d < 3; ++d) peskin4(fr[d], w[d]);
     return ok;
@@ -205,8 +266,8 @@ constexpr int SPREAD_WCAP = 2048;  // nodes of the FP64 spreading window
 
 // Accumulate the staged vertices [lo_v, hi_v) into an LDS window and flush
 // each touched node once to F; false if their window exceeds the capacity.
-template <class R>
-__device__ bool spread_window(const IbArgs<R>& a, const Stage<R>& st, double* win, int lo_v, int hi_v) {
+template <class R, int AS>
+__device__ bool spread_window(const IbArgs<R, AS>& a, const Stage<R>& st, double* win, int lo_v, int hi_v) {
     const int t = threadIdx.x;
     const bool in = t >= lo_v && t < hi_v && st.ok[t];
     const int tv = t < PATCH ? t : 0;
@@ -250,9 +311,9 @@ __device__ bool spread_window(const IbArgs<R>& a, const Stage<R>& st, double* wi
         const int lx = i % w.e[0], rest = i / w.e[0];
         const int ly = rest % w.e[1], lz = rest / w.e[1];
         const long long n = node_index(a.g, w.o[0] + lx, w.o[1] + ly, w.o[2] + lz);
-        unsafeAtomicAdd(a.F + n, R(vx));
-        unsafeAtomicAdd(a.F + N + n, R(vy));
-        unsafeAtomicAdd(a.F + 2 * N + n, R(vz));
+        atom_add(a.F + n, R(vx));
+        atom_add(a.F + N + n, R(vy));
+        atom_add(a.F + 2 * N + n, R(vz));
     }
     __syncthreads();
     return true;
@@ -260,8 +321,8 @@ __device__ bool spread_window(const IbArgs<R>& a, const Stage<R>& st, double* wi
 
 // Forces, tile marks and spreading of patch p from positions P. With
 // `commit`, P (the final smoothed positions) also becomes the state r.
-template <class R>
-__device__ void fs_patch(const IbArgs<R>& a, int p, const V4<R>* P, int commit, Stage<R>& st, double* win) {
+template <class R, int AS>
+__device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, int commit, Stage<R>& st, double* win) {
     const int t = threadIdx.x;
     const int k = p * PATCH + t;
     const int ep = a.ctl->epoch;
@@ -270,8 +331,8 @@ __device__ void fs_patch(const IbArgs<R>& a, int p, const V4<R>* P, int commit, 
     R w[3][4];
     bool ok = false;
     if (t < PATCH && k < a.nv) {
-        const V4<R> pos = P[k];
-        if (commit) a.r[k] = pos;
+        const V4<R> pos = ld4<V4<R>>(P + k);
+        if (commit) st4(a.r + k, pos);
         ok = stencil_of(a, pos, f, w);
         if (ok) {
             R fx, fy, fz;
@@ -296,9 +357,9 @@ __device__ void fs_patch(const IbArgs<R>& a, int p, const V4<R>* P, int commit, 
         if (!st.ok[v]) continue;
         const R wt = st.w[v][0][jx] * st.w[v][1][jy] * st.w[v][2][jz];
         const long long n = node_index(a.g, st.first[v][0] + jx, st.first[v][1] + jy, st.first[v][2] + jz);
-        unsafeAtomicAdd(a.F + n, st.val[v][0] * wt);
-        unsafeAtomicAdd(a.F + N + n, st.val[v][1] * wt);
-        unsafeAtomicAdd(a.F + 2 * N + n, st.val[v][2] * wt);
+        atom_add(a.F + n, st.val[v][0] * wt);
+        atom_add(a.F + N + n, st.val[v][1] * wt);
+        atom_add(a.F + 2 * N + n, st.val[v][2] * wt);
     }
 }
 
@@ -310,8 +371,8 @@ __global__ __launch_bounds__(IBT) void k_fs_patch(IbArgs<R> a, const V4<R>* P, i
 }
 
 // ---------------------------------------------------------------- interpolation
-template <class R>
-__device__ void interp_patch(const IbArgs<R>& a, int patch, R* win) {
+template <class R, int AS>
+__device__ void interp_patch(const IbArgs<R, AS>& a, int patch, R* win) {
     const int t = threadIdx.x;
     const int k = patch * PATCH + t;
     const long long N = a.g.N;
@@ -320,7 +381,7 @@ __device__ void interp_patch(const IbArgs<R>& a, int patch, R* win) {
     bool ok = false;
     V4<R> p = V4<R>{R(0), R(0), R(0), R(0)};
     if (t < PATCH && k < a.nv) {
-        p = a.r[k];
+        p = ld4<V4<R>>(a.r + k);
         ok = stencil_of(a, p, f, w);
     }
     const Win wn = block_window(ok, f, a.wcap);
@@ -367,7 +428,7 @@ __device__ void interp_patch(const IbArgs<R>& a, int patch, R* win) {
                 }
         }
     }
-    a.o[k] = V4<R>{p.x + ux, p.y + uy, p.z + uz, R(0)};
+    st4(a.o + k, V4<R>{p.x + ux, p.y + uy, p.z + uz, R(0)});
 }
 
 template <class R>
@@ -380,15 +441,15 @@ __global__ __launch_bounds__(IBT) void k_interp_patch(IbArgs<R> a) {
 // Sec. 3.3 with x_o = o: x_q = x_p; x_p = alpha x_o + (1-alpha) mean_nb(x_q);
 // x_b = x_p - (alpha x_o + (1-alpha) x_q); x_p -= gamma x_b + sign (1-gamma)
 // mean_nb(x_b); stop when max |x_p - x_q| < tol.
-template <class R>
-__device__ inline V4<R> ring_sum(const IbArgs<R>& a, const V4<R>* X, int k, int* m_out) {
+template <class R, int AS>
+__device__ inline V4<R> ring_sum(const IbArgs<R, AS>& a, Ptr<const V4<R>, AS> X, int k, int* m_out) {
     int nb[MAXV];
     const int m = load_fan(a.fan, k, nb);
     R sx = R(0), sy = R(0), sz = R(0);
 #pragma unroll
     for (int j = 0; j < MAXV; ++j) {
         if (j < m) {
-            const V4<R> v = X[nb[j]];
+            const V4<R> v = ld4<V4<R>>(X + nb[j]);
             sx += v.x; sy += v.y; sz += v.z;
         }
     }
@@ -396,28 +457,28 @@ __device__ inline V4<R> ring_sum(const IbArgs<R>& a, const V4<R>* X, int k, int*
     return V4<R>{sx, sy, sz, R(0)};
 }
 
-template <class R>
-__device__ inline void hc_first(const IbArgs<R>& a, const V4<R>* q, int k, R alpha) {
+template <class R, int AS>
+__device__ inline void hc_first(const IbArgs<R, AS>& a, Ptr<const V4<R>, AS> q, int k, R alpha) {
     int m;
     const V4<R> s = ring_sum(a, q, k, &m);
     const R c = (R(1) - alpha) / R(m);
-    const V4<R> ok = a.o[k], qk = q[k];
+    const V4<R> ok = ld4<V4<R>>(a.o + k), qk = ld4<V4<R>>(q + k);
     const R px = alpha * ok.x + c * s.x, py = alpha * ok.y + c * s.y, pz = alpha * ok.z + c * s.z;
-    a.pp[k] = V4<R>{px, py, pz, R(0)};
-    a.bb[k] = V4<R>{px - (alpha * ok.x + (R(1) - alpha) * qk.x), py - (alpha * ok.y + (R(1) - alpha) * qk.y),
-                    pz - (alpha * ok.z + (R(1) - alpha) * qk.z), R(0)};
+    st4(a.pp + k, V4<R>{px, py, pz, R(0)});
+    st4(a.bb + k, V4<R>{px - (alpha * ok.x + (R(1) - alpha) * qk.x), py - (alpha * ok.y + (R(1) - alpha) * qk.y),
+                    pz - (alpha * ok.z + (R(1) - alpha) * qk.z), R(0)});
 }
 
-template <class R>
-__device__ inline R hc_second(const IbArgs<R>& a, const V4<R>* q, V4<R>* qn, int k, R gamma, R sgn) {
+template <class R, int AS>
+__device__ inline R hc_second(const IbArgs<R, AS>& a, Ptr<const V4<R>, AS> q, Ptr<V4<R>, AS> qn, int k, R gamma, R sgn) {
     int m;
     const V4<R> s = ring_sum(a, a.bb, k, &m);
     const R c = sgn * (R(1) - gamma) / R(m);
-    const V4<R> bk = a.bb[k], pk = a.pp[k], qk = q[k];
+    const V4<R> bk = ld4<V4<R>>(a.bb + k), pk = ld4<V4<R>>(a.pp + k), qk = ld4<V4<R>>(q + k);
     const R nx = pk.x - (gamma * bk.x + c * s.x);
     const R ny = pk.y - (gamma * bk.y + c * s.y);
     const R nz = pk.z - (gamma * bk.z + c * s.z);
-    qn[k] = V4<R>{nx, ny, nz, R(0)};
+    st4(qn + k, V4<R>{nx, ny, nz, R(0)});
     const R dx = nx - qk.x, dy = ny - qk.y, dz = nz - qk.z;
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
@@ -437,8 +498,8 @@ __device__ inline float from_bits<float>(unsigned long long b) { return __uint_a
 template <>
 __device__ inline double from_bits<double>(unsigned long long b) { return __longlong_as_double((long long)b); }
 
-template <class R>
-__device__ void hc_finish(const IbArgs<R>& a);
+template <class R, int AS>
+__device__ void hc_finish(const IbArgs<R, AS>& a);
 
 // Smoothing of one step in one launch, one work-group per surface patch.
 // Phase 1: p' and b of iteration 1 (q = o) for the patch's vertices and its
@@ -456,8 +517,8 @@ constexpr int HALO_CAP = MAXV * PATCH;  // no patch can have more halo vertices
 // device-scope release that must precede its arrival (on this device a
 // write-back of its XCD's L2), which costs more than a launch once there are
 // thousands of work-groups.
-template <class R>
-__device__ void hc_fused(const IbArgs<R>& a, int p, int npatch, bool split) {
+template <class R, int AS>
+__device__ void hc_fused(const IbArgs<R, AS>& a, int p, int npatch, bool split) {
     __shared__ V4<R> sb[PATCH + HALO_CAP];
     __shared__ V4<R> spp[PATCH], so[PATCH];
     __shared__ R bred[IBT / 64];
@@ -479,7 +540,7 @@ __device__ void hc_fused(const IbArgs<R>& a, int p, int npatch, bool split) {
             const int v = i < PATCH ? base + i : a.hids[h0 + i - PATCH];
             int m;
             const V4<R> sum = ring_sum(a, a.o, v, &m);
-            const V4<R> ov = a.o[v];
+            const V4<R> ov = ld4<V4<R>>(a.o + v);
             const R c = (R(1) - alpha) / R(m);
             const R px = alpha * ov.x + c * sum.x, py = alpha * ov.y + c * sum.y, pz = alpha * ov.z + c * sum.z;
             sb[i] = V4<R>{px - (alpha * ov.x + (R(1) - alpha) * ov.x), py - (alpha * ov.y + (R(1) - alpha) * ov.y),
@@ -507,7 +568,7 @@ __device__ void hc_fused(const IbArgs<R>& a, int p, int npatch, bool split) {
             const R nx = pk.x - (gamma * bk.x + c * sx);
             const R ny = pk.y - (gamma * bk.y + c * sy);
             const R nz = pk.z - (gamma * bk.z + c * sz);
-            a.qa[base + t] = V4<R>{nx, ny, nz, R(0)};
+            st4(a.qa + base + t, V4<R>{nx, ny, nz, R(0)});
             const R dx = nx - ok.x, dy = ny - ok.y, dz = nz - ok.z;
             d = sqrt(dx * dx + dy * dy + dz * dz);
         }
@@ -519,16 +580,16 @@ __device__ void hc_fused(const IbArgs<R>& a, int p, int npatch, bool split) {
         if (t == 0 && on) {
             R b = bred[0];
             for (int w = 1; w < IBT / 64; ++w) b = fmax(b, bred[w]);
-            atomicMax(a.red, max_bits(b));
+            atom_max(a.red, max_bits(b));
         }
         return;
     }
     if (t == 0) {
         R b = bred[0];
         for (int w = 1; w < IBT / 64; ++w) b = fmax(b, bred[w]);
-        if (on) atomicMax(a.red, max_bits(b));
+        if (on) atom_max(a.red, max_bits(b));
         __threadfence();
-        last = atomicAdd(a.red + 1, 1ull) == (unsigned long long)(npatch - 1);
+        last = atom_inc(a.red + 1) == (unsigned long long)(npatch - 1);
     }
     __syncthreads();
     if (!last) return;
@@ -551,8 +612,8 @@ __global__ __launch_bounds__(1024) void k_hc_finish(IbArgs<R> a) {
 // reduction slot: continue while not converged (rare), leave the final
 // positions in qa, record the iteration count, advance the epoch and reset
 // both reduction slots.
-template <class R>
-__device__ void hc_finish(const IbArgs<R>& a) {
+template <class R, int AS>
+__device__ void hc_finish(const IbArgs<R, AS>& a) {
     __shared__ R bred[16];
     __shared__ int more;
     const int t = threadIdx.x, nth = blockDim.x;
@@ -570,8 +631,8 @@ __device__ void hc_finish(const IbArgs<R>& a) {
     bool capped = false;
     bool converged = dmax < tol;
     if (!converged && it >= a.sp.max_iter) capped = true;
-    V4<R>* q = a.qa;
-    V4<R>* qn = a.qb;
+    Ptr<V4<R>, AS> q = a.qa;
+    Ptr<V4<R>, AS> qn = a.qb;
     while (!converged && !capped) {
         ++it;
         for (int k = t; k < a.nv; k += nth) hc_first(a, q, k, alpha);
@@ -589,13 +650,13 @@ __device__ void hc_finish(const IbArgs<R>& a) {
         __syncthreads();
         converged = more == 0;
         capped = more == 2;
-        V4<R>* tmp = q;
+        Ptr<V4<R>, AS> tmp = q;
         q = qn;
         qn = tmp;
     }
     // the newest iterate is in q
     if (q != a.qa)
-        for (int k = t; k < a.nv; k += nth) a.qa[k] = q[k];
+        for (int k = t; k < a.nv; k += nth) st4(a.qa + k, ld4<V4<R>>(q + k));
     if (t == 0) {
         a.ctl->iters = it;
         if (capped) a.ctl->cap_hits += 1;
@@ -607,19 +668,22 @@ __device__ void hc_finish(const IbArgs<R>& a) {
 
 // ---------------------------------------------------------------- ensemble forms
 // Work-group b of a batched launch takes patch map[b].y of member map[b].x.
+// The member's record is read from memory and its pointers are taken as
+// global ones.
 template <class R>
 __global__ __launch_bounds__(IBT) void k_interp_batch(const IbArgs<R>* __restrict__ args,
                                                        const int2* __restrict__ map) {
     extern __shared__ __align__(16) unsigned char dyn[];
     const int2 e = map[blockIdx.x];
-    interp_patch(args[e.x], e.y, reinterpret_cast<R*>(dyn));
+    const IbArgs<R, 1> a = to_global(args[e.x]);
+    interp_patch(a, e.y, reinterpret_cast<R*>(dyn));
 }
 
 template <class R>
 __global__ __launch_bounds__(IBT) void k_hc_fused_batch(const IbArgs<R>* __restrict__ args,
                                                         const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
-    const IbArgs<R>& a = args[e.x];
+    const IbArgs<R, 1> a = to_global(args[e.x]);
     hc_fused(a, e.y, (a.nv + PATCH - 1) / PATCH, true);
 }
 
@@ -628,7 +692,7 @@ __global__ __launch_bounds__(IBT) void k_hc_fused_batch(const IbArgs<R>* __restr
 // the iteration count and the epoch.
 template <class R>
 __global__ __launch_bounds__(1024) void k_hc_finish_batch(const IbArgs<R>* __restrict__ args) {
-    const IbArgs<R>& a = args[blockIdx.x];
+    const IbArgs<R, 1> a = to_global(args[blockIdx.x]);
     if (a.nv == 0) return;
     hc_finish(a);
 }
@@ -639,8 +703,8 @@ __global__ __launch_bounds__(IBT) void k_fs_batch(const IbArgs<R>* __restrict__ 
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ Stage<R> st;
     const int2 e = map[blockIdx.x];
-    const IbArgs<R>& a = args[e.x];
-    const V4<R>* P = commit ? (a.sp.max_iter > 0 ? a.qa : a.o) : a.r;
+    const IbArgs<R, 1> a = to_global(args[e.x]);
+    const Ptr<const V4<R>, 1> P = commit ? (a.sp.max_iter > 0 ? a.qa : a.o) : a.r;
     fs_patch(a, e.y, P, commit, st, reinterpret_cast<double*>(dyn));
 }
 

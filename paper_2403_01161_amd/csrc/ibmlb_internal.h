@@ -143,9 +143,12 @@ hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
 // Tables 0-3: linear layout with LAT_BS[q]-node blocks; tables 4-7: row
 // layout with work-groups of LAT_BS[q - 4] threads, each member taking
 // floor(LAT_BS[q - 4] / Lx) whole rows per block (nblocks[q] = -1 when a
-// member's rows exceed that size).
+// member's rows exceed that size). The first nib[q] entries of table q
+// belong to members with a droplet, the rest to members without: two
+// launches, each compiled for one kind.
 hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* maps, const int moff[8],
-                                const int nblocks[8], int cur, long long step, int variant, hipStream_t s);
+                                const int nblocks[8], const int nib[8], int cur, long long step, int variant,
+                                hipStream_t s);
 hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, double* rho_out, double* u_out, hipStream_t s);
 hipError_t launch_observables(int storage, const Geom& g, const LatticeParams& lp,

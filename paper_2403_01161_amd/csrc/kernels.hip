@@ -88,8 +88,8 @@ __device__ inline unsigned xcd_order(unsigned b, unsigned nb) {
     return b < (per << 3) ? (b & 7u) * per + (b >> 3) : b;
 }
 
-template <class S, bool NTS>
-__device__ __forceinline__ void put(S* p, S v) {
+template <bool NTS, class P, class V>
+__device__ __forceinline__ void put(P p, V v) {
     if (NTS) __builtin_nontemporal_store(v, p);
     else *p = v;
 }
@@ -130,15 +130,18 @@ __device__ __forceinline__ long long push_target(const Geom& g, long long n, int
 
 // ROWS: x-moving populations that stay in the box go to stage[xslot(i) T + t]
 // instead of global memory (t: the thread's slot, T: slots per plane).
-template <class C, bool IB, bool NTL, bool ROWS, bool NTS>
-__device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp,
-                                             const typename C::store_t* __restrict__ fin,
-                                             typename C::store_t* __restrict__ fout,
-                                             typename C::real* __restrict__ F,
-                                             typename C::real* __restrict__ U,
-                                             const int* __restrict__ mark, Ctl* ctl,
-                                             const double* __restrict__ Arow, const long long n, const int x,
-                                             const int y, const int z, typename C::store_t* stage, int t, int T) {
+// The pointer parameters are plain pointers, or global-address-space
+// pointers where the caller read them from memory (so that the accesses
+// compile to global rather than flat instructions).
+// AREG: read the gradient row into registers before any store (for
+// pointers the compiler cannot tell apart from the stores' targets);
+// otherwise it is read where a reflection needs it.
+template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, class PIn, class POut, class PR, class PM,
+          class PC, class PA>
+__device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp, PIn fin, POut fout, PR F,
+                                             PR U, PM mark, PC ctl, PA Arow,
+                                             const long long n, const int x, const int y, const int z,
+                                             typename C::store_t* stage, int t, int T) {
     using R = typename C::real;
     using S = typename C::store_t;
     const long long N = g.N;
@@ -187,19 +190,23 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
         U[N + n] = uy;
         U[2 * N + n] = uz;
     }
-    if (!(rho > R(0)) || !isfinite(ux + uy + uz)) atomicOr(&ctl->flags, DFLAG_NONFINITE);
+    if (!(rho > R(0)) || !isfinite(ux + uy + uz)) atomicOr((int*)&ctl->flags, DFLAG_NONFINITE);
 
     const R omega = R(lp.omega), kg = R(lp.kguo), rho0 = R(lp.rho0);
     const R usq = ux * ux + uy * uy + uz * uz;
     const R uF = ux * Fx + uy * Fy + uz * Fz;
 
-    // Moving-wall term of a reflected population: c_i . u_w with the wall
-    // velocity u_w = A (x - x_c + c_i / 2) at the link midpoint, written as
-    // c_i . (A (x - x_c)) + c_i . (A c_i) / 2.
+    // Moving-wall term of a reflected population: 6 w_i rho0 c_i . u_w with
+    // the wall velocity u_w = A (x - x_c + c_i / 2) at the link midpoint.
+    double Ad[9];  // uniform: scalar registers
+    if constexpr (AREG) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Ad[k] = Arow[k];
+    }
     auto wall_term = [&](int i) {
         R A[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) A[k] = R(Arow[k]);
+        for (int k = 0; k < 9; ++k) A[k] = R(AREG ? Ad[k] : double(Arow[k]));
         const R xr = R(x - g.xci[0]) - R(g.xcf[0]);
         const R yr = R(y - g.xci[1]) - R(g.xcf[1]);
         const R zr = R(z - g.xci[2]) - R(g.xcf[2]);
@@ -216,9 +223,9 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
         const long long tg = push_target<i>(g, n, x, y, z, &wall);
         if (!wall) {
             if (ROWS && CX[i] != 0) stage[xslot(i) * T + t] = enc<C>(val, lp.scale);
-            else put<S, NTS>(&fout[i * N + tg], enc<C>(val, lp.scale));
+            else put<NTS>(&fout[i * N + tg], enc<C>(val, lp.scale));
         } else {
-            put<S, NTS>(&fout[opp(i) * N + n], enc<C>(val - wall_term(i), lp.scale));
+            put<NTS>(&fout[opp(i) * N + n], enc<C>(val - wall_term(i), lp.scale));
         }
     };
 
@@ -226,7 +233,7 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
         const R w = wgt<R>(0);
         const R deq = w * (drho + rho * (R(-1.5) * usq));
         const R S0 = kg * w * (R(-3) * uF);
-        put<S, NTS>(&fout[n], enc<C>(d[0] - omega * (d[0] - deq) + S0, lp.scale));
+        put<NTS>(&fout[n], enc<C>(d[0] - omega * (d[0] - deq) + S0, lp.scale));
     }
     static_for<1, 10>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
@@ -248,10 +255,9 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
 // its row (x - c_x wrapped on a periodic axis; nothing arrives through a
 // wall, and nothing whose row shift crosses a wall, both having been
 // reflected at the source).
-template <class C, bool NTS>
-__device__ __forceinline__ void rows_receive(const Geom& g, typename C::store_t* __restrict__ fout,
-                                             const typename C::store_t* stage, long long n, int x, int y, int z,
-                                             int t, int T) {
+template <class C, bool NTS, class POut>
+__device__ __forceinline__ void rows_receive(const Geom& g, POut fout, const typename C::store_t* stage, long long n,
+                                             int x, int y, int z, int t, int T) {
     const long long N = g.N;
     const long long LxLy = (long long)g.Lx * g.Ly;
     const int row0 = t - x;  // slot of x = 0 in this row
@@ -268,7 +274,7 @@ __device__ __forceinline__ void rows_receive(const Geom& g, typename C::store_t*
         if (CY[i] == -1 && y == 0) { if (!g.py) return; tg += LxLy; }
         if (CZ[i] == 1 && z == g.Lz - 1) { if (!g.pz) return; tg -= N; }
         if (CZ[i] == -1 && z == 0) { if (!g.pz) return; tg += N; }
-        put<typename C::store_t, NTS>(&fout[i * N + tg], stage[xslot(i) * T + row0 + xs]);
+        put<NTS>(&fout[i * N + tg], stage[xslot(i) * T + row0 + xs]);
     });
 }
 
@@ -285,7 +291,8 @@ __global__ __launch_bounds__(BS) void k_lattice(Geom g, LatticeParams lp,
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    lattice_node<C, IB, NTL, false, false>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0, 0);
+    lattice_node<C, IB, NTL, false, false, false>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0,
+                                                  0);
 }
 
 // Row layout: `rows` whole x-rows per work-group (blockDim = rows * Lx <= 512).
@@ -312,7 +319,8 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticePara
     const long long n = (long long)row * g.Lx + x;
     const bool act = n < g.N;
     if (act)
-        lattice_node<C, IB, NTL, true, NTS>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, stage, t, T);
+        lattice_node<C, IB, NTL, true, NTS, false>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, stage, t,
+                                                  T);
     __syncthreads();
     if (act) rows_receive<C, NTS>(g, fout, stage, n, x, y, z, t, T);
 }
@@ -320,58 +328,75 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticePara
 // Ensemble forms: one launch covers every member's lattice; work-group b
 // updates block map[b].y of member map[b].x (linear: BS nodes per block;
 // rows: floor(blockDim / Lx) whole rows of that member per block).
-template <class C, bool NTL, int BS>
-__global__ __launch_bounds__(BS) void k_lattice_batch(const LatDesc* __restrict__ desc, const int2* __restrict__ map,
-                                                       int cur, long long arow, int xcd) {
-    using R = typename C::real;
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+// A member's descriptor in registers, its pointers in the global address
+// space.
+template <class C>
+struct MemberView {
     using S = typename C::store_t;
+    using R = typename C::real;
+    Geom g;
+    LatticeParams lp;
+    gptr<const S> fin;
+    gptr<S> fout;
+    gptr<R> F, U;
+    gptr<const int> mark;
+    gptr<Ctl> ctl;
+    gptr<const double> A;
+    int ib;
+    __device__ MemberView(const LatDesc& D, int cur)
+        : g(D.g), lp(D.lp), fin((gptr<const S>)D.f[cur]), fout((gptr<S>)D.f[cur ^ 1]), F((gptr<R>)D.F),
+          U((gptr<R>)D.u), mark((gptr<const int>)D.mark), ctl((gptr<Ctl>)D.ctl), A((gptr<const double>)D.A), ib(D.ib) {}
+};
+
+// Waves per SIMD the batched kernel is compiled for: six fit the 16- and
+// 32-bit forms in 80 registers without spills; FP64 takes what it needs.
+template <class C>
+constexpr int batch_waves = 6;
+template <>
+constexpr int batch_waves<SF64> = 1;
+
+// IB: every member the launch covers carries a droplet, or none does.
+template <class C, bool IB, bool NTL, int BS>
+__global__ __launch_bounds__(BS, batch_waves<C>) void k_lattice_batch(const LatDesc* __restrict__ desc, const int2* __restrict__ map,
+                                                       int cur, long long arow, int xcd) {
     const int2 e = map[xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x];
-    const LatDesc& D = desc[e.x];
+    const MemberView<C> M(desc[e.x], cur);
     const long long n = (long long)e.y * BS + threadIdx.x;
-    if (n >= D.g.N) return;
+    if (n >= M.g.N) return;
     int x, y, z;
-    node_xyz(D.g, n, x, y, z);
-    const double* Arow = D.A + arow;
-    if (D.ib)
-        lattice_node<C, true, NTL, false, false>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F,
-                                                 (R*)D.u, D.mark, D.ctl, Arow, n, x, y, z, nullptr, 0, 0);
-    else
-        lattice_node<C, false, NTL, false, false>(D.g, D.lp, (const S*)D.f[cur], (S*)D.f[cur ^ 1], (R*)D.F,
-                                                  (R*)D.u, D.mark, D.ctl, Arow, n, x, y, z, nullptr, 0, 0);
+    node_xyz(M.g, n, x, y, z);
+    const gptr<const double> Arow = M.A + arow;
+    lattice_node<C, IB, NTL, false, false, true>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
+                                           nullptr, 0, 0);
 }
 
-template <class C, bool NTL, bool NTS>
+template <class C, bool IB, bool NTL, bool NTS>
 __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows_batch(const LatDesc* __restrict__ desc,
                                                                    const int2* __restrict__ map, int cur,
                                                                    long long arow) {
-    using R = typename C::real;
     using S = typename C::store_t;
     extern __shared__ __align__(16) unsigned char dyn[];
     S* stage = reinterpret_cast<S*>(dyn);
     const int2 e = map[blockIdx.x];
-    const LatDesc& D = desc[e.x];
-    const int rows = int(blockDim.x) / D.g.Lx;
-    const int T = rows * D.g.Lx;
+    const MemberView<C> M(desc[e.x], cur);
+    const int rows = int(blockDim.x) / M.g.Lx;
+    const int T = rows * M.g.Lx;
     const int t = threadIdx.x;
-    const int rl = t / D.g.Lx;
-    const int x = t - rl * D.g.Lx;
+    const int rl = t / M.g.Lx;
+    const int x = t - rl * M.g.Lx;
     const int row = e.y * rows + rl;
-    const int z = row / D.g.Ly, y = row - z * D.g.Ly;
-    const long long n = (long long)row * D.g.Lx + x;
-    const bool act = t < T && n < D.g.N;
-    const double* Arow = D.A + arow;
-    const S* fin = (const S*)D.f[cur];
-    S* fout = (S*)D.f[cur ^ 1];
-    if (act) {
-        if (D.ib)
-            lattice_node<C, true, NTL, true, NTS>(D.g, D.lp, fin, fout, (R*)D.F, (R*)D.u, D.mark, D.ctl, Arow, n,
-                                                  x, y, z, stage, t, T);
-        else
-            lattice_node<C, false, NTL, true, NTS>(D.g, D.lp, fin, fout, (R*)D.F, (R*)D.u, D.mark, D.ctl, Arow,
-                                                   n, x, y, z, stage, t, T);
-    }
+    const int z = row / M.g.Ly, y = row - z * M.g.Ly;
+    const long long n = (long long)row * M.g.Lx + x;
+    const bool act = t < T && n < M.g.N;
+    const gptr<const double> Arow = M.A + arow;
+    if (act)
+        lattice_node<C, IB, NTL, true, NTS, true>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
+                                            stage, t, T);
     __syncthreads();
-    if (act) rows_receive<C, NTS>(D.g, fout, stage, n, x, y, z, t, T);
+    if (act) rows_receive<C, NTS>(M.g, M.fout, stage, n, x, y, z, t, T);
 }
 
 // Diagnostic moments: rho and u (with F/2) of the current populations; the
@@ -738,59 +763,79 @@ hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, c
     return hipGetLastError();
 }
 
-template <class C, bool NTL>
+template <class C, bool IB, bool NTL>
 static void launch_batch_v(int bsi, const LatDesc* desc, const int2* map, int nblocks, int cur, long long step,
                            int xcd, hipStream_t s) {
+    if (nblocks <= 0) return;
     switch (bsi) {
         case 0:
-            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[0]>), dim3(nblocks), dim3(LAT_BS[0]), 0, s, desc, map,
-                               cur, step, xcd);
+            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[0]>), dim3(nblocks), dim3(LAT_BS[0]), 0, s, desc,
+                               map, cur, step, xcd);
             break;
         case 1:
-            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[1]>), dim3(nblocks), dim3(LAT_BS[1]), 0, s, desc, map,
-                               cur, step, xcd);
+            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[1]>), dim3(nblocks), dim3(LAT_BS[1]), 0, s, desc,
+                               map, cur, step, xcd);
             break;
         case 2:
-            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[2]>), dim3(nblocks), dim3(LAT_BS[2]), 0, s, desc, map,
-                               cur, step, xcd);
+            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[2]>), dim3(nblocks), dim3(LAT_BS[2]), 0, s, desc,
+                               map, cur, step, xcd);
             break;
         default:
-            hipLaunchKernelGGL((k_lattice_batch<C, NTL, LAT_BS[3]>), dim3(nblocks), dim3(LAT_BS[3]), 0, s, desc, map,
-                               cur, step, xcd);
+            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[3]>), dim3(nblocks), dim3(LAT_BS[3]), 0, s, desc,
+                               map, cur, step, xcd);
             break;
     }
 }
 
-template <class C, bool NTL, bool NTS>
+template <class C, bool IB, bool NTL, bool NTS>
 static void launch_rows_batch(int T, const LatDesc* desc, const int2* map, int nblocks, int cur, long long step,
                               hipStream_t s) {
+    if (nblocks <= 0) return;
     using S = typename C::store_t;
-    hipLaunchKernelGGL((k_lattice_rows_batch<C, NTL, NTS>), dim3(nblocks), dim3(T), size_t(NXMOVE) * T * sizeof(S),
-                       s, desc, map, cur, step);
+    hipLaunchKernelGGL((k_lattice_rows_batch<C, IB, NTL, NTS>), dim3(nblocks), dim3(T),
+                       size_t(NXMOVE) * T * sizeof(S), s, desc, map, cur, step);
+}
+
+template <class C, bool NTL, bool NTS>
+static void launch_rows_both(int T, const LatDesc* desc, const int2* map, int nblocks, int nib, int cur,
+                             long long step, hipStream_t s) {
+    launch_rows_batch<C, true, NTL, NTS>(T, desc, map, nib, cur, step, s);
+    launch_rows_batch<C, false, NTL, NTS>(T, desc, map + nib, nblocks - nib, cur, step, s);
+}
+
+template <class C, bool NTL>
+static void launch_batch_both(int bsi, const LatDesc* desc, const int2* map, int nblocks, int nib, int cur,
+                              long long step, int xcd, hipStream_t s) {
+    launch_batch_v<C, true, NTL>(bsi, desc, map, nib, cur, step, xcd, s);
+    launch_batch_v<C, false, NTL>(bsi, desc, map + nib, nblocks - nib, cur, step, xcd, s);
 }
 
 hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* maps, const int moff[8],
-                                const int nblocks[8], int cur, long long step, int variant, hipStream_t s) {
+                                const int nblocks[8], const int nib[8], int cur, long long step, int variant,
+                                hipStream_t s) {
     if (variant < 0 || variant >= STEP_VARIANTS) return hipErrorInvalidValue;
     const int bsi = (variant >> 1) & 3;
     const int xb = variant & VAR_X ? 1 : 0;
     if (variant & VAR_ROWS) {
         const int q = 4 + bsi;
         if (nblocks[q] <= 0) return hipErrorInvalidValue;
+        const int T = LAT_BS[bsi];
         DISPATCH_STORAGE(storage, C, {
             if (variant & 1) {
-                if (xb) launch_rows_batch<C, true, true>(LAT_BS[bsi], desc, maps + moff[q], nblocks[q], cur, step, s);
-                else launch_rows_batch<C, true, false>(LAT_BS[bsi], desc, maps + moff[q], nblocks[q], cur, step, s);
+                if (xb) launch_rows_both<C, true, true>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
+                else launch_rows_both<C, true, false>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
             } else {
-                if (xb) launch_rows_batch<C, false, true>(LAT_BS[bsi], desc, maps + moff[q], nblocks[q], cur, step, s);
-                else launch_rows_batch<C, false, false>(LAT_BS[bsi], desc, maps + moff[q], nblocks[q], cur, step, s);
+                if (xb) launch_rows_both<C, false, true>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
+                else launch_rows_both<C, false, false>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
             }
         });
         return hipGetLastError();
     }
     DISPATCH_STORAGE(storage, C, {
-        if (variant & 1) launch_batch_v<C, true>(bsi, desc, maps + moff[bsi], nblocks[bsi], cur, step, xb, s);
-        else launch_batch_v<C, false>(bsi, desc, maps + moff[bsi], nblocks[bsi], cur, step, xb, s);
+        if (variant & 1)
+            launch_batch_both<C, true>(bsi, desc, maps + moff[bsi], nblocks[bsi], nib[bsi], cur, step, xb, s);
+        else
+            launch_batch_both<C, false>(bsi, desc, maps + moff[bsi], nblocks[bsi], nib[bsi], cur, step, xb, s);
     });
     return hipGetLastError();
 }
