@@ -349,7 +349,7 @@ def precision_bench(dev, steps, every=500):
             "steps": steps, "sample_every": every, "formats": res}
 
 
-def counters_sequence(dev, storage, box="128"):
+def counters_sequence(dev, storage, box="128", fixed_variant=None):
     """Kernels whose HBM counters are read: a plain 256 MiB copy whose source
     was first pushed out of the 256 MB last-level cache by a 1 GiB fill (three
     times; the known 256 MiB read + 256 MiB write calibrate the counters), and
@@ -370,7 +370,8 @@ def counters_sequence(dev, storage, box="128"):
     table = ou_gradient_table(26, w["corr"], w["G"], seed=w["seed"])
     sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage=w["storage"],
                            A0=table[0], device=dev)
-    variant = sim.autotune(5)
+    variant = sim.autotune(5) if fixed_variant is None else fixed_variant
+    sim.set_variant(variant)
     sim.step_table(table[:5])
     sim.step_table(table[5:25])
     torch.cuda.synchronize()
@@ -392,6 +393,8 @@ def main():
                     help="steps of the 256^3 large-footprint leg (0 skips it)")
     ap.add_argument("--precision", type=int, default=0, metavar="STEPS",
                     help="run only the storage-precision study (256^3, every format) for STEPS steps")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="with --counters: run this step variant instead of the autotuner's choice")
     ap.add_argument("--counters", nargs="?", const="128", choices=["128", "256"], default=None,
                     help="short fixed sequence for hardware-counter runs: 3 device copies of "
                          "256 MiB (calibration) and 20 steps of the single-droplet workload")
@@ -408,7 +411,7 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.counters:
-        counters_sequence(dev, args.storage, args.counters)
+        counters_sequence(dev, args.storage, args.counters, args.variant)
         return
     if args.precision:
         print(json.dumps({"precision": precision_bench(dev, args.precision)}), flush=True)

@@ -187,19 +187,18 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  * as its own launch and ignore the bit.
  *
  * Autotuner: picks the variant for this configuration by timing `reps` whole
- * steps with each lattice variant that can run, in four interleaved rounds,
- * then (with a droplet) the chosen one with and without bit 5, all from a
- * snapshot of the state that is restored afterwards (the state after the
- * call equals the state before; the force field is spread again at the next
- * step). Lattice times within 1 % of the fastest count as ties, which go to
- * the default variant, else to the lowest index; bit 5 is set only when it
- * is more than 1 % faster. Synchronises the stream.
+ * steps with each lattice variant that can run (bit 5 set), in four
+ * interleaved rounds, from a snapshot of the state that is restored
+ * afterwards (the state after the call equals the state before; the force
+ * field is spread again at the next step). Times within 1 % of the fastest
+ * count as ties, which go to the default variant, else to the lowest index.
+ * Synchronises the stream.
  * *variant (may be NULL) receives the choice. Errors: EINVAL, ENOMEM,
  * EDEVICE, sticky.
  *
  * ibm_lb_set_variant selects a variant directly (EINVAL if out of range or
- * the row layout cannot take this box). The default is 1 (linear layout,
- * 128-thread work-groups, non-temporal loads). */
+ * the row layout cannot take this box). The default is 33 (linear layout,
+ * 128-thread work-groups, non-temporal loads, bit 5). */
 int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);
 int ibm_lb_set_variant(ibm_lb* h, int32_t variant);
 

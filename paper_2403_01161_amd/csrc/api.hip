@@ -340,7 +340,7 @@ struct ibm_lb {
     int sticky = IBM_LB_OK;
     bool f_ready = false;        // F and tile marks hold the spread of the current mesh
     std::vector<int> perm;       // internal vertex k is caller vertex perm[k]
-    int lattice_variant = 1;     // non-temporal loads, 128-thread work-groups until ibm_lb_autotune
+    int lattice_variant = 1 | VAR_HC_SPLIT;  // non-temporal loads, 128-thread work-groups, split smoothing
     double* stage = nullptr;     // pinned host staging for gradient rows
     hipEvent_t stage_done = nullptr;
     bool timing = false;
@@ -888,20 +888,15 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
                 if (e == hipSuccess) best_of[k] = std::min(best_of[k], ms);
             }
     };
-    // first the lattice variants (finish of the smoothing in its last
-    // work-group), then, with a droplet, that finish as its own launch
+    // the lattice variants, each with the smoothing's finish as its own
+    // launch (measured faster than finishing in the last work-group, whose
+    // arrival needs a device-scope release in every work-group)
     int cand[LATTICE_VARIANTS];
     float best_of[LATTICE_VARIANTS];
-    for (int v = 0; v < LATTICE_VARIANTS; ++v) cand[v] = v;
+    for (int v = 0; v < LATTICE_VARIANTS; ++v) cand[v] = v | VAR_HC_SPLIT;
     tune(cand, LATTICE_VARIANTS, best_of);
     int best_v = before;
-    if (e == hipSuccess && rc == IBM_LB_OK) best_v = pick_variant(best_of);
-    if (h->nv > 0 && e == hipSuccess && rc == IBM_LB_OK) {
-        const int pair[2] = {best_v, best_v | VAR_HC_SPLIT};
-        float t2[2];
-        tune(pair, 2, t2);
-        if (e == hipSuccess && rc == IBM_LB_OK && t2[1] < 0.99f * t2[0]) best_v = pair[1];
-    }
+    if (e == hipSuccess && rc == IBM_LB_OK) best_v = pick_variant(best_of) | VAR_HC_SPLIT;
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     h->timing = timing;
