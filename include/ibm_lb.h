@@ -220,8 +220,9 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
  * may differ in box size, periodicity, tau, sigma, mesh and gradient history
  * but share one storage format. Each step is one batched launch of the fused
  * lattice kernel over every member's nodes, then the batched IB kernels over
- * every member's surface patches; work-groups map to members by offset
- * tables, so heterogeneous boxes balance by tile count.
+ * every member's surface patches; work-groups map to members by per-block
+ * tables, so heterogeneous boxes balance by block count. Runs of steps are
+ * replayed as captured HIP graphs (ibm_lb_batch_set_graph).
  *
  * ibm_lb_batch_init: cfgs[n] as for ibm_lb_init (each member's workspace
  *   rule applies; cfgs[i].stream is ignored); all work goes to `stream`.
@@ -239,6 +240,12 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
  *   when every member's Lx fits in the work-group.
  * ibm_lb_batch_set_variant: as ibm_lb_set_variant (EINVAL if the variant
  *   cannot run on every member).
+ * ibm_lb_batch_set_graph: runs of `steps` batched steps (even, at most 4096;
+ *   default 32) go to the GPU as one captured HIP graph, replayed with the
+ *   gradient rows of the run; 0 uses plain launches throughout. Graphs are
+ *   captured on first use for each population parity and lattice variant
+ *   (on a private stream; nothing runs during capture) and hold no memset
+ *   nodes. Synchronises the ensemble's stream. Errors: EINVAL, EDEVICE.
  * ibm_lb_batch_destroy frees the ensemble and its members. */
 int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb_batch** out);
 int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps);
@@ -246,6 +253,7 @@ int ibm_lb_batch_observables(ibm_lb_batch* b, ibm_lb_obs* out);
 int ibm_lb_batch_member(ibm_lb_batch* b, int32_t i, ibm_lb** out);
 int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant);
 int ibm_lb_batch_set_variant(ibm_lb_batch* b, int32_t variant);
+int ibm_lb_batch_set_graph(ibm_lb_batch* b, int32_t steps);
 void ibm_lb_batch_destroy(ibm_lb_batch* b);
 
 /* ---- adjoint: reverse-mode derivatives of the droplet deformation ----

@@ -1130,6 +1130,13 @@ struct ibm_lb_batch {
     int64_t step = 0;
     bool f_ready = false;
     int variant = 1;
+    // HIP graphs of `graph_steps` batched steps (even; 0 = plain launches),
+    // one per population parity, recaptured when the variant changes
+    int graph_steps = 32;
+    LatDesc* lat_desc_g = nullptr;  // descriptors whose gradient rows move with each replay
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gvariant[2] = {-1, -1};
 };
 
 namespace {
@@ -1229,6 +1236,9 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     if ((e = hipMalloc((void**)&b->patch_map, sizeof(int2) * pm.size())) != hipSuccess) return bail(e, "maps");
     if ((e = hipMemcpy(b->lat_desc, ld.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "descriptors");
+    if ((e = hipMalloc((void**)&b->lat_desc_g, sizeof(LatDesc) * n)) != hipSuccess) return bail(e, "descriptors");
+    if ((e = hipMemcpy(b->lat_desc_g, ld.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "descriptors");
     if ((e = hipMemcpy(b->lat_map, lall.data(), sizeof(int2) * lall.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "maps");
     if ((e = hipMemcpy(b->ib_args, args.data(), rec * n, hipMemcpyHostToDevice)) != hipSuccess)
@@ -1242,6 +1252,51 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     }
     if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return bail(e, "sync");
     *out = b;
+    return IBM_LB_OK;
+}
+
+namespace {
+void drop_graphs(ibm_lb_batch* b) {
+    for (int k = 0; k < 2; ++k) {
+        if (b->gexec[k]) (void)hipGraphExecDestroy(b->gexec[k]);
+        b->gexec[k] = nullptr;
+        b->gvariant[k] = -1;
+    }
+}
+
+// Capture graph_steps batched steps starting from population copy `cur`
+// (on a private stream; nothing runs), reading gradient rows 0, 1, ... of
+// the graph descriptors.
+hipError_t capture_steps(ibm_lb_batch* b, int cur, hipGraphExec_t* out) {
+    hipError_t e = hipSuccess;
+    if (!b->cap_stream && (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < b->graph_steps && le == hipSuccess; ++k) {
+        le = launch_lattice_batch(b->storage, b->lat_desc_g, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib,
+                                  cur ^ (k & 1), 9ll * k, b->variant, b->cap_stream);
+        if (le == hipSuccess)
+            le = launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, b->n, b->cap_stream);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap_stream, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le != hipSuccess ? le : e;
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+}  // namespace
+
+int ibm_lb_batch_set_graph(ibm_lb_batch* b, int32_t steps) {
+    if (!b) return fail(IBM_LB_EINVAL, "batch handle is NULL");
+    if (steps < 0 || steps > ACAP || (steps & 1)) return fail(IBM_LB_EINVAL, "graph steps must be even, 0..4096");
+    HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    drop_graphs(b);
+    b->graph_steps = steps;
     return IBM_LB_OK;
 }
 
@@ -1268,7 +1323,20 @@ int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps) {
         double* dst = b->Atab + hf * tab;
         HIP_TRY(hipMemcpyAsync(dst, sg, sizeof(double) * tab, hipMemcpyHostToDevice, b->stream), "upload tables");
         HIP_TRY(hipEventRecord(b->stage_done[hf], b->stream), "hipEventRecord");
-        for (int j = 0; j < len; ++j) {
+        int j = 0;
+        // whole graphs first (an even number of steps leaves the parity as it was)
+        for (const int G = b->graph_steps; G > 0 && len - j >= G; j += G) {
+            const int c = b->cur;
+            if (!b->gexec[c] || b->gvariant[c] != b->variant) {
+                if (b->gexec[c]) (void)hipGraphExecDestroy(b->gexec[c]);
+                b->gexec[c] = nullptr;
+                HIP_TRY(capture_steps(b, c, &b->gexec[c]), "graph capture");
+                b->gvariant[c] = b->variant;
+            }
+            HIP_TRY(launch_set_rows(b->lat_desc_g, n, dst + 9ll * j, 9ll * ACAP, b->stream), "set rows");
+            HIP_TRY(hipGraphLaunch(b->gexec[c], b->stream), "hipGraphLaunch");
+        }
+        for (; j < len; ++j) {
             HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib, b->cur,
                                          (long long)hf * tab + 9ll * j, b->variant, b->stream),
                     "lattice batch launch");
@@ -1402,7 +1470,10 @@ void ibm_lb_batch_destroy(ibm_lb_batch* b) {
         if (ev) (void)hipEventDestroy(ev);
     if (b->stage) (void)hipHostFree(b->stage);
     if (b->Atab) (void)hipFree(b->Atab);
+    drop_graphs(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->lat_desc) (void)hipFree(b->lat_desc);
+    if (b->lat_desc_g) (void)hipFree(b->lat_desc_g);
     if (b->lat_map) (void)hipFree(b->lat_map);
     if (b->ib_args) (void)hipFree(b->ib_args);
     if (b->patch_map) (void)hipFree(b->patch_map);

@@ -149,6 +149,8 @@ hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
 hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* maps, const int moff[8],
                                 const int nblocks[8], const int nib[8], int cur, long long step, int variant,
                                 hipStream_t s);
+// desc[i].A = base + i * stride for the n members (on the stream).
+hipError_t launch_set_rows(LatDesc* desc, int n, const double* base, long long stride, hipStream_t s);
 hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, double* rho_out, double* u_out, hipStream_t s);
 hipError_t launch_observables(int storage, const Geom& g, const LatticeParams& lp,

@@ -840,6 +840,18 @@ hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* ma
     return hipGetLastError();
 }
 
+// Point every member's gradient rows at base + i * stride (graph replays of
+// the batched step read rows 0, 1, ... from there).
+__global__ void k_set_rows(LatDesc* desc, int n, const double* base, long long stride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) desc[i].A = base + (long long)i * stride;
+}
+
+hipError_t launch_set_rows(LatDesc* desc, int n, const double* base, long long stride, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_rows, dim3((n + 63) / 64), dim3(64), 0, s, desc, n, base, stride);
+    return hipGetLastError();
+}
+
 #define DISPATCH_REAL(storage, R, ...)                                   \
     if ((storage) == IBM_LB_F64) { using R = double; __VA_ARGS__; }     \
     else { using R = float; __VA_ARGS__; }

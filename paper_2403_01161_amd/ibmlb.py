@@ -58,7 +58,8 @@ EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_t
            "ibm_lb_timing_enable",
            "ibm_lb_timing_read", "ibm_lb_destroy", "ibm_lb_strerror", "ibm_lb_last_error",
            "ibm_lb_batch_init", "ibm_lb_batch_step", "ibm_lb_batch_observables", "ibm_lb_batch_member",
-           "ibm_lb_batch_autotune", "ibm_lb_batch_set_variant", "ibm_lb_batch_destroy", "ibm_lb_objective_grad",
+           "ibm_lb_batch_autotune", "ibm_lb_batch_set_variant", "ibm_lb_batch_set_graph",
+           "ibm_lb_batch_destroy", "ibm_lb_objective_grad",
            "ibm_lb_adjoint_segment"]
 
 
@@ -93,6 +94,7 @@ def lib():
         L.ibm_lb_batch_member.argtypes = [vp, i32, C.POINTER(vp)]
         L.ibm_lb_batch_autotune.argtypes = [vp, i32, C.POINTER(C.c_int32)]
         L.ibm_lb_batch_set_variant.argtypes = [vp, i32]
+        L.ibm_lb_batch_set_graph.argtypes = [vp, i32]
         L.ibm_lb_batch_destroy.argtypes = [vp]
         L.ibm_lb_batch_destroy.restype = None
         L.ibm_lb_objective_grad.argtypes = [vp, dp, vp]
@@ -365,6 +367,10 @@ class Ensemble:
 
     def set_variant(self, variant):
         _check(lib().ibm_lb_batch_set_variant(self._h, int(variant)), "ibm_lb_batch_set_variant")
+
+    def set_graph(self, steps):
+        """Replay runs of `steps` batched steps as captured HIP graphs (0: plain launches)."""
+        _check(lib().ibm_lb_batch_set_graph(self._h, int(steps)), "ibm_lb_batch_set_graph")
 
     def step(self, A_tables):
         """A_tables: host array [n, nsteps, 9]."""
