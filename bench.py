@@ -194,22 +194,37 @@ def counter_traffic(storage, box="128cubed"):
     return float(t.group(1))
 
 
-def cpu_baseline(w, table, steps):
+def cpu_baseline(w, table, steps, single_steps=8):
+    """The FP64 oracle on this host's cores (its lattice sweeps use OpenMP
+    over z-planes, the IB part is serial), then on one thread for a shorter
+    sample of the same run."""
+    import ctypes
     import numpy as np
     import oracle
     kw = dict(tau=w["tau"], sigma=w["sigma"], radius=w["R"], vertices=w["V"], triangles=w["T"],
               A0=table[0])
+    gomp = ctypes.CDLL("libgomp.so.1")  # the OpenMP runtime the oracle library uses
+    cores = int(gomp.omp_get_max_threads())
+    rows = table[1:1 + steps]
+    rows1 = table[1 + steps:1 + steps + single_steps]
+    steps, single_steps = len(rows), len(rows1)
     ref = oracle.Oracle(w["L"], **kw)
     ref.step_table(table[:1])
     t0 = time.perf_counter()
-    ref.step_table(table[1:1 + steps])
+    ref.step_table(rows)
     dt = time.perf_counter() - t0
+    gomp.omp_set_num_threads(1)
+    t1 = time.perf_counter()
+    ref.step_table(rows1)
+    dt1 = time.perf_counter() - t1
+    gomp.omp_set_num_threads(cores)
     nodes = int(np.prod(w["L"]))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     ref.close()
     return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, same 128^3 workload, {steps} steps after 1 warm-up step "
-                      f"({dt:.1f} s), OpenMP over z-planes for the lattice, serial IB"}
+                      f"({dt:.1f} s) on {cores} threads (OpenMP over z-planes for the lattice, serial IB), "
+                      f"then {single_steps} steps on 1 thread ({dt1:.1f} s)",
+            "single_thread_value": nodes * single_steps / dt1 / 1e6 if single_steps else None}
 
 
 def adjoint_workload():
