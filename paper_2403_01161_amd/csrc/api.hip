@@ -1193,7 +1193,6 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
         L.mark = h->d.mark;
         L.ctl = h->d.ctl;
         L.A = nullptr;  // set below, once the table is allocated
-        L.ib = h->nv > 0 ? 1 : 0;
         // members with a droplet first in every map, then the others (two
         // launches, each compiled for one kind)
         std::vector<int2>* dst = h->nv > 0 ? lm : lm_plain;

@@ -96,7 +96,6 @@ struct LatDesc {
     int* mark;
     Ctl* ctl;
     const double* A;
-    int ib;
 };
 
 // Vertices per surface patch: the set-up renumbering makes every run of

@@ -345,10 +345,9 @@ struct MemberView {
     gptr<const int> mark;
     gptr<Ctl> ctl;
     gptr<const double> A;
-    int ib;
     __device__ MemberView(const LatDesc& D, int cur)
         : g(D.g), lp(D.lp), fin((gptr<const S>)D.f[cur]), fout((gptr<S>)D.f[cur ^ 1]), F((gptr<R>)D.F),
-          U((gptr<R>)D.u), mark((gptr<const int>)D.mark), ctl((gptr<Ctl>)D.ctl), A((gptr<const double>)D.A), ib(D.ib) {}
+          U((gptr<R>)D.u), mark((gptr<const int>)D.mark), ctl((gptr<Ctl>)D.ctl), A((gptr<const double>)D.A) {}
 };
 
 // Waves per SIMD the batched kernel is compiled for: six fit the 16- and
