@@ -125,10 +125,13 @@ def describe_variant(v):
     else:
         d["xcd_grouped_order"] = bool(v & 8)
     d["smoothing_finish_launch"] = bool(v & 32)
+    d["in_place_streaming"] = bool(v & 64)
     return d
 
 
 def lattice_kernel_name(v):
+    if v & 64:
+        return "k_lattice_aa"
     return "k_lattice_rows" if v & 16 else "k_lattice"
 
 
@@ -409,7 +412,8 @@ def main():
     ap.add_argument("--precision", type=int, default=0, metavar="STEPS",
                     help="run only the storage-precision study (256^3, every format) for STEPS steps")
     ap.add_argument("--variant", type=int, default=None,
-                    help="with --counters: run this step variant instead of the autotuner's choice")
+                    help="run this step variant instead of the autotuner's choice (the single-droplet "
+                         "128^3 leg and --counters)")
     ap.add_argument("--counters", nargs="?", const="128", choices=["128", "256"], default=None,
                     help="short fixed sequence for hardware-counter runs: 3 device copies of "
                          "256 MiB (calibration) and 20 steps of the single-droplet workload")
@@ -439,7 +443,11 @@ def main():
     dtab = torch.from_numpy(table).to(dev)
     nodes = int(np.prod(w["L"]))
     nv = len(w["V"])
-    variant = sim.autotune(20)
+    if args.variant is None:
+        variant = sim.autotune(20)
+    else:
+        variant = args.variant
+        sim.set_variant(variant)
 
     sim.step_table(dtab[:W])
     torch.cuda.synchronize()

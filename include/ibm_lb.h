@@ -165,7 +165,7 @@ size_t ibm_lb_state_bytes(const ibm_lb* h);
 int ibm_lb_save(ibm_lb* h, void* dst, size_t n);
 int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
 
-/* Step variants, 0 <= variant < 64. Bits 0-4 select the lattice kernel's
+/* Step variants, 0 <= variant < 128. Bits 0-4 select the lattice kernel's
  * variant (all compute the same per-node arithmetic; they differ only in how
  * nodes map to work-groups and how populations reach memory):
  *   bit 0     non-temporal population loads;
@@ -185,19 +185,30 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  * instead of in the last of the smoothing's work-groups to finish (which
  * needs a device-scope release in every work-group); ensembles always run it
  * as its own launch and ignore the bit.
+ * Bit 6 (linear layout only; single droplets only) streams in place: one
+ * population copy, read and written by the same thread at the same
+ * locations, with even and odd steps in two index mappings (the AA pattern
+ * of Bailey et al., 2009). After an odd number of such steps the copy holds
+ * the populations in the odd mapping; every call that reads them (fields,
+ * observables, save, objective gradient) or steps with another variant
+ * first streams them back to natural order into the second copy, one extra
+ * pass over the populations. The adjoint's recompute of a segment runs
+ * without bit 6 (it records every step).
  *
  * Autotuner: picks the variant for this configuration by timing `reps` whole
- * steps with each lattice variant that can run (bit 5 set), in four
+ * steps with each lattice variant that can run (bit 5 set; with and without
+ * bit 6), in four
  * interleaved rounds, from a snapshot of the state that is restored
  * afterwards (the state after the call equals the state before; the force
  * field is spread again at the next step). Times within 1 % of the fastest
- * count as ties, which go to the default variant, else to the lowest index.
+ * count as ties, which go to the default variant, else to the first
+ * candidate (bit 6 clear before bit 6 set, then by index).
  * Synchronises the stream.
  * *variant (may be NULL) receives the choice. Errors: EINVAL, ENOMEM,
  * EDEVICE, sticky.
  *
- * ibm_lb_set_variant selects a variant directly (EINVAL if out of range or
- * the row layout cannot take this box). The default is 33 (linear layout,
+ * ibm_lb_set_variant selects a variant directly (EINVAL if out of range,
+ * bits 4 and 6 together, or the row layout cannot take this box). The default is 33 (linear layout,
  * 128-thread work-groups, non-temporal loads, bit 5). */
 int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);
 int ibm_lb_set_variant(ibm_lb* h, int32_t variant);
@@ -239,7 +250,7 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
  *   floor(size / Lx) whole rows of one member, so a row variant runs only
  *   when every member's Lx fits in the work-group.
  * ibm_lb_batch_set_variant: as ibm_lb_set_variant (EINVAL if the variant
- *   cannot run on every member).
+ *   cannot run on every member, or has bit 6).
  * ibm_lb_batch_set_graph: runs of `steps` batched steps (even, at most 4096;
  *   default 32) go to the GPU as one captured HIP graph, replayed with the
  *   gradient rows of the run; 0 uses plain launches throughout. Graphs are

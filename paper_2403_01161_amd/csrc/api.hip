@@ -341,6 +341,7 @@ struct ibm_lb {
     bool f_ready = false;        // F and tile marks hold the spread of the current mesh
     std::vector<int> perm;       // internal vertex k is caller vertex perm[k]
     int lattice_variant = 1 | VAR_HC_SPLIT;  // non-temporal loads, 128-thread work-groups, split smoothing
+    int aa_parity = 0;           // in-place variants: 1 after an even step (f[cur] not in natural order)
     double* stage = nullptr;     // pinned host staging for gradient rows
     hipEvent_t stage_done = nullptr;
     bool timing = false;
@@ -433,10 +434,23 @@ int ensure_force(ibm_lb* h) {
 // Per step: the fused lattice kernel (which consumes F^n and writes u^n in
 // the marked tiles), then the IB half: interpolation + Euler, smoothing and
 // the next step's forces + spreading.
+// Populations of f[cur] in natural order (after an even in-place step, one
+// streaming pass into the other copy); every reader of the populations and
+// every change of layout calls this first.
+int ensure_natural(ibm_lb* h) {
+    if (!h->aa_parity) return IBM_LB_OK;
+    HIP_TRY(launch_aa_settle(h->storage, h->g, h->d, h->cur, h->stream), "settle launch");
+    h->cur ^= 1;
+    h->aa_parity = 0;
+    return IBM_LB_OK;
+}
+
 int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
     const bool ib = h->nv > 0;
     int rc = ensure_force(h);
     if (rc) return rc;
+    const bool aa = (h->lattice_variant & VAR_AA) != 0;
+    if (!aa && (rc = ensure_natural(h))) return rc;
     h->ev_pending = -1;  // other work may have been queued since the last stamp
     for (int j = 0; j < nsteps; ++j) {
         const double* Arow = A + 9ll * j * stride;
@@ -458,8 +472,8 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
             e1 = h->ev[k1];
             done = ib ? h->ev[kd] : nullptr;
         }
-        HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->lattice_variant, h->stream, nullptr,
-                               e1),
+        HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->lattice_variant, h->aa_parity,
+                               h->stream, nullptr, e1),
                 "lattice launch");
         if (ib)
             HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream, done,
@@ -469,7 +483,8 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
             h->iv.push_back({k0, k1});
             h->ev_pending = ib ? kd : k1;
         }
-        h->cur ^= 1;
+        if (aa) h->aa_parity ^= 1;
+        else h->cur ^= 1;
         h->step++;
     }
     if (nsteps > 0) {
@@ -695,6 +710,7 @@ int ibm_lb_observables(ibm_lb* h, ibm_lb_obs* out) {
     if (!h || !out) return fail(IBM_LB_EINVAL, "bad observables arguments");
     int rc = set_device(h);
     if (rc) return rc;
+    if ((rc = ensure_natural(h))) return rc;
     HIP_TRY(launch_observables(h->storage, h->g, h->lp, h->d, h->cur, h->nv, h->nt, h->cfg.radius,
                                h->d.Abuf + 9ll * ACAP, h->stream),
             "observables launch");
@@ -746,6 +762,7 @@ int ibm_lb_read_field(ibm_lb* h, int32_t which, double* out) {
         return fail(IBM_LB_EINVAL, "bad read_field arguments");
     int rc = set_device(h);
     if (rc) return rc;
+    if ((rc = ensure_natural(h))) return rc;
     const size_t N = (size_t)h->g.N;
     double* tmp = nullptr;
     HIP_TRY(hipMalloc((void**)&tmp, sizeof(double) * 4 * N), "hipMalloc");
@@ -787,6 +804,7 @@ int ibm_lb_save(ibm_lb* h, void* dst, size_t n) {
     if (!h || !dst || n < ibm_lb_state_bytes(h)) return fail(IBM_LB_EINVAL, "bad save arguments");
     int rc = set_device(h);
     if (rc) return rc;
+    if ((rc = ensure_natural(h))) return rc;
     rc = sync_and_check(h);
     if (rc) return rc;
     StateHeader hd{STATE_MAGIC, h->storage, h->g.N, h->nv, h->step, {0, 0, 0}};
@@ -811,6 +829,7 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n) {
         return fail(IBM_LB_EINVAL, "checkpoint does not match this configuration");
     const size_t fb = 19ull * h->g.N * storage_bytes(h->storage);
     HIP_TRY(hipMemcpy(h->d.f[h->cur], p + sizeof(hd), fb, hipMemcpyDefault), "load populations");
+    h->aa_parity = 0;  // checkpoints hold natural order
     HIP_TRY(hipMemcpy(h->d.r, p + sizeof(hd) + fb, 4ull * real_bytes(h->storage) * h->nv, hipMemcpyDefault),
             "load vertices");
     h->step = hd.step;
@@ -829,16 +848,18 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n) {
 }
 
 namespace {
-// Variants within 1 % of the fastest count as ties (run-to-run noise of the
-// timing); among them the default variant wins, then the lowest index, so
-// that repeated tuning of one configuration settles on one choice.
-int pick_variant(const float* best_of) {
-    float t = 1e30f;
-    for (int v = 0; v < LATTICE_VARIANTS; ++v) t = std::min(t, best_of[v]);
-    if (best_of[1] <= 1.01f * t) return 1;
-    for (int v = 0; v < LATTICE_VARIANTS; ++v)
-        if (best_of[v] <= 1.01f * t) return v;
-    return 1;
+// Candidates within 1 % of the fastest count as ties (run-to-run noise of
+// the timing); among them the default lattice variant wins, then the first
+// in candidate order, so that repeated tuning of one configuration settles
+// on one choice.
+int pick_variant(const int* cand, const float* t, int nc) {
+    float tmin = 1e30f;
+    for (int k = 0; k < nc; ++k) tmin = std::min(tmin, t[k]);
+    for (int k = 0; k < nc; ++k)
+        if ((cand[k] & (VAR_HC_SPLIT - 1)) == 1 && !(cand[k] & VAR_AA) && t[k] <= 1.01f * tmin) return cand[k];
+    for (int k = 0; k < nc; ++k)
+        if (t[k] <= 1.01f * tmin) return cand[k];
+    return cand[0];
 }
 }  // namespace
 
@@ -888,15 +909,19 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
                 if (e == hipSuccess) best_of[k] = std::min(best_of[k], ms);
             }
     };
-    // the lattice variants, each with the smoothing's finish as its own
+    // the lattice variants with two population copies, then the in-place
+    // ones (linear layout), each with the smoothing's finish as its own
     // launch (measured faster than finishing in the last work-group, whose
     // arrival needs a device-scope release in every work-group)
-    int cand[LATTICE_VARIANTS];
-    float best_of[LATTICE_VARIANTS];
-    for (int v = 0; v < LATTICE_VARIANTS; ++v) cand[v] = v | VAR_HC_SPLIT;
-    tune(cand, LATTICE_VARIANTS, best_of);
+    int cand[2 * LATTICE_VARIANTS];
+    float best_of[2 * LATTICE_VARIANTS];
+    int nc = 0;
+    for (int v = 0; v < LATTICE_VARIANTS; ++v) cand[nc++] = v | VAR_HC_SPLIT;
+    for (int v = 0; v < LATTICE_VARIANTS; ++v)
+        if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
+    tune(cand, nc, best_of);
     int best_v = before;
-    if (e == hipSuccess && rc == IBM_LB_OK) best_v = pick_variant(best_of) | VAR_HC_SPLIT;
+    if (e == hipSuccess && rc == IBM_LB_OK) best_v = pick_variant(cand, best_of, nc);
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     h->timing = timing;
@@ -1012,6 +1037,7 @@ int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar) {
     if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
     int rc = set_device(h);
     if (rc) return rc;
+    if ((rc = ensure_natural(h))) return rc;
     rc = adj_reserve(h, std::max(h->adj_cap, 1));
     if (rc) return rc;
     HIP_TRY(launch_observables(h->storage, h->g, h->lp, h->d, h->cur, h->nv, h->nt, h->cfg.radius,
@@ -1044,6 +1070,14 @@ int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const
     if (rc) return rc;
     rc = adj_reserve(h, nsteps);
     if (rc) return rc;
+    // the recompute records every step's populations in natural order: two
+    // copies for its duration
+    struct KeepVariant {
+        ibm_lb* h;
+        int v;
+        ~KeepVariant() { h->lattice_variant = v; }
+    } keep{h, h->lattice_variant};
+    h->lattice_variant &= ~VAR_AA;
     const long long N = h->g.N;
     const int nv = h->nv;
     hipStream_t s = h->stream;
@@ -1141,7 +1175,7 @@ struct ibm_lb_batch {
 
 namespace {
 bool batch_variant_ok(const ibm_lb_batch* b, int v) {
-    if (v < 0 || v >= STEP_VARIANTS) return false;
+    if (v < 0 || v >= STEP_VARIANTS || (v & VAR_AA)) return false;
     return !(v & VAR_ROWS) || b->nblk[4 + ((v >> 1) & 3)] >= 0;
 }
 
@@ -1435,7 +1469,11 @@ int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     int best_v = before;
-    if (e == hipSuccess && rc == IBM_LB_OK) best_v = pick_variant(best_of);
+    if (e == hipSuccess && rc == IBM_LB_OK) {
+        int cand[LATTICE_VARIANTS];
+        for (int v = 0; v < LATTICE_VARIANTS; ++v) cand[v] = v;
+        best_v = pick_variant(cand, best_of, LATTICE_VARIANTS);
+    }
     b->variant = best_v;
     // restore every member (each load clears its force field and retires its marks)
     for (int i = 0; i < n; ++i) {

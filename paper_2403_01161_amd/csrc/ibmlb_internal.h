@@ -125,7 +125,10 @@ constexpr int VAR_ROWS = 16;
 // smoothing's finish as a launch of its own (single droplets; ensembles
 // always split it).
 constexpr int VAR_HC_SPLIT = 32;
-constexpr int STEP_VARIANTS = 64;
+// Bit 6 (VAR_AA): one population copy updated in place, even and odd steps
+// alternating (linear layout only).
+constexpr int VAR_AA = 64;
+constexpr int STEP_VARIANTS = 128;
 // Rows per work-group of a row-layout variant for rows of Lx nodes; 0 when
 // the variant is not a row layout or Lx exceeds the largest work-group.
 int lattice_rows_per_block(int variant, int Lx);
@@ -133,9 +136,13 @@ int lattice_rows_per_block(int variant, int Lx);
 int lattice_variant_ok(int variant, const Geom& g);
 // e0/e1 (may be null): events stamped at the start and at the completion of
 // the dispatch.
+// parity: for an in-place variant, 0 for the even step, 1 for the odd one.
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
-                          int cur, bool ib, const double* A_row, int variant, hipStream_t s,
+                          int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// After an even in-place step: the natural-order populations of f[cur] into
+// f[cur ^ 1].
+hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cur, hipStream_t s);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
 // maps: eight block maps, concatenated (table q from entry moff[q],
 // nblocks[q] entries; entry b = {member, block index within the member}).

@@ -128,6 +128,36 @@ __device__ __forceinline__ long long push_target(const Geom& g, long long n, int
     return t;
 }
 
+// In-place streaming in two alternating steps (one population copy):
+//   even step: node x reads its own populations f_i(x) and stores its
+//     post-collision f*_i(x) in slot opp(i) of x itself, the moving-wall
+//     term already applied when the link leaves through a wall;
+//   odd step: node x reads f_i(x) = f*_i(x - c_i) from slot opp(i) of
+//     x - c_i (from slot i of x itself when x - c_i lies beyond a wall),
+//     and stores f*_i(x) in slot i of x + c_i (slot opp(i) of x, with the
+//     wall term, through a wall).
+// Each thread reads and writes the same set of locations in either step, so
+// no two threads touch one location. After an odd step the copy holds the
+// populations in natural order again; after an even step they are read with
+// the odd step's mapping (aa_settle).
+//
+// Where population i of node (x, y, z) is read in the odd step: *slot and
+// the node index.
+template <int I>
+__device__ __forceinline__ long long pull_source(const Geom& g, long long n, int x, int y, int z, int* slot) {
+    const long long LxLy = (long long)g.Lx * g.Ly;
+    long long s = n - CX[I] - (long long)CY[I] * g.Lx - (long long)CZ[I] * LxLy;
+    bool w = false;
+    if (CX[I] == -1 && x == g.Lx - 1) { if (g.px) s -= g.Lx; else w = true; }
+    if (CX[I] == 1 && x == 0) { if (g.px) s += g.Lx; else w = true; }
+    if (CY[I] == -1 && y == g.Ly - 1) { if (g.py) s -= LxLy; else w = true; }
+    if (CY[I] == 1 && y == 0) { if (g.py) s += LxLy; else w = true; }
+    if (CZ[I] == -1 && z == g.Lz - 1) { if (g.pz) s -= g.N; else w = true; }
+    if (CZ[I] == 1 && z == 0) { if (g.pz) s += g.N; else w = true; }
+    *slot = w ? I : opp(I);
+    return w ? n : s;
+}
+
 // ROWS: x-moving populations that stay in the box go to stage[xslot(i) T + t]
 // instead of global memory (t: the thread's slot, T: slots per plane).
 // The pointer parameters are plain pointers, or global-address-space
@@ -136,8 +166,10 @@ __device__ __forceinline__ long long push_target(const Geom& g, long long n, int
 // AREG: read the gradient row into registers before any store (for
 // pointers the compiler cannot tell apart from the stores' targets);
 // otherwise it is read where a reflection needs it.
-template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, class PIn, class POut, class PR, class PM,
-          class PC, class PA>
+// AA: 0 two copies (read fin, push into fout), 1 even in-place step, 2 odd
+// in-place step (fin and fout the same copy).
+template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, int AA, class PIn, class POut, class PR,
+          class PM, class PC, class PA>
 __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp, PIn fin, POut fout, PR F,
                                              PR U, PM mark, PC ctl, PA Arow,
                                              const long long n, const int x, const int y, const int z,
@@ -147,11 +179,13 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
     const long long N = g.N;
 
     R d[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (NTL) d[i] = dec<C>(__builtin_nontemporal_load(&fin[i * N + n]), lp.inv_scale);
-        else d[i] = dec<C>(fin[i * N + n], lp.inv_scale);
-    }
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        int slot = i;
+        const long long src = AA == 2 ? pull_source<i>(g, n, x, y, z, &slot) : n;
+        if (NTL) d[i] = dec<C>(__builtin_nontemporal_load(&fin[slot * N + src]), lp.inv_scale);
+        else d[i] = dec<C>(fin[slot * N + src], lp.inv_scale);
+    });
 
     R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
@@ -221,7 +255,9 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
         constexpr int i = decltype(ic)::value;
         bool wall;
         const long long tg = push_target<i>(g, n, x, y, z, &wall);
-        if (!wall) {
+        if (AA == 1) {
+            put<NTS>(&fout[opp(i) * N + n], enc<C>(wall ? val - wall_term(i) : val, lp.scale));
+        } else if (!wall) {
             if (ROWS && CX[i] != 0) stage[xslot(i) * T + t] = enc<C>(val, lp.scale);
             else put<NTS>(&fout[i * N + tg], enc<C>(val, lp.scale));
         } else {
@@ -291,8 +327,42 @@ __global__ __launch_bounds__(BS) void k_lattice(Geom g, LatticeParams lp,
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    lattice_node<C, IB, NTL, false, false, false>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0,
+    lattice_node<C, IB, NTL, false, false, false, 0>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0,
                                                   0);
+}
+
+// In-place (single-copy) form, linear layout: ODD selects the step parity.
+template <class C, bool IB, bool NTL, int BS, bool ODD>
+__global__ __launch_bounds__(BS) void k_lattice_aa(Geom g, LatticeParams lp, typename C::store_t* f,
+                                                    typename C::real* __restrict__ F,
+                                                    typename C::real* __restrict__ U,
+                                                    const int* __restrict__ mark, Ctl* ctl,
+                                                    const double* __restrict__ Arow, int xcd) {
+    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    const long long n = (long long)b * BS + threadIdx.x;
+    if (n >= g.N) return;
+    int x, y, z;
+    node_xyz(g, n, x, y, z);
+    lattice_node<C, IB, NTL, false, false, false, ODD ? 2 : 1>(g, lp, (const typename C::store_t*)f, f, F, U, mark,
+                                                                ctl, Arow, n, x, y, z, nullptr, 0, 0);
+}
+
+// After an even in-place step: the populations of every node in natural
+// order, read with the odd step's mapping, into the other copy.
+template <class C>
+__global__ __launch_bounds__(256) void k_aa_settle(Geom g, const typename C::store_t* __restrict__ fin,
+                                                   typename C::store_t* __restrict__ fout) {
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (n >= g.N) return;
+    int x, y, z;
+    node_xyz(g, n, x, y, z);
+    const long long N = g.N;
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        int slot;
+        const long long src = pull_source<i>(g, n, x, y, z, &slot);
+        fout[i * N + n] = fin[slot * N + src];
+    });
 }
 
 // Row layout: `rows` whole x-rows per work-group (blockDim = rows * Lx <= 512).
@@ -319,7 +389,7 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticePara
     const long long n = (long long)row * g.Lx + x;
     const bool act = n < g.N;
     if (act)
-        lattice_node<C, IB, NTL, true, NTS, false>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, stage, t,
+        lattice_node<C, IB, NTL, true, NTS, false, 0>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, stage, t,
                                                   T);
     __syncthreads();
     if (act) rows_receive<C, NTS>(g, fout, stage, n, x, y, z, t, T);
@@ -368,7 +438,7 @@ __global__ __launch_bounds__(BS, batch_waves<C>) void k_lattice_batch(const LatD
     int x, y, z;
     node_xyz(M.g, n, x, y, z);
     const gptr<const double> Arow = M.A + arow;
-    lattice_node<C, IB, NTL, false, false, true>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
+    lattice_node<C, IB, NTL, false, false, true, 0>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
                                            nullptr, 0, 0);
 }
 
@@ -392,7 +462,7 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows_batch(const LatDesc
     const bool act = t < T && n < M.g.N;
     const gptr<const double> Arow = M.A + arow;
     if (act)
-        lattice_node<C, IB, NTL, true, NTS, true>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
+        lattice_node<C, IB, NTL, true, NTS, true, 0>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
                                             stage, t, T);
     __syncthreads();
     if (act) rows_receive<C, NTS>(M.g, M.fout, stage, n, x, y, z, t, T);
@@ -702,6 +772,28 @@ static void lattice_launch(const Geom& g, const LatticeParams& lp, const DevPtrs
                           xcd);
 }
 
+template <class C, bool IB, bool NTL, int BS>
+static void aa_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row, int xcd,
+                      int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    using R = typename C::real;
+    using S = typename C::store_t;
+    if (parity)
+        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, true>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1,
+                              0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, xcd);
+    else
+        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, false>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1,
+                              0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, xcd);
+}
+
+hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cur, hipStream_t s) {
+    DISPATCH_STORAGE(storage, C, {
+        using S = typename C::store_t;
+        hipLaunchKernelGGL(k_aa_settle<C>, dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, (const S*)d.f[cur],
+                           (S*)d.f[cur ^ 1]);
+    });
+    return hipGetLastError();
+}
+
 template <class C, bool IB, bool NTL, bool NTS>
 static void rows_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
                         int rows, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -724,13 +816,24 @@ int lattice_rows_per_block(int variant, int Lx) {
 
 int lattice_variant_ok(int variant, const Geom& g) {
     if (variant < 0 || variant >= STEP_VARIANTS) return 0;
+    if ((variant & VAR_AA) && (variant & VAR_ROWS)) return 0;
     if (variant & VAR_ROWS) return lattice_rows_per_block(variant, g.Lx) > 0;
     return 1;
 }
 
 template <class C, bool IB, bool NTL>
 static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                             const double* A_row, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                             const double* A_row, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (variant & VAR_AA) {
+        const int xcd = (variant & VAR_X) ? 1 : 0;
+        switch ((variant >> 1) & 3) {
+            case 0: aa_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
+            case 1: aa_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
+            case 2: aa_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
+            default: aa_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
+        }
+        return;
+    }
     if (variant & VAR_ROWS) {
         const int rows = lattice_rows_per_block(variant, g.Lx);
         if (variant & VAR_X) rows_launch<C, IB, NTL, true>(g, lp, d, cur, A_row, rows, s, e0, e1);
@@ -747,16 +850,16 @@ static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp
 }
 
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
-                          int cur, bool ib, const double* A_row, int variant, hipStream_t s, hipEvent_t e0,
-                          hipEvent_t e1) {
+                          int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
+                          hipEvent_t e0, hipEvent_t e1) {
     if (!lattice_variant_ok(variant, g)) return hipErrorInvalidValue;
     DISPATCH_STORAGE(storage, C, {
         if (ib) {
-            if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, s, e0, e1);
-            else launch_lattice_v<C, true, false>(variant, g, lp, d, cur, A_row, s, e0, e1);
+            if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
+            else launch_lattice_v<C, true, false>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
         } else {
-            if (variant & 1) launch_lattice_v<C, false, true>(variant, g, lp, d, cur, A_row, s, e0, e1);
-            else launch_lattice_v<C, false, false>(variant, g, lp, d, cur, A_row, s, e0, e1);
+            if (variant & 1) launch_lattice_v<C, false, true>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
+            else launch_lattice_v<C, false, false>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
         }
     });
     return hipGetLastError();

@@ -2,9 +2,11 @@
 
 The variants differ only in how nodes map to work-groups (linear blocks, an
 XCD-grouped block order, whole x-rows per work-group with the x-moving
-populations exchanged through LDS) and in cache hints, never in the per-node
-arithmetic. Without a droplet the step has no atomics, so every variant must
-reproduce the default variant's state bit for bit, on boxes with walls,
+populations exchanged through LDS), in cache hints and in where populations
+are stored between steps (two copies, or one copy streamed in place with
+alternating index mappings), never in the per-node arithmetic. Without a
+droplet the step has no atomics, so every variant must reproduce the default
+variant's state bit for bit, on boxes with walls,
 periodic axes, rows longer than a work-group and ragged last work-groups.
 With a droplet, a few variants are checked against the FP64 oracle.
 """
@@ -77,26 +79,62 @@ def test_row_layout_rejects_long_rows(ib):
     sim.set_variant(8 | 1)  # linear layouts take any row length
     sim.step(np.zeros(9), 2)
     sim.close()
-    with pytest.raises(ib.IbmLbError):
-        ib.Simulation((8, 8, 8), tau=0.8, storage="f32").set_variant(2 * NVAR)
+    sim = ib.Simulation((8, 8, 8), tau=0.8, storage="f32")
+    for bad in (4 * NVAR, -1, AA | ROWS | 1):
+        with pytest.raises(ib.IbmLbError):
+            sim.set_variant(bad)
+    sim.close()
 
 
 SPLIT = 32  # smoothing finish as a launch of its own
+AA = 64     # in-place streaming, one population copy
 
 
-@pytest.mark.parametrize("variant", [1, 9, ROWS | 1, ROWS | 8, ROWS | 4 | 8 | 1, ROWS | 6, SPLIT | 1,
-                                     SPLIT | ROWS | 8 | 1])
-def test_droplet_variants_match_oracle(ib, variant):
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16dev"])
+@pytest.mark.parametrize("L,periodic", BOXES)
+def test_in_place_variants_bit_identical(ib, storage, L, periodic):
+    # an odd and an even number of in-place steps (the odd count leaves the
+    # copy in the second mapping, settled by save)
+    A = _traceless(2e-3, 7) if not all(periodic) else np.zeros(9)
+    print(f"case in-place L={L} periodic={periodic} storage={storage}", flush=True)
+    for nsteps in (7, 8):
+        ref = _state_after(ib, L, periodic, storage, 1, A, nsteps)
+        for v in range(ROWS):
+            got = _state_after(ib, L, periodic, storage, AA | v, A, nsteps)
+            assert np.array_equal(got, ref), f"variant {AA | v}, {nsteps} steps"
+
+
+def test_in_place_switching_mid_run(ib):
+    # in-place runs of odd and even lengths interleaved with two-copy runs,
+    # row-layout runs and reads, against one two-copy run
+    L, periodic = (16, 12, 10), (1, 0, 0)
+    A = _traceless(2e-3, 9)
+    ref = _state_after(ib, L, periodic, "f32", 1, A, 23)
+    sim = ib.Simulation(L, tau=0.8, periodic=periodic, storage="f32", A0=A, init="linear")
+    for v, k in [(AA | 1, 3), (1, 4), (AA | 8 | 1, 5), (ROWS | 1, 1), (AA, 2), (AA | 1, 1), (9, 2), (AA | 3, 5)]:
+        sim.set_variant(v)
+        sim.step(A, k)
+        if v == AA | 1:
+            sim.fields()  # a read between in-place steps (after an odd count in total)
+    got = sim.save().cpu().numpy().copy()
+    sim.close()
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("variant,nsteps", [(1, 30), (9, 30), (ROWS | 1, 30), (ROWS | 8, 30), (ROWS | 4 | 8 | 1, 30),
+                                            (ROWS | 6, 30), (SPLIT | 1, 30), (SPLIT | ROWS | 8 | 1, 30),
+                                            (AA | SPLIT | 1, 30), (AA | SPLIT | 8 | 1, 29), (AA | 4, 31)])
+def test_droplet_variants_match_oracle(ib, variant, nsteps):
     L = (19, 17, 21)
     A = _traceless(3e-3, 2)
     V, T = icosphere(2, 3.2, box_center(L))
     kw = dict(tau=0.9, sigma=0.02, radius=3.2, vertices=V, triangles=T, A0=A)
-    print(f"case droplet L={L} variant={variant}", flush=True)
+    print(f"case droplet L={L} variant={variant} steps={nsteps}", flush=True)
     sim = ib.Simulation(L, storage="f64", **kw)
     sim.set_variant(variant)
     ref = oracle.Oracle(L, **kw)
-    sim.step(A, 30)
-    ref.step(A, 30)
+    sim.step(A, nsteps)
+    ref.step(A, nsteps)
     dr = np.abs(sim.vertices() - ref.vertices()).max()
     rho_g, u_g = sim.fields()
     rho_r, u_r = ref.fields()
@@ -116,6 +154,31 @@ def _ensemble_states(ib, members, tabs, variant):
     return out
 
 
+def test_droplet_in_place_adjoint_unchanged(ib):
+    # the forward run in place, then one adjoint segment from its checkpoint:
+    # the same objective and gradients as with two copies
+    L = (19, 17, 21)
+    A = np.tile(_traceless(3e-3, 4), (7, 1))
+    V, T = icosphere(2, 3.2, box_center(L))
+    out = []
+    for v in (SPLIT | 1, AA | SPLIT | 1):
+        print(f"case adjoint after variant {v}", flush=True)
+        sim = ib.Simulation(L, tau=0.9, sigma=0.02, radius=3.2, vertices=V, triangles=T, A0=A[0], storage="f64")
+        sim.set_variant(v)
+        ck = sim.save()
+        sim.step_table(A)
+        D, rbar = sim.objective_grad()
+        _, rb0, dA, ds = sim.adjoint_segment(ck, A, None, rbar)
+        out.append((D, rb0.cpu().numpy(), dA.cpu().numpy(), float(ds[0])))
+        sim.close()
+    (D1, r1, a1, s1), (D2, r2, a2, s2) = out
+    # equal up to the order of the float atomics of spreading (run to run)
+    assert abs(D1 - D2) < 1e-13
+    assert abs(s1 - s2) <= 1e-10 * abs(s1)
+    assert np.abs(r1 - r2).max() <= 1e-10 * np.abs(r1).max()
+    assert np.abs(a1 - a2).max() <= 1e-10 * np.abs(a1).max()
+
+
 def test_ensemble_variants_bit_identical(ib):
     # lattice-only members of mixed sizes and periodicity: rows of 48, 20,
     # 96 and 9 nodes, so the row layout packs different row counts per
@@ -128,6 +191,10 @@ def test_ensemble_variants_bit_identical(ib):
         tabs[i, :] = A
         members.append(dict(L=L, periodic=per, tau=0.85, A0=A))
     print("case ensemble variants", flush=True)
+    ens = ib.Ensemble(members, storage="f32")
+    with pytest.raises(ib.IbmLbError):
+        ens.set_variant(AA | 1)  # single droplets only
+    ens.close()
     ref = _ensemble_states(ib, members, tabs, 1)
     for v in range(NVAR):
         if v & ROWS and BS[(v >> 1) & 3] < 96:
