@@ -107,6 +107,9 @@ typedef struct ibm_lb_config {
                               and kept alive until ibm_lb_destroy; NULL: the library
                               allocates (and frees) its own */
     size_t workspace_bytes;
+    int32_t populations;   /* population copies: 2 (0 also selects 2), or 1 for in-place
+                              streaming only (step variants with bit 6; the populations take
+                              half the memory, 19 s bytes per node instead of 38 s) */
 } ibm_lb_config;
 
 typedef struct ibm_lb_obs {
@@ -191,9 +194,11 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  * of Bailey et al., 2009). After an odd number of such steps the copy holds
  * the populations in the odd mapping; every call that reads them (fields,
  * observables, save, objective gradient) or steps with another variant
- * first streams them back to natural order into the second copy, one extra
- * pass over the populations. The adjoint's recompute of a segment runs
- * without bit 6 (it records every step).
+ * first returns them to natural order in place (one pass of pairwise swaps).
+ * A handle made with populations = 1 holds one copy and runs only variants
+ * with bit 6 (default 96). The adjoint's recompute of a segment runs
+ * without bit 6 on two copies; on one copy each recomputed step is followed
+ * by the return to natural order.
  *
  * Autotuner: picks the variant for this configuration by timing `reps` whole
  * steps with each lattice variant that can run (bit 5 set; with and without
@@ -208,8 +213,10 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  * EDEVICE, sticky.
  *
  * ibm_lb_set_variant selects a variant directly (EINVAL if out of range,
- * bits 4 and 6 together, or the row layout cannot take this box). The default is 33 (linear layout,
- * 128-thread work-groups, non-temporal loads, bit 5). */
+ * bits 4 and 6 together, bit 6 clear on a one-copy handle, or the row layout
+ * cannot take this box). The default is 33 (linear layout,
+ * 128-thread work-groups, non-temporal loads, bit 5), or 96 on a one-copy
+ * handle (in place, 128-thread work-groups, bit 5). */
 int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);
 int ibm_lb_set_variant(ibm_lb* h, int32_t variant);
 
@@ -237,7 +244,8 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
  *
  * ibm_lb_batch_init: cfgs[n] as for ibm_lb_init (each member's workspace
  *   rule applies; cfgs[i].stream is ignored); all work goes to `stream`.
- *   Errors: EINVAL (n < 1, mixed storage, any member invalid), ENOMEM, EDEVICE.
+ *   Errors: EINVAL (n < 1, mixed storage, a member with one population
+ *   copy, any member invalid), ENOMEM, EDEVICE.
  * ibm_lb_batch_step: A_tables is host memory [n][nsteps][9] (member-major),
  *   copied before return; member i's step j uses A_tables + 9 (i nsteps + j).
  * ibm_lb_batch_observables: out[n]; synchronising; returns the first member

@@ -50,7 +50,7 @@ struct MeshCSR {
     std::vector<int> fan;
 };
 
-Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t nhalo) {
+Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t nhalo, int copies) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -60,7 +60,7 @@ Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t 
     };
     const size_t sb = storage_bytes(storage), rb = real_bytes(storage);
     L.f[0] = take(19ull * N * sb);
-    L.f[1] = take(19ull * N * sb);
+    L.f[1] = copies == 2 ? take(19ull * N * sb) : L.f[0];
     L.F = take(3ull * N * rb);
     L.u = take(3ull * N * rb);
     L.mark = take(sizeof(int) * (size_t)ntiles);
@@ -109,6 +109,7 @@ int validate(const ibm_lb_config* c) {
         if (!(c->f16_scale >= 1.0) || m != 0.5 || c->f16_scale > 65536.0)
             return fail(IBM_LB_EINVAL, "f16_scale must be a power of two in [1, 65536]");
     }
+    if (c->populations < 0 || c->populations > 2) return fail(IBM_LB_EINVAL, "populations must be 0, 1 or 2");
     const int nv = c->n_vertices, nt = c->n_triangles;
     if (nv < 0 || nt < 0) return fail(IBM_LB_EINVAL, "negative mesh size");
     if (nv == 0 && nt == 0) return IBM_LB_OK;
@@ -342,6 +343,7 @@ struct ibm_lb {
     std::vector<int> perm;       // internal vertex k is caller vertex perm[k]
     int lattice_variant = 1 | VAR_HC_SPLIT;  // non-temporal loads, 128-thread work-groups, split smoothing
     int aa_parity = 0;           // in-place variants: 1 after an even step (f[cur] not in natural order)
+    bool single = false;         // one population copy (f[1] aliases f[0]; in-place variants only)
     double* stage = nullptr;     // pinned host staging for gradient rows
     hipEvent_t stage_done = nullptr;
     bool timing = false;
@@ -435,12 +437,11 @@ int ensure_force(ibm_lb* h) {
 // the marked tiles), then the IB half: interpolation + Euler, smoothing and
 // the next step's forces + spreading.
 // Populations of f[cur] in natural order (after an even in-place step, one
-// streaming pass into the other copy); every reader of the populations and
+// in-place pass of pairwise swaps); every reader of the populations and
 // every change of layout calls this first.
 int ensure_natural(ibm_lb* h) {
     if (!h->aa_parity) return IBM_LB_OK;
     HIP_TRY(launch_aa_settle(h->storage, h->g, h->d, h->cur, h->stream), "settle launch");
-    h->cur ^= 1;
     h->aa_parity = 0;
     return IBM_LB_OK;
 }
@@ -534,7 +535,8 @@ int ibm_lb_workspace_size(const ibm_lb_config* cfg, size_t* bytes) {
     if (!bytes) return fail(IBM_LB_EINVAL, "bytes is NULL");
     Geom g = make_geom(cfg);
     *bytes = make_layout(cfg->storage, g.N, g.TX * g.TY * g.TZ, cfg->n_vertices, cfg->n_triangles,
-                         m.halos.hids.size()).total;
+                         m.halos.hids.size(), cfg->populations == 1 ? 1 : 2)
+                 .total;
     return IBM_LB_OK;
 }
 
@@ -574,7 +576,9 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
     const int ntiles = h->g.TX * h->g.TY * h->g.TZ;
-    h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt, mesh.halos.hids.size());
+    h->single = cfg->populations == 1;
+    if (h->single) h->lattice_variant = VAR_AA | VAR_HC_SPLIT;
+    h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt, mesh.halos.hids.size(), h->single ? 1 : 2);
     if (cfg->workspace) {
         if (cfg->workspace_bytes < h->lay.total)
             return bail(fail(IBM_LB_ENOMEM, "workspace smaller than ibm_lb_workspace_size"));
@@ -916,7 +920,8 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     int cand[2 * LATTICE_VARIANTS];
     float best_of[2 * LATTICE_VARIANTS];
     int nc = 0;
-    for (int v = 0; v < LATTICE_VARIANTS; ++v) cand[nc++] = v | VAR_HC_SPLIT;
+    if (!h->single)
+        for (int v = 0; v < LATTICE_VARIANTS; ++v) cand[nc++] = v | VAR_HC_SPLIT;
     for (int v = 0; v < LATTICE_VARIANTS; ++v)
         if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
     tune(cand, nc, best_of);
@@ -938,6 +943,8 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
 int ibm_lb_set_variant(ibm_lb* h, int32_t variant) {
     if (!h) return fail(IBM_LB_EINVAL, "handle is NULL");
     if (!lattice_variant_ok(variant, h->g)) return fail(IBM_LB_EINVAL, "lattice variant cannot run on this box");
+    if (h->single && !(variant & VAR_AA))
+        return fail(IBM_LB_EINVAL, "a handle with one population copy runs in-place variants only");
     h->lattice_variant = variant;
     return IBM_LB_OK;
 }
@@ -1070,14 +1077,15 @@ int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const
     if (rc) return rc;
     rc = adj_reserve(h, nsteps);
     if (rc) return rc;
-    // the recompute records every step's populations in natural order: two
-    // copies for its duration
+    // the recompute records every step's populations in natural order: with
+    // two copies it streams through both; with one, each step is an even
+    // in-place step followed by the in-place return to natural order
     struct KeepVariant {
         ibm_lb* h;
         int v;
         ~KeepVariant() { h->lattice_variant = v; }
     } keep{h, h->lattice_variant};
-    h->lattice_variant &= ~VAR_AA;
+    if (!h->single) h->lattice_variant &= ~VAR_AA;
     const long long N = h->g.N;
     const int nv = h->nv;
     hipStream_t s = h->stream;
@@ -1093,6 +1101,7 @@ int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const
         for (int j = 0; j < n; ++j) {
             rc = ensure_force(h);
             if (rc) return rc;
+            if ((rc = ensure_natural(h))) return rc;
             HIP_TRY(launch_adj_record(h->storage, h->g, h->lp, h->d, h->cur, nv, adj_step(h, done + j), s),
                     "record launch");
             rc = enqueue_steps(h, rows + 9ll * j, 1, 1);
@@ -1190,6 +1199,8 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     *out = nullptr;
     for (int i = 1; i < n; ++i)
         if (cfgs[i].storage != cfgs[0].storage) return fail(IBM_LB_EINVAL, "ensemble members need one storage format");
+    for (int i = 0; i < n; ++i)
+        if (cfgs[i].populations == 1) return fail(IBM_LB_EINVAL, "ensemble members keep two population copies");
     ibm_lb_batch* b = new (std::nothrow) ibm_lb_batch();
     if (!b) return fail(IBM_LB_ENOMEM, "host allocation");
     b->n = n;

@@ -140,8 +140,7 @@ int lattice_variant_ok(int variant, const Geom& g);
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// After an even in-place step: the natural-order populations of f[cur] into
-// f[cur ^ 1].
+// After an even in-place step: f[cur] back to natural order, in place.
 hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cur, hipStream_t s);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
 // maps: eight block maps, concatenated (table q from entry moff[q],

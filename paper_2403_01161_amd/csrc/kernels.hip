@@ -347,21 +347,31 @@ __global__ __launch_bounds__(BS) void k_lattice_aa(Geom g, LatticeParams lp, typ
                                                                 ctl, Arow, n, x, y, z, nullptr, 0, 0);
 }
 
-// After an even in-place step: the populations of every node in natural
-// order, read with the odd step's mapping, into the other copy.
+// After an even in-place step, back to natural order in place. In the odd
+// mapping f_i(x) sits in slot opp(i) of x - c_i, and slot i of x holds
+// f_opp(i)(x - c_i): the two swap. Node x swaps this pair for the directions
+// of odd index (each pair of opposite directions is (2p - 1, 2p)), so every
+// location belongs to one pair handled by one thread; where x - c_i lies
+// beyond a wall both populations are already in place.
 template <class C>
-__global__ __launch_bounds__(256) void k_aa_settle(Geom g, const typename C::store_t* __restrict__ fin,
-                                                   typename C::store_t* __restrict__ fout) {
+__global__ __launch_bounds__(256) void k_aa_settle(Geom g, typename C::store_t* __restrict__ f) {
     const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
     const long long N = g.N;
-    static_for<0, Q>([&](auto ic) {
+    static_for<1, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        int slot;
-        const long long src = pull_source<i>(g, n, x, y, z, &slot);
-        fout[i * N + n] = fin[slot * N + src];
+        if constexpr (i & 1) {
+            static_assert(opp(i) == i + 1, "opposite directions are paired (2p - 1, 2p)");
+            int slot;
+            const long long src = pull_source<i>(g, n, x, y, z, &slot);
+            if (slot != i) {
+                const typename C::store_t a = f[i * N + n], b = f[opp(i) * N + src];
+                f[i * N + n] = b;
+                f[opp(i) * N + src] = a;
+            }
+        }
     });
 }
 
@@ -788,8 +798,7 @@ static void aa_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, 
 hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cur, hipStream_t s) {
     DISPATCH_STORAGE(storage, C, {
         using S = typename C::store_t;
-        hipLaunchKernelGGL(k_aa_settle<C>, dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, (const S*)d.f[cur],
-                           (S*)d.f[cur ^ 1]);
+        hipLaunchKernelGGL(k_aa_settle<C>, dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, (S*)d.f[cur]);
     });
     return hipGetLastError();
 }

@@ -41,7 +41,8 @@ class Config(C.Structure):
                 ("reg_alpha", C.c_double), ("reg_gamma", C.c_double), ("reg_tol", C.c_double),
                 ("reg_max_iter", C.c_int32), ("reg_sign", C.c_int32), ("storage", C.c_int32),
                 ("init", C.c_int32), ("A0", C.c_double * 9), ("f16_scale", C.c_double),
-                ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("populations", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -117,7 +118,7 @@ def _dp(a):
 
 def make_config(L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None, periodic=(0, 0, 0),
                 storage="f32", init="linear", A0=None, rho0=1.0, reg_alpha=0.1, reg_gamma=0.51,
-                reg_tol=0.01, reg_max_iter=50, reg_sign=1, f16_scale=0.0):
+                reg_tol=0.01, reg_max_iter=50, reg_sign=1, f16_scale=0.0, populations=2):
     """Fill an ibm_lb_config; returns (config, keep-alive arrays)."""
     cfg = Config()
     for a in range(3):
@@ -141,6 +142,7 @@ def make_config(L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None, pe
     for k in range(9):
         cfg.A0[k] = A0[k]
     cfg.f16_scale = float(f16_scale)
+    cfg.populations = int(populations)
     return cfg, (V, T)
 
 

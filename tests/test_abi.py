@@ -74,12 +74,29 @@ def test_valid_config_sizes(ib):
     assert _size_rc(ib, cfg64)[1] > n
     cfg16, keep = _cfg(ib, storage="bf16dev")
     assert _size_rc(ib, cfg16)[1] < n
+    # one population copy: 19 N s bytes less (up to the 256-byte alignment)
+    cfg1, keep = _cfg(ib, populations=1)
+    rc1, n1 = _size_rc(ib, cfg1)
+    assert rc1 == 0 and abs((n - n1) - 19 * N * 4) <= 256
+
+
+def test_ensemble_rejects_one_copy_members(ib):
+    import ctypes as C
+    cfgs = (ib.Config * 2)()
+    keep = []
+    for i, pops in enumerate((2, 1)):
+        c, k = ib.make_config((8, 8, 8), 0.8, populations=pops)
+        cfgs[i] = c
+        keep.append(k)
+    b = C.c_void_p()
+    assert ib.lib().ibm_lb_batch_init(cfgs, 2, None, C.byref(b)) == ib.EINVAL
+    assert not b.value
 
 
 @pytest.mark.parametrize("bad", [
     dict(L=(7, 16, 16)), dict(tau=0.5), dict(sigma=-1.0), dict(radius=0.0), dict(rho0=0.0),
     dict(storage=7), dict(init=5), dict(reg_sign=2), dict(reg_max_iter=-1),
-    dict(f16_scale=3.0, storage="f16dev"), dict(A0=[np.nan] + [0] * 8),
+    dict(f16_scale=3.0, storage="f16dev"), dict(A0=[np.nan] + [0] * 8), dict(populations=3),
 ])
 def test_invalid_parameters(ib, bad):
     cfg, keep = _cfg(ib, **bad)

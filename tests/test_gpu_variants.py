@@ -43,8 +43,9 @@ def _row_ok(v, Lx):
     return not (v & ROWS) or Lx <= 512
 
 
-def _state_after(ib, L, periodic, storage, variant, A, nsteps):
-    sim = ib.Simulation(L, tau=0.8, periodic=periodic, storage=storage, A0=A, init="linear")
+def _state_after(ib, L, periodic, storage, variant, A, nsteps, populations=2):
+    sim = ib.Simulation(L, tau=0.8, periodic=periodic, storage=storage, A0=A, init="linear",
+                        populations=populations)
     sim.set_variant(variant)
     sim.step(A, nsteps)
     out = sim.save().cpu().numpy().copy()
@@ -104,6 +105,35 @@ def test_in_place_variants_bit_identical(ib, storage, L, periodic):
             assert np.array_equal(got, ref), f"variant {AA | v}, {nsteps} steps"
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16dev"])
+@pytest.mark.parametrize("L,periodic", BOXES)
+def test_one_copy_handles_bit_identical(ib, storage, L, periodic):
+    # one population copy: in-place variants only, the same states
+    A = _traceless(2e-3, 7) if not all(periodic) else np.zeros(9)
+    print(f"case one copy L={L} periodic={periodic} storage={storage}", flush=True)
+    for nsteps in (7, 8):
+        ref = _state_after(ib, L, periodic, storage, 1, A, nsteps)
+        for v in (AA, AA | SPLIT | 1, AA | 8 | 4):
+            got = _state_after(ib, L, periodic, storage, v, A, nsteps, populations=1)
+            assert np.array_equal(got, ref), f"variant {v}, {nsteps} steps"
+
+
+def test_one_copy_handle_rules(ib):
+    A = _traceless(2e-3, 8)
+    sim = ib.Simulation((12, 10, 9), tau=0.8, storage="f32", A0=A, populations=1)
+    for bad in (1, SPLIT | 1, ROWS | 1):
+        with pytest.raises(ib.IbmLbError):
+            sim.set_variant(bad)
+    sim.step(A, 3)
+    before = sim.save().cpu().numpy().copy()
+    v = sim.autotune(2)
+    assert v & AA
+    assert np.array_equal(sim.save().cpu().numpy(), before)  # the tuner restores the state
+    sim.close()
+    with pytest.raises(ib.IbmLbError):
+        ib.Ensemble([dict(L=(8, 8, 8), tau=0.8, populations=1)], storage="f32")
+
+
 def test_in_place_switching_mid_run(ib):
     # in-place runs of odd and even lengths interleaved with two-copy runs,
     # row-layout runs and reads, against one two-copy run
@@ -154,16 +184,37 @@ def _ensemble_states(ib, members, tabs, variant):
     return out
 
 
+def test_droplet_one_copy_matches_oracle(ib):
+    L = (19, 17, 21)
+    A = _traceless(3e-3, 2)
+    V, T = icosphere(2, 3.2, box_center(L))
+    kw = dict(tau=0.9, sigma=0.02, radius=3.2, vertices=V, triangles=T, A0=A)
+    sim = ib.Simulation(L, storage="f64", populations=1, **kw)
+    ref = oracle.Oracle(L, **kw)
+    for k in (5, 8, 18):  # a read after every call, odd and even totals
+        sim.step(A, k)
+        ref.step(A, k)
+        assert np.abs(sim.vertices() - ref.vertices()).max() <= 1e-11
+        rho_g, u_g = sim.fields()
+        rho_r, u_r = ref.fields()
+        assert np.abs(u_g - u_r).max() <= 1e-11 * np.abs(u_r).max()
+        assert np.abs(rho_g - rho_r).max() <= 1e-13
+        assert abs(sim.observables()["D"] - ref.observables()["D"]) <= 1e-11
+    sim.close()
+
+
 def test_droplet_in_place_adjoint_unchanged(ib):
     # the forward run in place, then one adjoint segment from its checkpoint:
-    # the same objective and gradients as with two copies
+    # the same objective and gradients as with two copies (and with one copy,
+    # where the recompute returns to natural order after every step)
     L = (19, 17, 21)
     A = np.tile(_traceless(3e-3, 4), (7, 1))
     V, T = icosphere(2, 3.2, box_center(L))
     out = []
-    for v in (SPLIT | 1, AA | SPLIT | 1):
-        print(f"case adjoint after variant {v}", flush=True)
-        sim = ib.Simulation(L, tau=0.9, sigma=0.02, radius=3.2, vertices=V, triangles=T, A0=A[0], storage="f64")
+    for v, pops in ((SPLIT | 1, 2), (AA | SPLIT | 1, 2), (AA | SPLIT, 1)):
+        print(f"case adjoint after variant {v}, {pops} copies", flush=True)
+        sim = ib.Simulation(L, tau=0.9, sigma=0.02, radius=3.2, vertices=V, triangles=T, A0=A[0], storage="f64",
+                            populations=pops)
         sim.set_variant(v)
         ck = sim.save()
         sim.step_table(A)
@@ -171,12 +222,13 @@ def test_droplet_in_place_adjoint_unchanged(ib):
         _, rb0, dA, ds = sim.adjoint_segment(ck, A, None, rbar)
         out.append((D, rb0.cpu().numpy(), dA.cpu().numpy(), float(ds[0])))
         sim.close()
-    (D1, r1, a1, s1), (D2, r2, a2, s2) = out
-    # equal up to the order of the float atomics of spreading (run to run)
-    assert abs(D1 - D2) < 1e-13
-    assert abs(s1 - s2) <= 1e-10 * abs(s1)
-    assert np.abs(r1 - r2).max() <= 1e-10 * np.abs(r1).max()
-    assert np.abs(a1 - a2).max() <= 1e-10 * np.abs(a1).max()
+    D1, r1, a1, s1 = out[0]
+    for D2, r2, a2, s2 in out[1:]:
+        # equal up to the order of the float atomics of spreading (run to run)
+        assert abs(D1 - D2) < 1e-13
+        assert abs(s1 - s2) <= 1e-10 * abs(s1)
+        assert np.abs(r1 - r2).max() <= 1e-10 * np.abs(r1).max()
+        assert np.abs(a1 - a2).max() <= 1e-10 * np.abs(a1).max()
 
 
 def test_ensemble_variants_bit_identical(ib):
