@@ -131,3 +131,14 @@ def ou_gradient_table(nsteps: int, corr_steps: float, rms: float, seed: int):
         out[n] = B - (tr / 3.0) * eye
         B = a * B + b * s * rng.standard_normal(9)
     return out
+
+
+def dns_gradient_frames(nframes: int, seed: int, tau_eta: float = 2.3e-2, dt: float = 2.25e-3):
+    """Synthetic stand-in for a Lagrangian velocity-gradient trajectory of
+    homogeneous isotropic turbulence, in DNS units, one frame every `dt`: the
+    traceless Ornstein-Uhlenbeck table above with correlation time tau_eta
+    (tau_eta / dt frames) and rms Frobenius norm 1 / tau_eta (in such flows
+    the mean of |grad u|^2 is epsilon / nu = 1 / tau_eta^2).
+
+    Returns float64 [nframes, 9]."""
+    return ou_gradient_table(nframes, tau_eta / dt, 1.0 / tau_eta, seed)
