@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libibmlb_oracle.so")
 
-OBS_N = 35
+OBS_N = 38
 FLAG_DEGENERATE, FLAG_E_ZERO, FLAG_REG_CAP = 1, 2, 4
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -4: "EDOMAIN", -5: "ENONFINITE"}
 
@@ -172,7 +172,8 @@ def _obs_dict(o):
             "S": o[5:14].reshape(3, 3).copy(), "eigval": o[14:17].copy(),
             "eigvec": o[17:26].reshape(3, 3).copy(), "D": o[26], "beta": o[27],
             "theta_deg": o[28], "mass": o[29], "momentum": o[30:33].copy(),
-            "reg_iters": int(o[33]), "flags": int(o[34])}
+            "reg_iters": int(o[33]), "flags": int(o[34]), "min_angle_deg": o[35], "edge_min": o[36],
+            "edge_max": o[37]}
 
 
 def shape(r, tris, A=None, radius=1.0):

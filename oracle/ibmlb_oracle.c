@@ -408,7 +408,11 @@ void ibo_eig3(const double S[9], double evals[3], double evecs[9])
  * Volume integrals are sums over the signed tetrahedra (o, a, b, c) of each
  * triangle with o the mean vertex position:
  *   V_t = a.(b x c)/6, int x dV = V_t (a+b+c)/4,
- *   int x x^T dV = V_t/20 (aa^T + bb^T + cc^T + (a+b+c)(a+b+c)^T). */
+ *   int x x^T dV = V_t/20 (aa^T + bb^T + cc^T + (a+b+c)(a+b+c)^T).
+ * Mesh quality (the loosening and clustering of elements that the smoothing
+ * of Sec. 3.3 prevents): the smallest interior angle of any triangle,
+ * angle(u, v) = atan2(|u x v|, u.v) at each corner, and the shortest and
+ * longest edge; out[35..37]. */
 int ibo_shape(int nv, const double* r, int nt, const int* tris, const double A[9],
               double radius, double out[IBO_OBS_N])
 {
@@ -419,10 +423,25 @@ int ibo_shape(int nv, const double* r, int nt, const int* tris, const double A[9
         for (int a = 0; a < 3; ++a) o[a] += r[3 * k + a];
     for (int a = 0; a < 3; ++a) o[a] /= (double)nv;
     double V = 0.0, m1[3] = {0.0, 0.0, 0.0}, m2[3][3] = {{0.0}};
+    double min_angle = INFINITY, emin = INFINITY, emax = 0.0;
     for (int t = 0; t < nt; ++t) {
         double p[3][3];
         for (int j = 0; j < 3; ++j)
             for (int a = 0; a < 3; ++a) p[j][a] = r[3 * tris[3 * t + j] + a] - o[a];
+        for (int j = 0; j < 3; ++j) {
+            double u[3], w[3], uxw[3];
+            for (int a = 0; a < 3; ++a) {
+                u[a] = p[(j + 1) % 3][a] - p[j][a];
+                w[a] = p[(j + 2) % 3][a] - p[j][a];
+            }
+            cross(u, w, uxw);
+            const double ang = atan2(sqrt(uxw[0] * uxw[0] + uxw[1] * uxw[1] + uxw[2] * uxw[2]),
+                                     u[0] * w[0] + u[1] * w[1] + u[2] * w[2]);
+            if (ang < min_angle) min_angle = ang;
+            const double len = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            if (len < emin) emin = len;
+            if (len > emax) emax = len;
+        }
         double bxc[3];
         cross(p[1], p[2], bxc);
         double Vt = (p[0][0] * bxc[0] + p[0][1] * bxc[1] + p[0][2] * bxc[2]) / 6.0;
@@ -467,6 +486,9 @@ int ibo_shape(int nv, const double* r, int nt, const int* tris, const double A[9
             beta = q / En;
         }
     }
+    out[35] = min_angle * 180.0 / M_PI;
+    out[36] = emin;
+    out[37] = emax;
     out[1] = V;
     for (int a = 0; a < 3; ++a) out[2 + a] = o[a] + xbar[a];
     for (int k = 0; k < 9; ++k) out[5 + k] = S[k];

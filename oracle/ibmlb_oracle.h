@@ -48,7 +48,7 @@ extern "C" {
  *  14..16 eigenvalues (descending), 17..25 eigenvectors (row k = vector k),
  *  26 D, 27 beta, 28 theta (degrees), 29 mass, 30..32 momentum,
  *  33 smoothing iterations of the last step, 34 flags. */
-#define IBO_OBS_N 35
+#define IBO_OBS_N 38
 
 typedef struct ibo_params {
     int L[3];          /* nodes per axis, each >= 4 */
