@@ -126,6 +126,9 @@ typedef struct ibm_lb_obs {
     double momentum[3];    /* sum over nodes of sum_i c_i f_i */
     int32_t reg_iters;     /* smoothing iterations of the last step */
     int32_t flags;         /* IBM_LB_OBS_* */
+    double min_angle_deg;  /* mesh quality: smallest interior angle of any triangle (degrees) */
+    double edge_min;       /* shortest mesh edge (lattice units) */
+    double edge_max;       /* longest mesh edge */
 } ibm_lb_obs;
 
 /* Device bytes the configuration needs when cfg->workspace is supplied.

@@ -738,6 +738,9 @@ int ibm_lb_observables(ibm_lb* h, ibm_lb_obs* out) {
     for (int a = 0; a < 3; ++a) out->momentum[a] = o[30 + a];
     out->reg_iters = (int)o[33];
     if (o[34] > 0) out->flags |= IBM_LB_OBS_REG_CAP;
+    out->min_angle_deg = o[35];
+    out->edge_min = o[36];
+    out->edge_max = o[37];
     return IBM_LB_OK;
 }
 

@@ -560,12 +560,15 @@ __global__ void k_clear(R* F, long long n) {
 // ---------------------------------------------------------------- observables (FP64)
 // Signed tetrahedra (x_c, a, b, c) of every triangle: V_t = a.(b x c)/6,
 // int x dV = V_t (a+b+c)/4, int x x^T dV = V_t/20 (aa^T+bb^T+cc^T+ss^T).
+// Mesh quality: the smallest corner angle atan2(|u x v|, u.v) and the
+// shortest and longest edge (block slots 10, 11, 12).
 template <class R>
 __global__ __launch_bounds__(256) void k_obs_partial(int nt, const int4* __restrict__ tris,
                                                      const V4<R>* __restrict__ r, double* part) {
     double s[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) s[k] = 0.0;
+    double amin = __builtin_inf(), emin = __builtin_inf(), emax = 0.0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x) {
         const int4 tr = tris[t];
         const V4<R> pa = r[tr.x], pb = r[tr.y], pc = r[tr.z];
@@ -587,18 +590,47 @@ __global__ __launch_bounds__(256) void k_obs_partial(int nt, const int4* __restr
         s[7] += v20 * (a[0] * a[1] + b[0] * b[1] + c[0] * c[1] + sx * sy);
         s[8] += v20 * (a[0] * a[2] + b[0] * b[2] + c[0] * c[2] + sx * sz);
         s[9] += v20 * (a[1] * a[2] + b[1] * b[2] + c[1] * c[2] + sy * sz);
+        const double* P[3] = {a, b, c};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double* p0 = P[j];
+            const double* p1 = P[(j + 1) % 3];
+            const double* p2 = P[(j + 2) % 3];
+            const double u0 = p1[0] - p0[0], u1 = p1[1] - p0[1], u2 = p1[2] - p0[2];
+            const double w0 = p2[0] - p0[0], w1 = p2[1] - p0[1], w2 = p2[2] - p0[2];
+            const double x0 = u1 * w2 - u2 * w1, x1 = u2 * w0 - u0 * w2, x2 = u0 * w1 - u1 * w0;
+            amin = fmin(amin, atan2(sqrt(x0 * x0 + x1 * x1 + x2 * x2), u0 * w0 + u1 * w1 + u2 * w2));
+            const double len = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+            emin = fmin(emin, len);
+            emax = fmax(emax, len);
+        }
     }
-    __shared__ double red[10][4];
+    __shared__ double red[13][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
         double v = wave_sum(s[k]);
         if (lane == 0) red[k][wv] = v;
     }
+    for (int m = 32; m > 0; m >>= 1) {
+        amin = fmin(amin, __shfl_xor(amin, m, 64));
+        emin = fmin(emin, __shfl_xor(emin, m, 64));
+        emax = fmax(emax, __shfl_xor(emax, m, 64));
+    }
+    if (lane == 0) {
+        red[10][wv] = amin;
+        red[11][wv] = emin;
+        red[12][wv] = emax;
+    }
     __syncthreads();
     if (threadIdx.x < 10) {
         const int k = threadIdx.x;
         part[blockIdx.x * 16 + k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    } else if (threadIdx.x < 13) {
+        const int k = threadIdx.x;
+        double v = red[k][0];
+        for (int w = 1; w < 4; ++w) v = k == 12 ? fmax(v, red[k][w]) : fmin(v, red[k][w]);
+        part[blockIdx.x * 16 + k] = v;
     }
 }
 
@@ -660,7 +692,8 @@ __device__ void jacobi3(const double S[9], double ev[3], double vec[9]) {
 
 // Output layout (doubles): 0 volume, 1..3 centroid (relative to x_c),
 // 4..12 S, 13..15 eigval, 16..24 eigvec, 25 D, 26 beta, 27 theta_deg,
-// 28 flags, 29 sum of deviations, 30..32 momentum, 33 iters, 34 cap hits.
+// 28 flags, 29 sum of deviations, 30..32 momentum, 33 iters, 34 cap hits,
+// 35 smallest triangle angle (degrees), 36 shortest edge, 37 longest edge.
 __global__ void k_obs_final(int nblocks, const double* part, int mblocks, const double* mpart,
                             const double* Arow, double radius, int has_mesh, Ctl* ctl,
                             double* out) {
@@ -678,8 +711,16 @@ __global__ void k_obs_final(int nblocks, const double* part, int mblocks, const 
     ctl->cap_hits = 0;
     if (!has_mesh) return;
     double s[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int b = 0; b < nblocks; ++b)
+    double amin = __builtin_inf(), emin = __builtin_inf(), emax = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
         for (int k = 0; k < 10; ++k) s[k] += part[16 * b + k];
+        amin = fmin(amin, part[16 * b + 10]);
+        emin = fmin(emin, part[16 * b + 11]);
+        emax = fmax(emax, part[16 * b + 12]);
+    }
+    out[35] = amin * (180.0 / 3.14159265358979323846);
+    out[36] = emin;
+    out[37] = emax;
     const double V = s[0];
     const double xb[3] = {s[1] / V, s[2] / V, s[3] / V};
     const double M[9] = {s[4], s[7], s[8], s[7], s[5], s[9], s[8], s[9], s[6]};

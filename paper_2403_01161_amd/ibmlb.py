@@ -50,7 +50,8 @@ class Obs(C.Structure):
                 ("S", C.c_double * 9), ("eigval", C.c_double * 3), ("eigvec", C.c_double * 9),
                 ("D", C.c_double), ("beta", C.c_double), ("theta_deg", C.c_double),
                 ("mass", C.c_double), ("momentum", C.c_double * 3), ("reg_iters", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("min_angle_deg", C.c_double), ("edge_min", C.c_double),
+                ("edge_max", C.c_double)]
 
 
 EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_table",
@@ -157,7 +158,8 @@ def _obs_dict(o):
             "S": np.array(o.S[:]).reshape(3, 3), "eigval": np.array(o.eigval[:]),
             "eigvec": np.array(o.eigvec[:]).reshape(3, 3), "D": o.D, "beta": o.beta,
             "theta_deg": o.theta_deg, "mass": o.mass, "momentum": np.array(o.momentum[:]),
-            "reg_iters": o.reg_iters, "flags": o.flags}
+            "reg_iters": o.reg_iters, "flags": o.flags, "min_angle_deg": o.min_angle_deg,
+            "edge_min": o.edge_min, "edge_max": o.edge_max}
 
 
 class Simulation:
