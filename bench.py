@@ -169,7 +169,7 @@ def large_footprint_bench(dev, steps=300, warmup=30):
                         "OU traceless A(t) rms Ca 0.15, f32 populations",
             "steps": steps, "mlups": round(nodes * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 4),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counter_traffic("f32", "256cubed"),
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counter_traffic("f32", "256cubed", variant),
                          "kernel": lattice_kernel_name(variant), "alg_bytes_per_launch": alg,
                          "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
                          "variant": describe_variant(variant)}}
@@ -183,16 +183,20 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(storage, box="128cubed"):
+def counter_traffic(storage, box="128cubed", variant=None):
     """HBM bytes per lattice launch from the committed rocprofv3 counter summary,
-    valid only while the kernel source is the one profiled."""
+    valid only while the kernel source is the one profiled and the lattice
+    kernel variant (bits 0-4 and 6 of the step variant) is the profiled one."""
     path = os.path.join(ROOT, "profiles", f"lattice_{storage}_{box}_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]{16})", txt)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not t or m.group(1) != kernel_source_hash():
+    v = re.search(r"lattice_variant:\s*([0-9]+)", txt)
+    if not m or not t or not v or m.group(1) != kernel_source_hash():
+        return None
+    if variant is not None and int(v.group(1)) != (variant & 95):
         return None
     return float(t.group(1))
 
@@ -472,7 +476,7 @@ def main():
     alg_bytes = 2 * 19 * sbytes * nodes
     avg_s = lat_ms / 1e3 / max(launches, 1)
     achieved = alg_bytes / avg_s / 1e9
-    traffic = counter_traffic(args.storage)
+    traffic = counter_traffic(args.storage, variant=variant)
 
     value = nodes * K / dt / 1e6
     line = {
