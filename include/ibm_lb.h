@@ -83,7 +83,7 @@ typedef struct ibm_lb ibm_lb;
 typedef struct ibm_lb_batch ibm_lb_batch;
 
 typedef struct ibm_lb_config {
-    int32_t L[3];          /* nodes per axis, each >= 8 */
+    int32_t L[3];          /* nodes per axis, each >= 8; at most 2^31 - 1 nodes in all */
     int32_t periodic[3];   /* per axis: 0 = moving walls, 1 = periodic */
     double tau;            /* BGK relaxation time (Eq. collision), > 0.5; nu = (tau - 1/2)/3 */
     double sigma;          /* surface tension (Eq. pi_drop), >= 0 */

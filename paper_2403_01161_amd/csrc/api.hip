@@ -91,8 +91,10 @@ int validate(const ibm_lb_config* c) {
     if (!c) return fail(IBM_LB_EINVAL, "config is NULL");
     for (int a = 0; a < 3; ++a)
         if (c->L[a] < 8) return fail(IBM_LB_EINVAL, "every box side needs at least 8 nodes");
-    if ((long long)c->L[0] * c->L[1] * c->L[2] > (1ll << 31) / 19)
-        return fail(IBM_LB_EINVAL, "box too large for 32-bit plane indexing");
+    // population and field offsets are 64-bit; node coordinates and tile
+    // indices are 32-bit
+    if ((long long)c->L[0] * c->L[1] * c->L[2] > 0x7fffffffll)
+        return fail(IBM_LB_EINVAL, "box above 2^31 - 1 nodes");
     if (!(c->tau > 0.5)) return fail(IBM_LB_EINVAL, "tau must exceed 1/2");
     if (!(c->sigma >= 0.0)) return fail(IBM_LB_EINVAL, "sigma must be >= 0");
     if (!(c->radius > 0.0)) return fail(IBM_LB_EINVAL, "radius must be > 0");

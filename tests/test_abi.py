@@ -126,6 +126,16 @@ def test_invalid_meshes(ib):
     assert _size_rc(ib, cfg)[0] == 0
 
 
+def test_box_size_limits(ib):
+    # 500^3 (above 2^31 / 19 nodes: population offsets need 64 bits) is valid;
+    # more than 2^31 - 1 nodes is not
+    cfg, keep = ib.make_config((500, 500, 500), 0.8)
+    rc, n = _size_rc(ib, cfg)
+    assert rc == 0 and n >= 2 * 19 * 4 * 500 ** 3
+    cfg, keep = ib.make_config((1300, 1300, 1300), 0.8)
+    assert _size_rc(ib, cfg)[0] == ib.EINVAL
+
+
 def test_lattice_only_config(ib):
     cfg, keep = ib.make_config((8, 9, 10), 0.8)
     assert _size_rc(ib, cfg)[0] == 0
