@@ -45,7 +45,7 @@ class _Params(C.Structure):
                 ("tris", C.POINTER(C.c_int)), ("reg_alpha", C.c_double),
                 ("reg_gamma", C.c_double), ("reg_tol", C.c_double),
                 ("reg_max_iter", C.c_int), ("reg_sign", C.c_int), ("init_rest", C.c_int),
-                ("A0", C.c_double * 9)]
+                ("A0", C.c_double * 9), ("collision", C.c_int), ("mrt_s", C.c_double * 5)]
 
 
 def lib():
@@ -66,6 +66,8 @@ def lib():
         L.ibo_interp.argtypes = [ip, ip, i, dp, dp, dp]
         L.ibo_hc.argtypes = [i, i, ip, C.c_double, C.c_double, C.c_double, i, i, dp, ip]
         L.ibo_eig3.argtypes = [dp, dp, dp]
+        L.ibo_mrt_basis.argtypes = [dp, dp]
+        L.ibo_mrt_basis.restype = None
         L.ibo_shape.argtypes = [i, dp, i, ip, dp, C.c_double, dp]
         L.ibo_create.argtypes = [C.POINTER(_Params), C.POINTER(C.c_void_p)]
         L.ibo_destroy.argtypes = [C.c_void_p]
@@ -176,6 +178,13 @@ def _obs_dict(o):
             "edge_max": o[37]}
 
 
+def mrt_basis():
+    """(M [19, 19], squared row norms [19]) of the MRT moment basis."""
+    M, n2 = np.zeros(19 * 19), np.zeros(19)
+    lib().ibo_mrt_basis(_dp(M), _dp(n2))
+    return M.reshape(19, 19), n2
+
+
 def shape(r, tris, A=None, radius=1.0):
     r = np.ascontiguousarray(r, dtype=np.float64)
     t = np.ascontiguousarray(tris, dtype=np.int32)
@@ -191,7 +200,7 @@ class Oracle:
 
     def __init__(self, L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None,
                  periodic=(0, 0, 0), rho0=1.0, reg_alpha=0.1, reg_gamma=0.51, reg_tol=0.01,
-                 reg_max_iter=50, reg_sign=1, init_rest=False, A0=None):
+                 reg_max_iter=50, reg_sign=1, init_rest=False, A0=None, collision="bgk", mrt_s=None):
         p = _Params()
         self.L = tuple(int(v) for v in L)
         for a in range(3):
@@ -212,6 +221,9 @@ class Oracle:
         A0 = np.zeros(9) if A0 is None else np.asarray(A0, dtype=np.float64).reshape(9)
         for k in range(9):
             p.A0[k] = A0[k]
+        p.collision = {"bgk": 0, "mrt": 1}[collision]
+        for k, v in enumerate(mrt_s if mrt_s is not None else [0.0] * 5):
+            p.mrt_s[k] = float(v)
         h = C.c_void_p()
         _check(lib().ibo_create(C.byref(p), C.byref(h)), "create")
         self._h = h

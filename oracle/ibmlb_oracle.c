@@ -116,6 +116,38 @@ void ibo_guo_source(double tau, const double u[3], const double F[3], double S[1
     }
 }
 
+/* Multiple-relaxation-time collision (the paper mentions it as an option for
+ * stability and for separating bulk viscosity; d'Humieres et al., 2002).
+ * Moments m = M f over the orthogonal D3Q19 basis of that reference, with
+ * c2 = |c|^2: rho; e = 19 c2 - 30; eps = (21 c2^2 - 53 c2 + 24)/2; j_a = c_a;
+ * q_a = (5 c2 - 9) c_a; 3p_xx = 3 c_x^2 - c2; 3pi_xx = (3 c_x^2 - c2)(3 c2 - 5);
+ * p_ww = c_y^2 - c_z^2; pi_ww = (c_y^2 - c_z^2)(3 c2 - 5); p_xy, p_yz, p_xz =
+ * c_a c_b; m_x = (c_y^2 - c_z^2) c_x, m_y = (c_z^2 - c_x^2) c_y,
+ * m_z = (c_x^2 - c_y^2) c_z. Order: rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z,
+ * 3p_xx, 3pi_xx, p_ww, pi_ww, p_xy, p_yz, p_xz, m_x, m_y, m_z. */
+void ibo_mrt_basis(double M[19 * 19], double norm2[19])
+{
+    for (int i = 0; i < 19; ++i) {
+        const double cx = CV[i][0], cy = CV[i][1], cz = CV[i][2];
+        const double c2 = cx * cx + cy * cy + cz * cz;
+        const double row[19] = {1.0,
+                                19.0 * c2 - 30.0,
+                                (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0,
+                                cx, (5.0 * c2 - 9.0) * cx,
+                                cy, (5.0 * c2 - 9.0) * cy,
+                                cz, (5.0 * c2 - 9.0) * cz,
+                                3.0 * cx * cx - c2, (3.0 * cx * cx - c2) * (3.0 * c2 - 5.0),
+                                cy * cy - cz * cz, (cy * cy - cz * cz) * (3.0 * c2 - 5.0),
+                                cx * cy, cy * cz, cx * cz,
+                                (cy * cy - cz * cz) * cx, (cz * cz - cx * cx) * cy, (cx * cx - cy * cy) * cz};
+        for (int k = 0; k < 19; ++k) M[19 * k + i] = row[k];
+    }
+    for (int k = 0; k < 19; ++k) {
+        norm2[k] = 0.0;
+        for (int i = 0; i < 19; ++i) norm2[k] += M[19 * k + i] * M[19 * k + i];
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Surface-tension nodal forces, Eq. (pi_drop): phi_k = -sigma dA/dr_k.
  * For triangle (a, b, c) with unit normal n = (b-a)x(c-a)/|(b-a)x(c-a)|,
@@ -521,6 +553,8 @@ struct ibo_sim {
     double A_last[9];
     int* sched;             /* frozen smoothing iteration counts, see ibo_freeze_iters */
     int sched_n, sched_pos;
+    int collision;          /* 0 BGK, 1 MRT */
+    double mrt_M[19 * 19], mrt_n2[19], mrt_s[19];  /* basis, squared norms, rate per moment */
 };
 
 long ibo_nodes(const ibo_sim* s) { return s->N; }
@@ -542,6 +576,9 @@ int ibo_create(const ibo_params* p, ibo_sim** out)
     for (int a = 0; a < 3; ++a)
         if (p->L[a] < 4) return IBO_EINVAL;
     if (!(p->tau > 0.5) || !(p->sigma >= 0.0) || !(p->rho0 > 0.0)) return IBO_EINVAL;
+    if (p->collision < 0 || p->collision > 1) return IBO_EINVAL;
+    for (int k = 0; k < 5; ++k)
+        if (!(p->mrt_s[k] >= 0.0 && p->mrt_s[k] < 2.0)) return IBO_EINVAL;
     if (p->nv < 0 || p->nt < 0 || (p->nv > 0 && (!p->verts || !p->tris || p->nt == 0)))
         return IBO_EINVAL;
     for (int t = 0; t < 3 * p->nt; ++t)
@@ -558,6 +595,20 @@ int ibo_create(const ibo_params* p, ibo_sim** out)
     s->nv = p->nv; s->nt = p->nt;
     s->reg_alpha = p->reg_alpha; s->reg_gamma = p->reg_gamma; s->reg_tol = p->reg_tol;
     s->reg_max_iter = p->reg_max_iter; s->reg_sign = p->reg_sign >= 0 ? 1 : -1;
+    s->collision = p->collision;
+    if (s->collision == 1) {
+        /* rate per moment: conserved rho and j at 1/tau (their non-equilibrium
+         * and source parts cancel), the five stress moments at 1/tau (the
+         * viscosity), the others from mrt_s */
+        static const double dflt[5] = {1.19, 1.4, 1.2, 1.4, 1.98};
+        double r[5];
+        for (int k = 0; k < 5; ++k) r[k] = p->mrt_s[k] > 0.0 ? p->mrt_s[k] : dflt[k];
+        const double sv = 1.0 / p->tau;
+        const double rate[19] = {sv, r[0], r[1], sv, r[2], sv, r[2], sv, r[2],
+                                 sv, r[3], sv, r[3], sv, sv, sv, r[4], r[4], r[4]};
+        memcpy(s->mrt_s, rate, sizeof(rate));
+        ibo_mrt_basis(s->mrt_M, s->mrt_n2);
+    }
     s->f = malloc(sizeof(double) * 19 * (size_t)s->N);
     s->fpost = malloc(sizeof(double) * 19 * (size_t)s->N);
     s->F = calloc(3 * (size_t)s->N, sizeof(double));
@@ -634,7 +685,11 @@ static void moments(ibo_sim* s)
 }
 
 /* BGK collision with Guo source, Eqs. (LBMEQ), (collision):
- * f*_i = f_i - (f_i - f_i^eq)/tau + S_i. */
+ * f*_i = f_i - (f_i - f_i^eq)/tau + S_i.
+ * MRT: f* = f - M^-1 [ S M (f - f_eq) - (I - S/2) M G ] with G the Guo term
+ * without its (1 - 1/(2 tau)) factor and S the diagonal of rates; the basis
+ * is orthogonal, so M^-1 = M^T diag(1/|M_k|^2). With every rate 1/tau this is
+ * the BGK step. */
 static void collide(ibo_sim* s)
 {
 #pragma omp parallel for schedule(static)
@@ -644,6 +699,26 @@ static void collide(ibo_sim* s)
                 long n = x + s->L[0] * (y + (long)s->L[1] * z);
                 double feq[19], S[19];
                 ibo_equilibrium(s->rho[n], s->u + 3 * n, feq);
+                if (s->collision == 1) {
+                    double G[19], mn[19], mg[19];
+                    ibo_guo_source(1.0, s->u + 3 * n, s->F + 3 * n, G);
+                    for (int i = 0; i < 19; ++i) G[i] *= 2.0;  /* the source at tau = 1 is G / 2 */
+                    for (int k = 0; k < 19; ++k) {
+                        mn[k] = mg[k] = 0.0;
+                        for (int i = 0; i < 19; ++i) {
+                            mn[k] += s->mrt_M[19 * k + i] * (s->f[19 * n + i] - feq[i]);
+                            mg[k] += s->mrt_M[19 * k + i] * G[i];
+                        }
+                    }
+                    for (int i = 0; i < 19; ++i) {
+                        double d = 0.0;
+                        for (int k = 0; k < 19; ++k)
+                            d += s->mrt_M[19 * k + i] *
+                                 (s->mrt_s[k] * mn[k] - (1.0 - 0.5 * s->mrt_s[k]) * mg[k]) / s->mrt_n2[k];
+                        s->fpost[19 * n + i] = s->f[19 * n + i] - d;
+                    }
+                    continue;
+                }
                 ibo_guo_source(s->tau, s->u + 3 * n, s->F + 3 * n, S);
                 for (int i = 0; i < 19; ++i)
                     s->fpost[19 * n + i] = s->f[19 * n + i] - (s->f[19 * n + i] - feq[i]) / s->tau + S[i];

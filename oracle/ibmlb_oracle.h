@@ -65,6 +65,10 @@ typedef struct ibo_params {
     int reg_sign;      /* +1: correction adds the neighbour mean of b; -1: subtracts it */
     int init_rest;     /* 0: linear field u = A0 (x - x_c) with its non-equilibrium part; 1: rest */
     double A0[9];
+    int collision;     /* 0: BGK (the paper's single relaxation time); 1: MRT */
+    double mrt_s[5];   /* MRT rates of the energy, energy-square, heat-flux, third-order
+                          stress and third-order antisymmetric moments; 0 selects 1.19,
+                          1.4, 1.2, 1.4, 1.98; the shear rate is 1/tau */
 } ibo_params;
 
 typedef struct ibo_sim ibo_sim;
@@ -74,6 +78,9 @@ void ibo_lattice(int c[19 * 3], double w[19], int opp[19]);
 double ibo_phi(double r);
 void ibo_equilibrium(double rho, const double u[3], double feq[19]);
 void ibo_guo_source(double tau, const double u[3], const double F[3], double S[19]);
+/* Moment basis of the MRT collision: M[19][19] (row k = moment k over the
+ * velocities) and the squared row norms. */
+void ibo_mrt_basis(double M[19 * 19], double norm2[19]);
 void ibo_forces(int nv, const double* r, int nt, const int* tris, double sigma, double* phi);
 int ibo_spread(const int L[3], const int periodic[3], int nv, const double* r,
                const double* phi, double* F);
