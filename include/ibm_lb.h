@@ -82,6 +82,8 @@ extern "C" {
 typedef struct ibm_lb ibm_lb;
 typedef struct ibm_lb_batch ibm_lb_batch;
 
+enum { IBM_LB_BGK = 0, IBM_LB_MRT = 1 };
+
 typedef struct ibm_lb_config {
     int32_t L[3];          /* nodes per axis, each >= 8; at most 2^31 - 1 nodes in all */
     int32_t periodic[3];   /* per axis: 0 = moving walls, 1 = periodic */
@@ -110,6 +112,14 @@ typedef struct ibm_lb_config {
     int32_t populations;   /* population copies: 2 (0 also selects 2), or 1 for in-place
                               streaming only (step variants with bit 6; the populations take
                               half the memory, 19 s bytes per node instead of 38 s) */
+    int32_t collision;     /* IBM_LB_BGK (0, the paper's single relaxation time) or IBM_LB_MRT:
+                              multiple relaxation times (Sec. 3.1 mentions it as an option) on
+                              the orthogonal moment basis of d'Humieres et al. (2002), the shear
+                              moments at 1/tau; MRT runs the linear layout with two copies,
+                              single droplets only, without the adjoint */
+    double mrt_s[5];       /* MRT rates in (0, 2) of the energy, energy-square, heat-flux,
+                              third-order stress and third-order antisymmetric moments;
+                              0 selects 1.19, 1.4, 1.2, 1.4, 1.98 */
 } ibm_lb_config;
 
 typedef struct ibm_lb_obs {
@@ -216,8 +226,8 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  * EDEVICE, sticky.
  *
  * ibm_lb_set_variant selects a variant directly (EINVAL if out of range,
- * bits 4 and 6 together, bit 6 clear on a one-copy handle, or the row layout
- * cannot take this box). The default is 33 (linear layout,
+ * bits 4 and 6 together, bit 6 clear on a one-copy handle, bit 4 or 6 on an
+ * MRT handle, or the row layout cannot take this box). The default is 33 (linear layout,
  * 128-thread work-groups, non-temporal loads, bit 5), or 96 on a one-copy
  * handle (in place, 128-thread work-groups, bit 5). */
 int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);

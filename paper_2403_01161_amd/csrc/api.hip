@@ -112,6 +112,11 @@ int validate(const ibm_lb_config* c) {
             return fail(IBM_LB_EINVAL, "f16_scale must be a power of two in [1, 65536]");
     }
     if (c->populations < 0 || c->populations > 2) return fail(IBM_LB_EINVAL, "populations must be 0, 1 or 2");
+    if (c->collision != IBM_LB_BGK && c->collision != IBM_LB_MRT) return fail(IBM_LB_EINVAL, "unknown collision");
+    for (int k = 0; k < 5; ++k)
+        if (!(c->mrt_s[k] >= 0.0 && c->mrt_s[k] < 2.0)) return fail(IBM_LB_EINVAL, "MRT rates must lie in (0, 2)");
+    if (c->collision == IBM_LB_MRT && c->populations == 1)
+        return fail(IBM_LB_EINVAL, "MRT runs with two population copies");
     const int nv = c->n_vertices, nt = c->n_triangles;
     if (nv < 0 || nt < 0) return fail(IBM_LB_EINVAL, "negative mesh size");
     if (nv == 0 && nt == 0) return IBM_LB_OK;
@@ -346,6 +351,8 @@ struct ibm_lb {
     int lattice_variant = 1 | VAR_HC_SPLIT;  // non-temporal loads, 128-thread work-groups, split smoothing
     int aa_parity = 0;           // in-place variants: 1 after an even step (f[cur] not in natural order)
     bool single = false;         // one population copy (f[1] aliases f[0]; in-place variants only)
+    bool mrt = false;            // MRT collision with the rates below
+    MrtRates mrt_rates{};
     double* stage = nullptr;     // pinned host staging for gradient rows
     hipEvent_t stage_done = nullptr;
     bool timing = false;
@@ -476,7 +483,7 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
             done = ib ? h->ev[kd] : nullptr;
         }
         HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->lattice_variant, h->aa_parity,
-                               h->stream, nullptr, e1),
+                               h->stream, nullptr, e1, h->mrt ? &h->mrt_rates : nullptr),
                 "lattice launch");
         if (ib)
             HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream, done,
@@ -579,6 +586,18 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
     const int ntiles = h->g.TX * h->g.TY * h->g.TZ;
     h->single = cfg->populations == 1;
+    h->mrt = cfg->collision == IBM_LB_MRT;
+    if (h->mrt) {
+        // per moment of the basis: conserved density and momentum and the five
+        // shear moments at 1/tau, the others from the configuration
+        static const double dflt[5] = {1.19, 1.4, 1.2, 1.4, 1.98};
+        double r[5];
+        for (int k = 0; k < 5; ++k) r[k] = cfg->mrt_s[k] > 0.0 ? cfg->mrt_s[k] : dflt[k];
+        const double sv = 1.0 / cfg->tau;
+        const double rate[19] = {sv, r[0], r[1], sv, r[2], sv, r[2], sv, r[2],
+                                 sv, r[3], sv, r[3], sv, sv, sv, r[4], r[4], r[4]};
+        for (int k = 0; k < 19; ++k) h->mrt_rates.s[k] = rate[k];
+    }
     if (h->single) h->lattice_variant = VAR_AA | VAR_HC_SPLIT;
     h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt, mesh.halos.hids.size(), h->single ? 1 : 2);
     if (cfg->workspace) {
@@ -926,9 +945,11 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     float best_of[2 * LATTICE_VARIANTS];
     int nc = 0;
     if (!h->single)
-        for (int v = 0; v < LATTICE_VARIANTS; ++v) cand[nc++] = v | VAR_HC_SPLIT;
-    for (int v = 0; v < LATTICE_VARIANTS; ++v)
-        if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
+        for (int v = 0; v < LATTICE_VARIANTS; ++v)
+            if (!h->mrt || !(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT;
+    if (!h->mrt)
+        for (int v = 0; v < LATTICE_VARIANTS; ++v)
+            if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
     tune(cand, nc, best_of);
     int best_v = before;
     if (e == hipSuccess && rc == IBM_LB_OK) best_v = pick_variant(cand, best_of, nc);
@@ -950,6 +971,8 @@ int ibm_lb_set_variant(ibm_lb* h, int32_t variant) {
     if (!lattice_variant_ok(variant, h->g)) return fail(IBM_LB_EINVAL, "lattice variant cannot run on this box");
     if (h->single && !(variant & VAR_AA))
         return fail(IBM_LB_EINVAL, "a handle with one population copy runs in-place variants only");
+    if (h->mrt && (variant & (VAR_ROWS | VAR_AA)))
+        return fail(IBM_LB_EINVAL, "MRT runs the linear layout with two copies");
     h->lattice_variant = variant;
     return IBM_LB_OK;
 }
@@ -1045,6 +1068,7 @@ extern "C" {
 
 int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar) {
     if (!h || !value || !rbar) return fail(IBM_LB_EINVAL, "bad objective_grad arguments");
+    if (h->mrt) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step");
     if (h->nv == 0) return fail(IBM_LB_EINVAL, "the objective needs a mesh");
     if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
     int rc = set_device(h);
@@ -1076,6 +1100,7 @@ int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const
         return fail(IBM_LB_EINVAL, "bad adjoint_segment arguments");
     if (h->nv > 0 && (!rbar_end || !rbar_begin))
         return fail(IBM_LB_EINVAL, "rbar_end and rbar_begin are required with a mesh");
+    if (h->mrt) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step");
     int rc = set_device(h);
     if (rc) return rc;
     rc = ibm_lb_load(h, ckpt, ckpt_bytes);
@@ -1204,8 +1229,10 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     *out = nullptr;
     for (int i = 1; i < n; ++i)
         if (cfgs[i].storage != cfgs[0].storage) return fail(IBM_LB_EINVAL, "ensemble members need one storage format");
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (cfgs[i].populations == 1) return fail(IBM_LB_EINVAL, "ensemble members keep two population copies");
+        if (cfgs[i].collision != IBM_LB_BGK) return fail(IBM_LB_EINVAL, "ensemble members run BGK");
+    }
     ibm_lb_batch* b = new (std::nothrow) ibm_lb_batch();
     if (!b) return fail(IBM_LB_ENOMEM, "host allocation");
     b->n = n;

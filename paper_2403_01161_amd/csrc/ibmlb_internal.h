@@ -44,6 +44,12 @@ struct LatticeParams {
     float scale, inv_scale;  // 16-bit deviation scaling
 };
 
+// Rates of the MRT collision, one per moment of the basis in lattice_common.h
+// (the shear moments at 1/tau).
+struct MrtRates {
+    double s[19];
+};
+
 struct SmoothParams {
     double alpha, gamma, tol;
     int max_iter, sign;
@@ -137,9 +143,11 @@ int lattice_variant_ok(int variant, const Geom& g);
 // e0/e1 (may be null): events stamped at the start and at the completion of
 // the dispatch.
 // parity: for an in-place variant, 0 for the even step, 1 for the odd one.
+// mrt (may be null): MRT collision with these rates instead of BGK (linear
+// layout with two copies only).
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
-                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const MrtRates* mrt = nullptr);
 // After an even in-place step: f[cur] back to natural order, in place.
 hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cur, hipStream_t s);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);

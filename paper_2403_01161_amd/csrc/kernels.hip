@@ -168,12 +168,16 @@ __device__ __forceinline__ long long pull_source(const Geom& g, long long n, int
 // otherwise it is read where a reflection needs it.
 // AA: 0 two copies (read fin, push into fout), 1 even in-place step, 2 odd
 // in-place step (fin and fout the same copy).
-template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, int AA, class PIn, class POut, class PR,
-          class PM, class PC, class PA>
+// MRT: the multiple-relaxation-time collision with the rates *mr instead of
+// BGK: f* = f - M^-1 [S M (f - f_eq) - (I - S/2) M G], G the Guo term without
+// its (1 - 1/(2 tau)) factor (with every rate 1/tau, the BGK step).
+template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, int AA, bool MRT = false, class PIn,
+          class POut, class PR, class PM, class PC, class PA>
 __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp, PIn fin, POut fout, PR F,
                                              PR U, PM mark, PC ctl, PA Arow,
                                              const long long n, const int x, const int y, const int z,
-                                             typename C::store_t* stage, int t, int T) {
+                                             typename C::store_t* stage, int t, int T,
+                                             const MrtRates* mr = nullptr) {
     using R = typename C::real;
     using S = typename C::store_t;
     const long long N = g.N;
@@ -265,6 +269,39 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
         }
     };
 
+    if constexpr (MRT) {
+        R nq[Q], gq[Q];
+        static_for<0, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const R w = wgt<R>(i);
+            const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+            const R cF = R(CX[i]) * Fx + R(CY[i]) * Fy + R(CZ[i]) * Fz;
+            nq[i] = d[i] - w * (drho + rho * (R(4.5) * cu * cu + R(3) * cu - R(1.5) * usq));
+            gq[i] = w * (R(3) * (cF - uF) + R(9) * cu * cF);
+        });
+        static_for<0, Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            R mn = R(0), mg = R(0);
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int m = mrt_m(k, i);
+                if constexpr (m != 0) {
+                    mn += R(m) * nq[i];
+                    mg += R(m) * gq[i];
+                }
+            });
+            const R sk = R(mr->s[k]);
+            const R r = (sk * mn - (R(1) - R(0.5) * sk) * mg) * (R(1) / R(mrt_norm2(k)));
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int m = mrt_m(k, i);
+                if constexpr (m != 0) d[i] -= R(m) * r;
+            });
+        });
+        put<NTS>(&fout[n], enc<C>(d[0], lp.scale));
+        static_for<1, Q>([&](auto ic) { push(ic, d[decltype(ic)::value]); });
+        return;
+    }
     {   // rest population
         const R w = wgt<R>(0);
         const R deq = w * (drho + rho * (R(-1.5) * usq));
@@ -329,6 +366,24 @@ __global__ __launch_bounds__(BS) void k_lattice(Geom g, LatticeParams lp,
     node_xyz(g, n, x, y, z);
     lattice_node<C, IB, NTL, false, false, false, 0>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0,
                                                   0);
+}
+
+// MRT collision, linear layout with two copies.
+template <class C, bool IB, bool NTL, int BS>
+__global__ __launch_bounds__(BS) void k_lattice_mrt(Geom g, LatticeParams lp,
+                                                     const typename C::store_t* __restrict__ fin,
+                                                     typename C::store_t* __restrict__ fout,
+                                                     typename C::real* __restrict__ F,
+                                                     typename C::real* __restrict__ U,
+                                                     const int* __restrict__ mark, Ctl* ctl,
+                                                     const double* __restrict__ Arow, int xcd, MrtRates mr) {
+    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    const long long n = (long long)b * BS + threadIdx.x;
+    if (n >= g.N) return;
+    int x, y, z;
+    node_xyz(g, n, x, y, z);
+    lattice_node<C, IB, NTL, false, false, false, 0, true>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z,
+                                                        nullptr, 0, 0, &mr);
 }
 
 // In-place (single-copy) form, linear layout: ODD selects the step parity.
@@ -824,6 +879,28 @@ static void lattice_launch(const Geom& g, const LatticeParams& lp, const DevPtrs
 }
 
 template <class C, bool IB, bool NTL, int BS>
+static void mrt_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
+                       int xcd, const MrtRates& mr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    using R = typename C::real;
+    using S = typename C::store_t;
+    hipExtLaunchKernelGGL((k_lattice_mrt<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1, 0, g,
+                          lp, (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl,
+                          A_row, xcd, mr);
+}
+
+template <class C, bool IB, bool NTL>
+static void launch_mrt_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
+                         const double* A_row, const MrtRates& mr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int xcd = (variant & VAR_X) ? 1 : 0;
+    switch ((variant >> 1) & 3) {
+        case 0: mrt_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
+        case 1: mrt_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
+        case 2: mrt_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
+        default: mrt_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
+    }
+}
+
+template <class C, bool IB, bool NTL, int BS>
 static void aa_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row, int xcd,
                       int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     using R = typename C::real;
@@ -901,8 +978,21 @@ static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp
 
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
-                          hipEvent_t e0, hipEvent_t e1) {
+                          hipEvent_t e0, hipEvent_t e1, const MrtRates* mrt) {
     if (!lattice_variant_ok(variant, g)) return hipErrorInvalidValue;
+    if (mrt) {
+        if (variant & (VAR_ROWS | VAR_AA)) return hipErrorInvalidValue;
+        DISPATCH_STORAGE(storage, C, {
+            if (ib) {
+                if (variant & 1) launch_mrt_v<C, true, true>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
+                else launch_mrt_v<C, true, false>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
+            } else {
+                if (variant & 1) launch_mrt_v<C, false, true>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
+                else launch_mrt_v<C, false, false>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
+            }
+        });
+        return hipGetLastError();
+    }
     DISPATCH_STORAGE(storage, C, {
         if (ib) {
             if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);

@@ -32,6 +32,46 @@ __host__ __device__ constexpr R wgt(int i) {
     return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
 }
 
+// ---------------------------------------------------------------- MRT basis
+// The orthogonal D3Q19 moment basis of d'Humieres et al. (2002), with
+// c2 = |c|^2: rho; e = 19 c2 - 30; eps = (21 c2^2 - 53 c2 + 24)/2; j_a = c_a;
+// q_a = (5 c2 - 9) c_a; 3p_xx = 3 c_x^2 - c2; 3pi_xx = (3 c_x^2 - c2)(3 c2 - 5);
+// p_ww = c_y^2 - c_z^2; pi_ww = (c_y^2 - c_z^2)(3 c2 - 5); p_xy, p_yz, p_xz;
+// m_x = (c_y^2 - c_z^2) c_x, m_y = (c_z^2 - c_x^2) c_y, m_z = (c_x^2 - c_y^2) c_z,
+// in the order rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, 3pi_xx, p_ww,
+// pi_ww, p_xy, p_yz, p_xz, m_x, m_y, m_z. Entry (k, i) is moment k of velocity i.
+__host__ __device__ constexpr int mrt_m(int k, int i) {
+    const int cx = CX[i], cy = CY[i], cz = CZ[i];
+    const int c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+        case 0: return 1;
+        case 1: return 19 * c2 - 30;
+        case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+        case 3: return cx;
+        case 4: return (5 * c2 - 9) * cx;
+        case 5: return cy;
+        case 6: return (5 * c2 - 9) * cy;
+        case 7: return cz;
+        case 8: return (5 * c2 - 9) * cz;
+        case 9: return 3 * cx * cx - c2;
+        case 10: return (3 * cx * cx - c2) * (3 * c2 - 5);
+        case 11: return cy * cy - cz * cz;
+        case 12: return (cy * cy - cz * cz) * (3 * c2 - 5);
+        case 13: return cx * cy;
+        case 14: return cy * cz;
+        case 15: return cx * cz;
+        case 16: return (cy * cy - cz * cz) * cx;
+        case 17: return (cz * cz - cx * cx) * cy;
+        default: return (cx * cx - cy * cy) * cz;
+    }
+}
+// Squared norm of basis row k (the basis is orthogonal: M^-1 = M^T diag(1/norm)).
+__host__ __device__ constexpr int mrt_norm2(int k) {
+    int s = 0;
+    for (int i = 0; i < Q; ++i) s += mrt_m(k, i) * mrt_m(k, i);
+    return s;
+}
+
 // ---------------------------------------------------------------- storage
 struct SF64 { using store_t = double; using real = double; };
 struct SF32 { using store_t = float; using real = float; };

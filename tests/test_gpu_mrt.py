@@ -1,0 +1,105 @@
+"""GPU MRT collision against the FP64 oracle's MRT (same basis and rates),
+its variants bit-identical to each other, and its limits (linear layout
+with two copies, single droplets, no adjoint)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_01161_amd.inputs import box_center, icosphere
+
+pytestmark = pytest.mark.gpu
+
+ROWS, SPLIT, AA = 16, 32, 64
+
+
+@pytest.fixture(scope="module")
+def ib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_01161_amd import ibmlb
+    ibmlb.lib()
+    return ibmlb
+
+
+def _traceless(scale, seed):
+    A = np.random.default_rng(seed).standard_normal((3, 3))
+    A -= np.trace(A) / 3 * np.eye(3)
+    return (scale * A / np.linalg.norm(A)).ravel()
+
+
+def _case(L=(19, 17, 21)):
+    A = _traceless(3e-3, 2)
+    V, T = icosphere(2, 3.2, box_center(L))
+    return A, dict(tau=0.9, sigma=0.02, radius=3.2, vertices=V, triangles=T, A0=A)
+
+
+@pytest.mark.parametrize("storage,mrt_s,tol", [
+    ("f64", None, (1e-11, 1e-11, 1e-13)),
+    ("f64", [1.5, 1.1, 1.7, 1.3, 1.0], (1e-11, 1e-11, 1e-13)),
+    ("f32", None, (2e-5, 2e-4, 1e-6)),
+])
+def test_mrt_droplet_matches_oracle(ib, storage, mrt_s, tol):
+    L = (19, 17, 21)
+    A, kw = _case(L)
+    print(f"case MRT droplet {storage} rates {mrt_s}", flush=True)
+    sim = ib.Simulation(L, storage=storage, collision="mrt", mrt_s=mrt_s, **kw)
+    ref = oracle.Oracle(L, collision="mrt", mrt_s=mrt_s, **kw)
+    sim.step(A, 30)
+    ref.step(A, 30)
+    dr = np.abs(sim.vertices() - ref.vertices()).max()
+    rho_g, u_g = sim.fields()
+    rho_r, u_r = ref.fields()
+    du = np.abs(u_g - u_r).max() / np.abs(u_r).max()
+    drho = np.abs(rho_g - rho_r).max()
+    print(f"  max|dr| {dr:.2e}  du {du:.2e}  drho {drho:.2e}", flush=True)
+    assert dr <= tol[0] and du <= tol[1] and drho <= tol[2]
+    assert abs(sim.observables()["mass"] - ref.observables()["mass"]) <= 1e-9 * ref.observables()["mass"]
+    sim.close()
+    ref.close()
+
+
+def test_mrt_equal_rates_match_bgk(ib):
+    L = (19, 17, 21)
+    A, kw = _case(L)
+    s = 1 / kw["tau"]
+    out = []
+    for coll, rates in (("bgk", None), ("mrt", [s] * 5)):
+        sim = ib.Simulation(L, storage="f64", collision=coll, mrt_s=rates, **kw)
+        sim.step(A, 30)
+        out.append((sim.vertices(), sim.fields()[1]))
+        sim.close()
+    assert np.abs(out[0][0] - out[1][0]).max() <= 1e-11
+    assert np.abs(out[0][1] - out[1][1]).max() <= 1e-11 * np.abs(out[0][1]).max()
+
+
+def test_mrt_variants_bit_identical(ib):
+    L, A = (40, 9, 11), _traceless(2e-3, 3)
+    states = {}
+    for v in (1, 0, 3, 5, 7, 8, 9, SPLIT | 1):
+        sim = ib.Simulation(L, 0.8, storage="f32", A0=A, collision="mrt", periodic=(1, 0, 0))
+        sim.set_variant(v)
+        sim.step(A, 7)
+        states[v] = sim.save().cpu().numpy().copy()
+        sim.close()
+    for v, st in states.items():
+        assert np.array_equal(st, states[1]), f"variant {v}"
+
+
+def test_mrt_limits(ib):
+    L = (12, 10, 9)
+    A, kw = _case((19, 17, 21))
+    sim = ib.Simulation(L, 0.8, storage="f32", A0=A, collision="mrt")
+    for bad in (ROWS | 1, AA | 1):
+        with pytest.raises(ib.IbmLbError):
+            sim.set_variant(bad)
+    v = sim.autotune(2)
+    assert not (v & (ROWS | AA))
+    sim.close()
+    with pytest.raises(ib.IbmLbError):
+        ib.Ensemble([dict(L=(8, 8, 8), tau=0.8, collision="mrt")], storage="f32")
+    sim = ib.Simulation((19, 17, 21), storage="f64", collision="mrt", **kw)
+    sim.step(A, 2)
+    with pytest.raises(ib.IbmLbError):
+        sim.objective_grad()
+    sim.close()
