@@ -59,7 +59,7 @@ def test_protocol_ensemble_follows_linear_theory(ib):
     res = P.run_ensemble(ens, frames, m)
     ens.close()
     for i in range(n):
-        one = {"D": res["D"][i], "beta": res["beta"][i], "A_lbu": res["A_lbu"][i]}
+        one = {"D": res["D"][i], "beta": res["beta"][i], "theta": res["theta"][i], "A_lbu": res["A_lbu"][i]}
         cD, ratio, cb = _against_linear_theory(m, one)
         print(f"  member {i}: corr D {cD:.3f}  D/D_LT {ratio:.3f}  corr beta {cb:.3f}", flush=True)
         assert cD > 0.8 and 1.0 < ratio < 1.5 and cb > 0.95

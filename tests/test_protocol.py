@@ -136,11 +136,9 @@ def _protocol_case(nframes):
 
 
 def _against_linear_theory(m, res):
-    S = P.lt_integrate(res["A_lbu"], m.N, m.R_lbu, m.tau_sigma_lbu)
-    D, beta, _ = P.descriptors(S, res["A_lbu"])
-    k = 5  # skip the first frames (start-up from the sphere)
-    return (np.corrcoef(res["D"][k:], D[k:])[0, 1], res["D"][k:].mean() / D[k:].mean(),
-            np.corrcoef(res["beta"][k:], beta[k:])[0, 1])
+    # the first 5 frames are skipped (start-up from the sphere)
+    c = P.compare_with_theory(m, res, skip=5)
+    return c["corr_D"], c["D_over_D_lt"], c["corr_beta"]
 
 
 def test_oracle_droplet_follows_linear_theory():
