@@ -463,20 +463,49 @@ __global__ __launch_bounds__(256) void k_adj_reduce_sigma(long long n, const dou
 // c = sqrt(l3), and dl_i/dS = v_i v_i^T, so Sbar = dD/dl1 v1 v1^T + dD/dl3 v3 v3^T.
 // Through S = 5M/V - 5 P P^T / V^2 (P = V xb):
 //   Mbar = 5 Sbar / V,  Pbar = -10 Sbar xb / V,  Vbar = (-Sbar:S + 5 xb.Sbar xb) / V.
+// Other objectives: J = lambda_max, Sbar = v1 v1^T; J = beta = v1^T E v1 / |E|
+// (Eq. beta, E of the last step held fixed), through the eigenvector
+// derivative dv1 = sum_{j > 1} v_j (v_j^T dS v1) / (l1 - l_j):
+// Sbar = sum_{j > 1} 2 (v1^T E v_j) / (|E| (l1 - l_j)) (v_j v1^T + v1 v_j^T) / 2.
 // obs: the observables record (0 V, 1..3 xb relative to x_c, 4..12 S,
-// 13..15 eigenvalues, 16..24 eigenvectors by rows). coef: Vbar, Pbar[3], Mbar[9].
-__global__ void k_adj_seed_coef(const double* __restrict__ obs, double* __restrict__ coef) {
+// 13..15 eigenvalues, 16..24 eigenvectors by rows). Arow: the last gradient.
+// which: 0 D, 1 lambda_max, 2 beta. coef: Vbar, Pbar[3], Mbar[9].
+__global__ void k_adj_seed_coef(const double* __restrict__ obs, const double* __restrict__ Arow, int which,
+                                double* __restrict__ coef) {
     if (threadIdx.x != 0) return;
     const double V = obs[0];
     const double xb[3] = {obs[1], obs[2], obs[3]};
     const double* S = obs + 4;
-    const double a = sqrt(obs[13]), c = sqrt(obs[15]);
-    const double d1 = c / (a * (a + c) * (a + c)), d3 = -a / (c * (a + c) * (a + c));
     const double* v1 = obs + 16;
     const double* v3 = obs + 22;
     double Sb[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Sb[3 * i + j] = d1 * v1[i] * v1[j] + d3 * v3[i] * v3[j];
+    if (which == 0) {
+        const double a = sqrt(obs[13]), c = sqrt(obs[15]);
+        const double d1 = c / (a * (a + c) * (a + c)), d3 = -a / (c * (a + c) * (a + c));
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Sb[3 * i + j] = d1 * v1[i] * v1[j] + d3 * v3[i] * v3[j];
+    } else if (which == 1) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Sb[3 * i + j] = v1[i] * v1[j];
+    } else {
+        double E[9], En = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                E[3 * i + j] = 0.5 * (Arow[3 * i + j] + Arow[3 * j + i]);
+                En += E[3 * i + j] * E[3 * i + j];
+            }
+        En = sqrt(En);
+        for (int k = 0; k < 9; ++k) Sb[k] = 0.0;
+        for (int jj = 1; jj < 3; ++jj) {
+            const double* vj = obs + 16 + 3 * jj;
+            double q = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) q += v1[i] * E[3 * i + j] * vj[j];
+            const double cj = 2.0 * q / (En * (obs[13] - obs[13 + jj]));
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) Sb[3 * i + j] += 0.5 * cj * (vj[i] * v1[j] + v1[i] * vj[j]);
+        }
+    }
     double SbS = 0.0, xSx = 0.0, Sx[3];
     for (int i = 0; i < 3; ++i) {
         Sx[i] = 0.0;
@@ -625,8 +654,9 @@ hipError_t launch_adj_reduce(int nsteps, int nbl, const double* Apart, int nbv, 
     return hipGetLastError();
 }
 
-hipError_t launch_adj_seed(int storage, int nv, const DevPtrs& d, double* coef, double4* rb, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_seed_coef, dim3(1), dim3(64), 0, s, d.obs_out, coef);
+hipError_t launch_adj_seed(int storage, int nv, const DevPtrs& d, double* coef, double4* rb, hipStream_t s,
+                           int which) {
+    hipLaunchKernelGGL(k_adj_seed_coef, dim3(1), dim3(64), 0, s, d.obs_out, d.Abuf + 9ll * ACAP, which, coef);
     if (storage == IBM_LB_F64)
         hipLaunchKernelGGL(k_adj_seed<double>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, d.fan,
                            (const V4<double>*)d.r, coef, rb);

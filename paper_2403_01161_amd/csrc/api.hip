@@ -1067,7 +1067,12 @@ AdjStep adj_step(ibm_lb* h, int j) {
 extern "C" {
 
 int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar) {
+    return ibm_lb_shape_objective_grad(h, IBM_LB_OBJ_D, value, rbar);
+}
+
+int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, double* rbar) {
     if (!h || !value || !rbar) return fail(IBM_LB_EINVAL, "bad objective_grad arguments");
+    if (objective < IBM_LB_OBJ_D || objective > IBM_LB_OBJ_BETA) return fail(IBM_LB_EINVAL, "unknown objective");
     if (h->mrt) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step");
     if (h->nv == 0) return fail(IBM_LB_EINVAL, "the objective needs a mesh");
     if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
@@ -1084,10 +1089,13 @@ int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar) {
     rc = sync_and_check(h);
     if (rc) return rc;
     const double tie = 1e-12 * h->cfg.radius * h->cfg.radius;
-    if (!(o[13] - o[14] >= tie) || !(o[14] - o[15] >= tie))
-        return fail(IBM_LB_EINVAL, "repeated eigenvalue of S: the deformation D has no derivative here");
-    *value = o[25];
-    HIP_TRY(launch_adj_seed(h->storage, h->nv, h->d, h->adj_coef, h->adj_v.rb, h->stream), "seed launch");
+    if (!(o[13] - o[14] >= tie) || (objective == IBM_LB_OBJ_D && !(o[14] - o[15] >= tie)))
+        return fail(IBM_LB_EINVAL, "repeated eigenvalue of S: the objective has no derivative here");
+    if (objective == IBM_LB_OBJ_BETA && (o[28] != o[28] || (int)o[28] & IBM_LB_OBS_E_ZERO))
+        return fail(IBM_LB_EINVAL, "beta needs a nonzero strain E");
+    *value = objective == IBM_LB_OBJ_D ? o[25] : (objective == IBM_LB_OBJ_LAMBDA_MAX ? o[13] : o[26]);
+    HIP_TRY(launch_adj_seed(h->storage, h->nv, h->d, h->adj_coef, h->adj_v.rb, h->stream, objective),
+            "seed launch");
     HIP_TRY(launch_adj_perm_out(h->nv, h->adj_perm, h->adj_v.rb, rbar, h->stream), "seed permute");
     HIP_TRY(hipStreamSynchronize(h->stream), "sync");
     return IBM_LB_OK;

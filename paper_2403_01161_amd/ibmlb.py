@@ -26,6 +26,9 @@ FIELD_RHO, FIELD_U = 0, 1
 _lib = None
 
 
+OBJECTIVES = {"D": 0, "lambda_max": 1, "beta": 2}
+
+
 class IbmLbError(RuntimeError):
     def __init__(self, code, where, detail=""):
         super().__init__(f"{where}: {_lib.ibm_lb_strerror(code).decode() if _lib else code}"
@@ -61,7 +64,7 @@ EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_t
            "ibm_lb_timing_read", "ibm_lb_destroy", "ibm_lb_strerror", "ibm_lb_last_error",
            "ibm_lb_batch_init", "ibm_lb_batch_step", "ibm_lb_batch_observables", "ibm_lb_batch_member",
            "ibm_lb_batch_autotune", "ibm_lb_batch_set_variant", "ibm_lb_batch_set_graph",
-           "ibm_lb_batch_destroy", "ibm_lb_objective_grad",
+           "ibm_lb_batch_destroy", "ibm_lb_objective_grad", "ibm_lb_shape_objective_grad",
            "ibm_lb_adjoint_segment"]
 
 
@@ -100,6 +103,7 @@ def lib():
         L.ibm_lb_batch_destroy.argtypes = [vp]
         L.ibm_lb_batch_destroy.restype = None
         L.ibm_lb_objective_grad.argtypes = [vp, dp, vp]
+        L.ibm_lb_shape_objective_grad.argtypes = [vp, i32, dp, vp]
         L.ibm_lb_adjoint_segment.argtypes = [vp, vp, C.c_size_t, vp, i32, i32, vp, vp, vp, vp, vp, vp]
         L.ibm_lb_strerror.argtypes = [C.c_int]
         L.ibm_lb_strerror.restype = C.c_char_p
@@ -272,11 +276,13 @@ class Simulation:
         return ms.value, n.value
 
     # ---- adjoint
-    def objective_grad(self):
-        """D of the current mesh and dD/dr as a float64 CUDA tensor [nv, 3] (caller vertex order)."""
+    def objective_grad(self, objective="D"):
+        """J of the current mesh and dJ/dr as a float64 CUDA tensor [nv, 3] (caller vertex order);
+        J is D, "lambda_max" or "beta" (the last step's strain held fixed)."""
         rbar = torch.empty((self.nv, 3), dtype=torch.float64, device=self.device)
         v = C.c_double()
-        _check(lib().ibm_lb_objective_grad(self._h, C.byref(v), rbar.data_ptr()), "ibm_lb_objective_grad")
+        _check(lib().ibm_lb_shape_objective_grad(self._h, OBJECTIVES[objective], C.byref(v), rbar.data_ptr()),
+               "ibm_lb_shape_objective_grad")
         return v.value, rbar
 
     def adjoint_segment(self, ckpt, A, fbar_end, rbar_end, fbar_begin=None, rbar_begin=None, dA=None,
@@ -411,7 +417,7 @@ class DeformationFunction(torch.autograd.Function):
     iteration counts are those the forward took."""
 
     @staticmethod
-    def forward(ctx, sigma, A, vertices, spec, K):
+    def forward(ctx, sigma, A, vertices, spec, K, objective="D"):
         spec = dict(spec)
         sim = Simulation(sigma=float(sigma), vertices=vertices.detach().cpu().numpy(), **spec)
         ctx.adev = A.device
@@ -421,7 +427,7 @@ class DeformationFunction(torch.autograd.Function):
         for s0 in range(0, n, K):
             ckpts.append(sim.save())
             sim.step_table(A[s0:s0 + K])
-        D, rbar = sim.objective_grad()
+        D, rbar = sim.objective_grad(objective)
         ctx.sim, ctx.ckpts, ctx.K, ctx.rbar, ctx.A = sim, ckpts, K, rbar, A
         ctx.sigma_shape, ctx.sdev, ctx.vdev = sigma.shape, sigma.device, vertices.device
         return torch.tensor(D, dtype=torch.float64, device=sim.device)
@@ -441,14 +447,16 @@ class DeformationFunction(torch.autograd.Function):
             sim.adjoint_segment(ctx.ckpts[idx], A[s0:s1], fbar, rbar, fbuf, rnext, dA[s0:s1], dsig)
             fbar = fbuf
             rbar, rnext = rnext, rbar
-        return (dsig.reshape(ctx.sigma_shape).to(ctx.sdev), dA.to(ctx.adev), rbar.to(ctx.vdev), None, None)
+        return (dsig.reshape(ctx.sigma_shape).to(ctx.sdev), dA.to(ctx.adev), rbar.to(ctx.vdev), None, None, None)
 
 
-def deformation(sigma, A, vertices, K=50, **spec):
-    """Differentiable droplet deformation D(r^T); spec holds the Simulation
-    keywords other than sigma and vertices (L, tau, radius, triangles, ...)."""
+def deformation(sigma, A, vertices, K=50, objective="D", **spec):
+    """Differentiable droplet shape objective J(r^T): the deformation D
+    (default), "lambda_max" or "beta" (the last step's strain held fixed);
+    spec holds the Simulation keywords other than sigma and vertices (L, tau,
+    radius, triangles, ...)."""
     if not isinstance(sigma, torch.Tensor):
         sigma = torch.tensor(float(sigma), dtype=torch.float64)
     if not isinstance(vertices, torch.Tensor):
         vertices = torch.as_tensor(np.asarray(vertices, dtype=np.float64))
-    return DeformationFunction.apply(sigma, A, vertices, spec, int(K))
+    return DeformationFunction.apply(sigma, A, vertices, spec, int(K), objective)
