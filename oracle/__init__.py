@@ -45,7 +45,8 @@ class _Params(C.Structure):
                 ("tris", C.POINTER(C.c_int)), ("reg_alpha", C.c_double),
                 ("reg_gamma", C.c_double), ("reg_tol", C.c_double),
                 ("reg_max_iter", C.c_int), ("reg_sign", C.c_int), ("init_rest", C.c_int),
-                ("A0", C.c_double * 9), ("collision", C.c_int), ("mrt_s", C.c_double * 5)]
+                ("A0", C.c_double * 9), ("wall_bc", C.c_int), ("collision", C.c_int),
+                ("mrt_s", C.c_double * 5)]
 
 
 def lib():
@@ -200,7 +201,8 @@ class Oracle:
 
     def __init__(self, L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None,
                  periodic=(0, 0, 0), rho0=1.0, reg_alpha=0.1, reg_gamma=0.51, reg_tol=0.01,
-                 reg_max_iter=50, reg_sign=1, init_rest=False, A0=None, collision="bgk", mrt_s=None):
+                 reg_max_iter=50, reg_sign=1, init_rest=False, A0=None, collision="bgk", mrt_s=None,
+                 walls="link"):
         p = _Params()
         self.L = tuple(int(v) for v in L)
         for a in range(3):
@@ -222,6 +224,7 @@ class Oracle:
         for k in range(9):
             p.A0[k] = A0[k]
         p.collision = {"bgk": 0, "mrt": 1}[collision]
+        p.wall_bc = {"link": 0, "wet": 1}[walls]
         for k, v in enumerate(mrt_s if mrt_s is not None else [0.0] * 5):
             p.mrt_s[k] = float(v)
         h = C.c_void_p()

@@ -553,6 +553,7 @@ struct ibo_sim {
     double A_last[9];
     int* sched;             /* frozen smoothing iteration counts, see ibo_freeze_iters */
     int sched_n, sched_pos;
+    int wall_bc;            /* 0 link bounce-back, 1 wet-node velocity walls */
     int collision;          /* 0 BGK, 1 MRT */
     double mrt_M[19 * 19], mrt_n2[19], mrt_s[19];  /* basis, squared norms, rate per moment */
 };
@@ -577,6 +578,7 @@ int ibo_create(const ibo_params* p, ibo_sim** out)
         if (p->L[a] < 4) return IBO_EINVAL;
     if (!(p->tau > 0.5) || !(p->sigma >= 0.0) || !(p->rho0 > 0.0)) return IBO_EINVAL;
     if (p->collision < 0 || p->collision > 1) return IBO_EINVAL;
+    if (p->wall_bc < 0 || p->wall_bc > 1) return IBO_EINVAL;
     for (int k = 0; k < 5; ++k)
         if (!(p->mrt_s[k] >= 0.0 && p->mrt_s[k] < 2.0)) return IBO_EINVAL;
     if (p->nv < 0 || p->nt < 0 || (p->nv > 0 && (!p->verts || !p->tris || p->nt == 0)))
@@ -595,6 +597,7 @@ int ibo_create(const ibo_params* p, ibo_sim** out)
     s->nv = p->nv; s->nt = p->nt;
     s->reg_alpha = p->reg_alpha; s->reg_gamma = p->reg_gamma; s->reg_tol = p->reg_tol;
     s->reg_max_iter = p->reg_max_iter; s->reg_sign = p->reg_sign >= 0 ? 1 : -1;
+    s->wall_bc = p->wall_bc;
     s->collision = p->collision;
     if (s->collision == 1) {
         /* rate per moment: conserved rho and j at 1/tau (their non-equilibrium
@@ -761,6 +764,145 @@ static void stream(ibo_sim* s, const double A[9])
             }
 }
 
+/* Wet-node velocity walls (Sec. 3.1): the walls pass through the boundary
+ * nodes, each with the velocity u_w = A (x - x_c) of Eq.
+ * (velo_facce_cubo_da_gradiente) at the node. After streaming, a population
+ * f_j whose source x - c_j lies outside the box is unknown; with n the
+ * inward normal of a wall plane through x and i the opposite of j:
+ *  (a) one wall: rho = (sum_{c.n=0} f + 2 sum_{c.n<0} f) / (1 - u_w.n) (mass
+ *      and normal momentum) and Eq. (ZH_bulk),
+ *      f_j = f_i - (2 - |t_i|) rho/6 c_i.u_w - rho/3 t_i.u_w
+ *            + 1/2 sum_k f_k (t_i.c_k)(1 - |c_k.n|),  t_i = c_i - (c_i.n) n;
+ *  (b) two walls (an edge): Eq. (ZH_edges) for the unknowns whose opposite is
+ *      known, with t_i = c_i - (c_i.n1) n1 - (c_i.n2) n2, then the two buried
+ *      links c = +-(n1 - n2) by Eq. (zh-buried-links-edges) and f_0 = 12 f_b;
+ *  (c) three walls (a corner): the unknowns whose opposite is known by plain
+ *      reflection f_j = f_i (the text gives no rule for them), then the six
+ *      buried links c.(n1 + n2 + n3) = 0 by Eq. (zh-buried-links-corners) and
+ *      f_0 = 12 f_b.
+ * The edge and corner rules are applied as printed: they carry no
+ * wall-velocity term. */
+static void wet_walls(ibo_sim* s, const double A[9])
+{
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < s->L[2]; ++z)
+        for (long y = 0; y < s->L[1]; ++y)
+            for (long x = 0; x < s->L[0]; ++x) {
+                const long xyz[3] = {x, y, z};
+                int nw = 0;
+                int nrm[3][3];
+                for (int a = 0; a < 3; ++a) {
+                    if (s->per[a]) continue;
+                    int dir = xyz[a] == 0 ? 1 : (xyz[a] == s->L[a] - 1 ? -1 : 0);
+                    if (!dir) continue;
+                    for (int b = 0; b < 3; ++b) nrm[nw][b] = b == a ? dir : 0;
+                    ++nw;
+                }
+                if (!nw) continue;
+                double* f = s->f + 19 * (x + s->L[0] * (y + (long)s->L[1] * z));
+                double u[3];
+                for (int a = 0; a < 3; ++a) {
+                    u[a] = 0.0;
+                    for (int b = 0; b < 3; ++b) u[a] += A[3 * a + b] * (xyz[b] - s->xc[b]);
+                }
+                int unknown[19];
+                for (int j = 0; j < 19; ++j) {
+                    unknown[j] = 0;
+                    for (int k = 0; k < nw; ++k) {
+                        int cn = CV[j][0] * nrm[k][0] + CV[j][1] * nrm[k][1] + CV[j][2] * nrm[k][2];
+                        if (cn > 0) unknown[j] = 1;
+                    }
+                }
+                if (nw == 1) {
+                    const int* n = nrm[0];
+                    double s0 = 0.0, sm = 0.0;
+                    for (int k = 0; k < 19; ++k) {
+                        int cn = CV[k][0] * n[0] + CV[k][1] * n[1] + CV[k][2] * n[2];
+                        if (cn == 0) s0 += f[k];
+                        if (cn < 0) sm += f[k];
+                    }
+                    const double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+                    const double rho = (s0 + 2.0 * sm) / (1.0 - un);
+                    double fn[19];
+                    memcpy(fn, f, sizeof(fn));
+                    for (int j = 0; j < 19; ++j) {
+                        if (!unknown[j]) continue;
+                        const int i = opposite(j);
+                        const int ci_n = CV[i][0] * n[0] + CV[i][1] * n[1] + CV[i][2] * n[2];
+                        double t[3], tt = 0.0, cu = 0.0, tu = 0.0, corr = 0.0;
+                        for (int a = 0; a < 3; ++a) {
+                            t[a] = CV[i][a] - ci_n * n[a];
+                            tt += t[a] * t[a];
+                            cu += CV[i][a] * u[a];
+                            tu += t[a] * u[a];
+                        }
+                        for (int k = 0; k < 19; ++k) {
+                            int ck_n = CV[k][0] * n[0] + CV[k][1] * n[1] + CV[k][2] * n[2];
+                            double tc = t[0] * CV[k][0] + t[1] * CV[k][1] + t[2] * CV[k][2];
+                            corr += f[k] * tc * (1.0 - abs(ck_n));
+                        }
+                        fn[j] = f[i] - (2.0 - sqrt(tt)) * rho / 6.0 * cu - rho / 3.0 * tu + 0.5 * corr;
+                    }
+                    memcpy(f, fn, sizeof(fn));
+                    continue;
+                }
+                int buried[19];
+                for (int j = 0; j < 19; ++j) buried[j] = unknown[j] && unknown[opposite(j)];
+                /* the unknowns whose opposite is known */
+                double fn[19];
+                memcpy(fn, f, sizeof(fn));
+                for (int j = 0; j < 19; ++j) {
+                    if (!unknown[j] || buried[j]) continue;
+                    const int i = opposite(j);
+                    if (nw == 3) {
+                        fn[j] = f[i];
+                        continue;
+                    }
+                    double t[3], corr = 0.0;
+                    const int* n1 = nrm[0];
+                    const int* n2 = nrm[1];
+                    const int c1 = CV[i][0] * n1[0] + CV[i][1] * n1[1] + CV[i][2] * n1[2];
+                    const int c2 = CV[i][0] * n2[0] + CV[i][1] * n2[1] + CV[i][2] * n2[2];
+                    for (int a = 0; a < 3; ++a) t[a] = CV[i][a] - c1 * n1[a] - c2 * n2[a];
+                    for (int k = 0; k < 19; ++k) {
+                        int k1 = CV[k][0] * n1[0] + CV[k][1] * n1[1] + CV[k][2] * n1[2];
+                        int k2 = CV[k][0] * n2[0] + CV[k][1] * n2[1] + CV[k][2] * n2[2];
+                        double tc = t[0] * CV[k][0] + t[1] * CV[k][1] + t[2] * CV[k][2];
+                        corr += f[k] * tc * (1.0 - abs(k1)) * (1.0 - abs(k2));
+                    }
+                    fn[j] = f[i] - 0.25 * corr;
+                }
+                memcpy(f, fn, sizeof(fn));
+                /* buried links and the rest population */
+                double fb = 0.0;
+                if (nw == 2) {
+                    const int* n1 = nrm[0];
+                    const int* n2 = nrm[1];
+                    const int cr[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2],
+                                       n1[0] * n2[1] - n1[1] * n2[0]};
+                    for (int i = 1; i < 19; ++i) {
+                        const double c2 = CV[i][0] * CV[i][0] + CV[i][1] * CV[i][1] + CV[i][2] * CV[i][2];
+                        const double a1 = abs(CV[i][0] * cr[0] + CV[i][1] * cr[1] + CV[i][2] * cr[2]);
+                        const double a2 = abs(CV[i][0] * (n1[0] + n2[0]) + CV[i][1] * (n1[1] + n2[1]) +
+                                              CV[i][2] * (n1[2] + n2[2])) / c2;
+                        fb += f[i] * (1.0 - (1.0 - a1) * (1.0 - a2));
+                    }
+                    fb /= 22.0;
+                } else {
+                    int N[3];
+                    for (int a = 0; a < 3; ++a) N[a] = nrm[0][a] + nrm[1][a] + nrm[2][a];
+                    for (int i = 1; i < 19; ++i) {
+                        const double c2 = CV[i][0] * CV[i][0] + CV[i][1] * CV[i][1] + CV[i][2] * CV[i][2];
+                        fb += f[i] * abs(CV[i][0] * N[0] + CV[i][1] * N[1] + CV[i][2] * N[2]) / c2;
+                    }
+                    fb /= 18.0;
+                }
+                for (int j = 0; j < 19; ++j)
+                    if (buried[j]) f[j] = fb;
+                f[0] = 12.0 * fb;
+            }
+}
+
 static int one_step(ibo_sim* s, const double A[9])
 {
     int rc = force_field(s);                                   /* phi, F */
@@ -772,6 +914,7 @@ static int one_step(ibo_sim* s, const double A[9])
     }
     collide(s);
     stream(s, A);
+    if (s->wall_bc == 1) wet_walls(s, A);
     for (int k = 0; k < 3 * s->nv; ++k) s->r[k] += s->U[k];   /* Eq. (fwd_euler) */
     int capped = 0;
     if (s->sched_pos < s->sched_n) {

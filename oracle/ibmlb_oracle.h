@@ -65,6 +65,9 @@ typedef struct ibo_params {
     int reg_sign;      /* +1: correction adds the neighbour mean of b; -1: subtracts it */
     int init_rest;     /* 0: linear field u = A0 (x - x_c) with its non-equilibrium part; 1: rest */
     double A0[9];
+    int wall_bc;       /* 0: link-wise moving-wall bounce-back, walls at -1/2 and L-1/2;
+                          1: wet-node velocity walls through the boundary nodes (Sec. 3.1,
+                          the Zou-He conditions in the 3D form of Hecht and Harting) */
     int collision;     /* 0: BGK (the paper's single relaxation time); 1: MRT */
     double mrt_s[5];   /* MRT rates of the energy, energy-square, heat-flux, third-order
                           stress and third-order antisymmetric moments; 0 selects 1.19,
