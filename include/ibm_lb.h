@@ -83,6 +83,7 @@ typedef struct ibm_lb ibm_lb;
 typedef struct ibm_lb_batch ibm_lb_batch;
 
 enum { IBM_LB_BGK = 0, IBM_LB_MRT = 1 };
+enum { IBM_LB_WALLS_LINK = 0, IBM_LB_WALLS_WET = 1 };
 
 typedef struct ibm_lb_config {
     int32_t L[3];          /* nodes per axis, each >= 8; at most 2^31 - 1 nodes in all */
@@ -120,6 +121,12 @@ typedef struct ibm_lb_config {
     double mrt_s[5];       /* MRT rates in (0, 2) of the energy, energy-square, heat-flux,
                               third-order stress and third-order antisymmetric moments;
                               0 selects 1.19, 1.4, 1.2, 1.4, 1.98 */
+    int32_t walls;         /* IBM_LB_WALLS_LINK (0): link-wise moving-wall bounce-back, walls
+                              half a link outside the boundary nodes; IBM_LB_WALLS_WET: the
+                              paper's wet-node velocity walls through the boundary nodes
+                              (Sec. 3.1: Zou-He faces with the transverse correction, the
+                              printed edge and corner rules with buried links), two population
+                              copies, single droplets, without the adjoint */
 } ibm_lb_config;
 
 typedef struct ibm_lb_obs {
@@ -227,7 +234,8 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  *
  * ibm_lb_set_variant selects a variant directly (EINVAL if out of range,
  * bits 4 and 6 together, bit 6 clear on a one-copy handle, bit 4 or 6 on an
- * MRT handle, or the row layout cannot take this box). The default is 33 (linear layout,
+ * MRT handle, bit 6 with wet-node walls, or the row layout cannot take this
+ * box). The default is 33 (linear layout,
  * 128-thread work-groups, non-temporal loads, bit 5), or 96 on a one-copy
  * handle (in place, 128-thread work-groups, bit 5). */
 int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);

@@ -117,6 +117,9 @@ int validate(const ibm_lb_config* c) {
         if (!(c->mrt_s[k] >= 0.0 && c->mrt_s[k] < 2.0)) return fail(IBM_LB_EINVAL, "MRT rates must lie in (0, 2)");
     if (c->collision == IBM_LB_MRT && c->populations == 1)
         return fail(IBM_LB_EINVAL, "MRT runs with two population copies");
+    if (c->walls != IBM_LB_WALLS_LINK && c->walls != IBM_LB_WALLS_WET) return fail(IBM_LB_EINVAL, "unknown walls");
+    if (c->walls == IBM_LB_WALLS_WET && c->populations == 1)
+        return fail(IBM_LB_EINVAL, "wet-node walls run with two population copies");
     const int nv = c->n_vertices, nt = c->n_triangles;
     if (nv < 0 || nt < 0) return fail(IBM_LB_EINVAL, "negative mesh size");
     if (nv == 0 && nt == 0) return IBM_LB_OK;
@@ -351,6 +354,7 @@ struct ibm_lb {
     int lattice_variant = 1 | VAR_HC_SPLIT;  // non-temporal loads, 128-thread work-groups, split smoothing
     int aa_parity = 0;           // in-place variants: 1 after an even step (f[cur] not in natural order)
     bool single = false;         // one population copy (f[1] aliases f[0]; in-place variants only)
+    bool wet = false;            // wet-node velocity walls after every lattice step
     bool mrt = false;            // MRT collision with the rates below
     MrtRates mrt_rates{};
     double* stage = nullptr;     // pinned host staging for gradient rows
@@ -485,6 +489,8 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
         HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->lattice_variant, h->aa_parity,
                                h->stream, nullptr, e1, h->mrt ? &h->mrt_rates : nullptr),
                 "lattice launch");
+        if (h->wet)
+            HIP_TRY(launch_wet_walls(h->storage, h->g, h->lp, h->d, h->cur ^ 1, Arow, h->stream), "walls launch");
         if (ib)
             HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream, done,
                                    (h->lattice_variant & VAR_HC_SPLIT) != 0),
@@ -587,6 +593,7 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     const int ntiles = h->g.TX * h->g.TY * h->g.TZ;
     h->single = cfg->populations == 1;
     h->mrt = cfg->collision == IBM_LB_MRT;
+    h->wet = cfg->walls == IBM_LB_WALLS_WET;
     if (h->mrt) {
         // per moment of the basis: conserved density and momentum and the five
         // shear moments at 1/tau, the others from the configuration
@@ -947,7 +954,7 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     if (!h->single)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
             if (!h->mrt || !(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT;
-    if (!h->mrt)
+    if (!h->mrt && !h->wet)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
             if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
     tune(cand, nc, best_of);
@@ -973,6 +980,7 @@ int ibm_lb_set_variant(ibm_lb* h, int32_t variant) {
         return fail(IBM_LB_EINVAL, "a handle with one population copy runs in-place variants only");
     if (h->mrt && (variant & (VAR_ROWS | VAR_AA)))
         return fail(IBM_LB_EINVAL, "MRT runs the linear layout with two copies");
+    if (h->wet && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "wet-node walls run with two copies");
     h->lattice_variant = variant;
     return IBM_LB_OK;
 }
@@ -1073,7 +1081,7 @@ int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar) {
 int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, double* rbar) {
     if (!h || !value || !rbar) return fail(IBM_LB_EINVAL, "bad objective_grad arguments");
     if (objective < IBM_LB_OBJ_D || objective > IBM_LB_OBJ_BETA) return fail(IBM_LB_EINVAL, "unknown objective");
-    if (h->mrt) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step");
+    if (h->mrt || h->wet) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step with link walls");
     if (h->nv == 0) return fail(IBM_LB_EINVAL, "the objective needs a mesh");
     if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
     int rc = set_device(h);
@@ -1108,7 +1116,7 @@ int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const
         return fail(IBM_LB_EINVAL, "bad adjoint_segment arguments");
     if (h->nv > 0 && (!rbar_end || !rbar_begin))
         return fail(IBM_LB_EINVAL, "rbar_end and rbar_begin are required with a mesh");
-    if (h->mrt) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step");
+    if (h->mrt || h->wet) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step with link walls");
     int rc = set_device(h);
     if (rc) return rc;
     rc = ibm_lb_load(h, ckpt, ckpt_bytes);
@@ -1240,6 +1248,7 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     for (int i = 0; i < n; ++i) {
         if (cfgs[i].populations == 1) return fail(IBM_LB_EINVAL, "ensemble members keep two population copies");
         if (cfgs[i].collision != IBM_LB_BGK) return fail(IBM_LB_EINVAL, "ensemble members run BGK");
+        if (cfgs[i].walls != IBM_LB_WALLS_LINK) return fail(IBM_LB_EINVAL, "ensemble members run link walls");
     }
     ibm_lb_batch* b = new (std::nothrow) ibm_lb_batch();
     if (!b) return fail(IBM_LB_ENOMEM, "host allocation");

@@ -151,6 +151,10 @@ hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, c
 // After an even in-place step: f[cur] back to natural order, in place.
 hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cur, hipStream_t s);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
+// Wet-node velocity walls on the streamed populations f[cur] (natural order)
+// with the gradient row A_row.
+hipError_t launch_wet_walls(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
+                            const double* A_row, hipStream_t s);
 // maps: eight block maps, concatenated (table q from entry moff[q],
 // nblocks[q] entries; entry b = {member, block index within the member}).
 // Tables 0-3: linear layout with LAT_BS[q]-node blocks; tables 4-7: row

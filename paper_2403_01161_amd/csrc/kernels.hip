@@ -612,6 +612,163 @@ __global__ void k_clear(R* F, long long n) {
         F[i] = R(0);
 }
 
+// ---------------------------------------------------------------- wet-node walls
+// Velocity walls through the boundary nodes (Sec. 3.1, the Zou-He conditions
+// in the 3D form of Hecht and Harting), applied to the streamed populations
+// of f: every population whose source lies outside the box is rebuilt from
+// the known ones and the wall velocity u_w = A (x - x_c) at the node. With n
+// the inward normal of a wall through the node and i the opposite of an
+// unknown j (deviations d = f - w rho0; the rest-weight parts cancel):
+//   one wall (Eq. ZH_bulk): rho = (rho0 + sum_{c.n=0} d + 2 sum_{c.n<0} d) / (1 - u_w.n),
+//     d_j = d_i - (2 - |t_i|) rho/6 c_i.u_w - rho/3 t_i.u_w + 1/2 sum_k d_k (t_i.c_k)(1 - |c_k.n|),
+//     t_i = c_i - (c_i.n) n;
+//   two walls (an edge, Eq. ZH_edges): d_j = d_i - 1/4 sum_k d_k (t_i.c_k)(1 - |c_k.n1|)(1 - |c_k.n2|)
+//     for the unknowns with a known opposite, then the buried links
+//     c = +-(n1 - n2) by Eq. (zh-buried-links-edges) and d_0 = 12 d_b;
+//   three walls (a corner): d_j = d_i for the unknowns with a known opposite
+//     (the text gives no rule for them), the six buried links
+//     c.(n1 + n2 + n3) = 0 by Eq. (zh-buried-links-corners) and d_0 = 12 d_b.
+// Thread t takes node t of the concatenated non-periodic face planes; a node on
+// several faces is rebuilt by the first of them (order x-, x+, y-, y+, z-, z+).
+template <class C>
+__global__ __launch_bounds__(256) void k_wet_walls(Geom g, LatticeParams lp, typename C::store_t* __restrict__ f,
+                                                   const double* __restrict__ Arow, long long total) {
+    using R = typename C::real;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= total) return;
+    const int L[3] = {g.Lx, g.Ly, g.Lz};
+    const int per[3] = {g.px, g.py, g.pz};
+    // face of this thread and the node on it
+    long long r = t;
+    int face = -1, p[3] = {0, 0, 0};
+    for (int fc = 0; fc < 6 && face < 0; ++fc) {
+        const int a = fc >> 1;
+        if (per[a]) continue;
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        const long long area = (long long)L[b] * L[c];
+        if (r < area) {
+            face = fc;
+            p[a] = (fc & 1) ? L[a] - 1 : 0;
+            p[b] = int(r % L[b]);
+            p[c] = int(r / L[b]);
+        } else {
+            r -= area;
+        }
+    }
+    if (face < 0) return;
+    int nrm[3][3], nw = 0, first = -1;
+    for (int a = 0; a < 3; ++a) {
+        if (per[a]) continue;
+        const int dir = p[a] == 0 ? 1 : (p[a] == L[a] - 1 ? -1 : 0);
+        if (!dir) continue;
+        if (first < 0) first = 2 * a + (dir < 0 ? 1 : 0);
+        for (int b = 0; b < 3; ++b) nrm[nw][b] = b == a ? dir : 0;
+        ++nw;
+    }
+    if (first != face) return;  // another face's thread rebuilds this node
+    const long long N = g.N;
+    const long long n = p[0] + (long long)g.Lx * (p[1] + (long long)g.Ly * p[2]);
+    R d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = dec<C>(f[i * N + n], lp.inv_scale);
+    R u[3];
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < 3; ++b) s += Arow[3 * a + b] * double(p[b] - g.xci[b] - g.xcf[b]);
+        u[a] = R(s);
+    }
+    auto dotn = [&](int i, const int* nv) { return CX[i] * nv[0] + CY[i] * nv[1] + CZ[i] * nv[2]; };
+    bool unknown[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        bool uk = false;
+        for (int k = 0; k < nw; ++k) uk = uk || dotn(j, nrm[k]) > 0;
+        unknown[j] = uk;
+    }
+    R out[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) out[j] = d[j];
+    if (nw == 1) {
+        const int* nv = nrm[0];
+        R s0 = R(0), sm = R(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const int cn = dotn(k, nv);
+            if (cn == 0) s0 += d[k];
+            if (cn < 0) sm += d[k];
+        }
+        const R un = u[0] * R(nv[0]) + u[1] * R(nv[1]) + u[2] * R(nv[2]);
+        const R rho = (R(lp.rho0) + s0 + R(2) * sm) / (R(1) - un);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            if (!unknown[j]) continue;
+            const int i = opp(j);
+            const int cin = dotn(i, nv);
+            const int tx = CX[i] - cin * nv[0], ty = CY[i] - cin * nv[1], tz = CZ[i] - cin * nv[2];
+            const R tn = R(tx * tx + ty * ty + tz * tz);  // |t| is 0 or 1
+            const R cu = R(CX[i]) * u[0] + R(CY[i]) * u[1] + R(CZ[i]) * u[2];
+            const R tu = R(tx) * u[0] + R(ty) * u[1] + R(tz) * u[2];
+            R corr = R(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+                if (dotn(k, nv) == 0) corr += d[k] * R(tx * CX[k] + ty * CY[k] + tz * CZ[k]);
+            out[j] = d[i] - (R(2) - tn) * rho / R(6) * cu - rho / R(3) * tu + R(0.5) * corr;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            if (!unknown[j] || unknown[opp(j)]) continue;
+            const int i = opp(j);
+            if (nw == 3) {
+                out[j] = d[i];
+                continue;
+            }
+            const int c1 = dotn(i, nrm[0]), c2 = dotn(i, nrm[1]);
+            const int tx = CX[i] - c1 * nrm[0][0] - c2 * nrm[1][0];
+            const int ty = CY[i] - c1 * nrm[0][1] - c2 * nrm[1][1];
+            const int tz = CZ[i] - c1 * nrm[0][2] - c2 * nrm[1][2];
+            R corr = R(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+                if (dotn(k, nrm[0]) == 0 && dotn(k, nrm[1]) == 0)
+                    corr += d[k] * R(tx * CX[k] + ty * CY[k] + tz * CZ[k]);
+            out[j] = d[i] - R(0.25) * corr;
+        }
+        R fb = R(0);
+        if (nw == 2) {
+            const int* n1 = nrm[0];
+            const int* n2 = nrm[1];
+            const int cr[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2],
+                               n1[0] * n2[1] - n1[1] * n2[0]};
+            const int sn[3] = {n1[0] + n2[0], n1[1] + n2[1], n1[2] + n2[2]};
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int c2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
+                const R a1 = R(abs(dotn(i, cr)));
+                const R a2 = R(abs(dotn(i, sn))) / R(c2);
+                fb += out[i] * (R(1) - (R(1) - a1) * (R(1) - a2));
+            }
+            fb /= R(22);
+        } else {
+            const int sn[3] = {nrm[0][0] + nrm[1][0] + nrm[2][0], nrm[0][1] + nrm[1][1] + nrm[2][1],
+                               nrm[0][2] + nrm[1][2] + nrm[2][2]};
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int c2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
+                fb += out[i] * R(abs(dotn(i, sn))) / R(c2);
+            }
+            fb /= R(18);
+        }
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+            if (unknown[j] && unknown[opp(j)]) out[j] = fb;
+        out[0] = R(12) * fb;
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+        if (unknown[j] || (j == 0 && nw > 1)) f[j * N + n] = enc<C>(out[j], lp.scale);
+}
+
 // ---------------------------------------------------------------- observables (FP64)
 // Signed tetrahedra (x_c, a, b, c) of every triangle: V_t = a.(b x c)/6,
 // int x dV = V_t (a+b+c)/4, int x x^T dV = V_t/20 (aa^T+bb^T+cc^T+ss^T).
@@ -1097,6 +1254,22 @@ hipError_t launch_set_rows(LatDesc* desc, int n, const double* base, long long s
 #define DISPATCH_REAL(storage, R, ...)                                   \
     if ((storage) == IBM_LB_F64) { using R = double; __VA_ARGS__; }     \
     else { using R = float; __VA_ARGS__; }
+
+hipError_t launch_wet_walls(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
+                            const double* A_row, hipStream_t s) {
+    const int L[3] = {g.Lx, g.Ly, g.Lz};
+    const int per[3] = {g.px, g.py, g.pz};
+    long long total = 0;
+    for (int a = 0; a < 3; ++a)
+        if (!per[a]) total += 2ll * L[(a + 1) % 3] * L[(a + 2) % 3];
+    if (total == 0) return hipSuccess;
+    DISPATCH_STORAGE(storage, C, {
+        using S = typename C::store_t;
+        hipLaunchKernelGGL(k_wet_walls<C>, dim3(blocks_for(total, 256)), dim3(256), 0, s, g, lp, (S*)d.f[cur], A_row,
+                           total);
+    });
+    return hipGetLastError();
+}
 
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s) {
     hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, s, d.ctl);

@@ -98,6 +98,7 @@ def test_ensemble_rejects_one_copy_members(ib):
     dict(storage=7), dict(init=5), dict(reg_sign=2), dict(reg_max_iter=-1),
     dict(f16_scale=3.0, storage="f16dev"), dict(A0=[np.nan] + [0] * 8), dict(populations=3),
     dict(collision=2), dict(collision="mrt", mrt_s=[2.0, 1, 1, 1, 1]), dict(collision="mrt", populations=1),
+    dict(walls=2), dict(walls="wet", populations=1),
 ])
 def test_invalid_parameters(ib, bad):
     cfg, keep = _cfg(ib, **bad)

@@ -1,0 +1,90 @@
+"""GPU wet-node velocity walls against the oracle's (the same rules: Zou-He
+faces with the transverse correction, the printed edge and corner rules with
+buried links): a droplet in FP64 and FP32, plane Couette flow exact at every
+node, every lattice variant bit-identical, and the limits (two copies,
+single droplets, no adjoint)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_01161_amd.inputs import box_center, icosphere
+
+pytestmark = pytest.mark.gpu
+
+ROWS, AA = 16, 64
+
+
+@pytest.fixture(scope="module")
+def ib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_01161_amd import ibmlb
+    ibmlb.lib()
+    return ibmlb
+
+
+def _traceless(scale, seed):
+    A = np.random.default_rng(seed).standard_normal((3, 3))
+    A -= np.trace(A) / 3 * np.eye(3)
+    return (scale * A / np.linalg.norm(A)).ravel()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", (1e-11, 1e-11, 1e-13)), ("f32", (2e-5, 2e-4, 1e-6))])
+def test_wet_walls_droplet_matches_oracle(ib, storage, tol):
+    L = (19, 17, 21)
+    A = _traceless(3e-3, 2)
+    V, T = icosphere(2, 3.2, box_center(L))
+    kw = dict(tau=0.9, sigma=0.02, radius=3.2, vertices=V, triangles=T, A0=A)
+    print(f"case wet walls droplet {storage}", flush=True)
+    sim = ib.Simulation(L, storage=storage, walls="wet", **kw)
+    ref = oracle.Oracle(L, walls="wet", **kw)
+    sim.step(A, 30)
+    ref.step(A, 30)
+    dr = np.abs(sim.vertices() - ref.vertices()).max()
+    rho_g, u_g = sim.fields()
+    rho_r, u_r = ref.fields()
+    du = np.abs(u_g - u_r).max() / np.abs(u_r).max()
+    drho = np.abs(rho_g - rho_r).max()
+    print(f"  max|dr| {dr:.2e}  du {du:.2e}  drho {drho:.2e}", flush=True)
+    assert dr <= tol[0] and du <= tol[1] and drho <= tol[2]
+    sim.close()
+    ref.close()
+
+
+def test_wet_walls_couette_exact(ib):
+    L = (8, 12, 8)
+    g = 1e-3
+    A = np.zeros(9)
+    A[1] = g
+    sim = ib.Simulation(L, 0.8, storage="f64", A0=A, periodic=(1, 0, 1), walls="wet")
+    sim.step(A, 200)
+    rho, u = sim.fields()
+    sim.close()
+    y = np.arange(L[1])[None, :, None]
+    assert np.abs(u[0] - g * (y - (L[1] - 1) / 2)).max() <= 1e-14
+    assert np.abs(u[1:]).max() <= 1e-14
+    assert np.abs(rho - 1.0).max() <= 1e-13
+
+
+def test_wet_walls_variants_bit_identical(ib):
+    L, A = (40, 9, 11), _traceless(2e-3, 3)
+    states = {}
+    for v in (1, 0, 3, 8, 9, ROWS | 1, ROWS | 8, ROWS | 6):
+        sim = ib.Simulation(L, 0.8, storage="f32", A0=A, walls="wet")
+        sim.set_variant(v)
+        sim.step(A, 7)
+        states[v] = sim.save().cpu().numpy().copy()
+        sim.close()
+    for v, st in states.items():
+        assert np.array_equal(st, states[1]), f"variant {v}"
+
+
+def test_wet_walls_limits(ib):
+    sim = ib.Simulation((12, 10, 9), 0.8, storage="f32", walls="wet")
+    with pytest.raises(ib.IbmLbError):
+        sim.set_variant(AA | 1)
+    assert not (sim.autotune(2) & AA)
+    sim.close()
+    with pytest.raises(ib.IbmLbError):
+        ib.Ensemble([dict(L=(8, 8, 8), tau=0.8, walls="wet")], storage="f32")
