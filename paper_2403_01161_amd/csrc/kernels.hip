@@ -628,145 +628,141 @@ __global__ void k_clear(R* F, long long n) {
 //   three walls (a corner): d_j = d_i for the unknowns with a known opposite
 //     (the text gives no rule for them), the six buried links
 //     c.(n1 + n2 + n3) = 0 by Eq. (zh-buried-links-corners) and d_0 = 12 d_b.
-// Thread t takes node t of the concatenated non-periodic face planes; a node on
-// several faces is rebuilt by the first of them (order x-, x+, y-, y+, z-, z+).
+// Thread t takes node t of the concatenated non-periodic face planes, the
+// lower in-plane axis fastest (so the y and z faces read whole x-rows); a
+// node on several faces is rebuilt by the first of them (order x-, x+, y-,
+// y+, z-, z+). With (wx, wy, wz) the inward normal components of the walls
+// through the node, every rule above is generic: t_i is c_i without its wall
+// components, the products (1 - |c.n|) run over the walls, n1 + n2 (+ n3) is
+// (wx, wy, wz), and n1 x n2 points along the axis without a wall.
 template <class C>
 __global__ __launch_bounds__(256) void k_wet_walls(Geom g, LatticeParams lp, typename C::store_t* __restrict__ f,
                                                    const double* __restrict__ Arow, long long total) {
     using R = typename C::real;
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= total) return;
-    const int L[3] = {g.Lx, g.Ly, g.Lz};
-    const int per[3] = {g.px, g.py, g.pz};
-    // face of this thread and the node on it
-    long long r = t;
-    int face = -1, p[3] = {0, 0, 0};
-    for (int fc = 0; fc < 6 && face < 0; ++fc) {
-        const int a = fc >> 1;
-        if (per[a]) continue;
-        const int b = (a + 1) % 3, c = (a + 2) % 3;
-        const long long area = (long long)L[b] * L[c];
-        if (r < area) {
-            face = fc;
-            p[a] = (fc & 1) ? L[a] - 1 : 0;
-            p[b] = int(r % L[b]);
-            p[c] = int(r / L[b]);
+    long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r >= total) return;
+    // the face of this thread and its node (faces of periodic axes absent)
+    int x = 0, y = 0, z = 0, face = -1;
+    const long long ax = (long long)g.Ly * g.Lz, ay = (long long)g.Lx * g.Lz, az = (long long)g.Lx * g.Ly;
+    if (!g.px) {
+        if (r < 2 * ax) {
+            face = r < ax ? 0 : 1;
+            const long long q = r - (face & 1) * ax;
+            x = face == 0 ? 0 : g.Lx - 1;
+            y = int(q % g.Ly);
+            z = int(q / g.Ly);
         } else {
-            r -= area;
+            r -= 2 * ax;
+        }
+    }
+    if (face < 0 && !g.py) {
+        if (r < 2 * ay) {
+            face = r < ay ? 2 : 3;
+            const long long q = r - (face & 1) * ay;
+            y = face == 2 ? 0 : g.Ly - 1;
+            x = int(q % g.Lx);
+            z = int(q / g.Lx);
+        } else {
+            r -= 2 * ay;
+        }
+    }
+    if (face < 0 && !g.pz) {
+        if (r < 2 * az) {
+            face = r < az ? 4 : 5;
+            const long long q = r - (face & 1) * az;
+            z = face == 4 ? 0 : g.Lz - 1;
+            x = int(q % g.Lx);
+            y = int(q / g.Lx);
         }
     }
     if (face < 0) return;
-    int nrm[3][3], nw = 0, first = -1;
-    for (int a = 0; a < 3; ++a) {
-        if (per[a]) continue;
-        const int dir = p[a] == 0 ? 1 : (p[a] == L[a] - 1 ? -1 : 0);
-        if (!dir) continue;
-        if (first < 0) first = 2 * a + (dir < 0 ? 1 : 0);
-        for (int b = 0; b < 3; ++b) nrm[nw][b] = b == a ? dir : 0;
-        ++nw;
-    }
+    // inward normal components of the walls through the node (0: no wall on that axis)
+    const int wx = g.px ? 0 : (x == 0 ? 1 : (x == g.Lx - 1 ? -1 : 0));
+    const int wy = g.py ? 0 : (y == 0 ? 1 : (y == g.Ly - 1 ? -1 : 0));
+    const int wz = g.pz ? 0 : (z == 0 ? 1 : (z == g.Lz - 1 ? -1 : 0));
+    const int first = wx ? (wx > 0 ? 0 : 1) : (wy ? (wy > 0 ? 2 : 3) : (wz > 0 ? 4 : 5));
     if (first != face) return;  // another face's thread rebuilds this node
+    const int nw = (wx != 0) + (wy != 0) + (wz != 0);
     const long long N = g.N;
-    const long long n = p[0] + (long long)g.Lx * (p[1] + (long long)g.Ly * p[2]);
+    const long long n = x + (long long)g.Lx * (y + (long long)g.Ly * z);
     R d[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = dec<C>(f[i * N + n], lp.inv_scale);
-    R u[3];
-    for (int a = 0; a < 3; ++a) {
-        double s = 0.0;
-        for (int b = 0; b < 3; ++b) s += Arow[3 * a + b] * double(p[b] - g.xci[b] - g.xcf[b]);
-        u[a] = R(s);
-    }
-    auto dotn = [&](int i, const int* nv) { return CX[i] * nv[0] + CY[i] * nv[1] + CZ[i] * nv[2]; };
-    bool unknown[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        bool uk = false;
-        for (int k = 0; k < nw; ++k) uk = uk || dotn(j, nrm[k]) > 0;
-        unknown[j] = uk;
-    }
+    const double rx = x - g.xci[0] - g.xcf[0], ry = y - g.xci[1] - g.xcf[1], rz = z - g.xci[2] - g.xcf[2];
+    const R u0 = R(Arow[0] * rx + Arow[1] * ry + Arow[2] * rz);
+    const R u1 = R(Arow[3] * rx + Arow[4] * ry + Arow[5] * rz);
+    const R u2 = R(Arow[6] * rx + Arow[7] * ry + Arow[8] * rz);
+    // per population: unknown (from outside), c.(sum of the normals), and the
+    // product over the walls of (1 - |c.n|)
+    auto unk = [&](int j) { return wx * CX[j] > 0 || wy * CY[j] > 0 || wz * CZ[j] > 0; };
+    auto cN = [&](int j) { return wx * CX[j] + wy * CY[j] + wz * CZ[j]; };
+    auto tang = [&](int k) {
+        return (1 - abs(wx * CX[k])) * (1 - abs(wy * CY[k])) * (1 - abs(wz * CZ[k]));
+    };
     R out[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) out[j] = d[j];
     if (nw == 1) {
-        const int* nv = nrm[0];
         R s0 = R(0), sm = R(0);
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-            const int cn = dotn(k, nv);
-            if (cn == 0) s0 += d[k];
-            if (cn < 0) sm += d[k];
+            const int cn = cN(k);
+            s0 += cn == 0 ? d[k] : R(0);
+            sm += cn < 0 ? d[k] : R(0);
         }
-        const R un = u[0] * R(nv[0]) + u[1] * R(nv[1]) + u[2] * R(nv[2]);
+        const R un = u0 * R(wx) + u1 * R(wy) + u2 * R(wz);
         const R rho = (R(lp.rho0) + s0 + R(2) * sm) / (R(1) - un);
 #pragma unroll
-        for (int j = 0; j < Q; ++j) {
-            if (!unknown[j]) continue;
+        for (int j = 1; j < Q; ++j) {
+            if (!unk(j)) continue;
             const int i = opp(j);
-            const int cin = dotn(i, nv);
-            const int tx = CX[i] - cin * nv[0], ty = CY[i] - cin * nv[1], tz = CZ[i] - cin * nv[2];
+            // t_i: c_i without its component along the normal
+            const int tx = wx ? 0 : CX[i], ty = wy ? 0 : CY[i], tz = wz ? 0 : CZ[i];
             const R tn = R(tx * tx + ty * ty + tz * tz);  // |t| is 0 or 1
-            const R cu = R(CX[i]) * u[0] + R(CY[i]) * u[1] + R(CZ[i]) * u[2];
-            const R tu = R(tx) * u[0] + R(ty) * u[1] + R(tz) * u[2];
+            const R cu = R(CX[i]) * u0 + R(CY[i]) * u1 + R(CZ[i]) * u2;
+            const R tu = R(tx) * u0 + R(ty) * u1 + R(tz) * u2;
             R corr = R(0);
 #pragma unroll
-            for (int k = 0; k < Q; ++k)
-                if (dotn(k, nv) == 0) corr += d[k] * R(tx * CX[k] + ty * CY[k] + tz * CZ[k]);
+            for (int k = 1; k < Q; ++k) corr += R(tang(k) * (tx * CX[k] + ty * CY[k] + tz * CZ[k])) * d[k];
             out[j] = d[i] - (R(2) - tn) * rho / R(6) * cu - rho / R(3) * tu + R(0.5) * corr;
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < Q; ++j) {
-            if (!unknown[j] || unknown[opp(j)]) continue;
+        for (int j = 1; j < Q; ++j) {
+            if (!unk(j) || unk(opp(j))) continue;
             const int i = opp(j);
             if (nw == 3) {
                 out[j] = d[i];
                 continue;
             }
-            const int c1 = dotn(i, nrm[0]), c2 = dotn(i, nrm[1]);
-            const int tx = CX[i] - c1 * nrm[0][0] - c2 * nrm[1][0];
-            const int ty = CY[i] - c1 * nrm[0][1] - c2 * nrm[1][1];
-            const int tz = CZ[i] - c1 * nrm[0][2] - c2 * nrm[1][2];
+            const int tx = wx ? 0 : CX[i], ty = wy ? 0 : CY[i], tz = wz ? 0 : CZ[i];
             R corr = R(0);
 #pragma unroll
-            for (int k = 0; k < Q; ++k)
-                if (dotn(k, nrm[0]) == 0 && dotn(k, nrm[1]) == 0)
-                    corr += d[k] * R(tx * CX[k] + ty * CY[k] + tz * CZ[k]);
+            for (int k = 1; k < Q; ++k) corr += R(tang(k) * (tx * CX[k] + ty * CY[k] + tz * CZ[k])) * d[k];
             out[j] = d[i] - R(0.25) * corr;
         }
         R fb = R(0);
-        if (nw == 2) {
-            const int* n1 = nrm[0];
-            const int* n2 = nrm[1];
-            const int cr[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2],
-                               n1[0] * n2[1] - n1[1] * n2[0]};
-            const int sn[3] = {n1[0] + n2[0], n1[1] + n2[1], n1[2] + n2[2]};
 #pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const int c2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
-                const R a1 = R(abs(dotn(i, cr)));
-                const R a2 = R(abs(dotn(i, sn))) / R(c2);
+        for (int i = 1; i < Q; ++i) {
+            const int c2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
+            const R a2 = R(abs(cN(i))) / R(c2);
+            if (nw == 2) {
+                // |c.(n1 x n2)|: the component along the axis without a wall
+                const R a1 = R(abs(wx ? (wy ? CZ[i] : CY[i]) : CX[i]));
                 fb += out[i] * (R(1) - (R(1) - a1) * (R(1) - a2));
+            } else {
+                fb += out[i] * a2;
             }
-            fb /= R(22);
-        } else {
-            const int sn[3] = {nrm[0][0] + nrm[1][0] + nrm[2][0], nrm[0][1] + nrm[1][1] + nrm[2][1],
-                               nrm[0][2] + nrm[1][2] + nrm[2][2]};
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const int c2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
-                fb += out[i] * R(abs(dotn(i, sn))) / R(c2);
-            }
-            fb /= R(18);
         }
+        fb /= nw == 2 ? R(22) : R(18);
 #pragma unroll
-        for (int j = 0; j < Q; ++j)
-            if (unknown[j] && unknown[opp(j)]) out[j] = fb;
+        for (int j = 1; j < Q; ++j)
+            if (unk(j) && unk(opp(j))) out[j] = fb;
         out[0] = R(12) * fb;
     }
 #pragma unroll
     for (int j = 0; j < Q; ++j)
-        if (unknown[j] || (j == 0 && nw > 1)) f[j * N + n] = enc<C>(out[j], lp.scale);
+        if ((j > 0 && unk(j)) || (j == 0 && nw > 1)) f[j * N + n] = enc<C>(out[j], lp.scale);
 }
 
 // ---------------------------------------------------------------- observables (FP64)
@@ -1257,11 +1253,10 @@ hipError_t launch_set_rows(LatDesc* desc, int n, const double* base, long long s
 
 hipError_t launch_wet_walls(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
                             const double* A_row, hipStream_t s) {
-    const int L[3] = {g.Lx, g.Ly, g.Lz};
-    const int per[3] = {g.px, g.py, g.pz};
     long long total = 0;
-    for (int a = 0; a < 3; ++a)
-        if (!per[a]) total += 2ll * L[(a + 1) % 3] * L[(a + 2) % 3];
+    if (!g.px) total += 2ll * g.Ly * g.Lz;
+    if (!g.py) total += 2ll * g.Lx * g.Lz;
+    if (!g.pz) total += 2ll * g.Lx * g.Ly;
     if (total == 0) return hipSuccess;
     DISPATCH_STORAGE(storage, C, {
         using S = typename C::store_t;
