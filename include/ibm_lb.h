@@ -313,10 +313,11 @@ void ibm_lb_batch_destroy(ibm_lb_batch* b);
  * ibm_lb_shape_objective_grad: the same for objective IBM_LB_OBJ_D (as
  *   above), IBM_LB_OBJ_LAMBDA_MAX (the largest eigenvalue of S; needs
  *   l1 - l2 >= 1e-12 radius^2) or IBM_LB_OBJ_BETA (Eq. beta with the strain
- *   E of the last step held fixed: the gradient does not include beta's
- *   direct dependence on the last gradient row; needs l1 - l2 >= 1e-12
- *   radius^2 and E != 0). The adjoint sweep is the same for every objective:
- *   rbar seeds ibm_lb_adjoint_segment.
+ *   E of the last gradient row; needs l1 - l2 >= 1e-12 radius^2 and E != 0).
+ *   dA_last (host double[9], may be NULL) receives the objective's direct
+ *   derivative with respect to the last gradient row (nonzero for beta
+ *   only), to be added to the last row of the adjoint's dJ/dA. The adjoint
+ *   sweep is the same for every objective: rbar seeds ibm_lb_adjoint_segment.
  *
  * ibm_lb_adjoint_segment: reverse one segment of nsteps >= 1 steps.
  *   ckpt (host or device, ckpt_bytes) is the checkpoint ibm_lb_save wrote at
@@ -339,7 +340,7 @@ void ibm_lb_batch_destroy(ibm_lb_batch* b);
  *   Errors: EINVAL (bad arguments or checkpoint), ENOMEM, EDEVICE, sticky. */
 enum { IBM_LB_OBJ_D = 0, IBM_LB_OBJ_LAMBDA_MAX = 1, IBM_LB_OBJ_BETA = 2 };
 int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar);
-int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, double* rbar);
+int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, double* rbar, double* dA_last);
 int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const double* A, int32_t nsteps,
                            int32_t A_on_device, const double* fbar_end, const double* rbar_end, double* fbar_begin,
                            double* rbar_begin, double* dA, double* dsigma);

@@ -464,7 +464,8 @@ __global__ __launch_bounds__(256) void k_adj_reduce_sigma(long long n, const dou
 // Through S = 5M/V - 5 P P^T / V^2 (P = V xb):
 //   Mbar = 5 Sbar / V,  Pbar = -10 Sbar xb / V,  Vbar = (-Sbar:S + 5 xb.Sbar xb) / V.
 // Other objectives: J = lambda_max, Sbar = v1 v1^T; J = beta = v1^T E v1 / |E|
-// (Eq. beta, E of the last step held fixed), through the eigenvector
+// (Eq. beta; its direct dependence on the last row, through E, is added on
+// the host), through the eigenvector
 // derivative dv1 = sum_{j > 1} v_j (v_j^T dS v1) / (l1 - l_j):
 // Sbar = sum_{j > 1} 2 (v1^T E v_j) / (|E| (l1 - l_j)) (v_j v1^T + v1 v_j^T) / 2.
 // obs: the observables record (0 V, 1..3 xb relative to x_c, 4..12 S,

@@ -1075,10 +1075,10 @@ AdjStep adj_step(ibm_lb* h, int j) {
 extern "C" {
 
 int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar) {
-    return ibm_lb_shape_objective_grad(h, IBM_LB_OBJ_D, value, rbar);
+    return ibm_lb_shape_objective_grad(h, IBM_LB_OBJ_D, value, rbar, nullptr);
 }
 
-int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, double* rbar) {
+int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, double* rbar, double* dA_last) {
     if (!h || !value || !rbar) return fail(IBM_LB_EINVAL, "bad objective_grad arguments");
     if (objective < IBM_LB_OBJ_D || objective > IBM_LB_OBJ_BETA) return fail(IBM_LB_EINVAL, "unknown objective");
     if (h->mrt || h->wet) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step with link walls");
@@ -1102,6 +1102,25 @@ int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, dou
     if (objective == IBM_LB_OBJ_BETA && (o[28] != o[28] || (int)o[28] & IBM_LB_OBS_E_ZERO))
         return fail(IBM_LB_EINVAL, "beta needs a nonzero strain E");
     *value = objective == IBM_LB_OBJ_D ? o[25] : (objective == IBM_LB_OBJ_LAMBDA_MAX ? o[13] : o[26]);
+    if (dA_last) {
+        // beta = v1^T E v1 / |E| also depends on the last gradient row through
+        // E = (A + A^T)/2: dbeta/dA = v1 v1^T / |E| - beta E / |E|^2 (symmetric);
+        // D and lambda_max do not
+        for (int k = 0; k < 9; ++k) dA_last[k] = 0.0;
+        if (objective == IBM_LB_OBJ_BETA) {
+            double A[9], E[9], En = 0.0;
+            HIP_TRY(hipMemcpy(A, h->d.Abuf + 9ll * ACAP, sizeof(A), hipMemcpyDeviceToHost), "gradient row");
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    E[3 * i + j] = 0.5 * (A[3 * i + j] + A[3 * j + i]);
+                    En += E[3 * i + j] * E[3 * i + j];
+                }
+            En = sqrt(En);
+            const double* v1 = o + 16;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) dA_last[3 * i + j] = v1[i] * v1[j] / En - o[26] * E[3 * i + j] / (En * En);
+        }
+    }
     HIP_TRY(launch_adj_seed(h->storage, h->nv, h->d, h->adj_coef, h->adj_v.rb, h->stream, objective),
             "seed launch");
     HIP_TRY(launch_adj_perm_out(h->nv, h->adj_perm, h->adj_v.rb, rbar, h->stream), "seed permute");

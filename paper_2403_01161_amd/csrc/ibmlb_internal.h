@@ -243,7 +243,8 @@ hipError_t launch_adj_ib_back(const Geom& g, int nv, const int4* fan, double sig
                               const double* Fbar, const AdjVerts& v, double* spart, hipStream_t s);
 hipError_t launch_adj_reduce(int nsteps, int nbl, const double* Apart, int nbv, const double* spart, double* dA,
                              double* dsigma, hipStream_t s);
-// which: 0 J = D, 1 J = lambda_max, 2 J = beta (E of the last step held fixed).
+// which: 0 J = D, 1 J = lambda_max, 2 J = beta (the mesh part; the direct
+// dependence on the last gradient row is added on the host).
 hipError_t launch_adj_seed(int storage, int nv, const DevPtrs& d, double* coef, double4* rb, hipStream_t s,
                            int which = 0);
 hipError_t launch_adj_perm_in(int nv, const int* perm, const double* user, double4* out, hipStream_t s);

@@ -104,7 +104,7 @@ def lib():
         L.ibm_lb_batch_destroy.argtypes = [vp]
         L.ibm_lb_batch_destroy.restype = None
         L.ibm_lb_objective_grad.argtypes = [vp, dp, vp]
-        L.ibm_lb_shape_objective_grad.argtypes = [vp, i32, dp, vp]
+        L.ibm_lb_shape_objective_grad.argtypes = [vp, i32, dp, vp, dp]
         L.ibm_lb_adjoint_segment.argtypes = [vp, vp, C.c_size_t, vp, i32, i32, vp, vp, vp, vp, vp, vp]
         L.ibm_lb_strerror.argtypes = [C.c_int]
         L.ibm_lb_strerror.restype = C.c_char_p
@@ -278,14 +278,17 @@ class Simulation:
         return ms.value, n.value
 
     # ---- adjoint
-    def objective_grad(self, objective="D"):
+    def objective_grad(self, objective="D", with_last_row=False):
         """J of the current mesh and dJ/dr as a float64 CUDA tensor [nv, 3] (caller vertex order);
-        J is D, "lambda_max" or "beta" (the last step's strain held fixed)."""
+        J is D, "lambda_max" or "beta" (with the strain of the last gradient row). With
+        with_last_row, also J's direct derivative by the last gradient row (numpy [9])."""
         rbar = torch.empty((self.nv, 3), dtype=torch.float64, device=self.device)
         v = C.c_double()
-        _check(lib().ibm_lb_shape_objective_grad(self._h, OBJECTIVES[objective], C.byref(v), rbar.data_ptr()),
+        dlast = np.zeros(9)
+        _check(lib().ibm_lb_shape_objective_grad(self._h, OBJECTIVES[objective], C.byref(v), rbar.data_ptr(),
+                                                 _dp(dlast)),
                "ibm_lb_shape_objective_grad")
-        return v.value, rbar
+        return (v.value, rbar, dlast) if with_last_row else (v.value, rbar)
 
     def adjoint_segment(self, ckpt, A, fbar_end, rbar_end, fbar_begin=None, rbar_begin=None, dA=None,
                         dsigma=None):
@@ -429,8 +432,8 @@ class DeformationFunction(torch.autograd.Function):
         for s0 in range(0, n, K):
             ckpts.append(sim.save())
             sim.step_table(A[s0:s0 + K])
-        D, rbar = sim.objective_grad(objective)
-        ctx.sim, ctx.ckpts, ctx.K, ctx.rbar, ctx.A = sim, ckpts, K, rbar, A
+        D, rbar, dlast = sim.objective_grad(objective, with_last_row=True)
+        ctx.sim, ctx.ckpts, ctx.K, ctx.rbar, ctx.A, ctx.dlast = sim, ckpts, K, rbar, A, dlast
         ctx.sigma_shape, ctx.sdev, ctx.vdev = sigma.shape, sigma.device, vertices.device
         return torch.tensor(D, dtype=torch.float64, device=sim.device)
 
@@ -449,12 +452,14 @@ class DeformationFunction(torch.autograd.Function):
             sim.adjoint_segment(ctx.ckpts[idx], A[s0:s1], fbar, rbar, fbuf, rnext, dA[s0:s1], dsig)
             fbar = fbuf
             rbar, rnext = rnext, rbar
+        # the objective's own dependence on the last gradient row (beta)
+        dA[-1] += torch.from_numpy(ctx.dlast).to(dA.device).reshape(dA[-1].shape) * gD
         return (dsig.reshape(ctx.sigma_shape).to(ctx.sdev), dA.to(ctx.adev), rbar.to(ctx.vdev), None, None, None)
 
 
 def deformation(sigma, A, vertices, K=50, objective="D", **spec):
     """Differentiable droplet shape objective J(r^T): the deformation D
-    (default), "lambda_max" or "beta" (the last step's strain held fixed);
+    (default), "lambda_max" or "beta" (with the strain of the last gradient row);
     spec holds the Simulation keywords other than sigma and vertices (L, tau,
     radius, triangles, ...)."""
     if not isinstance(sigma, torch.Tensor):
