@@ -46,7 +46,7 @@ class _Params(C.Structure):
                 ("reg_gamma", C.c_double), ("reg_tol", C.c_double),
                 ("reg_max_iter", C.c_int), ("reg_sign", C.c_int), ("init_rest", C.c_int),
                 ("A0", C.c_double * 9), ("wall_bc", C.c_int), ("collision", C.c_int),
-                ("mrt_s", C.c_double * 5)]
+                ("mrt_s", C.c_double * 5), ("chi", C.c_double)]
 
 
 def lib():
@@ -70,6 +70,10 @@ def lib():
         L.ibo_mrt_basis.argtypes = [dp, dp]
         L.ibo_mrt_basis.restype = None
         L.ibo_shape.argtypes = [i, dp, i, ip, dp, C.c_double, dp]
+        L.ibo_winding.restype = C.c_double
+        L.ibo_winding.argtypes = [i, dp, i, ip, dp]
+        L.ibo_indicator.argtypes = [ip, i, dp, i, ip, C.POINTER(C.c_ubyte)]
+        L.ibo_get_indicator.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte)]
         L.ibo_create.argtypes = [C.POINTER(_Params), C.POINTER(C.c_void_p)]
         L.ibo_destroy.argtypes = [C.c_void_p]
         L.ibo_destroy.restype = None
@@ -195,6 +199,29 @@ def shape(r, tris, A=None, radius=1.0):
     return _obs_dict(out)
 
 
+def winding(r, tris, p):
+    """Winding number of the closed mesh about the point p."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    q = np.ascontiguousarray(p, dtype=np.float64).reshape(3)
+    return float(lib().ibo_winding(len(r), _dp(r), len(t), _ip(t), _dp(q)))
+
+
+def _up(a):
+    return a.ctypes.data_as(C.POINTER(C.c_ubyte))
+
+
+def indicator(L, r, tris):
+    """Inside indicator of the closed mesh (absolute coordinates) on the
+    lattice L, as uint8 [Lz, Ly, Lx]."""
+    Lv = np.ascontiguousarray(L, dtype=np.int32)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    out = np.zeros(int(np.prod(Lv)), dtype=np.uint8)
+    lib().ibo_indicator(_ip(Lv), len(r), _dp(r), len(t), _ip(t), _up(out))
+    return out.reshape(int(Lv[2]), int(Lv[1]), int(Lv[0]))
+
+
 # ---------------------------------------------------------------- simulation
 class Oracle:
     """The coupled IB-LB timestep in plain FP64 loops."""
@@ -202,7 +229,7 @@ class Oracle:
     def __init__(self, L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None,
                  periodic=(0, 0, 0), rho0=1.0, reg_alpha=0.1, reg_gamma=0.51, reg_tol=0.01,
                  reg_max_iter=50, reg_sign=1, init_rest=False, A0=None, collision="bgk", mrt_s=None,
-                 walls="link"):
+                 walls="link", chi=1.0):
         p = _Params()
         self.L = tuple(int(v) for v in L)
         for a in range(3):
@@ -227,6 +254,7 @@ class Oracle:
         p.wall_bc = {"link": 0, "wet": 1}[walls]
         for k, v in enumerate(mrt_s if mrt_s is not None else [0.0] * 5):
             p.mrt_s[k] = float(v)
+        p.chi = float(chi)
         h = C.c_void_p()
         _check(lib().ibo_create(C.byref(p), C.byref(h)), "create")
         self._h = h
@@ -276,6 +304,14 @@ class Oracle:
 
     def last_iters(self):
         return int(lib().ibo_last_iters(self._h))
+
+    def indicator(self):
+        """Inside indicator of the current mesh, uint8 [Lz, Ly, Lx]: the nodes
+        that the next step relaxes with the inner relaxation time."""
+        out = np.zeros(self.N, dtype=np.uint8)
+        _check(lib().ibo_get_indicator(self._h, _up(out)), "indicator")
+        Lx, Ly, Lz = self.L
+        return out.reshape(Lz, Ly, Lx)
 
     def populations(self):
         f = np.zeros((self.N, 19))

@@ -37,10 +37,15 @@
  *    Smoothing runs after every step with an iteration cap.
  *  - S is (5/V) times the second moment of the enclosed volume about its
  *    centroid, so S = R^2 I for a sphere and the eigenvalues of an
- *    ellipsoid are the squared semi-axes (Sec. 2, "square root of
- *    lambda_max coincides with the major semi-axis").
+ *    ellipsoid are the squared semi-axes (Sec. 2 takes the root of the
+ *    largest eigenvalue as the major semi-axis).
  *  - Initial state: f_eq(rho0, A0 (x - x_c)) plus its Chapman-Enskog
- *    non-equilibrium part -3 tau w_i rho0 (c_i c_i - I/3):A0.
+ *    non-equilibrium part -3 tau w_i rho0 (c_i c_i - I/3):A0, with the outer
+ *    tau everywhere.
+ *  - Viscosity ratio chi (Sec. 2): one density, and nodes inside the mesh
+ *    (winding number above 1/2) relax with tau_in = 1/2 + chi (tau - 1/2),
+ *    both in the BGK rate and the Guo factor; the indicator of a step is
+ *    that of the mesh the step's forces come from.
  */
 #include "ibmlb_oracle.h"
 
@@ -533,6 +538,63 @@ int ibo_shape(int nv, const double* r, int nt, const int* tris, const double A[9
     return IBO_OK;
 }
 
+/* Viscosity ratio (Sec. 2: the droplet phase has viscosity chi mu). A node
+ * takes the inner relaxation time when it lies inside the closed surface.
+ * Inside is defined by the winding number: the solid angles that the
+ * triangles subtend at the point, summed with their orientation and divided
+ * by 4 pi, are 1 inside an outward-oriented closed surface and 0 outside.
+ * Each solid angle follows Van Oosterom and Strackee (1983):
+ * tan(Omega/2) = a.(b x c) / (|a||b||c| + (a.b)|c| + (a.c)|b| + (b.c)|a|),
+ * a, b, c the vertices relative to the point. */
+double ibo_winding(int nv, const double* r, int nt, const int* tris, const double p[3])
+{
+    (void)nv;
+    double sum = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        double a[3], b[3], c[3], bc[3];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = r[3 * tris[3 * t] + k] - p[k];
+            b[k] = r[3 * tris[3 * t + 1] + k] - p[k];
+            c[k] = r[3 * tris[3 * t + 2] + k] - p[k];
+        }
+        cross(b, c, bc);
+        double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        double lb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+        double lc = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        double num = a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2];
+        double den = la * lb * lc + (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) * lc +
+                     (a[0] * c[0] + a[1] * c[1] + a[2] * c[2]) * lb + (b[0] * c[0] + b[1] * c[1] + b[2] * c[2]) * la;
+        sum += 2.0 * atan2(num, den);
+    }
+    return sum / (4.0 * M_PI);
+}
+
+void ibo_indicator(const int L[3], int nv, const double* r, int nt, const int* tris, unsigned char* out)
+{
+    const long N = (long)L[0] * L[1] * L[2];
+    memset(out, 0, (size_t)N);
+    if (nv == 0 || nt == 0) return;
+    long lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        double mn = r[a], mx = r[a];
+        for (int k = 1; k < nv; ++k) {
+            if (r[3 * k + a] < mn) mn = r[3 * k + a];
+            if (r[3 * k + a] > mx) mx = r[3 * k + a];
+        }
+        lo[a] = (long)ceil(mn);
+        hi[a] = (long)floor(mx);
+        if (lo[a] < 0) lo[a] = 0;
+        if (hi[a] > L[a] - 1) hi[a] = L[a] - 1;
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (long z = lo[2]; z <= hi[2]; ++z)
+        for (long y = lo[1]; y <= hi[1]; ++y)
+            for (long x = lo[0]; x <= hi[0]; ++x) {
+                double p[3] = {(double)x, (double)y, (double)z};
+                out[x + L[0] * (y + (long)L[1] * z)] = ibo_winding(nv, r, nt, tris, p) > 0.5;
+            }
+}
+
 /* ------------------------------------------------------------------ */
 struct ibo_sim {
     int L[3], per[3];
@@ -556,6 +618,8 @@ struct ibo_sim {
     int wall_bc;            /* 0 link bounce-back, 1 wet-node velocity walls */
     int collision;          /* 0 BGK, 1 MRT */
     double mrt_M[19 * 19], mrt_n2[19], mrt_s[19];  /* basis, squared norms, rate per moment */
+    double tau_in;          /* relaxation time inside the droplet (tau when chi = 1) */
+    unsigned char* ind;     /* [N] inside indicator of the step's mesh, when tau_in != tau */
 };
 
 long ibo_nodes(const ibo_sim* s) { return s->N; }
@@ -566,6 +630,7 @@ void ibo_destroy(ibo_sim* s)
     free(s->f); free(s->fpost); free(s->F); free(s->rho); free(s->u);
     free(s->r); free(s->phi); free(s->U); free(s->tris);
     free(s->sched);
+    free(s->ind);
     free_ring(&s->ring);
     free(s);
 }
@@ -581,6 +646,7 @@ int ibo_create(const ibo_params* p, ibo_sim** out)
     if (p->wall_bc < 0 || p->wall_bc > 1) return IBO_EINVAL;
     for (int k = 0; k < 5; ++k)
         if (!(p->mrt_s[k] >= 0.0 && p->mrt_s[k] < 2.0)) return IBO_EINVAL;
+    if (!(p->chi >= 0.0) || (p->chi != 0.0 && p->chi != 1.0 && p->collision != 0)) return IBO_EINVAL;
     if (p->nv < 0 || p->nt < 0 || (p->nv > 0 && (!p->verts || !p->tris || p->nt == 0)))
         return IBO_EINVAL;
     for (int t = 0; t < 3 * p->nt; ++t)
@@ -598,6 +664,10 @@ int ibo_create(const ibo_params* p, ibo_sim** out)
     s->reg_alpha = p->reg_alpha; s->reg_gamma = p->reg_gamma; s->reg_tol = p->reg_tol;
     s->reg_max_iter = p->reg_max_iter; s->reg_sign = p->reg_sign >= 0 ? 1 : -1;
     s->wall_bc = p->wall_bc;
+    {
+        const double chi = p->chi == 0.0 ? 1.0 : p->chi;
+        s->tau_in = chi == 1.0 ? p->tau : 0.5 + chi * (p->tau - 0.5);
+    }
     s->collision = p->collision;
     if (s->collision == 1) {
         /* rate per moment: conserved rho and j at 1/tau (their non-equilibrium
@@ -622,7 +692,9 @@ int ibo_create(const ibo_params* p, ibo_sim** out)
     s->phi = malloc(sizeof(double) * nvb);
     s->U = malloc(sizeof(double) * nvb);
     s->tris = malloc(sizeof(int) * 3 * (size_t)(s->nt > 0 ? s->nt : 1));
-    if (!s->f || !s->fpost || !s->F || !s->rho || !s->u || !s->r || !s->phi || !s->U || !s->tris) {
+    if (s->tau_in != s->tau) s->ind = calloc((size_t)s->N, 1);
+    if (!s->f || !s->fpost || !s->F || !s->rho || !s->u || !s->r || !s->phi || !s->U || !s->tris ||
+        (s->tau_in != s->tau && !s->ind)) {
         ibo_destroy(s);
         return IBO_ENOMEM;
     }
@@ -722,9 +794,11 @@ static void collide(ibo_sim* s)
                     }
                     continue;
                 }
-                ibo_guo_source(s->tau, s->u + 3 * n, s->F + 3 * n, S);
+                /* the node's relaxation time: tau_in inside the droplet */
+                const double tn = s->ind && s->ind[n] ? s->tau_in : s->tau;
+                ibo_guo_source(tn, s->u + 3 * n, s->F + 3 * n, S);
                 for (int i = 0; i < 19; ++i)
-                    s->fpost[19 * n + i] = s->f[19 * n + i] - (s->f[19 * n + i] - feq[i]) / s->tau + S[i];
+                    s->fpost[19 * n + i] = s->f[19 * n + i] - (s->f[19 * n + i] - feq[i]) / tn + S[i];
             }
 }
 
@@ -907,6 +981,7 @@ static int one_step(ibo_sim* s, const double A[9])
 {
     int rc = force_field(s);                                   /* phi, F */
     if (rc) return rc;
+    if (s->ind) ibo_indicator(s->L, s->nv, s->r, s->nt, s->tris, s->ind); /* tau per node */
     moments(s);                                                /* rho, u */
     if (s->nv) {
         rc = ibo_interp(s->L, s->per, s->nv, s->r, s->u, s->U); /* U */
@@ -1004,6 +1079,13 @@ int ibo_fields(ibo_sim* s, double* rho, double* u)
     moments(s);
     memcpy(rho, s->rho, sizeof(double) * (size_t)s->N);
     memcpy(u, s->u, sizeof(double) * 3 * (size_t)s->N);
+    return IBO_OK;
+}
+
+int ibo_get_indicator(const ibo_sim* s, unsigned char* out)
+{
+    if (!s || !out) return IBO_EINVAL;
+    ibo_indicator(s->L, s->nv, s->r, s->nt, s->tris, out);
     return IBO_OK;
 }
 

@@ -72,6 +72,9 @@ typedef struct ibo_params {
     double mrt_s[5];   /* MRT rates of the energy, energy-square, heat-flux, third-order
                           stress and third-order antisymmetric moments; 0 selects 1.19,
                           1.4, 1.2, 1.4, 1.98; the shear rate is 1/tau */
+    double chi;        /* viscosity ratio inside/outside the droplet (Sec. 2); 0 or 1: one
+                          fluid. Nodes inside the mesh relax with tau_in = 1/2 + chi (tau - 1/2)
+                          (same density, Eq. tau_to_nu); BGK only */
 } ibo_params;
 
 typedef struct ibo_sim ibo_sim;
@@ -94,6 +97,13 @@ int ibo_hc(int nv, int nt, const int* tris, double alpha, double gamma, double t
 void ibo_eig3(const double S[9], double evals[3], double evecs[9]);
 int ibo_shape(int nv, const double* r, int nt, const int* tris, const double A[9],
               double radius, double out[IBO_OBS_N]);
+/* Inside/outside indicator of the closed mesh on the lattice (x fastest):
+ * out[n] = 1 where the winding number of the surface about node n exceeds
+ * 1/2, else 0. Nodes outside the mesh's bounding box are outside. */
+void ibo_indicator(const int L[3], int nv, const double* r, int nt, const int* tris, unsigned char* out);
+/* Winding number of the closed mesh about the point p (solid angles summed
+ * over the triangles, divided by 4 pi). */
+double ibo_winding(int nv, const double* r, int nt, const int* tris, const double p[3]);
 
 /* ---- the coupled simulation ---- */
 int ibo_create(const ibo_params* p, ibo_sim** out);
@@ -113,6 +123,8 @@ int ibo_freeze_iters(ibo_sim* s, const int* counts, int n);
 /* Smoothing iterations of the last step. */
 int ibo_last_iters(const ibo_sim* s);
 int ibo_get_populations(const ibo_sim* s, double* f); /* [N][19] */
+/* Indicator of the current mesh, the one the next step's collision uses ([N]). */
+int ibo_get_indicator(const ibo_sim* s, unsigned char* out);
 int ibo_set_populations(ibo_sim* s, const double* f); /* [N][19] */
 long ibo_nodes(const ibo_sim* s);
 
