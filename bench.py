@@ -129,7 +129,9 @@ def describe_variant(v):
     return d
 
 
-def lattice_kernel_name(v):
+def lattice_kernel_name(v, chi=1.0):
+    if chi != 1.0:
+        return "k_lattice_chi"
     if v & 64:
         return "k_lattice_aa"
     return "k_lattice_rows" if v & 16 else "k_lattice"
@@ -418,6 +420,10 @@ def main():
     ap.add_argument("--variant", type=int, default=None,
                     help="run this step variant instead of the autotuner's choice (the single-droplet "
                          "128^3 leg and --counters)")
+    ap.add_argument("--chi", type=float, default=1.0,
+                    help="viscosity ratio of the droplet for the single-droplet leg (1: one fluid); "
+                         "other values add the inside-indicator build per step and skip the CPU "
+                         "baseline (the oracle's winding-number indicator is far too slow at 128^3)")
     ap.add_argument("--counters", nargs="?", const="128", choices=["128", "256"], default=None,
                     help="short fixed sequence for hardware-counter runs: 3 device copies of "
                          "256 MiB (calibration) and 20 steps of the single-droplet workload")
@@ -443,7 +449,7 @@ def main():
     K, W = args.steps, args.warmup
     table = ou_gradient_table(W + 2 * K + 1, w["corr"], w["G"], seed=w["seed"])
     sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"],
-                           storage=w["storage"], A0=table[0], device=dev)
+                           storage=w["storage"], A0=table[0], device=dev, chi=args.chi)
     dtab = torch.from_numpy(table).to(dev)
     nodes = int(np.prod(w["L"]))
     nv = len(w["V"])
@@ -476,7 +482,8 @@ def main():
     alg_bytes = 2 * 19 * sbytes * nodes
     avg_s = lat_ms / 1e3 / max(launches, 1)
     achieved = alg_bytes / avg_s / 1e9
-    traffic = counter_traffic(args.storage, variant=variant)
+    # the committed counters are those of the one-fluid lattice kernel
+    traffic = counter_traffic(args.storage, variant=variant) if args.chi == 1.0 else None
 
     value = nodes * K / dt / 1e6
     line = {
@@ -494,12 +501,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single droplet, 128^3 moving-wall box, tau 0.8, R 16, "
                                "10242-vertex icosphere, OU traceless A(t) rms Ca 0.1, "
-                               f"{args.storage} populations",
-                   "box": list(w["L"]), "vertices": nv, "storage": args.storage},
+                               f"{args.storage} populations"
+                               + (f", viscosity ratio {args.chi:g}" if args.chi != 1.0 else ""),
+                   "box": list(w["L"]), "vertices": nv, "storage": args.storage, "chi": args.chi},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": lattice_kernel_name(variant),
+                     "kernel": lattice_kernel_name(variant, args.chi),
                      "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
                      "variant": describe_variant(variant)},
@@ -519,7 +527,7 @@ def main():
         line["ensemble"] = ensemble_bench(args.ensemble_steps)
     if not args.no_adjoint:
         line["adjoint"] = adjoint_bench(dev)
-    if not args.no_cpu:
+    if not args.no_cpu and args.chi == 1.0:
         line["cpu_baseline"] = cpu_baseline(w, table, args.cpu_steps)
     else:
         line["cpu_baseline"] = None

@@ -127,6 +127,15 @@ typedef struct ibm_lb_config {
                               (Sec. 3.1: Zou-He faces with the transverse correction, the
                               printed edge and corner rules with buried links), two population
                               copies, single droplets, without the adjoint */
+    double chi;            /* viscosity ratio of droplet to carrier (Sec. 2), in [0, 1e6]; 0 or 1:
+                              one fluid. Otherwise the nodes inside the mesh (parity of the mesh
+                              crossings along x, i.e. the winding number modulo 2) relax with
+                              tau_in = 1/2 + chi (tau - 1/2) (Eq. tau_to_nu at one density) in
+                              the BGK rate and the Guo factor; the inside is rebuilt from the mesh
+                              after every step. BGK with two population copies, linear lattice
+                              variants, single droplets, without the adjoint; the mesh stays
+                              inside the box (no periodic images). The initial non-equilibrium
+                              part uses tau everywhere */
 } ibm_lb_config;
 
 typedef struct ibm_lb_obs {
@@ -179,6 +188,12 @@ int ibm_lb_observables(ibm_lb* h, ibm_lb_obs* out);
  * [3][N]). read_field allocates a temporary device buffer. */
 int ibm_lb_read_vertices(ibm_lb* h, double* out);
 int ibm_lb_read_field(ibm_lb* h, int32_t which, double* out);
+
+/* Inside indicator that the next step's collision uses (Sec. 2, viscosity
+ * ratio chi), host uint8 [N] (x fastest): 1 for a node inside the current
+ * mesh, else 0. Synchronising. EINVAL for a handle without a viscosity
+ * ratio. */
+int ibm_lb_read_indicator(ibm_lb* h, uint8_t* out);
 
 /* Checkpoints: ibm_lb_state_bytes is the size of the state (populations,
  * vertices, step counter). save/load copy it to/from dst/src, which may be

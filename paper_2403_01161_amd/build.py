@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libibmlb.so")
-SOURCES = ["kernels.hip", "ib_patch.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["kernels.hip", "ib_patch.hip", "indicator.hip", "adjoint.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -39,7 +39,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 // Byte offsets of every device array inside one workspace.
 struct Layout {
     size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, tris, fan, lfan, hstart, hids, obs_part, mass_part,
-        obs_out, Abuf, red, total;
+        obs_out, Abuf, red, ind, ind_lines, total;
 };
 
 // Per vertex: valence m and the one-ring neighbours n_0 .. n_{m-1} in
@@ -50,7 +50,10 @@ struct MeshCSR {
     std::vector<int> fan;
 };
 
-Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t nhalo, int copies) {
+// ind_b, lines: bytes of the indicator and x-rows of the lattice when the
+// droplet has a viscosity ratio, else 0.
+Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t nhalo, int copies, size_t ind_b = 0,
+                   size_t lines = 0) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -82,9 +85,14 @@ Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t 
     L.obs_out = take(sizeof(double) * OBS_OUT_N);
     L.Abuf = take(sizeof(double) * 9 * (ACAP + 1));
     L.red = take(sizeof(unsigned long long) * 2);
+    L.ind = take(ind_b);
+    L.ind_lines = take(sizeof(int) * 2 * lines);
     L.total = off;
     return L;
 }
+
+// A viscosity ratio other than 1 (0 selects 1) with a droplet to define the inside.
+bool chi_active(const ibm_lb_config* c) { return c->chi != 0.0 && c->chi != 1.0 && c->n_vertices > 0; }
 
 // Validate the configuration and build the mesh adjacency.
 int validate(const ibm_lb_config* c) {
@@ -120,6 +128,9 @@ int validate(const ibm_lb_config* c) {
     if (c->walls != IBM_LB_WALLS_LINK && c->walls != IBM_LB_WALLS_WET) return fail(IBM_LB_EINVAL, "unknown walls");
     if (c->walls == IBM_LB_WALLS_WET && c->populations == 1)
         return fail(IBM_LB_EINVAL, "wet-node walls run with two population copies");
+    if (!(c->chi >= 0.0 && c->chi <= 1e6)) return fail(IBM_LB_EINVAL, "chi must lie in [0, 1e6]");
+    if (chi_active(c) && (c->collision != IBM_LB_BGK || c->populations == 1))
+        return fail(IBM_LB_EINVAL, "a viscosity ratio runs BGK with two population copies");
     const int nv = c->n_vertices, nt = c->n_triangles;
     if (nv < 0 || nt < 0) return fail(IBM_LB_EINVAL, "negative mesh size");
     if (nv == 0 && nt == 0) return IBM_LB_OK;
@@ -357,6 +368,8 @@ struct ibm_lb {
     bool wet = false;            // wet-node velocity walls after every lattice step
     bool mrt = false;            // MRT collision with the rates below
     MrtRates mrt_rates{};
+    bool chi = false;            // viscosity ratio: inner rates on the nodes inside the mesh
+    ChiRates chi_rates{};
     double* stage = nullptr;     // pinned host staging for gradient rows
     hipEvent_t stage_done = nullptr;
     bool timing = false;
@@ -438,9 +451,14 @@ int take_event(ibm_lb* h, int* idx) {
 
 // Forces and spreading of the current mesh into F (marks at the current
 // epoch), needed before the first lattice kernel after set-up or a load.
+// With a viscosity ratio, also the indicator of the current mesh.
 int ensure_force(ibm_lb* h) {
     if (h->f_ready || h->nv == 0) return IBM_LB_OK;
     HIP_TRY(launch_ib_pre(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream), "ib_pre launch");
+    if (h->chi) {
+        HIP_TRY(launch_indicator_clear(h->g, h->d, h->stream), "indicator clear");
+        HIP_TRY(launch_indicator(h->storage, h->g, h->d, h->nt, h->stream, nullptr), "indicator launch");
+    }
     h->f_ready = true;
     return IBM_LB_OK;
 }
@@ -487,14 +505,16 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
             done = ib ? h->ev[kd] : nullptr;
         }
         HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->lattice_variant, h->aa_parity,
-                               h->stream, nullptr, e1, h->mrt ? &h->mrt_rates : nullptr),
+                               h->stream, nullptr, e1, h->mrt ? &h->mrt_rates : nullptr,
+                               h->chi ? &h->chi_rates : nullptr),
                 "lattice launch");
         if (h->wet)
             HIP_TRY(launch_wet_walls(h->storage, h->g, h->lp, h->d, h->cur ^ 1, Arow, h->stream), "walls launch");
         if (ib)
-            HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream, done,
-                                   (h->lattice_variant & VAR_HC_SPLIT) != 0),
+            HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream,
+                                   h->chi ? nullptr : done, (h->lattice_variant & VAR_HC_SPLIT) != 0),
                     "ib_step launch");
+        if (h->chi) HIP_TRY(launch_indicator(h->storage, h->g, h->d, h->nt, h->stream, done), "indicator launch");
         if (h->timing) {
             h->iv.push_back({k0, k1});
             h->ev_pending = ib ? kd : k1;
@@ -549,8 +569,10 @@ int ibm_lb_workspace_size(const ibm_lb_config* cfg, size_t* bytes) {
     if (rc) return rc;
     if (!bytes) return fail(IBM_LB_EINVAL, "bytes is NULL");
     Geom g = make_geom(cfg);
+    const bool chi = chi_active(cfg);
     *bytes = make_layout(cfg->storage, g.N, g.TX * g.TY * g.TZ, cfg->n_vertices, cfg->n_triangles,
-                         m.halos.hids.size(), cfg->populations == 1 ? 1 : 2)
+                         m.halos.hids.size(), cfg->populations == 1 ? 1 : 2, chi ? ind_bytes(g) : 0,
+                         chi ? (size_t)g.Ly * g.Lz : 0)
                  .total;
     return IBM_LB_OK;
 }
@@ -594,6 +616,12 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     h->single = cfg->populations == 1;
     h->mrt = cfg->collision == IBM_LB_MRT;
     h->wet = cfg->walls == IBM_LB_WALLS_WET;
+    h->chi = chi_active(cfg);
+    if (h->chi) {
+        const double tau_in = 0.5 + cfg->chi * (cfg->tau - 0.5);  // nu_in = chi nu
+        h->chi_rates.omega_in = 1.0 / tau_in;
+        h->chi_rates.kguo_in = 1.0 - 1.0 / (2.0 * tau_in);
+    }
     if (h->mrt) {
         // per moment of the basis: conserved density and momentum and the five
         // shear moments at 1/tau, the others from the configuration
@@ -606,7 +634,8 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
         for (int k = 0; k < 19; ++k) h->mrt_rates.s[k] = rate[k];
     }
     if (h->single) h->lattice_variant = VAR_AA | VAR_HC_SPLIT;
-    h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt, mesh.halos.hids.size(), h->single ? 1 : 2);
+    h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt, mesh.halos.hids.size(), h->single ? 1 : 2,
+                         h->chi ? ind_bytes(h->g) : 0, h->chi ? (size_t)h->g.Ly * h->g.Lz : 0);
     if (cfg->workspace) {
         if (cfg->workspace_bytes < h->lay.total)
             return bail(fail(IBM_LB_ENOMEM, "workspace smaller than ibm_lb_workspace_size"));
@@ -652,6 +681,8 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     d.obs_out = (double*)(b + L.obs_out);
     d.Abuf = (double*)(b + L.Abuf);
     d.red = (unsigned long long*)(b + L.red);
+    d.ind = h->chi ? (unsigned char*)(b + L.ind) : nullptr;
+    d.ind_lines = h->chi ? (int*)(b + L.ind_lines) : nullptr;
     h->perm = mesh.perm;
     if (h->nv > 0) {
         e = patch_setup(h->storage);
@@ -822,6 +853,19 @@ int ibm_lb_read_field(ibm_lb* h, int32_t which, double* out) {
     return check_flags(h);
 }
 
+int ibm_lb_read_indicator(ibm_lb* h, uint8_t* out) {
+    if (!h || !out) return fail(IBM_LB_EINVAL, "bad read_indicator arguments");
+    if (!h->chi) return fail(IBM_LB_EINVAL, "the handle has no viscosity ratio (chi = 1 or no droplet)");
+    if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
+    int rc = set_device(h);
+    if (rc) return rc;
+    if ((rc = ensure_force(h))) return rc;
+    // bit 0: inside; the toggles (bit 1) are consumed within the build
+    HIP_TRY(hipMemcpyAsync(out, h->d.ind, (size_t)h->g.N, hipMemcpyDeviceToHost, h->stream), "indicator copy");
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    return check_flags(h);
+}
+
 namespace {
 struct StateHeader {
     int64_t magic, storage, N, nv, step, pad[3];
@@ -953,8 +997,8 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     int nc = 0;
     if (!h->single)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
-            if (!h->mrt || !(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT;
-    if (!h->mrt && !h->wet)
+            if ((!h->mrt && !h->chi) || !(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT;
+    if (!h->mrt && !h->wet && !h->chi)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
             if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
     tune(cand, nc, best_of);
@@ -981,6 +1025,8 @@ int ibm_lb_set_variant(ibm_lb* h, int32_t variant) {
     if (h->mrt && (variant & (VAR_ROWS | VAR_AA)))
         return fail(IBM_LB_EINVAL, "MRT runs the linear layout with two copies");
     if (h->wet && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "wet-node walls run with two copies");
+    if (h->chi && (variant & (VAR_ROWS | VAR_AA)))
+        return fail(IBM_LB_EINVAL, "a viscosity ratio runs the linear layout with two copies");
     h->lattice_variant = variant;
     return IBM_LB_OK;
 }
@@ -1081,7 +1127,8 @@ int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar) {
 int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, double* rbar, double* dA_last) {
     if (!h || !value || !rbar) return fail(IBM_LB_EINVAL, "bad objective_grad arguments");
     if (objective < IBM_LB_OBJ_D || objective > IBM_LB_OBJ_BETA) return fail(IBM_LB_EINVAL, "unknown objective");
-    if (h->mrt || h->wet) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step with link walls");
+    if (h->mrt || h->wet || h->chi)
+        return fail(IBM_LB_EINVAL, "the adjoint covers the one-fluid BGK step with link walls");
     if (h->nv == 0) return fail(IBM_LB_EINVAL, "the objective needs a mesh");
     if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
     int rc = set_device(h);
@@ -1135,7 +1182,8 @@ int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const
         return fail(IBM_LB_EINVAL, "bad adjoint_segment arguments");
     if (h->nv > 0 && (!rbar_end || !rbar_begin))
         return fail(IBM_LB_EINVAL, "rbar_end and rbar_begin are required with a mesh");
-    if (h->mrt || h->wet) return fail(IBM_LB_EINVAL, "the adjoint covers the BGK step with link walls");
+    if (h->mrt || h->wet || h->chi)
+        return fail(IBM_LB_EINVAL, "the adjoint covers the one-fluid BGK step with link walls");
     int rc = set_device(h);
     if (rc) return rc;
     rc = ibm_lb_load(h, ckpt, ckpt_bytes);
@@ -1268,6 +1316,7 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
         if (cfgs[i].populations == 1) return fail(IBM_LB_EINVAL, "ensemble members keep two population copies");
         if (cfgs[i].collision != IBM_LB_BGK) return fail(IBM_LB_EINVAL, "ensemble members run BGK");
         if (cfgs[i].walls != IBM_LB_WALLS_LINK) return fail(IBM_LB_EINVAL, "ensemble members run link walls");
+        if (chi_active(&cfgs[i])) return fail(IBM_LB_EINVAL, "ensemble members run one fluid");
     }
     ibm_lb_batch* b = new (std::nothrow) ibm_lb_batch();
     if (!b) return fail(IBM_LB_ENOMEM, "host allocation");

@@ -88,6 +88,18 @@ struct DevPtrs {
     double* obs_out;         // [48] final observables
     double* Abuf;            // [ACAP][9] gradient rows
     unsigned long long* red; // [2] grid-wide max reduction slots
+    unsigned char* ind;      // [N rounded up to 4] inside indicator (viscosity ratio only)
+    int* ind_lines;          // [2][Ly Lz] node range of each x-row's crossings (viscosity ratio only)
+};
+
+// Bytes of the indicator array (whole 32-bit words, for the atomic toggles).
+inline size_t ind_bytes(const Geom& g) { return ((size_t)g.N + 3) / 4 * 4; }
+
+// Relaxation inside the droplet for a viscosity ratio chi != 1:
+// tau_in = 1/2 + chi (tau - 1/2).
+struct ChiRates {
+    double omega_in;         // 1/tau_in
+    double kguo_in;          // 1 - 1/(2 tau_in)
 };
 
 // One ensemble member as the batched lattice kernel sees it. A points at the
@@ -145,9 +157,17 @@ int lattice_variant_ok(int variant, const Geom& g);
 // parity: for an in-place variant, 0 for the even step, 1 for the odd one.
 // mrt (may be null): MRT collision with these rates instead of BGK (linear
 // layout with two copies only).
+// chi (may be null): nodes whose indicator byte d.ind is set relax with
+// these rates; the byte is cleared (BGK, linear layout with two copies only).
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
-                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const MrtRates* mrt = nullptr);
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const MrtRates* mrt = nullptr,
+                          const ChiRates* chi = nullptr);
+// Indicator of the committed mesh d.r into d.ind (which must hold zeros and
+// empty row ranges); done (may be null) is stamped at completion.
+hipError_t launch_indicator(int storage, const Geom& g, const DevPtrs& d, int nt, hipStream_t s, hipEvent_t done);
+// Zero the indicator and empty every row range (not for graph capture).
+hipError_t launch_indicator_clear(const Geom& g, const DevPtrs& d, hipStream_t s);
 // After an even in-place step: f[cur] back to natural order, in place.
 hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cur, hipStream_t s);
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);

@@ -171,13 +171,17 @@ __device__ __forceinline__ long long pull_source(const Geom& g, long long n, int
 // MRT: the multiple-relaxation-time collision with the rates *mr instead of
 // BGK: f* = f - M^-1 [S M (f - f_eq) - (I - S/2) M G], G the Guo term without
 // its (1 - 1/(2 tau)) factor (with every rate 1/tau, the BGK step).
-template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, int AA, bool MRT = false, class PIn,
-          class POut, class PR, class PM, class PC, class PA>
+// CHI: a node whose indicator byte ind[n] is set (inside the droplet) relaxes
+// with the rates *ch instead of lp's; the byte is cleared for the next
+// step's indicator.
+template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, int AA, bool MRT = false, bool CHI = false,
+          class PIn, class POut, class PR, class PM, class PC, class PA>
 __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp, PIn fin, POut fout, PR F,
                                              PR U, PM mark, PC ctl, PA Arow,
                                              const long long n, const int x, const int y, const int z,
                                              typename C::store_t* stage, int t, int T,
-                                             const MrtRates* mr = nullptr) {
+                                             const MrtRates* mr = nullptr, unsigned char* ind = nullptr,
+                                             const ChiRates* ch = nullptr) {
     using R = typename C::real;
     using S = typename C::store_t;
     const long long N = g.N;
@@ -230,7 +234,15 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
     }
     if (!(rho > R(0)) || !isfinite(ux + uy + uz)) atomicOr((int*)&ctl->flags, DFLAG_NONFINITE);
 
-    const R omega = R(lp.omega), kg = R(lp.kguo), rho0 = R(lp.rho0);
+    R omega = R(lp.omega), kg = R(lp.kguo);
+    const R rho0 = R(lp.rho0);
+    if constexpr (CHI) {
+        if (ind[n]) {
+            omega = R(ch->omega_in);
+            kg = R(ch->kguo_in);
+            ind[n] = 0;
+        }
+    }
     const R usq = ux * ux + uy * uy + uz * uz;
     const R uF = ux * Fx + uy * Fy + uz * Fz;
 
@@ -384,6 +396,26 @@ __global__ __launch_bounds__(BS) void k_lattice_mrt(Geom g, LatticeParams lp,
     node_xyz(g, n, x, y, z);
     lattice_node<C, IB, NTL, false, false, false, 0, true>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z,
                                                         nullptr, 0, 0, &mr);
+}
+
+// Viscosity ratio: BGK with the inner rates on the nodes the indicator marks,
+// linear layout with two copies.
+template <class C, bool IB, bool NTL, int BS>
+__global__ __launch_bounds__(BS) void k_lattice_chi(Geom g, LatticeParams lp,
+                                                     const typename C::store_t* __restrict__ fin,
+                                                     typename C::store_t* __restrict__ fout,
+                                                     typename C::real* __restrict__ F,
+                                                     typename C::real* __restrict__ U,
+                                                     const int* __restrict__ mark, Ctl* ctl,
+                                                     const double* __restrict__ Arow, int xcd,
+                                                     unsigned char* __restrict__ ind, ChiRates ch) {
+    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    const long long n = (long long)b * BS + threadIdx.x;
+    if (n >= g.N) return;
+    int x, y, z;
+    node_xyz(g, n, x, y, z);
+    lattice_node<C, IB, NTL, false, false, false, 0, false, true>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y,
+                                                               z, nullptr, 0, 0, nullptr, ind, &ch);
 }
 
 // In-place (single-copy) form, linear layout: ODD selects the step parity.
@@ -1054,6 +1086,28 @@ static void launch_mrt_v(int variant, const Geom& g, const LatticeParams& lp, co
 }
 
 template <class C, bool IB, bool NTL, int BS>
+static void chi_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
+                       int xcd, const ChiRates& ch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    using R = typename C::real;
+    using S = typename C::store_t;
+    hipExtLaunchKernelGGL((k_lattice_chi<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1, 0, g,
+                          lp, (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl,
+                          A_row, xcd, d.ind, ch);
+}
+
+template <class C, bool IB, bool NTL>
+static void launch_chi_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
+                         const double* A_row, const ChiRates& ch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int xcd = (variant & VAR_X) ? 1 : 0;
+    switch ((variant >> 1) & 3) {
+        case 0: chi_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, ch, s, e0, e1); break;
+        case 1: chi_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, ch, s, e0, e1); break;
+        case 2: chi_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, ch, s, e0, e1); break;
+        default: chi_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, ch, s, e0, e1); break;
+    }
+}
+
+template <class C, bool IB, bool NTL, int BS>
 static void aa_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row, int xcd,
                       int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     using R = typename C::real;
@@ -1131,8 +1185,18 @@ static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp
 
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
-                          hipEvent_t e0, hipEvent_t e1, const MrtRates* mrt) {
+                          hipEvent_t e0, hipEvent_t e1, const MrtRates* mrt, const ChiRates* chi) {
     if (!lattice_variant_ok(variant, g)) return hipErrorInvalidValue;
+    if (mrt && chi) return hipErrorInvalidValue;
+    if (chi) {
+        // the indicator exists only with a droplet
+        if ((variant & (VAR_ROWS | VAR_AA)) || !ib || !d.ind) return hipErrorInvalidValue;
+        DISPATCH_STORAGE(storage, C, {
+            if (variant & 1) launch_chi_v<C, true, true>(variant, g, lp, d, cur, A_row, *chi, s, e0, e1);
+            else launch_chi_v<C, true, false>(variant, g, lp, d, cur, A_row, *chi, s, e0, e1);
+        });
+        return hipGetLastError();
+    }
     if (mrt) {
         if (variant & (VAR_ROWS | VAR_AA)) return hipErrorInvalidValue;
         DISPATCH_STORAGE(storage, C, {

@@ -46,7 +46,7 @@ class Config(C.Structure):
                 ("init", C.c_int32), ("A0", C.c_double * 9), ("f16_scale", C.c_double),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("populations", C.c_int32), ("collision", C.c_int32), ("mrt_s", C.c_double * 5),
-                ("walls", C.c_int32)]
+                ("walls", C.c_int32), ("chi", C.c_double)]
 
 
 class Obs(C.Structure):
@@ -59,7 +59,7 @@ class Obs(C.Structure):
 
 
 EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_table",
-           "ibm_lb_observables", "ibm_lb_read_vertices", "ibm_lb_read_field",
+           "ibm_lb_observables", "ibm_lb_read_vertices", "ibm_lb_read_field", "ibm_lb_read_indicator",
            "ibm_lb_state_bytes", "ibm_lb_save", "ibm_lb_load", "ibm_lb_autotune", "ibm_lb_set_variant",
            "ibm_lb_timing_enable",
            "ibm_lb_timing_read", "ibm_lb_destroy", "ibm_lb_strerror", "ibm_lb_last_error",
@@ -84,6 +84,7 @@ def lib():
         L.ibm_lb_observables.argtypes = [vp, C.POINTER(Obs)]
         L.ibm_lb_read_vertices.argtypes = [vp, dp]
         L.ibm_lb_read_field.argtypes = [vp, i32, dp]
+        L.ibm_lb_read_indicator.argtypes = [vp, C.POINTER(C.c_uint8)]
         L.ibm_lb_state_bytes.argtypes = [vp]
         L.ibm_lb_state_bytes.restype = C.c_size_t
         L.ibm_lb_save.argtypes = [vp, vp, C.c_size_t]
@@ -125,7 +126,7 @@ def _dp(a):
 def make_config(L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None, periodic=(0, 0, 0),
                 storage="f32", init="linear", A0=None, rho0=1.0, reg_alpha=0.1, reg_gamma=0.51,
                 reg_tol=0.01, reg_max_iter=50, reg_sign=1, f16_scale=0.0, populations=2, collision="bgk",
-                mrt_s=None, walls="link"):
+                mrt_s=None, walls="link", chi=1.0):
     """Fill an ibm_lb_config; returns (config, keep-alive arrays)."""
     cfg = Config()
     for a in range(3):
@@ -154,6 +155,7 @@ def make_config(L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None, pe
     for k, v in enumerate(mrt_s if mrt_s is not None else [0.0] * 5):
         cfg.mrt_s[k] = float(v)
     cfg.walls = {"link": 0, "wet": 1}[walls] if isinstance(walls, str) else int(walls)
+    cfg.chi = float(chi)
     return cfg, (V, T)
 
 
@@ -244,6 +246,14 @@ class Simulation:
         _check(lib().ibm_lb_read_field(self._h, FIELD_RHO, _dp(rho)), "ibm_lb_read_field")
         _check(lib().ibm_lb_read_field(self._h, FIELD_U, _dp(u)), "ibm_lb_read_field")
         return rho.reshape(Lz, Ly, Lx), u.reshape(3, Lz, Ly, Lx)
+
+    def indicator(self):
+        """Inside indicator of the current mesh (viscosity ratio only), uint8 [Lz, Ly, Lx]."""
+        Lx, Ly, Lz = self.L
+        out = np.zeros(self.N, dtype=np.uint8)
+        _check(lib().ibm_lb_read_indicator(self._h, out.ctypes.data_as(C.POINTER(C.c_uint8))),
+               "ibm_lb_read_indicator")
+        return out.reshape(Lz, Ly, Lx)
 
     def state_bytes(self):
         return lib().ibm_lb_state_bytes(self._h)

@@ -1,0 +1,192 @@
+"""GPU viscosity ratio chi (Sec. 2; inner relaxation time from Eq.
+tau_to_nu) against the FP64 oracle:
+
+* the inside indicator built by crossing parity along x-rows equals the
+  oracle's winding-number indicator node for node, on the same vertex
+  positions: a star-shaped non-convex mesh off the lattice's symmetry
+  planes, and an icosphere of integer radius centred on a node, whose
+  vertices sit on lattice rows (rows through vertices, and rows that only
+  graze the surface at a vertex, must count right);
+* a droplet with chi = 4 (FP64 storage) and chi = 1/4 (FP32) matches the
+  oracle's positions, velocities and density after 30 steps;
+* the physics: in simple shear at small Ca the deformation rises on the
+  time scale of the linear theory (Eq. eq:LT), tau_sigma / k(chi), so the
+  rise with chi = 4 is k(1)/k(4) = 2.3 times slower than with chi = 1;
+* the limits: BGK, two copies, linear variants, single droplets, no adjoint.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_01161_amd import protocol as P
+from paper_2403_01161_amd.inputs import box_center, icosphere
+
+from .test_oracle_viscosity_ratio import _offset_center, _star_mesh
+
+pytestmark = pytest.mark.gpu
+
+ROWS, AA = 16, 64
+
+
+@pytest.fixture(scope="module")
+def ib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_01161_amd import ibmlb
+    ibmlb.lib()
+    return ibmlb
+
+
+def _compare_indicator(sim, L, T):
+    V = sim.vertices()  # the GPU's own positions, so both sides decide on the same surface
+    got = sim.indicator()
+    want = oracle.indicator(L, V, T)
+    bad = np.argwhere(got != want)
+    for z, y, x in bad:
+        p = np.array([x, y, z], float)
+        # only a node on the surface itself may go either way
+        on_vertex = np.linalg.norm(V - p, axis=1).min() < 1e-9
+        w = oracle.winding(V, T, p)
+        assert on_vertex or abs(w - 0.5) < 1e-6, (x, y, z, got[z, y, x], want[z, y, x], w)
+    return int(want.sum()), len(bad)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_indicator_star_mesh_matches_oracle(ib, storage):
+    L = (30, 30, 30)
+    V, T = _star_mesh(_offset_center(L), 7.0)
+    print(f"case indicator star mesh {storage}", flush=True)
+    sim = ib.Simulation(L, 0.9, sigma=0.01, radius=7.0, vertices=V, triangles=T, storage=storage, chi=3.0)
+    n_in, n_bad = _compare_indicator(sim, L, T)
+    print(f"  inside {n_in}  on-surface mismatches {n_bad}", flush=True)
+    assert n_in > 1000 and n_bad == 0
+    A = np.zeros(9)
+    A[1] = 2e-3
+    sim.step(A, 20)  # the indicator follows the moving mesh
+    n_in, n_bad = _compare_indicator(sim, L, T)
+    assert n_in > 1000 and n_bad == 0
+    sim.close()
+
+
+def test_indicator_rows_through_vertices(ib):
+    L = (33, 33, 33)  # x_c = (16, 16, 16): vertices at integer radius lie on lattice rows
+    c = box_center(L)
+    assert all(float(v).is_integer() for v in c)
+    V, T = icosphere(3, 6.0, c)
+    print("case indicator icosphere on lattice rows", flush=True)
+    sim = ib.Simulation(L, 0.9, sigma=0.01, radius=6.0, vertices=V, triangles=T, storage="f64", chi=2.0)
+    n_in, n_bad = _compare_indicator(sim, L, T)
+    print(f"  inside {n_in}  on-vertex mismatches {n_bad}", flush=True)
+    got = sim.indicator()
+    # the rows that graze the sphere at (x_c, y_c +- 6, z_c) and (x_c, y_c, z_c +- 6) carry no inside node
+    # other than, possibly, the vertex itself
+    xc, yc, zc = (int(v) for v in c)
+    for dy, dz in ((6, 0), (-6, 0), (0, 6), (0, -6)):
+        row = got[zc + dz, yc + dy].copy()
+        row[xc] = 0
+        assert row.sum() == 0, (dy, dz)
+    # the rows through the poles (y_c, z_c) are inside between the two vertices
+    row = got[zc, yc]
+    assert row[xc - 5:xc + 6].all() and row[:xc - 6].sum() == 0 and row[xc + 7:].sum() == 0
+    sim.close()
+
+
+def _case():
+    L = (24, 22, 26)
+    V, T = icosphere(2, 5.0, _offset_center(L))
+    A = np.zeros(9)
+    A[1] = 3e-3
+    A[5] = -1e-3
+    return L, A, dict(tau=0.9, sigma=0.02, radius=5.0, vertices=V, triangles=T, A0=A)
+
+
+@pytest.mark.parametrize("storage,chi,tol", [
+    ("f64", 4.0, (1e-11, 1e-10, 1e-13)),
+    ("f32", 0.25, (2e-5, 2e-4, 1e-6)),
+])
+def test_viscosity_ratio_droplet_matches_oracle(ib, storage, chi, tol):
+    L, A, kw = _case()
+    print(f"case chi droplet {storage} chi {chi}", flush=True)
+    sim = ib.Simulation(L, storage=storage, chi=chi, **kw)
+    ref = oracle.Oracle(L, chi=chi, **kw)
+    sim.step(A, 30)
+    ref.step(A, 30)
+    dr = np.abs(sim.vertices() - ref.vertices()).max()
+    rho_g, u_g = sim.fields()
+    rho_r, u_r = ref.fields()
+    du = np.abs(u_g - u_r).max() / np.abs(u_r).max()
+    drho = np.abs(rho_g - rho_r).max()
+    print(f"  max|dr| {dr:.2e}  du {du:.2e}  drho {drho:.2e}", flush=True)
+    assert dr <= tol[0] and du <= tol[1] and drho <= tol[2]
+    assert np.array_equal(sim.indicator(), ref.indicator())
+    # the viscosity ratio does change the flow
+    one = oracle.Oracle(L, **kw)
+    one.step(A, 30)
+    assert np.abs(one.fields()[1] - u_r).max() > 10 * np.abs(u_g - u_r).max()
+    one.close()
+    sim.close()
+    ref.close()
+
+
+def _rise_time(D, frac=0.5):
+    """Step at which D first reaches frac of its plateau (mean of the last tenth)."""
+    plateau = D[-len(D) // 10:].mean()
+    return int(np.argmax(D >= frac * plateau)), plateau
+
+
+def test_shear_startup_follows_linear_theory_time_scale(ib):
+    L, R, tau = (40, 40, 40), 6.0, 1.0
+    V, T = icosphere(3, R, _offset_center(L))
+    mu = (tau - 0.5) / 3.0
+    tau_sigma = 60.0
+    sigma = mu * R / tau_sigma
+    Ca = 0.05
+    gamma = Ca / tau_sigma
+    A = np.zeros(9)
+    A[1] = gamma
+    nst, every = 1600, 10
+    out = {}
+    for chi in (1.0, 4.0):
+        print(f"case shear start-up chi {chi}", flush=True)
+        sim = ib.Simulation(L, tau, sigma=sigma, radius=R, vertices=V, triangles=T, storage="f32", A0=A, chi=chi)
+        D = []
+        for _ in range(nst // every):
+            sim.step(A, every)
+            D.append(sim.observables()["D"])
+        sim.close()
+        out[chi] = np.asarray(D)
+    k1, d1 = P.lt_coefficients(1.0)
+    k4, d4 = P.lt_coefficients(4.0)
+    t1, p1 = _rise_time(out[1.0])
+    t4, p4 = _rise_time(out[4.0])
+    print(f"  rise chi=1 {t1 * every} steps, chi=4 {t4 * every} steps, ratio {t4 / t1:.2f} "
+          f"(linear theory {k1 / k4:.2f}); plateaus {p1:.4f} {p4:.4f}", flush=True)
+    assert 0.75 * k1 / k4 <= t4 / t1 <= 1.25 * k1 / k4
+    # the plateaus: their ratio is the theory's (Taylor's (19 chi + 16)/(16 chi + 16) at steady
+    # state); each is the theory's steady deformation (d/k) Ca / 2 up to the diffuse interface
+    # of a six-node droplet, which deforms it more
+    assert abs((p4 / p1) / ((d4 / k4) / (d1 / k1)) - 1.0) < 0.05
+    for chi, p in ((1.0, p1), (4.0, p4)):
+        k, d = P.lt_coefficients(chi)
+        assert 0.8 <= p / (d / k * Ca / 2) <= 1.7, (chi, p)
+
+
+def test_viscosity_ratio_limits(ib):
+    L, A, kw = _case()
+    for extra in (dict(collision="mrt"), dict(populations=1)):
+        with pytest.raises(ib.IbmLbError):
+            ib.Simulation(L, storage="f32", chi=2.0, **kw, **extra)
+    sim = ib.Simulation(L, storage="f32", chi=2.0, **kw)
+    for v in (ROWS | 1, AA | 1):
+        with pytest.raises(ib.IbmLbError):
+            sim.set_variant(v)
+    with pytest.raises(ib.IbmLbError):
+        sim.objective_grad()
+    sim.close()
+    one = ib.Simulation(L, storage="f32", **kw)
+    with pytest.raises(ib.IbmLbError):
+        one.indicator()
+    one.close()
+    with pytest.raises(ib.IbmLbError):
+        ib.Ensemble([dict(L=L, chi=2.0, **kw)], storage="f32")
