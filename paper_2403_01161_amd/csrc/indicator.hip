@@ -77,7 +77,7 @@ __device__ inline int clamp_ceil(double v, int lo, int hi) {
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_ind_cross(Geom g, const V4<R>* __restrict__ r,
+__global__ __launch_bounds__(64) void k_ind_cross(Geom g, const V4<R>* __restrict__ r,
                                                    const int4* __restrict__ tris, int nt, unsigned* ind_words,
                                                    int* line_lo, int* line_hi) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -128,25 +128,46 @@ __global__ __launch_bounds__(256) void k_ind_scan(Geom g, unsigned char* ind, in
     if (line >= g.Ly * g.Lz) return;
     const int lo = line_lo[line], hi = line_hi[line];
     if (lo > hi) return;
-    unsigned char* row = ind + (long long)line * g.Lx;
-    unsigned char par = 0;
-    for (int x = lo; x <= hi; ++x) {
-        par ^= (row[x] >> 1) & 1;
-        row[x] = par;
+    // The walk is latency-bound: the row's bytes are read as aligned 32-bit
+    // words of the whole array, eight per round trip (a word may hold bytes of
+    // a neighbouring row, which are read but never written here); the bytes of
+    // this row are then rewritten one by one.
+    const long long n0 = (long long)line * g.Lx + lo, n1 = (long long)line * g.Lx + hi;
+    const unsigned* words = reinterpret_cast<const unsigned*>(ind);
+    unsigned par = 0;
+    for (long long w0 = n0 >> 2; w0 <= (n1 >> 2); w0 += 8) {
+        unsigned wv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wv[k] = w0 + k <= (n1 >> 2) ? words[w0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const long long n = 4 * (w0 + k) + b;
+                if (n >= n0 && n <= n1) {
+                    par ^= (wv[k] >> (8 * b + 1)) & 1u;
+                    ind[n] = (unsigned char)par;
+                }
+            }
     }
     line_lo[line] = IND_LINE_EMPTY;
     line_hi[line] = -1;
 }
 
+// One wave per work-group for the triangles: a 20k-triangle mesh spreads over
+// 320 work-groups instead of 80, so that the latency-bound threads run on
+// every compute unit.
+constexpr int IND_TB = 64;
+
 hipError_t launch_indicator(int storage, const Geom& g, const DevPtrs& d, int nt, hipStream_t s, hipEvent_t done) {
-    const unsigned nb = unsigned((nt + 255) / 256);
+    const unsigned nb = unsigned((nt + IND_TB - 1) / IND_TB);
     int* lo = d.ind_lines;
     int* hi = d.ind_lines + (long long)g.Ly * g.Lz;
     if (storage == IBM_LB_F64)
-        hipLaunchKernelGGL(k_ind_cross<double>, dim3(nb), dim3(256), 0, s, g, (const V4<double>*)d.r, d.tris, nt,
+        hipLaunchKernelGGL(k_ind_cross<double>, dim3(nb), dim3(IND_TB), 0, s, g, (const V4<double>*)d.r, d.tris, nt,
                            (unsigned*)d.ind, lo, hi);
     else
-        hipLaunchKernelGGL(k_ind_cross<float>, dim3(nb), dim3(256), 0, s, g, (const V4<float>*)d.r, d.tris, nt,
+        hipLaunchKernelGGL(k_ind_cross<float>, dim3(nb), dim3(IND_TB), 0, s, g, (const V4<float>*)d.r, d.tris, nt,
                            (unsigned*)d.ind, lo, hi);
     const unsigned nl = unsigned(((long long)g.Ly * g.Lz + 255) / 256);
     hipExtLaunchKernelGGL(k_ind_scan, dim3(nl), dim3(256), 0, s, nullptr, done, 0, g, d.ind, lo, hi);
