@@ -39,7 +39,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 // Byte offsets of every device array inside one workspace.
 struct Layout {
     size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, tris, fan, lfan, hstart, hids, obs_part, mass_part,
-        obs_out, Abuf, red, ind, ind_lines, total;
+        obs_out, Abuf, red, ind, ind_lines, ptris, ptstart, total;
 };
 
 // Per vertex: valence m and the one-ring neighbours n_0 .. n_{m-1} in
@@ -87,6 +87,8 @@ Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t 
     L.red = take(sizeof(unsigned long long) * 2);
     L.ind = take(ind_b);
     L.ind_lines = take(sizeof(int) * 2 * lines);
+    L.ptris = take(ind_b ? sizeof(int4) * (size_t)nt : 0);
+    L.ptstart = take(ind_b ? sizeof(int) * ((size_t)(nv + IB_PATCH - 1) / IB_PATCH + 1) : 0);
     L.total = off;
     return L;
 }
@@ -454,11 +456,9 @@ int take_event(ibm_lb* h, int* idx) {
 // With a viscosity ratio, also the indicator of the current mesh.
 int ensure_force(ibm_lb* h) {
     if (h->f_ready || h->nv == 0) return IBM_LB_OK;
+    if (h->chi) HIP_TRY(launch_indicator_clear(h->g, h->d, h->stream), "indicator clear");
     HIP_TRY(launch_ib_pre(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream), "ib_pre launch");
-    if (h->chi) {
-        HIP_TRY(launch_indicator_clear(h->g, h->d, h->stream), "indicator clear");
-        HIP_TRY(launch_indicator(h->storage, h->g, h->d, h->nt, h->stream, nullptr), "indicator launch");
-    }
+    if (h->chi) HIP_TRY(launch_indicator_scan(h->g, h->d, h->stream, nullptr), "indicator launch");
     h->f_ready = true;
     return IBM_LB_OK;
 }
@@ -514,7 +514,7 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
             HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream,
                                    h->chi ? nullptr : done, (h->lattice_variant & VAR_HC_SPLIT) != 0),
                     "ib_step launch");
-        if (h->chi) HIP_TRY(launch_indicator(h->storage, h->g, h->d, h->nt, h->stream, done), "indicator launch");
+        if (h->chi) HIP_TRY(launch_indicator_scan(h->g, h->d, h->stream, done), "indicator launch");
         if (h->timing) {
             h->iv.push_back({k0, k1});
             h->ev_pending = ib ? kd : k1;
@@ -683,6 +683,8 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     d.red = (unsigned long long*)(b + L.red);
     d.ind = h->chi ? (unsigned char*)(b + L.ind) : nullptr;
     d.ind_lines = h->chi ? (int*)(b + L.ind_lines) : nullptr;
+    d.ptris = h->chi ? (int4*)(b + L.ptris) : nullptr;
+    d.ptstart = h->chi ? (int*)(b + L.ptstart) : nullptr;
     h->perm = mesh.perm;
     if (h->nv > 0) {
         e = patch_setup(h->storage);
@@ -712,6 +714,20 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
         for (int t = 0; t < h->nt; ++t)
             tris[t] = int4{mesh.tris[3 * t], mesh.tris[3 * t + 1], mesh.tris[3 * t + 2], 0};
         INIT_TRY(hipMemcpy(d.tris, tris.data(), sizeof(int4) * h->nt, hipMemcpyHostToDevice), "tris");
+        if (h->chi) {
+            // each triangle goes to the patch of its lowest vertex id, patch by patch
+            const int npatch = (h->nv + IB_PATCH - 1) / IB_PATCH;
+            std::vector<int> start(npatch + 1, 0);
+            auto owner = [&](const int4& t) { return std::min(t.x, std::min(t.y, t.z)) / IB_PATCH; };
+            for (const int4& t : tris) start[owner(t) + 1]++;
+            for (int q = 0; q < npatch; ++q) start[q + 1] += start[q];
+            std::vector<int4> pt(h->nt);
+            std::vector<int> fill(start.begin(), start.end() - 1);
+            for (const int4& t : tris) pt[fill[owner(t)]++] = t;
+            INIT_TRY(hipMemcpy(d.ptris, pt.data(), sizeof(int4) * h->nt, hipMemcpyHostToDevice), "patch triangles");
+            INIT_TRY(hipMemcpy(d.ptstart, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice),
+                     "patch triangle starts");
+        }
         INIT_TRY(hipMemcpy(d.fan, csr.fan.data(), sizeof(int) * csr.fan.size(), hipMemcpyHostToDevice), "fan");
         const Halos& hl = mesh.halos;
         INIT_TRY(hipMemcpy(d.lfan, hl.lfan.data(), sizeof(int) * hl.lfan.size(), hipMemcpyHostToDevice), "lfan");

@@ -27,10 +27,14 @@
 //                   runs the rare further iterations, records the count and
 //                   advances the step epoch
 //   k_fs_patch      next step's surface-tension forces (Eq. pi_drop), tile
+//                   marks and spreading; with a viscosity ratio its idle
+//                   waves also cross the patch's triangles with the lattice
+//                   x-rows (first half of the inside indicator); the
 //                   marks and spreading, from the final positions
 #include <hip/hip_ext.h>
 
 #include "device_common.h"
+#include "indicator_common.h"
 
 namespace ibmlb {
 
@@ -319,10 +323,24 @@ __device__ bool spread_window(const IbArgs<R, AS>& a, const Stage<R>& st, double
     return true;
 }
 
+// The triangles each patch crosses with the lattice rows (viscosity ratio
+// only): those whose lowest vertex id lies in the patch, listed patch by
+// patch, and the indicator's toggle words and row ranges.
+struct IndArgs {
+    const int4* ptris;    // [nt], grouped by patch
+    const int* ptstart;   // [npatch + 1]
+    unsigned* words;      // indicator bytes as 32-bit words
+    int* lo;              // [Ly Lz] row ranges
+    int* hi;
+};
+
 // Forces, tile marks and spreading of patch p from positions P. With
 // `commit`, P (the final smoothed positions) also becomes the state r.
-template <class R, int AS>
-__device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, int commit, Stage<R>& st, double* win) {
+// CHI: waves 1-3, idle while the first wave computes the forces, cross the
+// patch's triangles (positions P) with the lattice rows.
+template <class R, int AS, bool CHI = false>
+__device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, int commit, Stage<R>& st, double* win,
+                         const IndArgs* ia = nullptr) {
     const int t = threadIdx.x;
     const int k = p * PATCH + t;
     const int ep = a.ctl->epoch;
@@ -349,6 +367,23 @@ __device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, 
         for (int d = 0; d < 3; ++d) st.first[t][d] = f[d];
         st.ok[t] = ok ? 1 : 0;
     }
+    if constexpr (CHI) {
+        if (t >= 64) {
+            const double xc[3] = {a.g.xci[0] + a.g.xcf[0], a.g.xci[1] + a.g.xcf[1], a.g.xci[2] + a.g.xcf[2]};
+            for (int q = ia->ptstart[p] + t - 64; q < ia->ptstart[p + 1]; q += IBT - 64) {
+                const int4 tv = ia->ptris[q];
+                const int id[3] = {tv.x, tv.y, tv.z};
+                double Pd[3][3];
+                for (int c = 0; c < 3; ++c) {
+                    const V4<R> pc = ld4<V4<R>>(P + id[c]);
+                    Pd[c][0] = double(pc.x) + xc[0];
+                    Pd[c][1] = double(pc.y) + xc[1];
+                    Pd[c][2] = double(pc.z) + xc[2];
+                }
+                triangle_row_crossings(a.g, id, Pd, ia->words, ia->lo, ia->hi);
+            }
+        }
+    }
     __syncthreads();
     if (spread_window(a, st, win, 0, PATCH)) return;
     // a patch too spread out for the window: direct global atomics
@@ -368,6 +403,14 @@ __global__ __launch_bounds__(IBT) void k_fs_patch(IbArgs<R> a, const V4<R>* P, i
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ Stage<R> st;
     fs_patch(a, blockIdx.x, P, commit, st, reinterpret_cast<double*>(dyn));
+}
+
+// The same with the row crossings of the viscosity ratio's indicator.
+template <class R>
+__global__ __launch_bounds__(IBT) void k_fs_patch_ind(IbArgs<R> a, const V4<R>* P, int commit, IndArgs ia) {
+    extern __shared__ __align__(16) unsigned char dyn[];
+    __shared__ Stage<R> st;
+    fs_patch<R, 0, true>(a, blockIdx.x, P, commit, st, reinterpret_cast<double*>(dyn), &ia);
 }
 
 // ---------------------------------------------------------------- interpolation
@@ -740,12 +783,19 @@ static IbArgs<R> make_args(const Geom& g, const DevPtrs& d, int nv, double sigma
     return a;
 }
 
+static IndArgs ind_args(const Geom& g, const DevPtrs& d) {
+    return IndArgs{d.ptris, d.ptstart, (unsigned*)d.ind, d.ind_lines, d.ind_lines + (long long)g.Ly * g.Lz};
+}
+
 hipError_t patch_setup(int storage) {
     const int lds = (int)dyn_lds(storage);
     hipError_t e;
     const int lds_s = (int)dyn_lds_spread();
     if (storage == IBM_LB_F64) {
         e = hipFuncSetAttribute((const void*)k_fs_patch<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_s);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_fs_patch_ind<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    lds_s);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_fs_batch<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_s);
         if (e == hipSuccess)
@@ -756,6 +806,9 @@ hipError_t patch_setup(int storage) {
                                     lds);
     } else {
         e = hipFuncSetAttribute((const void*)k_fs_patch<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_s);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_fs_patch_ind<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    lds_s);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_fs_batch<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_s);
         if (e == hipSuccess)
@@ -777,8 +830,12 @@ static hipError_t launch_step_t(const Geom& g, const DevPtrs& d, int nv, double 
     const V4<R>* final_pos = sp.max_iter > 0 ? a.qa : a.o;
     hipLaunchKernelGGL(k_hc_fused<R>, dim3(npatch), dim3(IBT), 0, s, a, (int)npatch, hc_split ? 1 : 0);
     if (hc_split) hipLaunchKernelGGL(k_hc_finish<R>, dim3(1), dim3(1024), 0, s, a);
-    hipExtLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr, done, 0, a,
-                          final_pos, 1);
+    if (d.ind)
+        hipExtLaunchKernelGGL(k_fs_patch_ind<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr,
+                              done, 0, a, final_pos, 1, ind_args(g, d));
+    else
+        hipExtLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr, done,
+                              0, a, final_pos, 1);
     return hipGetLastError();
 }
 
@@ -825,10 +882,18 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
     const size_t lds = dyn_lds_spread();
     if (storage == IBM_LB_F64) {
         IbArgs<double> a = make_args<double>(g, d, nv, sigma, sp);
-        hipLaunchKernelGGL(k_fs_patch<double>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<double>*)a.r, 0);
+        if (d.ind)
+            hipLaunchKernelGGL(k_fs_patch_ind<double>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<double>*)a.r, 0,
+                               ind_args(g, d));
+        else
+            hipLaunchKernelGGL(k_fs_patch<double>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<double>*)a.r, 0);
     } else {
         IbArgs<float> a = make_args<float>(g, d, nv, sigma, sp);
-        hipLaunchKernelGGL(k_fs_patch<float>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<float>*)a.r, 0);
+        if (d.ind)
+            hipLaunchKernelGGL(k_fs_patch_ind<float>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<float>*)a.r, 0,
+                               ind_args(g, d));
+        else
+            hipLaunchKernelGGL(k_fs_patch<float>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<float>*)a.r, 0);
     }
     return hipGetLastError();
 }

@@ -90,6 +90,8 @@ struct DevPtrs {
     unsigned long long* red; // [2] grid-wide max reduction slots
     unsigned char* ind;      // [N rounded up to 4] inside indicator (viscosity ratio only)
     int* ind_lines;          // [2][Ly Lz] node range of each x-row's crossings (viscosity ratio only)
+    int4* ptris;             // [nt] triangles grouped by the patch of their lowest vertex (viscosity ratio only)
+    int* ptstart;            // [npatch + 1] start of each patch's triangles (viscosity ratio only)
 };
 
 // Bytes of the indicator array (whole 32-bit words, for the atomic toggles).
@@ -163,9 +165,11 @@ hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, c
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const MrtRates* mrt = nullptr,
                           const ChiRates* chi = nullptr);
-// Indicator of the committed mesh d.r into d.ind (which must hold zeros and
-// empty row ranges); done (may be null) is stamped at completion.
-hipError_t launch_indicator(int storage, const Geom& g, const DevPtrs& d, int nt, hipStream_t s, hipEvent_t done);
+// Second half of the indicator: the running parity over each x-row of the
+// toggles that the force kernel left (d.ind non-null makes the force kernel
+// cross the mesh with the rows; d.ind must hold zeros and empty row ranges
+// before it); done (may be null) is stamped at completion.
+hipError_t launch_indicator_scan(const Geom& g, const DevPtrs& d, hipStream_t s, hipEvent_t done);
 // Zero the indicator and empty every row range (not for graph capture).
 hipError_t launch_indicator_clear(const Geom& g, const DevPtrs& d, hipStream_t s);
 // After an even in-place step: f[cur] back to natural order, in place.
