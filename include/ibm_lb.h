@@ -356,6 +356,14 @@ void ibm_lb_batch_destroy(ibm_lb_batch* b);
 enum { IBM_LB_OBJ_D = 0, IBM_LB_OBJ_LAMBDA_MAX = 1, IBM_LB_OBJ_BETA = 2 };
 int ibm_lb_objective_grad(ibm_lb* h, double* value, double* rbar);
 int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, double* rbar, double* dA_last);
+/* ibm_lb_adjoint_initial: dJ/dA0 through the initial state (IBM_LB_INIT_LINEAR:
+ * f_eq(rho0, A0 (x - x_c)) and its Chapman-Enskog part; zero for
+ * IBM_LB_INIT_REST). fbar0: device double [19][N] (x fastest), the adjoint of
+ * the population deviations at step 0 (fbar_begin of the first segment).
+ * dA0: host double [9], row-major. Synchronising; the handle's state is not
+ * used (A0, tau, rho0 and the box come from the configuration). Errors:
+ * EINVAL (bad arguments, MRT, wet walls or a viscosity ratio), EDEVICE. */
+int ibm_lb_adjoint_initial(ibm_lb* h, const double* fbar0, double* dA0);
 int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const double* A, int32_t nsteps,
                            int32_t A_on_device, const double* fbar_end, const double* rbar_end, double* fbar_begin,
                            double* rbar_begin, double* dA, double* dsigma);

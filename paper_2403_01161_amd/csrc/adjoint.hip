@@ -672,6 +672,71 @@ hipError_t launch_adj_perm_in(int nv, const int* perm, const double* user, doubl
     return hipGetLastError();
 }
 
+// dJ/dA0 through the initial populations (linear initial state):
+//   f_i^0 - w_i rho0 = w_i rho0 [3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u.u] - 3 tau w_i rho0 (c_i c_i - I/3):A0,
+//   u = A0 (x - x_c), so with d = x - x_c
+//   d f_i^0 / d A0_ab = w_i rho0 [(3 c_ia + 9 (c_i.u) c_ia - 3 u_a) d_b - 3 tau (c_ia c_ib - delta_ab / 3)].
+// Each work-group sums fbar_i(x) times that over its nodes (grid-stride) into
+// part[block][9]; the host adds the blocks in order.
+struct Mat9 {
+    double a[9];
+};
+
+__global__ __launch_bounds__(256) void k_adj_init_A0(Geom g, LatticeParams lp, Mat9 A0, const double* __restrict__ fbar,
+                                                     double* __restrict__ part) {
+    __shared__ double red[9][256];
+    const long long N = g.N;
+    const int LxLy = g.Lx * g.Ly;
+    double acc[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+    for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < N; n += (long long)gridDim.x * 256) {
+        const int z = int(n / LxLy), rem = int(n - (long long)z * LxLy), y = rem / g.Lx, x = rem - y * g.Lx;
+        const double dv[3] = {double(x - g.xci[0]) - g.xcf[0], double(y - g.xci[1]) - g.xcf[1],
+                              double(z - g.xci[2]) - g.xcf[2]};
+        double u[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] = A0.a[3 * a] * dv[0] + A0.a[3 * a + 1] * dv[1] + A0.a[3 * a + 2] * dv[2];
+        double G[3] = {0.0, 0.0, 0.0}, H[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) H[c] = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double wf = wgt<double>(i) * fbar[(long long)i * N + n];
+            const int ci[3] = {CX[i], CY[i], CZ[i]};
+            const double cu = ci[0] * u[0] + ci[1] * u[1] + ci[2] * u[2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                G[a] += wf * ((3.0 + 9.0 * cu) * ci[a] - 3.0 * u[a]);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) H[3 * a + b] += wf * (ci[a] * ci[b] - (a == b ? 1.0 / 3.0 : 0.0));
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc[3 * a + b] += lp.rho0 * (G[a] * dv[b] - 3.0 * lp.tau * H[3 * a + b]);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int c = 0; c < 9; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 9) part[9ll * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_adj_init_A0(const Geom& g, const LatticeParams& lp, const double A0[9], const double* fbar,
+                              double* part, int nblocks, hipStream_t s) {
+    Mat9 m;
+    for (int c = 0; c < 9; ++c) m.a[c] = A0[c];
+    hipLaunchKernelGGL(k_adj_init_A0, dim3(nblocks), dim3(256), 0, s, g, lp, m, fbar, part);
+    return hipGetLastError();
+}
+
 hipError_t launch_adj_perm_out(int nv, const int* perm, const double4* in, double* user, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_perm_out, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, perm, in, user);
     return hipGetLastError();

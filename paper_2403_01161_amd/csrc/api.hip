@@ -1191,6 +1191,28 @@ int ibm_lb_shape_objective_grad(ibm_lb* h, int32_t objective, double* value, dou
     return IBM_LB_OK;
 }
 
+int ibm_lb_adjoint_initial(ibm_lb* h, const double* fbar0, double* dA0) {
+    if (!h || !fbar0 || !dA0) return fail(IBM_LB_EINVAL, "bad adjoint_initial arguments");
+    if (h->mrt || h->wet || h->chi)
+        return fail(IBM_LB_EINVAL, "the adjoint covers the one-fluid BGK step with link walls");
+    if (h->sticky) return fail(h->sticky, "earlier asynchronous error");
+    for (int c = 0; c < 9; ++c) dA0[c] = 0.0;
+    if (h->cfg.init == IBM_LB_INIT_REST) return IBM_LB_OK;  // f^0 does not depend on A0
+    int rc = set_device(h);
+    if (rc) return rc;
+    // the observables' partial-sum slots serve as the block partials (OBS_BLOCKS x 16 doubles)
+    const int nb = OBS_BLOCKS;
+    HIP_TRY(launch_adj_init_A0(h->g, h->lp, h->cfg.A0, fbar0, h->d.obs_part, nb, h->stream), "adjoint A0 launch");
+    std::vector<double> part(9 * (size_t)nb);
+    HIP_TRY(hipMemcpyAsync(part.data(), h->d.obs_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost,
+                           h->stream),
+            "adjoint A0 copy");
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    for (int b = 0; b < nb; ++b)
+        for (int c = 0; c < 9; ++c) dA0[c] += part[9 * (size_t)b + c];
+    return IBM_LB_OK;
+}
+
 int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const double* A, int32_t nsteps,
                            int32_t A_on_device, const double* fbar_end, const double* rbar_end, double* fbar_begin,
                            double* rbar_begin, double* dA, double* dsigma) {

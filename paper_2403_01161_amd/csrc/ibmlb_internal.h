@@ -273,5 +273,9 @@ hipError_t launch_adj_seed(int storage, int nv, const DevPtrs& d, double* coef, 
                            int which = 0);
 hipError_t launch_adj_perm_in(int nv, const int* perm, const double* user, double4* out, hipStream_t s);
 hipError_t launch_adj_perm_out(int nv, const int* perm, const double4* in, double* user, hipStream_t s);
+// dJ/dA0 of the linear initial state from fbar0 [19][N]: per-block partial
+// sums part[nblocks][9] (row-major a, b).
+hipError_t launch_adj_init_A0(const Geom& g, const LatticeParams& lp, const double A0[9], const double* fbar,
+                              double* part, int nblocks, hipStream_t s);
 
 }  // namespace ibmlb

@@ -66,7 +66,7 @@ EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_t
            "ibm_lb_batch_init", "ibm_lb_batch_step", "ibm_lb_batch_observables", "ibm_lb_batch_member",
            "ibm_lb_batch_autotune", "ibm_lb_batch_set_variant", "ibm_lb_batch_set_graph",
            "ibm_lb_batch_destroy", "ibm_lb_objective_grad", "ibm_lb_shape_objective_grad",
-           "ibm_lb_adjoint_segment"]
+           "ibm_lb_adjoint_segment", "ibm_lb_adjoint_initial"]
 
 
 def lib():
@@ -107,6 +107,7 @@ def lib():
         L.ibm_lb_objective_grad.argtypes = [vp, dp, vp]
         L.ibm_lb_shape_objective_grad.argtypes = [vp, i32, dp, vp, dp]
         L.ibm_lb_adjoint_segment.argtypes = [vp, vp, C.c_size_t, vp, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.ibm_lb_adjoint_initial.argtypes = [vp, vp, dp]
         L.ibm_lb_strerror.argtypes = [C.c_int]
         L.ibm_lb_strerror.restype = C.c_char_p
         L.ibm_lb_last_error.restype = C.c_char_p
@@ -300,6 +301,15 @@ class Simulation:
                "ibm_lb_shape_objective_grad")
         return (v.value, rbar, dlast) if with_last_row else (v.value, rbar)
 
+    def adjoint_initial(self, fbar0):
+        """dJ/dA0 (numpy [9]) through the linear initial state from the adjoint of the step-0
+        population deviations (float64 CUDA tensor [19 N])."""
+        assert fbar0.dtype == torch.float64 and fbar0.is_cuda and fbar0.numel() == 19 * self.N
+        out = np.zeros(9)
+        _check(lib().ibm_lb_adjoint_initial(self._h, fbar0.contiguous().data_ptr(), _dp(out)),
+               "ibm_lb_adjoint_initial")
+        return out
+
     def adjoint_segment(self, ckpt, A, fbar_end, rbar_end, fbar_begin=None, rbar_begin=None, dA=None,
                         dsigma=None):
         """Reverse one segment that starts at checkpoint `ckpt` (a tensor written by save) and runs
@@ -432,8 +442,12 @@ class DeformationFunction(torch.autograd.Function):
     iteration counts are those the forward took."""
 
     @staticmethod
-    def forward(ctx, sigma, A, vertices, spec, K, objective="D"):
+    def forward(ctx, sigma, A, vertices, spec, K, objective="D", A0=None):
         spec = dict(spec)
+        ctx.a0 = A0 is not None
+        if ctx.a0:
+            ctx.a0dev, ctx.a0shape = A0.device, A0.shape
+            spec["A0"] = A0.detach().cpu().numpy().reshape(9)
         sim = Simulation(sigma=float(sigma), vertices=vertices.detach().cpu().numpy(), **spec)
         ctx.adev = A.device
         A = A.detach().to(device=sim.device, dtype=torch.float64).contiguous()
@@ -464,16 +478,28 @@ class DeformationFunction(torch.autograd.Function):
             rbar, rnext = rnext, rbar
         # the objective's own dependence on the last gradient row (beta)
         dA[-1] += torch.from_numpy(ctx.dlast).to(dA.device).reshape(dA[-1].shape) * gD
-        return (dsig.reshape(ctx.sigma_shape).to(ctx.sdev), dA.to(ctx.adev), rbar.to(ctx.vdev), None, None, None)
+        dA0 = None
+        if ctx.a0:
+            # fbar now holds the adjoint of the step-0 populations (gD already in the seed)
+            g0 = sim.adjoint_initial(fbar) if fbar is not None else np.zeros(9)
+            dA0 = torch.from_numpy(g0).to(ctx.a0dev).reshape(ctx.a0shape)
+        return (dsig.reshape(ctx.sigma_shape).to(ctx.sdev), dA.to(ctx.adev), rbar.to(ctx.vdev), None, None, None,
+                dA0)
 
 
 def deformation(sigma, A, vertices, K=50, objective="D", **spec):
     """Differentiable droplet shape objective J(r^T): the deformation D
     (default), "lambda_max" or "beta" (with the strain of the last gradient row);
     spec holds the Simulation keywords other than sigma and vertices (L, tau,
-    radius, triangles, ...)."""
+    radius, triangles, ...). A torch tensor A0 in spec (9 values) is
+    differentiated too, through the linear initial state."""
     if not isinstance(sigma, torch.Tensor):
         sigma = torch.tensor(float(sigma), dtype=torch.float64)
     if not isinstance(vertices, torch.Tensor):
         vertices = torch.as_tensor(np.asarray(vertices, dtype=np.float64))
+    A0 = spec.pop("A0", None)
+    if isinstance(A0, torch.Tensor):
+        return DeformationFunction.apply(sigma, A, vertices, spec, int(K), objective, A0)
+    if A0 is not None:
+        spec["A0"] = A0
     return DeformationFunction.apply(sigma, A, vertices, spec, int(K), objective)

@@ -3,7 +3,7 @@ largest eigenvalue of S) and beta (Eq. beta with the strain of the last
 gradient row, whose direct dependence on that row is part of dJ/dA),
 against central differences of the FP64 oracle with the smoothing
 iteration counts frozen at the nominal run's (the bar of the D objective:
-1e-3 relative)."""
+1e-3 relative). Also dJ/dA0 through the linear initial state."""
 import numpy as np
 import pytest
 
@@ -29,7 +29,9 @@ def _J(spec, sigma, V, A, counts, objective):
     o = _oracle(spec, sigma, V)
     o.freeze_iters(counts)
     o.step_table(A)
-    if objective == "lambda_max":
+    if objective == "D":
+        j = o.observables()["D"]
+    elif objective == "lambda_max":
         j = o.observables()["eigval"][0]
     else:
         # the strain of the (possibly perturbed) last gradient row
@@ -76,3 +78,38 @@ def test_shape_objective_adjoint_matches_oracle_fd(ib, objective):
     ad = float((Vt.grad.numpy() * dv).sum())
     print(f"  initial positions: adj={ad:.9e} fd={fd:.9e}", flush=True)
     assert _rel(ad, fd) < BAR
+
+
+def test_initial_gradient_adjoint_matches_oracle_fd(ib):
+    """dJ/dA0 through the linear initial state (the equilibrium of u = A0 (x - x_c) and its
+    Chapman-Enskog part) against oracle central differences in A0, two seeded directions."""
+    import torch
+    spec = _small_spec(50)
+    V = icosphere(3, 4.0, box_center(spec["L"]))[0]
+    nst, gamma = 30, 3e-3
+    A = _shear_ou(nst, gamma, 1e-3, 10.0, seed=29)
+    spec["A0"] = A[0]
+    sigma = (spec["tau"] - 0.5) / 3 * 4.0 * gamma / 0.1
+    counts, _, _ = _nominal(spec, sigma, V, A)
+    A0t = torch.tensor(A[0], dtype=torch.float64, requires_grad=True)
+    At = torch.tensor(A, dtype=torch.float64, device="cuda")
+    kw = {k: v for k, v in spec.items() if k != "A0"}
+    print("case adjoint initial state A0", flush=True)
+    J = ib.deformation(torch.tensor(sigma, dtype=torch.float64), At, V, K=12, A0=A0t, **kw)
+    J.backward()
+    g = A0t.grad.numpy()
+    rng = np.random.default_rng(31)
+    for k in range(2):
+        d = rng.standard_normal(9) * np.abs(A[0]).max()
+        Jp = _J(dict(spec, A0=A[0] + H * d), sigma, V, A, counts, "D")
+        Jm = _J(dict(spec, A0=A[0] - H * d), sigma, V, A, counts, "D")
+        fd = (Jp - Jm) / (2 * H)
+        ad = float(g @ d)
+        print(f"  direction {k}: adj={ad:.9e} fd={fd:.9e}", flush=True)
+        assert _rel(ad, fd) < BAR
+    # a rest initial state does not depend on A0
+    sim = ib.Simulation(kw["L"], kw["tau"], sigma=sigma, radius=4.0, vertices=V, triangles=kw["triangles"],
+                        storage="f64", init="rest", A0=A[0])
+    assert np.array_equal(sim.adjoint_initial(torch.ones(19 * sim.N, dtype=torch.float64, device="cuda")),
+                          np.zeros(9))
+    sim.close()
