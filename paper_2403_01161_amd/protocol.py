@@ -175,8 +175,9 @@ def run_ensemble(ens, frames_dnsu, m: Matching, stop_on_error: bool = False):
     return out
 
 
-def compare_with_theory(m: Matching, res, skip: int = 5):
-    """Frame-by-frame agreement of driven droplets with the linear theory.
+def compare_with_theory(m: Matching, res, skip: int = 5, chi: float = 1.0):
+    """Frame-by-frame agreement of driven droplets with the linear theory
+    for the viscosity ratio chi.
     res holds per-frame D, beta, theta and A_lbu, either [F] (one droplet) or
     [n, F] (an ensemble). Returns the mean of D / D_LT, the correlation of D
     with D_LT and of beta with beta_LT, and the mean |theta - theta_LT|
@@ -187,7 +188,7 @@ def compare_with_theory(m: Matching, res, skip: int = 5):
     A = np.asarray(res["A_lbu"]).reshape(D.shape[0], D.shape[1], 9)
     out = {"D_over_D_lt": [], "corr_D": [], "corr_beta": [], "theta_err_deg": [], "lt_valid_frac": []}
     for i in range(D.shape[0]):
-        S = lt_integrate(A[i], m.N, m.R_lbu, m.tau_sigma_lbu)
+        S = lt_integrate(A[i], m.N, m.R_lbu, m.tau_sigma_lbu, chi=chi)
         Dl, bl, tl = descriptors(S, A[i])
         ok = np.isfinite(Dl)
         ok[:skip] = False

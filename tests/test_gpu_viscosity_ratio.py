@@ -190,3 +190,24 @@ def test_viscosity_ratio_limits(ib):
     one.close()
     with pytest.raises(ib.IbmLbError):
         ib.Ensemble([dict(L=L, chi=2.0, **kw)], storage="f32")
+
+
+def test_protocol_with_viscosity_ratio_follows_its_theory(ib):
+    """The paper's protocol (DNS frames converted and held for N steps) on a droplet with
+    chi = 4 follows the linear theory for chi = 4 (Eq. eq:LT) within the bars of the one-fluid
+    protocol test. At this point (R / eta = 1/2, Ca = 0.05) the chi = 4 and chi = 1 theories
+    differ less than the droplet differs from either (correlations 0.87 and 0.88, D / D_LT
+    1.13 and 1.09 when measured), so the protocol does not tell the two apart here; the
+    shear start-up above does."""
+    from .test_protocol import _protocol_case
+    m, L, kw, fr = _protocol_case(60)
+    print(f"case protocol chi 4 N={m.N} frames={len(fr)}", flush=True)
+    sim = ib.Simulation(L, storage="f32", chi=4.0, **kw)
+    res = P.run(sim, fr, m)
+    sim.close()
+    c4 = P.compare_with_theory(m, res, skip=5, chi=4.0)
+    c1 = P.compare_with_theory(m, res, skip=5, chi=1.0)
+    print(f"  theory chi=4: corr D {c4['corr_D']:.3f}, D/D_LT {c4['D_over_D_lt']:.3f}, corr beta "
+          f"{c4['corr_beta']:.3f};  theory chi=1: corr D {c1['corr_D']:.3f}, D/D_LT {c1['D_over_D_lt']:.3f}, "
+          f"corr beta {c1['corr_beta']:.3f}", flush=True)
+    assert c4["corr_D"] > 0.8 and 1.0 < c4["D_over_D_lt"] < 1.5 and c4["corr_beta"] > 0.95
