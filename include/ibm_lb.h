@@ -133,9 +133,11 @@ typedef struct ibm_lb_config {
                               tau_in = 1/2 + chi (tau - 1/2) (Eq. tau_to_nu at one density) in
                               the BGK rate and the Guo factor; the inside is rebuilt from the mesh
                               after every step. BGK with two population copies, linear lattice
-                              variants, single droplets, without the adjoint; the mesh stays
-                              inside the box (no periodic images). The initial non-equilibrium
-                              part uses tau everywhere */
+                              variants, single droplets, without the adjoint. The inside is
+                              taken within the box's own node range: a vertex beyond [0, L - 1]
+                              on any axis (a droplet across a periodic boundary) ends the run
+                              with IBM_LB_EDOMAIN. The initial non-equilibrium part uses tau
+                              everywhere */
 } ibm_lb_config;
 
 typedef struct ibm_lb_obs {

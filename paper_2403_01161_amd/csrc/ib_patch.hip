@@ -332,6 +332,7 @@ struct IndArgs {
     unsigned* words;      // indicator bytes as 32-bit words
     int* lo;              // [Ly Lz] row ranges
     int* hi;
+    int* flags;           // the control block's error flags
 };
 
 // Forces, tile marks and spreading of patch p from positions P. With
@@ -380,7 +381,7 @@ __device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, 
                     Pd[c][1] = double(pc.y) + xc[1];
                     Pd[c][2] = double(pc.z) + xc[2];
                 }
-                triangle_row_crossings(a.g, id, Pd, ia->words, ia->lo, ia->hi);
+                triangle_row_crossings(a.g, id, Pd, ia->words, ia->lo, ia->hi, ia->flags);
             }
         }
     }
@@ -784,7 +785,8 @@ static IbArgs<R> make_args(const Geom& g, const DevPtrs& d, int nv, double sigma
 }
 
 static IndArgs ind_args(const Geom& g, const DevPtrs& d) {
-    return IndArgs{d.ptris, d.ptstart, (unsigned*)d.ind, d.ind_lines, d.ind_lines + (long long)g.Ly * g.Lz};
+    return IndArgs{d.ptris, d.ptstart, (unsigned*)d.ind, d.ind_lines, d.ind_lines + (long long)g.Ly * g.Lz,
+                   &d.ctl->flags};
 }
 
 hipError_t patch_setup(int storage) {

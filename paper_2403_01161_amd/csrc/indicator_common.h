@@ -69,11 +69,20 @@ __device__ inline int clamp_ceil(double v, int lo, int hi) {
 // or beyond x* (32-bit atomic XOR on the containing word) and widens the
 // row's [lo, hi] node range. Rows on the projection's boundary count too (the
 // perturbation decides).
+// The rows are those of the box itself: a mesh that reaches beyond the node
+// range [0, L - 1] of an axis (a periodic image would be needed) raises the
+// domain flag in *flags instead.
 __device__ inline void triangle_row_crossings(const Geom& g, const int id[3], const double P[3][3],
-                                              unsigned* ind_words, int* line_lo, int* line_hi) {
+                                              unsigned* ind_words, int* line_lo, int* line_hi, int* flags) {
+    const int Lax[3] = {g.Lx, g.Ly, g.Lz};
     for (int k = 0; k < 3; ++k)
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
             if (!(fabs(P[k][a]) < 1e9)) return;  // non-finite positions are reported by the IB kernels
+            if (P[k][a] < 0.0 || P[k][a] > Lax[a] - 1) {
+                atomicOr(flags, DFLAG_DOMAIN);
+                return;
+            }
+        }
     const double ymin = fmin(P[0][1], fmin(P[1][1], P[2][1])), ymax = fmax(P[0][1], fmax(P[1][1], P[2][1]));
     const double zmin = fmin(P[0][2], fmin(P[1][2], P[2][2])), zmax = fmax(P[0][2], fmax(P[1][2], P[2][2]));
     const int y0 = clamp_ceil(ymin, 0, g.Ly), y1 = clamp_floor(ymax, -1, g.Ly - 1);

@@ -211,3 +211,24 @@ def test_protocol_with_viscosity_ratio_follows_its_theory(ib):
           f"{c4['corr_beta']:.3f};  theory chi=1: corr D {c1['corr_D']:.3f}, D/D_LT {c1['D_over_D_lt']:.3f}, "
           f"corr beta {c1['corr_beta']:.3f}", flush=True)
     assert c4["corr_D"] > 0.8 and 1.0 < c4["D_over_D_lt"] < 1.5 and c4["corr_beta"] > 0.95
+
+
+def test_indicator_mesh_across_a_periodic_boundary_is_an_error(ib):
+    """The indicator uses the box's own rows: a droplet that reaches across a periodic
+    boundary (where the IB stencils wrap) stops with a domain error instead of a wrong inside."""
+    L = (24, 24, 24)
+    V, T = icosphere(2, 4.0, (1.3, 12.2, 11.9))
+    assert V[:, 0].min() < 0
+    print("case chi droplet across the periodic x boundary", flush=True)
+    sim = ib.Simulation(L, 0.9, sigma=0.01, radius=4.0, vertices=V, triangles=T, periodic=(1, 1, 1),
+                        storage="f64", chi=2.0)
+    with pytest.raises(ib.IbmLbError) as e:
+        sim.step(np.zeros(9), 1)
+        sim.observables()
+    assert e.value.code == ib.EDOMAIN
+    sim.close()
+    # the one-fluid droplet wraps as before
+    sim = ib.Simulation(L, 0.9, sigma=0.01, radius=4.0, vertices=V, triangles=T, periodic=(1, 1, 1), storage="f64")
+    sim.step(np.zeros(9), 1)
+    sim.observables()
+    sim.close()
