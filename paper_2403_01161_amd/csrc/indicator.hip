@@ -10,15 +10,20 @@
 //                row's [lo, hi] range leaves bit 0 = inside (an odd number of
 //                crossings at or before the node) and clears the toggles and
 //                the range.
-// The lattice kernel reads bit 0 and clears the byte, so between steps the
-// array holds exactly the indicator of the current mesh.
+// The lattice kernel reads bit 0 in the marked tiles (the scan marks every
+// tile with an inside node) and clears the byte, so between steps the array
+// holds exactly the indicator of the current mesh.
 #include <hip/hip_ext.h>
 
 #include "indicator_common.h"
 
 namespace ibmlb {
 
-__global__ __launch_bounds__(256) void k_ind_scan(Geom g, unsigned char* ind, int* line_lo, int* line_hi) {
+// Every tile that holds an inside node is marked for the step (mark[tile] =
+// epoch, as the spreading marks the tiles its stencils touch): the lattice
+// kernel reads the indicator in marked tiles only.
+__global__ __launch_bounds__(256) void k_ind_scan(Geom g, unsigned char* ind, int* line_lo, int* line_hi, int* mark,
+                                                  const Ctl* ctl) {
     const int line = blockIdx.x * blockDim.x + threadIdx.x;
     if (line >= g.Ly * g.Lz) return;
     const int lo = line_lo[line], hi = line_hi[line];
@@ -29,6 +34,10 @@ __global__ __launch_bounds__(256) void k_ind_scan(Geom g, unsigned char* ind, in
     // this row are then rewritten one by one.
     const long long n0 = (long long)line * g.Lx + lo, n1 = (long long)line * g.Lx + hi;
     const unsigned* words = reinterpret_cast<const unsigned*>(ind);
+    const int y = line % g.Ly, z = line / g.Ly;
+    const int trow = g.TX * ((y >> TILE_SHIFT) + g.TY * (z >> TILE_SHIFT));
+    const int ep = ctl->epoch;
+    int last_tile = -1;
     unsigned par = 0;
     for (long long w0 = n0 >> 2; w0 <= (n1 >> 2); w0 += 8) {
         unsigned wv[8];
@@ -42,6 +51,11 @@ __global__ __launch_bounds__(256) void k_ind_scan(Geom g, unsigned char* ind, in
                 if (n >= n0 && n <= n1) {
                     par ^= (wv[k] >> (8 * b + 1)) & 1u;
                     ind[n] = (unsigned char)par;
+                    const int tx = int(n - (long long)line * g.Lx) >> TILE_SHIFT;
+                    if (par && tx != last_tile) {
+                        mark[trow + tx] = ep;
+                        last_tile = tx;
+                    }
                 }
             }
     }
@@ -52,7 +66,7 @@ __global__ __launch_bounds__(256) void k_ind_scan(Geom g, unsigned char* ind, in
 hipError_t launch_indicator_scan(const Geom& g, const DevPtrs& d, hipStream_t s, hipEvent_t done) {
     const unsigned nl = unsigned(((long long)g.Ly * g.Lz + 255) / 256);
     hipExtLaunchKernelGGL(k_ind_scan, dim3(nl), dim3(256), 0, s, nullptr, done, 0, g, d.ind, d.ind_lines,
-                          d.ind_lines + (long long)g.Ly * g.Lz);
+                          d.ind_lines + (long long)g.Ly * g.Lz, d.mark, (const Ctl*)d.ctl);
     return hipGetLastError();
 }
 

@@ -173,7 +173,7 @@ __device__ __forceinline__ long long pull_source(const Geom& g, long long n, int
 // its (1 - 1/(2 tau)) factor (with every rate 1/tau, the BGK step).
 // CHI: a node whose indicator byte ind[n] is set (inside the droplet) relaxes
 // with the rates *ch instead of lp's; the byte is cleared for the next
-// step's indicator.
+// step's indicator. Only marked tiles hold inside nodes, so only they read it.
 template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, int AA, bool MRT = false, bool CHI = false,
           class PIn, class POut, class PR, class PM, class PC, class PA>
 __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp, PIn fin, POut fout, PR F,
@@ -237,7 +237,8 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
     R omega = R(lp.omega), kg = R(lp.kguo);
     const R rho0 = R(lp.rho0);
     if constexpr (CHI) {
-        if (ind[n]) {
+        // inside nodes lie in marked tiles only (the indicator build marks them)
+        if (marked && ind[n]) {
             omega = R(ch->omega_in);
             kg = R(ch->kguo_in);
             ind[n] = 0;
