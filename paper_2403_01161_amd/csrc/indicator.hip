@@ -36,8 +36,7 @@ __global__ __launch_bounds__(256) void k_ind_scan(Geom g, unsigned char* ind, in
     const unsigned* words = reinterpret_cast<const unsigned*>(ind);
     const int y = line % g.Ly, z = line / g.Ly;
     const int trow = g.TX * ((y >> TILE_SHIFT) + g.TY * (z >> TILE_SHIFT));
-    const int ep = ctl->epoch;
-    int last_tile = -1;
+    int in0 = g.Lx, in1 = -1;  // first and last inside node of the row
     unsigned par = 0;
     for (long long w0 = n0 >> 2; w0 <= (n1 >> 2); w0 += 8) {
         unsigned wv[8];
@@ -51,13 +50,17 @@ __global__ __launch_bounds__(256) void k_ind_scan(Geom g, unsigned char* ind, in
                 if (n >= n0 && n <= n1) {
                     par ^= (wv[k] >> (8 * b + 1)) & 1u;
                     ind[n] = (unsigned char)par;
-                    const int tx = int(n - (long long)line * g.Lx) >> TILE_SHIFT;
-                    if (par && tx != last_tile) {
-                        mark[trow + tx] = ep;
-                        last_tile = tx;
-                    }
+                    const int x = int(n - (long long)line * g.Lx);
+                    in0 = par ? min(in0, x) : in0;
+                    in1 = par ? x : in1;
                 }
             }
+    }
+    // the tiles from the first to the last inside node (a gap between two
+    // inside runs of a row marks a tile more, which is harmless)
+    if (in1 >= 0) {
+        const int ep = ctl->epoch;
+        for (int tx = in0 >> TILE_SHIFT; tx <= (in1 >> TILE_SHIFT); ++tx) mark[trow + tx] = ep;
     }
     line_lo[line] = IND_LINE_EMPTY;
     line_hi[line] = -1;
