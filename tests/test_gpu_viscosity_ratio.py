@@ -232,3 +232,38 @@ def test_indicator_mesh_across_a_periodic_boundary_is_an_error(ib):
     sim.step(np.zeros(9), 1)
     sim.observables()
     sim.close()
+
+
+def test_indicator_full_size_sampled(ib):
+    """The benchmark's droplet (128^3, R 16, 10242 vertices, FP32, autotuned variant) with
+    chi = 4 after 100 steps of a traceless gradient: the GPU indicator against the oracle's
+    winding number on 3000 sampled nodes of the droplet's bounding box and on every node of
+    the three rows through its centroid."""
+    import bench
+    w = bench.workload("f32")
+    L = w["L"]
+    A = np.zeros(9)
+    A[1], A[3] = 0.6 * w["G"], 0.2 * w["G"]
+    A[0], A[4] = 0.3 * w["G"], -0.3 * w["G"]
+    print("case indicator 128^3 bench droplet, chi 4", flush=True)
+    sim = ib.Simulation(L, w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage="f32", A0=A, chi=4.0)
+    sim.autotune(5)
+    sim.step(A, 100)
+    V = sim.vertices()
+    got = sim.indicator()
+    sim.close()
+    lo, hi = np.floor(V.min(0)).astype(int), np.ceil(V.max(0)).astype(int)
+    rng = np.random.default_rng(5)
+    pts = [rng.integers(lo, hi + 1) for _ in range(3000)]
+    c = np.rint(V.mean(0)).astype(int)
+    pts += [np.array([x, c[1], c[2]]) for x in range(L[0])]
+    pts += [np.array([c[0], y, c[2]]) for y in range(L[1])]
+    pts += [np.array([c[0], c[1], z]) for z in range(L[2])]
+    n_in = 0
+    for p in pts:
+        wn = oracle.winding(V, w["T"], p.astype(float))
+        if abs(wn - 0.5) < 1e-6:
+            continue
+        assert got[p[2], p[1], p[0]] == (wn > 0.5), (p, wn)
+        n_in += wn > 0.5
+    assert n_in > 1000
