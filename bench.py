@@ -131,7 +131,7 @@ def describe_variant(v):
 
 def lattice_kernel_name(v, chi=1.0):
     if chi != 1.0:
-        return "k_lattice_chi"
+        return "k_lattice_rows<..., CHI>" if v & 16 else "k_lattice_chi"
     if v & 64:
         return "k_lattice_aa"
     return "k_lattice_rows" if v & 16 else "k_lattice"

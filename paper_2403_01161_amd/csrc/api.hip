@@ -1013,7 +1013,7 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     int nc = 0;
     if (!h->single)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
-            if ((!h->mrt && !h->chi) || !(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT;
+            if (!h->mrt || !(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT;
     if (!h->mrt && !h->wet && !h->chi)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
             if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
@@ -1041,8 +1041,7 @@ int ibm_lb_set_variant(ibm_lb* h, int32_t variant) {
     if (h->mrt && (variant & (VAR_ROWS | VAR_AA)))
         return fail(IBM_LB_EINVAL, "MRT runs the linear layout with two copies");
     if (h->wet && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "wet-node walls run with two copies");
-    if (h->chi && (variant & (VAR_ROWS | VAR_AA)))
-        return fail(IBM_LB_EINVAL, "a viscosity ratio runs the linear layout with two copies");
+    if (h->chi && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "a viscosity ratio runs with two copies");
     h->lattice_variant = variant;
     return IBM_LB_OK;
 }

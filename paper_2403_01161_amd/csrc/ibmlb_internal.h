@@ -160,7 +160,7 @@ int lattice_variant_ok(int variant, const Geom& g);
 // mrt (may be null): MRT collision with these rates instead of BGK (linear
 // layout with two copies only).
 // chi (may be null): nodes whose indicator byte d.ind is set relax with
-// these rates; the byte is cleared (BGK, linear layout with two copies only).
+// these rates; the byte is cleared (BGK, two copies, linear or row layout).
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const MrtRates* mrt = nullptr,
