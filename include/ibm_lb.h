@@ -116,8 +116,8 @@ typedef struct ibm_lb_config {
     int32_t collision;     /* IBM_LB_BGK (0, the paper's single relaxation time) or IBM_LB_MRT:
                               multiple relaxation times (Sec. 3.1 mentions it as an option) on
                               the orthogonal moment basis of d'Humieres et al. (2002), the shear
-                              moments at 1/tau; MRT runs the linear layout with two copies,
-                              single droplets only, without the adjoint */
+                              moments at 1/tau; MRT runs with two copies (linear or row
+                              layout), single droplets only, without the adjoint */
     double mrt_s[5];       /* MRT rates in (0, 2) of the energy, energy-square, heat-flux,
                               third-order stress and third-order antisymmetric moments;
                               0 selects 1.19, 1.4, 1.2, 1.4, 1.98 */

@@ -1013,7 +1013,7 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     int nc = 0;
     if (!h->single)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
-            if (!h->mrt || !(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT;
+            cand[nc++] = v | VAR_HC_SPLIT;
     if (!h->mrt && !h->wet && !h->chi)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
             if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
@@ -1038,8 +1038,7 @@ int ibm_lb_set_variant(ibm_lb* h, int32_t variant) {
     if (!lattice_variant_ok(variant, h->g)) return fail(IBM_LB_EINVAL, "lattice variant cannot run on this box");
     if (h->single && !(variant & VAR_AA))
         return fail(IBM_LB_EINVAL, "a handle with one population copy runs in-place variants only");
-    if (h->mrt && (variant & (VAR_ROWS | VAR_AA)))
-        return fail(IBM_LB_EINVAL, "MRT runs the linear layout with two copies");
+    if (h->mrt && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "MRT runs with two copies");
     if (h->wet && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "wet-node walls run with two copies");
     if (h->chi && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "a viscosity ratio runs with two copies");
     h->lattice_variant = variant;

@@ -464,10 +464,11 @@ __global__ __launch_bounds__(256) void k_aa_settle(Geom g, typename C::store_t* 
 }
 
 // Row layout: `rows` whole x-rows per work-group (blockDim = rows * Lx <= 512).
-// CHI: the viscosity ratio's inner rates on the nodes the indicator marks.
+// CHI: the viscosity ratio's inner rates on the nodes the indicator marks;
+// MRT: the multiple-relaxation-time collision with the rates mr.
 constexpr int ROWS_MAX_T = 512;
 
-template <class C, bool IB, bool NTL, bool NTS, bool CHI = false>
+template <class C, bool IB, bool NTL, bool NTS, bool CHI = false, bool MRT = false>
 __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticeParams lp,
                                                              const typename C::store_t* __restrict__ fin,
                                                              typename C::store_t* __restrict__ fout,
@@ -476,7 +477,7 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticePara
                                                              const int* __restrict__ mark, Ctl* ctl,
                                                              const double* __restrict__ Arow, int rows,
                                                              unsigned char* __restrict__ ind = nullptr,
-                                                             ChiRates ch = ChiRates{}) {
+                                                             ChiRates ch = ChiRates{}, MrtRates mr = MrtRates{}) {
     using S = typename C::store_t;
     extern __shared__ __align__(16) unsigned char dyn[];
     S* stage = reinterpret_cast<S*>(dyn);
@@ -490,8 +491,8 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticePara
     const long long n = (long long)row * g.Lx + x;
     const bool act = n < g.N;
     if (act)
-        lattice_node<C, IB, NTL, true, NTS, false, 0, false, CHI>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y,
-                                                               z, stage, t, T, nullptr, ind, &ch);
+        lattice_node<C, IB, NTL, true, NTS, false, 0, MRT, CHI>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y,
+                                                             z, stage, t, T, &mr, ind, &ch);
     __syncthreads();
     if (act) rows_receive<C, NTS>(g, fout, stage, n, x, y, z, t, T);
 }
@@ -1132,18 +1133,19 @@ hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cu
     return hipGetLastError();
 }
 
-template <class C, bool IB, bool NTL, bool NTS, bool CHI = false>
+template <class C, bool IB, bool NTL, bool NTS, bool CHI = false, bool MRT = false>
 static void rows_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                        int rows, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr) {
+                        int rows, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr,
+                        const MrtRates* mr = nullptr) {
     using R = typename C::real;
     using S = typename C::store_t;
     const int T = rows * g.Lx;
     const long long nrows = (long long)g.Ly * g.Lz;
     const unsigned nb = unsigned((nrows + rows - 1) / rows);
-    hipExtLaunchKernelGGL((k_lattice_rows<C, IB, NTL, NTS, CHI>), dim3(nb), dim3(T), uint32_t(NXMOVE * T * sizeof(S)),
-                          s, e0, e1, 0, g, lp, (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u,
-                          (const int*)d.mark, d.ctl, A_row, rows, CHI ? d.ind : nullptr,
-                          ch ? *ch : ChiRates{});
+    hipExtLaunchKernelGGL((k_lattice_rows<C, IB, NTL, NTS, CHI, MRT>), dim3(nb), dim3(T),
+                          uint32_t(NXMOVE * T * sizeof(S)), s, e0, e1, 0, g, lp, (const S*)d.f[cur],
+                          (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, rows,
+                          CHI ? d.ind : nullptr, ch ? *ch : ChiRates{}, mr ? *mr : MrtRates{});
 }
 
 int lattice_rows_per_block(int variant, int Lx) {
@@ -1217,7 +1219,27 @@ hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, c
         return hipGetLastError();
     }
     if (mrt) {
-        if (variant & (VAR_ROWS | VAR_AA)) return hipErrorInvalidValue;
+        if (variant & VAR_AA) return hipErrorInvalidValue;
+        if (variant & VAR_ROWS) {
+            const int rows = lattice_rows_per_block(variant, g.Lx);
+            const bool nts = (variant & VAR_X) != 0;
+#define MRT_ROWS(IBV, NTLV)                                                                                   \
+    do {                                                                                                      \
+        if (nts) rows_launch<C, IBV, NTLV, true, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, mrt); \
+        else rows_launch<C, IBV, NTLV, false, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, mrt);  \
+    } while (0)
+            DISPATCH_STORAGE(storage, C, {
+                if (ib) {
+                    if (variant & 1) MRT_ROWS(true, true);
+                    else MRT_ROWS(true, false);
+                } else {
+                    if (variant & 1) MRT_ROWS(false, true);
+                    else MRT_ROWS(false, false);
+                }
+            });
+#undef MRT_ROWS
+            return hipGetLastError();
+        }
         DISPATCH_STORAGE(storage, C, {
             if (ib) {
                 if (variant & 1) launch_mrt_v<C, true, true>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
