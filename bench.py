@@ -129,7 +129,9 @@ def describe_variant(v):
     return d
 
 
-def lattice_kernel_name(v, chi=1.0):
+def lattice_kernel_name(v, chi=1.0, collision="bgk"):
+    if collision == "mrt":
+        return "k_lattice_rows<..., MRT>" if v & 16 else "k_lattice_mrt"
     if chi != 1.0:
         return "k_lattice_rows<..., CHI>" if v & 16 else "k_lattice_chi"
     if v & 64:
@@ -211,7 +213,7 @@ def cpu_baseline(w, table, steps, single_steps=8):
     import numpy as np
     import oracle
     kw = dict(tau=w["tau"], sigma=w["sigma"], radius=w["R"], vertices=w["V"], triangles=w["T"],
-              A0=table[0])
+              A0=table[0], collision=w.get("collision", "bgk"), walls=w.get("walls", "link"))
     gomp = ctypes.CDLL("libgomp.so.1")  # the OpenMP runtime the oracle library uses
     cores = int(gomp.omp_get_max_threads())
     rows = table[1:1 + steps]
@@ -424,6 +426,10 @@ def main():
                     help="viscosity ratio of the droplet for the single-droplet leg (1: one fluid); "
                          "other values add the inside-indicator build per step and skip the CPU "
                          "baseline (the oracle's winding-number indicator is far too slow at 128^3)")
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
+                    help="collision of the single-droplet leg (MRT: default rates)")
+    ap.add_argument("--walls", default="link", choices=["link", "wet"],
+                    help="wall rule of the single-droplet leg (wet: the wet-node velocity walls)")
     ap.add_argument("--counters", nargs="?", const="128", choices=["128", "256"], default=None,
                     help="short fixed sequence for hardware-counter runs: 3 device copies of "
                          "256 MiB (calibration) and 20 steps of the single-droplet workload")
@@ -449,7 +455,9 @@ def main():
     K, W = args.steps, args.warmup
     table = ou_gradient_table(W + 2 * K + 1, w["corr"], w["G"], seed=w["seed"])
     sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"],
-                           storage=w["storage"], A0=table[0], device=dev, chi=args.chi)
+                           storage=w["storage"], A0=table[0], device=dev, chi=args.chi,
+                           collision=args.collision, walls=args.walls)
+    w["collision"], w["walls"] = args.collision, args.walls
     dtab = torch.from_numpy(table).to(dev)
     nodes = int(np.prod(w["L"]))
     nv = len(w["V"])
@@ -483,7 +491,8 @@ def main():
     avg_s = lat_ms / 1e3 / max(launches, 1)
     achieved = alg_bytes / avg_s / 1e9
     # the committed counters are those of the one-fluid lattice kernel
-    traffic = counter_traffic(args.storage, variant=variant) if args.chi == 1.0 else None
+    plain = args.chi == 1.0 and args.collision == "bgk" and args.walls == "link"
+    traffic = counter_traffic(args.storage, variant=variant) if plain else None
 
     value = nodes * K / dt / 1e6
     line = {
@@ -502,12 +511,15 @@ def main():
         "config": {"workload": "single droplet, 128^3 moving-wall box, tau 0.8, R 16, "
                                "10242-vertex icosphere, OU traceless A(t) rms Ca 0.1, "
                                f"{args.storage} populations"
-                               + (f", viscosity ratio {args.chi:g}" if args.chi != 1.0 else ""),
-                   "box": list(w["L"]), "vertices": nv, "storage": args.storage, "chi": args.chi},
+                               + (f", viscosity ratio {args.chi:g}" if args.chi != 1.0 else "")
+                               + (", MRT collision" if args.collision == "mrt" else "")
+                               + (", wet-node walls" if args.walls == "wet" else ""),
+                   "box": list(w["L"]), "vertices": nv, "storage": args.storage, "chi": args.chi,
+                   "collision": args.collision, "walls": args.walls},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": lattice_kernel_name(variant, args.chi),
+                     "kernel": lattice_kernel_name(variant, args.chi, args.collision),
                      "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
                      "variant": describe_variant(variant)},
