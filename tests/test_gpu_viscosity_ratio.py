@@ -287,3 +287,22 @@ def test_indicator_full_size_sampled(ib):
         assert got[p[2], p[1], p[0]] == (wn > 0.5), (p, wn)
         n_in += wn > 0.5
     assert n_in > 1000
+
+
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+def test_viscosity_ratio_16bit_storage(ib, storage):
+    """The 16-bit population formats with chi = 4 under the soft gate of 16-bit storage:
+    finite, and D within 5 % of the FP64 oracle after 200 steps."""
+    L, A, kw = _case()
+    print(f"case chi droplet {storage}", flush=True)
+    sim = ib.Simulation(L, storage=storage, chi=4.0, **kw)
+    sim.step(A, 200)
+    ob = sim.observables()
+    V = sim.vertices()
+    sim.close()
+    ref = oracle.Oracle(L, chi=4.0, **kw)
+    ref.step(A, 200)
+    D0 = ref.observables()["D"]
+    ref.close()
+    print(f"  D {ob['D']:.6f} oracle {D0:.6f}", flush=True)
+    assert np.isfinite(V).all() and abs(ob["D"] - D0) <= 0.05 * D0
