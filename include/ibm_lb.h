@@ -132,8 +132,8 @@ typedef struct ibm_lb_config {
                               crossings along x, i.e. the winding number modulo 2) relax with
                               tau_in = 1/2 + chi (tau - 1/2) (Eq. tau_to_nu at one density) in
                               the BGK rate and the Guo factor; the inside is rebuilt from the mesh
-                              after every step. BGK with two population copies (linear or row
-                              layout), single droplets, without the adjoint. The inside is
+                              after every step. BGK (every lattice variant, one or two
+                              population copies), single droplets, without the adjoint. The inside is
                               taken within the box's own node range: a vertex beyond [0, L - 1]
                               on any axis (a droplet across a periodic boundary) ends the run
                               with IBM_LB_EDOMAIN. The initial non-equilibrium part uses tau

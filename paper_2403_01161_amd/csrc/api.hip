@@ -131,8 +131,7 @@ int validate(const ibm_lb_config* c) {
     if (c->walls == IBM_LB_WALLS_WET && c->populations == 1)
         return fail(IBM_LB_EINVAL, "wet-node walls run with two population copies");
     if (!(c->chi >= 0.0 && c->chi <= 1e6)) return fail(IBM_LB_EINVAL, "chi must lie in [0, 1e6]");
-    if (chi_active(c) && (c->collision != IBM_LB_BGK || c->populations == 1))
-        return fail(IBM_LB_EINVAL, "a viscosity ratio runs BGK with two population copies");
+    if (chi_active(c) && c->collision != IBM_LB_BGK) return fail(IBM_LB_EINVAL, "a viscosity ratio runs BGK");
     const int nv = c->n_vertices, nt = c->n_triangles;
     if (nv < 0 || nt < 0) return fail(IBM_LB_EINVAL, "negative mesh size");
     if (nv == 0 && nt == 0) return IBM_LB_OK;
@@ -1014,7 +1013,7 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     if (!h->single)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
             cand[nc++] = v | VAR_HC_SPLIT;
-    if (!h->mrt && !h->wet && !h->chi)
+    if (!h->mrt && !h->wet)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
             if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
     tune(cand, nc, best_of);
@@ -1040,7 +1039,6 @@ int ibm_lb_set_variant(ibm_lb* h, int32_t variant) {
         return fail(IBM_LB_EINVAL, "a handle with one population copy runs in-place variants only");
     if (h->mrt && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "MRT runs with two copies");
     if (h->wet && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "wet-node walls run with two copies");
-    if (h->chi && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "a viscosity ratio runs with two copies");
     h->lattice_variant = variant;
     return IBM_LB_OK;
 }

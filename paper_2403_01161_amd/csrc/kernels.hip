@@ -420,19 +420,22 @@ __global__ __launch_bounds__(BS) void k_lattice_chi(Geom g, LatticeParams lp,
 }
 
 // In-place (single-copy) form, linear layout: ODD selects the step parity.
-template <class C, bool IB, bool NTL, int BS, bool ODD>
+// CHI: the viscosity ratio's inner rates on the nodes the indicator marks.
+template <class C, bool IB, bool NTL, int BS, bool ODD, bool CHI = false>
 __global__ __launch_bounds__(BS) void k_lattice_aa(Geom g, LatticeParams lp, typename C::store_t* f,
                                                     typename C::real* __restrict__ F,
                                                     typename C::real* __restrict__ U,
                                                     const int* __restrict__ mark, Ctl* ctl,
-                                                    const double* __restrict__ Arow, int xcd) {
+                                                    const double* __restrict__ Arow, int xcd,
+                                                    unsigned char* __restrict__ ind = nullptr,
+                                                    ChiRates ch = ChiRates{}) {
     const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
     const long long n = (long long)b * BS + threadIdx.x;
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    lattice_node<C, IB, NTL, false, false, false, ODD ? 2 : 1>(g, lp, (const typename C::store_t*)f, f, F, U, mark,
-                                                                ctl, Arow, n, x, y, z, nullptr, 0, 0);
+    lattice_node<C, IB, NTL, false, false, false, ODD ? 2 : 1, false, CHI>(
+        g, lp, (const typename C::store_t*)f, f, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0, 0, nullptr, ind, &ch);
 }
 
 // After an even in-place step, back to natural order in place. In the odd
@@ -1112,17 +1115,21 @@ static void launch_chi_v(int variant, const Geom& g, const LatticeParams& lp, co
     }
 }
 
-template <class C, bool IB, bool NTL, int BS>
+template <class C, bool IB, bool NTL, int BS, bool CHI = false>
 static void aa_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row, int xcd,
-                      int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                      int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr) {
     using R = typename C::real;
     using S = typename C::store_t;
+    unsigned char* ind = CHI ? d.ind : nullptr;
+    const ChiRates cr = ch ? *ch : ChiRates{};
     if (parity)
-        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, true>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1,
-                              0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, xcd);
+        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, true, CHI>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0,
+                              e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, xcd,
+                              ind, cr);
     else
-        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, false>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1,
-                              0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, xcd);
+        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, false, CHI>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s,
+                              e0, e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row,
+                              xcd, ind, cr);
 }
 
 hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cur, hipStream_t s) {
@@ -1197,7 +1204,25 @@ hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, c
     if (mrt && chi) return hipErrorInvalidValue;
     if (chi) {
         // the indicator exists only with a droplet
-        if ((variant & VAR_AA) || !ib || !d.ind) return hipErrorInvalidValue;
+        if (!ib || !d.ind) return hipErrorInvalidValue;
+        if (variant & VAR_AA) {
+            const int xcd = (variant & VAR_X) ? 1 : 0;
+#define CHI_AA(NTLV)                                                                                               \
+    do {                                                                                                           \
+        switch ((variant >> 1) & 3) {                                                                              \
+            case 0: aa_launch<C, true, NTLV, LAT_BS[0], true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, chi); break; \
+            case 1: aa_launch<C, true, NTLV, LAT_BS[1], true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, chi); break; \
+            case 2: aa_launch<C, true, NTLV, LAT_BS[2], true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, chi); break; \
+            default: aa_launch<C, true, NTLV, LAT_BS[3], true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, chi); break; \
+        }                                                                                                          \
+    } while (0)
+            DISPATCH_STORAGE(storage, C, {
+                if (variant & 1) CHI_AA(true);
+                else CHI_AA(false);
+            });
+#undef CHI_AA
+            return hipGetLastError();
+        }
         if (variant & VAR_ROWS) {
             const int rows = lattice_rows_per_block(variant, g.Lx);
             const bool nts = (variant & VAR_X) != 0;

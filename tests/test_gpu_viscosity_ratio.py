@@ -12,8 +12,8 @@ tau_to_nu) against the FP64 oracle:
 * the physics: in simple shear at small Ca the deformation rises on the
   time scale of the linear theory (Eq. eq:LT), tau_sigma / k(chi), so the
   rise with chi = 4 is k(1)/k(4) = 2.3 times slower than with chi = 1;
-* every two-copy lattice variant agrees;
-* the limits: BGK, two copies, single droplets, no adjoint.
+* every lattice variant agrees, in-place streaming with one copy included;
+* the limits: BGK, single droplets, no adjoint.
 """
 import numpy as np
 import pytest
@@ -175,18 +175,23 @@ def test_shear_startup_follows_linear_theory_time_scale(ib):
 
 @pytest.mark.parametrize("storage,tol", [("f64", (1e-12, 1e-11)), ("f32", (2e-5, 2e-4))])
 def test_viscosity_ratio_variants_agree(ib, storage, tol):
-    """Every two-copy lattice variant (linear and row layouts, block sizes, load and store
-    options) gives the same state with chi = 4, to the rounding that the spreading's atomic
-    sums leave (their order varies from run to run, so droplet runs are not bit-identical)."""
+    """Every lattice variant (linear and row layouts, block sizes, load and store options, in-place
+    streaming with two copies and with one) gives the same state with chi = 4, to the rounding
+    that the spreading's atomic sums leave (their order varies from run to run, so droplet runs
+    are not bit-identical)."""
     L, A, kw = _case()
     states = {}
-    for v in (33, 32, 35, 37, 39, 41, ROWS | 33, ROWS | 41, ROWS | 32):
-        sim = ib.Simulation(L, storage=storage, chi=4.0, **kw)
+    runs = [(v, 2) for v in (33, 32, 35, 37, 39, 41, ROWS | 33, ROWS | 41, ROWS | 32, AA | 33, AA | 35)]
+    runs += [(AA | 33, 1)]  # one population copy
+    for v, copies in runs:
+        sim = ib.Simulation(L, storage=storage, chi=4.0, populations=copies, **kw)
         sim.set_variant(v)
-        sim.step(A, 12)
-        states[v] = (sim.vertices(), sim.fields()[1], sim.indicator())
+        sim.step(A, 12 if v != AA | 35 else 11)  # odd and even in-place step counts
+        if v == AA | 35:
+            sim.step(A, 1)
+        states[(v, copies)] = (sim.vertices(), sim.fields()[1], sim.indicator())
         sim.close()
-    ref = states[33]
+    ref = states[(33, 2)]
     for v, st in states.items():
         dr = np.abs(st[0] - ref[0]).max()
         du = np.abs(st[1] - ref[1]).max() / np.abs(ref[1]).max()
@@ -195,12 +200,9 @@ def test_viscosity_ratio_variants_agree(ib, storage, tol):
 
 def test_viscosity_ratio_limits(ib):
     L, A, kw = _case()
-    for extra in (dict(collision="mrt"), dict(populations=1)):
-        with pytest.raises(ib.IbmLbError):
-            ib.Simulation(L, storage="f32", chi=2.0, **kw, **extra)
-    sim = ib.Simulation(L, storage="f32", chi=2.0, **kw)
     with pytest.raises(ib.IbmLbError):
-        sim.set_variant(AA | 1)
+        ib.Simulation(L, storage="f32", chi=2.0, collision="mrt", **kw)
+    sim = ib.Simulation(L, storage="f32", chi=2.0, **kw)
     with pytest.raises(ib.IbmLbError):
         sim.objective_grad()
     sim.close()
