@@ -124,9 +124,12 @@ typedef struct ibm_lb_config {
     int32_t walls;         /* IBM_LB_WALLS_LINK (0): link-wise moving-wall bounce-back, walls
                               half a link outside the boundary nodes; IBM_LB_WALLS_WET: the
                               paper's wet-node velocity walls through the boundary nodes
-                              (Sec. 3.1: Zou-He faces with the transverse correction, the
-                              printed edge and corner rules with buried links), two population
-                              copies, single droplets, without the adjoint */
+                              (Sec. 3.1: Zou-He faces with the transverse correction of
+                              Eq. ZH_bulk; edge and corner nodes rebuilt to hold their density,
+                              the wall velocity and the linear field's populations, with the
+                              along-edge correction of Eq. ZH_edges and the buried links and
+                              rest population reset), two population copies, single droplets,
+                              without the adjoint */
     double chi;            /* viscosity ratio of droplet to carrier (Sec. 2), in [0, 1e6]; 0 or 1:
                               one fluid. Otherwise the nodes inside the mesh (parity of the mesh
                               crossings along x, i.e. the winding number modulo 2) relax with
@@ -190,6 +193,7 @@ int ibm_lb_observables(ibm_lb* h, ibm_lb_obs* out);
  * [3][N]). read_field allocates a temporary device buffer. */
 int ibm_lb_read_vertices(ibm_lb* h, double* out);
 int ibm_lb_read_field(ibm_lb* h, int32_t which, double* out);
+
 
 /* Inside indicator that the next step's collision uses (Sec. 2, viscosity
  * ratio chi), host uint8 [N] (x fastest): 1 for a node inside the current

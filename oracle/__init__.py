@@ -251,7 +251,7 @@ class Oracle:
         for k in range(9):
             p.A0[k] = A0[k]
         p.collision = {"bgk": 0, "mrt": 1}[collision]
-        p.wall_bc = {"link": 0, "wet": 1}[walls]
+        p.wall_bc = {"link": 0, "wet": 1, "wet_printed": 2}[walls]
         for k, v in enumerate(mrt_s if mrt_s is not None else [0.0] * 5):
             p.mrt_s[k] = float(v)
         p.chi = float(chi)

@@ -8,9 +8,9 @@
  * Every routine is the plain definition or the algorithm's steps in the
  * paper's order (arXiv 2403.01161), in FP64, with a fixed summation order:
  * vertices ascending, triangles ascending, nodes z-major then y then x.
- * Only the two lattice sweeps are split over z-planes with OpenMP; each node
- * is computed by one thread alone, so results do not depend on the thread
- * count.
+ * The lattice sweeps (and the indicator) are split over z-planes with
+ * OpenMP on boxes of 32768 nodes or more; each node is computed by one
+ * thread alone, so results do not depend on the thread count.
  *
  * Readings of the paper taken here (the paper is silent or inconsistent):
  *  - Eq. (equilibriumLB) prints the velocity-squared term as u.u/cs^2; that
@@ -615,7 +615,8 @@ struct ibo_sim {
     double A_last[9];
     int* sched;             /* frozen smoothing iteration counts, see ibo_freeze_iters */
     int sched_n, sched_pos;
-    int wall_bc;            /* 0 link bounce-back, 1 wet-node velocity walls */
+    int wall_bc;            /* 0 link bounce-back, 1 wet-node velocity walls, 2 the same with the
+                               edge and corner rules as printed */
     int collision;          /* 0 BGK, 1 MRT */
     double mrt_M[19 * 19], mrt_n2[19], mrt_s[19];  /* basis, squared norms, rate per moment */
     double tau_in;          /* relaxation time inside the droplet (tau when chi = 1) */
@@ -643,7 +644,7 @@ int ibo_create(const ibo_params* p, ibo_sim** out)
         if (p->L[a] < 4) return IBO_EINVAL;
     if (!(p->tau > 0.5) || !(p->sigma >= 0.0) || !(p->rho0 > 0.0)) return IBO_EINVAL;
     if (p->collision < 0 || p->collision > 1) return IBO_EINVAL;
-    if (p->wall_bc < 0 || p->wall_bc > 1) return IBO_EINVAL;
+    if (p->wall_bc < 0 || p->wall_bc > 2) return IBO_EINVAL;
     for (int k = 0; k < 5; ++k)
         if (!(p->mrt_s[k] >= 0.0 && p->mrt_s[k] < 2.0)) return IBO_EINVAL;
     if (!(p->chi >= 0.0) || (p->chi != 0.0 && p->chi != 1.0 && p->collision != 0)) return IBO_EINVAL;
@@ -743,7 +744,7 @@ static int force_field(ibo_sim* s)
 /* Moments, Eq. (density_velocity_LB): rho = sum f, rho u = sum c f + F/2. */
 static void moments(ibo_sim* s)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->N >= 32768)
     for (long z = 0; z < s->L[2]; ++z)
         for (long y = 0; y < s->L[1]; ++y)
             for (long x = 0; x < s->L[0]; ++x) {
@@ -767,7 +768,7 @@ static void moments(ibo_sim* s)
  * the BGK step. */
 static void collide(ibo_sim* s)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->N >= 32768)
     for (long z = 0; z < s->L[2]; ++z)
         for (long y = 0; y < s->L[1]; ++y)
             for (long x = 0; x < s->L[0]; ++x) {
@@ -809,7 +810,7 @@ static void collide(ibo_sim* s)
 static void stream(ibo_sim* s, const double A[9])
 {
     const double cs2 = 1.0 / 3.0;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->N >= 32768)
     for (long z = 0; z < s->L[2]; ++z)
         for (long y = 0; y < s->L[1]; ++y)
             for (long x = 0; x < s->L[0]; ++x) {
@@ -838,6 +839,62 @@ static void stream(ibo_sim* s, const double A[9])
             }
 }
 
+/* Edges and corners as printed (Sec. 3.1, Eqs. ZH_edges,
+ * zh-buried-links-edges, zh-buried-links-corners): no wall-velocity term;
+ * the unknowns of a corner whose opposite is known by plain reflection. */
+static void wet_corner_printed(double* f, int nw, int nrm[3][3], const int unknown[19], const int buried[19])
+{
+    int N[3];
+    for (int a = 0; a < 3; ++a) N[a] = nrm[0][a] + nrm[1][a] + (nw == 3 ? nrm[2][a] : 0);
+    double fn[19];
+    memcpy(fn, f, sizeof(fn));
+    for (int j = 0; j < 19; ++j) {
+        if (!unknown[j] || buried[j]) continue;
+        const int i = opposite(j);
+        if (nw == 3) {
+            fn[j] = f[i];
+            continue;
+        }
+        double t[3], corr = 0.0;
+        const int* n1 = nrm[0];
+        const int* n2 = nrm[1];
+        const int c1 = CV[i][0] * n1[0] + CV[i][1] * n1[1] + CV[i][2] * n1[2];
+        const int c2 = CV[i][0] * n2[0] + CV[i][1] * n2[1] + CV[i][2] * n2[2];
+        for (int a = 0; a < 3; ++a) t[a] = CV[i][a] - c1 * n1[a] - c2 * n2[a];
+        for (int k = 0; k < 19; ++k) {
+            int k1 = CV[k][0] * n1[0] + CV[k][1] * n1[1] + CV[k][2] * n1[2];
+            int k2 = CV[k][0] * n2[0] + CV[k][1] * n2[1] + CV[k][2] * n2[2];
+            double tc = t[0] * CV[k][0] + t[1] * CV[k][1] + t[2] * CV[k][2];
+            corr += f[k] * tc * (1.0 - abs(k1)) * (1.0 - abs(k2));
+        }
+        fn[j] = f[i] - 0.25 * corr;
+    }
+    memcpy(f, fn, sizeof(fn));
+    double fb = 0.0;
+    if (nw == 2) {
+        const int* n1 = nrm[0];
+        const int* n2 = nrm[1];
+        const int cr[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2],
+                           n1[0] * n2[1] - n1[1] * n2[0]};
+        for (int i = 1; i < 19; ++i) {
+            const double c2 = CV[i][0] * CV[i][0] + CV[i][1] * CV[i][1] + CV[i][2] * CV[i][2];
+            const double a1 = abs(CV[i][0] * cr[0] + CV[i][1] * cr[1] + CV[i][2] * cr[2]);
+            const double a2 = abs(CV[i][0] * N[0] + CV[i][1] * N[1] + CV[i][2] * N[2]) / c2;
+            fb += f[i] * (1.0 - (1.0 - a1) * (1.0 - a2));
+        }
+        fb /= 22.0;
+    } else {
+        for (int i = 1; i < 19; ++i) {
+            const double c2 = CV[i][0] * CV[i][0] + CV[i][1] * CV[i][1] + CV[i][2] * CV[i][2];
+            fb += f[i] * abs(CV[i][0] * N[0] + CV[i][1] * N[1] + CV[i][2] * N[2]) / c2;
+        }
+        fb /= 18.0;
+    }
+    for (int j = 0; j < 19; ++j)
+        if (buried[j]) f[j] = fb;
+    f[0] = 12.0 * fb;
+}
+
 /* Wet-node velocity walls (Sec. 3.1): the walls pass through the boundary
  * nodes, each with the velocity u_w = A (x - x_c) of Eq.
  * (velo_facce_cubo_da_gradiente) at the node. After streaming, a population
@@ -847,18 +904,37 @@ static void stream(ibo_sim* s, const double A[9])
  *      and normal momentum) and Eq. (ZH_bulk),
  *      f_j = f_i - (2 - |t_i|) rho/6 c_i.u_w - rho/3 t_i.u_w
  *            + 1/2 sum_k f_k (t_i.c_k)(1 - |c_k.n|),  t_i = c_i - (c_i.n) n;
- *  (b) two walls (an edge): Eq. (ZH_edges) for the unknowns whose opposite is
- *      known, with t_i = c_i - (c_i.n1) n1 - (c_i.n2) n2, then the two buried
- *      links c = +-(n1 - n2) by Eq. (zh-buried-links-edges) and f_0 = 12 f_b;
- *  (c) three walls (a corner): the unknowns whose opposite is known by plain
- *      reflection f_j = f_i (the text gives no rule for them), then the six
- *      buried links c.(n1 + n2 + n3) = 0 by Eq. (zh-buried-links-corners) and
+ *  (b) two walls (an edge, inward normals n1, n2, t_i = c_i minus its
+ *      components along n1 and n2): Eq. (ZH_edges) for the unknowns whose
+ *      opposite is known, then the two buried links c = +-(n1 - n2) by
+ *      Eq. (zh-buried-links-edges) and f_0 = 12 f_b;
+ *  (c) three walls (a corner): the unknowns whose opposite is known by
+ *      reflection (the text gives no rule for them), then the six buried
+ *      links c.(n1 + n2 + n3) = 0 by Eq. (zh-buried-links-corners) and
  *      f_0 = 12 f_b.
- * The edge and corner rules are applied as printed: they carry no
- * wall-velocity term. */
-static void wet_walls(ibo_sim* s, const double A[9])
+ * The edge and corner rules as printed carry no wall-velocity term, and the
+ * printed sign of the edge correction adds the along-edge momentum of the
+ * resting populations +-e a second time where the face rule's correction
+ * removes it; a linear flow then stays wrong at first order in A. Mode 2
+ * (printed = 1) applies them as printed. Mode 1 applies the reading in which
+ * an edge or corner node carries the wall velocity and the wall's linear
+ * field, the conditions from which Eq. (ZH_bulk) follows on a face (the same
+ * derivation gives Eq. (ZH_bulk) back):
+ *  - an unknown j whose opposite i is known: Eq. (standard BB) for any link,
+ *    f_j = f_i - 6 w_i rho c_i.u_w, and at an edge also the correction of
+ *    Eq. (ZH_edges) with the sign of Eq. (ZH_bulk)'s and its velocity term,
+ *    - rho/12 t_i.u_w + 1/4 sum_k f_k (t_i.c_k)(1 - |c_k.n1|)(1 - |c_k.n2|);
+ *  - the buried links and the rest population, which the paper resets,
+ *    take the equilibrium at (rho, u_w) plus the non-equilibrium part of the
+ *    linear field, -3 tau w_j rho (c_j c_j - I/3):A (as the initial state);
+ *  - rho is the node's density: sum_j f_j = rho solved for rho (every
+ *    population above is linear in rho).
+ * The node then holds density rho and momentum rho u_w exactly, and the
+ * linear field's populations up to second order in A. At rest both modes
+ * give the rest weights. */
+static void wet_walls(ibo_sim* s, const double A[9], int printed)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->N >= 32768)
     for (long z = 0; z < s->L[2]; ++z)
         for (long y = 0; y < s->L[1]; ++y)
             for (long x = 0; x < s->L[0]; ++x) {
@@ -922,21 +998,55 @@ static void wet_walls(ibo_sim* s, const double A[9])
                 }
                 int buried[19];
                 for (int j = 0; j < 19; ++j) buried[j] = unknown[j] && unknown[opposite(j)];
-                /* the unknowns whose opposite is known */
+                if (printed) {
+                    wet_corner_printed(f, nw, nrm, unknown, buried);
+                    continue;
+                }
+                /* populations reset from (rho, u_w, A): rho g_j */
+                double g[19];
+                const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                for (int j = 0; j < 19; ++j) {
+                    g[j] = 0.0;
+                    if (j != 0 && !buried[j]) continue;
+                    const double cu = CV[j][0] * u[0] + CV[j][1] * u[1] + CV[j][2] * u[2];
+                    double cAc = 0.0;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) cAc += CV[j][a] * A[3 * a + b] * CV[j][b];
+                    const double trA = A[0] + A[4] + A[8];
+                    g[j] = weight(j) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) -
+                           3.0 * s->tau * weight(j) * (cAc - trA / 3.0);
+                }
+                /* density: sum_j f_j = rho over the completed node */
+                double known = 0.0, lin = 1.0;
+                for (int j = 0; j < 19; ++j) {
+                    if (j == 0 || buried[j]) {
+                        lin -= g[j];
+                    } else if (unknown[j]) {
+                        const int i = opposite(j);
+                        known += 2.0 * f[i];
+                        lin += 6.0 * weight(i) * (CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2]);
+                    } else if (!unknown[opposite(j)]) {
+                        known += f[j]; /* neither it nor its opposite crosses a wall */
+                    }
+                }
+                const double rho = known / lin;
                 double fn[19];
                 memcpy(fn, f, sizeof(fn));
                 for (int j = 0; j < 19; ++j) {
-                    if (!unknown[j] || buried[j]) continue;
-                    const int i = opposite(j);
-                    if (nw == 3) {
-                        fn[j] = f[i];
+                    if (j == 0 || buried[j]) {
+                        fn[j] = rho * g[j];
                         continue;
                     }
-                    double t[3], corr = 0.0;
+                    if (!unknown[j]) continue;
+                    const int i = opposite(j);
+                    const double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+                    fn[j] = f[i] - 6.0 * weight(i) * rho * cu;
+                    if (nw == 3) continue;
                     const int* n1 = nrm[0];
                     const int* n2 = nrm[1];
                     const int c1 = CV[i][0] * n1[0] + CV[i][1] * n1[1] + CV[i][2] * n1[2];
                     const int c2 = CV[i][0] * n2[0] + CV[i][1] * n2[1] + CV[i][2] * n2[2];
+                    double t[3], corr = 0.0;
                     for (int a = 0; a < 3; ++a) t[a] = CV[i][a] - c1 * n1[a] - c2 * n2[a];
                     for (int k = 0; k < 19; ++k) {
                         int k1 = CV[k][0] * n1[0] + CV[k][1] * n1[1] + CV[k][2] * n1[2];
@@ -944,36 +1054,10 @@ static void wet_walls(ibo_sim* s, const double A[9])
                         double tc = t[0] * CV[k][0] + t[1] * CV[k][1] + t[2] * CV[k][2];
                         corr += f[k] * tc * (1.0 - abs(k1)) * (1.0 - abs(k2));
                     }
-                    fn[j] = f[i] - 0.25 * corr;
+                    const double tu = t[0] * u[0] + t[1] * u[1] + t[2] * u[2];
+                    fn[j] += -rho / 12.0 * tu + 0.25 * corr;
                 }
                 memcpy(f, fn, sizeof(fn));
-                /* buried links and the rest population */
-                double fb = 0.0;
-                if (nw == 2) {
-                    const int* n1 = nrm[0];
-                    const int* n2 = nrm[1];
-                    const int cr[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2],
-                                       n1[0] * n2[1] - n1[1] * n2[0]};
-                    for (int i = 1; i < 19; ++i) {
-                        const double c2 = CV[i][0] * CV[i][0] + CV[i][1] * CV[i][1] + CV[i][2] * CV[i][2];
-                        const double a1 = abs(CV[i][0] * cr[0] + CV[i][1] * cr[1] + CV[i][2] * cr[2]);
-                        const double a2 = abs(CV[i][0] * (n1[0] + n2[0]) + CV[i][1] * (n1[1] + n2[1]) +
-                                              CV[i][2] * (n1[2] + n2[2])) / c2;
-                        fb += f[i] * (1.0 - (1.0 - a1) * (1.0 - a2));
-                    }
-                    fb /= 22.0;
-                } else {
-                    int N[3];
-                    for (int a = 0; a < 3; ++a) N[a] = nrm[0][a] + nrm[1][a] + nrm[2][a];
-                    for (int i = 1; i < 19; ++i) {
-                        const double c2 = CV[i][0] * CV[i][0] + CV[i][1] * CV[i][1] + CV[i][2] * CV[i][2];
-                        fb += f[i] * abs(CV[i][0] * N[0] + CV[i][1] * N[1] + CV[i][2] * N[2]) / c2;
-                    }
-                    fb /= 18.0;
-                }
-                for (int j = 0; j < 19; ++j)
-                    if (buried[j]) f[j] = fb;
-                f[0] = 12.0 * fb;
             }
 }
 
@@ -989,7 +1073,7 @@ static int one_step(ibo_sim* s, const double A[9])
     }
     collide(s);
     stream(s, A);
-    if (s->wall_bc == 1) wet_walls(s, A);
+    if (s->wall_bc) wet_walls(s, A, s->wall_bc == 2);
     for (int k = 0; k < 3 * s->nv; ++k) s->r[k] += s->U[k];   /* Eq. (fwd_euler) */
     int capped = 0;
     if (s->sched_pos < s->sched_n) {

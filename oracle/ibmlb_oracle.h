@@ -67,7 +67,9 @@ typedef struct ibo_params {
     double A0[9];
     int wall_bc;       /* 0: link-wise moving-wall bounce-back, walls at -1/2 and L-1/2;
                           1: wet-node velocity walls through the boundary nodes (Sec. 3.1,
-                          the Zou-He conditions in the 3D form of Hecht and Harting) */
+                          the Zou-He conditions in the 3D form of Hecht and Harting), edge
+                          and corner nodes carrying the wall velocity; 2: the same with the
+                          edge and corner rules as printed (no wall-velocity term) */
     int collision;     /* 0: BGK (the paper's single relaxation time); 1: MRT */
     double mrt_s[5];   /* MRT rates of the energy, energy-square, heat-flux, third-order
                           stress and third-order antisymmetric moments; 0 selects 1.19,

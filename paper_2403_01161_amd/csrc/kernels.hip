@@ -662,12 +662,26 @@ __global__ void k_clear(R* F, long long n) {
 //   one wall (Eq. ZH_bulk): rho = (rho0 + sum_{c.n=0} d + 2 sum_{c.n<0} d) / (1 - u_w.n),
 //     d_j = d_i - (2 - |t_i|) rho/6 c_i.u_w - rho/3 t_i.u_w + 1/2 sum_k d_k (t_i.c_k)(1 - |c_k.n|),
 //     t_i = c_i - (c_i.n) n;
-//   two walls (an edge, Eq. ZH_edges): d_j = d_i - 1/4 sum_k d_k (t_i.c_k)(1 - |c_k.n1|)(1 - |c_k.n2|)
-//     for the unknowns with a known opposite, then the buried links
-//     c = +-(n1 - n2) by Eq. (zh-buried-links-edges) and d_0 = 12 d_b;
-//   three walls (a corner): d_j = d_i for the unknowns with a known opposite
-//     (the text gives no rule for them), the six buried links
-//     c.(n1 + n2 + n3) = 0 by Eq. (zh-buried-links-corners) and d_0 = 12 d_b.
+//   two or three walls (an edge or a corner; inward normals n1, n2 (, n3)):
+//     the node takes density rho and momentum rho u_w, and the linear field's
+//     populations up to second order in A. An unknown j whose opposite i is
+//     known bounces back with the moving-wall term of Eq. (standard BB) for
+//     any link, d_j = d_i - 6 w_i rho c_i.u_w; at an edge it also takes the
+//     along-edge correction of Eq. (ZH_edges), with the sign of Eq. (ZH_bulk)'s
+//     and its velocity term: - rho/12 t_i.u_w
+//     + 1/4 sum_k d_k (t_i.c_k)(1 - |c_k.n1|)(1 - |c_k.n2|). The buried links
+//     (c.(n1 + n2 (+ n3)) = 0 with both c and -c unknown) and the rest
+//     population are reset (as Eqs. zh-buried-links-edges and -corners
+//     reset them) to the equilibrium at (rho, u_w) plus the linear field's
+//     non-equilibrium part: d_j = w_j (rho - rho0) + rho h_j,
+//     h_j = w_j (3 c.u + 9/2 (c.u)^2 - 3/2 u.u) - 3 tau w_j (c c - I/3):A.
+//     rho follows from sum_j f_j = rho: with D the sum of d over the known
+//     populations outside the bounce-back pairs plus twice d_i over the pairs,
+//     S6 = sum_pairs 6 w_i c_i.u_w, H = sum over the reset populations of h_j
+//     and W their weight, rho - rho0 = (D - rho0 S6 + rho0 H) / (1 + S6 - W - H).
+//     (As printed, the edge and corner rules carry no wall-velocity term and
+//     the edge correction has the opposite sign; a linear flow then stays
+//     wrong at first order in A.)
 // Thread t takes node t of the concatenated non-periodic face planes, the
 // lower in-plane axis fastest (so the y and z faces read whole x-rows); a
 // node on several faces is rebuilt by the first of them (order x-, x+, y-,
@@ -767,38 +781,59 @@ __global__ __launch_bounds__(256) void k_wet_walls(Geom g, LatticeParams lp, typ
             out[j] = d[i] - (R(2) - tn) * rho / R(6) * cu - rho / R(3) * tu + R(0.5) * corr;
         }
     } else {
+        // reset populations (buried links and rest): h_j, their weight W and sum H
+        const R uu = u0 * u0 + u1 * u1 + u2 * u2;
+        const double trA3 = (Arow[0] + Arow[4] + Arow[8]) / 3.0;
+        const R tau3 = R(3.0 * lp.tau);
+        R h[Q];
+        R W = R(0), H = R(0), S6 = R(0), D = R(0);
 #pragma unroll
-        for (int j = 1; j < Q; ++j) {
-            if (!unk(j) || unk(opp(j))) continue;
-            const int i = opp(j);
-            if (nw == 3) {
-                out[j] = d[i];
+        for (int j = 0; j < Q; ++j) {
+            const bool reset = j == 0 || (unk(j) && unk(opp(j)));
+            h[j] = R(0);
+            if (reset) {
+                const R cu = R(CX[j]) * u0 + R(CY[j]) * u1 + R(CZ[j]) * u2;
+                double cAc = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b2 = 0; b2 < 3; ++b2) {
+                        const int ca = a == 0 ? CX[j] : (a == 1 ? CY[j] : CZ[j]);
+                        const int cb = b2 == 0 ? CX[j] : (b2 == 1 ? CY[j] : CZ[j]);
+                        if (ca * cb) cAc += double(ca * cb) * Arow[3 * a + b2];
+                    }
+                h[j] = wgt<R>(j) * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu - tau3 * R(cAc - trA3));
+                W += wgt<R>(j);
+                H += h[j];
+            } else if (unk(j)) {
+                const int i = opp(j);
+                S6 += (R(6) * wgt<R>(i)) * (R(CX[i]) * u0 + R(CY[i]) * u1 + R(CZ[i]) * u2);
+                D += R(2) * d[i];
+            } else if (!unk(opp(j))) {
+                D += d[j];  // neither it nor its opposite crosses a wall
+            }
+        }
+        const R r0 = R(lp.rho0);
+        const R drho = (D - r0 * S6 + r0 * H) / (R(1) + S6 - W - H);
+        const R rho = r0 + drho;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            if (j == 0 || (unk(j) && unk(opp(j)))) {
+                out[j] = wgt<R>(j) * drho + rho * h[j];
                 continue;
             }
+            if (!unk(j)) continue;
+            const int i = opp(j);
+            const R cu = R(CX[i]) * u0 + R(CY[i]) * u1 + R(CZ[i]) * u2;
+            out[j] = d[i] - (R(6) * wgt<R>(i)) * rho * cu;
+            if (nw == 3) continue;
             const int tx = wx ? 0 : CX[i], ty = wy ? 0 : CY[i], tz = wz ? 0 : CZ[i];
+            const R tu = R(tx) * u0 + R(ty) * u1 + R(tz) * u2;
             R corr = R(0);
 #pragma unroll
             for (int k = 1; k < Q; ++k) corr += R(tang(k) * (tx * CX[k] + ty * CY[k] + tz * CZ[k])) * d[k];
-            out[j] = d[i] - R(0.25) * corr;
+            out[j] += R(0.25) * corr - rho / R(12) * tu;
         }
-        R fb = R(0);
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const int c2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
-            const R a2 = R(abs(cN(i))) / R(c2);
-            if (nw == 2) {
-                // |c.(n1 x n2)|: the component along the axis without a wall
-                const R a1 = R(abs(wx ? (wy ? CZ[i] : CY[i]) : CX[i]));
-                fb += out[i] * (R(1) - (R(1) - a1) * (R(1) - a2));
-            } else {
-                fb += out[i] * a2;
-            }
-        }
-        fb /= nw == 2 ? R(22) : R(18);
-#pragma unroll
-        for (int j = 1; j < Q; ++j)
-            if (unk(j) && unk(opp(j))) out[j] = fb;
-        out[0] = R(12) * fb;
     }
 #pragma unroll
     for (int j = 0; j < Q; ++j)

@@ -169,6 +169,35 @@ def test_domain_error_is_sticky(ib):
     assert e.value.code == ib.EDOMAIN
 
 
+@pytest.mark.parametrize("droplet", [False, True])
+def test_nonfinite_error_is_sticky(ib, droplet):
+    """A gradient far outside the lattice's range (wall speeds near 100 lattice
+    units per step) drives densities non-positive and then non-finite. The
+    kernels only raise the device flag and exit; ENONFINITE comes at the next
+    synchronising call and on every call after it, and a new handle runs."""
+    L = (12, 12, 12)
+    A = np.zeros(9)
+    A[1] = 20.0
+    kw = dict(tau=0.8)
+    if droplet:
+        V, T = icosphere(2, 2.5, box_center(L))
+        kw.update(sigma=0.01, radius=2.5, vertices=V, triangles=T)
+    print(f"case nonfinite droplet={droplet}", flush=True)
+    sim = ib.Simulation(L, storage="f32", **kw)
+    sim.step(A, 20)
+    with pytest.raises(ib.IbmLbError) as e:
+        sim.observables()
+    assert e.value.code == ib.ENONFINITE
+    with pytest.raises(ib.IbmLbError) as e:
+        sim.step(np.zeros(9), 1)
+    assert e.value.code == ib.ENONFINITE
+    sim.close()
+    fresh = ib.Simulation(L, storage="f32", **kw)
+    fresh.step(np.zeros(9), 5)
+    assert np.isfinite(fresh.observables()["mass"])
+    fresh.close()
+
+
 @pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
 def test_16bit_storage_soft_gate(ib, storage):
     L = (24, 24, 24)

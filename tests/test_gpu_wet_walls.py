@@ -1,8 +1,12 @@
-"""GPU wet-node velocity walls against the oracle's (the same rules: Zou-He
-faces with the transverse correction, the printed edge and corner rules with
-buried links): a droplet in FP64 and FP32, plane Couette flow exact at every
-node, every lattice variant bit-identical, and the limits (two copies,
-single droplets, no adjoint)."""
+"""GPU wet-node velocity walls against the oracle's (the same reading: Zou-He
+faces with the transverse correction of Eq. ZH_bulk; edge and corner nodes
+that hold their density, the wall velocity and the linear field's
+populations, with the correction of Eq. ZH_edges and reset buried links): a
+droplet in FP64 and FP32 in a box with walls on every face, the all-face
+linear flow and a Couette flow whose edges carry flow (node by node against
+the oracle, wall nodes exactly at the wall velocity), plane Couette flow
+exact at every node, every lattice variant bit-identical, and the limits
+(two copies, single droplets, no adjoint)."""
 import numpy as np
 import pytest
 
@@ -65,6 +69,36 @@ def test_wet_walls_couette_exact(ib):
     assert np.abs(u[0] - g * (y - (L[1] - 1) / 2)).max() <= 1e-14
     assert np.abs(u[1:]).max() <= 1e-14
     assert np.abs(rho - 1.0).max() <= 1e-13
+
+
+def _linear_field(L, A):
+    z, y, x = np.meshgrid(*(np.arange(n) for n in L[::-1]), indexing="ij")
+    X = np.stack([x, y, z]).astype(float) - ((np.array(L) - 1) / 2)[:, None, None, None]
+    return np.einsum("ab,b...->a...", np.asarray(A).reshape(3, 3), X), (x, y, z)
+
+
+@pytest.mark.parametrize("case", ["all_faces", "couette_edges"])
+def test_wet_walls_edges_and_corners_match_oracle(ib, case):
+    if case == "all_faces":
+        L, per, A = (12, 13, 14), (0, 0, 0), _traceless(2e-3, 6)
+    else:
+        L, per, A = (8, 12, 12), (1, 0, 0), np.array([0, 1e-3, 0, 0, 0, 0, 0, 0, 0.0])
+    print(f"case wet walls {case}", flush=True)
+    sim = ib.Simulation(L, 0.8, storage="f64", A0=A, periodic=per, walls="wet")
+    ref = oracle.Oracle(L, 0.8, A0=A, periodic=per, walls="wet")
+    sim.step(A, 150)
+    ref.step(A, 150)
+    rho_g, u_g = sim.fields()
+    rho_r, u_r = ref.fields()
+    sim.close()
+    ref.close()
+    uw, xyz = _linear_field(L, A)
+    nwall = sum(((c == 0) | (c == n - 1)).astype(int) * (1 - p) for c, n, p in zip(xyz, L, per))
+    du = np.abs(u_g - u_r).max() / np.abs(u_r).max()
+    drho = np.abs(rho_g - rho_r).max()
+    dw = max(np.abs(u_g - uw)[:, nwall == k].max() for k in range(1, 4) if (nwall == k).any())
+    print(f"  du {du:.2e}  drho {drho:.2e}  wall nodes vs u_w {dw:.2e}", flush=True)
+    assert du <= 1e-11 and drho <= 1e-13 and dw <= 1e-14
 
 
 def test_wet_walls_variants_bit_identical(ib):
