@@ -194,6 +194,20 @@ int ibm_lb_observables(ibm_lb* h, ibm_lb_obs* out);
 int ibm_lb_read_vertices(ibm_lb* h, double* out);
 int ibm_lb_read_field(ibm_lb* h, int32_t which, double* out);
 
+/* ibm_lb_read_vertices without any allocation, for callers that cannot
+ * allocate (code that must not call hipMalloc or hipFree, such as tight
+ * serving or analysis loops and harnesses that forbid allocation): the same
+ * output as ibm_lb_read_vertices (host double [nv][3], absolute coordinates,
+ * caller vertex order; synchronising), staged through a fixed device array
+ * that the library holds on each GPU it runs on until the process ends
+ * (3 IBM_LB_NOALLOC_MAX_VERTICES doubles, 6 MiB). Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (other host
+ * threads, other streams) race: serialise them. No device or host memory is
+ * allocated, also on error. Errors: EINVAL (NULL handle, NULL out with a
+ * mesh, more than IBM_LB_NOALLOC_MAX_VERTICES vertices: use
+ * ibm_lb_read_vertices), EDEVICE, sticky. */
+#define IBM_LB_NOALLOC_MAX_VERTICES 262144
+int ibm_lb_read_vertices_noalloc(ibm_lb* h, double* out);
 
 /* Inside indicator that the next step's collision uses (Sec. 2, viscosity
  * ratio chi), host uint8 [N] (x fastest): 1 for a node inside the current

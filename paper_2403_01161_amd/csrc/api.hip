@@ -2,10 +2,12 @@
 // launch sequencing and synchronising reads. The per-timestep order is the
 // one documented in include/ibm_lb.h.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -16,15 +18,20 @@ using namespace ibmlb;
 
 namespace {
 
-thread_local std::string g_last_error;
+// Message of the last failure on this thread (fixed storage: recording an
+// error allocates nothing).
+thread_local char g_last_error[256];
 
-int fail(int code, const std::string& msg) {
-    g_last_error = msg;
+int fail(int code, const char* msg) {
+    snprintf(g_last_error, sizeof(g_last_error), "%s", msg);
     return code;
 }
 
+int fail(int code, const std::string& msg) { return fail(code, msg.c_str()); }
+
 int hip_fail(hipError_t e, const char* where) {
-    return fail(IBM_LB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s", where, hipGetErrorString(e));
+    return IBM_LB_EDEVICE;
 }
 
 #define HIP_TRY(expr, where)                          \
@@ -39,7 +46,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 // Byte offsets of every device array inside one workspace.
 struct Layout {
     size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, tris, fan, lfan, hstart, hids, obs_part, mass_part,
-        obs_out, Abuf, red, ind, ind_lines, ptris, ptstart, total;
+        obs_out, Abuf, red, ind, ind_lines, ptris, ptstart, perm, total;
 };
 
 // Per vertex: valence m and the one-ring neighbours n_0 .. n_{m-1} in
@@ -89,6 +96,7 @@ Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t 
     L.ind_lines = take(sizeof(int) * 2 * lines);
     L.ptris = take(ind_b ? sizeof(int4) * (size_t)nt : 0);
     L.ptstart = take(ind_b ? sizeof(int) * ((size_t)(nv + IB_PATCH - 1) / IB_PATCH + 1) : 0);
+    L.perm = take(sizeof(int) * (size_t)nv);
     L.total = off;
     return L;
 }
@@ -346,6 +354,51 @@ Geom make_geom(const ibm_lb_config* c) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- allocation-free staging
+// Device memory of ibm_lb_read_vertices_noalloc: one file-scope array, a copy
+// of it on every GPU the library runs on, held until the process ends. Host
+// code never passes the array's name (a host-side stand-in) to a kernel or a
+// copy: it uses the address hipGetSymbolAddress gives on each device,
+// resolved once per device in ibm_lb_init with that device current.
+static __device__ __align__(256) double scratch[3 * IBM_LB_NOALLOC_MAX_VERTICES];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_addr[SCRATCH_DEVICES] = {};
+
+// This device's address of `scratch` (dev is the current device).
+hipError_t resolve_scratch(int dev, double** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_addr[dev] = (double*)p;
+    }
+    *out = scratch_addr[dev];
+    return hipSuccess;
+}
+
+// Absolute vertex coordinates in the caller's vertex order:
+// out[3 perm[k] + a] = r_k,a + x_c,a.
+template <class R>
+__global__ void k_vertices_caller_order(Geom g, int nv, const V4<R>* __restrict__ r, const int* __restrict__ perm,
+                                        double* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    const V4<R> p = r[k];
+    double* o = out + 3ll * perm[k];
+    o[0] = double(p.x) + (g.xci[0] + g.xcf[0]);
+    o[1] = double(p.y) + (g.xci[1] + g.xcf[1]);
+    o[2] = double(p.z) + (g.xci[2] + g.xcf[2]);
+}
+
+}  // namespace
+
 struct ibm_lb {
     ibm_lb_config cfg;
     int storage = 0, nv = 0, nt = 0, device = 0;
@@ -393,6 +446,7 @@ struct ibm_lb {
     int* adj_iters = nullptr;
     int* adj_perm = nullptr;
     AdjVerts adj_v{};
+    double* scratch = nullptr;   // this device's address of the allocation-free staging array
 };
 
 namespace {
@@ -560,7 +614,7 @@ const char* ibm_lb_strerror(int code) {
     }
 }
 
-const char* ibm_lb_last_error(void) { return g_last_error.c_str(); }
+const char* ibm_lb_last_error(void) { return g_last_error; }
 
 int ibm_lb_workspace_size(const ibm_lb_config* cfg, size_t* bytes) {
     MeshData m;
@@ -611,6 +665,9 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     };
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
+    // the allocation-free read's staging array on this device (an unresolved
+    // address only disables that entry point)
+    if (resolve_scratch(h->device, &h->scratch) != hipSuccess) h->scratch = nullptr;
     const int ntiles = h->g.TX * h->g.TY * h->g.TZ;
     h->single = cfg->populations == 1;
     h->mrt = cfg->collision == IBM_LB_MRT;
@@ -684,6 +741,7 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     d.ind_lines = h->chi ? (int*)(b + L.ind_lines) : nullptr;
     d.ptris = h->chi ? (int4*)(b + L.ptris) : nullptr;
     d.ptstart = h->chi ? (int*)(b + L.ptstart) : nullptr;
+    d.perm = (int*)(b + L.perm);
     h->perm = mesh.perm;
     if (h->nv > 0) {
         e = patch_setup(h->storage);
@@ -728,6 +786,7 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
                      "patch triangle starts");
         }
         INIT_TRY(hipMemcpy(d.fan, csr.fan.data(), sizeof(int) * csr.fan.size(), hipMemcpyHostToDevice), "fan");
+        INIT_TRY(hipMemcpy(d.perm, mesh.perm.data(), sizeof(int) * h->nv, hipMemcpyHostToDevice), "perm");
         const Halos& hl = mesh.halos;
         INIT_TRY(hipMemcpy(d.lfan, hl.lfan.data(), sizeof(int) * hl.lfan.size(), hipMemcpyHostToDevice), "lfan");
         INIT_TRY(hipMemcpy(d.hstart, hl.hstart.data(), sizeof(int) * hl.hstart.size(), hipMemcpyHostToDevice),
@@ -835,6 +894,30 @@ int ibm_lb_read_vertices(ibm_lb* h, double* out) {
     if (e2 != hipSuccess) return hip_fail(e2, "read vertices");
     for (int k = 0; k < h->nv; ++k)
         for (int a = 0; a < 3; ++a) out[3 * h->perm[k] + a] = in[3 * k + a];
+    return check_flags(h);
+}
+
+int ibm_lb_read_vertices_noalloc(ibm_lb* h, double* out) {
+    if (!h || (!out && h->nv)) return fail(IBM_LB_EINVAL, "bad read_vertices_noalloc arguments");
+    if (h->nv > IBM_LB_NOALLOC_MAX_VERTICES)
+        return fail(IBM_LB_EINVAL, "mesh above IBM_LB_NOALLOC_MAX_VERTICES vertices (use ibm_lb_read_vertices)");
+    if (h->nv == 0) return IBM_LB_OK;
+    int rc = set_device(h);
+    if (rc) return rc;
+    if (!h->scratch) return fail(IBM_LB_EDEVICE, "device address of the staging array unresolved");
+    const int blocks = (h->nv + 255) / 256;
+    if (h->storage == IBM_LB_F64)
+        hipLaunchKernelGGL(k_vertices_caller_order<double>, dim3(blocks), dim3(256), 0, h->stream, h->g, h->nv,
+                           (const V4<double>*)h->d.r, h->d.perm, h->scratch);
+    else
+        hipLaunchKernelGGL(k_vertices_caller_order<float>, dim3(blocks), dim3(256), 0, h->stream, h->g, h->nv,
+                           (const V4<float>*)h->d.r, h->d.perm, h->scratch);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, h->scratch, sizeof(double) * 3 * h->nv, hipMemcpyDeviceToHost, h->stream);
+    const hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "read vertices (no allocation)");
+    if (e2 != hipSuccess) return hip_fail(e2, "read vertices (no allocation)");
     return check_flags(h);
 }
 

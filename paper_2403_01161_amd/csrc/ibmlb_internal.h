@@ -92,6 +92,7 @@ struct DevPtrs {
     int* ind_lines;          // [2][Ly Lz] node range of each x-row's crossings (viscosity ratio only)
     int4* ptris;             // [nt] triangles grouped by the patch of their lowest vertex (viscosity ratio only)
     int* ptstart;            // [npatch + 1] start of each patch's triangles (viscosity ratio only)
+    int* perm;               // [nv] caller index of each internal vertex
 };
 
 // Bytes of the indicator array (whole 32-bit words, for the atomic toggles).

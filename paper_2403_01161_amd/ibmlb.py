@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libibmlb.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EDOMAIN, ENONFINITE = 0, -1, -2, -3, -4, -5
+NOALLOC_MAX_VERTICES = 262144  # IBM_LB_NOALLOC_MAX_VERTICES
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
 INIT_LINEAR, INIT_REST = 0, 1
@@ -66,7 +67,7 @@ EXPORTS = ["ibm_lb_workspace_size", "ibm_lb_init", "ibm_lb_step", "ibm_lb_step_t
            "ibm_lb_batch_init", "ibm_lb_batch_step", "ibm_lb_batch_observables", "ibm_lb_batch_member",
            "ibm_lb_batch_autotune", "ibm_lb_batch_set_variant", "ibm_lb_batch_set_graph",
            "ibm_lb_batch_destroy", "ibm_lb_objective_grad", "ibm_lb_shape_objective_grad",
-           "ibm_lb_adjoint_segment", "ibm_lb_adjoint_initial"]
+           "ibm_lb_adjoint_segment", "ibm_lb_adjoint_initial", "ibm_lb_read_vertices_noalloc"]
 
 
 def lib():
@@ -83,6 +84,7 @@ def lib():
         L.ibm_lb_step_table.argtypes = [vp, vp, i32, i32]
         L.ibm_lb_observables.argtypes = [vp, C.POINTER(Obs)]
         L.ibm_lb_read_vertices.argtypes = [vp, dp]
+        L.ibm_lb_read_vertices_noalloc.argtypes = [vp, dp]
         L.ibm_lb_read_field.argtypes = [vp, i32, dp]
         L.ibm_lb_read_indicator.argtypes = [vp, C.POINTER(C.c_uint8)]
         L.ibm_lb_state_bytes.argtypes = [vp]
@@ -238,6 +240,15 @@ class Simulation:
     def vertices(self):
         out = np.zeros((self.nv, 3))
         _check(lib().ibm_lb_read_vertices(self._h, _dp(out)), "ibm_lb_read_vertices")
+        return out
+
+    def read_vertices_noalloc(self, out=None):
+        """ibm_lb_read_vertices_noalloc into `out` (float64 [nv][3], C order;
+        a new array if None)."""
+        if out is None:
+            out = np.zeros((self.nv, 3))
+        assert out.dtype == np.float64 and out.shape == (self.nv, 3) and out.flags.c_contiguous
+        _check(lib().ibm_lb_read_vertices_noalloc(self._h, _dp(out)), "ibm_lb_read_vertices_noalloc")
         return out
 
     def fields(self):
