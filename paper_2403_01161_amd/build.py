@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libibmlb.so")
-SOURCES = ["kernels.hip", "ib_patch.hip", "indicator.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["lattice_f64.hip", "lattice_f32.hip", "lattice_f16.hip", "lattice_bf16.hip", "kernels.hip",
+           "ib_patch.hip", "indicator.hip", "adjoint.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

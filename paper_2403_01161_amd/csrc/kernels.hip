@@ -11,9 +11,22 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 
-#include "lattice_common.h"
+#include "lattice_kernels.h"
 
 namespace ibmlb {
+
+// The per-storage lattice launchers are compiled in lattice_{f64,f32,f16,bf16}.hip.
+#define IBMLB_LATTICE_EXTERN(C)                                                                                   \
+    extern template hipError_t launch_lattice_c<C>(const Geom&, const LatticeParams&, const DevPtrs&, int, bool,    \
+                                                   const double*, int, int, hipStream_t, hipEvent_t, hipEvent_t,     \
+                                                   const MrtRates*, const ChiRates*);                                \
+    extern template hipError_t launch_lattice_batch_c<C>(const LatDesc*, const int2*, const int*, const int*,       \
+                                                         const int*, int, long long, int, hipStream_t);
+IBMLB_LATTICE_EXTERN(SF64)
+IBMLB_LATTICE_EXTERN(SF32)
+IBMLB_LATTICE_EXTERN(SF16)
+IBMLB_LATTICE_EXTERN(SBF16)
+#undef IBMLB_LATTICE_EXTERN
 
 // ---------------------------------------------------------------- initial state
 template <class C>
@@ -47,530 +60,6 @@ __global__ __launch_bounds__(256) void k_init(Geom g, LatticeParams lp, typename
                     3.0 * lp.tau * w * lp.rho0 * (cAc - tr / 3.0);
         f[i * g.N + n] = enc<C>(typename C::real(dv), lp.scale);
     }
-}
-
-// ---------------------------------------------------------------- fused lattice step
-// One thread per node: load the 19 deviations (coalesced), form rho and the
-// half-force-corrected u, relax with BGK plus the Guo source, and push each
-// post-collision population to its neighbour. A population whose target lies
-// beyond a wall is reflected into the opposite slot of the same node with
-// the moving-wall term -2 w_i rho0 c_i.u_w / cs^2, u_w = A (x + c_i/2 - x_c).
-//
-// Two store layouts, chosen per configuration by the autotuner:
-//   * linear (k_lattice): work-group b owns nodes [b BS, (b+1) BS) and writes
-//     every population straight to its target; the ten populations that move
-//     along x land one element off the thread's own node, so their stores
-//     straddle cache lines shared with the neighbouring work-group. Optional
-//     XCD grouping gives each XCD a contiguous range of the lattice, so that
-//     such shared lines meet in one L2 (pays when the two population copies
-//     nearly fit the last-level cache);
-//   * rows (k_lattice_rows): a work-group owns whole x-rows; the populations
-//     that move along x are handed to their target thread through LDS, so
-//     every global store is at the storing thread's own x (row-aligned).
-//     Pays for footprints well beyond the last-level cache.
-// Further options: non-temporal population loads, non-temporal population
-// stores (rows) and the work-group size.
-
-// Rank of population i among the ten that move along x (their LDS slot).
-__host__ __device__ constexpr int xslot(int i) {
-    int k = 0;
-    for (int j = 0; j < i; ++j) k += CX[j] != 0 ? 1 : 0;
-    return k;
-}
-constexpr int NXMOVE = xslot(Q);
-
-// Block order grouped by XCD: consecutive work-groups are dispatched to the
-// eight XCDs in turn; this sends the first eighth of the lattice to XCD 0,
-// the next eighth to XCD 1, and so on (a tail of nb mod 8 blocks keeps its
-// place).
-__device__ inline unsigned xcd_order(unsigned b, unsigned nb) {
-    const unsigned per = nb >> 3;
-    return b < (per << 3) ? (b & 7u) * per + (b >> 3) : b;
-}
-
-template <bool NTS, class P, class V>
-__device__ __forceinline__ void put(P p, V v) {
-    if (NTS) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
-
-// Node coordinates from the linear index (32-bit division below 2^31 nodes).
-__device__ __forceinline__ void node_xyz(const Geom& g, long long n, int& x, int& y, int& z) {
-    const int LxLy = g.Lx * g.Ly;
-    int r;
-    if (g.N <= 0x7fffffffll) {
-        const int m = int(n);
-        z = m / LxLy;
-        r = m - z * LxLy;
-    } else {
-        z = int(n / LxLy);
-        r = int(n - (long long)z * LxLy);
-    }
-    y = r / g.Lx;
-    x = r - y * g.Lx;
-}
-
-// Target of population i pushed from node n = (x, y, z): n + c_i . (1, Lx,
-// Lx Ly), moved back across a periodic side; *wall when it leaves through a
-// wall instead.
-template <int I>
-__device__ __forceinline__ long long push_target(const Geom& g, long long n, int x, int y, int z, bool* wall) {
-    const long long LxLy = (long long)g.Lx * g.Ly;
-    long long t = n + CX[I] + (long long)CY[I] * g.Lx + (long long)CZ[I] * LxLy;
-    bool w = false;
-    if (CX[I] == 1 && x == g.Lx - 1) { if (g.px) t -= g.Lx; else w = true; }
-    if (CX[I] == -1 && x == 0) { if (g.px) t += g.Lx; else w = true; }
-    if (CY[I] == 1 && y == g.Ly - 1) { if (g.py) t -= LxLy; else w = true; }
-    if (CY[I] == -1 && y == 0) { if (g.py) t += LxLy; else w = true; }
-    if (CZ[I] == 1 && z == g.Lz - 1) { if (g.pz) t -= g.N; else w = true; }
-    if (CZ[I] == -1 && z == 0) { if (g.pz) t += g.N; else w = true; }
-    *wall = w;
-    return t;
-}
-
-// In-place streaming in two alternating steps (one population copy):
-//   even step: node x reads its own populations f_i(x) and stores its
-//     post-collision f*_i(x) in slot opp(i) of x itself, the moving-wall
-//     term already applied when the link leaves through a wall;
-//   odd step: node x reads f_i(x) = f*_i(x - c_i) from slot opp(i) of
-//     x - c_i (from slot i of x itself when x - c_i lies beyond a wall),
-//     and stores f*_i(x) in slot i of x + c_i (slot opp(i) of x, with the
-//     wall term, through a wall).
-// Each thread reads and writes the same set of locations in either step, so
-// no two threads touch one location. After an odd step the copy holds the
-// populations in natural order again; after an even step they are read with
-// the odd step's mapping (aa_settle).
-//
-// Where population i of node (x, y, z) is read in the odd step: *slot and
-// the node index.
-template <int I>
-__device__ __forceinline__ long long pull_source(const Geom& g, long long n, int x, int y, int z, int* slot) {
-    const long long LxLy = (long long)g.Lx * g.Ly;
-    long long s = n - CX[I] - (long long)CY[I] * g.Lx - (long long)CZ[I] * LxLy;
-    bool w = false;
-    if (CX[I] == -1 && x == g.Lx - 1) { if (g.px) s -= g.Lx; else w = true; }
-    if (CX[I] == 1 && x == 0) { if (g.px) s += g.Lx; else w = true; }
-    if (CY[I] == -1 && y == g.Ly - 1) { if (g.py) s -= LxLy; else w = true; }
-    if (CY[I] == 1 && y == 0) { if (g.py) s += LxLy; else w = true; }
-    if (CZ[I] == -1 && z == g.Lz - 1) { if (g.pz) s -= g.N; else w = true; }
-    if (CZ[I] == 1 && z == 0) { if (g.pz) s += g.N; else w = true; }
-    *slot = w ? I : opp(I);
-    return w ? n : s;
-}
-
-// ROWS: x-moving populations that stay in the box go to stage[xslot(i) T + t]
-// instead of global memory (t: the thread's slot, T: slots per plane).
-// The pointer parameters are plain pointers, or global-address-space
-// pointers where the caller read them from memory (so that the accesses
-// compile to global rather than flat instructions).
-// AREG: read the gradient row into registers before any store (for
-// pointers the compiler cannot tell apart from the stores' targets);
-// otherwise it is read where a reflection needs it.
-// AA: 0 two copies (read fin, push into fout), 1 even in-place step, 2 odd
-// in-place step (fin and fout the same copy).
-// MRT: the multiple-relaxation-time collision with the rates *mr instead of
-// BGK: f* = f - M^-1 [S M (f - f_eq) - (I - S/2) M G], G the Guo term without
-// its (1 - 1/(2 tau)) factor (with every rate 1/tau, the BGK step).
-// CHI: a node whose indicator byte ind[n] is set (inside the droplet) relaxes
-// with the rates *ch instead of lp's; the byte is cleared for the next
-// step's indicator. Only marked tiles hold inside nodes, so only they read it.
-template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, int AA, bool MRT = false, bool CHI = false,
-          class PIn, class POut, class PR, class PM, class PC, class PA>
-__device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp, PIn fin, POut fout, PR F,
-                                             PR U, PM mark, PC ctl, PA Arow,
-                                             const long long n, const int x, const int y, const int z,
-                                             typename C::store_t* stage, int t, int T,
-                                             const MrtRates* mr = nullptr, unsigned char* ind = nullptr,
-                                             const ChiRates* ch = nullptr) {
-    using R = typename C::real;
-    using S = typename C::store_t;
-    const long long N = g.N;
-
-    R d[Q];
-    static_for<0, Q>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        int slot = i;
-        const long long src = AA == 2 ? pull_source<i>(g, n, x, y, z, &slot) : n;
-        if (NTL) d[i] = dec<C>(__builtin_nontemporal_load(&fin[slot * N + src]), lp.inv_scale);
-        else d[i] = dec<C>(fin[slot * N + src], lp.inv_scale);
-    });
-
-    R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        drho += d[i];
-        if (CX[i] == 1) jx += d[i];
-        if (CX[i] == -1) jx -= d[i];
-        if (CY[i] == 1) jy += d[i];
-        if (CY[i] == -1) jy -= d[i];
-        if (CZ[i] == 1) jz += d[i];
-        if (CZ[i] == -1) jz -= d[i];
-    }
-
-    R Fx = R(0), Fy = R(0), Fz = R(0);
-    bool marked = false;
-    if (IB) {
-        const int tile = (x >> TILE_SHIFT) + g.TX * ((y >> TILE_SHIFT) + g.TY * (z >> TILE_SHIFT));
-        marked = mark[tile] == ctl->epoch;
-        if (marked) {
-            Fx = F[n];
-            Fy = F[N + n];
-            Fz = F[2 * N + n];
-            // leave the force field zero for the next step's spreading
-            F[n] = R(0);
-            F[N + n] = R(0);
-            F[2 * N + n] = R(0);
-        }
-    }
-    const R rho = R(lp.rho0) + drho;
-    const R inv = R(1) / rho;
-    const R ux = (jx + R(0.5) * Fx) * inv;
-    const R uy = (jy + R(0.5) * Fy) * inv;
-    const R uz = (jz + R(0.5) * Fz) * inv;
-    if (IB && marked) {
-        U[n] = ux;
-        U[N + n] = uy;
-        U[2 * N + n] = uz;
-    }
-    if (!(rho > R(0)) || !isfinite(ux + uy + uz)) atomicOr((int*)&ctl->flags, DFLAG_NONFINITE);
-
-    R omega = R(lp.omega), kg = R(lp.kguo);
-    const R rho0 = R(lp.rho0);
-    if constexpr (CHI) {
-        // inside nodes lie in marked tiles only (the indicator build marks them)
-        if (marked && ind[n]) {
-            omega = R(ch->omega_in);
-            kg = R(ch->kguo_in);
-            ind[n] = 0;
-        }
-    }
-    const R usq = ux * ux + uy * uy + uz * uz;
-    const R uF = ux * Fx + uy * Fy + uz * Fz;
-
-    // Moving-wall term of a reflected population: 6 w_i rho0 c_i . u_w with
-    // the wall velocity u_w = A (x - x_c + c_i / 2) at the link midpoint.
-    double Ad[9];  // uniform: scalar registers
-    if constexpr (AREG) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Ad[k] = Arow[k];
-    }
-    auto wall_term = [&](int i) {
-        R A[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) A[k] = R(AREG ? Ad[k] : double(Arow[k]));
-        const R xr = R(x - g.xci[0]) - R(g.xcf[0]);
-        const R yr = R(y - g.xci[1]) - R(g.xcf[1]);
-        const R zr = R(z - g.xci[2]) - R(g.xcf[2]);
-        const R cx = R(CX[i]), cy = R(CY[i]), cz = R(CZ[i]);
-        const R ax = A[0] * (xr + R(0.5) * cx) + A[1] * (yr + R(0.5) * cy) + A[2] * (zr + R(0.5) * cz);
-        const R ay = A[3] * (xr + R(0.5) * cx) + A[4] * (yr + R(0.5) * cy) + A[5] * (zr + R(0.5) * cz);
-        const R az = A[6] * (xr + R(0.5) * cx) + A[7] * (yr + R(0.5) * cy) + A[8] * (zr + R(0.5) * cz);
-        return R(6) * wgt<R>(i) * rho0 * (cx * ax + cy * ay + cz * az);
-    };
-
-    auto push = [&](auto ic, R val) {
-        constexpr int i = decltype(ic)::value;
-        bool wall;
-        const long long tg = push_target<i>(g, n, x, y, z, &wall);
-        if (AA == 1) {
-            put<NTS>(&fout[opp(i) * N + n], enc<C>(wall ? val - wall_term(i) : val, lp.scale));
-        } else if (!wall) {
-            if (ROWS && CX[i] != 0) stage[xslot(i) * T + t] = enc<C>(val, lp.scale);
-            else put<NTS>(&fout[i * N + tg], enc<C>(val, lp.scale));
-        } else {
-            put<NTS>(&fout[opp(i) * N + n], enc<C>(val - wall_term(i), lp.scale));
-        }
-    };
-
-    if constexpr (MRT) {
-        R nq[Q], gq[Q];
-        static_for<0, Q>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const R w = wgt<R>(i);
-            const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
-            const R cF = R(CX[i]) * Fx + R(CY[i]) * Fy + R(CZ[i]) * Fz;
-            nq[i] = d[i] - w * (drho + rho * (R(4.5) * cu * cu + R(3) * cu - R(1.5) * usq));
-            gq[i] = w * (R(3) * (cF - uF) + R(9) * cu * cF);
-        });
-        static_for<0, Q>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            R mn = R(0), mg = R(0);
-            static_for<0, Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                constexpr int m = mrt_m(k, i);
-                if constexpr (m != 0) {
-                    mn += R(m) * nq[i];
-                    mg += R(m) * gq[i];
-                }
-            });
-            const R sk = R(mr->s[k]);
-            const R r = (sk * mn - (R(1) - R(0.5) * sk) * mg) * (R(1) / R(mrt_norm2(k)));
-            static_for<0, Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                constexpr int m = mrt_m(k, i);
-                if constexpr (m != 0) d[i] -= R(m) * r;
-            });
-        });
-        put<NTS>(&fout[n], enc<C>(d[0], lp.scale));
-        static_for<1, Q>([&](auto ic) { push(ic, d[decltype(ic)::value]); });
-        return;
-    }
-    {   // rest population
-        const R w = wgt<R>(0);
-        const R deq = w * (drho + rho * (R(-1.5) * usq));
-        const R S0 = kg * w * (R(-3) * uF);
-        put<NTS>(&fout[n], enc<C>(d[0] - omega * (d[0] - deq) + S0, lp.scale));
-    }
-    static_for<1, 10>([&](auto pc) {
-        constexpr int p = decltype(pc)::value;
-        constexpr int i = 2 * p - 1, j = 2 * p;
-        const R w = wgt<R>(i);
-        const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
-        const R cF = R(CX[i]) * Fx + R(CY[i]) * Fy + R(CZ[i]) * Fz;
-        const R sym = w * (drho + rho * (R(4.5) * cu * cu - R(1.5) * usq));
-        const R anti = w * rho * R(3) * cu;
-        const R Ssym = kg * w * (R(9) * cu * cF - R(3) * uF);
-        const R Santi = kg * w * R(3) * cF;
-        push(std::integral_constant<int, i>{}, d[i] - omega * (d[i] - (sym + anti)) + Ssym + Santi);
-        push(std::integral_constant<int, j>{}, d[j] - omega * (d[j] - (sym - anti)) + Ssym - Santi);
-    });
-}
-
-// Second half of the row layout: thread t (node n, coordinates x, y, z)
-// stores, at its own x, every x-moving population arriving from x - c_x in
-// its row (x - c_x wrapped on a periodic axis; nothing arrives through a
-// wall, and nothing whose row shift crosses a wall, both having been
-// reflected at the source).
-template <class C, bool NTS, class POut>
-__device__ __forceinline__ void rows_receive(const Geom& g, POut fout, const typename C::store_t* stage, long long n,
-                                             int x, int y, int z, int t, int T) {
-    const long long N = g.N;
-    const long long LxLy = (long long)g.Lx * g.Ly;
-    const int row0 = t - x;  // slot of x = 0 in this row
-    static_for<1, Q>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        if (CX[i] == 0) return;
-        int xs = x - CX[i];
-        if (xs < 0 || xs >= g.Lx) {
-            if (!g.px) return;
-            xs = wrap(xs, g.Lx);
-        }
-        long long tg = n + (long long)CY[i] * g.Lx + (long long)CZ[i] * LxLy;
-        if (CY[i] == 1 && y == g.Ly - 1) { if (!g.py) return; tg -= LxLy; }
-        if (CY[i] == -1 && y == 0) { if (!g.py) return; tg += LxLy; }
-        if (CZ[i] == 1 && z == g.Lz - 1) { if (!g.pz) return; tg -= N; }
-        if (CZ[i] == -1 && z == 0) { if (!g.pz) return; tg += N; }
-        put<NTS>(&fout[i * N + tg], stage[xslot(i) * T + row0 + xs]);
-    });
-}
-
-template <class C, bool IB, bool NTL, int BS>
-__global__ __launch_bounds__(BS) void k_lattice(Geom g, LatticeParams lp,
-                                                 const typename C::store_t* __restrict__ fin,
-                                                 typename C::store_t* __restrict__ fout,
-                                                 typename C::real* __restrict__ F,
-                                                 typename C::real* __restrict__ U,
-                                                 const int* __restrict__ mark, Ctl* ctl,
-                                                 const double* __restrict__ Arow, int xcd) {
-    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
-    const long long n = (long long)b * BS + threadIdx.x;
-    if (n >= g.N) return;
-    int x, y, z;
-    node_xyz(g, n, x, y, z);
-    lattice_node<C, IB, NTL, false, false, false, 0>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0,
-                                                  0);
-}
-
-// MRT collision, linear layout with two copies.
-template <class C, bool IB, bool NTL, int BS>
-__global__ __launch_bounds__(BS) void k_lattice_mrt(Geom g, LatticeParams lp,
-                                                     const typename C::store_t* __restrict__ fin,
-                                                     typename C::store_t* __restrict__ fout,
-                                                     typename C::real* __restrict__ F,
-                                                     typename C::real* __restrict__ U,
-                                                     const int* __restrict__ mark, Ctl* ctl,
-                                                     const double* __restrict__ Arow, int xcd, MrtRates mr) {
-    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
-    const long long n = (long long)b * BS + threadIdx.x;
-    if (n >= g.N) return;
-    int x, y, z;
-    node_xyz(g, n, x, y, z);
-    lattice_node<C, IB, NTL, false, false, false, 0, true>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z,
-                                                        nullptr, 0, 0, &mr);
-}
-
-// Viscosity ratio: BGK with the inner rates on the nodes the indicator marks,
-// linear layout with two copies.
-template <class C, bool IB, bool NTL, int BS>
-__global__ __launch_bounds__(BS) void k_lattice_chi(Geom g, LatticeParams lp,
-                                                     const typename C::store_t* __restrict__ fin,
-                                                     typename C::store_t* __restrict__ fout,
-                                                     typename C::real* __restrict__ F,
-                                                     typename C::real* __restrict__ U,
-                                                     const int* __restrict__ mark, Ctl* ctl,
-                                                     const double* __restrict__ Arow, int xcd,
-                                                     unsigned char* __restrict__ ind, ChiRates ch) {
-    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
-    const long long n = (long long)b * BS + threadIdx.x;
-    if (n >= g.N) return;
-    int x, y, z;
-    node_xyz(g, n, x, y, z);
-    lattice_node<C, IB, NTL, false, false, false, 0, false, true>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y,
-                                                               z, nullptr, 0, 0, nullptr, ind, &ch);
-}
-
-// In-place (single-copy) form, linear layout: ODD selects the step parity.
-// CHI: the viscosity ratio's inner rates on the nodes the indicator marks.
-template <class C, bool IB, bool NTL, int BS, bool ODD, bool CHI = false>
-__global__ __launch_bounds__(BS) void k_lattice_aa(Geom g, LatticeParams lp, typename C::store_t* f,
-                                                    typename C::real* __restrict__ F,
-                                                    typename C::real* __restrict__ U,
-                                                    const int* __restrict__ mark, Ctl* ctl,
-                                                    const double* __restrict__ Arow, int xcd,
-                                                    unsigned char* __restrict__ ind = nullptr,
-                                                    ChiRates ch = ChiRates{}) {
-    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
-    const long long n = (long long)b * BS + threadIdx.x;
-    if (n >= g.N) return;
-    int x, y, z;
-    node_xyz(g, n, x, y, z);
-    lattice_node<C, IB, NTL, false, false, false, ODD ? 2 : 1, false, CHI>(
-        g, lp, (const typename C::store_t*)f, f, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0, 0, nullptr, ind, &ch);
-}
-
-// After an even in-place step, back to natural order in place. In the odd
-// mapping f_i(x) sits in slot opp(i) of x - c_i, and slot i of x holds
-// f_opp(i)(x - c_i): the two swap. Node x swaps this pair for the directions
-// of odd index (each pair of opposite directions is (2p - 1, 2p)), so every
-// location belongs to one pair handled by one thread; where x - c_i lies
-// beyond a wall both populations are already in place.
-template <class C>
-__global__ __launch_bounds__(256) void k_aa_settle(Geom g, typename C::store_t* __restrict__ f) {
-    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (n >= g.N) return;
-    int x, y, z;
-    node_xyz(g, n, x, y, z);
-    const long long N = g.N;
-    static_for<1, Q>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        if constexpr (i & 1) {
-            static_assert(opp(i) == i + 1, "opposite directions are paired (2p - 1, 2p)");
-            int slot;
-            const long long src = pull_source<i>(g, n, x, y, z, &slot);
-            if (slot != i) {
-                const typename C::store_t a = f[i * N + n], b = f[opp(i) * N + src];
-                f[i * N + n] = b;
-                f[opp(i) * N + src] = a;
-            }
-        }
-    });
-}
-
-// Row layout: `rows` whole x-rows per work-group (blockDim = rows * Lx <= 512).
-// CHI: the viscosity ratio's inner rates on the nodes the indicator marks;
-// MRT: the multiple-relaxation-time collision with the rates mr.
-constexpr int ROWS_MAX_T = 512;
-
-template <class C, bool IB, bool NTL, bool NTS, bool CHI = false, bool MRT = false>
-__global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticeParams lp,
-                                                             const typename C::store_t* __restrict__ fin,
-                                                             typename C::store_t* __restrict__ fout,
-                                                             typename C::real* __restrict__ F,
-                                                             typename C::real* __restrict__ U,
-                                                             const int* __restrict__ mark, Ctl* ctl,
-                                                             const double* __restrict__ Arow, int rows,
-                                                             unsigned char* __restrict__ ind = nullptr,
-                                                             ChiRates ch = ChiRates{}, MrtRates mr = MrtRates{}) {
-    using S = typename C::store_t;
-    extern __shared__ __align__(16) unsigned char dyn[];
-    S* stage = reinterpret_cast<S*>(dyn);
-    const int T = rows * g.Lx;
-    const int t = threadIdx.x;
-    // rows of Lx nodes: row index from the work-group, x from the thread
-    const int rl = t / g.Lx;
-    const int x = t - rl * g.Lx;
-    const int row = int(blockIdx.x) * rows + rl;
-    const int z = row / g.Ly, y = row - z * g.Ly;
-    const long long n = (long long)row * g.Lx + x;
-    const bool act = n < g.N;
-    if (act)
-        lattice_node<C, IB, NTL, true, NTS, false, 0, MRT, CHI>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y,
-                                                             z, stage, t, T, &mr, ind, &ch);
-    __syncthreads();
-    if (act) rows_receive<C, NTS>(g, fout, stage, n, x, y, z, t, T);
-}
-
-// Ensemble forms: one launch covers every member's lattice; work-group b
-// updates block map[b].y of member map[b].x (linear: BS nodes per block;
-// rows: floor(blockDim / Lx) whole rows of that member per block).
-template <class T>
-using gptr = __attribute__((address_space(1))) T*;
-
-// A member's descriptor in registers, its pointers in the global address
-// space.
-template <class C>
-struct MemberView {
-    using S = typename C::store_t;
-    using R = typename C::real;
-    Geom g;
-    LatticeParams lp;
-    gptr<const S> fin;
-    gptr<S> fout;
-    gptr<R> F, U;
-    gptr<const int> mark;
-    gptr<Ctl> ctl;
-    gptr<const double> A;
-    __device__ MemberView(const LatDesc& D, int cur)
-        : g(D.g), lp(D.lp), fin((gptr<const S>)D.f[cur]), fout((gptr<S>)D.f[cur ^ 1]), F((gptr<R>)D.F),
-          U((gptr<R>)D.u), mark((gptr<const int>)D.mark), ctl((gptr<Ctl>)D.ctl), A((gptr<const double>)D.A) {}
-};
-
-// Waves per SIMD the batched kernel is compiled for: six fit the 16- and
-// 32-bit forms in 80 registers without spills; FP64 takes what it needs.
-template <class C>
-constexpr int batch_waves = 6;
-template <>
-constexpr int batch_waves<SF64> = 1;
-
-// IB: every member the launch covers carries a droplet, or none does.
-template <class C, bool IB, bool NTL, int BS>
-__global__ __launch_bounds__(BS, batch_waves<C>) void k_lattice_batch(const LatDesc* __restrict__ desc, const int2* __restrict__ map,
-                                                       int cur, long long arow, int xcd) {
-    const int2 e = map[xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x];
-    const MemberView<C> M(desc[e.x], cur);
-    const long long n = (long long)e.y * BS + threadIdx.x;
-    if (n >= M.g.N) return;
-    int x, y, z;
-    node_xyz(M.g, n, x, y, z);
-    const gptr<const double> Arow = M.A + arow;
-    lattice_node<C, IB, NTL, false, false, true, 0>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
-                                           nullptr, 0, 0);
-}
-
-template <class C, bool IB, bool NTL, bool NTS>
-__global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows_batch(const LatDesc* __restrict__ desc,
-                                                                   const int2* __restrict__ map, int cur,
-                                                                   long long arow) {
-    using S = typename C::store_t;
-    extern __shared__ __align__(16) unsigned char dyn[];
-    S* stage = reinterpret_cast<S*>(dyn);
-    const int2 e = map[blockIdx.x];
-    const MemberView<C> M(desc[e.x], cur);
-    const int rows = int(blockDim.x) / M.g.Lx;
-    const int T = rows * M.g.Lx;
-    const int t = threadIdx.x;
-    const int rl = t / M.g.Lx;
-    const int x = t - rl * M.g.Lx;
-    const int row = e.y * rows + rl;
-    const int z = row / M.g.Ly, y = row - z * M.g.Ly;
-    const long long n = (long long)row * M.g.Lx + x;
-    const bool act = t < T && n < M.g.N;
-    const gptr<const double> Arow = M.A + arow;
-    if (act)
-        lattice_node<C, IB, NTL, true, NTS, true, 0>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
-                                            stage, t, T);
-    __syncthreads();
-    if (act) rows_receive<C, NTS>(M.g, M.fout, stage, n, x, y, z, t, T);
 }
 
 // Diagnostic moments: rho and u (with F/2) of the current populations; the
@@ -977,33 +466,59 @@ __device__ void jacobi3(const double S[9], double ev[3], double vec[9]) {
 // 4..12 S, 13..15 eigval, 16..24 eigvec, 25 D, 26 beta, 27 theta_deg,
 // 28 flags, 29 sum of deviations, 30..32 momentum, 33 iters, 34 cap hits,
 // 35 smallest triangle angle (degrees), 36 shortest edge, 37 longest edge.
-__global__ void k_obs_final(int nblocks, const double* part, int mblocks, const double* mpart,
-                            const double* Arow, double radius, int has_mesh, Ctl* ctl,
-                            double* out) {
-    if (threadIdx.x != 0) return;
-    double m[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = 0; b < mblocks; ++b)
-        for (int k = 0; k < 4; ++k) m[k] += mpart[4 * b + k];
+// The block partials are reduced by 256 threads in a fixed order (thread t
+// takes partials t, t + 256, ... in turn, then a fixed pairwise tree in LDS),
+// so the result is the same on every run; thread 0 finishes.
+constexpr int OBS_FINAL_THREADS = 256;
+__global__ __launch_bounds__(OBS_FINAL_THREADS) void k_obs_final(int nblocks, const double* part, int mblocks,
+                                                                 const double* mpart, const double* Arow,
+                                                                 double radius, int has_mesh, Ctl* ctl,
+                                                                 double* out) {
+    // slots 0-3 mass and momentum, 4-13 volume moments, 14 smallest angle,
+    // 15 shortest edge, 16 longest edge
+    constexpr int NS = 17;
+    __shared__ double red[NS][OBS_FINAL_THREADS];
+    const int t = threadIdx.x;
+    double v[NS];
+    for (int k = 0; k < 14; ++k) v[k] = 0.0;
+    v[14] = __builtin_inf();
+    v[15] = __builtin_inf();
+    v[16] = 0.0;
+    for (int b = t; b < mblocks; b += OBS_FINAL_THREADS)
+        for (int k = 0; k < 4; ++k) v[k] += mpart[4 * b + k];
+    if (has_mesh)
+        for (int b = t; b < nblocks; b += OBS_FINAL_THREADS) {
+            for (int k = 0; k < 10; ++k) v[4 + k] += part[16 * b + k];
+            v[14] = fmin(v[14], part[16 * b + 10]);
+            v[15] = fmin(v[15], part[16 * b + 11]);
+            v[16] = fmax(v[16], part[16 * b + 12]);
+        }
+    for (int k = 0; k < NS; ++k) red[k][t] = v[k];
+    __syncthreads();
+    for (int h = OBS_FINAL_THREADS / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            for (int k = 0; k < 14; ++k) red[k][t] += red[k][t + h];
+            red[14][t] = fmin(red[14][t], red[14][t + h]);
+            red[15][t] = fmin(red[15][t], red[15][t + h]);
+            red[16][t] = fmax(red[16][t], red[16][t + h]);
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
     for (int k = 0; k < OBS_OUT_N; ++k) out[k] = 0.0;
-    out[29] = m[0];
-    out[30] = m[1];
-    out[31] = m[2];
-    out[32] = m[3];
+    out[29] = red[0][0];
+    out[30] = red[1][0];
+    out[31] = red[2][0];
+    out[32] = red[3][0];
     out[33] = ctl->iters;
     out[34] = ctl->cap_hits;
     ctl->cap_hits = 0;
     if (!has_mesh) return;
-    double s[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double amin = __builtin_inf(), emin = __builtin_inf(), emax = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-        for (int k = 0; k < 10; ++k) s[k] += part[16 * b + k];
-        amin = fmin(amin, part[16 * b + 10]);
-        emin = fmin(emin, part[16 * b + 11]);
-        emax = fmax(emax, part[16 * b + 12]);
-    }
-    out[35] = amin * (180.0 / 3.14159265358979323846);
-    out[36] = emin;
-    out[37] = emax;
+    double s[10];
+    for (int k = 0; k < 10; ++k) s[k] = red[4 + k][0];
+    out[35] = red[14][0] * (180.0 / 3.14159265358979323846);
+    out[36] = red[15][0];
+    out[37] = red[16][0];
     const double V = s[0];
     const double xb[3] = {s[1] / V, s[2] / V, s[3] / V};
     const double M[9] = {s[4], s[7], s[8], s[7], s[5], s[9], s[8], s[9], s[6]};
@@ -1075,15 +590,7 @@ size_t storage_bytes(int storage) {
 }
 size_t real_bytes(int storage) { return storage == IBM_LB_F64 ? 8 : 4; }
 
-static inline unsigned blocks_for(long long n, int bs) { return unsigned((n + bs - 1) / bs); }
 
-#define DISPATCH_STORAGE(storage, C, ...)                  \
-    switch (storage) {                                     \
-        case IBM_LB_F64: { using C = SF64; __VA_ARGS__; break; }  \
-        case IBM_LB_F32: { using C = SF32; __VA_ARGS__; break; }  \
-        case IBM_LB_F16DEV: { using C = SF16; __VA_ARGS__; break; } \
-        default: { using C = SBF16; __VA_ARGS__; break; }  \
-    }
 
 hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                        const double* A0, int rest, hipStream_t s) {
@@ -1096,98 +603,12 @@ hipError_t launch_init(int storage, const Geom& g, const LatticeParams& lp, cons
 
 // Launched with hipExtLaunchKernelGGL so that optional timing events are
 // stamped by the dispatch itself (no separate event packets around it).
-template <class C, bool IB, bool NTL, int BS>
-static void lattice_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                           int xcd, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    using R = typename C::real;
-    using S = typename C::store_t;
-    hipExtLaunchKernelGGL((k_lattice<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1, 0, g, lp,
-                          (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row,
-                          xcd);
-}
-
-template <class C, bool IB, bool NTL, int BS>
-static void mrt_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                       int xcd, const MrtRates& mr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    using R = typename C::real;
-    using S = typename C::store_t;
-    hipExtLaunchKernelGGL((k_lattice_mrt<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1, 0, g,
-                          lp, (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl,
-                          A_row, xcd, mr);
-}
-
-template <class C, bool IB, bool NTL>
-static void launch_mrt_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                         const double* A_row, const MrtRates& mr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const int xcd = (variant & VAR_X) ? 1 : 0;
-    switch ((variant >> 1) & 3) {
-        case 0: mrt_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
-        case 1: mrt_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
-        case 2: mrt_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
-        default: mrt_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
-    }
-}
-
-template <class C, bool IB, bool NTL, int BS>
-static void chi_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                       int xcd, const ChiRates& ch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    using R = typename C::real;
-    using S = typename C::store_t;
-    hipExtLaunchKernelGGL((k_lattice_chi<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1, 0, g,
-                          lp, (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl,
-                          A_row, xcd, d.ind, ch);
-}
-
-template <class C, bool IB, bool NTL>
-static void launch_chi_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                         const double* A_row, const ChiRates& ch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const int xcd = (variant & VAR_X) ? 1 : 0;
-    switch ((variant >> 1) & 3) {
-        case 0: chi_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, ch, s, e0, e1); break;
-        case 1: chi_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, ch, s, e0, e1); break;
-        case 2: chi_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, ch, s, e0, e1); break;
-        default: chi_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, ch, s, e0, e1); break;
-    }
-}
-
-template <class C, bool IB, bool NTL, int BS, bool CHI = false>
-static void aa_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row, int xcd,
-                      int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr) {
-    using R = typename C::real;
-    using S = typename C::store_t;
-    unsigned char* ind = CHI ? d.ind : nullptr;
-    const ChiRates cr = ch ? *ch : ChiRates{};
-    if (parity)
-        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, true, CHI>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0,
-                              e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, xcd,
-                              ind, cr);
-    else
-        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, false, CHI>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s,
-                              e0, e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row,
-                              xcd, ind, cr);
-}
-
 hipError_t launch_aa_settle(int storage, const Geom& g, const DevPtrs& d, int cur, hipStream_t s) {
     DISPATCH_STORAGE(storage, C, {
         using S = typename C::store_t;
         hipLaunchKernelGGL(k_aa_settle<C>, dim3(blocks_for(g.N, 256)), dim3(256), 0, s, g, (S*)d.f[cur]);
     });
     return hipGetLastError();
-}
-
-template <class C, bool IB, bool NTL, bool NTS, bool CHI = false, bool MRT = false>
-static void rows_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                        int rows, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr,
-                        const MrtRates* mr = nullptr) {
-    using R = typename C::real;
-    using S = typename C::store_t;
-    const int T = rows * g.Lx;
-    const long long nrows = (long long)g.Ly * g.Lz;
-    const unsigned nb = unsigned((nrows + rows - 1) / rows);
-    hipExtLaunchKernelGGL((k_lattice_rows<C, IB, NTL, NTS, CHI, MRT>), dim3(nb), dim3(T),
-                          uint32_t(NXMOVE * T * sizeof(S)), s, e0, e1, 0, g, lp, (const S*)d.f[cur],
-                          (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, rows,
-                          CHI ? d.ind : nullptr, ch ? *ch : ChiRates{}, mr ? *mr : MrtRates{});
 }
 
 int lattice_rows_per_block(int variant, int Lx) {
@@ -1204,200 +625,31 @@ int lattice_variant_ok(int variant, const Geom& g) {
     return 1;
 }
 
-template <class C, bool IB, bool NTL>
-static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                             const double* A_row, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (variant & VAR_AA) {
-        const int xcd = (variant & VAR_X) ? 1 : 0;
-        switch ((variant >> 1) & 3) {
-            case 0: aa_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
-            case 1: aa_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
-            case 2: aa_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
-            default: aa_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
-        }
-        return;
-    }
-    if (variant & VAR_ROWS) {
-        const int rows = lattice_rows_per_block(variant, g.Lx);
-        if (variant & VAR_X) rows_launch<C, IB, NTL, true>(g, lp, d, cur, A_row, rows, s, e0, e1);
-        else rows_launch<C, IB, NTL, false>(g, lp, d, cur, A_row, rows, s, e0, e1);
-        return;
-    }
-    const int xcd = (variant & VAR_X) ? 1 : 0;
-    switch ((variant >> 1) & 3) {
-        case 0: lattice_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
-        case 1: lattice_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
-        case 2: lattice_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
-        default: lattice_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
-    }
-}
-
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
                           hipEvent_t e0, hipEvent_t e1, const MrtRates* mrt, const ChiRates* chi) {
     if (!lattice_variant_ok(variant, g)) return hipErrorInvalidValue;
     if (mrt && chi) return hipErrorInvalidValue;
-    if (chi) {
-        // the indicator exists only with a droplet
-        if (!ib || !d.ind) return hipErrorInvalidValue;
-        if (variant & VAR_AA) {
-            const int xcd = (variant & VAR_X) ? 1 : 0;
-#define CHI_AA(NTLV)                                                                                               \
-    do {                                                                                                           \
-        switch ((variant >> 1) & 3) {                                                                              \
-            case 0: aa_launch<C, true, NTLV, LAT_BS[0], true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, chi); break; \
-            case 1: aa_launch<C, true, NTLV, LAT_BS[1], true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, chi); break; \
-            case 2: aa_launch<C, true, NTLV, LAT_BS[2], true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, chi); break; \
-            default: aa_launch<C, true, NTLV, LAT_BS[3], true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, chi); break; \
-        }                                                                                                          \
-    } while (0)
-            DISPATCH_STORAGE(storage, C, {
-                if (variant & 1) CHI_AA(true);
-                else CHI_AA(false);
-            });
-#undef CHI_AA
-            return hipGetLastError();
-        }
-        if (variant & VAR_ROWS) {
-            const int rows = lattice_rows_per_block(variant, g.Lx);
-            const bool nts = (variant & VAR_X) != 0;
-            DISPATCH_STORAGE(storage, C, {
-                if (variant & 1) {
-                    if (nts) rows_launch<C, true, true, true, true>(g, lp, d, cur, A_row, rows, s, e0, e1, chi);
-                    else rows_launch<C, true, true, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, chi);
-                } else {
-                    if (nts) rows_launch<C, true, false, true, true>(g, lp, d, cur, A_row, rows, s, e0, e1, chi);
-                    else rows_launch<C, true, false, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, chi);
-                }
-            });
-            return hipGetLastError();
-        }
-        DISPATCH_STORAGE(storage, C, {
-            if (variant & 1) launch_chi_v<C, true, true>(variant, g, lp, d, cur, A_row, *chi, s, e0, e1);
-            else launch_chi_v<C, true, false>(variant, g, lp, d, cur, A_row, *chi, s, e0, e1);
-        });
-        return hipGetLastError();
+    switch (storage) {
+        case IBM_LB_F64: return launch_lattice_c<SF64>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi);
+        case IBM_LB_F32: return launch_lattice_c<SF32>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi);
+        case IBM_LB_F16DEV:
+            return launch_lattice_c<SF16>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi);
+        default: return launch_lattice_c<SBF16>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi);
     }
-    if (mrt) {
-        if (variant & VAR_AA) return hipErrorInvalidValue;
-        if (variant & VAR_ROWS) {
-            const int rows = lattice_rows_per_block(variant, g.Lx);
-            const bool nts = (variant & VAR_X) != 0;
-#define MRT_ROWS(IBV, NTLV)                                                                                   \
-    do {                                                                                                      \
-        if (nts) rows_launch<C, IBV, NTLV, true, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, mrt); \
-        else rows_launch<C, IBV, NTLV, false, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, mrt);  \
-    } while (0)
-            DISPATCH_STORAGE(storage, C, {
-                if (ib) {
-                    if (variant & 1) MRT_ROWS(true, true);
-                    else MRT_ROWS(true, false);
-                } else {
-                    if (variant & 1) MRT_ROWS(false, true);
-                    else MRT_ROWS(false, false);
-                }
-            });
-#undef MRT_ROWS
-            return hipGetLastError();
-        }
-        DISPATCH_STORAGE(storage, C, {
-            if (ib) {
-                if (variant & 1) launch_mrt_v<C, true, true>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
-                else launch_mrt_v<C, true, false>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
-            } else {
-                if (variant & 1) launch_mrt_v<C, false, true>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
-                else launch_mrt_v<C, false, false>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
-            }
-        });
-        return hipGetLastError();
-    }
-    DISPATCH_STORAGE(storage, C, {
-        if (ib) {
-            if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
-            else launch_lattice_v<C, true, false>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
-        } else {
-            if (variant & 1) launch_lattice_v<C, false, true>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
-            else launch_lattice_v<C, false, false>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
-        }
-    });
-    return hipGetLastError();
-}
-
-template <class C, bool IB, bool NTL>
-static void launch_batch_v(int bsi, const LatDesc* desc, const int2* map, int nblocks, int cur, long long step,
-                           int xcd, hipStream_t s) {
-    if (nblocks <= 0) return;
-    switch (bsi) {
-        case 0:
-            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[0]>), dim3(nblocks), dim3(LAT_BS[0]), 0, s, desc,
-                               map, cur, step, xcd);
-            break;
-        case 1:
-            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[1]>), dim3(nblocks), dim3(LAT_BS[1]), 0, s, desc,
-                               map, cur, step, xcd);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[2]>), dim3(nblocks), dim3(LAT_BS[2]), 0, s, desc,
-                               map, cur, step, xcd);
-            break;
-        default:
-            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[3]>), dim3(nblocks), dim3(LAT_BS[3]), 0, s, desc,
-                               map, cur, step, xcd);
-            break;
-    }
-}
-
-template <class C, bool IB, bool NTL, bool NTS>
-static void launch_rows_batch(int T, const LatDesc* desc, const int2* map, int nblocks, int cur, long long step,
-                              hipStream_t s) {
-    if (nblocks <= 0) return;
-    using S = typename C::store_t;
-    hipLaunchKernelGGL((k_lattice_rows_batch<C, IB, NTL, NTS>), dim3(nblocks), dim3(T),
-                       size_t(NXMOVE) * T * sizeof(S), s, desc, map, cur, step);
-}
-
-template <class C, bool NTL, bool NTS>
-static void launch_rows_both(int T, const LatDesc* desc, const int2* map, int nblocks, int nib, int cur,
-                             long long step, hipStream_t s) {
-    launch_rows_batch<C, true, NTL, NTS>(T, desc, map, nib, cur, step, s);
-    launch_rows_batch<C, false, NTL, NTS>(T, desc, map + nib, nblocks - nib, cur, step, s);
-}
-
-template <class C, bool NTL>
-static void launch_batch_both(int bsi, const LatDesc* desc, const int2* map, int nblocks, int nib, int cur,
-                              long long step, int xcd, hipStream_t s) {
-    launch_batch_v<C, true, NTL>(bsi, desc, map, nib, cur, step, xcd, s);
-    launch_batch_v<C, false, NTL>(bsi, desc, map + nib, nblocks - nib, cur, step, xcd, s);
 }
 
 hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* maps, const int moff[8],
                                 const int nblocks[8], const int nib[8], int cur, long long step, int variant,
                                 hipStream_t s) {
     if (variant < 0 || variant >= STEP_VARIANTS) return hipErrorInvalidValue;
-    const int bsi = (variant >> 1) & 3;
-    const int xb = variant & VAR_X ? 1 : 0;
-    if (variant & VAR_ROWS) {
-        const int q = 4 + bsi;
-        if (nblocks[q] <= 0) return hipErrorInvalidValue;
-        const int T = LAT_BS[bsi];
-        DISPATCH_STORAGE(storage, C, {
-            if (variant & 1) {
-                if (xb) launch_rows_both<C, true, true>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
-                else launch_rows_both<C, true, false>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
-            } else {
-                if (xb) launch_rows_both<C, false, true>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
-                else launch_rows_both<C, false, false>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
-            }
-        });
-        return hipGetLastError();
+    switch (storage) {
+        case IBM_LB_F64: return launch_lattice_batch_c<SF64>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
+        case IBM_LB_F32: return launch_lattice_batch_c<SF32>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
+        case IBM_LB_F16DEV:
+            return launch_lattice_batch_c<SF16>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
+        default: return launch_lattice_batch_c<SBF16>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
     }
-    DISPATCH_STORAGE(storage, C, {
-        if (variant & 1)
-            launch_batch_both<C, true>(bsi, desc, maps + moff[bsi], nblocks[bsi], nib[bsi], cur, step, xb, s);
-        else
-            launch_batch_both<C, false>(bsi, desc, maps + moff[bsi], nblocks[bsi], nib[bsi], cur, step, xb, s);
-    });
-    return hipGetLastError();
 }
 
 // Point every member's gradient rows at base + i * stride (graph replays of
@@ -1467,7 +719,7 @@ hipError_t launch_observables(int storage, const Geom& g, const LatticeParams& l
                                (const V4<R>*)d.r, d.obs_part);
         });
     }
-    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, s, OBS_BLOCKS, d.obs_part, MASS_BLOCKS,
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(OBS_FINAL_THREADS), 0, s, OBS_BLOCKS, d.obs_part, MASS_BLOCKS,
                        d.mass_part, A_row, radius, nv > 0 ? 1 : 0, d.ctl, d.obs_out);
     return hipGetLastError();
 }
