@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the coupled IB-LB droplet timestep on one MI355X.
 
-Workload (single droplet, FP32 populations): 128^3 box with moving walls,
-tau = 0.8, droplet of rest radius 16 on a level-5 icosphere (10242 vertices,
-20480 triangles), and a seeded traceless Ornstein-Uhlenbeck velocity gradient
-A(t) (correlation time 2000 steps, rms capillary number 0.1 at R/eta = 0.472).
-One step is the whole coupled update: forces, spreading, fused
-collide-stream with the moving walls, interpolation + Euler, HC smoothing.
+Headline workload (single droplet, FP32 populations): 256^3 box with moving
+walls, tau = 0.8, droplet of rest radius 32 on a level-6 icosphere (40962
+vertices, 81920 triangles), and a seeded traceless Ornstein-Uhlenbeck velocity
+gradient A(t) (correlation time 2000 steps, rms capillary number 0.15 at
+R/eta = 0.472). Its two population copies (2.55 GB) are far beyond the 256 MB
+last-level cache. One step is the whole coupled update: forces, spreading,
+fused collide-stream with the moving walls, interpolation + Euler, HC
+smoothing.
 
 Prints one JSON line: throughput in MLUPS (lattice node updates per second,
-whole job), the fused lattice kernel's HBM roofline fraction (algorithmic
-152 B per node update over its HIP-event-timed average duration), and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+whole job; the median of five timed runs of --steps steps), the fused lattice
+kernel's HBM roofline fraction (algorithmic 2 x 19 x s bytes per node update
+over its HIP-event-timed average duration), the same box with FP64, FP16 and
+BF16 population storage, the 128^3 single droplet, the 64-droplet ensemble
+against the same droplets one at a time, the adjoint, and the FP64 CPU oracle
+timed on bounded samples.
 """
 from __future__ import annotations
 
@@ -87,27 +92,28 @@ def ensemble_bench(steps, warmup=20):
     obs = ens.observables()
     ens.close()
     del ens
+    # the same droplets one at a time: each a one-member ensemble, so the solo
+    # runs use the same batched kernels and the same captured graph replays
     solos = []
     for d in range(n):
-        kw = dict(members[d])
-        L, tau = kw.pop("L"), kw.pop("tau")
-        s = ibmlb.Simulation(L, tau, storage="f32", **kw)
-        s.autotune(5)
-        s.step_table(tabs[d, :warmup])
-        solos.append(s)
+        e = ibmlb.Ensemble([members[d]], storage="f32")
+        e.autotune(3)
+        e.step(tabs[d:d + 1, :warmup])
+        solos.append(e)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for d in range(n):
-        solos[d].step_table(tabs[d, warmup:])
+        solos[d].step(tabs[d:d + 1, warmup:])
     torch.cuda.synchronize()
     t_solo = time.perf_counter() - t0
-    for s in solos:
-        s.close()
+    for e in solos:
+        e.close()
     return {"workload": "64 droplets, boxes drawn from {48,64,96}^3, R = L/8, 2562-vertex icospheres, "
                         "tau 1, OU A(t) per droplet, rms Ca U(0.05, 0.2), f32",
             "droplets": n, "nodes": nodes, "vertices": sum(len(m["vertices"]) for m in members),
             "steps": steps, "batched_mlups": round(nodes * steps / t_batch / 1e6, 1),
             "solo_mlups": round(nodes * steps / t_solo / 1e6, 1),
+            "solo": "each droplet as a one-member ensemble, one after another (same kernels, same graphs)",
             "batched_over_solo": round(t_solo / t_batch, 3),
             "batched_ms_per_step": round(t_batch / steps * 1e3, 4),
             "batched_hbm_frac": round(152 * nodes * steps / t_batch / 1e9 / HBM_PEAK_GBS, 4),
@@ -139,44 +145,77 @@ def lattice_kernel_name(v, chi=1.0, collision="bgk"):
     return "k_lattice_rows" if v & 16 else "k_lattice"
 
 
-def large_footprint_bench(dev, steps=300, warmup=30):
-    """The 256^3 droplet (1.27 GB per population copy, far beyond the 256 MB
-    last-level cache) in FP32: whole-step throughput and the lattice kernel's
-    roofline fraction with the autotuner's variant."""
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
+DTYPE = {"f64": "f64", "f32": "f32", "f16dev": "f16", "bf16dev": "bf16"}
+
+
+def droplet_leg(dev, w, storage, K, W, reps=5, variant=None, chi=1.0, collision="bgk", walls="link",
+                box="256cubed"):
+    """One droplet workload `w` with `storage` populations: W warm-up steps,
+    then `reps` timed runs of K whole steps (hipStream synchronised around
+    each; the median is reported), then K more steps with HIP events stamped
+    by every lattice dispatch for the lattice kernel's average duration."""
     import numpy as np
     import torch
     from paper_2403_01161_amd import ibmlb
     from paper_2403_01161_amd.inputs import ou_gradient_table
-    w = precision_workload()
-    table = ou_gradient_table(warmup + 2 * steps, w["corr"], w["G"], seed=w["seed"])
+    table = ou_gradient_table(W + (reps + 1) * K + 1, w["corr"], w["G"], seed=w["seed"])
+    sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage=storage,
+                           A0=table[0], device=dev, chi=chi, collision=collision, walls=walls)
     dtab = torch.from_numpy(table).to(dev)
     nodes = int(np.prod(w["L"]))
-    sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage="f32",
-                           A0=table[0], device=dev)
-    variant = sim.autotune(5)
-    sim.step_table(dtab[:warmup])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step_table(dtab[warmup:warmup + steps])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    nv = len(w["V"])
+    if variant is None:
+        variant = sim.autotune(5)
+    else:
+        sim.set_variant(variant)
+    sim.step_table(dtab[:W])
+    obs0 = sim.observables()  # synchronises
+    times = []
+    for r in range(reps):
+        t0 = time.perf_counter()
+        sim.step_table(dtab[W + r * K:W + (r + 1) * K])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    dt = sorted(times)[reps // 2]
     sim.timing(True)
-    sim.step_table(dtab[warmup + steps:warmup + 2 * steps])
+    t1 = time.perf_counter()
+    sim.step_table(dtab[W + reps * K:W + (reps + 1) * K])
+    torch.cuda.synchronize()
+    dt_ev = time.perf_counter() - t1
     lat_ms, launches = sim.timing_read()
+    sim.timing(False)
+    obs = sim.observables()
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    alg = 2 * 19 * 4 * nodes
+    alg = 2 * 19 * STORAGE_BYTES[storage] * nodes
     avg_s = lat_ms / 1e3 / max(launches, 1)
     ach = alg / avg_s / 1e9
-    return {"workload": "single droplet, 256^3 moving-wall box, tau 0.8, R 32, 40962-vertex icosphere, "
-                        "OU traceless A(t) rms Ca 0.15, f32 populations",
-            "steps": steps, "mlups": round(nodes * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 4),
+    plain = chi == 1.0 and collision == "bgk" and walls == "link"
+    return {"mlups": round(nodes * K / dt / 1e6, 2), "ms_per_step": round(dt / K * 1e3, 5),
+            "rep_ms_per_step": [round(t / K * 1e3, 5) for t in times],
+            "ms_per_step_with_kernel_events": round(dt_ev / K * 1e3, 5),
+            "vertex_updates_per_s": round(nv * K / dt, 1),
+            "hbm_frac_whole_step": round(alg * K / dt / 1e9 / HBM_PEAK_GBS, 4),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counter_traffic("f32", "256cubed", variant),
-                         "kernel": lattice_kernel_name(variant), "alg_bytes_per_launch": alg,
-                         "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-                         "variant": describe_variant(variant)}}
+                         "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "traffic": counter_traffic(storage, box, variant) if plain else None,
+                         "kernel": lattice_kernel_name(variant, chi, collision), "alg_bytes_per_launch": alg,
+                         "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
+                         "variant": describe_variant(variant)},
+            "observables": {"step": obs["step"], "D": obs["D"], "theta_deg": obs["theta_deg"],
+                            "beta": obs["beta"], "reg_iters": obs["reg_iters"],
+                            "mass_drift_rel": (obs["mass"] - obs0["mass"]) / obs0["mass"]}}
+
+
+def workload_name(w, storage, chi=1.0, collision="bgk", walls="link"):
+    L = w["L"][0]
+    return (f"single droplet, {L}^3 moving-wall box, tau {w['tau']:g}, R {w['R']:g}, {len(w['V'])}-vertex "
+            f"icosphere, OU traceless A(t) rms Ca {w['Ca']:g}, {storage} populations"
+            + (f", viscosity ratio {chi:g}" if chi != 1.0 else "")
+            + (", MRT collision" if collision == "mrt" else "")
+            + (", wet-node walls" if walls == "wet" else ""))
 
 
 def kernel_source_hash():
@@ -205,37 +244,88 @@ def counter_traffic(storage, box="128cubed", variant=None):
     return float(t.group(1))
 
 
-def cpu_baseline(w, table, steps, single_steps=8):
-    """The FP64 oracle on this host's cores (its lattice sweeps use OpenMP
-    over z-planes, the IB part is serial), then on one thread for a shorter
-    sample of the same run."""
-    import ctypes
+def _oracle_rate(w, steps, warm=2, seed=None, threads=None):
+    """FP64 oracle MLUPS on workload w: `warm` untimed steps, then `steps`
+    timed steps (its own OU table, or w["A"] when given)."""
     import numpy as np
     import oracle
-    kw = dict(tau=w["tau"], sigma=w["sigma"], radius=w["R"], vertices=w["V"], triangles=w["T"],
-              A0=table[0], collision=w.get("collision", "bgk"), walls=w.get("walls", "link"))
+    from paper_2403_01161_amd.inputs import ou_gradient_table
+    if "A" in w:
+        table = np.asarray(w["A"])[:1 + warm + steps]
+    else:
+        table = ou_gradient_table(1 + warm + steps, w["corr"], w["G"], seed=w["seed"] if seed is None else seed)
+    ref = oracle.Oracle(w["L"], w["tau"], sigma=w["sigma"], radius=w["R"], vertices=w["V"], triangles=w["T"],
+                        A0=table[0])
+    ref.step_table(table[1:1 + warm])
+    t0 = time.perf_counter()
+    ref.step_table(table[1 + warm:1 + warm + steps])
+    dt = time.perf_counter() - t0
+    ref.close()
+    return int(np.prod(w["L"])) * steps / dt / 1e6, dt
+
+
+def cpu_baseline(w, steps=20, single_steps=3, per_config=True):
+    """The FP64 oracle on this host's cores (its lattice sweeps use OpenMP over
+    z-planes, the IB part is serial) on a bounded sample of the headline
+    workload, then on one thread for a shorter sample; then the other
+    configurations: the plain-method run in full (32^3, 1000 steps) and
+    20 timed steps of the others, whose full-run times are extrapolated."""
+    import ctypes
+    import numpy as np
+    from paper_2403_01161_amd.inputs import box_center, icosphere, ou_gradient_table, simple_shear
     gomp = ctypes.CDLL("libgomp.so.1")  # the OpenMP runtime the oracle library uses
     cores = int(gomp.omp_get_max_threads())
-    rows = table[1:1 + steps]
-    rows1 = table[1 + steps:1 + steps + single_steps]
-    steps, single_steps = len(rows), len(rows1)
-    ref = oracle.Oracle(w["L"], **kw)
-    ref.step_table(table[:1])
-    t0 = time.perf_counter()
-    ref.step_table(rows)
-    dt = time.perf_counter() - t0
+    value, dt = _oracle_rate(w, steps)
     gomp.omp_set_num_threads(1)
-    t1 = time.perf_counter()
-    ref.step_table(rows1)
-    dt1 = time.perf_counter() - t1
-    gomp.omp_set_num_threads(cores)
+    try:
+        single, dt1 = _oracle_rate(w, single_steps, warm=0, seed=w["seed"] + 1)
+    finally:
+        gomp.omp_set_num_threads(cores)
     nodes = int(np.prod(w["L"]))
+    out = {"value": round(value, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"FP64 oracle, the headline {w['L'][0]}^3 workload: {steps} steps after 2 warm-up steps "
+                     f"({dt:.1f} s) on {cores} threads (OpenMP over z-planes for the lattice, serial IB); "
+                     f"then {single_steps} steps from a fresh start on 1 thread ({dt1:.1f} s)",
+           "single_thread_value": round(single, 3)}
+    if not per_config:
+        return out
+    pc = {}
+    # plain method: 32^3, tau 1, R 5 (642 vertices), simple shear Ca 0.05, 1000 steps, in full
+    from oracle import Oracle
+    g = 1e-3
+    V, T = icosphere(3, 5.0, box_center((32, 32, 32)))
+    ref = Oracle((32, 32, 32), 1.0, sigma=(1 / 6) * g * 5.0 / 0.05, radius=5.0, vertices=V, triangles=T,
+                 A0=simple_shear(g))
+    t0 = time.perf_counter()
+    ref.step(simple_shear(g), 1000)
+    t1k = time.perf_counter() - t0
+    D = ref.observables()["D"]
     ref.close()
-    return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle, same 128^3 workload, {steps} steps after 1 warm-up step "
-                      f"({dt:.1f} s) on {cores} threads (OpenMP over z-planes for the lattice, serial IB), "
-                      f"then {single_steps} steps on 1 thread ({dt1:.1f} s)",
-            "single_thread_value": nodes * single_steps / dt1 / 1e6 if single_steps else None}
+    pc["plain_32cubed_1000_steps"] = {"mlups": round(32 ** 3 * 1000 / t1k / 1e6, 3), "seconds": round(t1k, 2),
+                                      "D": D, "measured": "full run"}
+    w2 = workload("f32")
+    m2, _ = _oracle_rate(w2, 20)
+    pc["single_128cubed_20000_steps"] = {"mlups": round(m2, 3), "measured": "20 steps after 2 warm-up",
+                                        "full_run_seconds_extrapolated": round(128 ** 3 * 20000 / m2 / 1e6, 0)}
+    pc["precision_256cubed_5000_steps"] = {"mlups": round(value, 3), "measured": f"{steps} steps (above)",
+                                          "full_run_seconds_extrapolated": round(nodes * 5000 / value / 1e6, 0)}
+    members, rms = ensemble_workload()
+    t_ens, n_ens = 0.0, 0
+    for d, m in enumerate(members):
+        wd = dict(L=m["L"], tau=m["tau"], sigma=m["sigma"], R=m["radius"], V=m["vertices"], T=m["triangles"],
+                  corr=2000.0, G=rms[d], seed=1000 + d)
+        _, dtd = _oracle_rate(wd, 20)
+        t_ens += dtd
+        n_ens += int(np.prod(m["L"])) * 20
+    pc["ensemble_64_droplets_10000_steps"] = {
+        "mlups": round(n_ens / t_ens / 1e6, 3), "measured": "20 steps of each droplet after 2 warm-up",
+        "full_run_seconds_extrapolated": round(n_ens / 20 * 10000 / (n_ens / t_ens), 0)}
+    wa = adjoint_workload()
+    ma, _ = _oracle_rate(dict(wa, corr=0, G=0, seed=0), 20)
+    pc["adjoint_64cubed_500_steps_forward"] = {"mlups": round(ma, 3), "measured": "20 steps after 2 warm-up",
+                                               "full_run_seconds_extrapolated": round(64 ** 3 * 500 / ma / 1e6, 1)}
+    out["per_config"] = pc
+    return out
 
 
 def adjoint_workload():
@@ -319,7 +409,7 @@ def precision_workload():
     nu = (tau - 0.5) / 3.0
     G = (0.472 ** 2) * nu / R ** 2
     V, T = icosphere(6, R, box_center(L))
-    return dict(L=L, R=R, tau=tau, G=G, sigma=nu * R * G / Ca, V=V, T=T, corr=2000.0, seed=4)
+    return dict(L=L, R=R, tau=tau, G=G, Ca=Ca, sigma=nu * R * G / Ca, V=V, T=T, corr=2000.0, seed=4)
 
 
 def precision_bench(dev, steps, every=500):
@@ -408,28 +498,29 @@ def counters_sequence(dev, storage, box="128", fixed_variant=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1000, help="steps per timed run (five runs; median)")
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--box", default="256", choices=["256", "128"],
+                    help="single-droplet workload of the headline leg: 256^3 (R 32) or 128^3 (R 16)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16dev", "bf16dev"])
-    ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-formats", action="store_true", help="skip the other storage formats of the box")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline leg only (no other formats, 128^3 leg, ensemble, adjoint or CPU baseline)")
     ap.add_argument("--ensemble-steps", type=int, default=300)
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--large-steps", type=int, default=300,
-                    help="steps of the 256^3 large-footprint leg (0 skips it)")
     ap.add_argument("--precision", type=int, default=0, metavar="STEPS",
                     help="run only the storage-precision study (256^3, every format) for STEPS steps")
     ap.add_argument("--variant", type=int, default=None,
-                    help="run this step variant instead of the autotuner's choice (the single-droplet "
-                         "128^3 leg and --counters)")
+                    help="run this step variant instead of the autotuner's choice (the headline leg "
+                         "and --counters)")
     ap.add_argument("--chi", type=float, default=1.0,
-                    help="viscosity ratio of the droplet for the single-droplet leg (1: one fluid); "
-                         "other values add the inside-indicator build per step and skip the CPU "
-                         "baseline (the oracle's winding-number indicator is far too slow at 128^3)")
+                    help="viscosity ratio of the droplet for the headline leg (1: one fluid)")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
-                    help="collision of the single-droplet leg (MRT: default rates)")
+                    help="collision of the headline leg (MRT: default rates)")
     ap.add_argument("--walls", default="link", choices=["link", "wet"],
-                    help="wall rule of the single-droplet leg (wet: the wet-node velocity walls)")
+                    help="wall rule of the headline leg (wet: the wet-node velocity walls)")
     ap.add_argument("--counters", nargs="?", const="128", choices=["128", "256"], default=None,
                     help="short fixed sequence for hardware-counter runs: 3 device copies of "
                          "256 MiB (calibration) and 20 steps of the single-droplet workload")
@@ -439,10 +530,7 @@ def main():
                                    "z-slab split are the multi-GPU designs (not run here)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2403_01161_amd import ibmlb
-    from paper_2403_01161_amd.inputs import ou_gradient_table
 
     dev = torch.device("cuda:0")
     if args.counters:
@@ -451,96 +539,61 @@ def main():
     if args.precision:
         print(json.dumps({"precision": precision_bench(dev, args.precision)}), flush=True)
         return
-    w = workload(args.storage)
     K, W = args.steps, args.warmup
-    table = ou_gradient_table(W + 2 * K + 1, w["corr"], w["G"], seed=w["seed"])
-    sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"],
-                           storage=w["storage"], A0=table[0], device=dev, chi=args.chi,
-                           collision=args.collision, walls=args.walls)
-    w["collision"], w["walls"] = args.collision, args.walls
-    dtab = torch.from_numpy(table).to(dev)
-    nodes = int(np.prod(w["L"]))
-    nv = len(w["V"])
-    if args.variant is None:
-        variant = sim.autotune(20)
-    else:
-        variant = args.variant
-        sim.set_variant(variant)
-
-    sim.step_table(dtab[:W])
-    torch.cuda.synchronize()
-    # timed region: K whole steps
-    t0 = time.perf_counter()
-    sim.step_table(dtab[W:W + K])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    obs = sim.observables()
-
-    # second pass of K steps with HIP start/stop events stamped by every lattice dispatch on
-    # the library's stream: the dominant kernel's average duration
-    sim.timing(True)
-    t1 = time.perf_counter()
-    sim.step_table(dtab[W + K:W + 2 * K])
-    torch.cuda.synchronize()
-    dt_ev = time.perf_counter() - t1
-    lat_ms, launches = sim.timing_read()
-    sim.timing(False)
-    obs2 = sim.observables()
-    sbytes = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[args.storage]
-    alg_bytes = 2 * 19 * sbytes * nodes
-    avg_s = lat_ms / 1e3 / max(launches, 1)
-    achieved = alg_bytes / avg_s / 1e9
-    # the committed counters are those of the one-fluid lattice kernel
-    plain = args.chi == 1.0 and args.collision == "bgk" and args.walls == "link"
-    traffic = counter_traffic(args.storage, variant=variant) if plain else None
-
-    value = nodes * K / dt / 1e6
+    variant_kw = dict(chi=args.chi, collision=args.collision, walls=args.walls)
+    w = precision_workload() if args.box == "256" else workload(args.storage)
+    box = f"{args.box}cubed"
+    head = droplet_leg(dev, w, args.storage, K, W, variant=args.variant, box=box, **variant_kw)
+    print(json.dumps({"leg_done": "headline", "mlups": head["mlups"], "frac": head["roofline"]["frac"]}),
+          file=sys.stderr, flush=True)
     line = {
         "metric": "IB-LB MLUPS",
-        "value": round(value, 2),
+        "value": head["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": round(dt / K * 1e3, 5),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "f16dev": "f16", "bf16dev": "bf16"}[args.storage],
+        "dtype": DTYPE[args.storage],
         "data": "synthetic",
-        "config": {"workload": "single droplet, 128^3 moving-wall box, tau 0.8, R 16, "
-                               "10242-vertex icosphere, OU traceless A(t) rms Ca 0.1, "
-                               f"{args.storage} populations"
-                               + (f", viscosity ratio {args.chi:g}" if args.chi != 1.0 else "")
-                               + (", MRT collision" if args.collision == "mrt" else "")
-                               + (", wet-node walls" if args.walls == "wet" else ""),
-                   "box": list(w["L"]), "vertices": nv, "storage": args.storage, "chi": args.chi,
-                   "collision": args.collision, "walls": args.walls},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": lattice_kernel_name(variant, args.chi, args.collision),
-                     "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
-                     "variant": describe_variant(variant)},
-        "vertex_updates_per_s": round(nv * K / dt, 1),
-        "hbm_frac_whole_step": round(alg_bytes * K / dt / 1e9 / HBM_PEAK_GBS, 4),
-        "ms_per_step_with_kernel_events": round(dt_ev / K * 1e3, 5),
-        "observables": {"step": obs2["step"], "D": obs2["D"], "theta_deg": obs2["theta_deg"],
-                        "beta": obs2["beta"], "reg_iters": obs2["reg_iters"],
-                        "mass_drift_rel": (obs2["mass"] - obs["mass"]) / obs["mass"]},
+        "config": {"workload": workload_name(w, args.storage, **variant_kw), "box": list(w["L"]),
+                   "vertices": len(w["V"]), "storage": args.storage, "chi": args.chi,
+                   "collision": args.collision, "walls": args.walls,
+                   "timing": "median of 5 timed runs of `steps` steps"},
+        "roofline": head["roofline"],
     }
-    sim.close()
-    del sim
-    torch.cuda.empty_cache()
-    if args.large_steps > 0:
-        line["large_footprint"] = large_footprint_bench(dev, args.large_steps)
-    if args.ensemble_steps > 0:
+    for k in ("rep_ms_per_step", "ms_per_step_with_kernel_events", "vertex_updates_per_s",
+              "hbm_frac_whole_step", "observables"):
+        line[k] = head[k]
+    extras = not args.no_extras
+    plain = args.chi == 1.0 and args.collision == "bgk" and args.walls == "link"
+    if extras and not args.no_formats and plain:
+        fm = {}
+        for st in ("f64", "f32", "f16dev", "bf16dev"):
+            if st == args.storage:
+                continue
+            leg = droplet_leg(dev, w, st, K, W, box=box)
+            fm[st] = {"workload": workload_name(w, st), **{k: leg[k] for k in (
+                "mlups", "ms_per_step", "rep_ms_per_step", "hbm_frac_whole_step", "roofline", "observables")}}
+            print(json.dumps({"leg_done": st, "mlups": leg["mlups"], "frac": leg["roofline"]["frac"]}),
+                  file=sys.stderr, flush=True)
+        line["storage_formats"] = fm
+    if extras and args.box == "256" and plain:
+        w2 = workload("f32")
+        leg = droplet_leg(dev, w2, "f32", K, W, box="128cubed")
+        line["single_droplet_128cubed"] = {"workload": workload_name(w2, "f32"), **leg}
+        print(json.dumps({"leg_done": "128cubed", "mlups": leg["mlups"]}), file=sys.stderr, flush=True)
+    if extras and args.ensemble_steps > 0:
         line["ensemble"] = ensemble_bench(args.ensemble_steps)
-    if not args.no_adjoint:
+        print(json.dumps({"leg_done": "ensemble"}), file=sys.stderr, flush=True)
+    if extras and not args.no_adjoint:
         line["adjoint"] = adjoint_bench(dev)
-    if not args.no_cpu and args.chi == 1.0:
-        line["cpu_baseline"] = cpu_baseline(w, table, args.cpu_steps)
+        print(json.dumps({"leg_done": "adjoint"}), file=sys.stderr, flush=True)
+    if extras and not args.no_cpu and args.chi == 1.0 and args.box == "256":
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
