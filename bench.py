@@ -220,7 +220,7 @@ def workload_name(w, storage, chi=1.0, collision="bgk", walls="link"):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("kernels.hip", "lattice_common.h", "device_common.h"):
+    for name in ("kernels.hip", "lattice_kernels.h", "lattice_common.h", "device_common.h"):
         with open(os.path.join(ROOT, "paper_2403_01161_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

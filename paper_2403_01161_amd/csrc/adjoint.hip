@@ -175,38 +175,207 @@ __device__ inline bool stencil_d(const Geom& g, double4 p, int f[3], double w[3]
     return ok;
 }
 
-// Transpose of the interpolation U_k = sum_x u(x) Delta: ubar(x) += Ubar_k
-// Delta(r_k - x). One wave per vertex, one lane per stencil node.
+// Transpose of the interpolation U_k = sum_x u(x) Delta(r_k - x): ubar(x) +=
+// Ubar_k Delta(r_k - x). One work-group per surface patch of IB_PATCH
+// consecutive vertices (the internal order numbers the vertices patch by
+// patch): the patch's 64 stencil contributions per vertex are summed in an
+// FP64 LDS window over the patch's stencils (one lane per stencil node, each
+// wave taking every fourth vertex), then every touched node takes one global
+// atomic add per component. A patch whose window exceeds ADJ_WCAP nodes adds
+// its contributions straight to global memory.
+constexpr int ADJ_WCAP = 2048;
+
 __global__ __launch_bounds__(256) void k_adj_spread(Geom g, int nv, const double4* __restrict__ pos,
                                                     const double4* __restrict__ Ub, double* __restrict__ ubar) {
-    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (k >= nv) return;
-    int f[3];
-    double w[3][4], dw[3][4];
-    if (!stencil_d(g, pos[k], f, w, dw)) return;
-    const int jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
-    const double wt = w[0][jx] * w[1][jy] * w[2][jz];
-    const long long n = node_index(g, f[0] + jx, f[1] + jy, f[2] + jz);
-    const double4 v = Ub[k];
+    __shared__ int sf[IB_PATCH][3];
+    __shared__ double sw[IB_PATCH][3][4];
+    __shared__ double sv[IB_PATCH][3];
+    __shared__ int sok[IB_PATCH];
+    __shared__ int red[6][4];
+    __shared__ double win[3 * ADJ_WCAP];
+    const int t = threadIdx.x;
+    const int k = blockIdx.x * IB_PATCH + t;
+    int f[3] = {0, 0, 0};
+    bool ok = false;
+    if (t < IB_PATCH && k < nv) {
+        double w[3][4], dw[3][4];
+        ok = stencil_d(g, pos[k], f, w, dw);
+        if (ok) {
+            for (int d = 0; d < 3; ++d)
+                for (int j = 0; j < 4; ++j) sw[t][d][j] = w[d][j];
+            const double4 v = Ub[k];
+            sv[t][0] = v.x;
+            sv[t][1] = v.y;
+            sv[t][2] = v.z;
+        }
+    }
+    if (t < IB_PATCH) {
+        for (int d = 0; d < 3; ++d) sf[t][d] = f[d];
+        sok[t] = ok ? 1 : 0;
+    }
+    // window: origin and extent of the active stencils
+    int mn[3], mx[3];
+    for (int d = 0; d < 3; ++d) {
+        mn[d] = ok ? f[d] : 0x3fffffff;
+        mx[d] = ok ? f[d] : -0x3fffffff;
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = min(mn[d], __shfl_xor(mn[d], off, 64));
+            mx[d] = max(mx[d], __shfl_xor(mx[d], off, 64));
+        }
+    if ((t & 63) == 0)
+        for (int d = 0; d < 3; ++d) {
+            red[d][t >> 6] = mn[d];
+            red[3 + d][t >> 6] = mx[d];
+        }
+    __syncthreads();
+    int o[3], e[3];
+    long long vol = 1;
+    bool any = true;
+    for (int d = 0; d < 3; ++d) {
+        int lo = red[d][0], hi = red[3 + d][0];
+        for (int q = 1; q < 4; ++q) {
+            lo = min(lo, red[d][q]);
+            hi = max(hi, red[3 + d][q]);
+        }
+        any = any && lo <= hi;
+        o[d] = lo;
+        e[d] = any ? hi - lo + 4 : 0;
+        vol *= e[d];
+    }
+    if (!any) return;
     const long long N = g.N;
-    unsafeAtomicAdd(ubar + n, v.x * wt);
-    unsafeAtomicAdd(ubar + N + n, v.y * wt);
-    unsafeAtomicAdd(ubar + 2 * N + n, v.z * wt);
+    const int lane = t & 63, jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
+    if (vol > ADJ_WCAP) {
+        for (int v = t >> 6; v < IB_PATCH; v += 4) {
+            if (!sok[v]) continue;
+            const double wt = sw[v][0][jx] * sw[v][1][jy] * sw[v][2][jz];
+            const long long n = node_index(g, sf[v][0] + jx, sf[v][1] + jy, sf[v][2] + jz);
+            unsafeAtomicAdd(ubar + n, sv[v][0] * wt);
+            unsafeAtomicAdd(ubar + N + n, sv[v][1] * wt);
+            unsafeAtomicAdd(ubar + 2 * N + n, sv[v][2] * wt);
+        }
+        return;
+    }
+    const int nw = int(vol);
+    for (int i = t; i < 3 * nw; i += 256) win[i] = 0.0;
+    __syncthreads();
+    for (int v = t >> 6; v < IB_PATCH; v += 4) {
+        if (!sok[v]) continue;
+        const double wt = sw[v][0][jx] * sw[v][1][jy] * sw[v][2][jz];
+        const int cell = (sf[v][0] + jx - o[0]) + e[0] * ((sf[v][1] + jy - o[1]) + e[1] * (sf[v][2] + jz - o[2]));
+        atomicAdd(&win[cell], sv[v][0] * wt);
+        atomicAdd(&win[nw + cell], sv[v][1] * wt);
+        atomicAdd(&win[2 * nw + cell], sv[v][2] * wt);
+    }
+    __syncthreads();
+    for (int i = t; i < nw; i += 256) {
+        const double vx = win[i], vy = win[nw + i], vz = win[2 * nw + i];
+        if (vx == 0.0 && vy == 0.0 && vz == 0.0) continue;
+        const int lx = i % e[0], rest = i / e[0];
+        const int ly = rest % e[1], lz = rest / e[1];
+        const long long n = node_index(g, o[0] + lx, o[1] + ly, o[2] + lz);
+        unsafeAtomicAdd(ubar + n, vx);
+        unsafeAtomicAdd(ubar + N + n, vy);
+        unsafeAtomicAdd(ubar + 2 * N + n, vz);
+    }
 }
 
 // ---------------------------------------------------------------- lattice adjoint
 // One thread per node x. Streaming transpose (pull): gbar_i(x) = fbar_i(x +
-// c_i), or fbar_{-i}(x) when x + c_i lies beyond a wall; in the latter case
-// the wall term -6 w_i rho0 c_i.A(x + c_i/2 - x_c) contributes
-// gbar_i (-6 w_i rho0) c_i (x + c_i/2 - x_c)^T to dJ/dA. Collision and
+// c_i), or fbar_{-i}(x) when x + c_i lies beyond a wall. Collision and
 // moments transpose with the recorded rho, u, F:
 //   rhobar = omega sum_i gbar_i f^eq_i / rho
 //   ubar   = ubar_ext + sum_i gbar_i [omega df^eq_i/du + dS_i/du]
 //   Fbar   = sum_i gbar_i dS_i/dF + ubar / (2 rho)
 //   fbar_j = (1 - omega) gbar_j + rhobar + ubar.(c_j - u) / rho.
-// ubar_ext (the transposed interpolation) is cleared once read. Each block
-// writes its 9 partial sums of dJ/dA to part[block][9].
+// ubar_ext (the transposed interpolation) is cleared once read. Afterwards
+// (so that its registers are free) a boundary node adds the moving-wall
+// terms' share of dJ/dA: the forward reflected f*_i(x) into slot -i with the
+// term -6 w_i rho0 c_i . A (x + c_i/2 - x_c), so dJ/dA += fbar_{-i}(x)
+// (-6 w_i rho0) c_i (x + c_i/2 - x_c)^T; each work-group writes its 9 sums to
+// part[block][9] (fixed order).
+__device__ __forceinline__ void adj_lattice_node(const Geom& g, const LatticeParams& lp, const double* __restrict__ fbin,
+                                                 double* __restrict__ fbout, const double* __restrict__ rho_,
+                                                 const double* __restrict__ u_, const double* __restrict__ F_,
+                                                 double* __restrict__ ubar, double* __restrict__ Fbar, long long n,
+                                                 int x, int y, int z) {
+    const long long N = g.N;
+    const int LxLy = g.Lx * g.Ly;
+    double gb[Q];
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        // the pull source x + c_i, moved back across a periodic side
+        long long src = n + CX[i] + (long long)CY[i] * g.Lx + (long long)CZ[i] * LxLy;
+        bool wall = false;
+        if (CX[i] == 1 && x == g.Lx - 1) { if (g.px) src -= g.Lx; else wall = true; }
+        if (CX[i] == -1 && x == 0) { if (g.px) src += g.Lx; else wall = true; }
+        if (CY[i] == 1 && y == g.Ly - 1) { if (g.py) src -= LxLy; else wall = true; }
+        if (CY[i] == -1 && y == 0) { if (g.py) src += LxLy; else wall = true; }
+        if (CZ[i] == 1 && z == g.Lz - 1) { if (g.pz) src -= N; else wall = true; }
+        if (CZ[i] == -1 && z == 0) { if (g.pz) src += N; else wall = true; }
+        gb[i] = wall ? fbin[opp(i) * N + n] : fbin[i * N + src];
+    });
+    const double rho = rho_[n];
+    const double ux = u_[n], uy = u_[N + n], uz = u_[2 * N + n];
+    const double Fx = F_[n], Fy = F_[N + n], Fz = F_[2 * N + n];
+    double ex = ubar[n], ey = ubar[N + n], ez = ubar[2 * N + n];
+    if (ex != 0.0 || ey != 0.0 || ez != 0.0) {
+        ubar[n] = 0.0;
+        ubar[N + n] = 0.0;
+        ubar[2 * N + n] = 0.0;
+    }
+    // the sums over i reduce to weighted moments of gbar: G0 = sum w_i g_i,
+    // G1 = sum w_i g_i c_i, G2 = sum w_i g_i c_i c_i (c.u = c_i.u, c.F = c_i.F):
+    //   rhobar / omega = G0 + 3 G1.u + 9/2 u.G2.u - 3/2 (u.u) G0
+    //   ubar - ubar_ext = omega rho (3 G1 + 9 G2 u - 3 u G0) + kg (9 G2 F - 3 F G0)
+    //   Fbar_S = kg (3 G1 + 9 G2 u - 3 u G0)
+    double G0 = 0.0, G1x = 0.0, G1y = 0.0, G1z = 0.0;
+    double Gxx = 0.0, Gyy = 0.0, Gzz = 0.0, Gxy = 0.0, Gxz = 0.0, Gyz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double wg = wgt<double>(i) * gb[i];
+        G0 += wg;
+        if (CX[i]) G1x += CX[i] * wg;
+        if (CY[i]) G1y += CY[i] * wg;
+        if (CZ[i]) G1z += CZ[i] * wg;
+        if (CX[i]) Gxx += wg;
+        if (CY[i]) Gyy += wg;
+        if (CZ[i]) Gzz += wg;
+        if (CX[i] * CY[i]) Gxy += CX[i] * CY[i] * wg;
+        if (CX[i] * CZ[i]) Gxz += CX[i] * CZ[i] * wg;
+        if (CY[i] * CZ[i]) Gyz += CY[i] * CZ[i] * wg;
+    }
+    const double om = lp.omega, kg = lp.kguo;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double Gux = Gxx * ux + Gxy * uy + Gxz * uz;
+    const double Guy = Gxy * ux + Gyy * uy + Gyz * uz;
+    const double Guz = Gxz * ux + Gyz * uy + Gzz * uz;
+    const double GFx = Gxx * Fx + Gxy * Fy + Gxz * Fz;
+    const double GFy = Gxy * Fx + Gyy * Fy + Gyz * Fz;
+    const double GFz = Gxz * Fx + Gyz * Fy + Gzz * Fz;
+    double rb = G0 + 3.0 * (G1x * ux + G1y * uy + G1z * uz) + 4.5 * (ux * Gux + uy * Guy + uz * Guz) - 1.5 * uu * G0;
+    const double sx = 3.0 * G1x + 9.0 * Gux - 3.0 * ux * G0;
+    const double sy = 3.0 * G1y + 9.0 * Guy - 3.0 * uy * G0;
+    const double sz = 3.0 * G1z + 9.0 * Guz - 3.0 * uz * G0;
+    const double ubx = ex + om * rho * sx + kg * (9.0 * GFx - 3.0 * Fx * G0);
+    const double uby = ey + om * rho * sy + kg * (9.0 * GFy - 3.0 * Fy * G0);
+    const double ubz = ez + om * rho * sz + kg * (9.0 * GFz - 3.0 * Fz * G0);
+    const double fbx = kg * sx, fby = kg * sy, fbz = kg * sz;
+    rb *= om;
+    const double inv = 1.0 / rho;
+    const double ubu = ubx * ux + uby * uy + ubz * uz;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const double ubc = ubx * CX[j] + uby * CY[j] + ubz * CZ[j];
+        fbout[j * N + n] = (1.0 - om) * gb[j] + rb + (ubc - ubu) * inv;
+    }
+    Fbar[n] = fbx + 0.5 * ubx * inv;
+    Fbar[N + n] = fby + 0.5 * uby * inv;
+    Fbar[2 * N + n] = fbz + 0.5 * ubz * inv;
+}
+
 __global__ __launch_bounds__(256) void k_adj_lattice(Geom g, LatticeParams lp, const double* __restrict__ fbin,
                                                      double* __restrict__ fbout, const double* __restrict__ rho_,
                                                      const double* __restrict__ u_, const double* __restrict__ F_,
@@ -214,88 +383,39 @@ __global__ __launch_bounds__(256) void k_adj_lattice(Geom g, LatticeParams lp, c
                                                      double* __restrict__ part) {
     const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long N = g.N;
+    const bool act = n < N;
+    int x = 0, y = 0, z = 0;
+    if (act) {
+        const int LxLy = g.Lx * g.Ly;
+        z = int(n / LxLy);
+        const int rem = int(n - (long long)z * LxLy);
+        y = rem / g.Lx;
+        x = rem - y * g.Lx;
+        adj_lattice_node(g, lp, fbin, fbout, rho_, u_, F_, ubar, Fbar, n, x, y, z);
+    }
     double dA[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) dA[c] = 0.0;
-    if (n < N) {
-        const int LxLy = g.Lx * g.Ly;
-        const int z = int(n / LxLy), rem = int(n - (long long)z * LxLy), y = rem / g.Lx, x = rem - y * g.Lx;
+    const bool bnd = act && ((!g.px && (x == 0 || x == g.Lx - 1)) || (!g.py && (y == 0 || y == g.Ly - 1)) ||
+                             (!g.pz && (z == 0 || z == g.Lz - 1)));
+    if (bnd) {
         const double xr = double(x - g.xci[0]) - g.xcf[0];
         const double yr = double(y - g.xci[1]) - g.xcf[1];
         const double zr = double(z - g.xci[2]) - g.xcf[2];
-        const double rho0 = lp.rho0;
-        double gb[Q];
+        static_for<1, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const bool wall = (!g.px && ((CX[i] == 1 && x == g.Lx - 1) || (CX[i] == -1 && x == 0))) ||
+                              (!g.py && ((CY[i] == 1 && y == g.Ly - 1) || (CY[i] == -1 && y == 0))) ||
+                              (!g.pz && ((CZ[i] == 1 && z == g.Lz - 1) || (CZ[i] == -1 && z == 0)));
+            if (!wall) return;
+            const double sv = -6.0 * wgt<double>(i) * lp.rho0 * fbin[opp(i) * N + n];
+            const double wv[3] = {xr + 0.5 * CX[i], yr + 0.5 * CY[i], zr + 0.5 * CZ[i]};
+            const int ci[3] = {CX[i], CY[i], CZ[i]};
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
-            bool wall = false;
-            if (CX[i] != 0 && (tx < 0 || tx >= g.Lx)) {
-                if (g.px) tx = wrap(tx, g.Lx); else wall = true;
-            }
-            if (CY[i] != 0 && (ty < 0 || ty >= g.Ly)) {
-                if (g.py) ty = wrap(ty, g.Ly); else wall = true;
-            }
-            if (CZ[i] != 0 && (tz < 0 || tz >= g.Lz)) {
-                if (g.pz) tz = wrap(tz, g.Lz); else wall = true;
-            }
-            if (!wall) {
-                gb[i] = fbin[i * N + tx + (long long)g.Lx * (ty + (long long)g.Ly * tz)];
-            } else {
-                const double v = fbin[opp(i) * N + n];
-                gb[i] = v;
-                const double s = -6.0 * wgt<double>(i) * rho0 * v;
-                const double wv[3] = {xr + 0.5 * CX[i], yr + 0.5 * CY[i], zr + 0.5 * CZ[i]};
-                const int ci[3] = {CX[i], CY[i], CZ[i]};
+            for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) dA[3 * a + b] += s * ci[a] * wv[b];
-            }
-        }
-        const double rho = rho_[n];
-        const double ux = u_[n], uy = u_[N + n], uz = u_[2 * N + n];
-        const double Fx = F_[n], Fy = F_[N + n], Fz = F_[2 * N + n];
-        double ex = ubar[n], ey = ubar[N + n], ez = ubar[2 * N + n];
-        if (ex != 0.0 || ey != 0.0 || ez != 0.0) {
-            ubar[n] = 0.0;
-            ubar[N + n] = 0.0;
-            ubar[2 * N + n] = 0.0;
-        }
-        const double om = lp.omega, kg = lp.kguo;
-        const double uu = ux * ux + uy * uy + uz * uz;
-        double rb = 0.0, ubx = ex, uby = ey, ubz = ez, fbx = 0.0, fby = 0.0, fbz = 0.0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double w = wgt<double>(i);
-            const double cx = CX[i], cy = CY[i], cz = CZ[i];
-            const double cu = cx * ux + cy * uy + cz * uz;
-            const double cF = cx * Fx + cy * Fy + cz * Fz;
-            const double gi = gb[i];
-            rb += gi * w * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-            // omega df^eq_i/du_a = omega w rho (3 c_a + 9 cu c_a - 3 u_a); dS_i/du_a = kg w (9 c_a cF - 3 F_a)
-            const double e1 = om * w * rho * (3.0 + 9.0 * cu) + kg * w * 9.0 * cF;
-            const double e2 = -om * w * rho * 3.0;
-            const double e3 = -kg * w * 3.0;
-            ubx += gi * (e1 * cx + e2 * ux + e3 * Fx);
-            uby += gi * (e1 * cy + e2 * uy + e3 * Fy);
-            ubz += gi * (e1 * cz + e2 * uz + e3 * Fz);
-            // dS_i/dF_a = kg w (3 c_a - 3 u_a + 9 cu c_a)
-            const double h1 = kg * w * (3.0 + 9.0 * cu), h2 = -kg * w * 3.0;
-            fbx += gi * (h1 * cx + h2 * ux);
-            fby += gi * (h1 * cy + h2 * uy);
-            fbz += gi * (h1 * cz + h2 * uz);
-        }
-        rb *= om;
-        const double inv = 1.0 / rho;
-        const double ubu = ubx * ux + uby * uy + ubz * uz;
-#pragma unroll
-        for (int j = 0; j < Q; ++j) {
-            const double ubc = ubx * CX[j] + uby * CY[j] + ubz * CZ[j];
-            fbout[j * N + n] = (1.0 - om) * gb[j] + rb + (ubc - ubu) * inv;
-        }
-        Fbar[n] = fbx + 0.5 * ubx * inv;
-        Fbar[N + n] = fby + 0.5 * uby * inv;
-        Fbar[2 * N + n] = fbz + 0.5 * ubz * inv;
+                for (int b = 0; b < 3; ++b) dA[3 * a + b] += sv * ci[a] * wv[b];
+        });
     }
     __shared__ double red[9][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -623,7 +743,7 @@ hipError_t launch_adj_hc(int nv, const int4* fan, const SmoothParams& sp, int it
 
 hipError_t launch_adj_ib_spread(const Geom& g, int nv, const double4* pos, const AdjVerts& v, double* ubar,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_spread, dim3(nblk(nv, 4)), dim3(256), 0, s, g, nv, pos, v.Ob, ubar);
+    hipLaunchKernelGGL(k_adj_spread, dim3(nblk(nv, IB_PATCH)), dim3(256), 0, s, g, nv, pos, v.Ob, ubar);
     return hipGetLastError();
 }
 
