@@ -150,7 +150,7 @@ DTYPE = {"f64": "f64", "f32": "f32", "f16dev": "f16", "bf16dev": "bf16"}
 
 
 def droplet_leg(dev, w, storage, K, W, reps=5, variant=None, chi=1.0, collision="bgk", walls="link",
-                box="256cubed"):
+                deterministic=False, box="256cubed"):
     """One droplet workload `w` with `storage` populations: W warm-up steps,
     then `reps` timed runs of K whole steps (hipStream synchronised around
     each; the median is reported), then K more steps with HIP events stamped
@@ -161,7 +161,8 @@ def droplet_leg(dev, w, storage, K, W, reps=5, variant=None, chi=1.0, collision=
     from paper_2403_01161_amd.inputs import ou_gradient_table
     table = ou_gradient_table(W + (reps + 1) * K + 1, w["corr"], w["G"], seed=w["seed"])
     sim = ibmlb.Simulation(w["L"], w["tau"], w["sigma"], w["R"], w["V"], w["T"], storage=storage,
-                           A0=table[0], device=dev, chi=chi, collision=collision, walls=walls)
+                           A0=table[0], device=dev, chi=chi, collision=collision, walls=walls,
+                           deterministic=deterministic)
     dtab = torch.from_numpy(table).to(dev)
     nodes = int(np.prod(w["L"]))
     nv = len(w["V"])
@@ -209,13 +210,14 @@ def droplet_leg(dev, w, storage, K, W, reps=5, variant=None, chi=1.0, collision=
                             "mass_drift_rel": (obs["mass"] - obs0["mass"]) / obs0["mass"]}}
 
 
-def workload_name(w, storage, chi=1.0, collision="bgk", walls="link"):
+def workload_name(w, storage, chi=1.0, collision="bgk", walls="link", deterministic=False):
     L = w["L"][0]
     return (f"single droplet, {L}^3 moving-wall box, tau {w['tau']:g}, R {w['R']:g}, {len(w['V'])}-vertex "
             f"icosphere, OU traceless A(t) rms Ca {w['Ca']:g}, {storage} populations"
             + (f", viscosity ratio {chi:g}" if chi != 1.0 else "")
             + (", MRT collision" if collision == "mrt" else "")
-            + (", wet-node walls" if walls == "wet" else ""))
+            + (", wet-node walls" if walls == "wet" else "")
+            + (", deterministic spreading" if deterministic else ""))
 
 
 def kernel_source_hash():
@@ -521,6 +523,8 @@ def main():
                     help="collision of the headline leg (MRT: default rates)")
     ap.add_argument("--walls", default="link", choices=["link", "wet"],
                     help="wall rule of the headline leg (wet: the wet-node velocity walls)")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="headline leg with the deterministic (fixed-order gather) spreading")
     ap.add_argument("--counters", nargs="?", const="128", choices=["128", "256"], default=None,
                     help="short fixed sequence for hardware-counter runs: 3 device copies of "
                          "256 MiB (calibration) and 20 steps of the single-droplet workload")
@@ -540,7 +544,7 @@ def main():
         print(json.dumps({"precision": precision_bench(dev, args.precision)}), flush=True)
         return
     K, W = args.steps, args.warmup
-    variant_kw = dict(chi=args.chi, collision=args.collision, walls=args.walls)
+    variant_kw = dict(chi=args.chi, collision=args.collision, walls=args.walls, deterministic=args.deterministic)
     w = precision_workload() if args.box == "256" else workload(args.storage)
     box = f"{args.box}cubed"
     head = droplet_leg(dev, w, args.storage, K, W, variant=args.variant, box=box, **variant_kw)
@@ -561,7 +565,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_name(w, args.storage, **variant_kw), "box": list(w["L"]),
                    "vertices": len(w["V"]), "storage": args.storage, "chi": args.chi,
-                   "collision": args.collision, "walls": args.walls,
+                   "collision": args.collision, "walls": args.walls, "deterministic": args.deterministic,
                    "timing": "median of 5 timed runs of `steps` steps"},
         "roofline": head["roofline"],
     }
@@ -569,7 +573,7 @@ def main():
               "hbm_frac_whole_step", "observables"):
         line[k] = head[k]
     extras = not args.no_extras
-    plain = args.chi == 1.0 and args.collision == "bgk" and args.walls == "link"
+    plain = args.chi == 1.0 and args.collision == "bgk" and args.walls == "link" and not args.deterministic
     if extras and not args.no_formats and plain:
         fm = {}
         for st in ("f64", "f32", "f16dev", "bf16dev"):

@@ -141,6 +141,16 @@ typedef struct ibm_lb_config {
                               on any axis (a droplet across a periodic boundary) ends the run
                               with IBM_LB_EDOMAIN. The initial non-equilibrium part uses tau
                               everywhere */
+    int32_t deterministic; /* spreading (Sec. 3.1, Eq. ibm_force_d, first line). 0: each surface
+                              patch sums its vertices' contributions in an FP64 LDS window with
+                              LDS atomics and adds it to F with device atomics, so the order of
+                              the additions, and the last bits of F, may change from run to run.
+                              1: every node of a tile touched by a stencil gathers its
+                              contributions in increasing vertex order, in FP64, and F is stored
+                              once per node: a run repeats bit for bit (and differs from mode 0
+                              by the order of the additions only). Single droplets; the
+                              workspace grows by 76 B (FP64: 136 B) per vertex and 32 B per
+                              64-vertex patch */
 } ibm_lb_config;
 
 typedef struct ibm_lb_obs {

@@ -46,7 +46,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 // Byte offsets of every device array inside one workspace.
 struct Layout {
     size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, tris, fan, lfan, hstart, hids, obs_part, mass_part,
-        obs_out, Abuf, red, ind, ind_lines, ptris, ptstart, perm, total;
+        obs_out, Abuf, red, ind, ind_lines, ptris, ptstart, perm, det, pbox, total;
 };
 
 // Per vertex: valence m and the one-ring neighbours n_0 .. n_{m-1} in
@@ -60,7 +60,7 @@ struct MeshCSR {
 // ind_b, lines: bytes of the indicator and x-rows of the lattice when the
 // droplet has a viscosity ratio, else 0.
 Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t nhalo, int copies, size_t ind_b = 0,
-                   size_t lines = 0) {
+                   size_t lines = 0, bool det = false) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -97,6 +97,9 @@ Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t 
     L.ptris = take(ind_b ? sizeof(int4) * (size_t)nt : 0);
     L.ptstart = take(ind_b ? sizeof(int) * ((size_t)(nv + IB_PATCH - 1) / IB_PATCH + 1) : 0);
     L.perm = take(sizeof(int) * (size_t)nv);
+    const size_t npatch = (size_t)(nv + IB_PATCH - 1) / IB_PATCH;
+    L.det = take(det ? det_rec_bytes(storage) * (size_t)nv : 0);
+    L.pbox = take(det ? sizeof(int) * 8 * npatch : 0);
     L.total = off;
     return L;
 }
@@ -140,6 +143,7 @@ int validate(const ibm_lb_config* c) {
         return fail(IBM_LB_EINVAL, "wet-node walls run with two population copies");
     if (!(c->chi >= 0.0 && c->chi <= 1e6)) return fail(IBM_LB_EINVAL, "chi must lie in [0, 1e6]");
     if (chi_active(c) && c->collision != IBM_LB_BGK) return fail(IBM_LB_EINVAL, "a viscosity ratio runs BGK");
+    if (c->deterministic != 0 && c->deterministic != 1) return fail(IBM_LB_EINVAL, "deterministic must be 0 or 1");
     const int nv = c->n_vertices, nt = c->n_triangles;
     if (nv < 0 || nt < 0) return fail(IBM_LB_EINVAL, "negative mesh size");
     if (nv == 0 && nt == 0) return IBM_LB_OK;
@@ -625,7 +629,7 @@ int ibm_lb_workspace_size(const ibm_lb_config* cfg, size_t* bytes) {
     const bool chi = chi_active(cfg);
     *bytes = make_layout(cfg->storage, g.N, g.TX * g.TY * g.TZ, cfg->n_vertices, cfg->n_triangles,
                          m.halos.hids.size(), cfg->populations == 1 ? 1 : 2, chi ? ind_bytes(g) : 0,
-                         chi ? (size_t)g.Ly * g.Lz : 0)
+                         chi ? (size_t)g.Ly * g.Lz : 0, cfg->deterministic == 1 && cfg->n_vertices > 0)
                  .total;
     return IBM_LB_OK;
 }
@@ -690,8 +694,9 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
         for (int k = 0; k < 19; ++k) h->mrt_rates.s[k] = rate[k];
     }
     if (h->single) h->lattice_variant = VAR_AA | VAR_HC_SPLIT;
+    const bool det = cfg->deterministic == 1 && h->nv > 0;
     h->lay = make_layout(h->storage, h->g.N, ntiles, h->nv, h->nt, mesh.halos.hids.size(), h->single ? 1 : 2,
-                         h->chi ? ind_bytes(h->g) : 0, h->chi ? (size_t)h->g.Ly * h->g.Lz : 0);
+                         h->chi ? ind_bytes(h->g) : 0, h->chi ? (size_t)h->g.Ly * h->g.Lz : 0, det);
     if (cfg->workspace) {
         if (cfg->workspace_bytes < h->lay.total)
             return bail(fail(IBM_LB_ENOMEM, "workspace smaller than ibm_lb_workspace_size"));
@@ -742,6 +747,8 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     d.ptris = h->chi ? (int4*)(b + L.ptris) : nullptr;
     d.ptstart = h->chi ? (int*)(b + L.ptstart) : nullptr;
     d.perm = (int*)(b + L.perm);
+    d.det = det ? (void*)(b + L.det) : nullptr;
+    d.pbox = det ? (int*)(b + L.pbox) : nullptr;
     h->perm = mesh.perm;
     if (h->nv > 0) {
         e = patch_setup(h->storage);
@@ -1434,6 +1441,7 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
         if (cfgs[i].collision != IBM_LB_BGK) return fail(IBM_LB_EINVAL, "ensemble members run BGK");
         if (cfgs[i].walls != IBM_LB_WALLS_LINK) return fail(IBM_LB_EINVAL, "ensemble members run link walls");
         if (chi_active(&cfgs[i])) return fail(IBM_LB_EINVAL, "ensemble members run one fluid");
+        if (cfgs[i].deterministic) return fail(IBM_LB_EINVAL, "ensemble members spread with atomics");
     }
     ibm_lb_batch* b = new (std::nothrow) ibm_lb_batch();
     if (!b) return fail(IBM_LB_ENOMEM, "host allocation");

@@ -55,6 +55,16 @@ struct PtrT<T, 1> {
 template <class T, int AS>
 using Ptr = typename PtrT<T, AS>::type;
 
+// Deterministic spreading: the staged stencil of a vertex, written by the
+// force kernel for the gather that follows it.
+template <class R>
+struct DetRec {
+    int fw[3];  // first stencil node, wrapped into the box
+    int ok;     // 0: no valid stencil (the error flag is raised)
+    R w[3][4];  // Peskin weights per axis
+    R val[3];   // force
+};
+
 template <class R, int AS = 0>
 struct IbArgs {
     Geom g;
@@ -76,6 +86,8 @@ struct IbArgs {
     Ptr<int, AS> mark;
     Ptr<Ctl, AS> ctl;
     Ptr<unsigned long long, AS> red;  // grid-wide max of |p - q| (bit pattern of a non-negative real)
+    Ptr<DetRec<R>, AS> det;      // [nv] staged stencils for the deterministic spreading, or null
+    Ptr<int, AS> pbox;           // [npatch][8] window of each patch (origin, extent), with det
     int wcap;                    // LDS window capacity in nodes
 };
 
@@ -102,6 +114,8 @@ __device__ inline IbArgs<R, 1> to_global(const IbArgs<R, 0>& a) {
     b.mark = (Ptr<int, 1>)a.mark;
     b.ctl = (Ptr<Ctl, 1>)a.ctl;
     b.red = (Ptr<unsigned long long, 1>)a.red;
+    b.det = (Ptr<DetRec<R>, 1>)a.det;
+    b.pbox = (Ptr<int, 1>)a.pbox;
     b.wcap = a.wcap;
     return b;
 }
@@ -323,6 +337,33 @@ __device__ bool spread_window(const IbArgs<R, AS>& a, const Stage<R>& st, double
     return true;
 }
 
+// Deterministic spreading, first half: the patch's staged stencils and its
+// window go to memory instead of into the atomics.
+template <class R, int AS>
+__device__ void det_stage(const IbArgs<R, AS>& a, int p, const Stage<R>& st) {
+    const int t = threadIdx.x;
+    const int k = p * PATCH + t;
+    const bool own = t < PATCH && k < a.nv;
+    const int tv = t < PATCH ? t : 0;
+    const int f[3] = {st.first[tv][0], st.first[tv][1], st.first[tv][2]};
+    const Win w = block_window(own && st.ok[tv], f, 0x7fffffff);
+    if (own) {
+        const int L[3] = {a.g.Lx, a.g.Ly, a.g.Lz};
+        const int ok = st.ok[t];
+        auto rec = a.det + k;
+        for (int d = 0; d < 3; ++d) {
+            rec->fw[d] = wrap_any(f[d], L[d]);
+            for (int j = 0; j < 4; ++j) rec->w[d][j] = ok ? st.w[t][d][j] : R(0);
+            rec->val[d] = ok ? st.val[t][d] : R(0);
+        }
+        rec->ok = ok;
+    }
+    if (t < 3) {
+        a.pbox[8 * p + t] = w.o[t];
+        a.pbox[8 * p + 3 + t] = w.e[t];
+    }
+}
+
 // The triangles each patch crosses with the lattice rows (viscosity ratio
 // only): those whose lowest vertex id lies in the patch, listed patch by
 // patch, and the indicator's toggle words and row ranges.
@@ -386,6 +427,10 @@ __device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, 
         }
     }
     __syncthreads();
+    if (a.det) {
+        det_stage(a, p, st);
+        return;
+    }
     if (spread_window(a, st, win, 0, PATCH)) return;
     // a patch too spread out for the window: direct global atomics
     const int lane = t & 63, jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
@@ -412,6 +457,100 @@ __global__ __launch_bounds__(IBT) void k_fs_patch_ind(IbArgs<R> a, const V4<R>* 
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ Stage<R> st;
     fs_patch<R, 0, true>(a, blockIdx.x, P, commit, st, reinterpret_cast<double*>(dyn), &ia);
+}
+
+// Deterministic spreading, second half (Eq. ibm_force_d, first line, as a
+// gather): one work-group per 8^3 tile, one thread per node. A tile marked
+// for this step takes the patches whose windows meet it in increasing patch
+// order, stages each one's records in LDS, and every node adds the
+// contributions of the patch's vertices in increasing order, in FP64; F is
+// stored once per node. Each node's sum is therefore taken in one order
+// (increasing vertex index) whatever the scheduling, and a run repeats bit
+// for bit. The window atomics above differ from it only by the order of
+// their additions (and, for FP32, by rounding each patch's part to FP32).
+static_assert(TILE_SHIFT == 3, "the gather maps one 512-thread work-group onto an 8^3 tile");
+constexpr int DET_T = 512;
+
+__device__ inline int pmod(int a, int L) {
+    const int m = a % L;
+    return m < 0 ? m + L : m;
+}
+
+template <class R>
+__global__ __launch_bounds__(DET_T) void k_spread_det(IbArgs<R> a, int npatch) {
+    __shared__ DetRec<R> sv[PATCH];
+    __shared__ int cand[DET_T];
+    __shared__ int wcount[DET_T / 64];
+    const int tile = blockIdx.x;
+    if (a.mark[tile] != a.ctl->epoch) return;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int L[3] = {a.g.Lx, a.g.Ly, a.g.Lz};
+    const int T0[3] = {(tile % a.g.TX) << TILE_SHIFT, ((tile / a.g.TX) % a.g.TY) << TILE_SHIFT,
+                       (tile / (a.g.TX * a.g.TY)) << TILE_SHIFT};
+    const int x = T0[0] + (t & 7), y = T0[1] + ((t >> 3) & 7), z = T0[2] + (t >> 6);
+    const bool act = x < L[0] && y < L[1] && z < L[2];
+    int cnt[3];
+    for (int d = 0; d < 3; ++d) cnt[d] = min(8, L[d] - T0[d]);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int base = 0; base < npatch; base += DET_T) {
+        // which of these patches' windows meet the tile (a window covers the
+        // nodes o .. o + e - 1 of each axis, folded into the box)
+        const int p = base + t;
+        bool meet = p < npatch;
+        if (meet)
+            for (int d = 0; d < 3; ++d) {
+                const int o = a.pbox[8 * p + d], e = a.pbox[8 * p + 3 + d];
+                meet = meet && e > 0 && (pmod(T0[d] - o, L[d]) < e || pmod(o - T0[d], L[d]) < cnt[d]);
+            }
+        // their list in increasing order
+        const unsigned long long m = __ballot(meet);
+        if (lane == 0) wcount[wv] = __popcll(m);
+        __syncthreads();
+        int off = 0, total = 0;
+        for (int i = 0; i < DET_T / 64; ++i) {
+            off += i < wv ? wcount[i] : 0;
+            total += wcount[i];
+        }
+        if (meet) cand[off + __popcll(m & ((1ull << lane) - 1ull))] = p;
+        __syncthreads();
+        for (int c = 0; c < total; ++c) {
+            const int q = cand[c];
+            if (t < PATCH) {
+                const int k = q * PATCH + t;
+                if (k < a.nv) sv[t] = a.det[k];
+                else sv[t].ok = 0;
+            }
+            __syncthreads();
+            if (act)
+                for (int v = 0; v < PATCH; ++v) {
+                    if (!sv[v].ok) continue;
+                    // offsets into the stencil; a node before the first one
+                    // folds to at least 4 (walls: the stencil ends 4 nodes
+                    // inside; periodic: the box has at least 8 nodes)
+                    int dx = x - sv[v].fw[0], dy = y - sv[v].fw[1], dz = z - sv[v].fw[2];
+                    dx += dx < 0 ? L[0] : 0;
+                    dy += dy < 0 ? L[1] : 0;
+                    dz += dz < 0 ? L[2] : 0;
+                    if (dx > 3 || dy > 3 || dz > 3) continue;
+                    const double wt = double(sv[v].w[0][dx]) * double(sv[v].w[1][dy]) * double(sv[v].w[2][dz]);
+                    acc[0] += double(sv[v].val[0]) * wt;
+                    acc[1] += double(sv[v].val[1]) * wt;
+                    acc[2] += double(sv[v].val[2]) * wt;
+                }
+            __syncthreads();
+        }
+    }
+    if (act) {
+        const long long N = a.g.N;
+        const long long n = x + (long long)L[0] * (y + (long long)L[1] * z);
+        a.F[n] = R(acc[0]);
+        a.F[N + n] = R(acc[1]);
+        a.F[2 * N + n] = R(acc[2]);
+    }
+}
+
+size_t det_rec_bytes(int storage) {
+    return storage == IBM_LB_F64 ? sizeof(DetRec<double>) : sizeof(DetRec<float>);
 }
 
 // ---------------------------------------------------------------- interpolation
@@ -780,6 +919,8 @@ static IbArgs<R> make_args(const Geom& g, const DevPtrs& d, int nv, double sigma
     a.mark = d.mark;
     a.ctl = d.ctl;
     a.red = d.red;
+    a.det = (DetRec<R>*)d.det;
+    a.pbox = d.pbox;
     a.wcap = patch_window_nodes(sizeof(R) == 8 ? IBM_LB_F64 : IBM_LB_F32);
     return a;
 }
@@ -832,12 +973,17 @@ static hipError_t launch_step_t(const Geom& g, const DevPtrs& d, int nv, double 
     const V4<R>* final_pos = sp.max_iter > 0 ? a.qa : a.o;
     hipLaunchKernelGGL(k_hc_fused<R>, dim3(npatch), dim3(IBT), 0, s, a, (int)npatch, hc_split ? 1 : 0);
     if (hc_split) hipLaunchKernelGGL(k_hc_finish<R>, dim3(1), dim3(1024), 0, s, a);
+    // the stop event of the last launch before the next lattice kernel
+    hipEvent_t fs_done = d.det ? nullptr : done;
     if (d.ind)
         hipExtLaunchKernelGGL(k_fs_patch_ind<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr,
-                              done, 0, a, final_pos, 1, ind_args(g, d));
+                              fs_done, 0, a, final_pos, 1, ind_args(g, d));
     else
-        hipExtLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr, done,
-                              0, a, final_pos, 1);
+        hipExtLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr,
+                              fs_done, 0, a, final_pos, 1);
+    if (d.det)
+        hipExtLaunchKernelGGL(k_spread_det<R>, dim3(g.TX * g.TY * g.TZ), dim3(DET_T), 0, s, nullptr, done, 0, a,
+                              (int)npatch);
     return hipGetLastError();
 }
 
@@ -889,6 +1035,8 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
                                ind_args(g, d));
         else
             hipLaunchKernelGGL(k_fs_patch<double>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<double>*)a.r, 0);
+        if (d.det)
+            hipLaunchKernelGGL(k_spread_det<double>, dim3(g.TX * g.TY * g.TZ), dim3(DET_T), 0, s, a, (int)npatch);
     } else {
         IbArgs<float> a = make_args<float>(g, d, nv, sigma, sp);
         if (d.ind)
@@ -896,6 +1044,8 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
                                ind_args(g, d));
         else
             hipLaunchKernelGGL(k_fs_patch<float>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<float>*)a.r, 0);
+        if (d.det)
+            hipLaunchKernelGGL(k_spread_det<float>, dim3(g.TX * g.TY * g.TZ), dim3(DET_T), 0, s, a, (int)npatch);
     }
     return hipGetLastError();
 }

@@ -93,6 +93,8 @@ struct DevPtrs {
     int4* ptris;             // [nt] triangles grouped by the patch of their lowest vertex (viscosity ratio only)
     int* ptstart;            // [npatch + 1] start of each patch's triangles (viscosity ratio only)
     int* perm;               // [nv] caller index of each internal vertex
+    void* det;               // [nv] staged stencils of the deterministic spreading, or null
+    int* pbox;               // [npatch][8] patch windows of the deterministic spreading
 };
 
 // Bytes of the indicator array (whole 32-bit words, for the atomic toggles).
@@ -211,6 +213,8 @@ hipError_t launch_positions_from_abs(int storage, const Geom& g, const DevPtrs& 
 // runs as a launch of its own instead of in the last work-group to arrive.
 hipError_t patch_setup(int storage);
 int patch_window_nodes(int storage);
+// Bytes of one vertex's staged stencil for the deterministic spreading.
+size_t det_rec_bytes(int storage);
 hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,
                          const SmoothParams& sp, hipStream_t s);
 hipError_t launch_ib_step(int storage, const Geom& g, const DevPtrs& d, int nv, double sigma,

@@ -47,7 +47,7 @@ class Config(C.Structure):
                 ("init", C.c_int32), ("A0", C.c_double * 9), ("f16_scale", C.c_double),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("populations", C.c_int32), ("collision", C.c_int32), ("mrt_s", C.c_double * 5),
-                ("walls", C.c_int32), ("chi", C.c_double)]
+                ("walls", C.c_int32), ("chi", C.c_double), ("deterministic", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -129,7 +129,7 @@ def _dp(a):
 def make_config(L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None, periodic=(0, 0, 0),
                 storage="f32", init="linear", A0=None, rho0=1.0, reg_alpha=0.1, reg_gamma=0.51,
                 reg_tol=0.01, reg_max_iter=50, reg_sign=1, f16_scale=0.0, populations=2, collision="bgk",
-                mrt_s=None, walls="link", chi=1.0):
+                mrt_s=None, walls="link", chi=1.0, deterministic=False):
     """Fill an ibm_lb_config; returns (config, keep-alive arrays)."""
     cfg = Config()
     for a in range(3):
@@ -159,6 +159,7 @@ def make_config(L, tau, sigma=0.0, radius=1.0, vertices=None, triangles=None, pe
         cfg.mrt_s[k] = float(v)
     cfg.walls = {"link": 0, "wet": 1}[walls] if isinstance(walls, str) else int(walls)
     cfg.chi = float(chi)
+    cfg.deterministic = int(deterministic)
     return cfg, (V, T)
 
 

@@ -93,12 +93,32 @@ def test_ensemble_rejects_one_copy_members(ib):
     assert not b.value
 
 
+def test_deterministic_spreading_sizes(ib):
+    """The deterministic spreading stages 76 B (FP64: 136 B) per vertex and a
+    32 B window per 64-vertex patch; ensembles refuse it."""
+    import ctypes as C
+    for storage, rec in (("f32", 76), ("f64", 136)):
+        cfg, keep = _cfg(ib, storage=storage)
+        n0 = _size_rc(ib, cfg)[1]
+        cfg.deterministic = 1
+        rc, n1 = _size_rc(ib, cfg)
+        nv = cfg.n_vertices
+        extra = rec * nv + 32 * ((nv + 63) // 64)
+        assert rc == 0 and abs((n1 - n0) - extra) <= 512, (storage, n1 - n0, extra)  # 256-byte alignment
+    cfgs = (ib.Config * 1)()
+    c, k = ib.make_config((8, 8, 8), 0.8, deterministic=1)
+    cfgs[0] = c
+    b = C.c_void_p()
+    assert ib.lib().ibm_lb_batch_init(cfgs, 1, None, C.byref(b)) == ib.EINVAL
+    assert not b.value
+
+
 @pytest.mark.parametrize("bad", [
     dict(L=(7, 16, 16)), dict(tau=0.5), dict(sigma=-1.0), dict(radius=0.0), dict(rho0=0.0),
     dict(storage=7), dict(init=5), dict(reg_sign=2), dict(reg_max_iter=-1),
     dict(f16_scale=3.0, storage="f16dev"), dict(A0=[np.nan] + [0] * 8), dict(populations=3),
     dict(collision=2), dict(collision="mrt", mrt_s=[2.0, 1, 1, 1, 1]), dict(collision="mrt", populations=1),
-    dict(walls=2), dict(walls="wet", populations=1),
+    dict(walls=2), dict(walls="wet", populations=1), dict(deterministic=2),
 ])
 def test_invalid_parameters(ib, bad):
     cfg, keep = _cfg(ib, **bad)

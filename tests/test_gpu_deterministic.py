@@ -1,0 +1,137 @@
+"""Deterministic spreading (configuration field `deterministic`): every node
+of a marked tile gathers its force contributions in increasing vertex order,
+in FP64, instead of the patch windows' atomics.
+
+* FP64 against the oracle at the round-off bars of the atomics path: a walled
+  ragged box, a droplet wrapped around a periodic corner, and a viscosity
+  ratio (the force kernel's indicator form);
+* run to run: two handles on the same inputs hold the same state bytes after
+  an OU run, in the linear and the row layout of the lattice kernel;
+* checkpoint and resume: 100 steps equal 50 + save/load + 50, bit for bit;
+* against the atomics path in FP32: equal to FP32 rounding (only the order of
+  the additions differs).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_01161_amd.inputs import box_center, icosphere, ou_gradient_table, simple_shear
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = dict(tol_r=1e-11, tol_u=1e-11, tol_rho=1e-13)
+
+
+@pytest.fixture(scope="module")
+def ib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_01161_amd import ibmlb
+    ibmlb.lib()
+    return ibmlb
+
+
+def _traceless(scale, seed):
+    A = np.random.default_rng(seed).standard_normal((3, 3))
+    A -= np.trace(A) / 3 * np.eye(3)
+    return (scale * A / np.linalg.norm(A)).ravel()
+
+
+def _compare(sim, ref, tol_r, tol_u, tol_rho):
+    dr = np.abs(sim.vertices() - ref.vertices()).max()
+    rho_g, u_g = sim.fields()
+    rho_r, u_r = ref.fields()
+    du = np.abs(u_g - u_r).max() / np.abs(u_r).max()
+    drho = np.abs(rho_g - rho_r).max()
+    print(f"  max|dr| {dr:.2e}, max|du|/max|u| {du:.2e}, max|drho| {drho:.2e}", flush=True)
+    assert dr <= tol_r and du <= tol_u and drho <= tol_rho
+
+
+CASES = {
+    "walls_ragged": dict(L=(19, 17, 21), R=3.2, level=2, steps=30, A=_traceless(3e-3, 2),
+                         kw=dict(tau=0.9, sigma=0.02)),
+    "periodic_corner": dict(L=(12, 13, 16), R=2.5, level=2, steps=25, A=np.zeros(9), center=(0.3, 12.6, 0.0),
+                            kw=dict(tau=0.8, sigma=0.03, periodic=(1, 1, 1))),
+    "viscosity_ratio": dict(L=(16, 18, 16), R=3.5, level=2, steps=30, A=simple_shear(2e-3),
+                            kw=dict(tau=0.9, sigma=0.02, chi=4.0)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_f64_matches_oracle(ib, case):
+    c = CASES[case]
+    L = c["L"]
+    V, T = icosphere(c["level"], c["R"], c.get("center", box_center(L)))
+    kw = dict(radius=c["R"], vertices=V, triangles=T, A0=c["A"], **c["kw"])
+    print(f"case {case}: L={L} nv={len(V)} FP64, deterministic spreading", flush=True)
+    sim = ib.Simulation(L, storage="f64", deterministic=True, **kw)
+    ref = oracle.Oracle(L, **kw)
+    sim.step(c["A"], c["steps"])
+    ref.step(c["A"], c["steps"])
+    _compare(sim, ref, **F64_TOL)
+    sim.close()
+    ref.close()
+
+
+def _ou_case(n):
+    L = (48, 48, 48)
+    V, T = icosphere(3, 8.0, box_center(L))
+    table = ou_gradient_table(n + 1, 50.0, 4e-3, seed=17)
+    kw = dict(tau=0.9, sigma=(1 / 6) * 4e-3 * 8.0 / 0.1, radius=8.0, vertices=V, triangles=T, A0=table[0])
+    return L, kw, table
+
+
+def _state(sim):
+    return sim.save().cpu().numpy()
+
+
+def test_repeats_bit_for_bit(ib):
+    L, kw, table = _ou_case(400)
+    print(f"case 48^3 FP32, 400 OU steps, three deterministic handles", flush=True)
+    states = []
+    for variant in (33, 33, 32 | 16 | 8 | 1):  # linear (twice), then the row layout
+        sim = ib.Simulation(L, storage="f32", deterministic=True, **kw)
+        sim.set_variant(variant)
+        sim.step_table(table[1:])
+        states.append(_state(sim))
+        sim.close()
+    assert states[0].size > 0
+    assert np.array_equal(states[0], states[1]), "deterministic runs differ"
+    assert np.array_equal(states[0], states[2]), "linear and row layouts differ"
+
+
+def test_checkpoint_resume_bit_for_bit(ib):
+    L, kw, table = _ou_case(100)
+    print("case 48^3 FP32: 100 steps against 50 + save/load + 50", flush=True)
+    full = ib.Simulation(L, storage="f32", deterministic=True, **kw)
+    full.step_table(table[1:101])
+    half = ib.Simulation(L, storage="f32", deterministic=True, **kw)
+    half.step_table(table[1:51])
+    ck = half.save()
+    half.close()
+    resumed = ib.Simulation(L, storage="f32", deterministic=True, **kw)
+    resumed.load(ck)
+    resumed.step_table(table[51:101])
+    assert resumed.observables()["step"] == 100
+    assert np.array_equal(_state(full), _state(resumed))
+    full.close()
+    resumed.close()
+
+
+def test_f32_matches_atomics(ib):
+    L, kw, table = _ou_case(300)
+    print("case 48^3 FP32, 300 OU steps: deterministic against atomics", flush=True)
+    det = ib.Simulation(L, storage="f32", deterministic=True, **kw)
+    ato = ib.Simulation(L, storage="f32", **kw)
+    det.step_table(table[1:])
+    ato.step_table(table[1:])
+    dr = np.abs(det.vertices() - ato.vertices()).max()
+    _, ud = det.fields()
+    _, ua = ato.fields()
+    du = np.abs(ud - ua).max() / np.abs(ua).max()
+    Dd, Da = det.observables()["D"], ato.observables()["D"]
+    print(f"  max|dr| {dr:.2e}, max|du|/max|u| {du:.2e}, dD/D {abs(Dd - Da) / Da:.2e}", flush=True)
+    assert dr <= 2e-5 and du <= 2e-4 and abs(Dd - Da) <= 1e-5 * Da
+    det.close()
+    ato.close()
