@@ -34,13 +34,27 @@ __device__ inline double4 cross3(double4 a, double4 b) {
 
 // ---------------------------------------------------------------- recording
 // rho, u (with F/2) and F of the current populations on every node: the
-// state the lattice kernel of this step will see.
+// state the lattice kernel of this step will see. The work-groups after the
+// node range record the vertex positions, and the first of them the
+// previous step's smoothing iteration count (when prev_iters is not null).
 template <class C>
 __global__ __launch_bounds__(256) void k_rec_fields(Geom g, LatticeParams lp, const typename C::store_t* __restrict__ fin,
                                                     const typename C::real* __restrict__ F,
                                                     const int* __restrict__ mark, const Ctl* __restrict__ ctl, int ib,
                                                     double* __restrict__ rho, double* __restrict__ u,
-                                                    double* __restrict__ Fo) {
+                                                    double* __restrict__ Fo, int nv,
+                                                    const V4<typename C::real>* __restrict__ r,
+                                                    double4* __restrict__ pos, int* __restrict__ prev_iters) {
+    const long long nbN = (g.N + 255) / 256;
+    if ((long long)blockIdx.x >= nbN) {
+        const int k = int(((long long)blockIdx.x - nbN) * 256) + threadIdx.x;
+        if (k < nv) {
+            const V4<typename C::real> p = r[k];
+            pos[k] = d4(double(p.x), double(p.y), double(p.z));
+        }
+        if (k == 0 && prev_iters) *prev_iters = ctl->iters;
+        return;
+    }
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
     const long long N = g.N;
@@ -64,22 +78,14 @@ __global__ __launch_bounds__(256) void k_rec_fields(Geom g, LatticeParams lp, co
             Fz = double(F[2 * N + n]);
         }
     }
-    const double r = lp.rho0 + dr;
-    rho[n] = r;
-    u[n] = (jx + 0.5 * Fx) / r;
-    u[N + n] = (jy + 0.5 * Fy) / r;
-    u[2 * N + n] = (jz + 0.5 * Fz) / r;
+    const double rh = lp.rho0 + dr;
+    rho[n] = rh;
+    u[n] = (jx + 0.5 * Fx) / rh;
+    u[N + n] = (jy + 0.5 * Fy) / rh;
+    u[2 * N + n] = (jz + 0.5 * Fz) / rh;
     Fo[n] = Fx;
     Fo[N + n] = Fy;
     Fo[2 * N + n] = Fz;
-}
-
-template <class R>
-__global__ void k_rec_pos(int nv, const V4<R>* __restrict__ r, double4* __restrict__ out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nv) return;
-    const V4<R> p = r[k];
-    out[k] = d4(double(p.x), double(p.y), double(p.z));
 }
 
 __global__ void k_rec_iters(const Ctl* ctl, int* slot) {
@@ -92,18 +98,9 @@ __global__ void k_rec_iters(const Ctl* ctl, int* slot) {
 // Transpose for an incoming pbar:
 //   bbar = -g pbar - s (1-g) M^T pbar,   p'bar = pbar + bbar,
 //   obar += a pbar,   qbar = -(1-a) bbar + (1-a) M^T p'bar,
-// with (M^T y)_j = sum_{k in ring(j)} y_k / m_k. After the m iterations
-// (q_0 = o), obar += qbar. PS and PpS hold P / m and P' / m.
-__global__ void k_adj_hc_init(int nv, const int4* __restrict__ fan, const double4* __restrict__ rb,
-                              double4* __restrict__ P, double4* __restrict__ PS, double4* __restrict__ Ob) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nv) return;
-    const double4 v = rb[k];
-    P[k] = v;
-    PS[k] = (1.0 / double(fan[4 * k].x)) * v;
-    Ob[k] = d4(0.0, 0.0, 0.0);
-}
-
+// with (M^T y)_j = sum_{k in ring(j)} y_k / m_k. The sweep starts from
+// pbar = rbar with obar = 0, and after the m iterations (q_0 = o) obar +=
+// qbar. PS and PpS hold P / m and P' / m.
 __device__ inline double4 ring_total(const int4* fan, const double4* X, int k, int* m_out) {
     int nb[MAXV];
     const int m = load_fan(fan, k, nb);
@@ -142,10 +139,44 @@ __global__ void k_adj_hc_b(int nv, const int4* __restrict__ fan, double alpha, c
     PS[k] = (1.0 / double(m)) * q;
 }
 
-__global__ void k_adj_hc_end(int nv, const double4* __restrict__ P, double4* __restrict__ Ob) {
+// The first iteration's pass a with the initialisation folded in (P = rbar,
+// PS = rbar / m, obar = 0 before it), and the last iteration's pass b with
+// the final obar += qbar folded in: the same operations in the same order.
+__global__ void k_adj_hc_a_first(int nv, const int4* __restrict__ fan, double alpha, double gamma, double sgn,
+                                 const double4* __restrict__ rb, double4* __restrict__ Pp, double4* __restrict__ PpS,
+                                 double4* __restrict__ Ob, double4* __restrict__ Qp) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nv) return;
-    Ob[k] = Ob[k] + P[k];
+    int nb[MAXV];
+    const int m = load_fan(fan, k, nb);
+    double4 s = d4(0.0, 0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+        if (j < m) s = s + (1.0 / double(fan[4 * nb[j]].x)) * rb[nb[j]];
+    const double4 p = rb[k];
+    const double4 bb = (-gamma) * p - (sgn * (1.0 - gamma)) * s;
+    const double4 pp = p + bb;
+    Pp[k] = pp;
+    PpS[k] = (1.0 / double(m)) * pp;
+    Ob[k] = alpha * p;
+    Qp[k] = (-(1.0 - alpha)) * bb;
+}
+
+__global__ void k_adj_hc_b_last(int nv, const int4* __restrict__ fan, double alpha, const double4* __restrict__ PpS,
+                                const double4* __restrict__ Qp, double4* __restrict__ Ob) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    int m;
+    const double4 s = ring_total(fan, PpS, k, &m);
+    const double4 q = Qp[k] + (1.0 - alpha) * s;
+    Ob[k] = Ob[k] + q;
+}
+
+// No smoothing iteration in the forward step: obar = rbar.
+__global__ void k_adj_hc_none(int nv, const double4* __restrict__ rb, double4* __restrict__ Ob) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    Ob[k] = rb[k];
 }
 
 // ---------------------------------------------------------------- stencils (FP64)
@@ -417,17 +448,26 @@ __global__ __launch_bounds__(256) void k_adj_lattice(Geom g, LatticeParams lp, c
                 for (int b = 0; b < 3; ++b) dA[3 * a + b] += sv * ci[a] * wv[b];
         });
     }
-    __shared__ double red[9][4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // fixed-order work-group sums through LDS: 72 threads add runs of 32
+    // nodes, then 9 threads add the 8 runs
+    __shared__ double red[9][256];
+    __shared__ double run[9][8];
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-        const double v = wave_sum(dA[c]);
-        if (lane == 0) red[c][wv] = v;
+    for (int c = 0; c < 9; ++c) red[c][t] = dA[c];
+    __syncthreads();
+    if (t < 72) {
+        const int c = t >> 3, r0 = (t & 7) * 32;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < 32; ++i) acc += red[c][r0 + i];
+        run[c][t & 7] = acc;
     }
     __syncthreads();
-    if (threadIdx.x < 9) {
-        const int c = threadIdx.x;
-        part[(long long)blockIdx.x * 9 + c] = ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3];
+    if (t < 9) {
+        double acc = run[t][0];
+        for (int r = 1; r < 8; ++r) acc += run[t][r];
+        part[(long long)blockIdx.x * 9 + t] = acc;
     }
 }
 
@@ -711,14 +751,13 @@ static inline unsigned nblk(long long n, int bs) { return unsigned((n + bs - 1) 
     }
 
 hipError_t launch_adj_record(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                             int nv, const AdjStep& st, hipStream_t s) {
+                             int nv, const AdjStep& st, int* prev_iters, hipStream_t s) {
     ADJ_DISPATCH_STORAGE(storage, C, {
         using R = typename C::real;
-        hipLaunchKernelGGL(k_rec_fields<C>, dim3(nblk(g.N, 256)), dim3(256), 0, s, g, lp,
+        const unsigned nbv = nv > 0 ? nblk(nv, 256) : (prev_iters ? 1u : 0u);
+        hipLaunchKernelGGL(k_rec_fields<C>, dim3(nblk(g.N, 256) + nbv), dim3(256), 0, s, g, lp,
                            (const typename C::store_t*)d.f[cur], (const R*)d.F, d.mark, d.ctl, nv > 0 ? 1 : 0,
-                           st.rho, st.u, st.F);
-        if (nv > 0)
-            hipLaunchKernelGGL(k_rec_pos<R>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, (const V4<R>*)d.r, st.pos);
+                           st.rho, st.u, st.F, nv, (const V4<R>*)d.r, st.pos, prev_iters);
     });
     return hipGetLastError();
 }
@@ -731,13 +770,22 @@ hipError_t launch_adj_record_iters(const DevPtrs& d, int* slot, hipStream_t s) {
 hipError_t launch_adj_hc(int nv, const int4* fan, const SmoothParams& sp, int iters, const AdjVerts& v,
                          hipStream_t s) {
     const unsigned nb = nblk(nv, 256);
-    hipLaunchKernelGGL(k_adj_hc_init, dim3(nb), dim3(256), 0, s, nv, fan, v.rb, v.P, v.PS, v.Ob);
-    for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL(k_adj_hc_a, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, sp.gamma, double(sp.sign), v.P,
-                           v.PS, v.Pp, v.PpS, v.Ob, v.Qp);
-        hipLaunchKernelGGL(k_adj_hc_b, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, v.PpS, v.Qp, v.P, v.PS);
+    if (iters == 0) {
+        hipLaunchKernelGGL(k_adj_hc_none, dim3(nb), dim3(256), 0, s, nv, v.rb, v.Ob);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_adj_hc_end, dim3(nb), dim3(256), 0, s, nv, v.P, v.Ob);
+    for (int it = 0; it < iters; ++it) {
+        if (it == 0)
+            hipLaunchKernelGGL(k_adj_hc_a_first, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, sp.gamma,
+                               double(sp.sign), v.rb, v.Pp, v.PpS, v.Ob, v.Qp);
+        else
+            hipLaunchKernelGGL(k_adj_hc_a, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, sp.gamma, double(sp.sign),
+                               v.P, v.PS, v.Pp, v.PpS, v.Ob, v.Qp);
+        if (it == iters - 1)
+            hipLaunchKernelGGL(k_adj_hc_b_last, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, v.PpS, v.Qp, v.Ob);
+        else
+            hipLaunchKernelGGL(k_adj_hc_b, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, v.PpS, v.Qp, v.P, v.PS);
+    }
     return hipGetLastError();
 }
 

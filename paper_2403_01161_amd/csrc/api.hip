@@ -1339,14 +1339,16 @@ int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const
             rc = ensure_force(h);
             if (rc) return rc;
             if ((rc = ensure_natural(h))) return rc;
-            HIP_TRY(launch_adj_record(h->storage, h->g, h->lp, h->d, h->cur, nv, adj_step(h, done + j), s),
+            // the record of step done + j also takes step done + j - 1's iteration count
+            HIP_TRY(launch_adj_record(h->storage, h->g, h->lp, h->d, h->cur, nv, adj_step(h, done + j),
+                                      done + j > 0 ? h->adj_iters + done + j - 1 : nullptr, s),
                     "record launch");
             rc = enqueue_steps(h, rows + 9ll * j, 1, 1);
             if (rc) return rc;
-            HIP_TRY(launch_adj_record_iters(h->d, h->adj_iters + done + j, s), "record iterations");
         }
         done += n;
     }
+    HIP_TRY(launch_adj_record_iters(h->d, h->adj_iters + nsteps - 1, s), "record iterations");
     std::vector<int> iters(nsteps);
     HIP_TRY(hipMemcpyAsync(iters.data(), h->adj_iters, sizeof(int) * nsteps, hipMemcpyDeviceToHost, s),
             "read iteration counts");

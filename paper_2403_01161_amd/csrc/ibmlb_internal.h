@@ -258,7 +258,7 @@ struct AdjVerts {
 };
 
 hipError_t launch_adj_record(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                             int nv, const AdjStep& st, hipStream_t s);
+                             int nv, const AdjStep& st, int* prev_iters, hipStream_t s);
 hipError_t launch_adj_record_iters(const DevPtrs& d, int* slot, hipStream_t s);
 hipError_t launch_adj_hc(int nv, const int4* fan, const SmoothParams& sp, int iters, const AdjVerts& v,
                          hipStream_t s);
