@@ -460,84 +460,132 @@ __global__ __launch_bounds__(IBT) void k_fs_patch_ind(IbArgs<R> a, const V4<R>* 
 }
 
 // Deterministic spreading, second half (Eq. ibm_force_d, first line, as a
-// gather): one work-group per 8^3 tile, one thread per node. A tile marked
-// for this step takes the patches whose windows meet it in increasing patch
-// order, stages each one's records in LDS, and every node adds the
-// contributions of the patch's vertices in increasing order, in FP64; F is
-// stored once per node. Each node's sum is therefore taken in one order
-// (increasing vertex index) whatever the scheduling, and a run repeats bit
-// for bit. The window atomics above differ from it only by the order of
-// their additions (and, for FP32, by rounding each patch's part to FP32).
-static_assert(TILE_SHIFT == 3, "the gather maps one 512-thread work-group onto an 8^3 tile");
-constexpr int DET_T = 512;
+// gather): one single-wave work-group per z-slice of an 8^3 tile, one lane
+// per node of the 8 x 8 slice. A tile marked for this step goes through the
+// patches 64 at a time; those whose windows meet the slice are taken in
+// increasing patch order, DET_CB at a time (lane v loads vertex v of each,
+// all loads in flight together). For each patch in turn, the vertices whose
+// stencils reach the slice are listed in LDS in increasing order (a ballot
+// and prefix count), and every lane adds their contributions to its node in
+// that order, in FP64. F is stored once per
+// node. Each node's sum is therefore taken in one order (increasing vertex
+// index) whatever the scheduling, and a run repeats bit for bit. The window
+// atomics above differ from it only by the order of their additions (and,
+// for FP32, by rounding each patch's part to FP32).
+static_assert(TILE_SHIFT == 3, "the gather maps one wave onto an 8 x 8 slice of an 8^3 tile");
+constexpr int DET_SLICES = 8;
 
 __device__ inline int pmod(int a, int L) {
     const int m = a % L;
     return m < 0 ? m + L : m;
 }
 
+// Does the window origin o, extent e (unwrapped) cover any of the nodes
+// t0 .. t0 + n - 1 of an axis of L nodes?
+__device__ inline bool covers(int o, int e, int t0, int n, int L) {
+    return e > 0 && (pmod(t0 - o, L) < e || pmod(o - t0, L) < n);
+}
+
+constexpr int DET_CB = 4;  // candidate patches loaded per round
+
 template <class R>
-__global__ __launch_bounds__(DET_T) void k_spread_det(IbArgs<R> a, int npatch) {
-    __shared__ DetRec<R> sv[PATCH];
-    __shared__ int cand[DET_T];
-    __shared__ int wcount[DET_T / 64];
-    const int tile = blockIdx.x;
+__global__ __launch_bounds__(64) void k_spread_det(IbArgs<R> a, int npatch) {
+    // the vertices of one candidate patch that reach the slice, compacted in
+    // increasing order
+    __shared__ int4 sfw[PATCH];     // first stencil node (folded)
+    __shared__ R sw[PATCH][3][4];   // weights
+    __shared__ R sval[PATCH][3];    // forces
+    const int tile = blockIdx.x / DET_SLICES, zs = blockIdx.x % DET_SLICES;
     if (a.mark[tile] != a.ctl->epoch) return;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int lane = threadIdx.x;
     const int L[3] = {a.g.Lx, a.g.Ly, a.g.Lz};
     const int T0[3] = {(tile % a.g.TX) << TILE_SHIFT, ((tile / a.g.TX) % a.g.TY) << TILE_SHIFT,
-                       (tile / (a.g.TX * a.g.TY)) << TILE_SHIFT};
-    const int x = T0[0] + (t & 7), y = T0[1] + ((t >> 3) & 7), z = T0[2] + (t >> 6);
-    const bool act = x < L[0] && y < L[1] && z < L[2];
-    int cnt[3];
-    for (int d = 0; d < 3; ++d) cnt[d] = min(8, L[d] - T0[d]);
+                       ((tile / (a.g.TX * a.g.TY)) << TILE_SHIFT) + zs};
+    if (T0[2] >= L[2]) return;  // a slice beyond a ragged z end
+    const int cnt[3] = {min(8, L[0] - T0[0]), min(8, L[1] - T0[1]), 1};
+    const int x = T0[0] + (lane & 7), y = T0[1] + (lane >> 3), z = T0[2];
+    const bool act = x < L[0] && y < L[1];
+    const unsigned long long below = (1ull << lane) - 1ull;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int base = 0; base < npatch; base += DET_T) {
-        // which of these patches' windows meet the tile (a window covers the
-        // nodes o .. o + e - 1 of each axis, folded into the box)
-        const int p = base + t;
+    for (int base = 0; base < npatch; base += 64) {
+        // lane l tests patch base + l
+        const int p = base + lane;
         bool meet = p < npatch;
         if (meet)
-            for (int d = 0; d < 3; ++d) {
-                const int o = a.pbox[8 * p + d], e = a.pbox[8 * p + 3 + d];
-                meet = meet && e > 0 && (pmod(T0[d] - o, L[d]) < e || pmod(o - T0[d], L[d]) < cnt[d]);
+            for (int d = 0; d < 3; ++d)
+                meet = meet && covers(a.pbox[8 * p + d], a.pbox[8 * p + 3 + d], T0[d], cnt[d], L[d]);
+        unsigned long long m = __ballot(meet);
+        while (m) {
+            // the next DET_CB candidates in increasing order; lane v loads
+            // vertex v of each (all loads in flight together)
+            int qc[DET_CB];
+            int nc = 0;
+#pragma unroll
+            for (int c = 0; c < DET_CB; ++c) {
+                qc[c] = -1;
+                if (m) {
+                    qc[c] = base + __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    nc = c + 1;
+                }
             }
-        // their list in increasing order
-        const unsigned long long m = __ballot(meet);
-        if (lane == 0) wcount[wv] = __popcll(m);
-        __syncthreads();
-        int off = 0, total = 0;
-        for (int i = 0; i < DET_T / 64; ++i) {
-            off += i < wv ? wcount[i] : 0;
-            total += wcount[i];
-        }
-        if (meet) cand[off + __popcll(m & ((1ull << lane) - 1ull))] = p;
-        __syncthreads();
-        for (int c = 0; c < total; ++c) {
-            const int q = cand[c];
-            if (t < PATCH) {
-                const int k = q * PATCH + t;
-                if (k < a.nv) sv[t] = a.det[k];
-                else sv[t].ok = 0;
+            int fw[DET_CB][3], ok[DET_CB];
+            R w[DET_CB][3][4], val[DET_CB][3];
+#pragma unroll
+            for (int c = 0; c < DET_CB; ++c) {
+                const int k = qc[c] * PATCH + lane;
+                ok[c] = 0;
+                if (qc[c] >= 0 && k < a.nv) {
+                    const DetRec<R>* r = a.det + k;
+                    ok[c] = r->ok;
+                    for (int d = 0; d < 3; ++d) {
+                        fw[c][d] = r->fw[d];
+                        val[c][d] = r->val[d];
+                        for (int j = 0; j < 4; ++j) w[c][d][j] = r->w[d][j];
+                    }
+                }
             }
-            __syncthreads();
-            if (act)
-                for (int v = 0; v < PATCH; ++v) {
-                    if (!sv[v].ok) continue;
+#pragma unroll
+            for (int c = 0; c < DET_CB; ++c) {
+                if (c >= nc) break;
+                // does this lane's vertex reach the slice? (its stencil covers
+                // z and meets the slice's x and y ranges)
+                bool rel = ok[c] != 0;
+                if (rel) {
+                    int dz = z - fw[c][2];
+                    dz += dz < 0 ? L[2] : 0;
+                    rel = dz <= 3 && covers(fw[c][0], 4, T0[0], cnt[0], L[0]) && covers(fw[c][1], 4, T0[1], cnt[1], L[1]);
+                }
+                const unsigned long long rm = __ballot(rel);
+                if (rm == 0ull) continue;
+                __syncthreads();  // the previous candidate's list is consumed
+                if (rel) {
+                    const int slot = __popcll(rm & below);
+                    sfw[slot] = make_int4(fw[c][0], fw[c][1], fw[c][2], 0);
+                    for (int d = 0; d < 3; ++d) {
+                        for (int j = 0; j < 4; ++j) sw[slot][d][j] = w[c][d][j];
+                        sval[slot][d] = val[c][d];
+                    }
+                }
+                __syncthreads();
+                const int nrel = __popcll(rm);
+                if (!act) continue;
+                for (int v = 0; v < nrel; ++v) {
+                    const int4 f = sfw[v];
                     // offsets into the stencil; a node before the first one
                     // folds to at least 4 (walls: the stencil ends 4 nodes
                     // inside; periodic: the box has at least 8 nodes)
-                    int dx = x - sv[v].fw[0], dy = y - sv[v].fw[1], dz = z - sv[v].fw[2];
+                    int dx = x - f.x, dy = y - f.y, dz = z - f.z;
                     dx += dx < 0 ? L[0] : 0;
                     dy += dy < 0 ? L[1] : 0;
                     dz += dz < 0 ? L[2] : 0;
                     if (dx > 3 || dy > 3 || dz > 3) continue;
-                    const double wt = double(sv[v].w[0][dx]) * double(sv[v].w[1][dy]) * double(sv[v].w[2][dz]);
-                    acc[0] += double(sv[v].val[0]) * wt;
-                    acc[1] += double(sv[v].val[1]) * wt;
-                    acc[2] += double(sv[v].val[2]) * wt;
+                    const double wt = double(sw[v][0][dx]) * double(sw[v][1][dy]) * double(sw[v][2][dz]);
+                    acc[0] += double(sval[v][0]) * wt;
+                    acc[1] += double(sval[v][1]) * wt;
+                    acc[2] += double(sval[v][2]) * wt;
                 }
-            __syncthreads();
+            }
         }
     }
     if (act) {
@@ -982,8 +1030,8 @@ static hipError_t launch_step_t(const Geom& g, const DevPtrs& d, int nv, double 
         hipExtLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr,
                               fs_done, 0, a, final_pos, 1);
     if (d.det)
-        hipExtLaunchKernelGGL(k_spread_det<R>, dim3(g.TX * g.TY * g.TZ), dim3(DET_T), 0, s, nullptr, done, 0, a,
-                              (int)npatch);
+        hipExtLaunchKernelGGL(k_spread_det<R>, dim3(g.TX * g.TY * g.TZ * DET_SLICES), dim3(64), 0, s, nullptr, done,
+                              0, a, (int)npatch);
     return hipGetLastError();
 }
 
@@ -1036,7 +1084,8 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
         else
             hipLaunchKernelGGL(k_fs_patch<double>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<double>*)a.r, 0);
         if (d.det)
-            hipLaunchKernelGGL(k_spread_det<double>, dim3(g.TX * g.TY * g.TZ), dim3(DET_T), 0, s, a, (int)npatch);
+            hipLaunchKernelGGL(k_spread_det<double>, dim3(g.TX * g.TY * g.TZ * DET_SLICES), dim3(64), 0, s, a,
+                               (int)npatch);
     } else {
         IbArgs<float> a = make_args<float>(g, d, nv, sigma, sp);
         if (d.ind)
@@ -1045,7 +1094,8 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
         else
             hipLaunchKernelGGL(k_fs_patch<float>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<float>*)a.r, 0);
         if (d.det)
-            hipLaunchKernelGGL(k_spread_det<float>, dim3(g.TX * g.TY * g.TZ), dim3(DET_T), 0, s, a, (int)npatch);
+            hipLaunchKernelGGL(k_spread_det<float>, dim3(g.TX * g.TY * g.TZ * DET_SLICES), dim3(64), 0, s, a,
+                               (int)npatch);
     }
     return hipGetLastError();
 }
