@@ -130,7 +130,7 @@ def describe_variant(v):
         d["nontemporal_stores"] = bool(v & 8)
     else:
         d["xcd_grouped_order"] = bool(v & 8)
-    d["smoothing_finish_launch"] = bool(v & 32)
+    d["smoothing_finish_in_force_kernel"] = bool(v & 32)
     d["in_place_streaming"] = bool(v & 64)
     return d
 

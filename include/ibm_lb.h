@@ -249,10 +249,14 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  *             contiguous eighth of the lattice; row layout: non-temporal
  *             population stores.
  * Bit 5 runs the end of the smoothing (convergence test, further
- * iterations, iteration count) as a one-work-group launch of its own
- * instead of in the last of the smoothing's work-groups to finish (which
- * needs a device-scope release in every work-group); ensembles always run it
- * as its own launch and ignore the bit.
+ * iterations, iteration count) at the start of the force kernel instead of
+ * in the last of the smoothing's work-groups to finish (which needs a
+ * device-scope release in every work-group): every force work-group reads
+ * the first iteration's maximum; in the rare step that needs further
+ * iterations, the first work-group runs them and then spreads every vertex
+ * with direct atomics. With deterministic spreading the end runs as a
+ * one-work-group launch of its own; ensembles always run it so and ignore
+ * the bit.
  * Bit 6 (linear layout only; single droplets only) streams in place: one
  * population copy, read and written by the same thread at the same
  * locations, with even and odd steps in two index mappings (the AA pattern

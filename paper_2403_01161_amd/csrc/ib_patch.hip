@@ -445,18 +445,111 @@ __device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, 
 }
 
 template <class R>
-__global__ __launch_bounds__(IBT) void k_fs_patch(IbArgs<R> a, const V4<R>* P, int commit) {
+__device__ inline R from_bits(unsigned long long b);
+template <>
+__device__ inline float from_bits<float>(unsigned long long b) { return __uint_as_float((unsigned)b); }
+template <>
+__device__ inline double from_bits<double>(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+template <class R, int AS>
+__device__ int hc_more_iterations(const IbArgs<R, AS>& a, bool* capped);
+
+// The smoothing's finish folded into the force kernel (bit 5 of the step
+// variant; not with the deterministic spreading). Every work-group takes the
+// same decision from the reduction slot that the first smoothing iteration
+// filled: when that iteration converged, hit the iteration cap or smoothing
+// is off, work-group 0 records the count and every work-group treats its own
+// patch; otherwise (rare) work-group 0 alone runs the further iterations,
+// records the count and then treats every vertex with direct atomics, while
+// the others return. The step epoch was advanced and the reduction slots
+// cleared by the interpolation launch of the step.
+// Forces, tile marks and spreading of every vertex by one work-group, with
+// direct global atomics (the rare path below; the viscosity ratio's row
+// crossings of every triangle with CHI).
+template <class R, bool CHI>
+__device__ void fs_all_vertices(const IbArgs<R>& a, const V4<R>* P, int commit, const IndArgs* ia, int npatch) {
+    const int t = threadIdx.x;
+    const int ep = a.ctl->epoch;
+    const long long N = a.g.N;
+    for (int k = t; k < a.nv; k += IBT) {
+        const V4<R> pos = ld4<V4<R>>(P + k);
+        if (commit) st4(a.r + k, pos);
+        int f[3];
+        R w[3][4];
+        if (!stencil_of(a, pos, f, w)) continue;
+        R fx, fy, fz;
+        force_of(a, P, k, pos, fx, fy, fz);
+        mark_tiles(a, f, ep);
+        for (int j = 0; j < 64; ++j) {
+            const int jx = j & 3, jy = (j >> 2) & 3, jz = j >> 4;
+            const R wt = w[0][jx] * w[1][jy] * w[2][jz];
+            const long long n = node_index(a.g, f[0] + jx, f[1] + jy, f[2] + jz);
+            atom_add(a.F + n, fx * wt);
+            atom_add(a.F + N + n, fy * wt);
+            atom_add(a.F + 2 * N + n, fz * wt);
+        }
+    }
+    if constexpr (CHI) {
+        const double xc[3] = {a.g.xci[0] + a.g.xcf[0], a.g.xci[1] + a.g.xcf[1], a.g.xci[2] + a.g.xcf[2]};
+        for (int q = t; q < ia->ptstart[npatch]; q += IBT) {
+            const int4 tv = ia->ptris[q];
+            const int id[3] = {tv.x, tv.y, tv.z};
+            double Pd[3][3];
+            for (int c = 0; c < 3; ++c) {
+                const V4<R> pc = ld4<V4<R>>(P + id[c]);
+                Pd[c][0] = double(pc.x) + xc[0];
+                Pd[c][1] = double(pc.y) + xc[1];
+                Pd[c][2] = double(pc.z) + xc[2];
+            }
+            triangle_row_crossings(a.g, id, Pd, ia->words, ia->lo, ia->hi, ia->flags);
+        }
+    }
+}
+
+template <class R, bool CHI>
+__device__ void fs_step(const IbArgs<R>& a, int fold, int npatch, const V4<R>* P, int commit, Stage<R>& st,
+                        double* win, const IndArgs* ia) {
+    const int t = threadIdx.x;
+    if (fold) {
+        bool more = false, capped = false;
+        if (a.sp.max_iter > 0) {
+            const bool converged = from_bits<R>(*a.red) < R(a.sp.tol);
+            capped = !converged && a.sp.max_iter <= 1;
+            more = !converged && !capped;
+        }
+        if (more) {
+            if (blockIdx.x != 0) return;
+            const int it = hc_more_iterations(a, &capped);
+            if (t == 0) {
+                a.ctl->iters = it;
+                if (capped) a.ctl->cap_hits += 1;
+            }
+            __syncthreads();  // the final positions in qa, written by this work-group
+            fs_all_vertices<R, CHI>(a, P, commit, ia, npatch);
+            return;
+        }
+        if (blockIdx.x == 0 && t == 0) {
+            a.ctl->iters = a.sp.max_iter > 0 ? 1 : 0;
+            if (capped) a.ctl->cap_hits += 1;
+        }
+    }
+    fs_patch<R, 0, CHI>(a, blockIdx.x, P, commit, st, win, ia);
+}
+
+template <class R>
+__global__ __launch_bounds__(IBT) void k_fs_patch(IbArgs<R> a, const V4<R>* P, int commit, int fold, int npatch) {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ Stage<R> st;
-    fs_patch(a, blockIdx.x, P, commit, st, reinterpret_cast<double*>(dyn));
+    fs_step<R, false>(a, fold, npatch, P, commit, st, reinterpret_cast<double*>(dyn), nullptr);
 }
 
 // The same with the row crossings of the viscosity ratio's indicator.
 template <class R>
-__global__ __launch_bounds__(IBT) void k_fs_patch_ind(IbArgs<R> a, const V4<R>* P, int commit, IndArgs ia) {
+__global__ __launch_bounds__(IBT) void k_fs_patch_ind(IbArgs<R> a, const V4<R>* P, int commit, IndArgs ia, int fold,
+                                                      int npatch) {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ Stage<R> st;
-    fs_patch<R, 0, true>(a, blockIdx.x, P, commit, st, reinterpret_cast<double*>(dyn), &ia);
+    fs_step<R, true>(a, fold, npatch, P, commit, st, reinterpret_cast<double*>(dyn), &ia);
 }
 
 // Deterministic spreading, second half (Eq. ibm_force_d, first line, as a
@@ -663,8 +756,16 @@ __device__ void interp_patch(const IbArgs<R, AS>& a, int patch, R* win) {
 }
 
 template <class R>
-__global__ __launch_bounds__(IBT) void k_interp_patch(IbArgs<R> a) {
+__global__ __launch_bounds__(IBT) void k_interp_patch(IbArgs<R> a, int fold) {
     extern __shared__ __align__(16) unsigned char dyn[];
+    // the step's reduction slots start at zero; with the smoothing's finish
+    // folded into the force kernel, the step epoch advances here (nothing
+    // between this launch and the force kernel reads it)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.red[0] = 0ull;
+        a.red[1] = 0ull;
+        if (fold) a.ctl->epoch += 1;
+    }
     interp_patch(a, blockIdx.x, reinterpret_cast<R*>(dyn));
 }
 
@@ -722,13 +823,6 @@ template <>
 __device__ inline unsigned long long max_bits<double>(double v) {
     return (unsigned long long)__double_as_longlong(v);
 }
-template <class R>
-__device__ inline R from_bits(unsigned long long b);
-template <>
-__device__ inline float from_bits<float>(unsigned long long b) { return __uint_as_float((unsigned)b); }
-template <>
-__device__ inline double from_bits<double>(unsigned long long b) { return __longlong_as_double((long long)b); }
-
 template <class R, int AS>
 __device__ void hc_finish(const IbArgs<R, AS>& a);
 
@@ -833,29 +927,22 @@ __global__ __launch_bounds__(IBT) void k_hc_fused(IbArgs<R> a, int npatch, int s
     hc_fused(a, blockIdx.x, npatch, split != 0);
 }
 
-// Split smoothing of one droplet: the finish as a launch of its own.
+// Split smoothing of one droplet with the deterministic spreading: the finish
+// as a launch of its own.
 template <class R>
 __global__ __launch_bounds__(1024) void k_hc_finish(IbArgs<R> a) {
     hc_finish(a);
 }
 
 // One work-group, after iteration 1 is in qa and its maximum in the
-// reduction slot: continue while not converged (rare), leave the final
-// positions in qa, record the iteration count, advance the epoch and reset
-// both reduction slots.
+// reduction slot (smoothing on): continue while not converged (rare) and
+// leave the final positions in qa. Returns the iteration count; *capped_out
+// tells whether the cap ended it.
 template <class R, int AS>
-__device__ void hc_finish(const IbArgs<R, AS>& a) {
+__device__ int hc_more_iterations(const IbArgs<R, AS>& a, bool* capped_out) {
     __shared__ R bred[16];
     __shared__ int more;
     const int t = threadIdx.x, nth = blockDim.x;
-    if (a.sp.max_iter <= 0) {
-        if (t == 0) {
-            a.ctl->iters = 0;
-            a.ctl->epoch += 1;
-            a.red[1] = 0ull;
-        }
-        return;
-    }
     const R alpha = R(a.sp.alpha), gamma = R(a.sp.gamma), tol = R(a.sp.tol), sgn = R(a.sp.sign);
     const R dmax = from_bits<R>(*a.red);
     int it = 1;
@@ -888,6 +975,26 @@ __device__ void hc_finish(const IbArgs<R, AS>& a) {
     // the newest iterate is in q
     if (q != a.qa)
         for (int k = t; k < a.nv; k += nth) st4(a.qa + k, ld4<V4<R>>(q + k));
+    *capped_out = capped;
+    return it;
+}
+
+// The finish of a step's smoothing in one work-group (the last smoothing
+// work-group to arrive, or one per ensemble member): further iterations if
+// needed, the iteration count, the epoch, and both reduction slots reset.
+template <class R, int AS>
+__device__ void hc_finish(const IbArgs<R, AS>& a) {
+    const int t = threadIdx.x;
+    if (a.sp.max_iter <= 0) {
+        if (t == 0) {
+            a.ctl->iters = 0;
+            a.ctl->epoch += 1;
+            a.red[1] = 0ull;
+        }
+        return;
+    }
+    bool capped = false;
+    const int it = hc_more_iterations(a, &capped);
     if (t == 0) {
         a.ctl->iters = it;
         if (capped) a.ctl->cap_hits += 1;
@@ -1017,18 +1124,21 @@ static hipError_t launch_step_t(const Geom& g, const DevPtrs& d, int nv, double 
                                 hipStream_t s, size_t lds, hipEvent_t done, bool hc_split) {
     IbArgs<R> a = make_args<R>(g, d, nv, sigma, sp);
     const unsigned npatch = (nv + PATCH - 1) / PATCH;
-    hipLaunchKernelGGL(k_interp_patch<R>, dim3(npatch), dim3(IBT), lds, s, a);
+    // split smoothing: its finish folded into the force kernel, or (with the
+    // deterministic spreading) a launch of its own
+    const int fold = hc_split && !d.det ? 1 : 0;
+    hipLaunchKernelGGL(k_interp_patch<R>, dim3(npatch), dim3(IBT), lds, s, a, fold);
     const V4<R>* final_pos = sp.max_iter > 0 ? a.qa : a.o;
     hipLaunchKernelGGL(k_hc_fused<R>, dim3(npatch), dim3(IBT), 0, s, a, (int)npatch, hc_split ? 1 : 0);
-    if (hc_split) hipLaunchKernelGGL(k_hc_finish<R>, dim3(1), dim3(1024), 0, s, a);
+    if (hc_split && !fold) hipLaunchKernelGGL(k_hc_finish<R>, dim3(1), dim3(1024), 0, s, a);
     // the stop event of the last launch before the next lattice kernel
     hipEvent_t fs_done = d.det ? nullptr : done;
     if (d.ind)
         hipExtLaunchKernelGGL(k_fs_patch_ind<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr,
-                              fs_done, 0, a, final_pos, 1, ind_args(g, d));
+                              fs_done, 0, a, final_pos, 1, ind_args(g, d), fold, (int)npatch);
     else
         hipExtLaunchKernelGGL(k_fs_patch<R>, dim3(npatch), dim3(IBT), uint32_t(dyn_lds_spread()), s, nullptr,
-                              fs_done, 0, a, final_pos, 1);
+                              fs_done, 0, a, final_pos, 1, fold, (int)npatch);
     if (d.det)
         hipExtLaunchKernelGGL(k_spread_det<R>, dim3(g.TX * g.TY * g.TZ * DET_SLICES), dim3(64), 0, s, nullptr, done,
                               0, a, (int)npatch);
@@ -1080,9 +1190,10 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
         IbArgs<double> a = make_args<double>(g, d, nv, sigma, sp);
         if (d.ind)
             hipLaunchKernelGGL(k_fs_patch_ind<double>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<double>*)a.r, 0,
-                               ind_args(g, d));
+                               ind_args(g, d), 0, (int)npatch);
         else
-            hipLaunchKernelGGL(k_fs_patch<double>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<double>*)a.r, 0);
+            hipLaunchKernelGGL(k_fs_patch<double>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<double>*)a.r, 0, 0,
+                               (int)npatch);
         if (d.det)
             hipLaunchKernelGGL(k_spread_det<double>, dim3(g.TX * g.TY * g.TZ * DET_SLICES), dim3(64), 0, s, a,
                                (int)npatch);
@@ -1090,9 +1201,10 @@ hipError_t launch_ib_pre(int storage, const Geom& g, const DevPtrs& d, int nv, d
         IbArgs<float> a = make_args<float>(g, d, nv, sigma, sp);
         if (d.ind)
             hipLaunchKernelGGL(k_fs_patch_ind<float>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<float>*)a.r, 0,
-                               ind_args(g, d));
+                               ind_args(g, d), 0, (int)npatch);
         else
-            hipLaunchKernelGGL(k_fs_patch<float>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<float>*)a.r, 0);
+            hipLaunchKernelGGL(k_fs_patch<float>, dim3(npatch), dim3(IBT), lds, s, a, (const V4<float>*)a.r, 0, 0,
+                               (int)npatch);
         if (d.det)
             hipLaunchKernelGGL(k_spread_det<float>, dim3(g.TX * g.TY * g.TZ * DET_SLICES), dim3(64), 0, s, a,
                                (int)npatch);

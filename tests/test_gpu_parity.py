@@ -242,3 +242,52 @@ def test_fp32_plain_geometry_200_steps(ib):
     assert abs(og["D"] - orf["D"]) <= 1e-2 * orf["D"]
     assert abs(og["theta_deg"] - orf["theta_deg"]) <= 0.5
     _compare(sim, ref, tol_r=1e-4, tol_u=1e-3, tol_rho=1e-5)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_several_smoothing_iterations_every_step(ib, storage, tol):
+    """A tolerance no smoothing iteration meets: every step runs to the cap of
+    4 iterations. On the GPU the force kernel's first work-group then runs
+    iterations 2-4 itself and spreads every vertex with direct atomics."""
+    L = (19, 17, 21)
+    A = _traceless(3e-3, 2)
+    sim, ref = _pair(ib, storage, L, R=3.2, level=2, tau=0.9, sigma=0.02, A0=A, reg_tol=1e-12, reg_max_iter=4)
+    sim.step(A, 20)
+    ref.step(A, 20)
+    _compare(sim, ref, **tol)
+    og, orf = sim.observables(), ref.observables()
+    assert og["reg_iters"] == orf["reg_iters"] == 4
+
+
+def test_smoothing_iterations_vary_between_steps(ib):
+    """A tolerance met after one to a few iterations, so that steps with one
+    iteration (the patch path) and with more (the first work-group's path)
+    alternate (the oracle takes 1 iteration in 21 of the 30 steps and 2-6 in
+    the others); FP64 against the oracle, iteration counts equal every step."""
+    L = (19, 17, 21)
+    A = _traceless(3e-3, 5)
+    sim, ref = _pair(ib, "f64", L, R=3.2, level=2, tau=0.9, sigma=0.02, A0=A, reg_tol=3e-3)
+    counts = []
+    for _ in range(30):
+        sim.step(A, 1)
+        ref.step(A, 1)
+        og, orf = sim.observables(), ref.observables()
+        assert og["reg_iters"] == orf["reg_iters"]
+        counts.append(og["reg_iters"])
+    print(f"  iteration counts {np.bincount(counts)}", flush=True)
+    assert min(counts) == 1 and max(counts) > 1
+    _compare(sim, ref, **F64_TOL)
+
+
+def test_viscosity_ratio_several_smoothing_iterations(ib):
+    """The same path with a viscosity ratio: the first work-group also crosses
+    every triangle with the lattice rows; indicator and fields against the
+    oracle (FP64)."""
+    L = (16, 18, 16)
+    A = simple_shear(2e-3)
+    sim, ref = _pair(ib, "f64", L, R=3.5, level=2, tau=0.9, sigma=0.02, A0=A, chi=4.0, reg_tol=1e-12,
+                     reg_max_iter=3)
+    sim.step(A, 20)
+    ref.step(A, 20)
+    assert np.array_equal(sim.indicator(), ref.indicator())
+    _compare(sim, ref, **F64_TOL)
