@@ -472,37 +472,35 @@ __global__ __launch_bounds__(256) void k_adj_lattice(Geom g, LatticeParams lp, c
 }
 
 // ---------------------------------------------------------------- vertex adjoints
-// Nodal surface-tension forces (FP64) of the recorded positions, same rule
-// as the forward: phi_k = -sigma sum_t n_t x (r_{n_{j+1}} - r_{n_j}) / 2.
-__global__ void k_adj_forces(int nv, const int4* __restrict__ fan, double sigma, const double4* __restrict__ pos,
-                             double4* __restrict__ phi) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nv) return;
-    int nb[MAXV];
-    const int m = load_fan(fan, k, nb);
-    const double4 pk = pos[k];
-    double4 f = d4(0.0, 0.0, 0.0);
-    for (int j = 0; j < m; ++j) {
-        const double4 pa = pos[nb[j]], pb = pos[nb[j + 1 < m ? j + 1 : 0]];
-        const double4 nn = cross3(pa - pk, pb - pk);
-        const double len = sqrt(dot3(nn, nn));
-        if (len > 0.0) f = f - (0.5 * sigma / len) * cross3(nn, pb - pa);
-    }
-    phi[k] = f;
-}
-
 // Transposes of spreading and interpolation with respect to the forces and
 // the positions. One wave per vertex, one lane per stencil node:
 //   phibar_k = sum_x Fbar(x) Delta(r_k - x)
 //   rt_k     = Ob_k + sum_x [Fbar(x).phi_k + u(x).Ubar_k] grad Delta(r_k - x)
-// (Ob = Ubar is also the direct term of the Euler move o = r + U.)
-__global__ __launch_bounds__(256) void k_adj_interp(Geom g, int nv, const double4* __restrict__ pos,
-                                                    const double4* __restrict__ phi, const double4* __restrict__ Ob,
+// (Ob = Ubar is also the direct term of the Euler move o = r + U.) The
+// vertex's force phi_k is recomputed (FP64) from the recorded positions by
+// the forward's rule, phi_k = -sigma sum_t n_t x (r_{n_{j+1}} - r_{n_j}) / 2,
+// one lane per triangle of the fan.
+__global__ __launch_bounds__(256) void k_adj_interp(Geom g, int nv, const int4* __restrict__ fan, double sigma,
+                                                    const double4* __restrict__ pos, const double4* __restrict__ Ob,
                                                     const double* __restrict__ Fbar, const double* __restrict__ u_,
                                                     double4* __restrict__ phib, double4* __restrict__ rt) {
     const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (k >= nv) return;
+    double4 phi;
+    {
+        // the fan holds 16 ints per vertex: the valence, then the ordered ring
+        const int* fi = reinterpret_cast<const int*>(fan) + 4 * 4 * (long long)k;
+        const int m = fi[0];
+        double4 term = d4(0.0, 0.0, 0.0);
+        if (lane < m) {
+            const double4 pk = pos[k], pa = pos[fi[1 + lane]], pb = pos[fi[1 + (lane + 1 < m ? lane + 1 : 0)]];
+            const double4 nn = cross3(pa - pk, pb - pk);
+            const double len = sqrt(dot3(nn, nn));
+            if (len > 0.0) term = (-0.5 * sigma / len) * cross3(nn, pb - pa);
+        }
+        phi = d4(wave_sum(term.x), wave_sum(term.y), wave_sum(term.z));
+    }
     int f[3];
     double w[3][4], dw[3][4];
     const double4 ub = Ob[k];
@@ -522,7 +520,7 @@ __global__ __launch_bounds__(256) void k_adj_interp(Geom g, int nv, const double
     const double Gz = w[0][jx] * w[1][jy] * dw[2][jz];
     const double4 fb = d4(Fbar[n], Fbar[N + n], Fbar[2 * N + n]);
     const double4 uu = d4(u_[n], u_[N + n], u_[2 * N + n]);
-    const double s = dot3(fb, phi[k]) + dot3(uu, ub);
+    const double s = dot3(fb, phi) + dot3(uu, ub);
     const double px = wave_sum(fb.x * W), py = wave_sum(fb.y * W), pz = wave_sum(fb.z * W);
     const double rx = wave_sum(s * Gx), ry = wave_sum(s * Gy), rz = wave_sum(s * Gz);
     if (lane == 0) {
@@ -807,8 +805,7 @@ hipError_t launch_adj_lattice(const Geom& g, const LatticeParams& lp, const doub
 
 hipError_t launch_adj_ib_back(const Geom& g, int nv, const int4* fan, double sigma, const AdjStep& st,
                               const double* Fbar, const AdjVerts& v, double* spart, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_forces, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, fan, sigma, st.pos, v.phi);
-    hipLaunchKernelGGL(k_adj_interp, dim3(nblk(nv, 4)), dim3(256), 0, s, g, nv, st.pos, v.phi, v.Ob, Fbar, st.u,
+    hipLaunchKernelGGL(k_adj_interp, dim3(nblk(nv, 4)), dim3(256), 0, s, g, nv, fan, sigma, st.pos, v.Ob, Fbar, st.u,
                        v.phib, v.rt);
     hipLaunchKernelGGL(k_adj_hess, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, fan, sigma, st.pos, v.phib, v.rt, v.rb,
                        spart);

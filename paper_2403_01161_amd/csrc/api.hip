@@ -1184,8 +1184,8 @@ int adj_reserve(ibm_lb* h, int steps) {
     const size_t o_sp = take(sizeof(double) * (nbv > 0 ? nbv : 1) * steps);
     const size_t o_coef = take(sizeof(double) * 16);
     const size_t o_perm = take(sizeof(int) * nv);
-    size_t o_v[10];
-    for (int k = 0; k < 10; ++k) o_v[k] = take(sizeof(double4) * nv);
+    size_t o_v[9];
+    for (int k = 0; k < 9; ++k) o_v[k] = take(sizeof(double4) * nv);
     char* b = nullptr;
     if (hipMalloc((void**)&b, off) != hipSuccess) {
         (void)hipGetLastError();
@@ -1204,9 +1204,9 @@ int adj_reserve(ibm_lb* h, int steps) {
     h->adj_spart = (double*)(b + o_sp);
     h->adj_coef = (double*)(b + o_coef);
     h->adj_perm = (int*)(b + o_perm);
-    double4** vv[10] = {&h->adj_v.rb, &h->adj_v.P,   &h->adj_v.PS,  &h->adj_v.Pp,   &h->adj_v.PpS,
-                        &h->adj_v.Ob, &h->adj_v.Qp,  &h->adj_v.phi, &h->adj_v.phib, &h->adj_v.rt};
-    for (int k = 0; k < 10; ++k) *vv[k] = (double4*)(b + o_v[k]);
+    double4** vv[9] = {&h->adj_v.rb, &h->adj_v.P,  &h->adj_v.PS,   &h->adj_v.Pp, &h->adj_v.PpS,
+                       &h->adj_v.Ob, &h->adj_v.Qp, &h->adj_v.phib, &h->adj_v.rt};
+    for (int k = 0; k < 9; ++k) *vv[k] = (double4*)(b + o_v[k]);
     if (nv > 0)
         HIP_TRY(hipMemcpy(h->adj_perm, h->perm.data(), sizeof(int) * nv, hipMemcpyHostToDevice), "perm upload");
     return IBM_LB_OK;

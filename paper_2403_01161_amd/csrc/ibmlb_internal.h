@@ -145,8 +145,9 @@ constexpr int LAT_BS[4] = {128, 256, 512, 64};
 constexpr int VAR_X = 8;
 constexpr int VAR_ROWS = 16;
 // Step variant = lattice variant (bits 0-4) + bit 5 (VAR_HC_SPLIT): the
-// smoothing's finish as a launch of its own (single droplets; ensembles
-// always split it).
+// smoothing's finish split from its first launch, folded into the force
+// kernel (single droplets; with deterministic spreading, and always for
+// ensembles, a launch of its own).
 constexpr int VAR_HC_SPLIT = 32;
 // Bit 6 (VAR_AA): one population copy updated in place, even and odd steps
 // alternating (linear layout only).
@@ -252,7 +253,6 @@ struct AdjVerts {
     double4* PpS;            // Pp / valence
     double4* Ob;             // adjoint of o (= of U)
     double4* Qp;             // partial adjoint of q
-    double4* phi;            // recomputed nodal forces
     double4* phib;           // adjoint of the nodal forces
     double4* rt;             // adjoint of the positions before the force term
 };
