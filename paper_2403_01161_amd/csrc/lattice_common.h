@@ -72,6 +72,27 @@ __host__ __device__ constexpr int mrt_norm2(int k) {
     return s;
 }
 
+// Weighted moments of the basis rows, in units of 1/36 (36 w_i = 12, 2, 1):
+// sum_i m_ki 36 w_i, sum_i m_ki 36 w_i c_ia and sum_i m_ki 36 w_i c_ia c_ib.
+// Moment k of any field w_i (a + b.c_i + c_i^T C c_i) follows from them.
+__host__ __device__ constexpr int w36(int i) { return i == 0 ? 12 : (i <= 6 ? 2 : 1); }
+__host__ __device__ constexpr int cc(int i, int a) { return a == 0 ? CX[i] : (a == 1 ? CY[i] : CZ[i]); }
+__host__ __device__ constexpr int mrt_w0(int k) {
+    int s = 0;
+    for (int i = 0; i < Q; ++i) s += mrt_m(k, i) * w36(i);
+    return s;
+}
+__host__ __device__ constexpr int mrt_w1(int k, int a) {
+    int s = 0;
+    for (int i = 0; i < Q; ++i) s += mrt_m(k, i) * w36(i) * cc(i, a);
+    return s;
+}
+__host__ __device__ constexpr int mrt_w2(int k, int a, int b) {
+    int s = 0;
+    for (int i = 0; i < Q; ++i) s += mrt_m(k, i) * w36(i) * cc(i, a) * cc(i, b);
+    return s;
+}
+
 // ---------------------------------------------------------------- storage
 struct SF64 { using store_t = double; using real = double; };
 struct SF32 { using store_t = float; using real = float; };

@@ -247,28 +247,46 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
     };
 
     if constexpr (MRT) {
-        R nq[Q], gq[Q];
-        static_for<0, Q>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const R w = wgt<R>(i);
-            const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
-            const R cF = R(CX[i]) * Fx + R(CY[i]) * Fy + R(CZ[i]) * Fz;
-            nq[i] = d[i] - w * (drho + rho * (R(4.5) * cu * cu + R(3) * cu - R(1.5) * usq));
-            gq[i] = w * (R(3) * (cF - uF) + R(9) * cu * cF);
-        });
+        // Moment k of the non-equilibrium part and of the Guo term. The
+        // equilibrium deviation w_i (drho - 1.5 rho u.u + 3 rho c_i.u + 4.5 rho
+        // (c_i.u)^2) and the Guo term w_i (3 c_i.F - 3 u.F + 9 (c_i.u)(c_i.F))
+        // are quadratic in c_i, so their moments come from the basis rows'
+        // weighted moments (compile-time integers, most of them zero); only
+        // the populations' moments sum over i. The basis is orthogonal, so
+        // the updates of the other moments leave sum_i m_ki d_i unchanged and
+        // d can be updated moment by moment.
+        const R uv[3] = {ux, uy, uz}, Fv[3] = {Fx, Fy, Fz};
+        const R e0 = drho - R(1.5) * rho * usq;
         static_for<0, Q>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            R mn = R(0), mg = R(0);
+            R md = R(0);
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 constexpr int m = mrt_m(k, i);
-                if constexpr (m != 0) {
-                    mn += R(m) * nq[i];
-                    mg += R(m) * gq[i];
-                }
+                if constexpr (m != 0) md += R(m) * d[i];
             });
+            R meq = R(0), mg = R(0);
+            if constexpr (mrt_w0(k) != 0) {
+                meq += R(mrt_w0(k)) * e0;
+                mg -= R(3 * mrt_w0(k)) * uF;
+            }
+            static_for<0, 3>([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                if constexpr (mrt_w1(k, a) != 0) {
+                    meq += R(3 * mrt_w1(k, a)) * rho * uv[a];
+                    mg += R(3 * mrt_w1(k, a)) * Fv[a];
+                }
+                static_for<0, 3>([&](auto bc) {
+                    constexpr int b = decltype(bc)::value;
+                    if constexpr (mrt_w2(k, a, b) != 0) {
+                        meq += R(4.5) * R(mrt_w2(k, a, b)) * rho * uv[a] * uv[b];
+                        mg += R(9 * mrt_w2(k, a, b)) * uv[a] * Fv[b];
+                    }
+                });
+            });
+            const R mn = md - meq * R(1.0 / 36.0);
             const R sk = R(mr->s[k]);
-            const R r = (sk * mn - (R(1) - R(0.5) * sk) * mg) * (R(1) / R(mrt_norm2(k)));
+            const R r = (sk * mn - (R(1) - R(0.5) * sk) * (mg * R(1.0 / 36.0))) * (R(1) / R(mrt_norm2(k)));
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 constexpr int m = mrt_m(k, i);
