@@ -463,31 +463,55 @@ __device__ int hc_more_iterations(const IbArgs<R, AS>& a, bool* capped);
 // records the count and then treats every vertex with direct atomics, while
 // the others return. The step epoch was advanced and the reduction slots
 // cleared by the interpolation launch of the step.
-// Forces, tile marks and spreading of every vertex by one work-group, with
-// direct global atomics (the rare path below; the viscosity ratio's row
-// crossings of every triangle with CHI).
+// Forces, tile marks and spreading of every vertex by one work-group (the
+// rare path below), 256 vertices at a time: one thread per vertex computes
+// its stencil and force into LDS records (in the dynamic window's memory),
+// then one wave per vertex adds its 64 contributions with direct global
+// atomics, one lane per stencil node. With CHI, the viscosity ratio's row
+// crossings of every triangle follow.
 template <class R, bool CHI>
-__device__ void fs_all_vertices(const IbArgs<R>& a, const V4<R>* P, int commit, const IndArgs* ia, int npatch) {
-    const int t = threadIdx.x;
+__device__ void fs_all_vertices(const IbArgs<R>& a, const V4<R>* P, int commit, const IndArgs* ia, int npatch,
+                                double* win) {
+    const int t = threadIdx.x, lane = t & 63;
     const int ep = a.ctl->epoch;
     const long long N = a.g.N;
-    for (int k = t; k < a.nv; k += IBT) {
-        const V4<R> pos = ld4<V4<R>>(P + k);
-        if (commit) st4(a.r + k, pos);
-        int f[3];
-        R w[3][4];
-        if (!stencil_of(a, pos, f, w)) continue;
-        R fx, fy, fz;
-        force_of(a, P, k, pos, fx, fy, fz);
-        mark_tiles(a, f, ep);
-        for (int j = 0; j < 64; ++j) {
-            const int jx = j & 3, jy = (j >> 2) & 3, jz = j >> 4;
-            const R wt = w[0][jx] * w[1][jy] * w[2][jz];
-            const long long n = node_index(a.g, f[0] + jx, f[1] + jy, f[2] + jz);
-            atom_add(a.F + n, fx * wt);
-            atom_add(a.F + N + n, fy * wt);
-            atom_add(a.F + 2 * N + n, fz * wt);
+    static_assert(IBT * sizeof(DetRec<R>) <= 3 * SPREAD_WCAP * sizeof(double), "records fit the window's LDS");
+    DetRec<R>* rec = reinterpret_cast<DetRec<R>*>(win);  // IBT records, within the window's LDS
+    const int jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
+    for (int c0 = 0; c0 < a.nv; c0 += IBT) {
+        const int k = c0 + t;
+        int ok = 0;
+        if (k < a.nv) {
+            const V4<R> pos = ld4<V4<R>>(P + k);
+            if (commit) st4(a.r + k, pos);
+            int f[3];
+            R w[3][4];
+            if (stencil_of(a, pos, f, w)) {
+                ok = 1;
+                R fx, fy, fz;
+                force_of(a, P, k, pos, fx, fy, fz);
+                mark_tiles(a, f, ep);
+                for (int d = 0; d < 3; ++d) {
+                    rec[t].fw[d] = f[d];
+                    for (int j = 0; j < 4; ++j) rec[t].w[d][j] = w[d][j];
+                }
+                rec[t].val[0] = fx;
+                rec[t].val[1] = fy;
+                rec[t].val[2] = fz;
+            }
         }
+        rec[t].ok = ok;
+        __syncthreads();
+        const int nc = min(IBT, a.nv - c0);
+        for (int v = t >> 6; v < nc; v += IBT / 64) {
+            if (!rec[v].ok) continue;
+            const R wt = rec[v].w[0][jx] * rec[v].w[1][jy] * rec[v].w[2][jz];
+            const long long n = node_index(a.g, rec[v].fw[0] + jx, rec[v].fw[1] + jy, rec[v].fw[2] + jz);
+            atom_add(a.F + n, rec[v].val[0] * wt);
+            atom_add(a.F + N + n, rec[v].val[1] * wt);
+            atom_add(a.F + 2 * N + n, rec[v].val[2] * wt);
+        }
+        __syncthreads();
     }
     if constexpr (CHI) {
         const double xc[3] = {a.g.xci[0] + a.g.xcf[0], a.g.xci[1] + a.g.xcf[1], a.g.xci[2] + a.g.xcf[2]};
@@ -525,7 +549,7 @@ __device__ void fs_step(const IbArgs<R>& a, int fold, int npatch, const V4<R>* P
                 if (capped) a.ctl->cap_hits += 1;
             }
             __syncthreads();  // the final positions in qa, written by this work-group
-            fs_all_vertices<R, CHI>(a, P, commit, ia, npatch);
+            fs_all_vertices<R, CHI>(a, P, commit, ia, npatch, win);
             return;
         }
         if (blockIdx.x == 0 && t == 0) {
