@@ -321,17 +321,17 @@ __global__ __launch_bounds__(256) void k_adj_spread(Geom g, int nv, const double
 //   ubar   = ubar_ext + sum_i gbar_i [omega df^eq_i/du + dS_i/du]
 //   Fbar   = sum_i gbar_i dS_i/dF + ubar / (2 rho)
 //   fbar_j = (1 - omega) gbar_j + rhobar + ubar.(c_j - u) / rho.
-// ubar_ext (the transposed interpolation) is cleared once read. Afterwards
-// (so that its registers are free) a boundary node adds the moving-wall
-// terms' share of dJ/dA: the forward reflected f*_i(x) into slot -i with the
-// term -6 w_i rho0 c_i . A (x + c_i/2 - x_c), so dJ/dA += fbar_{-i}(x)
+// ubar_ext (the transposed interpolation) is cleared once read. Afterwards a
+// boundary node adds the moving-wall terms' share of dJ/dA from its pulled
+// values: the forward reflected f*_i(x) into slot -i with the term
+// -6 w_i rho0 c_i . A (x + c_i/2 - x_c), so dJ/dA += fbar_{-i}(x)
 // (-6 w_i rho0) c_i (x + c_i/2 - x_c)^T; each work-group writes its 9 sums to
 // part[block][9] (fixed order).
 __device__ __forceinline__ void adj_lattice_node(const Geom& g, const LatticeParams& lp, const double* __restrict__ fbin,
                                                  double* __restrict__ fbout, const double* __restrict__ rho_,
                                                  const double* __restrict__ u_, const double* __restrict__ F_,
                                                  double* __restrict__ ubar, double* __restrict__ Fbar, long long n,
-                                                 int x, int y, int z) {
+                                                 int x, int y, int z, double dA[9]) {
     const long long N = g.N;
     const int LxLy = g.Lx * g.Ly;
     double gb[Q];
@@ -405,30 +405,10 @@ __device__ __forceinline__ void adj_lattice_node(const Geom& g, const LatticePar
     Fbar[n] = fbx + 0.5 * ubx * inv;
     Fbar[N + n] = fby + 0.5 * uby * inv;
     Fbar[2 * N + n] = fbz + 0.5 * ubz * inv;
-}
-
-__global__ __launch_bounds__(256) void k_adj_lattice(Geom g, LatticeParams lp, const double* __restrict__ fbin,
-                                                     double* __restrict__ fbout, const double* __restrict__ rho_,
-                                                     const double* __restrict__ u_, const double* __restrict__ F_,
-                                                     double* __restrict__ ubar, double* __restrict__ Fbar,
-                                                     double* __restrict__ part) {
-    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
-    const long long N = g.N;
-    const bool act = n < N;
-    int x = 0, y = 0, z = 0;
-    if (act) {
-        const int LxLy = g.Lx * g.Ly;
-        z = int(n / LxLy);
-        const int rem = int(n - (long long)z * LxLy);
-        y = rem / g.Lx;
-        x = rem - y * g.Lx;
-        adj_lattice_node(g, lp, fbin, fbout, rho_, u_, F_, ubar, Fbar, n, x, y, z);
-    }
-    double dA[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) dA[c] = 0.0;
-    const bool bnd = act && ((!g.px && (x == 0 || x == g.Lx - 1)) || (!g.py && (y == 0 || y == g.Ly - 1)) ||
-                             (!g.pz && (z == 0 || z == g.Lz - 1)));
+    // the moving-wall terms' share of dJ/dA on a boundary node, from the
+    // pulled values of its wall links (gbar_i = fbar_{-i}(x) there)
+    const bool bnd = (!g.px && (x == 0 || x == g.Lx - 1)) || (!g.py && (y == 0 || y == g.Ly - 1)) ||
+                     (!g.pz && (z == 0 || z == g.Lz - 1));
     if (bnd) {
         const double xr = double(x - g.xci[0]) - g.xcf[0];
         const double yr = double(y - g.xci[1]) - g.xcf[1];
@@ -439,7 +419,7 @@ __global__ __launch_bounds__(256) void k_adj_lattice(Geom g, LatticeParams lp, c
                               (!g.py && ((CY[i] == 1 && y == g.Ly - 1) || (CY[i] == -1 && y == 0))) ||
                               (!g.pz && ((CZ[i] == 1 && z == g.Lz - 1) || (CZ[i] == -1 && z == 0)));
             if (!wall) return;
-            const double sv = -6.0 * wgt<double>(i) * lp.rho0 * fbin[opp(i) * N + n];
+            const double sv = -6.0 * wgt<double>(i) * lp.rho0 * gb[i];
             const double wv[3] = {xr + 0.5 * CX[i], yr + 0.5 * CY[i], zr + 0.5 * CZ[i]};
             const int ci[3] = {CX[i], CY[i], CZ[i]};
 #pragma unroll
@@ -447,6 +427,26 @@ __global__ __launch_bounds__(256) void k_adj_lattice(Geom g, LatticeParams lp, c
 #pragma unroll
                 for (int b = 0; b < 3; ++b) dA[3 * a + b] += sv * ci[a] * wv[b];
         });
+    }
+}
+
+__global__ __launch_bounds__(256) void k_adj_lattice(Geom g, LatticeParams lp, const double* __restrict__ fbin,
+                                                     double* __restrict__ fbout, const double* __restrict__ rho_,
+                                                     const double* __restrict__ u_, const double* __restrict__ F_,
+                                                     double* __restrict__ ubar, double* __restrict__ Fbar,
+                                                     double* __restrict__ part) {
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long N = g.N;
+    double dA[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dA[c] = 0.0;
+    if (n < N) {
+        const int LxLy = g.Lx * g.Ly;
+        const int z = int(n / LxLy);
+        const int rem = int(n - (long long)z * LxLy);
+        const int y = rem / g.Lx;
+        const int x = rem - y * g.Lx;
+        adj_lattice_node(g, lp, fbin, fbout, rho_, u_, F_, ubar, Fbar, n, x, y, z, dA);
     }
     // fixed-order work-group sums through LDS: 72 threads add runs of 32
     // nodes, then 9 threads add the 8 runs
