@@ -3,8 +3,9 @@ of a marked tile gathers its force contributions in increasing vertex order,
 in FP64, instead of the patch windows' atomics.
 
 * FP64 against the oracle at the round-off bars of the atomics path: a walled
-  ragged box, a droplet wrapped around a periodic corner, and a viscosity
-  ratio (the force kernel's indicator form);
+  ragged box, a droplet wrapped around a periodic corner, a viscosity ratio
+  (the force kernel's indicator form), the MRT collision, the wet-node walls
+  and one population copy (in-place streaming);
 * run to run: two handles on the same inputs hold the same state bytes after
   an OU run, in the linear and the row layout of the lattice kernel;
 * checkpoint and resume: 100 steps equal 50 + save/load + 50, bit for bit;
@@ -55,6 +56,10 @@ CASES = {
                             kw=dict(tau=0.8, sigma=0.03, periodic=(1, 1, 1))),
     "viscosity_ratio": dict(L=(16, 18, 16), R=3.5, level=2, steps=30, A=simple_shear(2e-3),
                             kw=dict(tau=0.9, sigma=0.02, chi=4.0)),
+    "mrt": dict(L=(17, 16, 18), R=3.2, level=2, steps=30, A=_traceless(3e-3, 4),
+                kw=dict(tau=0.9, sigma=0.02, collision="mrt")),
+    "wet_walls": dict(L=(17, 16, 18), R=3.2, level=2, steps=30, A=_traceless(3e-3, 6),
+                      kw=dict(tau=0.9, sigma=0.02, walls="wet")),
 }
 
 
@@ -69,6 +74,22 @@ def test_f64_matches_oracle(ib, case):
     ref = oracle.Oracle(L, **kw)
     sim.step(c["A"], c["steps"])
     ref.step(c["A"], c["steps"])
+    _compare(sim, ref, **F64_TOL)
+    sim.close()
+    ref.close()
+
+
+def test_f64_one_population_copy_matches_oracle(ib):
+    """In-place streaming (one population copy) with the deterministic spreading."""
+    L = (19, 17, 21)
+    A = _traceless(3e-3, 8)
+    V, T = icosphere(2, 3.2, box_center(L))
+    kw = dict(tau=0.9, sigma=0.02, radius=3.2, vertices=V, triangles=T, A0=A)
+    print("case one population copy, FP64, deterministic spreading", flush=True)
+    sim = ib.Simulation(L, storage="f64", deterministic=True, populations=1, **kw)
+    ref = oracle.Oracle(L, **kw)
+    sim.step(A, 31)  # an odd count leaves the copy in the odd mapping until the reads
+    ref.step(A, 31)
     _compare(sim, ref, **F64_TOL)
     sim.close()
     ref.close()
