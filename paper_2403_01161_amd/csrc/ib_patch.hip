@@ -382,7 +382,7 @@ struct IndArgs {
 // patch's triangles (positions P) with the lattice rows.
 template <class R, int AS, bool CHI = false>
 __device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, int commit, Stage<R>& st, double* win,
-                         const IndArgs* ia = nullptr) {
+                         const IndArgs* ia = nullptr, const V4<R>* pre = nullptr) {
     const int t = threadIdx.x;
     const int k = p * PATCH + t;
     const int ep = a.ctl->epoch;
@@ -391,7 +391,8 @@ __device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, 
     R w[3][4];
     bool ok = false;
     if (t < PATCH && k < a.nv) {
-        const V4<R> pos = ld4<V4<R>>(P + k);
+        // the position, or the one the caller already loaded
+        const V4<R> pos = pre ? *pre : ld4<V4<R>>(P + k);
         if (commit) st4(a.r + k, pos);
         ok = stencil_of(a, pos, f, w);
         if (ok) {
@@ -534,6 +535,11 @@ template <class R, bool CHI>
 __device__ void fs_step(const IbArgs<R>& a, int fold, int npatch, const V4<R>* P, int commit, Stage<R>& st,
                         double* win, const IndArgs* ia) {
     const int t = threadIdx.x;
+    // this thread's vertex position, loaded together with the reduction slot
+    // so that the two loads overlap
+    const int k0 = blockIdx.x * PATCH + t;
+    V4<R> pos0{};
+    if (t < PATCH && k0 < a.nv) pos0 = ld4<V4<R>>(P + k0);
     if (fold) {
         bool more = false, capped = false;
         if (a.sp.max_iter > 0) {
@@ -557,7 +563,7 @@ __device__ void fs_step(const IbArgs<R>& a, int fold, int npatch, const V4<R>* P
             if (capped) a.ctl->cap_hits += 1;
         }
     }
-    fs_patch<R, 0, CHI>(a, blockIdx.x, P, commit, st, win, ia);
+    fs_patch<R, 0, CHI>(a, blockIdx.x, P, commit, st, win, ia, &pos0);
 }
 
 template <class R>
