@@ -455,15 +455,6 @@ __device__ inline double from_bits<double>(unsigned long long b) { return __long
 template <class R, int AS>
 __device__ int hc_more_iterations(const IbArgs<R, AS>& a, bool* capped);
 
-// The smoothing's finish folded into the force kernel (bit 5 of the step
-// variant; not with the deterministic spreading). Every work-group takes the
-// same decision from the reduction slot that the first smoothing iteration
-// filled: when that iteration converged, hit the iteration cap or smoothing
-// is off, work-group 0 records the count and every work-group treats its own
-// patch; otherwise (rare) work-group 0 alone runs the further iterations,
-// records the count and then treats every vertex with direct atomics, while
-// the others return. The step epoch was advanced and the reduction slots
-// cleared by the interpolation launch of the step.
 // Forces, tile marks and spreading of every vertex by one work-group (the
 // rare path below), 256 vertices at a time: one thread per vertex computes
 // its stencil and force into LDS records (in the dynamic window's memory),
@@ -531,6 +522,15 @@ __device__ void fs_all_vertices(const IbArgs<R>& a, const V4<R>* P, int commit, 
     }
 }
 
+// The smoothing's finish folded into the force kernel (bit 5 of the step
+// variant; not with the deterministic spreading). Every work-group takes the
+// same decision from the reduction slot that the first smoothing iteration
+// filled: when that iteration converged, hit the iteration cap or smoothing
+// is off, work-group 0 records the count and every work-group treats its own
+// patch; otherwise (rare) work-group 0 alone runs the further iterations,
+// records the count and then treats every vertex with direct atomics, while
+// the others return. The step epoch was advanced and the reduction slots
+// cleared by the interpolation launch of the step.
 template <class R, bool CHI>
 __device__ void fs_step(const IbArgs<R>& a, int fold, int npatch, const V4<R>* P, int commit, Stage<R>& st,
                         double* win, const IndArgs* ia) {
