@@ -2,7 +2,9 @@
 times (the autotuner's variant), against the FP64 oracle.
 
 * 128^3 single droplet (R 16, 10242 vertices, OU gradient), FP32 storage:
-  every vertex and every node's rho and u after 12 steps.
+  every vertex and every node's rho and u after 12 steps; and after 8 steps
+  with each option of the step (MRT collision, viscosity ratio 4, wet-node
+  walls, deterministic spreading).
 * 256^3 single droplet (R 32, 40962 vertices), FP32 storage: every vertex,
   and rho and u on every node of sampled z-planes (through the walls and the
   droplet) after 4 steps.
@@ -36,13 +38,14 @@ def ib():
     return ibmlb
 
 
-def _single(ib, w, nsteps, planes=None):
+def _single(ib, w, nsteps, planes=None, options=None, gpu_only=None):
     import bench
     from paper_2403_01161_amd.inputs import ou_gradient_table
     table = ou_gradient_table(nsteps + 1, w["corr"], w["G"], seed=w["seed"])
-    kw = dict(tau=w["tau"], sigma=w["sigma"], radius=w["R"], vertices=w["V"], triangles=w["T"], A0=table[0])
-    print(f"case full size L={w['L']} nv={len(w['V'])} steps={nsteps}", flush=True)
-    sim = ib.Simulation(w["L"], storage="f32", **kw)
+    kw = dict(tau=w["tau"], sigma=w["sigma"], radius=w["R"], vertices=w["V"], triangles=w["T"], A0=table[0],
+              **(options or {}))
+    print(f"case full size L={w['L']} nv={len(w['V'])} steps={nsteps} {options or ''} {gpu_only or ''}", flush=True)
+    sim = ib.Simulation(w["L"], storage="f32", **kw, **(gpu_only or {}))
     variant = sim.autotune(3)
     print(f"  variant {variant}: {bench.describe_variant(variant)}", flush=True)
     sim.step_table(table[:nsteps])
@@ -68,6 +71,20 @@ def _single(ib, w, nsteps, planes=None):
 def test_single_droplet_128(ib):
     import bench
     _single(ib, bench.workload("f32"), 12)
+
+
+@pytest.mark.parametrize("options,gpu_only", [
+    (dict(collision="mrt"), None),
+    (dict(chi=4.0), None),
+    (dict(walls="wet"), None),
+    (None, dict(deterministic=True)),
+], ids=["mrt", "chi4", "wet_walls", "deterministic"])
+def test_single_droplet_128_options(ib, options, gpu_only):
+    """The 128^3 droplet with each option of the step (MRT collision,
+    viscosity ratio 4, wet-node walls, deterministic spreading) in the
+    autotuner's variant, after 8 steps."""
+    import bench
+    _single(ib, bench.workload("f32"), 8, options=options, gpu_only=gpu_only)
 
 
 def test_single_droplet_256_sampled_planes(ib):
