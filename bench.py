@@ -132,7 +132,6 @@ def describe_variant(v):
         d["xcd_grouped_order"] = bool(v & 8)
     d["smoothing_finish_in_force_kernel"] = bool(v & 32)
     d["in_place_streaming"] = bool(v & 64)
-    d["ib_half_beside_next_lattice_update"] = bool(v & 128)
     return d
 
 
@@ -141,15 +140,12 @@ def lattice_kernel_name(v, chi=1.0, collision="bgk"):
         return "k_lattice_rows<..., MRT>" if v & 16 else "k_lattice_mrt"
     if chi != 1.0:
         return "k_lattice_rows<..., CHI>" if v & 16 else "k_lattice_chi"
-    name = "k_lattice_aa" if v & 64 else ("k_lattice_rows" if v & 16 else "k_lattice")
-    if v & 128:
-        name += " (two launches a sweep: the rows outside the row box, then those inside)"
-    return name
+    if v & 64:
+        return "k_lattice_aa"
+    return "k_lattice_rows" if v & 16 else "k_lattice"
 
 
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
-# step-variant bits that change what the lattice launches do (bit 5 does not)
-LATTICE_BITS = 31 | 64 | 128
 DTYPE = {"f64": "f64", "f32": "f32", "f16dev": "f16", "bf16dev": "bf16"}
 
 
@@ -198,7 +194,7 @@ def droplet_leg(dev, w, storage, K, W, reps=5, variant=None, chi=1.0, collision=
     avg_s = lat_ms / 1e3 / max(launches, 1)
     ach = alg / avg_s / 1e9
     plain = chi == 1.0 and collision == "bgk" and walls == "link"
-    return {"mlups": round(nodes * K / dt / 1e6, 2), "ms_per_step": round(dt / K * 1e3, 5), "step_variant": variant,
+    return {"mlups": round(nodes * K / dt / 1e6, 2), "ms_per_step": round(dt / K * 1e3, 5),
             "rep_ms_per_step": [round(t / K * 1e3, 5) for t in times],
             "ms_per_step_with_kernel_events": round(dt_ev / K * 1e3, 5),
             "vertex_updates_per_s": round(nv * K / dt, 1),
@@ -235,7 +231,7 @@ def kernel_source_hash():
 def counter_traffic(storage, box="128cubed", variant=None):
     """HBM bytes per lattice launch from the committed rocprofv3 counter summary,
     valid only while the kernel source is the one profiled and the lattice
-    kernel variant (bits 0-4, 6 and 7 of the step variant) is the profiled one."""
+    kernel variant (bits 0-4 and 6 of the step variant) is the profiled one."""
     path = os.path.join(ROOT, "profiles", f"lattice_{storage}_{box}_counters.md")
     if not os.path.exists(path):
         return None
@@ -245,7 +241,7 @@ def counter_traffic(storage, box="128cubed", variant=None):
     v = re.search(r"lattice_variant:\s*([0-9]+)", txt)
     if not m or not t or not v or m.group(1) != kernel_source_hash():
         return None
-    if variant is not None and int(v.group(1)) != (variant & LATTICE_BITS):
+    if variant is not None and int(v.group(1)) != (variant & 95):
         return None
     return float(t.group(1))
 
@@ -589,14 +585,6 @@ def main():
             print(json.dumps({"leg_done": st, "mlups": leg["mlups"], "frac": leg["roofline"]["frac"]}),
                   file=sys.stderr, flush=True)
         line["storage_formats"] = fm
-    if extras and plain and not head["step_variant"] & 128:
-        # the same workload with the IB half beside the next lattice update
-        # (step variant bit 7; its roofline is the lattice update's span over
-        # its two launches)
-        leg = droplet_leg(dev, w, args.storage, K, W, variant=head["step_variant"] | 128, box=box)
-        line["overlapped_step"] = {k: leg[k] for k in (
-            "mlups", "ms_per_step", "rep_ms_per_step", "hbm_frac_whole_step", "roofline")}
-        print(json.dumps({"leg_done": "overlapped_step", "mlups": leg["mlups"]}), file=sys.stderr, flush=True)
     if extras and args.box == "256" and plain:
         w2 = workload("f32")
         leg = droplet_leg(dev, w2, "f32", K, W, box="128cubed")

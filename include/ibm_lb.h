@@ -55,8 +55,7 @@ extern "C" {
 #define IBM_LB_EINVAL (-1)     /* invalid argument or configuration */
 #define IBM_LB_ENOMEM (-2)     /* device or host allocation failed, or workspace too small */
 #define IBM_LB_EDEVICE (-3)    /* a HIP runtime call failed */
-#define IBM_LB_EDOMAIN (-4)    /* a vertex stencil left the box across a wall, or moved
-                                  further in one step than step variant bit 7 allows */
+#define IBM_LB_EDOMAIN (-4)    /* a vertex stencil left the box across a wall */
 #define IBM_LB_ENONFINITE (-5) /* non-finite or non-positive density, velocity or position */
 
 /* ---- population storage formats (populations are stored as deviations
@@ -269,22 +268,6 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  * with bit 6 (default 96). The adjoint's recompute of a segment runs
  * without bit 6 on two copies; on one copy each recomputed step is followed
  * by the return to natural order.
- * Bit 7 (a droplet without a viscosity ratio or wet-node walls; ignored
- * otherwise, and refused by ensembles) overlaps consecutive steps within one
- * call on two streams, the handle's and a second one the handle creates:
- * the lattice update of step n + 1 runs as two launches, one over the x-rows
- * (y, z) outside a box of rows, one over the rows inside it. The outer half
- * runs beside the IB half of step n and the inner half of step n + 1, on the
- * second stream, one after the other. The box is the y and z range the
- * vertex stencils reached one step earlier, widened by 2 rows on each side
- * (Sec. 3.1: the IB half reads velocities and writes forces only in the
- * 4-node stencils of the vertices); the outer half reads and writes no
- * force or velocity, so results equal those without bit 7 to the bit (with
- * deterministic spreading; with the float atomics, to their rounding). A
- * vertex whose stencil moves more than 2 rows in y or z within one step is
- * outside that assumption: the step then raises the sticky EDOMAIN. The
- * first lattice update of a call (and of every run of 1024 steps) is one
- * launch.
  *
  * Autotuner: picks the variant for this configuration by timing `reps` whole
  * steps with each lattice variant that can run (bit 5 set; with and without
@@ -293,10 +276,7 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  * afterwards (the state after the call equals the state before; the force
  * field is spread again at the next step). Times within 1 % of the fastest
  * count as ties, which go to the default variant, else to the first
- * candidate (bit 6 clear before bit 6 set, then by index). Bit 7 is left
- * to the caller: it trades the lattice update's own rate for the overlap
- * (measured faster per step on large boxes, slower on small ones, where the
- * IB half slowed by the concurrent update outlasts it).
+ * candidate (bit 6 clear before bit 6 set, then by index).
  * Synchronises the stream.
  * *variant (may be NULL) receives the choice. Errors: EINVAL, ENOMEM,
  * EDEVICE, sticky.
@@ -316,12 +296,9 @@ int ibm_lb_set_variant(ibm_lb* h, int32_t variant);
  * (hipExtLaunchKernel stop events; the first launch of each call starts
  * from an event recorded just before it). Consecutive dispatches of one
  * stream start as the previous one completes, so this is the kernel's
- * duration without the cost of separate event packets around it. With step
- * variant bit 7 every launch carries start and stop events, and a lattice
- * update of two launches counts once, for the span from the earlier start to
- * the later stop.
+ * duration without the cost of separate event packets around it.
  * ibm_lb_timing_read synchronises and returns the summed elapsed time (ms)
- * and launch count (sweeps) since the last read. */
+ * and launch count since the last read. */
 int ibm_lb_timing_enable(ibm_lb* h, int32_t enable);
 int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
 

@@ -46,7 +46,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 // Byte offsets of every device array inside one workspace.
 struct Layout {
     size_t f[2], F, u, mark, ctl, r, o, qa, qb, pp, bb, tris, fan, lfan, hstart, hids, obs_part, mass_part,
-        obs_out, Abuf, red, ind, ind_lines, ptris, ptstart, perm, det, pbox, rbox, total;
+        obs_out, Abuf, red, ind, ind_lines, ptris, ptstart, perm, det, pbox, total;
 };
 
 // Per vertex: valence m and the one-ring neighbours n_0 .. n_{m-1} in
@@ -100,7 +100,6 @@ Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t 
     const size_t npatch = (size_t)(nv + IB_PATCH - 1) / IB_PATCH;
     L.det = take(det ? det_rec_bytes(storage) * (size_t)nv : 0);
     L.pbox = take(det ? sizeof(int) * 8 * npatch : 0);
-    L.rbox = take(nv > 0 ? sizeof(int) * row_box_ints(nv) : 0);
     L.total = off;
     return L;
 }
@@ -437,12 +436,7 @@ struct ibm_lb {
     // own completion, both stamped by the dispatches themselves
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
-    // a sweep in one launch (start, stop), or in two launches on two streams
-    // (the span from the earlier start to the later stop); pool indices
-    struct Span {
-        int start, stop, start2 = -1, stop2 = -1;
-    };
-    std::vector<Span> iv;
+    std::vector<std::pair<int, int>> iv;
     int ev_pending = -1;  // pool index stamped by the last dispatch, or -1
     double acc_ms = 0.0;
     int64_t launches = 0;
@@ -457,9 +451,6 @@ struct ibm_lb {
     int* adj_perm = nullptr;
     AdjVerts adj_v{};
     double* scratch = nullptr;   // this device's address of the allocation-free staging array
-    // overlapped step: the second stream and the events that order the two
-    hipStream_t side = nullptr;
-    hipEvent_t ev_a[2] = {nullptr, nullptr}, ev_b[2] = {nullptr, nullptr}, ev_join = nullptr;
 };
 
 namespace {
@@ -481,10 +472,6 @@ int check_flags(ibm_lb* h) {
         h->sticky = IBM_LB_EDOMAIN;
         return fail(IBM_LB_EDOMAIN, "a vertex stencil left the box across a wall");
     }
-    if (c.flags & DFLAG_MOVED) {
-        h->sticky = IBM_LB_EDOMAIN;
-        return fail(IBM_LB_EDOMAIN, "a vertex stencil moved more than 2 rows in one overlapped step");
-    }
     return IBM_LB_OK;
 }
 
@@ -497,16 +484,10 @@ int accumulate_timing(ibm_lb* h) {
     for (size_t k = 0; k < h->ev_used; ++k) HIP_TRY(hipEventSynchronize(h->ev[k]), "hipEventSynchronize");
     for (const auto& p : h->iv) {
         float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, h->ev[p.start], h->ev[p.stop]), "hipEventElapsedTime");
-        if (p.start2 >= 0) {
-            float s2 = 0.0f, e2 = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&s2, h->ev[p.start], h->ev[p.start2]), "hipEventElapsedTime");
-            HIP_TRY(hipEventElapsedTime(&e2, h->ev[p.start], h->ev[p.stop2]), "hipEventElapsedTime");
-            ms = std::max(ms, e2) - std::min(0.0f, s2);
-        }
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev[p.first], h->ev[p.second]), "hipEventElapsedTime");
         h->acc_ms += ms;
-        h->launches += 1;
     }
+    h->launches += (int64_t)h->iv.size();
     h->iv.clear();
     h->ev_used = 0;
     h->ev_pending = -1;
@@ -553,156 +534,51 @@ int ensure_natural(ibm_lb* h) {
     return IBM_LB_OK;
 }
 
-// The second stream of the overlapped step and its ordering events (created
-// on first use, default priority).
-int ensure_side_stream(ibm_lb* h) {
-    if (h->side) return IBM_LB_OK;
-    for (int k = 0; k < 2; ++k) {
-        HIP_TRY(hipEventCreate(&h->ev_a[k]), "hipEventCreate");
-        HIP_TRY(hipEventCreate(&h->ev_b[k]), "hipEventCreate");
-    }
-    HIP_TRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming), "hipEventCreate");
-    HIP_TRY(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "hipStreamCreate");
-    return IBM_LB_OK;
-}
-
-// Overlapped steps (step variant bit 7, nsteps > 1). Sweep k + 1 (the
-// lattice update of step k + 1) runs as two launches: the rows outside the
-// row box R_k on the handle's stream (A), the rows inside it on the side
-// stream (B). A runs the outer halves back to back; B runs the IB half of
-// step k, then the inner half of sweep k + 1. The outer half of sweep k + 1
-// waits for the inner half of sweep k, the inner half of sweep k + 1 for the
-// outer half of sweep k (the populations each reads and overwrites), so the
-// IB half and the inner half run beside the outer half. The outer half
-// reads no force, tile mark or velocity, and writes none; R_k holds every
-// row where the force of sweep k + 1 is non-zero and every row whose
-// velocity the IB half of step k + 1 reads: the rows of the stencils of the
-// positions the IB half of step k leaves, which that IB half checks. R_k is
-// the box of the positions at the start of step k, in slot k mod 3 (three
-// slots: the IB half of step k writes R_{k+1} while the outer half of sweep
-// k may still read R_{k-1}).
-int enqueue_overlapped(ibm_lb* h, const double* A, int nsteps, int stride) {
-    int rc = ensure_side_stream(h);
-    if (rc) return rc;
-    hipStream_t sa = h->stream, sb = h->side;
-    const MrtRates* mrt = h->mrt ? &h->mrt_rates : nullptr;
-    const bool aa = (h->lattice_variant & VAR_AA) != 0;
-    const bool hc_split = (h->lattice_variant & VAR_HC_SPLIT) != 0;
-    const int v = h->lattice_variant;
-    // sweep k reads copy cur ^ (k & 1) (two copies) or runs with parity
-    // aa_parity ^ (k & 1) (one copy in place)
-    auto cur_of = [&](int k) { return aa ? h->cur : h->cur ^ (k & 1); };
-    auto par_of = [&](int k) { return aa ? h->aa_parity ^ (k & 1) : h->aa_parity; };
-    auto row = [&](int k) { return A + 9ll * k * stride; };
-    auto pool = [&](int* k) { return take_event(h, k); };
-    if (h->timing && h->iv.size() + 4 * (size_t)nsteps > 4096 && (rc = accumulate_timing(h))) return rc;
-    HIP_TRY(launch_row_box(h->storage, h->g, h->d, h->nv, 0, -1, sa), "row box launch");
-    hipEvent_t a_done = nullptr, b_done = nullptr;  // outer (or whole) and inner half of the last sweep
-    {   // sweep 0 in one launch
-        int k0 = -1, k1 = -1;
-        if (h->timing && ((rc = pool(&k0)) || (rc = pool(&k1)))) return rc;
-        a_done = h->timing ? h->ev[k1] : h->ev_a[0];
-        HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, cur_of(0), true, row(0), v, par_of(0), sa,
-                               h->timing ? h->ev[k0] : nullptr, a_done, mrt),
-                "lattice launch");
-        if (h->timing) h->iv.push_back({k0, k1});
-    }
-    for (int j = 0; j < nsteps; ++j) {
-        const bool next = j + 1 < nsteps;
-        const int* box = h->d.rbox + 4 * (j % 3);
-        int k0 = -1, k1 = -1, k2 = -1, k3 = -1;
-        if (next && h->timing && ((rc = pool(&k0)) || (rc = pool(&k1)) || (rc = pool(&k2)) || (rc = pool(&k3))))
-            return rc;
-        hipEvent_t a_next = nullptr, b_next = nullptr;
-        if (next) {  // A: outer half of sweep j + 1, once the inner half of sweep j is done
-            if (b_done) HIP_TRY(hipStreamWaitEvent(sa, b_done, 0), "hipStreamWaitEvent");
-            a_next = h->timing ? h->ev[k1] : h->ev_a[(j + 1) & 1];
-            HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, cur_of(j + 1), true, row(j + 1), v, par_of(j + 1),
-                                   sa, h->timing ? h->ev[k0] : nullptr, a_next, mrt, nullptr,
-                                   RowPart{box, ROWS_FAR}),
-                    "lattice launch (rows outside the box)");
-        }
-        // B: IB half of step j, then the inner half of sweep j + 1
-        if (j == 0) HIP_TRY(hipStreamWaitEvent(sb, a_done, 0), "hipStreamWaitEvent");
-        HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, sb, nullptr, hc_split),
-                "ib_step launch");
-        if (next) {
-            HIP_TRY(launch_row_box(h->storage, h->g, h->d, h->nv, (j + 1) % 3, j % 3, sb), "row box launch");
-            HIP_TRY(hipStreamWaitEvent(sb, a_done, 0), "hipStreamWaitEvent");
-            b_next = h->timing ? h->ev[k3] : h->ev_b[(j + 1) & 1];
-            HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, cur_of(j + 1), true, row(j + 1), v, par_of(j + 1),
-                                   sb, h->timing ? h->ev[k2] : nullptr, b_next, mrt, nullptr,
-                                   RowPart{box, ROWS_NEAR}),
-                    "lattice launch (rows in the box)");
-            if (h->timing) h->iv.push_back({k0, k1, k2, k3});
-            a_done = a_next;
-            b_done = b_next;
-        }
-    }
-    // A waits for the last IB half
-    HIP_TRY(hipEventRecord(h->ev_join, sb), "hipEventRecord");
-    HIP_TRY(hipStreamWaitEvent(sa, h->ev_join, 0), "hipStreamWaitEvent");
-    if (aa) h->aa_parity ^= nsteps & 1;
-    else h->cur ^= nsteps & 1;
-    h->step += nsteps;
-    h->ev_pending = -1;
-    return IBM_LB_OK;
-}
-
-// nsteps steps: the lattice sweep, then the IB half (overlapped with step
-// variant bit 7 for a droplet without a viscosity ratio or wet-node walls).
 int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
     const bool ib = h->nv > 0;
     int rc = ensure_force(h);
     if (rc) return rc;
     const bool aa = (h->lattice_variant & VAR_AA) != 0;
     if (!aa && (rc = ensure_natural(h))) return rc;
-    if (ib && !h->chi && !h->wet && (h->lattice_variant & VAR_OVERLAP) && nsteps > 1) {
-        // runs of at most 1024 steps (the timing pool holds four events a step)
-        for (int done = 0; done < nsteps; done += 1024)
-            if ((rc = enqueue_overlapped(h, A + 9ll * done * stride, std::min(1024, nsteps - done), stride)))
-                return rc;
-    } else {
-        h->ev_pending = -1;  // other work may have been queued since the last stamp
-        for (int j = 0; j < nsteps; ++j) {
-            const double* Arow = A + 9ll * j * stride;
-            hipEvent_t e1 = nullptr, done = nullptr;
-            int k0 = -1, k1 = -1, kd = -1;
-            if (h->timing) {
-                if (h->iv.size() >= 4096 && (rc = accumulate_timing(h))) return rc;
-                if (h->ev_pending >= 0) {
-                    k0 = h->ev_pending;
-                } else {
-                    if ((rc = take_event(h, &k0))) return rc;
-                    HIP_TRY(hipEventRecord(h->ev[k0], h->stream), "hipEventRecord");
-                }
-                if ((rc = take_event(h, &k1))) return rc;
-                if (ib && (rc = take_event(h, &kd))) return rc;
-                e1 = h->ev[k1];
-                done = ib ? h->ev[kd] : nullptr;
+    h->ev_pending = -1;  // other work may have been queued since the last stamp
+    for (int j = 0; j < nsteps; ++j) {
+        const double* Arow = A + 9ll * j * stride;
+        hipEvent_t e1 = nullptr, done = nullptr;
+        int k0 = -1, k1 = -1, kd = -1;
+        if (h->timing) {
+            if (h->iv.size() >= 4096) {
+                rc = accumulate_timing(h);
+                if (rc) return rc;
             }
-            HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->lattice_variant,
-                                   h->aa_parity, h->stream, nullptr, e1, h->mrt ? &h->mrt_rates : nullptr,
-                                   h->chi ? &h->chi_rates : nullptr),
-                    "lattice launch");
-            if (h->wet)
-                HIP_TRY(launch_wet_walls(h->storage, h->g, h->lp, h->d, h->cur ^ 1, Arow, h->stream),
-                        "walls launch");
-            if (ib)
-                HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream,
-                                       h->chi ? nullptr : done, (h->lattice_variant & VAR_HC_SPLIT) != 0),
-                        "ib_step launch");
-            if (h->chi) HIP_TRY(launch_indicator_scan(h->g, h->d, h->stream, done), "indicator launch");
-            if (h->timing) {
-                h->iv.push_back({k0, k1});
-                // the next sweep starts from the last stamped dispatch of the
-                // stream (none when the walls came last)
-                h->ev_pending = ib ? kd : (h->wet ? -1 : k1);
+            if (h->ev_pending >= 0) {
+                k0 = h->ev_pending;
+            } else {
+                if ((rc = take_event(h, &k0))) return rc;
+                HIP_TRY(hipEventRecord(h->ev[k0], h->stream), "hipEventRecord");
             }
-            if (aa) h->aa_parity ^= 1;
-            else h->cur ^= 1;
-            h->step++;
+            if ((rc = take_event(h, &k1))) return rc;
+            if (ib && (rc = take_event(h, &kd))) return rc;
+            e1 = h->ev[k1];
+            done = ib ? h->ev[kd] : nullptr;
         }
+        HIP_TRY(launch_lattice(h->storage, h->g, h->lp, h->d, h->cur, ib, Arow, h->lattice_variant, h->aa_parity,
+                               h->stream, nullptr, e1, h->mrt ? &h->mrt_rates : nullptr,
+                               h->chi ? &h->chi_rates : nullptr),
+                "lattice launch");
+        if (h->wet)
+            HIP_TRY(launch_wet_walls(h->storage, h->g, h->lp, h->d, h->cur ^ 1, Arow, h->stream), "walls launch");
+        if (ib)
+            HIP_TRY(launch_ib_step(h->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, h->stream,
+                                   h->chi ? nullptr : done, (h->lattice_variant & VAR_HC_SPLIT) != 0),
+                    "ib_step launch");
+        if (h->chi) HIP_TRY(launch_indicator_scan(h->g, h->d, h->stream, done), "indicator launch");
+        if (h->timing) {
+            h->iv.push_back({k0, k1});
+            h->ev_pending = ib ? kd : k1;
+        }
+        if (aa) h->aa_parity ^= 1;
+        else h->cur ^= 1;
+        h->step++;
     }
     if (nsteps > 0) {
         const double* last = A + 9ll * (nsteps - 1) * stride;
@@ -873,7 +749,6 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     d.perm = (int*)(b + L.perm);
     d.det = det ? (void*)(b + L.det) : nullptr;
     d.pbox = det ? (int*)(b + L.pbox) : nullptr;
-    d.rbox = h->nv > 0 ? (int*)(b + L.rbox) : nullptr;
     h->perm = mesh.perm;
     if (h->nv > 0) {
         e = patch_setup(h->storage);
@@ -891,7 +766,6 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     INIT_TRY(hipMemsetAsync(d.u, 0, 3 * rb * (size_t)h->g.N, h->stream), "zero u");
     INIT_TRY(hipMemsetAsync(d.mark, 0, sizeof(int) * (size_t)ntiles, h->stream), "zero marks");
     INIT_TRY(hipMemsetAsync(d.red, 0, 2 * sizeof(unsigned long long), h->stream), "zero reduction slots");
-    if (d.rbox) INIT_TRY(hipMemsetAsync(d.rbox, 0, sizeof(int) * row_box_ints(h->nv), h->stream), "zero row boxes");
     Ctl ctl0{};
     ctl0.epoch = 1;
     INIT_TRY(hipMemcpyAsync(d.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice, h->stream), "ctl");
@@ -1549,7 +1423,7 @@ struct ibm_lb_batch {
 
 namespace {
 bool batch_variant_ok(const ibm_lb_batch* b, int v) {
-    if (v < 0 || v >= STEP_VARIANTS || (v & (VAR_AA | VAR_OVERLAP))) return false;
+    if (v < 0 || v >= STEP_VARIANTS || (v & VAR_AA)) return false;
     return !(v & VAR_ROWS) || b->nblk[4 + ((v >> 1) & 3)] >= 0;
 }
 
@@ -1903,15 +1777,6 @@ void ibm_lb_destroy(ibm_lb* h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
-    if (h->side) {
-        (void)hipStreamSynchronize(h->side);
-        (void)hipStreamDestroy(h->side);
-    }
-    for (int k = 0; k < 2; ++k) {
-        if (h->ev_a[k]) (void)hipEventDestroy(h->ev_a[k]);
-        if (h->ev_b[k]) (void)hipEventDestroy(h->ev_b[k]);
-    }
-    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     if (h->stage_done) (void)hipEventDestroy(h->stage_done);
     if (h->stage) (void)hipHostFree(h->stage);

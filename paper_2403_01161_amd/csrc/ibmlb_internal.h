@@ -13,7 +13,6 @@ namespace ibmlb {
 enum : int {
     DFLAG_DOMAIN = 1,
     DFLAG_NONFINITE = 2,
-    DFLAG_MOVED = 4,  // a stencil left the rows its overlapped lattice update assumed
 };
 
 // IB tiles: 8x8x8 lattice nodes. A tile is "marked" for a step when some
@@ -96,30 +95,7 @@ struct DevPtrs {
     int* perm;               // [nv] caller index of each internal vertex
     void* det;               // [nv] staged stencils of the deterministic spreading, or null
     int* pbox;               // [npatch][8] patch windows of the deterministic spreading
-    int* rbox;               // row boxes of the overlapped step (row_box_ints), or null
 };
-
-// Overlapped step (step variant bit 7): the lattice update of step n runs in
-// two launches on two streams, the x-rows outside a box of rows beside the
-// IB half of step n - 1 and the rows inside the box. The box holds every row
-// the stencils of step n reach: the rows (y, z) with (y - y0) mod Ly < ny
-// and (z - z0) mod Lz < nz, stored as {y0, ny, z0, nz}. It is the rows of
-// the stencils one step earlier widened by ROW_MARGIN on each side (clipped
-// at walls), so a vertex may move up to ROW_MARGIN lattice units in y and z
-// per step; a stencil beyond raises DFLAG_MOVED.
-constexpr int ROW_MARGIN = 2;
-constexpr int ROW_BOX_T = 256;  // vertices per work-group of the row-box kernel
-enum : int { ROWS_ALL = 0, ROWS_FAR = 1, ROWS_NEAR = 2 };
-struct RowPart {
-    const int* box;          // {y0, ny, z0, nz} (16-byte aligned), with ROWS_FAR / ROWS_NEAR
-    int mode;                // ROWS_*
-};
-// rbox layout: three box slots [3][4], a ticket [4], then four partials per
-// work-group of the row-box kernel.
-constexpr int ROW_BOX_SLOTS = 3;
-constexpr int ROW_BOX_TICKET = 4 * ROW_BOX_SLOTS;
-constexpr int ROW_BOX_PART = ROW_BOX_TICKET + 4;
-inline size_t row_box_ints(int nv) { return ROW_BOX_PART + 4 * (size_t)((nv + ROW_BOX_T - 1) / ROW_BOX_T); }
 
 // Bytes of the indicator array (whole 32-bit words, for the atomic toggles).
 inline size_t ind_bytes(const Geom& g) { return ((size_t)g.N + 3) / 4 * 4; }
@@ -176,10 +152,7 @@ constexpr int VAR_HC_SPLIT = 32;
 // Bit 6 (VAR_AA): one population copy updated in place, even and odd steps
 // alternating (linear layout only).
 constexpr int VAR_AA = 64;
-// Bit 7 (VAR_OVERLAP): the overlapped step above (single droplets without a
-// viscosity ratio or wet-node walls; otherwise ignored).
-constexpr int VAR_OVERLAP = 128;
-constexpr int STEP_VARIANTS = 256;
+constexpr int STEP_VARIANTS = 128;
 // Rows per work-group of a row-layout variant for rows of Lx nodes; 0 when
 // the variant is not a row layout or Lx exceeds the largest work-group.
 int lattice_rows_per_block(int variant, int Lx);
@@ -192,12 +165,10 @@ int lattice_variant_ok(int variant, const Geom& g);
 // copies, linear or row layout).
 // chi (may be null): nodes whose indicator byte d.ind is set relax with
 // these rates; the byte is cleared (BGK, two copies, linear or row layout).
-// part: the rows this launch updates (every row, or one side of a row box;
-// not with chi).
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const MrtRates* mrt = nullptr,
-                          const ChiRates* chi = nullptr, RowPart part = RowPart{nullptr, ROWS_ALL});
+                          const ChiRates* chi = nullptr);
 // Second half of the indicator: the running parity over each x-row of the
 // toggles that the force kernel left (d.ind non-null makes the force kernel
 // cross the mesh with the rows; d.ind must hold zeros and empty row ranges
@@ -260,10 +231,6 @@ hipError_t launch_ib_pre_batch(int storage, const void* args, const int2* map, i
 hipError_t launch_ib_step_batch(int storage, const void* args, const int2* map, int npatch_total, int ndrop,
                                 hipStream_t s);
 hipError_t launch_clear_force(int storage, const Geom& g, const DevPtrs& d, hipStream_t s);
-// Row box of the current positions d.r into slot `out` of d.rbox (widened by
-// ROW_MARGIN); with check >= 0, a stencil outside the box in slot `check`
-// raises DFLAG_MOVED.
-hipError_t launch_row_box(int storage, const Geom& g, const DevPtrs& d, int nv, int out, int check, hipStream_t s);
 
 size_t storage_bytes(int storage);
 size_t real_bytes(int storage);

@@ -19,7 +19,7 @@ namespace ibmlb {
 #define IBMLB_LATTICE_EXTERN(C)                                                                                   \
     extern template hipError_t launch_lattice_c<C>(const Geom&, const LatticeParams&, const DevPtrs&, int, bool,    \
                                                    const double*, int, int, hipStream_t, hipEvent_t, hipEvent_t,     \
-                                                   const MrtRates*, const ChiRates*, RowPart);                       \
+                                                   const MrtRates*, const ChiRates*);                                \
     extern template hipError_t launch_lattice_batch_c<C>(const LatDesc*, const int2*, const int*, const int*,       \
                                                          const int*, int, long long, int, hipStream_t);
 IBMLB_LATTICE_EXTERN(SF64)
@@ -132,110 +132,6 @@ __global__ __launch_bounds__(256) void k_mass(Geom g, LatticeParams lp,
 
 __global__ void k_bump_epoch(Ctl* ctl) {
     if (threadIdx.x == 0) ctl->epoch += 1;
-}
-
-// Row box of the overlapped step: the rows (y, z) that the stencils of the
-// positions r reach, widened by ROW_MARGIN on each side (clipped at walls,
-// every row once the widened extent covers a periodic axis), into slot `out`
-// of rbox. Each work-group folds the extremes of its vertices' first stencil
-// rows into a partial; the last to finish folds the partials into the box and
-// resets the ticket. With check >= 0, a stencil outside the box in slot
-// `check` raises DFLAG_MOVED. Positions that are not finite or whose stencil
-// crosses a wall are left to the force kernel's flags.
-template <class R>
-__global__ __launch_bounds__(ROW_BOX_T) void k_row_box(Geom g, const V4<R>* __restrict__ r, int nv,
-                                                       int* __restrict__ rbox, int out, int check, Ctl* ctl) {
-    __shared__ int red[4][ROW_BOX_T / 64];
-    __shared__ int last;
-    const int t = threadIdx.x;
-    int v[4] = {0x3fffffff, -0x3fffffff, 0x3fffffff, -0x3fffffff};  // min y, max y, min z, max z
-    auto fold = [&]() {
-        for (int off = 32; off > 0; off >>= 1) {
-            v[0] = min(v[0], __shfl_xor(v[0], off, 64));
-            v[1] = max(v[1], __shfl_xor(v[1], off, 64));
-            v[2] = min(v[2], __shfl_xor(v[2], off, 64));
-            v[3] = max(v[3], __shfl_xor(v[3], off, 64));
-        }
-        if ((t & 63) == 0)
-            for (int c = 0; c < 4; ++c) red[c][t >> 6] = v[c];
-        __syncthreads();
-        for (int w = 1; w < ROW_BOX_T / 64; ++w) {
-            v[0] = min(v[0], red[0][w]);
-            v[1] = max(v[1], red[1][w]);
-            v[2] = min(v[2], red[2][w]);
-            v[3] = max(v[3], red[3][w]);
-        }
-        v[0] = min(v[0], red[0][0]);
-        v[1] = max(v[1], red[1][0]);
-        v[2] = min(v[2], red[2][0]);
-        v[3] = max(v[3], red[3][0]);
-        __syncthreads();
-    };
-    const int k = int(blockIdx.x) * ROW_BOX_T + t;
-    if (k < nv) {
-        const V4<R> p = r[k];
-        int fy = 0, fz = 0;
-        R fr;
-        const bool ok = isfinite(p.y) && isfinite(p.z) &&
-                        stencil_base(p.y, g.xci[1], g.xcf[1], g.Ly, g.py, &fy, &fr) &&
-                        stencil_base(p.z, g.xci[2], g.xcf[2], g.Lz, g.pz, &fz, &fr);
-        if (ok) {
-            v[0] = fy;
-            v[1] = fy + 3;
-            v[2] = fz;
-            v[3] = fz + 3;
-            if (check >= 0) {
-                const int4 b = *reinterpret_cast<const int4*>(rbox + 4 * check);
-                const bool iny = b.y >= g.Ly || wrap_any(fy - b.x, g.Ly) + 3 < b.y;
-                const bool inz = b.w >= g.Lz || wrap_any(fz - b.z, g.Lz) + 3 < b.w;
-                if (!(iny && inz)) atomicOr(&ctl->flags, DFLAG_MOVED);
-            }
-        }
-    }
-    fold();
-    int* part = rbox + ROW_BOX_PART;
-    if (t == 0) {
-        for (int c = 0; c < 4; ++c) part[4 * blockIdx.x + c] = v[c];
-        __threadfence();
-        last = atomicAdd(rbox + ROW_BOX_TICKET, 1) == int(gridDim.x) - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    v[0] = v[2] = 0x3fffffff;
-    v[1] = v[3] = -0x3fffffff;
-    for (int b = t; b < int(gridDim.x); b += ROW_BOX_T) {
-        v[0] = min(v[0], __hip_atomic_load(part + 4 * b + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        v[1] = max(v[1], __hip_atomic_load(part + 4 * b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        v[2] = min(v[2], __hip_atomic_load(part + 4 * b + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        v[3] = max(v[3], __hip_atomic_load(part + 4 * b + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    }
-    fold();
-    if (t == 0) {
-        auto axis = [](int lo, int hi, int L, int periodic, int& o, int& n) {
-            if (lo > hi) {  // no stencil at all
-                o = 0;
-                n = 0;
-                return;
-            }
-            lo -= ROW_MARGIN;
-            hi += ROW_MARGIN;
-            if (periodic) {
-                n = hi - lo + 1 >= L ? L : hi - lo + 1;
-                o = n == L ? 0 : wrap_any(lo, L);
-            } else {
-                lo = max(lo, 0);
-                hi = min(hi, L - 1);
-                o = lo;
-                n = max(hi - lo + 1, 0);
-            }
-        };
-        int4 b;
-        axis(v[0], v[1], g.Ly, g.py, b.x, b.y);
-        axis(v[2], v[3], g.Lz, g.pz, b.z, b.w);
-        *reinterpret_cast<int4*>(rbox + 4 * out) = b;
-        rbox[ROW_BOX_TICKET] = 0;
-    }
 }
 
 template <class R>
@@ -731,17 +627,15 @@ int lattice_variant_ok(int variant, const Geom& g) {
 
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,
                           int cur, bool ib, const double* A_row, int variant, int parity, hipStream_t s,
-                          hipEvent_t e0, hipEvent_t e1, const MrtRates* mrt, const ChiRates* chi, RowPart part) {
+                          hipEvent_t e0, hipEvent_t e1, const MrtRates* mrt, const ChiRates* chi) {
     if (!lattice_variant_ok(variant, g)) return hipErrorInvalidValue;
     if (mrt && chi) return hipErrorInvalidValue;
     switch (storage) {
-        case IBM_LB_F64:
-            return launch_lattice_c<SF64>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi, part);
-        case IBM_LB_F32:
-            return launch_lattice_c<SF32>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi, part);
+        case IBM_LB_F64: return launch_lattice_c<SF64>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi);
+        case IBM_LB_F32: return launch_lattice_c<SF32>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi);
         case IBM_LB_F16DEV:
-            return launch_lattice_c<SF16>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi, part);
-        default: return launch_lattice_c<SBF16>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi, part);
+            return launch_lattice_c<SF16>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi);
+        default: return launch_lattice_c<SBF16>(g, lp, d, cur, ib, A_row, variant, parity, s, e0, e1, mrt, chi);
     }
 }
 
@@ -791,17 +685,6 @@ hipError_t launch_wet_walls(int storage, const Geom& g, const LatticeParams& lp,
 
 hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s) {
     hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, s, d.ctl);
-    return hipGetLastError();
-}
-
-hipError_t launch_row_box(int storage, const Geom& g, const DevPtrs& d, int nv, int out, int check, hipStream_t s) {
-    if (!d.rbox || nv <= 0 || out < 0 || out >= ROW_BOX_SLOTS || check >= ROW_BOX_SLOTS || check == out)
-        return hipErrorInvalidValue;
-    const unsigned nb = unsigned((nv + ROW_BOX_T - 1) / ROW_BOX_T);
-    DISPATCH_REAL(storage, R, {
-        hipLaunchKernelGGL(k_row_box<R>, dim3(nb), dim3(ROW_BOX_T), 0, s, g, (const V4<R>*)d.r, nv, d.rbox, out,
-                           check, d.ctl);
-    });
     return hipGetLastError();
 }
 

@@ -9,8 +9,6 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 
-#include <algorithm>
-
 #include "lattice_common.h"
 
 namespace ibmlb {
@@ -54,15 +52,6 @@ __device__ inline unsigned xcd_order(unsigned b, unsigned nb) {
     return b < (per << 3) ? (b & 7u) * per + (b >> 3) : b;
 }
 
-// Row box of an overlapped step's launch, and whether row (y, z) lies in it.
-__device__ __forceinline__ int4 row_box(const RowPart& p) { return *reinterpret_cast<const int4*>(p.box); }
-__device__ __forceinline__ bool in_row_box(const Geom& g, const int4& b, int y, int z) {
-    int dy = y - b.x, dz = z - b.z;
-    if (dy < 0) dy += g.Ly;
-    if (dz < 0) dz += g.Lz;
-    return dy < b.y && dz < b.w;
-}
-
 template <bool NTS, class P, class V>
 __device__ __forceinline__ void put(P p, V v) {
     if (NTS) __builtin_nontemporal_store(v, p);
@@ -83,18 +72,6 @@ __device__ __forceinline__ void node_xyz(const Geom& g, long long n, int& x, int
     }
     y = r / g.Lx;
     x = r - y * g.Lx;
-}
-
-// Node of this thread in work-group b of a linear-layout launch (the b-th
-// run of BS nodes of the lattice). False when it has none or, with ROWS_FAR,
-// when its row lies in the box.
-template <int BS>
-__device__ __forceinline__ bool part_node(const Geom& g, const RowPart& p, unsigned b, long long& n, int& x, int& y,
-                                          int& z) {
-    n = (long long)b * BS + threadIdx.x;
-    if (n >= g.N) return false;
-    node_xyz(g, n, x, y, z);
-    return p.mode != ROWS_FAR || !in_row_box(g, row_box(p), y, z);
 }
 
 // Target of population i pushed from node n = (x, y, z): n + c_i . (1, Lx,
@@ -161,8 +138,6 @@ __device__ __forceinline__ long long pull_source(const Geom& g, long long n, int
 // CHI: a node whose indicator byte ind[n] is set (inside the droplet) relaxes
 // with the rates *ch instead of lp's; the byte is cleared for the next
 // step's indicator. Only marked tiles hold inside nodes, so only they read it.
-// far: the node lies outside the row box of an overlapped sweep, where the
-// force is zero and the tile marks are being rewritten: it reads neither.
 template <class C, bool IB, bool NTL, bool ROWS, bool NTS, bool AREG, int AA, bool MRT = false, bool CHI = false,
           class PIn, class POut, class PR, class PM, class PC, class PA>
 __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams& lp, PIn fin, POut fout, PR F,
@@ -170,7 +145,7 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
                                              const long long n, const int x, const int y, const int z,
                                              typename C::store_t* stage, int t, int T,
                                              const MrtRates* mr = nullptr, unsigned char* ind = nullptr,
-                                             const ChiRates* ch = nullptr, bool far = false) {
+                                             const ChiRates* ch = nullptr) {
     using R = typename C::real;
     using S = typename C::store_t;
     const long long N = g.N;
@@ -199,10 +174,8 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
     R Fx = R(0), Fy = R(0), Fz = R(0);
     bool marked = false;
     if (IB) {
-        if (!far) {
-            const int tile = (x >> TILE_SHIFT) + g.TX * ((y >> TILE_SHIFT) + g.TY * (z >> TILE_SHIFT));
-            marked = mark[tile] == ctl->epoch;
-        }
+        const int tile = (x >> TILE_SHIFT) + g.TX * ((y >> TILE_SHIFT) + g.TY * (z >> TILE_SHIFT));
+        marked = mark[tile] == ctl->epoch;
         if (marked) {
             Fx = F[n];
             Fy = F[N + n];
@@ -212,10 +185,6 @@ __device__ __forceinline__ void lattice_node(const Geom& g, const LatticeParams&
             F[N + n] = R(0);
             F[2 * N + n] = R(0);
         }
-        // One instruction sequence for every node from here, whether its
-        // force was read or is zero (no path specialised for a zero force):
-        // a node's result does not depend on which launch updates it.
-        asm volatile("" : "+v"(Fx), "+v"(Fy), "+v"(Fz));
     }
     const R rho = R(lp.rho0) + drho;
     const R inv = R(1) / rho;
@@ -384,12 +353,14 @@ __global__ __launch_bounds__(BS) void k_lattice(Geom g, LatticeParams lp,
                                                  typename C::real* __restrict__ F,
                                                  typename C::real* __restrict__ U,
                                                  const int* __restrict__ mark, Ctl* ctl,
-                                                 const double* __restrict__ Arow, int xcd, RowPart part) {
-    long long n;
+                                                 const double* __restrict__ Arow, int xcd) {
+    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    const long long n = (long long)b * BS + threadIdx.x;
+    if (n >= g.N) return;
     int x, y, z;
-    if (!part_node<BS>(g, part, xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x, n, x, y, z)) return;
+    node_xyz(g, n, x, y, z);
     lattice_node<C, IB, NTL, false, false, false, 0>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0,
-                                                  0, nullptr, nullptr, nullptr, part.mode == ROWS_FAR);
+                                                  0);
 }
 
 // MRT collision, linear layout with two copies.
@@ -400,13 +371,14 @@ __global__ __launch_bounds__(BS) void k_lattice_mrt(Geom g, LatticeParams lp,
                                                      typename C::real* __restrict__ F,
                                                      typename C::real* __restrict__ U,
                                                      const int* __restrict__ mark, Ctl* ctl,
-                                                     const double* __restrict__ Arow, int xcd, MrtRates mr,
-                                                     RowPart part) {
-    long long n;
+                                                     const double* __restrict__ Arow, int xcd, MrtRates mr) {
+    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    const long long n = (long long)b * BS + threadIdx.x;
+    if (n >= g.N) return;
     int x, y, z;
-    if (!part_node<BS>(g, part, xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x, n, x, y, z)) return;
+    node_xyz(g, n, x, y, z);
     lattice_node<C, IB, NTL, false, false, false, 0, true>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z,
-                                                        nullptr, 0, 0, &mr, nullptr, nullptr, part.mode == ROWS_FAR);
+                                                        nullptr, 0, 0, &mr);
 }
 
 // Viscosity ratio: BGK with the inner rates on the nodes the indicator marks,
@@ -438,14 +410,14 @@ __global__ __launch_bounds__(BS) void k_lattice_aa(Geom g, LatticeParams lp, typ
                                                     const int* __restrict__ mark, Ctl* ctl,
                                                     const double* __restrict__ Arow, int xcd,
                                                     unsigned char* __restrict__ ind = nullptr,
-                                                    ChiRates ch = ChiRates{},
-                                                    RowPart part = RowPart{nullptr, ROWS_ALL}) {
-    long long n;
+                                                    ChiRates ch = ChiRates{}) {
+    const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    const long long n = (long long)b * BS + threadIdx.x;
+    if (n >= g.N) return;
     int x, y, z;
-    if (!part_node<BS>(g, part, xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x, n, x, y, z)) return;
+    node_xyz(g, n, x, y, z);
     lattice_node<C, IB, NTL, false, false, false, ODD ? 2 : 1, false, CHI>(
-        g, lp, (const typename C::store_t*)f, f, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0, 0, nullptr, ind, &ch,
-        part.mode == ROWS_FAR);
+        g, lp, (const typename C::store_t*)f, f, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0, 0, nullptr, ind, &ch);
 }
 
 // After an even in-place step, back to natural order in place. In the odd
@@ -490,63 +462,24 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows(Geom g, LatticePara
                                                              const int* __restrict__ mark, Ctl* ctl,
                                                              const double* __restrict__ Arow, int rows,
                                                              unsigned char* __restrict__ ind = nullptr,
-                                                             ChiRates ch = ChiRates{}, MrtRates mr = MrtRates{},
-                                                             RowPart part = RowPart{nullptr, ROWS_ALL}) {
+                                                             ChiRates ch = ChiRates{}, MrtRates mr = MrtRates{}) {
     using S = typename C::store_t;
     extern __shared__ __align__(16) unsigned char dyn[];
     S* stage = reinterpret_cast<S*>(dyn);
     const int T = rows * g.Lx;
     const int t = threadIdx.x;
-    // rows of Lx nodes: row index from the work-group (of the lattice, or of
-    // the box's rows in order with ROWS_NEAR), x from the thread
     // rows of Lx nodes: row index from the work-group, x from the thread
-    // (ROWS_FAR: rows in the box idle)
     const int rl = t / g.Lx;
     const int x = t - rl * g.Lx;
     const int row = int(blockIdx.x) * rows + rl;
     const int z = row / g.Ly, y = row - z * g.Ly;
     const long long n = (long long)row * g.Lx + x;
-    bool act = n < g.N;
-    if (part.mode == ROWS_FAR && act) act = !in_row_box(g, row_box(part), y, z);
+    const bool act = n < g.N;
     if (act)
         lattice_node<C, IB, NTL, true, NTS, false, 0, MRT, CHI>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y,
-                                                             z, stage, t, T, &mr, ind, &ch, part.mode == ROWS_FAR);
+                                                             z, stage, t, T, &mr, ind, &ch);
     __syncthreads();
     if (act) rows_receive<C, NTS>(g, fout, stage, n, x, y, z, t, T);
-}
-
-// The rows inside a row box (ROWS_NEAR), linear layout, for every lattice
-// variant (a row's update does not depend on the layout): each work-group
-// takes every gridDim.x-th run of NEAR_BS nodes of the box's rows in order
-// (z, then y, then x), the grid being capped since only the device knows the
-// box. MRT: the MRT collision; AA: 0 two copies (fin, fout), 1 and 2 the
-// even and odd in-place steps (fin = fout).
-constexpr int NEAR_BS = 128;
-constexpr long long NEAR_THREADS = 1 << 18;
-
-template <class C, bool NTL, bool MRT, int AA>
-__global__ __launch_bounds__(NEAR_BS) void k_lattice_near(Geom g, LatticeParams lp,
-                                                          const typename C::store_t* fin,
-                                                          typename C::store_t* fout,
-                                                          typename C::real* __restrict__ F,
-                                                          typename C::real* __restrict__ U,
-                                                          const int* __restrict__ mark, Ctl* ctl,
-                                                          const double* __restrict__ Arow, MrtRates mr,
-                                                          const int* __restrict__ box) {
-    const int4 bx = *reinterpret_cast<const int4*>(box);
-    const long long kend = (long long)bx.y * bx.w * g.Lx;
-    for (long long k = (long long)blockIdx.x * NEAR_BS + threadIdx.x; k < kend;
-         k += (long long)gridDim.x * NEAR_BS) {
-        const long long rk = k / g.Lx;
-        const int x = int(k - rk * g.Lx);
-        const int zz = int(rk / bx.y), yy = int(rk - (long long)zz * bx.y);
-        int y = bx.x + yy, z = bx.z + zz;
-        if (y >= g.Ly) y -= g.Ly;
-        if (z >= g.Lz) z -= g.Lz;
-        const long long n = x + (long long)g.Lx * (y + (long long)g.Ly * z);
-        lattice_node<C, true, NTL, false, false, false, AA, MRT>(g, lp, fin, fout, F, U, mark, ctl, Arow, n, x, y, z,
-                                                              nullptr, 0, 0, &mr);
-    }
 }
 
 // Ensemble forms: one launch covers every member's lattice; work-group b
@@ -625,39 +558,6 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows_batch(const LatDesc
 // ---------------------------------------------------------------- launchers
 static inline unsigned blocks_for(long long n, int bs) { return unsigned((n + bs - 1) / bs); }
 
-// The rows inside a row box for any lattice variant (k_lattice_near).
-template <class C>
-static void near_launch(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                        const double* A_row, int parity, const MrtRates* mrt, const int* box, hipStream_t s,
-                        hipEvent_t e0, hipEvent_t e1) {
-    using R = typename C::real;
-    using S = typename C::store_t;
-    const unsigned nb = unsigned(std::min<long long>(blocks_for(g.N, NEAR_BS), NEAR_THREADS / NEAR_BS));
-    const MrtRates mr = mrt ? *mrt : MrtRates{};
-    const bool ntl = variant & 1;
-    S* f0 = (S*)d.f[cur];
-    S* f1 = (S*)d.f[cur ^ 1];
-#define NEAR_GO(NTLV, MRTV, AAV, FOUT)                                                                          \
-    hipExtLaunchKernelGGL((k_lattice_near<C, NTLV, MRTV, AAV>), dim3(nb), dim3(NEAR_BS), 0, s, e0, e1, 0, g, lp, \
-                          (const S*)f0, FOUT, (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, mr, box)
-    if (variant & VAR_AA) {
-        if (parity) {
-            if (ntl) NEAR_GO(true, false, 2, f0);
-            else NEAR_GO(false, false, 2, f0);
-        } else {
-            if (ntl) NEAR_GO(true, false, 1, f0);
-            else NEAR_GO(false, false, 1, f0);
-        }
-    } else if (mrt) {
-        if (ntl) NEAR_GO(true, true, 0, f1);
-        else NEAR_GO(false, true, 0, f1);
-    } else {
-        if (ntl) NEAR_GO(true, false, 0, f1);
-        else NEAR_GO(false, false, 0, f1);
-    }
-#undef NEAR_GO
-}
-
 #define DISPATCH_STORAGE(storage, C, ...)                  \
     switch (storage) {                                     \
         case IBM_LB_F64: { using C = SF64; __VA_ARGS__; break; }  \
@@ -668,34 +568,33 @@ static void near_launch(int variant, const Geom& g, const LatticeParams& lp, con
 
 template <class C, bool IB, bool NTL, int BS>
 static void lattice_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                           int xcd, hipStream_t s, hipEvent_t e0, hipEvent_t e1, RowPart part) {
+                           int xcd, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     using R = typename C::real;
     using S = typename C::store_t;
     hipExtLaunchKernelGGL((k_lattice<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1, 0, g, lp,
                           (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row,
-                          xcd, part);
+                          xcd);
 }
 
 template <class C, bool IB, bool NTL, int BS>
 static void mrt_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
-                       int xcd, const MrtRates& mr, hipStream_t s, hipEvent_t e0, hipEvent_t e1, RowPart part) {
+                       int xcd, const MrtRates& mr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     using R = typename C::real;
     using S = typename C::store_t;
     hipExtLaunchKernelGGL((k_lattice_mrt<C, IB, NTL, BS>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0, e1, 0, g,
                           lp, (const S*)d.f[cur], (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl,
-                          A_row, xcd, mr, part);
+                          A_row, xcd, mr);
 }
 
 template <class C, bool IB, bool NTL>
 static void launch_mrt_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                         const double* A_row, const MrtRates& mr, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                         RowPart part) {
+                         const double* A_row, const MrtRates& mr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int xcd = (variant & VAR_X) ? 1 : 0;
     switch ((variant >> 1) & 3) {
-        case 0: mrt_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1, part); break;
-        case 1: mrt_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1, part); break;
-        case 2: mrt_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1, part); break;
-        default: mrt_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1, part); break;
+        case 0: mrt_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
+        case 1: mrt_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
+        case 2: mrt_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
+        default: mrt_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, mr, s, e0, e1); break;
     }
 }
 
@@ -723,8 +622,7 @@ static void launch_chi_v(int variant, const Geom& g, const LatticeParams& lp, co
 
 template <class C, bool IB, bool NTL, int BS, bool CHI = false>
 static void aa_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row, int xcd,
-                      int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr,
-                      RowPart part = RowPart{nullptr, ROWS_ALL}) {
+                      int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr) {
     using R = typename C::real;
     using S = typename C::store_t;
     unsigned char* ind = CHI ? d.ind : nullptr;
@@ -732,17 +630,17 @@ static void aa_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, 
     if (parity)
         hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, true, CHI>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0,
                               e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, xcd,
-                              ind, cr, part);
+                              ind, cr);
     else
         hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, false, CHI>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s,
                               e0, e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row,
-                              xcd, ind, cr, part);
+                              xcd, ind, cr);
 }
 
 template <class C, bool IB, bool NTL, bool NTS, bool CHI = false, bool MRT = false>
 static void rows_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row,
                         int rows, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr,
-                        const MrtRates* mr = nullptr, RowPart part = RowPart{nullptr, ROWS_ALL}) {
+                        const MrtRates* mr = nullptr) {
     using R = typename C::real;
     using S = typename C::store_t;
     const int T = rows * g.Lx;
@@ -751,51 +649,44 @@ static void rows_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d
     hipExtLaunchKernelGGL((k_lattice_rows<C, IB, NTL, NTS, CHI, MRT>), dim3(nb), dim3(T),
                           uint32_t(NXMOVE * T * sizeof(S)), s, e0, e1, 0, g, lp, (const S*)d.f[cur],
                           (S*)d.f[cur ^ 1], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, rows,
-                          CHI ? d.ind : nullptr, ch ? *ch : ChiRates{}, mr ? *mr : MrtRates{}, part);
+                          CHI ? d.ind : nullptr, ch ? *ch : ChiRates{}, mr ? *mr : MrtRates{});
 }
 
 template <class C, bool IB, bool NTL>
 static void launch_lattice_v(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
-                             const double* A_row, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                             RowPart part) {
+                             const double* A_row, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (variant & VAR_AA) {
         const int xcd = (variant & VAR_X) ? 1 : 0;
         switch ((variant >> 1) & 3) {
-            case 0: aa_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, nullptr, part); break;
-            case 1: aa_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, nullptr, part); break;
-            case 2: aa_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, nullptr, part); break;
-            default: aa_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, nullptr, part); break;
+            case 0: aa_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
+            case 1: aa_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
+            case 2: aa_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
+            default: aa_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1); break;
         }
         return;
     }
     if (variant & VAR_ROWS) {
         const int rows = lattice_rows_per_block(variant, g.Lx);
-        if (variant & VAR_X) rows_launch<C, IB, NTL, true>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, nullptr, part);
-        else rows_launch<C, IB, NTL, false>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, nullptr, part);
+        if (variant & VAR_X) rows_launch<C, IB, NTL, true>(g, lp, d, cur, A_row, rows, s, e0, e1);
+        else rows_launch<C, IB, NTL, false>(g, lp, d, cur, A_row, rows, s, e0, e1);
         return;
     }
     const int xcd = (variant & VAR_X) ? 1 : 0;
     switch ((variant >> 1) & 3) {
-        case 0: lattice_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, s, e0, e1, part); break;
-        case 1: lattice_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, s, e0, e1, part); break;
-        case 2: lattice_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, s, e0, e1, part); break;
-        default: lattice_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, s, e0, e1, part); break;
+        case 0: lattice_launch<C, IB, NTL, LAT_BS[0]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
+        case 1: lattice_launch<C, IB, NTL, LAT_BS[1]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
+        case 2: lattice_launch<C, IB, NTL, LAT_BS[2]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
+        default: lattice_launch<C, IB, NTL, LAT_BS[3]>(g, lp, d, cur, A_row, xcd, s, e0, e1); break;
     }
 }
 
 template <class C>
 hipError_t launch_lattice_c(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, bool ib,
                             const double* A_row, int variant, int parity, hipStream_t s, hipEvent_t e0,
-                            hipEvent_t e1, const MrtRates* mrt, const ChiRates* chi, RowPart part) {
-    if (part.mode != ROWS_ALL && !part.box) return hipErrorInvalidValue;
-    if (part.mode == ROWS_NEAR) {
-        if (!ib || chi) return hipErrorInvalidValue;
-        near_launch<C>(variant, g, lp, d, cur, A_row, parity, mrt, part.box, s, e0, e1);
-        return hipGetLastError();
-    }
+                            hipEvent_t e1, const MrtRates* mrt, const ChiRates* chi) {
     if (chi) {
-        // the indicator exists only with a droplet; every row in one launch
-        if (!ib || !d.ind || part.mode != ROWS_ALL) return hipErrorInvalidValue;
+        // the indicator exists only with a droplet
+        if (!ib || !d.ind) return hipErrorInvalidValue;
         if (variant & VAR_AA) {
             const int xcd = (variant & VAR_X) ? 1 : 0;
 #define CHI_AA(NTLV)                                                                                               \
@@ -841,8 +732,8 @@ hipError_t launch_lattice_c(const Geom& g, const LatticeParams& lp, const DevPtr
             const bool nts = (variant & VAR_X) != 0;
 #define MRT_ROWS(IBV, NTLV)                                                                                   \
     do {                                                                                                      \
-        if (nts) rows_launch<C, IBV, NTLV, true, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, mrt, part); \
-        else rows_launch<C, IBV, NTLV, false, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, mrt, part);  \
+        if (nts) rows_launch<C, IBV, NTLV, true, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, mrt); \
+        else rows_launch<C, IBV, NTLV, false, false, true>(g, lp, d, cur, A_row, rows, s, e0, e1, nullptr, mrt);  \
     } while (0)
             {
                 if (ib) {
@@ -858,22 +749,22 @@ hipError_t launch_lattice_c(const Geom& g, const LatticeParams& lp, const DevPtr
         }
         {
             if (ib) {
-                if (variant & 1) launch_mrt_v<C, true, true>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1, part);
-                else launch_mrt_v<C, true, false>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1, part);
+                if (variant & 1) launch_mrt_v<C, true, true>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
+                else launch_mrt_v<C, true, false>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
             } else {
-                if (variant & 1) launch_mrt_v<C, false, true>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1, part);
-                else launch_mrt_v<C, false, false>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1, part);
+                if (variant & 1) launch_mrt_v<C, false, true>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
+                else launch_mrt_v<C, false, false>(variant, g, lp, d, cur, A_row, *mrt, s, e0, e1);
             }
         }
         return hipGetLastError();
     }
     {
         if (ib) {
-            if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, parity, s, e0, e1, part);
-            else launch_lattice_v<C, true, false>(variant, g, lp, d, cur, A_row, parity, s, e0, e1, part);
+            if (variant & 1) launch_lattice_v<C, true, true>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
+            else launch_lattice_v<C, true, false>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
         } else {
-            if (variant & 1) launch_lattice_v<C, false, true>(variant, g, lp, d, cur, A_row, parity, s, e0, e1, part);
-            else launch_lattice_v<C, false, false>(variant, g, lp, d, cur, A_row, parity, s, e0, e1, part);
+            if (variant & 1) launch_lattice_v<C, false, true>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
+            else launch_lattice_v<C, false, false>(variant, g, lp, d, cur, A_row, parity, s, e0, e1);
         }
     }
     return hipGetLastError();

@@ -288,10 +288,9 @@ class Simulation:
         return v.value
 
     def set_variant(self, variant):
-        """Select a step variant directly (0 <= variant < 256: lattice layout and options in
+        """Select a step variant directly (0 <= variant < 128: lattice layout and options in
         bits 0-4, the smoothing's finish in the force kernel in bit 5, in-place streaming in
-        bit 6, the IB half overlapped with the next lattice update in bit 7; see
-        ibm_lb_set_variant)."""
+        bit 6; see ibm_lb_set_variant)."""
         _check(lib().ibm_lb_set_variant(self._h, int(variant)), "ibm_lb_set_variant")
 
     def timing(self, enable=True):

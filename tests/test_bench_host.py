@@ -40,9 +40,7 @@ def test_workloads_have_the_stated_shapes():
 def test_describe_variant_bits():
     d = bench.describe_variant(57)
     assert d == {"layout": "rows", "nontemporal_loads": True, "block": 128, "nontemporal_stores": True,
-                 "smoothing_finish_in_force_kernel": True, "in_place_streaming": False,
-                 "ib_half_beside_next_lattice_update": False}
-    assert bench.describe_variant(57 | 128)["ib_half_beside_next_lattice_update"]
+                 "smoothing_finish_in_force_kernel": True, "in_place_streaming": False}
     d = bench.describe_variant(2 | 8 | 64)
     assert d["layout"] == "linear" and d["block"] == 256 and d["xcd_grouped_order"] and d["in_place_streaming"]
 
@@ -62,7 +60,6 @@ def test_counter_traffic_only_for_the_profiled_kernel(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: sha)
     assert bench.counter_traffic("f32", "256cubed", 57) == 2582617607.0
     assert bench.counter_traffic("f32", "256cubed", 57 | 64) is None  # another lattice variant
-    assert bench.counter_traffic("f32", "256cubed", 57 | 128) is None  # the sweep in two launches
     assert bench.counter_traffic("f32", "256cubed", 57 & ~32) == 2582617607.0  # bit 5 is not a lattice bit
     assert bench.counter_traffic("f16dev", "256cubed", 34) is None  # profiled from another kernel source
     assert bench.counter_traffic("bf16dev", "256cubed", 34) is None  # no summary

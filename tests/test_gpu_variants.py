@@ -81,7 +81,7 @@ def test_row_layout_rejects_long_rows(ib):
     sim.step(np.zeros(9), 2)
     sim.close()
     sim = ib.Simulation((8, 8, 8), tau=0.8, storage="f32")
-    for bad in (8 * NVAR, -1, AA | ROWS | 1):  # step variants run below 256
+    for bad in (4 * NVAR, -1, AA | ROWS | 1):
         with pytest.raises(ib.IbmLbError):
             sim.set_variant(bad)
     sim.close()
