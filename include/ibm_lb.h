@@ -116,8 +116,9 @@ typedef struct ibm_lb_config {
     int32_t collision;     /* IBM_LB_BGK (0, the paper's single relaxation time) or IBM_LB_MRT:
                               multiple relaxation times (Sec. 3.1 mentions it as an option) on
                               the orthogonal moment basis of d'Humieres et al. (2002), the shear
-                              moments at 1/tau; MRT runs with two copies (linear or row
-                              layout), single droplets only, without the adjoint */
+                              moments at 1/tau; MRT runs every layout (two copies: linear or
+                              rows; one copy: in place), single droplets only, without the
+                              adjoint */
     double mrt_s[5];       /* MRT rates in (0, 2) of the energy, energy-square, heat-flux,
                               third-order stress and third-order antisymmetric moments;
                               0 selects 1.19, 1.4, 1.2, 1.4, 1.98 */
@@ -282,9 +283,8 @@ int ibm_lb_load(ibm_lb* h, const void* src, size_t n);
  * EDEVICE, sticky.
  *
  * ibm_lb_set_variant selects a variant directly (EINVAL if out of range,
- * bits 4 and 6 together, bit 6 clear on a one-copy handle, bit 4 or 6 on an
- * MRT handle, bit 6 with wet-node walls, or the row layout cannot take this
- * box). The default is 33 (linear layout,
+ * bits 4 and 6 together, bit 6 clear on a one-copy handle, bit 6 with
+ * wet-node walls, or the row layout cannot take this box). The default is 33 (linear layout,
  * 128-thread work-groups, non-temporal loads, bit 5), or 96 on a one-copy
  * handle (in place, 128-thread work-groups, bit 5). */
 int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant);

@@ -136,8 +136,6 @@ int validate(const ibm_lb_config* c) {
     if (c->collision != IBM_LB_BGK && c->collision != IBM_LB_MRT) return fail(IBM_LB_EINVAL, "unknown collision");
     for (int k = 0; k < 5; ++k)
         if (!(c->mrt_s[k] >= 0.0 && c->mrt_s[k] < 2.0)) return fail(IBM_LB_EINVAL, "MRT rates must lie in (0, 2)");
-    if (c->collision == IBM_LB_MRT && c->populations == 1)
-        return fail(IBM_LB_EINVAL, "MRT runs with two population copies");
     if (c->walls != IBM_LB_WALLS_LINK && c->walls != IBM_LB_WALLS_WET) return fail(IBM_LB_EINVAL, "unknown walls");
     if (c->walls == IBM_LB_WALLS_WET && c->populations == 1)
         return fail(IBM_LB_EINVAL, "wet-node walls run with two population copies");
@@ -1103,7 +1101,7 @@ int ibm_lb_autotune(ibm_lb* h, int32_t reps, int32_t* variant) {
     if (!h->single)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
             cand[nc++] = v | VAR_HC_SPLIT;
-    if (!h->mrt && !h->wet)
+    if (!h->wet)
         for (int v = 0; v < LATTICE_VARIANTS; ++v)
             if (!(v & VAR_ROWS)) cand[nc++] = v | VAR_HC_SPLIT | VAR_AA;
     tune(cand, nc, best_of);
@@ -1127,7 +1125,6 @@ int ibm_lb_set_variant(ibm_lb* h, int32_t variant) {
     if (!lattice_variant_ok(variant, h->g)) return fail(IBM_LB_EINVAL, "lattice variant cannot run on this box");
     if (h->single && !(variant & VAR_AA))
         return fail(IBM_LB_EINVAL, "a handle with one population copy runs in-place variants only");
-    if (h->mrt && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "MRT runs with two copies");
     if (h->wet && (variant & VAR_AA)) return fail(IBM_LB_EINVAL, "wet-node walls run with two copies");
     h->lattice_variant = variant;
     return IBM_LB_OK;

@@ -161,8 +161,8 @@ int lattice_variant_ok(int variant, const Geom& g);
 // e0/e1 (may be null): events stamped at the start and at the completion of
 // the dispatch.
 // parity: for an in-place variant, 0 for the even step, 1 for the odd one.
-// mrt (may be null): MRT collision with these rates instead of BGK (two
-// copies, linear or row layout).
+// mrt (may be null): MRT collision with these rates instead of BGK (any
+// layout).
 // chi (may be null): nodes whose indicator byte d.ind is set relax with
 // these rates; the byte is cleared (BGK, two copies, linear or row layout).
 hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,

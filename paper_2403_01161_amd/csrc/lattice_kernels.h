@@ -402,22 +402,23 @@ __global__ __launch_bounds__(BS) void k_lattice_chi(Geom g, LatticeParams lp,
 }
 
 // In-place (single-copy) form, linear layout: ODD selects the step parity.
-// CHI: the viscosity ratio's inner rates on the nodes the indicator marks.
-template <class C, bool IB, bool NTL, int BS, bool ODD, bool CHI = false>
+// CHI: the viscosity ratio's inner rates on the nodes the indicator marks;
+// MRT: the multiple-relaxation-time collision with the rates mr.
+template <class C, bool IB, bool NTL, int BS, bool ODD, bool CHI = false, bool MRT = false>
 __global__ __launch_bounds__(BS) void k_lattice_aa(Geom g, LatticeParams lp, typename C::store_t* f,
                                                     typename C::real* __restrict__ F,
                                                     typename C::real* __restrict__ U,
                                                     const int* __restrict__ mark, Ctl* ctl,
                                                     const double* __restrict__ Arow, int xcd,
                                                     unsigned char* __restrict__ ind = nullptr,
-                                                    ChiRates ch = ChiRates{}) {
+                                                    ChiRates ch = ChiRates{}, MrtRates mr = MrtRates{}) {
     const unsigned b = xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
     const long long n = (long long)b * BS + threadIdx.x;
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    lattice_node<C, IB, NTL, false, false, false, ODD ? 2 : 1, false, CHI>(
-        g, lp, (const typename C::store_t*)f, f, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0, 0, nullptr, ind, &ch);
+    lattice_node<C, IB, NTL, false, false, false, ODD ? 2 : 1, MRT, CHI>(
+        g, lp, (const typename C::store_t*)f, f, F, U, mark, ctl, Arow, n, x, y, z, nullptr, 0, 0, &mr, ind, &ch);
 }
 
 // After an even in-place step, back to natural order in place. In the odd
@@ -620,21 +621,37 @@ static void launch_chi_v(int variant, const Geom& g, const LatticeParams& lp, co
     }
 }
 
-template <class C, bool IB, bool NTL, int BS, bool CHI = false>
+template <class C, bool IB, bool NTL, int BS, bool CHI = false, bool MRT = false>
 static void aa_launch(const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur, const double* A_row, int xcd,
-                      int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr) {
+                      int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const ChiRates* ch = nullptr,
+                      const MrtRates* mr = nullptr) {
     using R = typename C::real;
     using S = typename C::store_t;
     unsigned char* ind = CHI ? d.ind : nullptr;
     const ChiRates cr = ch ? *ch : ChiRates{};
+    const MrtRates mrr = mr ? *mr : MrtRates{};
     if (parity)
-        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, true, CHI>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s, e0,
-                              e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row, xcd,
-                              ind, cr);
+        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, true, CHI, MRT>), dim3(blocks_for(g.N, BS)), dim3(BS), 0,
+                              s, e0, e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row,
+                              xcd, ind, cr, mrr);
     else
-        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, false, CHI>), dim3(blocks_for(g.N, BS)), dim3(BS), 0, s,
-                              e0, e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row,
-                              xcd, ind, cr);
+        hipExtLaunchKernelGGL((k_lattice_aa<C, IB, NTL, BS, false, CHI, MRT>), dim3(blocks_for(g.N, BS)), dim3(BS), 0,
+                              s, e0, e1, 0, g, lp, (S*)d.f[cur], (R*)d.F, (R*)d.u, (const int*)d.mark, d.ctl, A_row,
+                              xcd, ind, cr, mrr);
+}
+
+// MRT, in place (one copy), linear layout.
+template <class C, bool IB, bool NTL>
+static void launch_mrt_aa(int variant, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
+                          const double* A_row, int parity, const MrtRates* mr, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1) {
+    const int xcd = (variant & VAR_X) ? 1 : 0;
+    switch ((variant >> 1) & 3) {
+        case 0: aa_launch<C, IB, NTL, LAT_BS[0], false, true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, nullptr, mr); break;
+        case 1: aa_launch<C, IB, NTL, LAT_BS[1], false, true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, nullptr, mr); break;
+        case 2: aa_launch<C, IB, NTL, LAT_BS[2], false, true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, nullptr, mr); break;
+        default: aa_launch<C, IB, NTL, LAT_BS[3], false, true>(g, lp, d, cur, A_row, xcd, parity, s, e0, e1, nullptr, mr); break;
+    }
 }
 
 template <class C, bool IB, bool NTL, bool NTS, bool CHI = false, bool MRT = false>
@@ -726,7 +743,16 @@ hipError_t launch_lattice_c(const Geom& g, const LatticeParams& lp, const DevPtr
         return hipGetLastError();
     }
     if (mrt) {
-        if (variant & VAR_AA) return hipErrorInvalidValue;
+        if (variant & VAR_AA) {
+            if (ib) {
+                if (variant & 1) launch_mrt_aa<C, true, true>(variant, g, lp, d, cur, A_row, parity, mrt, s, e0, e1);
+                else launch_mrt_aa<C, true, false>(variant, g, lp, d, cur, A_row, parity, mrt, s, e0, e1);
+            } else {
+                if (variant & 1) launch_mrt_aa<C, false, true>(variant, g, lp, d, cur, A_row, parity, mrt, s, e0, e1);
+                else launch_mrt_aa<C, false, false>(variant, g, lp, d, cur, A_row, parity, mrt, s, e0, e1);
+            }
+            return hipGetLastError();
+        }
         if (variant & VAR_ROWS) {
             const int rows = lattice_rows_per_block(variant, g.Lx);
             const bool nts = (variant & VAR_X) != 0;

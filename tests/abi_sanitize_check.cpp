@@ -89,6 +89,9 @@ int main(int argc, char** argv) {
         c.chi = 1.0;
         c.collision = IBM_LB_MRT;
         expect(size_rc(c) == IBM_LB_OK, "MRT");
+        c.populations = 1;
+        expect(size_rc(c) == IBM_LB_OK, "MRT in place");
+        c.populations = 0;
         c.collision = IBM_LB_BGK;
         c.walls = IBM_LB_WALLS_WET;
         expect(size_rc(c) == IBM_LB_OK, "wet walls");

@@ -117,7 +117,7 @@ def test_deterministic_spreading_sizes(ib):
     dict(L=(7, 16, 16)), dict(tau=0.5), dict(sigma=-1.0), dict(radius=0.0), dict(rho0=0.0),
     dict(storage=7), dict(init=5), dict(reg_sign=2), dict(reg_max_iter=-1),
     dict(f16_scale=3.0, storage="f16dev"), dict(A0=[np.nan] + [0] * 8), dict(populations=3),
-    dict(collision=2), dict(collision="mrt", mrt_s=[2.0, 1, 1, 1, 1]), dict(collision="mrt", populations=1),
+    dict(collision=2), dict(collision="mrt", mrt_s=[2.0, 1, 1, 1, 1]),
     dict(walls=2), dict(walls="wet", populations=1), dict(deterministic=2),
 ])
 def test_invalid_parameters(ib, bad):

@@ -1,7 +1,7 @@
 """GPU MRT collision against the FP64 oracle's MRT (same basis and rates),
-its variants (linear and row layouts) bit-identical to each other on a
-lattice-only box, and its limits (two copies, single droplets, no
-adjoint)."""
+with two population copies and with one (in place); its variants (linear,
+row and in-place layouts) bit-identical to each other on a lattice-only box;
+its limits (single droplets, no adjoint)."""
 import numpy as np
 import pytest
 
@@ -60,6 +60,31 @@ def test_mrt_droplet_matches_oracle(ib, storage, mrt_s, tol):
     ref.close()
 
 
+@pytest.mark.parametrize("pops,variant,steps", [(1, AA | SPLIT | 1, 31), (2, AA | SPLIT | 8, 30)])
+def test_mrt_in_place_matches_oracle(ib, pops, variant, steps):
+    """In-place streaming with MRT: one population copy (an odd step count
+    leaves it in the odd mapping until the reads), or in-place variants on a
+    two-copy handle."""
+    L = (19, 17, 21)
+    A, kw = _case(L)
+    rates = [1.5, 1.1, 1.7, 1.3, 1.0]
+    print(f"case MRT in place: populations {pops}, variant {variant}, {steps} steps", flush=True)
+    sim = ib.Simulation(L, storage="f64", collision="mrt", mrt_s=rates, populations=pops, **kw)
+    sim.set_variant(variant)
+    ref = oracle.Oracle(L, collision="mrt", mrt_s=rates, **kw)
+    sim.step(A, steps)
+    ref.step(A, steps)
+    dr = np.abs(sim.vertices() - ref.vertices()).max()
+    rho_g, u_g = sim.fields()
+    rho_r, u_r = ref.fields()
+    du = np.abs(u_g - u_r).max() / np.abs(u_r).max()
+    drho = np.abs(rho_g - rho_r).max()
+    print(f"  max|dr| {dr:.2e}, max|du|/max|u| {du:.2e}, max|drho| {drho:.2e}", flush=True)
+    assert dr <= 1e-11 and du <= 1e-11 and drho <= 1e-13
+    sim.close()
+    ref.close()
+
+
 def test_mrt_equal_rates_match_bgk(ib):
     L = (19, 17, 21)
     A, kw = _case(L)
@@ -77,7 +102,7 @@ def test_mrt_equal_rates_match_bgk(ib):
 def test_mrt_variants_bit_identical(ib):
     L, A = (40, 9, 11), _traceless(2e-3, 3)
     states = {}
-    for v in (1, 0, 3, 5, 7, 8, 9, SPLIT | 1, ROWS | 1, ROWS | 9, ROWS, ROWS | 3):
+    for v in (1, 0, 3, 5, 7, 8, 9, SPLIT | 1, ROWS | 1, ROWS | 9, ROWS, ROWS | 3, AA | 1, AA | 3, AA | 8 | 1):
         sim = ib.Simulation(L, 0.8, storage="f32", A0=A, collision="mrt", periodic=(1, 0, 0))
         sim.set_variant(v)
         sim.step(A, 7)
@@ -90,11 +115,11 @@ def test_mrt_variants_bit_identical(ib):
 def test_mrt_limits(ib):
     L = (12, 10, 9)
     A, kw = _case((19, 17, 21))
-    sim = ib.Simulation(L, 0.8, storage="f32", A0=A, collision="mrt")
+    sim = ib.Simulation(L, 0.8, storage="f32", A0=A, collision="mrt", populations=1)
     with pytest.raises(ib.IbmLbError):
-        sim.set_variant(AA | 1)
+        sim.set_variant(1)  # one copy: in-place variants only
     v = sim.autotune(2)
-    assert not (v & AA)
+    assert v & AA
     sim.close()
     with pytest.raises(ib.IbmLbError):
         ib.Ensemble([dict(L=(8, 8, 8), tau=0.8, collision="mrt")], storage="f32")
