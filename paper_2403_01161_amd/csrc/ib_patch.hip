@@ -280,7 +280,13 @@ struct Stage {
     int ok[PATCH];
 };
 
-constexpr int SPREAD_WCAP = 2048;  // nodes of the FP64 spreading window
+// Nodes of the FP64 spreading window: 3 x 1456 x 8 B = 34,944 B of dynamic
+// LDS, so that with the force kernel's static LDS (about 5 KB in FP32) four
+// work-groups fit in a CU's 160 KB, as many as its registers allow. A patch's
+// window (the box of its vertices' stencils) holds 300-900 nodes on average
+// for the benchmark meshes, up to about 1400 for a 2562-vertex droplet of
+// radius 12 stretched to D = 0.3; a larger one falls back to direct atomics.
+constexpr int SPREAD_WCAP = 1456;
 
 // Accumulate the staged vertices [lo_v, hi_v) into an LDS window and flush
 // each touched node once to F; false if their window exceeds the capacity.
@@ -358,9 +364,9 @@ __device__ void det_stage(const IbArgs<R, AS>& a, int p, const Stage<R>& st) {
         }
         rec->ok = ok;
     }
-    if (t < 3) {
-        a.pbox[8 * p + t] = w.o[t];
-        a.pbox[8 * p + 3 + t] = w.e[t];
+    if (t < 3) {  // selected, not indexed: a per-thread index would put the window in scratch
+        a.pbox[8 * p + t] = t == 0 ? w.o[0] : (t == 1 ? w.o[1] : w.o[2]);
+        a.pbox[8 * p + 3 + t] = t == 0 ? w.e[0] : (t == 1 ? w.e[1] : w.e[2]);
     }
 }
 
