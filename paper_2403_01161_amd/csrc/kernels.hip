@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256) void k_obs_partial(int nt, const int4* __restr
 
 // Symmetric 3x3 eigenpairs by cyclic Jacobi rotations (FP64), descending, each
 // eigenvector with its largest-magnitude component positive.
-__device__ void jacobi3(const double S[9], double ev[3], double vec[9]) {
+__device__ __forceinline__ void jacobi3(const double S[9], double ev[3], double vec[9]) {
     double a[3][3], v[3][3];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
@@ -443,22 +443,36 @@ __device__ void jacobi3(const double S[9], double ev[3], double vec[9]) {
                 }
             }
     }
-    int o[3] = {0, 1, 2};
-    for (int i = 0; i < 3; ++i)
-        for (int j = i + 1; j < 3; ++j)
-            if (a[o[j]][o[j]] > a[o[i]][o[i]]) {
-                const int t = o[i];
-                o[i] = o[j];
-                o[j] = t;
+    // eigenpairs by decreasing eigenvalue: compare-exchanges (0, 1), (0, 2),
+    // (1, 2) of the diagonal that carry the columns of v along (constant
+    // indices throughout, so the arrays stay in registers)
+    double e[3] = {a[0][0], a[1][1], a[2][2]};
+    double c[3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) c[k][i] = v[i][k];
+    auto cx = [&](int i, int j) {
+        if (e[j] > e[i]) {
+            const double t = e[i];
+            e[i] = e[j];
+            e[j] = t;
+            for (int m = 0; m < 3; ++m) {
+                const double u = c[i][m];
+                c[i][m] = c[j][m];
+                c[j][m] = u;
             }
+        }
+    };
+    cx(0, 1);
+    cx(0, 2);
+    cx(1, 2);
     for (int k = 0; k < 3; ++k) {
-        const int col = o[k];
-        ev[k] = a[col][col];
-        int big = 0;
-        for (int i = 1; i < 3; ++i)
-            if (fabs(v[i][col]) > fabs(v[big][col])) big = i;
-        const double sg = v[big][col] < 0.0 ? -1.0 : 1.0;
-        for (int i = 0; i < 3; ++i) vec[3 * k + i] = sg * v[i][col];
+        ev[k] = e[k];
+        // sign: the largest component (the first of equal ones) positive
+        double big = c[k][0];
+        if (fabs(c[k][1]) > fabs(big)) big = c[k][1];
+        if (fabs(c[k][2]) > fabs(big)) big = c[k][2];
+        const double sg = big < 0.0 ? -1.0 : 1.0;
+        for (int i = 0; i < 3; ++i) vec[3 * k + i] = sg * c[k][i];
     }
 }
 
