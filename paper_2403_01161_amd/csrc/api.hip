@@ -91,7 +91,7 @@ Layout make_layout(int storage, long long N, int ntiles, int nv, int nt, size_t 
     L.mass_part = take(sizeof(double) * 4 * MASS_BLOCKS);
     L.obs_out = take(sizeof(double) * OBS_OUT_N);
     L.Abuf = take(sizeof(double) * 9 * (ACAP + 1));
-    L.red = take(sizeof(unsigned long long) * 2);
+    L.red = take(sizeof(unsigned long long) * (RED_SLOTS + 1));
     L.ind = take(ind_b);
     L.ind_lines = take(sizeof(int) * 2 * lines);
     L.ptris = take(ind_b ? sizeof(int4) * (size_t)nt : 0);
@@ -763,7 +763,8 @@ int ibm_lb_init(const ibm_lb_config* cfg, ibm_lb** out) {
     INIT_TRY(hipMemsetAsync(d.F, 0, 3 * rb * (size_t)h->g.N, h->stream), "zero F");
     INIT_TRY(hipMemsetAsync(d.u, 0, 3 * rb * (size_t)h->g.N, h->stream), "zero u");
     INIT_TRY(hipMemsetAsync(d.mark, 0, sizeof(int) * (size_t)ntiles, h->stream), "zero marks");
-    INIT_TRY(hipMemsetAsync(d.red, 0, 2 * sizeof(unsigned long long), h->stream), "zero reduction slots");
+    INIT_TRY(hipMemsetAsync(d.red, 0, (RED_SLOTS + 1) * sizeof(unsigned long long), h->stream),
+             "zero reduction slots");
     Ctl ctl0{};
     ctl0.epoch = 1;
     INIT_TRY(hipMemcpyAsync(d.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice, h->stream), "ctl");

@@ -458,6 +458,27 @@ __device__ inline float from_bits<float>(unsigned long long b) { return __uint_a
 template <>
 __device__ inline double from_bits<double>(unsigned long long b) { return __longlong_as_double((long long)b); }
 
+// The step's largest |p - q| so far: the maximum over the reduction slots,
+// one slot a lane, folded across the wave (every lane of the calling wave
+// active; each wave gets the value).
+template <class R, int AS>
+__device__ inline R red_max(const IbArgs<R, AS>& a) {
+    unsigned long long v = a.red[threadIdx.x & (RED_SLOTS - 1)];
+    for (int m = 32; m > 0; m >>= 1) {
+        const unsigned long long o = __shfl_xor(v, m, 64);
+        v = o > v ? o : v;
+    }
+    return from_bits<R>(v);
+}
+
+// Zero the reduction slots and the arrival count (the first wave of a
+// work-group).
+template <class R, int AS>
+__device__ inline void red_clear(const IbArgs<R, AS>& a) {
+    if (threadIdx.x < RED_SLOTS) a.red[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) a.red[RED_SLOTS] = 0ull;
+}
+
 template <class R, int AS>
 __device__ int hc_more_iterations(const IbArgs<R, AS>& a, bool* capped);
 
@@ -549,7 +570,7 @@ __device__ void fs_step(const IbArgs<R>& a, int fold, int npatch, const V4<R>* P
     if (fold) {
         bool more = false, capped = false;
         if (a.sp.max_iter > 0) {
-            const bool converged = from_bits<R>(*a.red) < R(a.sp.tol);
+            const bool converged = red_max(a) < R(a.sp.tol);
             capped = !converged && a.sp.max_iter <= 1;
             more = !converged && !capped;
         }
@@ -797,10 +818,9 @@ __global__ __launch_bounds__(IBT) void k_interp_patch(IbArgs<R> a, int fold) {
     // the step's reduction slots start at zero; with the smoothing's finish
     // folded into the force kernel, the step epoch advances here (nothing
     // between this launch and the force kernel reads it)
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.red[0] = 0ull;
-        a.red[1] = 0ull;
-        if (fold) a.ctl->epoch += 1;
+    if (blockIdx.x == 0) {
+        red_clear(a);
+        if (fold && threadIdx.x == 0) a.ctl->epoch += 1;
     }
     interp_patch(a, blockIdx.x, reinterpret_cast<R*>(dyn));
 }
@@ -941,16 +961,16 @@ __device__ void hc_fused(const IbArgs<R, AS>& a, int p, int npatch, bool split) 
         if (t == 0 && on) {
             R b = bred[0];
             for (int w = 1; w < IBT / 64; ++w) b = fmax(b, bred[w]);
-            atom_max(a.red, max_bits(b));
+            atom_max(a.red + (p & (RED_SLOTS - 1)), max_bits(b));
         }
         return;
     }
     if (t == 0) {
         R b = bred[0];
         for (int w = 1; w < IBT / 64; ++w) b = fmax(b, bred[w]);
-        if (on) atom_max(a.red, max_bits(b));
+        if (on) atom_max(a.red + (p & (RED_SLOTS - 1)), max_bits(b));
         __threadfence();
-        last = atom_inc(a.red + 1) == (unsigned long long)(npatch - 1);
+        last = atom_inc(a.red + RED_SLOTS) == (unsigned long long)(npatch - 1);
     }
     __syncthreads();
     if (!last) return;
@@ -980,7 +1000,7 @@ __device__ int hc_more_iterations(const IbArgs<R, AS>& a, bool* capped_out) {
     __shared__ int more;
     const int t = threadIdx.x, nth = blockDim.x;
     const R alpha = R(a.sp.alpha), gamma = R(a.sp.gamma), tol = R(a.sp.tol), sgn = R(a.sp.sign);
-    const R dmax = from_bits<R>(*a.red);
+    const R dmax = red_max(a);
     int it = 1;
     bool capped = false;
     bool converged = dmax < tol;
@@ -1025,7 +1045,7 @@ __device__ void hc_finish(const IbArgs<R, AS>& a) {
         if (t == 0) {
             a.ctl->iters = 0;
             a.ctl->epoch += 1;
-            a.red[1] = 0ull;
+            a.red[RED_SLOTS] = 0ull;
         }
         return;
     }
@@ -1035,9 +1055,8 @@ __device__ void hc_finish(const IbArgs<R, AS>& a) {
         a.ctl->iters = it;
         if (capped) a.ctl->cap_hits += 1;
         a.ctl->epoch += 1;
-        a.red[0] = 0ull;
-        a.red[1] = 0ull;
     }
+    red_clear(a);
 }
 
 // ---------------------------------------------------------------- ensemble forms

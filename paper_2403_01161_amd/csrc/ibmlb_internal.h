@@ -87,7 +87,7 @@ struct DevPtrs {
     double* mass_part;       // [MASS_BLOCKS][4]
     double* obs_out;         // [48] final observables
     double* Abuf;            // [ACAP][9] gradient rows
-    unsigned long long* red; // [2] grid-wide max reduction slots
+    unsigned long long* red; // [RED_SLOTS + 1] grid-wide max |p - q| (spread over slots), arrival count
     unsigned char* ind;      // [N rounded up to 4] inside indicator (viscosity ratio only)
     int* ind_lines;          // [2][Ly Lz] node range of each x-row's crossings (viscosity ratio only)
     int4* ptris;             // [nt] triangles grouped by the patch of their lowest vertex (viscosity ratio only)
@@ -125,6 +125,12 @@ struct LatDesc {
 // IB_PATCH consecutive vertices spatially compact; the patch-organised IB
 // kernels give one work-group to one patch.
 constexpr int IB_PATCH = 64;
+
+// Slots of the smoothing's grid-wide maximum: work-group p folds its value
+// into slot p mod RED_SLOTS (device-scope atomics on one address serialise,
+// and a step has up to thousands of work-groups); readers take the maximum of
+// all slots. Slot RED_SLOTS counts arrivals.
+constexpr int RED_SLOTS = 64;
 
 constexpr int OBS_BLOCKS = 128;
 constexpr int MASS_BLOCKS = 512;
