@@ -1063,8 +1063,10 @@ __device__ void hc_finish(const IbArgs<R, AS>& a) {
 // Work-group b of a batched launch takes patch map[b].y of member map[b].x.
 // The member's record is read from memory and its pointers are taken as
 // global ones.
+// Registers bounded for six waves per SIMD: left free, the compiler took 127
+// (four waves), although the single-droplet form needs 71.
 template <class R>
-__global__ __launch_bounds__(IBT) void k_interp_batch(const IbArgs<R>* __restrict__ args,
+__global__ __launch_bounds__(IBT, 6) void k_interp_batch(const IbArgs<R>* __restrict__ args,
                                                        const int2* __restrict__ map) {
     extern __shared__ __align__(16) unsigned char dyn[];
     const int2 e = map[blockIdx.x];

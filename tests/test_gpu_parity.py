@@ -69,6 +69,20 @@ def test_lattice_only_walls_ragged(ib, storage, tol):
 
 
 @pytest.mark.parametrize("storage,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_patch_windows_beyond_capacity(ib, storage, tol):
+    """A coarse mesh on a large droplet (162 vertices in three patches, R 9):
+    each patch's stencils span about 22 x 22 x 13 nodes, beyond the LDS
+    windows of the interpolation (2048 nodes) and of the spreading (1456), so
+    both kernels take their direct global-memory paths."""
+    L = (27, 26, 28)
+    A = _traceless(2e-3, 5)
+    sim, ref = _pair(ib, storage, L, R=9.0, level=2, tau=0.9, sigma=0.02, A0=A)
+    sim.step(A, 25)
+    ref.step(A, 25)
+    _compare(sim, ref, **tol)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
 def test_droplet_walls_ragged(ib, storage, tol):
     L = (19, 17, 21)
     A = _traceless(3e-3, 2)
