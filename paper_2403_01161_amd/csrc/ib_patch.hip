@@ -551,7 +551,7 @@ __device__ void fs_all_vertices(const IbArgs<R>& a, const V4<R>* P, int commit, 
 
 // The smoothing's finish folded into the force kernel (bit 5 of the step
 // variant; not with the deterministic spreading). Every work-group takes the
-// same decision from the reduction slot that the first smoothing iteration
+// same decision from the reduction slots that the first smoothing iteration
 // filled: when that iteration converged, hit the iteration cap or smoothing
 // is off, work-group 0 records the count and every work-group treats its own
 // patch; otherwise (rare) work-group 0 alone runs the further iterations,
@@ -562,7 +562,7 @@ template <class R, bool CHI>
 __device__ void fs_step(const IbArgs<R>& a, int fold, int npatch, const V4<R>* P, int commit, Stage<R>& st,
                         double* win, const IndArgs* ia) {
     const int t = threadIdx.x;
-    // this thread's vertex position, loaded together with the reduction slot
+    // this thread's vertex position, loaded together with the reduction slots
     // so that the two loads overlap
     const int k0 = blockIdx.x * PATCH + t;
     V4<R> pos0{};
@@ -886,7 +886,7 @@ __device__ void hc_finish(const IbArgs<R, AS>& a);
 // Phase 1: p' and b of iteration 1 (q = o) for the patch's vertices and its
 // halo (ring neighbours outside the patch) from the rings of o, into LDS.
 // Phase 2: p of the patch's vertices from the b of their rings (LDS), into
-// qa, and max |p - o| folded into the reduction slot. The last work-group to
+// qa, and max |p - o| folded into its reduction slot. The last work-group to
 // arrive (counted in the second slot) sees every patch's result and finishes
 // the step: the convergence test, further iterations in the rare case they
 // are needed, the iteration count and the epoch. The arithmetic is that of a
@@ -894,7 +894,7 @@ __device__ void hc_finish(const IbArgs<R, AS>& a);
 constexpr int HALO_CAP = MAXV * PATCH;  // no patch can have more halo vertices
 
 // split: no arrival count; a later launch (k_hc_finish_batch) finishes the
-// step from the reduction slot. This spares every work-group the
+// step from the reduction slots. This spares every work-group the
 // device-scope release that must precede its arrival (on this device a
 // write-back of its XCD's L2), which costs more than a launch once there are
 // thousands of work-groups.
@@ -991,7 +991,7 @@ __global__ __launch_bounds__(1024) void k_hc_finish(IbArgs<R> a) {
 }
 
 // One work-group, after iteration 1 is in qa and its maximum in the
-// reduction slot (smoothing on): continue while not converged (rare) and
+// reduction slots (smoothing on): continue while not converged (rare) and
 // leave the final positions in qa. Returns the iteration count; *capped_out
 // tells whether the cap ended it.
 template <class R, int AS>
@@ -1037,7 +1037,7 @@ __device__ int hc_more_iterations(const IbArgs<R, AS>& a, bool* capped_out) {
 
 // The finish of a step's smoothing in one work-group (the last smoothing
 // work-group to arrive, or one per ensemble member): further iterations if
-// needed, the iteration count, the epoch, and both reduction slots reset.
+// needed, the iteration count, the epoch, and the reduction slots reset.
 template <class R, int AS>
 __device__ void hc_finish(const IbArgs<R, AS>& a) {
     const int t = threadIdx.x;
