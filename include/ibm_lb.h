@@ -117,8 +117,8 @@ typedef struct ibm_lb_config {
                               multiple relaxation times (Sec. 3.1 mentions it as an option) on
                               the orthogonal moment basis of d'Humieres et al. (2002), the shear
                               moments at 1/tau; MRT runs every layout (two copies: linear or
-                              rows; one copy: in place), single droplets only, without the
-                              adjoint */
+                              rows; one copy: in place), in ensembles whose members all run
+                              it (each with its own rates), without the adjoint */
     double mrt_s[5];       /* MRT rates in (0, 2) of the energy, energy-square, heat-flux,
                               third-order stress and third-order antisymmetric moments;
                               0 selects 1.19, 1.4, 1.2, 1.4, 1.98 */
@@ -305,8 +305,9 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
 /* ---- ensembles of independent droplets (one set of launches per step) ----
  * The paper's statistics come from many independent trajectories, one
  * droplet each (Sec. 4); an ensemble advances n of them together. Members
- * may differ in box size, periodicity, tau, sigma, mesh and gradient history
- * but share one storage format. Each step is one batched launch of the fused
+ * may differ in box size, periodicity, tau, sigma, MRT rates, mesh and
+ * gradient history but share one storage format and one collision (BGK or
+ * MRT). Each step is one batched launch of the fused
  * lattice kernel over every member's nodes, then the batched IB kernels over
  * every member's surface patches; work-groups map to members by per-block
  * tables, so heterogeneous boxes balance by block count. Runs of steps are
@@ -314,8 +315,9 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
  *
  * ibm_lb_batch_init: cfgs[n] as for ibm_lb_init (each member's workspace
  *   rule applies; cfgs[i].stream is ignored); all work goes to `stream`.
- *   Errors: EINVAL (n < 1, mixed storage, a member with one population
- *   copy, any member invalid), ENOMEM, EDEVICE.
+ *   Errors: EINVAL (n < 1, mixed storage or collision, a member with one
+ *   population copy, wet-node walls, a viscosity ratio or deterministic
+ *   spreading, any member invalid), ENOMEM, EDEVICE.
  * ibm_lb_batch_step: A_tables is host memory [n][nsteps][9] (member-major),
  *   copied before return; member i's step j uses A_tables + 9 (i nsteps + j).
  * ibm_lb_batch_observables: out[n]; synchronising; returns the first member

@@ -1410,6 +1410,8 @@ struct ibm_lb_batch {
     int64_t step = 0;
     bool f_ready = false;
     int variant = 1;
+    bool mrt = false;             // every member runs MRT (rates per member in mrt_rates)
+    double* mrt_rates = nullptr;  // device [n][19]
     // HIP graphs of `graph_steps` batched steps (even; 0 = plain launches),
     // one per population parity, recaptured when the variant changes
     int graph_steps = 32;
@@ -1438,7 +1440,8 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
         if (cfgs[i].storage != cfgs[0].storage) return fail(IBM_LB_EINVAL, "ensemble members need one storage format");
     for (int i = 0; i < n; ++i) {
         if (cfgs[i].populations == 1) return fail(IBM_LB_EINVAL, "ensemble members keep two population copies");
-        if (cfgs[i].collision != IBM_LB_BGK) return fail(IBM_LB_EINVAL, "ensemble members run BGK");
+        if (cfgs[i].collision != cfgs[0].collision)
+            return fail(IBM_LB_EINVAL, "ensemble members share one collision (BGK or MRT)");
         if (cfgs[i].walls != IBM_LB_WALLS_LINK) return fail(IBM_LB_EINVAL, "ensemble members run link walls");
         if (chi_active(&cfgs[i])) return fail(IBM_LB_EINVAL, "ensemble members run one fluid");
         if (cfgs[i].deterministic) return fail(IBM_LB_EINVAL, "ensemble members spread with atomics");
@@ -1463,6 +1466,17 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     b->device = b->m[0]->device;
     auto bail = [&](hipError_t e, const char* where) { return batch_fail_cleanup(b, hip_fail(e, where)); };
     hipError_t e;
+    b->mrt = cfgs[0].collision == IBM_LB_MRT;
+    if (b->mrt) {
+        std::vector<double> rates(19 * (size_t)n);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < 19; ++k) rates[19 * (size_t)i + k] = b->m[i]->mrt_rates.s[k];
+        if ((e = hipMalloc((void**)&b->mrt_rates, sizeof(double) * rates.size())) != hipSuccess)
+            return bail(e, "MRT rates");
+        if ((e = hipMemcpy(b->mrt_rates, rates.data(), sizeof(double) * rates.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return bail(e, "MRT rates");
+    }
     std::vector<LatDesc> ld(n);
     std::vector<int2> lm[8], lm_plain[8], pm;
     bool rows_ok[4] = {true, true, true, true};
@@ -1480,6 +1494,7 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
         L.mark = h->d.mark;
         L.ctl = h->d.ctl;
         L.A = nullptr;  // set below, once the table is allocated
+        L.mrt = b->mrt ? b->mrt_rates + 19 * (size_t)i : nullptr;
         // members with a droplet first in every map, then the others (two
         // launches, each compiled for one kind)
         std::vector<int2>* dst = h->nv > 0 ? lm : lm_plain;
@@ -1560,7 +1575,7 @@ hipError_t capture_steps(ibm_lb_batch* b, int cur, hipGraphExec_t* out) {
     hipError_t le = hipSuccess;
     for (int k = 0; k < b->graph_steps && le == hipSuccess; ++k) {
         le = launch_lattice_batch(b->storage, b->lat_desc_g, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib,
-                                  cur ^ (k & 1), 9ll * k, b->variant, b->cap_stream);
+                                  cur ^ (k & 1), 9ll * k, b->variant, b->mrt, b->cap_stream);
         if (le == hipSuccess)
             le = launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, b->n, b->cap_stream);
     }
@@ -1624,7 +1639,7 @@ int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps) {
         }
         for (; j < len; ++j) {
             HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib, b->cur,
-                                         (long long)hf * tab + 9ll * j, b->variant, b->stream),
+                                         (long long)hf * tab + 9ll * j, b->variant, b->mrt, b->stream),
                     "lattice batch launch");
             HIP_TRY(launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, n, b->stream),
                     "ib batch launch");
@@ -1700,7 +1715,7 @@ int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant) {
         hipError_t r = hipSuccess;
         for (int j = 0; j < k && r == hipSuccess; ++j) {
             r = launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib, b->cur, 0, v,
-                                     b->stream);
+                                     b->mrt, b->stream);
             if (r == hipSuccess)
                 r = launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, n, b->stream);
             b->cur ^= 1;
@@ -1767,6 +1782,7 @@ void ibm_lb_batch_destroy(ibm_lb_batch* b) {
     if (b->lat_map) (void)hipFree(b->lat_map);
     if (b->ib_args) (void)hipFree(b->ib_args);
     if (b->patch_map) (void)hipFree(b->patch_map);
+    if (b->mrt_rates) (void)hipFree(b->mrt_rates);
     for (ibm_lb* h : b->m) ibm_lb_destroy(h);
     delete b;
 }

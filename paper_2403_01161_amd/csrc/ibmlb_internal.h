@@ -119,6 +119,7 @@ struct LatDesc {
     int* mark;
     Ctl* ctl;
     const double* A;
+    const double* mrt;       // [19] the member's MRT rates, or null (BGK)
 };
 
 // Vertices per surface patch: the set-up renumbering makes every run of
@@ -197,9 +198,10 @@ hipError_t launch_wet_walls(int storage, const Geom& g, const LatticeParams& lp,
 // member's rows exceed that size). The first nib[q] entries of table q
 // belong to members with a droplet, the rest to members without: two
 // launches, each compiled for one kind.
+// mrt: every member runs the MRT collision with the rates desc[i].mrt.
 hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* maps, const int moff[8],
                                 const int nblocks[8], const int nib[8], int cur, long long step, int variant,
-                                hipStream_t s);
+                                bool mrt, hipStream_t s);
 // desc[i].A = base + i * stride for the n members (on the stream).
 hipError_t launch_set_rows(LatDesc* desc, int n, const double* base, long long stride, hipStream_t s);
 hipError_t launch_moments(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d,

@@ -21,7 +21,7 @@ namespace ibmlb {
                                                    const double*, int, int, hipStream_t, hipEvent_t, hipEvent_t,     \
                                                    const MrtRates*, const ChiRates*);                                \
     extern template hipError_t launch_lattice_batch_c<C>(const LatDesc*, const int2*, const int*, const int*,       \
-                                                         const int*, int, long long, int, hipStream_t);
+                                                         const int*, int, long long, int, bool, hipStream_t);
 IBMLB_LATTICE_EXTERN(SF64)
 IBMLB_LATTICE_EXTERN(SF32)
 IBMLB_LATTICE_EXTERN(SF16)
@@ -655,14 +655,14 @@ hipError_t launch_lattice(int storage, const Geom& g, const LatticeParams& lp, c
 
 hipError_t launch_lattice_batch(int storage, const LatDesc* desc, const int2* maps, const int moff[8],
                                 const int nblocks[8], const int nib[8], int cur, long long step, int variant,
-                                hipStream_t s) {
+                                bool mrt, hipStream_t s) {
     if (variant < 0 || variant >= STEP_VARIANTS) return hipErrorInvalidValue;
     switch (storage) {
-        case IBM_LB_F64: return launch_lattice_batch_c<SF64>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
-        case IBM_LB_F32: return launch_lattice_batch_c<SF32>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
+        case IBM_LB_F64: return launch_lattice_batch_c<SF64>(desc, maps, moff, nblocks, nib, cur, step, variant, mrt, s);
+        case IBM_LB_F32: return launch_lattice_batch_c<SF32>(desc, maps, moff, nblocks, nib, cur, step, variant, mrt, s);
         case IBM_LB_F16DEV:
-            return launch_lattice_batch_c<SF16>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
-        default: return launch_lattice_batch_c<SBF16>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
+            return launch_lattice_batch_c<SF16>(desc, maps, moff, nblocks, nib, cur, step, variant, mrt, s);
+        default: return launch_lattice_batch_c<SBF16>(desc, maps, moff, nblocks, nib, cur, step, variant, mrt, s);
     }
 }
 

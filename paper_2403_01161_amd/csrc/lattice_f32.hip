@@ -7,5 +7,5 @@ template hipError_t launch_lattice_c<SF32>(const Geom&, const LatticeParams&, co
                                           int, int, hipStream_t, hipEvent_t, hipEvent_t, const MrtRates*,
                                           const ChiRates*);
 template hipError_t launch_lattice_batch_c<SF32>(const LatDesc*, const int2*, const int*, const int*, const int*, int,
-                                                long long, int, hipStream_t);
+                                                long long, int, bool, hipStream_t);
 }  // namespace ibmlb

@@ -503,9 +503,18 @@ struct MemberView {
     gptr<const int> mark;
     gptr<Ctl> ctl;
     gptr<const double> A;
+    gptr<const double> mrt;
     __device__ MemberView(const LatDesc& D, int cur)
         : g(D.g), lp(D.lp), fin((gptr<const S>)D.f[cur]), fout((gptr<S>)D.f[cur ^ 1]), F((gptr<R>)D.F),
-          U((gptr<R>)D.u), mark((gptr<const int>)D.mark), ctl((gptr<Ctl>)D.ctl), A((gptr<const double>)D.A) {}
+          U((gptr<R>)D.u), mark((gptr<const int>)D.mark), ctl((gptr<Ctl>)D.ctl), A((gptr<const double>)D.A),
+          mrt((gptr<const double>)D.mrt) {}
+    // the member's MRT rates, read into registers (uniform: scalar loads)
+    __device__ MrtRates rates() const {
+        MrtRates r;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) r.s[k] = mrt[k];
+        return r;
+    }
 };
 
 // Waves per SIMD the batched kernel is compiled for: six fit the 16- and
@@ -516,7 +525,8 @@ template <>
 inline constexpr int batch_waves<SF64> = 1;
 
 // IB: every member the launch covers carries a droplet, or none does.
-template <class C, bool IB, bool NTL, int BS>
+// MRT: every member runs the MRT collision (with its own rates), or none does.
+template <class C, bool IB, bool NTL, int BS, bool MRT = false>
 __global__ __launch_bounds__(BS, batch_waves<C>) void k_lattice_batch(const LatDesc* __restrict__ desc, const int2* __restrict__ map,
                                                        int cur, long long arow, int xcd) {
     const int2 e = map[xcd ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x];
@@ -526,11 +536,13 @@ __global__ __launch_bounds__(BS, batch_waves<C>) void k_lattice_batch(const LatD
     int x, y, z;
     node_xyz(M.g, n, x, y, z);
     const gptr<const double> Arow = M.A + arow;
-    lattice_node<C, IB, NTL, false, false, true, 0>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
-                                           nullptr, 0, 0);
+    MrtRates mr;
+    if constexpr (MRT) mr = M.rates();
+    lattice_node<C, IB, NTL, false, false, true, 0, MRT>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x,
+                                                     y, z, nullptr, 0, 0, &mr);
 }
 
-template <class C, bool IB, bool NTL, bool NTS>
+template <class C, bool IB, bool NTL, bool NTS, bool MRT = false>
 __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows_batch(const LatDesc* __restrict__ desc,
                                                                    const int2* __restrict__ map, int cur,
                                                                    long long arow) {
@@ -549,9 +561,11 @@ __global__ __launch_bounds__(ROWS_MAX_T) void k_lattice_rows_batch(const LatDesc
     const long long n = (long long)row * M.g.Lx + x;
     const bool act = t < T && n < M.g.N;
     const gptr<const double> Arow = M.A + arow;
+    MrtRates mr;
+    if constexpr (MRT) mr = M.rates();
     if (act)
-        lattice_node<C, IB, NTL, true, NTS, true, 0>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x, y, z,
-                                            stage, t, T);
+        lattice_node<C, IB, NTL, true, NTS, true, 0, MRT>(M.g, M.lp, M.fin, M.fout, M.F, M.U, M.mark, M.ctl, Arow, n, x,
+                                                      y, z, stage, t, T, &mr);
     __syncthreads();
     if (act) rows_receive<C, NTS>(M.g, M.fout, stage, n, x, y, z, t, T);
 }
@@ -797,81 +811,84 @@ hipError_t launch_lattice_c(const Geom& g, const LatticeParams& lp, const DevPtr
 }
 
 
-template <class C, bool IB, bool NTL>
+template <class C, bool IB, bool NTL, bool MRT>
 static void launch_batch_v(int bsi, const LatDesc* desc, const int2* map, int nblocks, int cur, long long step,
                            int xcd, hipStream_t s) {
     if (nblocks <= 0) return;
     switch (bsi) {
         case 0:
-            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[0]>), dim3(nblocks), dim3(LAT_BS[0]), 0, s, desc,
-                               map, cur, step, xcd);
+            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[0], MRT>), dim3(nblocks), dim3(LAT_BS[0]), 0, s,
+                               desc, map, cur, step, xcd);
             break;
         case 1:
-            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[1]>), dim3(nblocks), dim3(LAT_BS[1]), 0, s, desc,
-                               map, cur, step, xcd);
+            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[1], MRT>), dim3(nblocks), dim3(LAT_BS[1]), 0, s,
+                               desc, map, cur, step, xcd);
             break;
         case 2:
-            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[2]>), dim3(nblocks), dim3(LAT_BS[2]), 0, s, desc,
-                               map, cur, step, xcd);
+            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[2], MRT>), dim3(nblocks), dim3(LAT_BS[2]), 0, s,
+                               desc, map, cur, step, xcd);
             break;
         default:
-            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[3]>), dim3(nblocks), dim3(LAT_BS[3]), 0, s, desc,
-                               map, cur, step, xcd);
+            hipLaunchKernelGGL((k_lattice_batch<C, IB, NTL, LAT_BS[3], MRT>), dim3(nblocks), dim3(LAT_BS[3]), 0, s,
+                               desc, map, cur, step, xcd);
             break;
     }
 }
 
-template <class C, bool IB, bool NTL, bool NTS>
+template <class C, bool IB, bool NTL, bool NTS, bool MRT>
 static void launch_rows_batch(int T, const LatDesc* desc, const int2* map, int nblocks, int cur, long long step,
                               hipStream_t s) {
     if (nblocks <= 0) return;
     using S = typename C::store_t;
-    hipLaunchKernelGGL((k_lattice_rows_batch<C, IB, NTL, NTS>), dim3(nblocks), dim3(T),
+    hipLaunchKernelGGL((k_lattice_rows_batch<C, IB, NTL, NTS, MRT>), dim3(nblocks), dim3(T),
                        size_t(NXMOVE) * T * sizeof(S), s, desc, map, cur, step);
 }
 
-template <class C, bool NTL, bool NTS>
+template <class C, bool NTL, bool NTS, bool MRT>
 static void launch_rows_both(int T, const LatDesc* desc, const int2* map, int nblocks, int nib, int cur,
                              long long step, hipStream_t s) {
-    launch_rows_batch<C, true, NTL, NTS>(T, desc, map, nib, cur, step, s);
-    launch_rows_batch<C, false, NTL, NTS>(T, desc, map + nib, nblocks - nib, cur, step, s);
+    launch_rows_batch<C, true, NTL, NTS, MRT>(T, desc, map, nib, cur, step, s);
+    launch_rows_batch<C, false, NTL, NTS, MRT>(T, desc, map + nib, nblocks - nib, cur, step, s);
 }
 
-template <class C, bool NTL>
+template <class C, bool NTL, bool MRT>
 static void launch_batch_both(int bsi, const LatDesc* desc, const int2* map, int nblocks, int nib, int cur,
                               long long step, int xcd, hipStream_t s) {
-    launch_batch_v<C, true, NTL>(bsi, desc, map, nib, cur, step, xcd, s);
-    launch_batch_v<C, false, NTL>(bsi, desc, map + nib, nblocks - nib, cur, step, xcd, s);
+    launch_batch_v<C, true, NTL, MRT>(bsi, desc, map, nib, cur, step, xcd, s);
+    launch_batch_v<C, false, NTL, MRT>(bsi, desc, map + nib, nblocks - nib, cur, step, xcd, s);
 }
 
-template <class C>
-hipError_t launch_lattice_batch_c(const LatDesc* desc, const int2* maps, const int moff[8],
-                                  const int nblocks[8], const int nib[8], int cur, long long step, int variant,
-                                  hipStream_t s) {
+template <class C, bool MRT>
+static hipError_t launch_batch_c(const LatDesc* desc, const int2* maps, const int moff[8], const int nblocks[8],
+                                 const int nib[8], int cur, long long step, int variant, hipStream_t s) {
     const int bsi = (variant >> 1) & 3;
     const int xb = variant & VAR_X ? 1 : 0;
     if (variant & VAR_ROWS) {
         const int q = 4 + bsi;
         if (nblocks[q] <= 0) return hipErrorInvalidValue;
         const int T = LAT_BS[bsi];
-        {
-            if (variant & 1) {
-                if (xb) launch_rows_both<C, true, true>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
-                else launch_rows_both<C, true, false>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
-            } else {
-                if (xb) launch_rows_both<C, false, true>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
-                else launch_rows_both<C, false, false>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
-            }
+        if (variant & 1) {
+            if (xb) launch_rows_both<C, true, true, MRT>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
+            else launch_rows_both<C, true, false, MRT>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
+        } else {
+            if (xb) launch_rows_both<C, false, true, MRT>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
+            else launch_rows_both<C, false, false, MRT>(T, desc, maps + moff[q], nblocks[q], nib[q], cur, step, s);
         }
         return hipGetLastError();
     }
-    {
-        if (variant & 1)
-            launch_batch_both<C, true>(bsi, desc, maps + moff[bsi], nblocks[bsi], nib[bsi], cur, step, xb, s);
-        else
-            launch_batch_both<C, false>(bsi, desc, maps + moff[bsi], nblocks[bsi], nib[bsi], cur, step, xb, s);
-    }
+    if (variant & 1)
+        launch_batch_both<C, true, MRT>(bsi, desc, maps + moff[bsi], nblocks[bsi], nib[bsi], cur, step, xb, s);
+    else
+        launch_batch_both<C, false, MRT>(bsi, desc, maps + moff[bsi], nblocks[bsi], nib[bsi], cur, step, xb, s);
     return hipGetLastError();
+}
+
+template <class C>
+hipError_t launch_lattice_batch_c(const LatDesc* desc, const int2* maps, const int moff[8],
+                                  const int nblocks[8], const int nib[8], int cur, long long step, int variant,
+                                  bool mrt, hipStream_t s) {
+    if (mrt) return launch_batch_c<C, true>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
+    return launch_batch_c<C, false>(desc, maps, moff, nblocks, nib, cur, step, variant, s);
 }
 
 

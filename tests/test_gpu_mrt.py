@@ -1,7 +1,8 @@
 """GPU MRT collision against the FP64 oracle's MRT (same basis and rates),
-with two population copies and with one (in place); its variants (linear,
-row and in-place layouts) bit-identical to each other on a lattice-only box;
-its limits (single droplets, no adjoint)."""
+with two population copies and with one (in place), and in ensembles (each
+member with its own rates); its variants (linear, row and in-place layouts)
+bit-identical to each other on a lattice-only box; its limits (ensembles of
+one collision, no adjoint)."""
 import numpy as np
 import pytest
 
@@ -121,10 +122,51 @@ def test_mrt_limits(ib):
     v = sim.autotune(2)
     assert v & AA
     sim.close()
-    with pytest.raises(ib.IbmLbError):
-        ib.Ensemble([dict(L=(8, 8, 8), tau=0.8, collision="mrt")], storage="f32")
+    with pytest.raises(ib.IbmLbError):  # BGK and MRT members together
+        ib.Ensemble([dict(L=(8, 8, 8), tau=0.8, collision="mrt"), dict(L=(8, 8, 8), tau=0.8)], storage="f32")
     sim = ib.Simulation((19, 17, 21), storage="f64", collision="mrt", **kw)
     sim.step(A, 2)
     with pytest.raises(ib.IbmLbError):
         sim.objective_grad()
     sim.close()
+
+
+def test_mrt_ensemble_matches_oracle(ib):
+    """MRT members with different rates, with and without a droplet, through
+    the batched kernels (the autotuner's choice and the row layout) against
+    the oracle in FP64."""
+    from paper_2403_01161_amd.inputs import ou_gradient_table
+    specs = [((16, 16, 16), 0.9, 0.02, 3.0, [1.5, 1.1, 1.7, 1.3, 1.0]),
+             ((20, 14, 18), 1.0, 0.01, 2.6, None),
+             ((13, 9, 11), 0.7, 0.0, None, [1.2, 1.9, 1.1, 1.6, 1.4])]
+    members = []
+    for i, (L, tau, sigma, R, rates) in enumerate(specs):
+        kw = dict(L=L, tau=tau, sigma=sigma, collision="mrt", mrt_s=rates)
+        if R is not None:
+            V, T = icosphere(2, R, box_center(L))
+            kw.update(vertices=V, triangles=T, radius=R)
+        members.append(kw)
+    tabs = np.stack([ou_gradient_table(25, 15.0, 3e-3, seed=200 + i) for i in range(len(members))])
+    for i, m in enumerate(members):
+        m["A0"] = tabs[i, 0]
+    for variant in (None, ROWS | 1):
+        print(f"case MRT ensemble, variant {variant}", flush=True)
+        ens = ib.Ensemble(members, storage="f64")
+        if variant is not None:
+            ens.set_variant(variant)
+        ens.step(tabs[:, :12])
+        ens.step(tabs[:, 12:])
+        for i, m in enumerate(members):
+            kw = dict(m)
+            L = kw.pop("L")
+            ref = oracle.Oracle(L, **kw)
+            ref.step_table(tabs[i])
+            mem = ens.member(i)
+            if mem.nv:
+                assert np.abs(mem.vertices() - ref.vertices()).max() < 1e-11, i
+            rho_g, u_g = mem.fields()
+            rho_r, u_r = ref.fields()
+            assert np.abs(u_g - u_r).max() <= 1e-11 * max(np.abs(u_r).max(), 1e-30), i
+            assert np.abs(rho_g - rho_r).max() < 1e-13, i
+            ref.close()
+        ens.close()
