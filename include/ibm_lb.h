@@ -316,8 +316,9 @@ int ibm_lb_timing_read(ibm_lb* h, double* lattice_ms, int64_t* launches);
  * ibm_lb_batch_init: cfgs[n] as for ibm_lb_init (each member's workspace
  *   rule applies; cfgs[i].stream is ignored); all work goes to `stream`.
  *   Errors: EINVAL (n < 1, mixed storage or collision, a member with one
- *   population copy, wet-node walls, a viscosity ratio or deterministic
- *   spreading, any member invalid), ENOMEM, EDEVICE.
+ *   population copy, a viscosity ratio or deterministic spreading, any
+ *   member invalid), ENOMEM, EDEVICE. Members may mix link and wet-node
+ *   walls (the latter after each batched lattice launch, batched too).
  * ibm_lb_batch_step: A_tables is host memory [n][nsteps][9] (member-major),
  *   copied before return; member i's step j uses A_tables + 9 (i nsteps + j).
  * ibm_lb_batch_observables: out[n]; synchronising; returns the first member

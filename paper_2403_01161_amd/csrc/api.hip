@@ -1412,6 +1412,8 @@ struct ibm_lb_batch {
     int variant = 1;
     bool mrt = false;             // every member runs MRT (rates per member in mrt_rates)
     double* mrt_rates = nullptr;  // device [n][19]
+    int2* wall_map = nullptr;     // device [nwall] {member, block of 256 face nodes}: wet-node walls
+    int nwall = 0;
     // HIP graphs of `graph_steps` batched steps (even; 0 = plain launches),
     // one per population parity, recaptured when the variant changes
     int graph_steps = 32;
@@ -1442,7 +1444,6 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
         if (cfgs[i].populations == 1) return fail(IBM_LB_EINVAL, "ensemble members keep two population copies");
         if (cfgs[i].collision != cfgs[0].collision)
             return fail(IBM_LB_EINVAL, "ensemble members share one collision (BGK or MRT)");
-        if (cfgs[i].walls != IBM_LB_WALLS_LINK) return fail(IBM_LB_EINVAL, "ensemble members run link walls");
         if (chi_active(&cfgs[i])) return fail(IBM_LB_EINVAL, "ensemble members run one fluid");
         if (cfgs[i].deterministic) return fail(IBM_LB_EINVAL, "ensemble members spread with atomics");
     }
@@ -1478,7 +1479,7 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
             return bail(e, "MRT rates");
     }
     std::vector<LatDesc> ld(n);
-    std::vector<int2> lm[8], lm_plain[8], pm;
+    std::vector<int2> lm[8], lm_plain[8], pm, wm;
     bool rows_ok[4] = {true, true, true, true};
     const size_t rec = ib_args_bytes(b->storage);
     std::vector<char> args(rec * n);
@@ -1509,6 +1510,8 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
             for (int k = 0; k < (int)((nrows + rows - 1) / rows); ++k) dst[4 + q].push_back(int2{i, k});
         }
         for (int k = 0; k < (h->nv + IB_PATCH - 1) / IB_PATCH; ++k) pm.push_back(int2{i, k});
+        if (h->wet)
+            for (long long k = 0; k < (wall_node_count(h->g) + 255) / 256; ++k) wm.push_back(int2{i, (int)k});
         fill_ib_args(b->storage, h->g, h->d, h->nv, h->cfg.sigma, h->sp, args.data() + rec * i);
     }
     std::vector<int2> lall;
@@ -1535,6 +1538,12 @@ int ibm_lb_batch_init(const ibm_lb_config* cfgs, int32_t n, void* stream, ibm_lb
     if ((e = hipMalloc((void**)&b->lat_map, sizeof(int2) * lall.size())) != hipSuccess) return bail(e, "maps");
     if ((e = hipMalloc(&b->ib_args, rec * n)) != hipSuccess) return bail(e, "ib records");
     if ((e = hipMalloc((void**)&b->patch_map, sizeof(int2) * pm.size())) != hipSuccess) return bail(e, "maps");
+    b->nwall = (int)wm.size();
+    if (b->nwall > 0) {
+        if ((e = hipMalloc((void**)&b->wall_map, sizeof(int2) * wm.size())) != hipSuccess) return bail(e, "maps");
+        if ((e = hipMemcpy(b->wall_map, wm.data(), sizeof(int2) * wm.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(e, "maps");
+    }
     if ((e = hipMemcpy(b->lat_desc, ld.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "descriptors");
     if ((e = hipMalloc((void**)&b->lat_desc_g, sizeof(LatDesc) * n)) != hipSuccess) return bail(e, "descriptors");
@@ -1576,6 +1585,9 @@ hipError_t capture_steps(ibm_lb_batch* b, int cur, hipGraphExec_t* out) {
     for (int k = 0; k < b->graph_steps && le == hipSuccess; ++k) {
         le = launch_lattice_batch(b->storage, b->lat_desc_g, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib,
                                   cur ^ (k & 1), 9ll * k, b->variant, b->mrt, b->cap_stream);
+        if (le == hipSuccess)
+            le = launch_wet_walls_batch(b->storage, b->lat_desc_g, b->wall_map, b->nwall, cur ^ (k & 1), 9ll * k,
+                                        b->cap_stream);
         if (le == hipSuccess)
             le = launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, b->n, b->cap_stream);
     }
@@ -1641,6 +1653,9 @@ int ibm_lb_batch_step(ibm_lb_batch* b, const double* A_tables, int32_t nsteps) {
             HIP_TRY(launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib, b->cur,
                                          (long long)hf * tab + 9ll * j, b->variant, b->mrt, b->stream),
                     "lattice batch launch");
+            HIP_TRY(launch_wet_walls_batch(b->storage, b->lat_desc, b->wall_map, b->nwall, b->cur,
+                                           (long long)hf * tab + 9ll * j, b->stream),
+                    "walls batch launch");
             HIP_TRY(launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, n, b->stream),
                     "ib batch launch");
             b->cur ^= 1;
@@ -1717,6 +1732,8 @@ int ibm_lb_batch_autotune(ibm_lb_batch* b, int32_t reps, int32_t* variant) {
             r = launch_lattice_batch(b->storage, b->lat_desc, b->lat_map, b->lat_moff, b->nblk, b->nblk_ib, b->cur, 0, v,
                                      b->mrt, b->stream);
             if (r == hipSuccess)
+                r = launch_wet_walls_batch(b->storage, b->lat_desc, b->wall_map, b->nwall, b->cur, 0, b->stream);
+            if (r == hipSuccess)
                 r = launch_ib_step_batch(b->storage, b->ib_args, b->patch_map, b->npatch_total, n, b->stream);
             b->cur ^= 1;
         }
@@ -1783,6 +1800,7 @@ void ibm_lb_batch_destroy(ibm_lb_batch* b) {
     if (b->ib_args) (void)hipFree(b->ib_args);
     if (b->patch_map) (void)hipFree(b->patch_map);
     if (b->mrt_rates) (void)hipFree(b->mrt_rates);
+    if (b->wall_map) (void)hipFree(b->wall_map);
     for (ibm_lb* h : b->m) ibm_lb_destroy(h);
     delete b;
 }

@@ -190,6 +190,13 @@ hipError_t launch_bump_epoch(const DevPtrs& d, hipStream_t s);
 // with the gradient row A_row.
 hipError_t launch_wet_walls(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
                             const double* A_row, hipStream_t s);
+// Face nodes of the non-periodic axes (the wet-node walls' work).
+long long wall_node_count(const Geom& g);
+// Ensemble form: map [nblocks] entries {member, block of 256 face nodes}, the
+// members' lattice launch having read copy cur (the walls act on cur ^ 1)
+// with gradient rows at desc[i].A + arow.
+hipError_t launch_wet_walls_batch(int storage, const LatDesc* desc, const int2* map, int nblocks, int cur,
+                                  long long arow, hipStream_t s);
 // maps: eight block maps, concatenated (table q from entry moff[q],
 // nblocks[q] entries; entry b = {member, block index within the member}).
 // Tables 0-3: linear layout with LAT_BS[q]-node blocks; tables 4-7: row

@@ -178,12 +178,19 @@ __global__ void k_clear(R* F, long long n) {
 // through the node, every rule above is generic: t_i is c_i without its wall
 // components, the products (1 - |c.n|) run over the walls, n1 + n2 (+ n3) is
 // (wx, wy, wz), and n1 x n2 points along the axis without a wall.
-template <class C>
-__global__ __launch_bounds__(256) void k_wet_walls(Geom g, LatticeParams lp, typename C::store_t* __restrict__ f,
-                                                   const double* __restrict__ Arow, long long total) {
+// Face nodes of the non-periodic axes, concatenated.
+__host__ __device__ inline long long wall_nodes(const Geom& g) {
+    long long total = 0;
+    if (!g.px) total += 2ll * g.Ly * g.Lz;
+    if (!g.py) total += 2ll * g.Lx * g.Lz;
+    if (!g.pz) total += 2ll * g.Lx * g.Ly;
+    return total;
+}
+
+// Face node r (< wall_nodes(g)) of the walls above; f plain or global-space.
+template <class C, class PF, class PA>
+__device__ __forceinline__ void wet_wall_node(const Geom& g, const LatticeParams& lp, PF f, PA Arow, long long r) {
     using R = typename C::real;
-    long long r = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (r >= total) return;
     // the face of this thread and its node (faces of periodic axes absent)
     int x = 0, y = 0, z = 0, face = -1;
     const long long ax = (long long)g.Ly * g.Lz, ay = (long long)g.Lx * g.Lz, az = (long long)g.Lx * g.Ly;
@@ -327,6 +334,27 @@ __global__ __launch_bounds__(256) void k_wet_walls(Geom g, LatticeParams lp, typ
 #pragma unroll
     for (int j = 0; j < Q; ++j)
         if ((j > 0 && unk(j)) || (j == 0 && nw > 1)) f[j * N + n] = enc<C>(out[j], lp.scale);
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_wet_walls(Geom g, LatticeParams lp, typename C::store_t* __restrict__ f,
+                                                   const double* __restrict__ Arow, long long total) {
+    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r >= total) return;
+    wet_wall_node<C>(g, lp, f, Arow, r);
+}
+
+// Ensemble form: work-group b takes block map[b].y of the face nodes of
+// member map[b].x, on the copy its lattice launch (input copy cur) wrote,
+// with the gradient row at A + arow.
+template <class C>
+__global__ __launch_bounds__(256) void k_wet_walls_batch(const LatDesc* __restrict__ desc,
+                                                         const int2* __restrict__ map, int cur, long long arow) {
+    const int2 e = map[blockIdx.x];
+    const MemberView<C> M(desc[e.x], cur);
+    const long long r = (long long)e.y * 256 + threadIdx.x;
+    if (r >= wall_nodes(M.g)) return;
+    wet_wall_node<C>(M.g, M.lp, M.fout, M.A + arow, r);
 }
 
 // ---------------------------------------------------------------- observables (FP64)
@@ -682,12 +710,20 @@ hipError_t launch_set_rows(LatDesc* desc, int n, const double* base, long long s
     if ((storage) == IBM_LB_F64) { using R = double; __VA_ARGS__; }     \
     else { using R = float; __VA_ARGS__; }
 
+long long wall_node_count(const Geom& g) { return wall_nodes(g); }
+
+hipError_t launch_wet_walls_batch(int storage, const LatDesc* desc, const int2* map, int nblocks, int cur,
+                                  long long arow, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    DISPATCH_STORAGE(storage, C, {
+        hipLaunchKernelGGL(k_wet_walls_batch<C>, dim3(nblocks), dim3(256), 0, s, desc, map, cur, arow);
+    });
+    return hipGetLastError();
+}
+
 hipError_t launch_wet_walls(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
                             const double* A_row, hipStream_t s) {
-    long long total = 0;
-    if (!g.px) total += 2ll * g.Ly * g.Lz;
-    if (!g.py) total += 2ll * g.Lx * g.Lz;
-    if (!g.pz) total += 2ll * g.Lx * g.Ly;
+    const long long total = wall_nodes(g);
     if (total == 0) return hipSuccess;
     DISPATCH_STORAGE(storage, C, {
         using S = typename C::store_t;

@@ -45,6 +45,36 @@ def _tables(n, nsteps, scale=3e-3):
     return tabs
 
 
+def test_ensemble_wet_walls_match_oracle_fp64(ib):
+    """Members with the wet-node walls (two of them, one with a droplet) beside
+    link-wall and periodic members, FP64 against the oracle."""
+    members = _members()
+    members[0]["walls"] = "wet"
+    members[3]["walls"] = "wet"
+    tabs = _tables(len(members), 20)
+    for i, m in enumerate(members):
+        m["A0"] = tabs[i, 0]
+    ens = ib.Ensemble(members, storage="f64")
+    ens.step(tabs[:, :9])
+    ens.step(tabs[:, 9:])
+    for i, m in enumerate(members):
+        kw = dict(m)
+        L = kw.pop("L")
+        ref = oracle.Oracle(L, **kw)
+        ref.step_table(tabs[i])
+        mem = ens.member(i)
+        if mem.nv:
+            assert np.abs(mem.vertices() - ref.vertices()).max() < 1e-11, i
+        rho_g, u_g = mem.fields()
+        rho_r, u_r = ref.fields()
+        du = np.abs(u_g - u_r).max() / max(np.abs(u_r).max(), 1e-30)
+        print(f"  member {i} ({m.get('walls', 'link')} walls): max|du|/max|u| {du:.1e}", flush=True)
+        assert du <= 1e-11, i
+        assert np.abs(rho_g - rho_r).max() < 1e-13, i
+        ref.close()
+    ens.close()
+
+
 def test_ensemble_members_match_oracle_fp64(ib):
     members = _members()
     tabs = _tables(len(members), 25)
@@ -156,6 +186,12 @@ def test_ensemble_graph_replays_match_launches(ib):
     for call, (a, b) in enumerate(zip(sg, sl)):
         for i in range(len(specs)):
             assert np.array_equal(a[i], b[i]), f"call {call}, member {i}"
+    # the same with the wet-node walls on the member walled on every face
+    members[0]["walls"] = "wet"
+    (sg, _), (sl, _) = _graph_vs_launches(ib, members, "f32", tabs, [8, 8, 13, 9, 16], 8)
+    for call, (a, b) in enumerate(zip(sg, sl)):
+        for i in range(len(specs)):
+            assert np.array_equal(a[i], b[i]), f"wet walls: call {call}, member {i}"
 
 
 def test_ensemble_graph_replays_with_droplets(ib):

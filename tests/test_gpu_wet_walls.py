@@ -6,7 +6,7 @@ droplet in FP64 and FP32 in a box with walls on every face, the all-face
 linear flow and a Couette flow whose edges carry flow (node by node against
 the oracle, wall nodes exactly at the wall velocity), plane Couette flow
 exact at every node, every lattice variant bit-identical, and the limits
-(two copies, single droplets, no adjoint)."""
+(two copies, no adjoint; ensembles in tests/test_gpu_ensemble.py)."""
 import numpy as np
 import pytest
 
@@ -120,5 +120,6 @@ def test_wet_walls_limits(ib):
         sim.set_variant(AA | 1)
     assert not (sim.autotune(2) & AA)
     sim.close()
+    # ensembles run them (tests/test_gpu_ensemble.py), with two copies
     with pytest.raises(ib.IbmLbError):
-        ib.Ensemble([dict(L=(8, 8, 8), tau=0.8, walls="wet")], storage="f32")
+        ib.Ensemble([dict(L=(8, 8, 8), tau=0.8, walls="wet", populations=1)], storage="f32")
