@@ -129,8 +129,8 @@ typedef struct ibm_lb_config {
                               Eq. ZH_bulk; edge and corner nodes rebuilt to hold their density,
                               the wall velocity and the linear field's populations, with the
                               along-edge correction of Eq. ZH_edges and the buried links and
-                              rest population reset), two population copies, single droplets,
-                              without the adjoint */
+                              rest population reset), two population copies (single droplets
+                              and ensembles), without the adjoint */
     double chi;            /* viscosity ratio of droplet to carrier (Sec. 2), in [0, 1e6]; 0 or 1:
                               one fluid. Otherwise the nodes inside the mesh (parity of the mesh
                               crossings along x, i.e. the winding number modulo 2) relax with
