@@ -229,21 +229,26 @@ def kernel_source_hash():
 
 
 def counter_traffic(storage, box="128cubed", variant=None):
-    """HBM bytes per lattice launch from the committed rocprofv3 counter summary,
-    valid only while the kernel source is the one profiled and the lattice
-    kernel variant (bits 0-4 and 6 of the step variant) is the profiled one."""
-    path = os.path.join(ROOT, "profiles", f"lattice_{storage}_{box}_counters.md")
-    if not os.path.exists(path):
+    """HBM bytes per lattice launch from a committed rocprofv3 counter summary
+    (profiles/lattice_{storage}_{box}[_v{variant}]_counters.md), valid only
+    while the kernel source is the one profiled and the lattice kernel variant
+    (bits 0-4 and 6 of the step variant) is the profiled one."""
+    prof = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(prof):
         return None
-    txt = open(path).read()
-    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]{16})", txt)
-    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    v = re.search(r"lattice_variant:\s*([0-9]+)", txt)
-    if not m or not t or not v or m.group(1) != kernel_source_hash():
-        return None
-    if variant is not None and int(v.group(1)) != (variant & 95):
-        return None
-    return float(t.group(1))
+    for fn in sorted(os.listdir(prof)):
+        if not (fn.startswith(f"lattice_{storage}_{box}") and fn.endswith("_counters.md")) or "diagnostic" in fn:
+            continue
+        txt = open(os.path.join(prof, fn)).read()
+        m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]{16})", txt)
+        t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+        v = re.search(r"lattice_variant:\s*([0-9]+)", txt)
+        if not m or not t or not v or m.group(1) != kernel_source_hash():
+            continue
+        if variant is not None and int(v.group(1)) != (variant & 95):
+            continue
+        return float(t.group(1))
+    return None
 
 
 def _oracle_rate(w, steps, warm=2, seed=None, threads=None):

@@ -63,6 +63,11 @@ def test_counter_traffic_only_for_the_profiled_kernel(tmp_path, monkeypatch):
     assert bench.counter_traffic("f32", "256cubed", 57 & ~32) == 2582617607.0  # bit 5 is not a lattice bit
     assert bench.counter_traffic("f16dev", "256cubed", 34) is None  # profiled from another kernel source
     assert bench.counter_traffic("bf16dev", "256cubed", 34) is None  # no summary
+    # a second summary of the same box, for another variant
+    (tmp_path / "profiles" / "lattice_f32_256cubed_v36_counters.md").write_text(
+        f"# test\n\nhbm_bytes_per_launch: 2582000000\nlattice_variant: 4\nkernel_source_sha256_16: {sha}\n")
+    assert bench.counter_traffic("f32", "256cubed", 36) == 2582000000.0
+    assert bench.counter_traffic("f32", "256cubed", 57) == 2582617607.0
 
 
 def test_committed_counter_summaries_are_consistent():
@@ -74,7 +79,7 @@ def test_committed_counter_summaries_are_consistent():
     for fn in sorted(os.listdir(prof)):
         if not (fn.startswith("lattice_") and fn.endswith("_counters.md")) or "diagnostic" in fn:
             continue
-        storage, box = fn[len("lattice_"):-len("_counters.md")].rsplit("_", 1)
+        storage, box = fn[len("lattice_"):-len("_counters.md")].split("_")[:2]
         txt = open(os.path.join(prof, fn)).read()
         nbytes = float(txt.split("hbm_bytes_per_launch:")[1].split()[0])
         alg = 2 * 19 * bench.STORAGE_BYTES[storage] * nodes[box]
