@@ -140,8 +140,9 @@ __global__ void k_adj_hc_b(int nv, const int4* __restrict__ fan, double alpha, c
 }
 
 // The first iteration's pass a with the initialisation folded in (P = rbar,
-// PS = rbar / m, obar = 0 before it), and the last iteration's pass b with
-// the final obar += qbar folded in: the same operations in the same order.
+// PS = rbar / m, obar = 0 before it). The last iteration's pass b, with the
+// final obar += qbar, runs at the start of the interpolation transpose
+// (k_adj_spread), in the same operations and order.
 __global__ void k_adj_hc_a_first(int nv, const int4* __restrict__ fan, double alpha, double gamma, double sgn,
                                  const double4* __restrict__ rb, double4* __restrict__ Pp, double4* __restrict__ PpS,
                                  double4* __restrict__ Ob, double4* __restrict__ Qp) {
@@ -160,23 +161,6 @@ __global__ void k_adj_hc_a_first(int nv, const int4* __restrict__ fan, double al
     PpS[k] = (1.0 / double(m)) * pp;
     Ob[k] = alpha * p;
     Qp[k] = (-(1.0 - alpha)) * bb;
-}
-
-__global__ void k_adj_hc_b_last(int nv, const int4* __restrict__ fan, double alpha, const double4* __restrict__ PpS,
-                                const double4* __restrict__ Qp, double4* __restrict__ Ob) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nv) return;
-    int m;
-    const double4 s = ring_total(fan, PpS, k, &m);
-    const double4 q = Qp[k] + (1.0 - alpha) * s;
-    Ob[k] = Ob[k] + q;
-}
-
-// No smoothing iteration in the forward step: obar = rbar.
-__global__ void k_adj_hc_none(int nv, const double4* __restrict__ rb, double4* __restrict__ Ob) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nv) return;
-    Ob[k] = rb[k];
 }
 
 // ---------------------------------------------------------------- stencils (FP64)
@@ -216,8 +200,17 @@ __device__ inline bool stencil_d(const Geom& g, double4 p, int f[3], double w[3]
 // its contributions straight to global memory.
 constexpr int ADJ_WCAP = 2048;
 
+//
+// The work-group's first wave first finishes obar of its vertices, for every
+// vertex whether or not its stencil lies in the box: with HC the last
+// smoothing iteration's pass b (obar += qbar, qbar = Qp + (1 - alpha) M^T
+// p'bar); without smoothing in the forward step obar = rbar.
+template <bool HC>
 __global__ __launch_bounds__(256) void k_adj_spread(Geom g, int nv, const double4* __restrict__ pos,
-                                                    const double4* __restrict__ Ub, double* __restrict__ ubar) {
+                                                    const int4* __restrict__ fan, double alpha,
+                                                    const double4* __restrict__ PpS, const double4* __restrict__ Qp,
+                                                    const double4* __restrict__ rb, double4* __restrict__ Ob,
+                                                    double* __restrict__ ubar) {
     __shared__ int sf[IB_PATCH][3];
     __shared__ double sw[IB_PATCH][3][4];
     __shared__ double sv[IB_PATCH][3];
@@ -229,12 +222,21 @@ __global__ __launch_bounds__(256) void k_adj_spread(Geom g, int nv, const double
     int f[3] = {0, 0, 0};
     bool ok = false;
     if (t < IB_PATCH && k < nv) {
+        double4 v;
+        if constexpr (HC) {
+            int m;
+            const double4 sr = ring_total(fan, PpS, k, &m);
+            const double4 q = Qp[k] + (1.0 - alpha) * sr;
+            v = Ob[k] + q;
+        } else {
+            v = rb[k];
+        }
+        Ob[k] = v;
         double w[3][4], dw[3][4];
         ok = stencil_d(g, pos[k], f, w, dw);
         if (ok) {
             for (int d = 0; d < 3; ++d)
                 for (int j = 0; j < 4; ++j) sw[t][d][j] = w[d][j];
-            const double4 v = Ub[k];
             sv[t][0] = v.x;
             sv[t][1] = v.y;
             sv[t][2] = v.z;
@@ -768,10 +770,6 @@ hipError_t launch_adj_record_iters(const DevPtrs& d, int* slot, hipStream_t s) {
 hipError_t launch_adj_hc(int nv, const int4* fan, const SmoothParams& sp, int iters, const AdjVerts& v,
                          hipStream_t s) {
     const unsigned nb = nblk(nv, 256);
-    if (iters == 0) {
-        hipLaunchKernelGGL(k_adj_hc_none, dim3(nb), dim3(256), 0, s, nv, v.rb, v.Ob);
-        return hipGetLastError();
-    }
     for (int it = 0; it < iters; ++it) {
         if (it == 0)
             hipLaunchKernelGGL(k_adj_hc_a_first, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, sp.gamma,
@@ -779,17 +777,20 @@ hipError_t launch_adj_hc(int nv, const int4* fan, const SmoothParams& sp, int it
         else
             hipLaunchKernelGGL(k_adj_hc_a, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, sp.gamma, double(sp.sign),
                                v.P, v.PS, v.Pp, v.PpS, v.Ob, v.Qp);
-        if (it == iters - 1)
-            hipLaunchKernelGGL(k_adj_hc_b_last, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, v.PpS, v.Qp, v.Ob);
-        else
+        if (it < iters - 1)
             hipLaunchKernelGGL(k_adj_hc_b, dim3(nb), dim3(256), 0, s, nv, fan, sp.alpha, v.PpS, v.Qp, v.P, v.PS);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_adj_ib_spread(const Geom& g, int nv, const double4* pos, const AdjVerts& v, double* ubar,
-                                hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_spread, dim3(nblk(nv, IB_PATCH)), dim3(256), 0, s, g, nv, pos, v.Ob, ubar);
+hipError_t launch_adj_ib_spread(const Geom& g, int nv, const int4* fan, double alpha, int iters,
+                                const double4* pos, const AdjVerts& v, double* ubar, hipStream_t s) {
+    if (iters > 0)
+        hipLaunchKernelGGL(k_adj_spread<true>, dim3(nblk(nv, IB_PATCH)), dim3(256), 0, s, g, nv, pos, fan, alpha,
+                           v.PpS, v.Qp, v.rb, v.Ob, ubar);
+    else
+        hipLaunchKernelGGL(k_adj_spread<false>, dim3(nblk(nv, IB_PATCH)), dim3(256), 0, s, g, nv, pos, fan, alpha,
+                           v.PpS, v.Qp, v.rb, v.Ob, ubar);
     return hipGetLastError();
 }
 

@@ -532,7 +532,10 @@ int ensure_natural(ibm_lb* h) {
     return IBM_LB_OK;
 }
 
-int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
+// keep_last: copy the last row used into the gradient slot that later calls
+// (observables, wet-node walls of the next step) read; a caller that issues a
+// run one step at a time asks for it on the run's last step only.
+int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride, bool keep_last = true) {
     const bool ib = h->nv > 0;
     int rc = ensure_force(h);
     if (rc) return rc;
@@ -578,7 +581,7 @@ int enqueue_steps(ibm_lb* h, const double* A, int nsteps, int stride) {
         else h->cur ^= 1;
         h->step++;
     }
-    if (nsteps > 0) {
+    if (nsteps > 0 && keep_last) {
         const double* last = A + 9ll * (nsteps - 1) * stride;
         double* slot = h->d.Abuf + 9ll * ACAP;
         if (last != slot)
@@ -1341,7 +1344,7 @@ int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const
             HIP_TRY(launch_adj_record(h->storage, h->g, h->lp, h->d, h->cur, nv, adj_step(h, done + j),
                                       done + j > 0 ? h->adj_iters + done + j - 1 : nullptr, s),
                     "record launch");
-            rc = enqueue_steps(h, rows + 9ll * j, 1, 1);
+            rc = enqueue_steps(h, rows + 9ll * j, 1, 1, done + j == nsteps - 1);
             if (rc) return rc;
         }
         done += n;
@@ -1366,9 +1369,10 @@ int ibm_lb_adjoint_segment(ibm_lb* h, const void* ckpt, size_t ckpt_bytes, const
     for (int j = nsteps - 1; j >= 0; --j) {
         const AdjStep st = adj_step(h, j);
         if (nv > 0) {
-            HIP_TRY(launch_adj_hc(nv, h->d.fan, h->sp, h->sp.max_iter > 0 ? iters[j] : 0, h->adj_v, s),
-                    "HC transpose");
-            HIP_TRY(launch_adj_ib_spread(h->g, nv, st.pos, h->adj_v, h->adj_ubar, s), "interp transpose");
+            const int it = h->sp.max_iter > 0 ? iters[j] : 0;
+            HIP_TRY(launch_adj_hc(nv, h->d.fan, h->sp, it, h->adj_v, s), "HC transpose");
+            HIP_TRY(launch_adj_ib_spread(h->g, nv, h->d.fan, h->sp.alpha, it, st.pos, h->adj_v, h->adj_ubar, s),
+                    "interp transpose");
         }
         HIP_TRY(launch_adj_lattice(h->g, h->lp, h->adj_fb[c], h->adj_fb[c ^ 1], st, h->adj_ubar, h->adj_Fbar,
                                    h->adj_Apart + 9ll * nbl * j, s),

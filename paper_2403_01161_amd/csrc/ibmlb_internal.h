@@ -275,10 +275,14 @@ struct AdjVerts {
 hipError_t launch_adj_record(int storage, const Geom& g, const LatticeParams& lp, const DevPtrs& d, int cur,
                              int nv, const AdjStep& st, int* prev_iters, hipStream_t s);
 hipError_t launch_adj_record_iters(const DevPtrs& d, int* slot, hipStream_t s);
+// The transposed smoothing of a step with `iters` iterations, up to the last
+// iteration's pass b, which launch_adj_ib_spread (given the same `iters`)
+// runs ahead of the transposed interpolation; with iters = 0 it takes obar =
+// rbar there.
 hipError_t launch_adj_hc(int nv, const int4* fan, const SmoothParams& sp, int iters, const AdjVerts& v,
                          hipStream_t s);
-hipError_t launch_adj_ib_spread(const Geom& g, int nv, const double4* pos, const AdjVerts& v, double* ubar,
-                                hipStream_t s);
+hipError_t launch_adj_ib_spread(const Geom& g, int nv, const int4* fan, double alpha, int iters, const double4* pos,
+                                const AdjVerts& v, double* ubar, hipStream_t s);
 int adj_lattice_blocks(long long N);
 int adj_vertex_blocks(int nv);
 hipError_t launch_adj_lattice(const Geom& g, const LatticeParams& lp, const double* fbin, double* fbout,
