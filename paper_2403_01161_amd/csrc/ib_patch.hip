@@ -144,15 +144,17 @@ __device__ inline void atom_max(__attribute__((address_space(1))) unsigned long 
 // Surface-tension force of vertex k at positions P: Eq. (pi_drop) read as
 // phi_k = -sigma dA/dr_k, with dA/dr_k = n_t x (r_{n_{j+1}} - r_{n_j}) / 2
 // for the triangle t = (k, n_j, n_{j+1}) of unit normal n_t.
+// Positions in P of the m fan neighbours nb of a vertex.
 template <class R, int AS>
-__device__ inline void force_of(const IbArgs<R, AS>& a, Ptr<const V4<R>, AS> P, int k, const V4<R>& pk, R& fx,
-                                R& fy, R& fz) {
-    int nb[MAXV];
-    const int m = load_fan(a.fan, k, nb);
-    V4<R> pn[MAXV];
+__device__ inline void fan_positions(Ptr<const V4<R>, AS> P, int m, const int nb[MAXV], V4<R> pn[MAXV]) {
 #pragma unroll
     for (int j = 0; j < MAXV; ++j)
         if (j < m) pn[j] = ld4<V4<R>>(P + nb[j]);
+}
+
+template <class R, int AS>
+__device__ inline void force_sum(const IbArgs<R, AS>& a, int m, const V4<R> pn[MAXV], const V4<R>& pk, R& fx, R& fy,
+                                 R& fz) {
     fx = fy = fz = R(0);
 #pragma unroll
     for (int j = 0; j < MAXV; ++j) {
@@ -173,6 +175,28 @@ __device__ inline void force_of(const IbArgs<R, AS>& a, Ptr<const V4<R>, AS> P, 
         }
     }
 }
+
+// Surface-tension force of vertex k at positions P: Eq. (pi_drop) read as
+// phi_k = -sigma dA/dr_k, with dA/dr_k = n_t x (r_{n_{j+1}} - r_{n_j}) / 2
+// for the triangle t = (k, n_j, n_{j+1}) of unit normal n_t.
+template <class R, int AS>
+__device__ inline void force_of(const IbArgs<R, AS>& a, Ptr<const V4<R>, AS> P, int k, const V4<R>& pk, R& fx,
+                                R& fy, R& fz) {
+    int nb[MAXV];
+    const int m = load_fan(a.fan, k, nb);
+    V4<R> pn[MAXV];
+    fan_positions<R, AS>(P, m, nb, pn);
+    force_sum(a, m, pn, pk, fx, fy, fz);
+}
+
+// A vertex's position and its fan (valence and neighbours), loaded ahead of
+// the force.
+template <class R>
+struct FanPre {
+    V4<R> pos;
+    int nb[MAXV];
+    int m;
+};
 
 // Tiles touched by a stencil starting at unwrapped `first`, marked with `ep`.
 template <class R, int AS>
@@ -386,9 +410,11 @@ struct IndArgs {
 // `commit`, P (the final smoothed positions) also becomes the state r.
 // CHI: waves 1-3, idle while the first wave computes the forces, cross the
 // patch's triangles (positions P) with the lattice rows.
+// `pre` holds this thread's vertex position in P and its fan (for a thread
+// that owns a vertex).
 template <class R, int AS, bool CHI = false>
 __device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, int commit, Stage<R>& st, double* win,
-                         const IndArgs* ia = nullptr, const V4<R>* pre = nullptr) {
+                         const IndArgs* ia, const FanPre<R>& pre) {
     const int t = threadIdx.x;
     const int k = p * PATCH + t;
     const int ep = a.ctl->epoch;
@@ -397,13 +423,14 @@ __device__ void fs_patch(const IbArgs<R, AS>& a, int p, Ptr<const V4<R>, AS> P, 
     R w[3][4];
     bool ok = false;
     if (t < PATCH && k < a.nv) {
-        // the position, or the one the caller already loaded
-        const V4<R> pos = pre ? *pre : ld4<V4<R>>(P + k);
+        const V4<R> pos = pre.pos;
         if (commit) st4(a.r + k, pos);
         ok = stencil_of(a, pos, f, w);
         if (ok) {
             R fx, fy, fz;
-            force_of(a, P, k, pos, fx, fy, fz);
+            V4<R> pn[MAXV];
+            fan_positions<R, AS>(P, pre.m, pre.nb, pn);
+            force_sum(a, pre.m, pn, pos, fx, fy, fz);
             mark_tiles(a, f, ep);
             st.val[t][0] = fx;
             st.val[t][1] = fy;
@@ -461,14 +488,18 @@ __device__ inline double from_bits<double>(unsigned long long b) { return __long
 // The step's largest |p - q| so far: the maximum over the reduction slots,
 // one slot a lane, folded across the wave (every lane of the calling wave
 // active; each wave gets the value).
-template <class R, int AS>
-__device__ inline R red_max(const IbArgs<R, AS>& a) {
-    unsigned long long v = a.red[threadIdx.x & (RED_SLOTS - 1)];
+template <class R>
+__device__ inline R slot_max(unsigned long long v) {
     for (int m = 32; m > 0; m >>= 1) {
         const unsigned long long o = __shfl_xor(v, m, 64);
         v = o > v ? o : v;
     }
     return from_bits<R>(v);
+}
+
+template <class R, int AS>
+__device__ inline R red_max(const IbArgs<R, AS>& a) {
+    return slot_max<R>(a.red[threadIdx.x & (RED_SLOTS - 1)]);
 }
 
 // Zero the reduction slots and the arrival count (the first wave of a
@@ -562,15 +593,23 @@ template <class R, bool CHI>
 __device__ void fs_step(const IbArgs<R>& a, int fold, int npatch, const V4<R>* P, int commit, Stage<R>& st,
                         double* win, const IndArgs* ia) {
     const int t = threadIdx.x;
-    // this thread's vertex position, loaded together with the reduction slots
-    // so that the two loads overlap
+    // the reduction slot, this thread's vertex position and its fan are
+    // loaded together, before the decision that needs the slot (a path that
+    // runs further iterations drops the vertex data)
+    const bool test = fold && a.sp.max_iter > 0;
+    const unsigned long long slot = test ? a.red[t & (RED_SLOTS - 1)] : 0ull;
     const int k0 = blockIdx.x * PATCH + t;
-    V4<R> pos0{};
-    if (t < PATCH && k0 < a.nv) pos0 = ld4<V4<R>>(P + k0);
+    FanPre<R> pre;
+    pre.m = 0;
+    pre.pos = V4<R>{};
+    if (t < PATCH && k0 < a.nv) {
+        pre.pos = ld4<V4<R>>(P + k0);
+        pre.m = load_fan(a.fan, k0, pre.nb);
+    }
     if (fold) {
         bool more = false, capped = false;
-        if (a.sp.max_iter > 0) {
-            const bool converged = red_max(a) < R(a.sp.tol);
+        if (test) {
+            const bool converged = slot_max<R>(slot) < R(a.sp.tol);
             capped = !converged && a.sp.max_iter <= 1;
             more = !converged && !capped;
         }
@@ -590,7 +629,7 @@ __device__ void fs_step(const IbArgs<R>& a, int fold, int npatch, const V4<R>* P
             if (capped) a.ctl->cap_hits += 1;
         }
     }
-    fs_patch<R, 0, CHI>(a, blockIdx.x, P, commit, st, win, ia, &pos0);
+    fs_patch<R, 0, CHI>(a, blockIdx.x, P, commit, st, win, ia, pre);
 }
 
 template <class R>
@@ -1100,7 +1139,15 @@ __global__ __launch_bounds__(IBT) void k_fs_batch(const IbArgs<R>* __restrict__ 
     const int2 e = map[blockIdx.x];
     const IbArgs<R, 1> a = to_global(args[e.x]);
     const Ptr<const V4<R>, 1> P = commit ? (a.sp.max_iter > 0 ? a.qa : a.o) : a.r;
-    fs_patch(a, e.y, P, commit, st, reinterpret_cast<double*>(dyn));
+    const int k = e.y * PATCH + int(threadIdx.x);
+    FanPre<R> pre;
+    pre.m = 0;
+    pre.pos = V4<R>{};
+    if (threadIdx.x < PATCH && k < a.nv) {
+        pre.pos = ld4<V4<R>>(P + k);
+        pre.m = load_fan(a.fan, k, pre.nb);
+    }
+    fs_patch(a, e.y, P, commit, st, reinterpret_cast<double*>(dyn), nullptr, pre);
 }
 
 // ---------------------------------------------------------------- launchers
