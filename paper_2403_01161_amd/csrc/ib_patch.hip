@@ -306,7 +306,8 @@ struct Stage {
 
 // Nodes of the FP64 spreading window: 3 x 1456 x 8 B = 34,944 B of dynamic
 // LDS, so that with the force kernel's static LDS (about 5 KB in FP32) four
-// work-groups fit in a CU's 160 KB, as many as its registers allow. A patch's
+// work-groups fit in a CU's 160 KB, as many as the batched kernel's registers
+// allow (the single-droplet kernel's allow three in FP32). A patch's
 // window (the box of its vertices' stencils) holds 300-900 nodes on average
 // for the benchmark meshes, up to about 1400 for a 2562-vertex droplet of
 // radius 12 stretched to D = 0.3; a larger one falls back to direct atomics.
